@@ -1,0 +1,234 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: tests/, __graft_entry__.smoke() and the
+cpu_baseline leg of bench.py are the only callers.  The product path
+(paper_2002_01184_amd) never imports this package, and this package never
+imports the product.  Arrays are numpy float64 (targets are upcast exactly by
+the caller), states are [C, D] row-major.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+STD_NORMAL, GAUSS_DIAG, GAUSS_DENSE, LOGREG = 0, 1, 2, 3
+TAG_MOMENTUM, TAG_ACCEPT = 0, 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+
+class _Target(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("dim", ctypes.c_int64),
+                ("prec", _dp), ("X", _dp), ("y", _dp), ("n_rows", ctypes.c_int64),
+                ("prior_scale", ctypes.c_double)]
+
+
+class _DualAvg(ctypes.Structure):
+    _fields_ = [("log_eps", ctypes.c_double), ("hbar", ctypes.c_double),
+                ("log_eps_bar", ctypes.c_double), ("mu", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b  # noqa: F401  (build script beside the source)
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.orc_philox_many.argtypes = [ctypes.c_int64, _u32p, _u32p, _u32p]
+        L.orc_normal4.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.c_uint32, _dp]
+        L.orc_momentum.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, _dp]
+        L.orc_momentum_many.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int64, _dp]
+        L.orc_accept_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        L.orc_accept_uniform.restype = ctypes.c_double
+        L.orc_accept_uniform_many.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, _dp]
+        L.orc_logp_grad.argtypes = [ctypes.POINTER(_Target), _dp, _dp]
+        L.orc_logp_grad.restype = ctypes.c_double
+        L.orc_leapfrog.argtypes = [ctypes.POINTER(_Target), ctypes.c_double, ctypes.c_int32, _dp, _dp, _dp, _dp]
+        L.orc_transition.argtypes = [ctypes.POINTER(_Target), ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_int32, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_transition.restype = ctypes.c_int
+        L.orc_dual_avg_init.argtypes = [ctypes.POINTER(_DualAvg), ctypes.c_double]
+        L.orc_dual_avg_update.argtypes = [ctypes.POINTER(_DualAvg), ctypes.c_int64, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_bootstrap.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, _dp, _dp, _dp, ctypes.c_int32]
+        L.orc_step.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                               ctypes.c_uint32, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u8p,
+                               ctypes.c_int32]
+        L.orc_sample_chain.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                       ctypes.c_uint32, _dp, _dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       _dp, _dp, _u8p, _dp, _dp, ctypes.c_int32]
+        L.orc_sample_chain.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a, typ=_dp):
+    if a is None:
+        return None
+    return a.ctypes.data_as(typ)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class Target:
+    """A target in FP64.  kind: STD_NORMAL / GAUSS_DIAG / GAUSS_DENSE / LOGREG."""
+    kind: int
+    dim: int
+    prec: np.ndarray | None = None
+    X: np.ndarray | None = None
+    y: np.ndarray | None = None
+    prior_scale: float = 1.0
+
+    def __post_init__(self):
+        if self.prec is not None:
+            self.prec = _f64(self.prec)
+        if self.X is not None:
+            self.X = _f64(self.X)
+        if self.y is not None:
+            self.y = _f64(self.y)
+        n = 0 if self.X is None else self.X.shape[0]
+        self._c = _Target(self.kind, 0, self.dim, _p(self.prec), _p(self.X), _p(self.y), n,
+                          float(self.prior_scale))
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+# ---------------------------------------------------------------- RNG --
+def philox(ctr: np.ndarray, key) -> np.ndarray:
+    """Philox4x32-10 blocks: ctr [n, 4] uint32 -> [n, 4] uint32 under key (k0, k1)."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.empty_like(ctr)
+    lib().orc_philox_many(ctr.shape[0], _p(ctr, _u32p), _p(k, _u32p), _p(out, _u32p))
+    return out
+
+
+def normal4(seed: int, c0: int, c1: int, c2: int, tag: int) -> np.ndarray:
+    z = np.empty(4)
+    lib().orc_normal4(seed, c0, c1, c2, tag, _p(z))
+    return z
+
+
+def momentum(seed: int, C: int, t: int, D: int) -> np.ndarray:
+    p = np.empty((C, D))
+    lib().orc_momentum_many(seed, C, t, D, _p(p))
+    return p
+
+
+def accept_uniform(seed: int, C: int, t: int) -> np.ndarray:
+    u = np.empty(C)
+    lib().orc_accept_uniform_many(seed, C, t, _p(u))
+    return u
+
+
+# ------------------------------------------------------------- target --
+def logp_grad(tg: Target, x: np.ndarray):
+    """Batch semantics: x [C, D] -> (logp [C], grad [C, D])."""
+    x = _f64(x)
+    squeeze = x.ndim == 1
+    x2 = x.reshape(-1, tg.dim)
+    lp = np.empty(x2.shape[0])
+    g = np.empty_like(x2)
+    for c in range(x2.shape[0]):
+        lp[c] = lib().orc_logp_grad(tg.c, _p(x2[c]), _p(g[c]))
+    if squeeze:
+        return lp[0], g[0]
+    return lp, g
+
+
+def leapfrog(tg: Target, eps: float, L: int, x: np.ndarray, p: np.ndarray):
+    """One chain: L leapfrog steps from (x, p).  Returns (x_L, p_L, logp_L, g_L)."""
+    x = _f64(x).copy()
+    p = _f64(p).copy()
+    _, g = logp_grad(tg, x)
+    g = g.copy()
+    lp = ctypes.c_double(0.0)
+    lib().orc_leapfrog(tg.c, eps, L, _p(x), _p(p), _p(g), ctypes.byref(lp))
+    return x, p, lp.value, g
+
+
+def bootstrap(tg: Target, x: np.ndarray, nthreads: int = 0):
+    x = _f64(x)
+    C = x.shape[0]
+    lp = np.empty(C)
+    g = np.empty_like(x)
+    lib().orc_bootstrap(tg.c, C, _p(x), _p(lp), _p(g), nthreads)
+    return lp, g
+
+
+def step(tg: Target, L: int, seed: int, t: int, eps, x, logp=None, g=None, nthreads: int = 0):
+    """One transition of all chains from state x (logp/g recomputed if None).
+
+    Returns dict with new state x/logp/g, proposal x_prop/p_prop/logp_prop,
+    delta_h, log_accept_ratio, accepted."""
+    x = _f64(x).copy()
+    C, D = x.shape
+    if logp is None or g is None:
+        logp, g = bootstrap(tg, x, nthreads)
+    logp = _f64(logp).copy()
+    g = _f64(g).copy()
+    eps = np.broadcast_to(_f64(eps), (C,)).copy()
+    xp = np.empty_like(x)
+    pp = np.empty_like(x)
+    lpp = np.empty(C)
+    dh = np.empty(C)
+    lar = np.empty(C)
+    acc = np.empty(C, dtype=np.uint8)
+    lib().orc_step(tg.c, C, L, seed, t, _p(eps), _p(x), _p(logp), _p(g), _p(xp), _p(pp), _p(lpp),
+                   _p(dh), _p(lar), _p(acc, _u8p), nthreads)
+    return dict(x=x, logp=logp, g=g, x_prop=xp, p_prop=pp, logp_prop=lpp, delta_h=dh,
+                log_accept_ratio=lar, accepted=acc.astype(bool))
+
+
+def dual_avg_run(eps0: float, alphas, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75):
+    """Run the dual-averaging recursion over a scripted alpha sequence; returns
+    arrays (log_eps, hbar, log_eps_bar) after each iteration m = 1..len(alphas)."""
+    s = _DualAvg()
+    lib().orc_dual_avg_init(ctypes.byref(s), eps0)
+    out = []
+    for m, a in enumerate(alphas, start=1):
+        lib().orc_dual_avg_update(ctypes.byref(s), m, float(a), target_accept, gamma, t0, kappa)
+        out.append((s.log_eps, s.hbar, s.log_eps_bar))
+    out = np.array(out)
+    return out[:, 0], out[:, 1], out[:, 2], s.mu
+
+
+def sample_chain(tg: Target, L: int, seed: int, x0, eps0, num_burnin: int, num_results: int,
+                 adapt: bool = False, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75,
+                 t_begin: int = 0, store_samples: bool = True, nthreads: int = 0):
+    """Oracle sample_chain.  Returns dict(samples [R,C,D] or None, step_size, is_accepted,
+    log_accept_ratio, target_log_prob [R,C], final_x [C,D], final_eps [C])."""
+    x = _f64(x0).copy()
+    C, D = x.shape
+    eps = np.broadcast_to(_f64(eps0), (C,)).copy()
+    R = num_results
+    samples = np.empty((R, C, D)) if store_samples else None
+    st = np.empty((R, C))
+    acc = np.empty((R, C), dtype=np.uint8)
+    lar = np.empty((R, C))
+    lp = np.empty((R, C))
+    lib().orc_sample_chain(tg.c, C, L, seed, t_begin, _p(x), _p(eps), num_burnin, num_results,
+                           1 if adapt else 0, target_accept, gamma, t0, kappa,
+                           _p(samples), _p(st), _p(acc, _u8p), _p(lar), _p(lp), nthreads)
+    return dict(samples=samples, step_size=st, is_accepted=acc.astype(bool), log_accept_ratio=lar,
+                target_log_prob=lp, final_x=x, final_eps=eps)

@@ -1,0 +1,384 @@
+/*
+ * oracle.c -- FP64 CPU oracle of the batched HMC transition.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h): tests/, __graft_entry__.smoke()
+ * and bench.py's cpu_baseline leg are its only users.  Nothing here is
+ * blocked, fused or reordered beyond the definitions it follows, so each
+ * function can be checked against the cited passage by eye.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------
+ * Philox4x32-10 (Salmon et al., SC'11, Sec. 3.2 and Table 2).
+ * One round: two 32x32->64 products of the even counter words with the
+ * round multipliers; the odd words and the key are xor-ed into the high
+ * halves and the words are permuted.  The key is bumped by the Weyl
+ * constants (golden ratio, sqrt(3)-1) between rounds.
+ * ---------------------------------------------------------------------- */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t prod0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void philox_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                         uint32_t w[4])
+{
+    const uint32_t ctr[4] = {c0, c1, c2, c3};
+    const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, w);
+}
+
+/* Uniform in (0,1) from the top 23 bits of a word: (k + 1/2) / 2^23.  The
+ * value is exactly representable in binary32 as well as binary64. */
+static double uniform23(uint32_t w)
+{
+    return ((double)(w >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+/* Box & Muller (1958): (u1, u2) uniform -> two independent N(0,1). */
+void orc_normal4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag, double z[4])
+{
+    uint32_t w[4];
+    philox_block(seed, c0, c1, c2, tag, w);
+    for (int pair = 0; pair < 2; ++pair) {
+        double u1 = uniform23(w[2 * pair]);
+        double u2 = uniform23(w[2 * pair + 1]);
+        double radius = sqrt(-2.0 * log(u1));
+        double angle = 2.0 * M_PI * u2;
+        z[2 * pair] = radius * cos(angle);
+        z[2 * pair + 1] = radius * sin(angle);
+    }
+}
+
+/* Paper Sec. 2.1: one independent momentum per state variable per chain. */
+void orc_momentum(uint64_t seed, uint32_t chain, uint32_t t, int64_t D, double *p)
+{
+    for (int64_t i = 0; i < D; ++i) {
+        double z[4];
+        orc_normal4(seed, chain, t, (uint32_t)(i / 4), ORC_TAG_MOMENTUM, z);
+        p[i] = z[i % 4];
+    }
+}
+
+/* Uniform in (0,1) with 52 random bits: (k + 1/2) / 2^52, k from the top
+ * 26 bits of the first two words of the block (chain, t, 0, ACCEPT). */
+double orc_accept_uniform(uint64_t seed, uint32_t chain, uint32_t t)
+{
+    uint32_t w[4];
+    philox_block(seed, chain, t, 0, ORC_TAG_ACCEPT, w);
+    double k = (double)(w[0] >> 6) * 67108864.0 + (double)(w[1] >> 6);
+    return (k + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+void orc_philox_many(int64_t n, const uint32_t *ctr, const uint32_t key[2], uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+void orc_momentum_many(uint64_t seed, int64_t C, uint32_t t, int64_t D, double *p)
+{
+    for (int64_t c = 0; c < C; ++c)
+        orc_momentum(seed, (uint32_t)c, t, D, p + c * D);
+}
+
+void orc_accept_uniform_many(uint64_t seed, int64_t C, uint32_t t, double *u)
+{
+    for (int64_t c = 0; c < C; ++c)
+        u[c] = orc_accept_uniform(seed, (uint32_t)c, t);
+}
+
+/* ------------------------------------------------------------------------
+ * Targets: log-probability up to a constant and its gradient.  Batch
+ * semantics (paper Sec. 2): each chain's value reduces over its own event
+ * axis only.
+ * ---------------------------------------------------------------------- */
+static double softplus(double s)
+{
+    /* log(1 + e^s) without overflow */
+    return (s > 0.0 ? s : 0.0) + log1p(exp(-fabs(s)));
+}
+
+static double sigmoid(double s)
+{
+    if (s >= 0.0)
+        return 1.0 / (1.0 + exp(-s));
+    double e = exp(s);
+    return e / (1.0 + e);
+}
+
+double orc_logp_grad(const orc_target *tg, const double *x, double *g)
+{
+    const int64_t D = tg->dim;
+    double logp = 0.0;
+    switch (tg->kind) {
+    case ORC_STD_NORMAL:
+        /* log N(x; 0, I) = -1/2 x.x */
+        for (int64_t i = 0; i < D; ++i) {
+            g[i] = -x[i];
+            logp += -0.5 * x[i] * x[i];
+        }
+        break;
+    case ORC_GAUSS_DIAG:
+        /* precision diag(prec): -1/2 sum prec_i x_i^2 */
+        for (int64_t i = 0; i < D; ++i) {
+            g[i] = -tg->prec[i] * x[i];
+            logp += -0.5 * tg->prec[i] * x[i] * x[i];
+        }
+        break;
+    case ORC_GAUSS_DENSE:
+        /* precision P: logp = -1/2 x^T P x, grad = -P x */
+        for (int64_t i = 0; i < D; ++i) {
+            double row = 0.0;
+            for (int64_t j = 0; j < D; ++j)
+                row += tg->prec[i * D + j] * x[j];
+            g[i] = -row;
+            logp += -0.5 * x[i] * row;
+        }
+        break;
+    case ORC_LOGREG: {
+        /* Bayesian logistic regression, prior N(0, s^2 I):
+         *   logp = sum_n [y_n z_n - softplus(z_n)] - |theta|^2 / (2 s^2),  z = X theta
+         *   grad = X^T (y - sigmoid(z)) - theta / s^2 */
+        const double inv_var = 1.0 / (tg->prior_scale * tg->prior_scale);
+        for (int64_t i = 0; i < D; ++i) {
+            g[i] = -x[i] * inv_var;
+            logp += -0.5 * x[i] * x[i] * inv_var;
+        }
+        for (int64_t n = 0; n < tg->n_rows; ++n) {
+            const double *row = tg->X + n * D;
+            double z = 0.0;
+            for (int64_t i = 0; i < D; ++i)
+                z += row[i] * x[i];
+            logp += tg->y[n] * z - softplus(z);
+            double r = tg->y[n] - sigmoid(z);
+            for (int64_t i = 0; i < D; ++i)
+                g[i] += row[i] * r;
+        }
+        break;
+    }
+    default:
+        logp = NAN;
+    }
+    return logp;
+}
+
+/* ------------------------------------------------------------------------
+ * Leapfrog (Neal 2011, Sec. 5.2.3.3): half step in momentum, full step in
+ * position, half step in momentum; potential U = -logp, so -dU/dx = grad.
+ * Written as L complete steps (the half kicks are not merged).
+ * ---------------------------------------------------------------------- */
+void orc_leapfrog(const orc_target *tg, double eps, int32_t L,
+                  double *x, double *p, double *g, double *logp)
+{
+    const int64_t D = tg->dim;
+    for (int32_t l = 0; l < L; ++l) {
+        for (int64_t i = 0; i < D; ++i)
+            p[i] += 0.5 * eps * g[i];
+        for (int64_t i = 0; i < D; ++i)
+            x[i] += eps * p[i];
+        *logp = orc_logp_grad(tg, x, g);
+        for (int64_t i = 0; i < D; ++i)
+            p[i] += 0.5 * eps * g[i];
+    }
+}
+
+static double kinetic(const double *p, int64_t D)
+{
+    /* identity mass matrix: K(p) = 1/2 p.p */
+    double k = 0.0;
+    for (int64_t i = 0; i < D; ++i)
+        k += 0.5 * p[i] * p[i];
+    return k;
+}
+
+/* Paper Sec. 2.1 (HMC case study) with the Metropolis-Hastings correction
+ * of Sec. 4.1; H(x, p) = -logp(x) + K(p). */
+int orc_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uint32_t t,
+                   int32_t L, double eps, double *x, double *logp, double *g,
+                   double *x_prop, double *p_prop, double *logp_prop,
+                   double *delta_h, double *log_accept_ratio)
+{
+    const int64_t D = tg->dim;
+    double *buf = (double *)malloc(sizeof(double) * 3 * (size_t)D);
+    double *xn = buf, *pn = buf + D, *gn = buf + 2 * D;
+
+    /* 1. momentum draw */
+    orc_momentum(seed, chain, t, D, pn);
+    double h0 = -(*logp) + kinetic(pn, D);
+
+    /* 2. trajectory from the current state with its cached gradient */
+    memcpy(xn, x, sizeof(double) * (size_t)D);
+    memcpy(gn, g, sizeof(double) * (size_t)D);
+    double lp = *logp;
+    orc_leapfrog(tg, eps, L, xn, pn, gn, &lp);
+    double h1 = -lp + kinetic(pn, D);
+    double dh = h1 - h0;
+
+    /* 3. Metropolis-Hastings: accept iff log u < -dH; NaN/+inf dH rejects */
+    double lar = -dh;
+    if (isnan(dh) || (isinf(dh) && dh > 0))
+        lar = -INFINITY;
+    double u = orc_accept_uniform(seed, chain, t);
+    int accepted = log(u) < lar;
+
+    if (x_prop) memcpy(x_prop, xn, sizeof(double) * (size_t)D);
+    if (p_prop) memcpy(p_prop, pn, sizeof(double) * (size_t)D);
+    if (logp_prop) *logp_prop = lp;
+    if (delta_h) *delta_h = dh;
+    if (log_accept_ratio) *log_accept_ratio = lar;
+
+    /* 4. select (the paper's vectorised where: rejected chains keep state) */
+    if (accepted) {
+        memcpy(x, xn, sizeof(double) * (size_t)D);
+        memcpy(g, gn, sizeof(double) * (size_t)D);
+        *logp = lp;
+    }
+    free(buf);
+    return accepted;
+}
+
+/* ------------------------------------------------------------------------
+ * Dual averaging (Hoffman & Gelman 2014, Sec. 3.2, eq. 6):
+ *   Hbar_m     = (1 - 1/(m + t0)) Hbar_{m-1} + (delta - alpha_m) / (m + t0)
+ *   log eps_m  = mu - sqrt(m) / gamma * Hbar_m
+ *   log ebar_m = m^-kappa log eps_m + (1 - m^-kappa) log ebar_{m-1}
+ * with mu = log(10 eps0), Hbar_0 = 0, ebar_0 = 1.
+ * ---------------------------------------------------------------------- */
+void orc_dual_avg_init(orc_dual_avg *s, double eps0)
+{
+    s->log_eps = log(eps0);
+    s->hbar = 0.0;
+    s->log_eps_bar = 0.0;
+    s->mu = log(10.0 * eps0);
+}
+
+void orc_dual_avg_update(orc_dual_avg *s, int64_t m, double alpha, double target_accept,
+                         double gamma, double t0, double kappa)
+{
+    double md = (double)m;
+    double w = 1.0 / (md + t0);
+    s->hbar = (1.0 - w) * s->hbar + w * (target_accept - alpha);
+    s->log_eps = s->mu - sqrt(md) / gamma * s->hbar;
+    double eta = pow(md, -kappa);
+    s->log_eps_bar = eta * s->log_eps + (1.0 - eta) * s->log_eps_bar;
+}
+
+/* ------------------------------------------------------------------------
+ * Batched entry points.  Chains are independent (paper Sec. 2), so the
+ * OpenMP loop runs each chain on its own; results do not depend on the
+ * thread count.
+ * ---------------------------------------------------------------------- */
+static void set_threads(int32_t nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+void orc_bootstrap(const orc_target *tg, int64_t C, const double *x, double *logp, double *g,
+                   int32_t nthreads)
+{
+    const int64_t D = tg->dim;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < C; ++c)
+        logp[c] = orc_logp_grad(tg, x + c * D, g + c * D);
+}
+
+void orc_step(const orc_target *tg, int64_t C, int32_t L, uint64_t seed, uint32_t t,
+              const double *eps, double *x, double *logp, double *g,
+              double *x_prop, double *p_prop, double *logp_prop, double *delta_h,
+              double *log_accept_ratio, uint8_t *accepted, int32_t nthreads)
+{
+    const int64_t D = tg->dim;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < C; ++c) {
+        int a = orc_transition(tg, seed, (uint32_t)c, t, L, eps[c], x + c * D, logp + c, g + c * D,
+                               x_prop ? x_prop + c * D : NULL, p_prop ? p_prop + c * D : NULL,
+                               logp_prop ? logp_prop + c : NULL, delta_h ? delta_h + c : NULL,
+                               log_accept_ratio ? log_accept_ratio + c : NULL);
+        if (accepted)
+            accepted[c] = (uint8_t)a;
+    }
+}
+
+/* Paper Sec. 4.2 (sample_chain): burn-in transitions are not stored; the
+ * state after transition burnin + r is kept sample r; tracing records the
+ * kernel results of each kept transition. */
+int orc_sample_chain(const orc_target *tg, int64_t C, int32_t L, uint64_t seed,
+                     uint32_t t_begin, double *x, double *eps,
+                     int64_t num_burnin, int64_t num_results,
+                     int32_t adapt, double target_accept, double gamma, double t0, double kappa,
+                     double *samples, double *tr_step, uint8_t *tr_acc, double *tr_lar,
+                     double *tr_logp, int32_t nthreads)
+{
+    const int64_t D = tg->dim;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < C; ++c) {
+        double *xc = x + c * D;
+        double *gc = (double *)malloc(sizeof(double) * (size_t)D);
+        double lp = orc_logp_grad(tg, xc, gc);   /* bootstrap */
+        orc_dual_avg da;
+        orc_dual_avg_init(&da, eps[c]);
+        double step = eps[c];
+        for (int64_t i = 0; i < num_burnin + num_results; ++i) {
+            uint32_t t = t_begin + (uint32_t)i;
+            double lar;
+            int a = orc_transition(tg, seed, (uint32_t)c, t, L, step, xc, &lp, gc,
+                                   NULL, NULL, NULL, NULL, &lar);
+            double used = step;
+            if (adapt && i < num_burnin) {
+                double alpha = lar < 0.0 ? exp(lar) : 1.0;   /* min(1, e^-dH); 0 for NaN */
+                orc_dual_avg_update(&da, i + 1, alpha, target_accept, gamma, t0, kappa);
+                step = (i + 1 < num_burnin) ? exp(da.log_eps) : exp(da.log_eps_bar);
+            }
+            if (i >= num_burnin) {
+                int64_t r = i - num_burnin;
+                if (samples)
+                    memcpy(samples + (r * C + c) * D, xc, sizeof(double) * (size_t)D);
+                if (tr_step) tr_step[r * C + c] = used;
+                if (tr_acc) tr_acc[r * C + c] = (uint8_t)a;
+                if (tr_lar) tr_lar[r * C + c] = lar;
+                if (tr_logp) tr_logp[r * C + c] = lp;
+            }
+        }
+        eps[c] = step;
+        free(gc);
+    }
+    return 0;
+}

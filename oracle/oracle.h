@@ -1,0 +1,136 @@
+/*
+ * oracle.h -- FP64 CPU oracle of the batched HMC transition.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
+ * correct reference that the GPU path is checked against.  Only tests/,
+ * __graft_entry__.smoke() and the cpu_baseline leg of bench.py may load it.
+ * It shares no source with the HIP library (paper_2002_01184_amd/csrc) and
+ * includes nothing from it.
+ *
+ * What it computes (paper: "tfp.mcmc: Modern Markov Chain Monte Carlo Tools
+ * Built for Modern Hardware", arXiv 2002.01184):
+ *   - Sec. 2.1 (Case Study: HMC): draw one independent Gaussian momentum per
+ *     state variable per chain, run a symplectic integrator for a fixed
+ *     number of steps, accept or reject the proposal with a
+ *     Metropolis-Hastings test; every chain is independent.
+ *   - Sec. 2 (batch semantics): the target log-probability of a [C, D]
+ *     batch reduces over the event axis D only, giving one value per chain.
+ *   - Sec. 4.1 (TransitionKernel): bootstrap computes the target
+ *     log-probability and its gradient at the initial state; one_step
+ *     carries them so they are not recomputed.
+ *   - Sec. 4.2 (Driver): sample_chain = burn-in (not stored), sampling
+ *     (stored), tracing of kernel results.
+ *   - Leapfrog integrator: Neal (2011), "MCMC using Hamiltonian dynamics",
+ *     Sec. 5.2.3.3 (cited by the paper for HMC).
+ *   - Step-size adaptation by dual averaging: Hoffman & Gelman (2014),
+ *     Sec. 3.2, eq. (6) (cited by the paper for NUTS; the adaptation-wrapper
+ *     pattern is the paper's Sec. 4.1).
+ *   - Random numbers: Philox4x32-10 from Salmon, Moraes, Dror & Shaw,
+ *     "Parallel Random Numbers: As Easy as 1, 2, 3" (SC'11); normals by the
+ *     Box-Muller transform (Box & Muller 1958).
+ *
+ * All arithmetic is double precision.  Callers upcast FP32/BF16 device
+ * arrays to double exactly before passing them here.
+ */
+#ifndef HMC_ORACLE_H
+#define HMC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_STD_NORMAL = 0, ORC_GAUSS_DIAG = 1, ORC_GAUSS_DENSE = 2, ORC_LOGREG = 3 };
+enum { ORC_TAG_MOMENTUM = 0, ORC_TAG_ACCEPT = 1 };
+
+typedef struct {
+    int32_t kind;          /* ORC_* target family */
+    int32_t reserved;
+    int64_t dim;           /* D */
+    const double *prec;    /* GAUSS_DIAG: [D]; GAUSS_DENSE: [D*D] row-major precision */
+    const double *X;       /* LOGREG: [N*D] row-major design matrix */
+    const double *y;       /* LOGREG: [N] labels in {0, 1} */
+    int64_t n_rows;        /* LOGREG: N */
+    double prior_scale;    /* LOGREG: prior N(0, prior_scale^2 I) */
+} orc_target;
+
+/* Philox4x32-10 block function (SC'11, Sec. 3.2): 10 rounds, key bumped
+ * by the Weyl constants between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Four standard normals from one Philox block keyed by seed with counter
+ * (c0, c1, c2, tag): Box-Muller on word pairs (w0,w1) and (w2,w3). */
+void orc_normal4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag, double z[4]);
+
+/* Momentum of one chain at transition t: p[i] = normal (i mod 4) of block
+ * floor(i/4) with counter (chain, t, block, MOMENTUM). */
+void orc_momentum(uint64_t seed, uint32_t chain, uint32_t t, int64_t D, double *p);
+
+/* Accept uniform of one chain at transition t, in (0, 1), from the block
+ * with counter (chain, t, 0, ACCEPT). */
+double orc_accept_uniform(uint64_t seed, uint32_t chain, uint32_t t);
+
+/* Batched helpers for tests: n Philox blocks (ctr [n*4] -> out [n*4]) under one
+ * key; momenta of chains 0..C-1 at transition t ([C*D]); accept uniforms [C]. */
+void orc_philox_many(int64_t n, const uint32_t *ctr, const uint32_t key[2], uint32_t *out);
+void orc_momentum_many(uint64_t seed, int64_t C, uint32_t t, int64_t D, double *p);
+void orc_accept_uniform_many(uint64_t seed, int64_t C, uint32_t t, double *u);
+
+/* Target log-probability (up to an additive constant) and its gradient. */
+double orc_logp_grad(const orc_target *tg, const double *x, double *g);
+
+/* L leapfrog steps from (x, p) with gradient g at x.  On return x, p hold the
+ * end of the trajectory, g and *logp the gradient and log-probability there. */
+void orc_leapfrog(const orc_target *tg, double eps, int32_t L,
+                  double *x, double *p, double *g, double *logp);
+
+/* One HMC transition of one chain.  (x, *logp, g) is the current state with
+ * its cached log-probability and gradient; it is replaced by the proposal on
+ * acceptance and left unchanged otherwise.  Optional outputs (NULL allowed):
+ * x_prop/p_prop [D] the end of the trajectory, logp_prop, delta_h.
+ * Returns 1 if accepted.  *log_accept_ratio = -dH (-inf when dH is NaN/+inf). */
+int orc_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uint32_t t,
+                   int32_t L, double eps, double *x, double *logp, double *g,
+                   double *x_prop, double *p_prop, double *logp_prop,
+                   double *delta_h, double *log_accept_ratio);
+
+/* Dual-averaging step-size state of one chain (Hoffman & Gelman 2014, eq. 6). */
+typedef struct {
+    double log_eps;      /* log step size used by the next transition */
+    double hbar;         /* running average of (target_accept - alpha) */
+    double log_eps_bar;  /* averaged log step size */
+    double mu;           /* shrinkage point log(10 * eps0) */
+} orc_dual_avg;
+
+void orc_dual_avg_init(orc_dual_avg *s, double eps0);
+/* Iteration m >= 1 with acceptance statistic alpha in [0, 1]. */
+void orc_dual_avg_update(orc_dual_avg *s, int64_t m, double alpha, double target_accept,
+                         double gamma, double t0, double kappa);
+
+/* Batched entry points over C chains ([C, D] row-major states), OpenMP over
+ * chains.  nthreads <= 0 uses the OpenMP default. */
+void orc_bootstrap(const orc_target *tg, int64_t C, const double *x, double *logp, double *g,
+                   int32_t nthreads);
+
+void orc_step(const orc_target *tg, int64_t C, int32_t L, uint64_t seed, uint32_t t,
+              const double *eps, double *x, double *logp, double *g,
+              double *x_prop, double *p_prop, double *logp_prop, double *delta_h,
+              double *log_accept_ratio, uint8_t *accepted, int32_t nthreads);
+
+/* sample_chain: transitions t_begin .. t_begin + burnin + results - 1.
+ * x [C*D] and eps [C] are read as the start and hold the final state / step
+ * size on return.  With adapt != 0 each chain runs dual averaging during the
+ * burn-in (iteration m = 1..burnin) and then uses exp(log_eps_bar).
+ * samples [R*C*D] and traces [R*C] may be NULL.  Returns 0. */
+int orc_sample_chain(const orc_target *tg, int64_t C, int32_t L, uint64_t seed,
+                     uint32_t t_begin, double *x, double *eps,
+                     int64_t num_burnin, int64_t num_results,
+                     int32_t adapt, double target_accept, double gamma, double t0, double kappa,
+                     double *samples, double *tr_step, uint8_t *tr_acc, double *tr_lar,
+                     double *tr_logp, int32_t nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,108 @@
+"""Convergence diagnostics on the host: split R-hat and effective sample size.
+
+The paper (Sec. 5, Discussion) names rank-normalized R-hat (Vehtari et al.
+2019) and the effective sample size (Geyer 2011; Gelman et al. 2013) as the
+convergence checks for many-chain MCMC; it does not define them.  This module
+follows Vehtari et al. (2019): chains are split in half, draws are rank
+normalized, R-hat is the larger of the bulk and folded (tail) values, and ESS
+uses the multi-chain autocorrelation with Geyer's initial monotone sequence.
+
+These are measurement tools (they read kept samples back from the device);
+they are not part of the sampler's hot path.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import ndtri
+
+
+def _split(x: np.ndarray) -> np.ndarray:
+    """x [n, M] -> [n//2, 2M] (first and second halves as separate chains)."""
+    n = x.shape[0] // 2
+    return np.concatenate([x[:n], x[x.shape[0] - n:]], axis=1)
+
+
+def _rank_normalize(x: np.ndarray) -> np.ndarray:
+    """Normal scores of the pooled ranks (average ranks for ties), Blom offset 3/8."""
+    from scipy.stats import rankdata
+    S = x.size
+    r = rankdata(x, method="average").reshape(x.shape)
+    return ndtri((r - 0.375) / (S + 0.25))
+
+
+def _rhat_basic(x: np.ndarray) -> float:
+    """Potential scale reduction of chains x [n, M] (Gelman et al. 2013, eq. 11.4)."""
+    n, M = x.shape
+    means = x.mean(0)
+    W = x.var(0, ddof=1).mean()
+    B = n * means.var(ddof=1)
+    var_plus = (n - 1) / n * W + B / n
+    if W == 0:
+        return np.nan
+    return float(np.sqrt(var_plus / W))
+
+
+def rhat(x: np.ndarray) -> float:
+    """Rank-normalized split R-hat of one scalar quantity; x is [n_draws, n_chains]."""
+    xs = _split(np.asarray(x, dtype=np.float64))
+    bulk = _rhat_basic(_rank_normalize(xs))
+    folded = np.abs(xs - np.median(xs))
+    tail = _rhat_basic(_rank_normalize(folded))
+    return float(max(bulk, tail))
+
+
+def _autocov(x: np.ndarray) -> np.ndarray:
+    """Per-chain autocovariance (biased, divided by n) for lags 0..n-1; x [n, M]."""
+    n = x.shape[0]
+    xc = x - x.mean(0)
+    nfft = 1 << int(np.ceil(np.log2(2 * n)))
+    f = np.fft.rfft(xc, n=nfft, axis=0)
+    ac = np.fft.irfft(f * np.conj(f), n=nfft, axis=0)[:n]
+    return ac / n
+
+
+def ess(x: np.ndarray) -> float:
+    """Effective sample size of chains x [n, M] (no splitting or normalization).
+
+    rho_t = 1 - (W - mean_m(acov_{t,m})) / var_plus, summed over Geyer's initial
+    positive sequence of pair sums with the monotone correction."""
+    x = np.asarray(x, dtype=np.float64)
+    n, M = x.shape
+    if n < 4:
+        return np.nan
+    acov = _autocov(x)                         # [n, M]
+    chain_var = acov[0] * n / (n - 1.0)
+    W = chain_var.mean()
+    var_plus = W * (n - 1.0) / n
+    if M > 1:
+        var_plus += x.mean(0).var(ddof=1)
+    if var_plus <= 0:
+        return np.nan
+    rho = 1.0 - (W - acov.mean(1)) / var_plus
+    rho[0] = 1.0
+    # Geyer: pair sums P_k = rho_2k + rho_2k+1, keep the initial positive run,
+    # and make it monotone non-increasing.
+    npairs = n // 2
+    P = rho[0:2 * npairs:2] + rho[1:2 * npairs:2]
+    k = 0
+    while k < npairs and P[k] > 0:
+        k += 1
+    P = np.minimum.accumulate(P[:k]) if k > 0 else P[:0]
+    tau = -1.0 + 2.0 * P.sum()
+    tau = max(tau, 1.0 / np.log10(n * M))
+    return float(n * M / tau)
+
+
+def ess_bulk(x: np.ndarray) -> float:
+    """Bulk ESS: ESS of the rank-normalized split chains; x is [n_draws, n_chains]."""
+    return ess(_rank_normalize(_split(np.asarray(x, dtype=np.float64))))
+
+
+def summarize(samples: np.ndarray, max_dims: int | None = None) -> dict:
+    """samples [R, C, D] -> min bulk-ESS and max R-hat over coordinates."""
+    R, C, D = samples.shape
+    dims = range(D) if max_dims is None else range(min(D, max_dims))
+    e = [ess_bulk(samples[:, :, d]) for d in dims]
+    r = [rhat(samples[:, :, d]) for d in dims]
+    return dict(min_ess_bulk=float(np.min(e)), max_rhat=float(np.max(r)),
+                ess_bulk=np.array(e), rhat=np.array(r))
