@@ -1,0 +1,179 @@
+"""Benchmark of the batched HMC hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--form auto|plain|graph|fused]
+
+One step = one complete sample_chain pass over the workload: reset the chains
+to the seeded start (bootstrap of logp and gradient), then burn-in with
+dual-averaging adaptation and sampling, every chain doing momentum draw,
+L leapfrog steps, energy, accept/select, adaptation, sample and trace writes.
+`value` is leapfrog chain-steps per second over the K timed steps (inputs
+resident in HBM).  ESS/s (bulk ESS, min over coordinates) is reported when the
+max split R-hat <= 1.01.  The roofline object refers to the dominant kernel,
+timed with HIP events on the stream it runs on; the cpu_baseline object is the
+FP64 oracle on a bounded sample of the same workload on the host's cores.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "leapfrog chain-steps/sec and ESS/sec at R-hat≤1.01; p50/p99 request latency"
+PEAK = {"fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12}
+
+
+def algorithmic_work(w):
+    """(kind, per chain-step amount, unit) of the dominant contraction / traffic."""
+    import workloads as W
+    if w.kind == W.LOGREG:
+        return "mfma", 4.0 * w.n_rows * w.dim, "flop"          # X theta and X^T r
+    if w.kind == W.GAUSS_DENSE:
+        return "mfma", 2.0 * w.dim * w.dim, "flop"             # P x
+    es = 8 if w.state_dtype == "f64" else 4
+    return "hbm", 4.0 * es * w.dim, "byte"                      # read x, p; write x, p
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The FP64 oracle, as it stands, on a bounded sample: the first c chains of
+    the same workload (Philox is keyed by chain id, so they are the same chains)
+    over the full burn-in + sampling schedule, OpenMP over chains."""
+    import numpy as np
+
+    import oracle
+    ncores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    tg = oracle.Target(w.kind, w.dim, prec=w.prec64(), X=w.X64(), y=w.y64(), prior_scale=w.prior_scale)
+    T = w.num_burnin + w.num_results
+    # calibrate on one chain with a short schedule
+    t0 = time.perf_counter()
+    probe_T = max(1, min(T, 20))
+    oracle.sample_chain(tg, w.num_leapfrog_steps, w.seed, w.x0[:1].astype(np.float64), w.step_size,
+                        min(w.num_burnin, probe_T), probe_T - min(w.num_burnin, probe_T), adapt=w.adapt,
+                        store_samples=False, nthreads=1)
+    per_chain_step = (time.perf_counter() - t0) / (probe_T * w.num_leapfrog_steps)
+    # chains x transitions that fit the budget on ncores
+    full_chain_s = per_chain_step * T * w.num_leapfrog_steps
+    nchains = int(max(1, min(w.num_chains, budget_s * ncores / max(full_chain_s, 1e-9))))
+    if nchains >= ncores:
+        nchains = (nchains // ncores) * ncores
+        Ts, B = T, w.num_burnin
+    else:
+        nchains = min(w.num_chains, ncores)
+        Ts = int(max(2, min(T, budget_s / max(per_chain_step * w.num_leapfrog_steps, 1e-12))))
+        B = min(w.num_burnin, Ts // 2)
+    t0 = time.perf_counter()
+    oracle.sample_chain(tg, w.num_leapfrog_steps, w.seed, w.x0[:nchains].astype(np.float64), w.step_size,
+                        B, Ts - B, adapt=w.adapt, store_samples=False, nthreads=ncores)
+    el = time.perf_counter() - t0
+    value = nchains * w.num_leapfrog_steps * Ts / el
+    return {"value": value, "unit": "leapfrog chain-steps/s", "cores": ncores, "kind": "oracle",
+            "sample": f"first {nchains} of {w.num_chains} chains x {Ts} transitions (L={w.num_leapfrog_steps}), "
+                      f"FP64, {el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="logreg_1000x25")
+    ap.add_argument("--form", default="auto", choices=["auto", "plain", "graph", "fused"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-diagnostics", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X "
+              "(chains shard across GPUs without communication; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2002_01184_amd import diagnostics as dg
+    from paper_2002_01184_amd import hmc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = W.CONFIGS[args.config]()
+    form = {"auto": hmc.HMC_FORM_AUTO, "plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_GRAPH,
+            "fused": hmc.HMC_FORM_FUSED}[args.form]
+    s = hmc.sampler_for(w, device=dev, form=form)
+    x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).to(dev)
+    eps0 = torch.full((w.num_chains,), float(w.step_size), dtype=torch.float64, device=dev)
+    T = w.num_burnin + w.num_results
+    stream = torch.cuda.current_stream(dev)
+
+    def one_step(ev=None):
+        s.set_state(x0, eps0, 0)
+        if ev is not None:
+            ev[0].record(stream)
+        out = s.sample_chain(w.num_results, w.num_burnin, adapt=w.adapt)
+        if ev is not None:
+            ev[1].record(stream)
+        return out
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for k in range(args.steps):
+        out = one_step(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    chain_steps = w.chain_steps() * args.steps
+    value = chain_steps / elapsed
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+    bound, per_cs, unit = algorithmic_work(w)
+    if bound == "mfma":
+        peak = PEAK["bf16_mfma"] if (w.X_bf16 is not None and False) else PEAK["fp32_mfma"]
+        achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None}
+    else:
+        achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK["hbm"], "traffic": None}
+    roof["kernel"] = {hmc.HMC_FORM_FUSED: "fused transition kernel", hmc.HMC_FORM_PLAIN: "plain kernels",
+                      hmc.HMC_FORM_GRAPH: "plain kernels (graph)"}.get(hmc.hmc_effective_form(s.ctx))
+    roof["kernel_ms_per_launch"] = kernel_ms
+    roof["work_per_launch"] = per_cs * w.chain_steps()
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "leapfrog chain-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if w.state_dtype == "f64" else "f32",
+        "data": "synthetic (seeded; shapes of the paper's workloads)",
+        "config": {"workload": w.name, "num_chains": w.num_chains, "dim": w.dim, "n_rows": w.n_rows,
+                   "num_leapfrog_steps": w.num_leapfrog_steps, "num_burnin": w.num_burnin,
+                   "num_results": w.num_results, "adapt": "dual averaging to 0.8" if w.adapt else "none",
+                   "form": s.form, "parallelism": "chains (1 GPU)"},
+        "roofline": roof,
+    }
+    if not args.no_diagnostics and out.get("samples") is not None:
+        smp = out["samples"].float().cpu().numpy()
+        summ = dg.summarize(smp)
+        result["max_rhat"] = summ["max_rhat"]
+        result["min_ess_bulk"] = summ["min_ess_bulk"]
+        result["ess_per_sec"] = (summ["min_ess_bulk"] / (elapsed / args.steps)) if summ["max_rhat"] <= 1.01 else None
+        result["accept_rate"] = float(out["is_accepted"].float().mean().item())
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    s.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

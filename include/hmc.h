@@ -1,0 +1,183 @@
+/*
+ * hmc.h -- C ABI of libhmc.so: batched Hamiltonian Monte Carlo on MI355X (gfx950).
+ *
+ * One HMC transition applied to thousands of independent chains at once
+ * (arXiv 2002.01184, Sec. 2.1 "Case Study: HMC"): per chain, a Gaussian
+ * momentum with one independent component per state variable, L leapfrog
+ * steps each evaluating the target log-probability and its gradient, and a
+ * Metropolis-Hastings accept/reject on the energy change dH, taken as a
+ * per-chain select (Sec. 2.1, last paragraph: vectorised where, no branch).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every call returns hmc_status; HMC_OK is 0.  On a non-OK status a
+ *    message is available from hmc_last_error() (thread-local) and no state
+ *    was changed.  Nothing else crosses the ABI (no exceptions).
+ *  - Device pointers are HIP device memory on the current device (allocated
+ *    by the caller, e.g. PyTorch); host pointers are marked "host".  The
+ *    library borrows every caller buffer and never frees it; buffers passed to
+ *    hmc_init must stay alive until hmc_destroy.
+ *  - States are [C, D] row-major ("list of vectors", Sec. 2.1: one row per
+ *    chain), in the configured state dtype.  Per-chain scalars are [C].
+ *    log-probabilities, energies, step sizes and log accept ratios are FP64.
+ *  - Batch semantics (Sec. 2): the target log-probability of a [C, D] batch
+ *    reduces over D only; chain c's results never depend on other chains.
+ *  - All work is enqueued on the hipStream_t given to hmc_init and is
+ *    asynchronous; hmc_get_state and hmc_destroy synchronize that stream.
+ *    A device fault surfaces as HMC_E_DEVICE at the next synchronizing call.
+ *  - One context is used by one host thread at a time.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed low
+ *    word, seed high word), counter = (chain, t, block, tag); tag 0 =
+ *    momentum (block = d / 4, Box-Muller on word pairs (0,1), (2,3) with
+ *    u = ((w >> 9) + 1/2) 2^-23), tag 1 = accept uniform
+ *    u = ((w0 >> 6) 2^26 + (w1 >> 6) + 1/2) 2^-52.  t counts transitions
+ *    since hmc_init (or the value given to hmc_set_state).
+ */
+#ifndef HMC_H
+#define HMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HMC_OK = 0,
+    HMC_E_INVALID = 1,      /* bad argument: sizes, null pointers, non-finite step size */
+    HMC_E_UNSUPPORTED = 2,  /* valid but unsupported combination (dtype x target x form) */
+    HMC_E_NOMEM = 3,        /* workspace smaller than hmc_workspace_size() */
+    HMC_E_DEVICE = 4,       /* HIP runtime or kernel error */
+    HMC_E_BUSY = 5          /* serving: no capacity for the request right now */
+} hmc_status;
+
+typedef enum { HMC_F64 = 0, HMC_F32 = 1, HMC_BF16 = 2 } hmc_dtype;
+
+typedef enum {
+    HMC_TGT_STD_NORMAL = 0,   /* logp = -1/2 |x|^2 (the paper's Sec. 1 example, any D) */
+    HMC_TGT_GAUSS_DIAG = 1,   /* logp = -1/2 sum_i prec_i x_i^2 */
+    HMC_TGT_GAUSS_DENSE = 2,  /* logp = -1/2 x^T P x, P symmetric positive definite */
+    HMC_TGT_LOGREG = 3        /* Bayesian logistic regression, prior N(0, s^2 I):
+                                 logp = sum_n [y_n z_n - softplus(z_n)] - |x|^2/(2 s^2), z = X x */
+} hmc_target_kind;
+
+/* Built-in target (the paper's Sec. 3 Python callable cannot run on the GPU;
+ * the target is a descriptor of one of these families with hand-written
+ * gradients).  All arrays are device memory, borrowed. */
+typedef struct hmc_target {
+    int32_t kind;             /* hmc_target_kind */
+    int32_t reserved0;
+    int64_t dim;              /* D >= 1 */
+    const void* prec;         /* DIAG: [D]; DENSE: [D, D] row-major; dtype = state dtype */
+    const void* X;            /* LOGREG: [N, D] row-major, dtype x_dtype */
+    int32_t x_dtype;          /* LOGREG: HMC_F32 or HMC_BF16 */
+    int32_t reserved1;
+    int64_t n_rows;           /* LOGREG: N >= 1 */
+    const uint8_t* y;         /* LOGREG: [N] labels, each 0 or 1 */
+    double prior_scale;       /* LOGREG: s > 0 */
+} hmc_target;
+
+/* Execution form. */
+enum {
+    HMC_FORM_AUTO = 0,        /* fused where the target's shape allows, else plain */
+    HMC_FORM_PLAIN = 1,       /* one kernel per leapfrog step, state in HBM between steps */
+    HMC_FORM_FUSED = 2,       /* persistent kernel: whole transitions per chain tile in registers/LDS */
+    HMC_FORM_GRAPH = 3        /* plain kernels replayed from a captured hipGraph */
+};
+
+typedef struct hmc_config {
+    int64_t num_chains;          /* C >= 1 */
+    int32_t num_leapfrog_steps;  /* L >= 1 */
+    int32_t state_dtype;         /* HMC_F64 (elementwise targets) or HMC_F32 */
+    int32_t grad_dtype;          /* HMC_F32, or HMC_BF16 (LOGREG with BF16 X: MFMA operands in BF16,
+                                    FP32 accumulation; logp for dH from an FP32 logit pass) */
+    int32_t form;                /* HMC_FORM_* */
+    uint64_t seed;               /* Philox key */
+} hmc_config;
+
+/* Dual averaging of the per-chain step size during burn-in (Hoffman &
+ * Gelman 2014, Sec. 3.2, eq. 6), adaptation wrapper pattern of the paper's
+ * Sec. 4.1.  mu = log(10 eps0) with eps0 each chain's step size at the start
+ * of hmc_sample_chain; after burn-in each chain uses exp(log eps_bar). */
+typedef struct hmc_adapt {
+    int32_t enabled;
+    int32_t reserved;
+    double target_accept;        /* delta, e.g. 0.8 */
+    double gamma;                /* 0.05 */
+    double t0;                   /* 10 */
+    double kappa;                /* 0.75 */
+} hmc_adapt;
+
+/* Trace of kept transitions (paper Sec. 4.2 "tracing"): each pointer is a
+ * device array [R, C] or NULL. */
+typedef struct hmc_trace {
+    double* step_size;           /* step size used by the transition */
+    uint8_t* is_accepted;
+    double* log_accept_ratio;    /* -dH; -inf when dH is NaN or +inf */
+    double* target_log_prob;     /* logp of the post-decision state */
+} hmc_trace;
+
+/* Optional per-transition outputs of hmc_step (device pointers or NULL). */
+typedef struct hmc_step_out {
+    uint8_t* is_accepted;        /* [C] */
+    double* log_accept_ratio;    /* [C] */
+    double* target_log_prob;     /* [C] post-decision */
+    void* proposed_state;        /* [C, D] state dtype: end of the trajectory before the decision */
+    void* proposed_momentum;     /* [C, D] state dtype: momentum at the end of the trajectory */
+    double* delta_h;             /* [C] H(end) - H(start) */
+} hmc_step_out;
+
+typedef struct hmc_ctx hmc_ctx;
+
+/* Bytes of device workspace hmc_init needs for this target and config. */
+hmc_status hmc_workspace_size(const hmc_target* target, const hmc_config* config, size_t* bytes);
+
+/* bootstrap_results (paper Sec. 4.1): binds the target, copies init_state
+ * [C, D] (device) into the context, evaluates logp and its gradient there and
+ * caches them, sets t = 0.  step_size (host) holds 1 value (broadcast) or C
+ * values, each finite and > 0.  workspace (device) must hold
+ * hmc_workspace_size() bytes, 256-byte aligned.  hip_stream is a hipStream_t
+ * (NULL = default stream).  On HMC_OK *out owns a host object freed by
+ * hmc_destroy. */
+hmc_status hmc_init(const hmc_target* target, const hmc_config* config, const void* init_state,
+                    const double* step_size, int64_t step_size_len, void* workspace,
+                    size_t workspace_bytes, void* hip_stream, hmc_ctx** out);
+
+/* one_step (paper Sec. 4.1): one transition of every chain; t += 1.
+ * Exactly L gradient evaluations per chain (the cached gradient starts the
+ * trajectory).  out may be NULL. */
+hmc_status hmc_step(hmc_ctx* ctx, const hmc_step_out* out);
+
+/* sample_chain (paper Sec. 4.2): num_burnin + num_results transitions.  Burn-in
+ * states are not stored; samples [R, C, D] (device, state dtype) receives the
+ * state after transition burnin + r, r = 0..R-1.  adapt (host, NULL = off)
+ * enables dual averaging over the burn-in.  trace (host struct of device
+ * pointers) may be NULL.  samples may be NULL (no samples stored). */
+hmc_status hmc_sample_chain(hmc_ctx* ctx, int64_t num_results, int64_t num_burnin_steps,
+                            const hmc_adapt* adapt, void* samples, const hmc_trace* trace);
+
+/* Checkpoint (synchronizes): state [C, D] (device) and step_size [C] (device,
+ * FP64) may be NULL; *t (host) may be NULL. */
+hmc_status hmc_get_state(hmc_ctx* ctx, void* state, double* step_size, uint64_t* t);
+
+/* Resume: replaces the state (device [C, D]) and, if step_size (device [C],
+ * FP64) is not NULL, the step sizes; recomputes the cached logp and gradient;
+ * sets the transition counter to t.  Runs resumed this way reproduce an
+ * uninterrupted run bit for bit. */
+hmc_status hmc_set_state(hmc_ctx* ctx, const void* state, const double* step_size, uint64_t t);
+
+/* Frees the context (synchronizes its stream first).  NULL is a no-op. */
+hmc_status hmc_destroy(hmc_ctx* ctx);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+const char* hmc_last_error(void);
+
+/* Form that hmc_step / hmc_sample_chain will use for this context
+ * (HMC_FORM_PLAIN, HMC_FORM_FUSED or HMC_FORM_GRAPH). */
+int32_t hmc_effective_form(const hmc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,385 @@
+// hmc_api.hip -- the C ABI of libhmc.so (include/hmc.h): argument checks,
+// workspace layout, form selection and stream-ordered launches.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hmc_internal.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+
+hmc_status fail(hmc_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+hmc_status check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return HMC_OK;
+    return fail(HMC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+}  // namespace
+
+struct hmc_ctx {
+    hmc::PlainArgs a;
+    hmc_config cfg;
+    hipStream_t stream;
+    uint64_t t;
+    int32_t form;            // effective form
+    hipGraphExec_t graph_exec;
+    bool graph_ready;
+};
+
+namespace hmc {
+
+size_t elem_size(int32_t dtype) { return dtype == HMC_F64 ? 8 : (dtype == HMC_BF16 ? 2 : 4); }
+
+Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg, size_t* total) {
+    const int64_t C = cfg.num_chains, D = tg.D;
+    const size_t es = elem_size(cfg.state_dtype);
+    const size_t state = (size_t)C * D * es;
+    const int64_t nsplit = tg.kind == HMC_TGT_LOGREG ? logreg_nsplit(tg.N, C) : 0;
+    char* p = (char*)base;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        void* r = p ? (void*)(p + off) : nullptr;
+        off += align256(n);
+        return r;
+    };
+    Workspace w;
+    w.x = take(state);
+    w.g = take(state);
+    w.logp = (double*)take((size_t)C * 8);
+    w.eps = (double*)take((size_t)C * 8);
+    w.da = (DualAvg*)take((size_t)C * sizeof(DualAvg));
+    w.xq = take(state);
+    w.pq = take(state);
+    w.gq = take(state);
+    w.lpq = (double*)take((size_t)C * 8);
+    w.h0 = (double*)take((size_t)C * 8);
+    w.part_g = (float*)take((size_t)nsplit * C * D * 4);
+    w.part_lp = (double*)take((size_t)nsplit * C * 8);
+    w.ctrl = (Ctrl*)take(sizeof(Ctrl));
+    w.bytes = off;
+    if (total) *total = off;
+    return w;
+}
+
+}  // namespace hmc
+
+using namespace hmc;
+
+static hmc_status validate(const hmc_target* tg, const hmc_config* cfg, TargetDev* out) {
+    if (!tg || !cfg) return fail(HMC_E_INVALID, "target and config must not be NULL");
+    if (tg->dim < 1) return fail(HMC_E_INVALID, "target dim must be >= 1");
+    if (cfg->num_chains < 1) return fail(HMC_E_INVALID, "num_chains must be >= 1");
+    if (cfg->num_chains > (int64_t)0x7fffffff) return fail(HMC_E_INVALID, "num_chains must be < 2^31");
+    if (cfg->num_leapfrog_steps < 1) return fail(HMC_E_INVALID, "num_leapfrog_steps must be >= 1");
+    if (cfg->state_dtype != HMC_F32 && cfg->state_dtype != HMC_F64)
+        return fail(HMC_E_UNSUPPORTED, "state_dtype must be HMC_F32 or HMC_F64");
+    if (cfg->grad_dtype != HMC_F32 && cfg->grad_dtype != HMC_BF16)
+        return fail(HMC_E_UNSUPPORTED, "grad_dtype must be HMC_F32 or HMC_BF16");
+    if (cfg->form < HMC_FORM_AUTO || cfg->form > HMC_FORM_GRAPH) return fail(HMC_E_INVALID, "unknown form");
+    TargetDev t{};
+    t.kind = tg->kind;
+    t.D = tg->dim;
+    t.prec = tg->prec;
+    t.X = tg->X;
+    t.N = tg->n_rows;
+    t.y = tg->y;
+    t.inv_var = 1.0;
+    switch (tg->kind) {
+    case HMC_TGT_STD_NORMAL:
+        break;
+    case HMC_TGT_GAUSS_DIAG:
+    case HMC_TGT_GAUSS_DENSE:
+        if (!tg->prec) return fail(HMC_E_INVALID, "Gaussian target needs prec");
+        if (tg->kind == HMC_TGT_GAUSS_DENSE && cfg->state_dtype != HMC_F32)
+            return fail(HMC_E_UNSUPPORTED, "dense Gaussian runs in FP32 state");
+        if (tg->kind == HMC_TGT_GAUSS_DENSE && tg->dim > 1024)
+            return fail(HMC_E_UNSUPPORTED, "dense Gaussian supports D <= 1024");
+        break;
+    case HMC_TGT_LOGREG:
+        if (!tg->X || !tg->y) return fail(HMC_E_INVALID, "logistic regression needs X and y");
+        if (tg->n_rows < 1) return fail(HMC_E_INVALID, "n_rows must be >= 1");
+        if (!(tg->prior_scale > 0.0) || !std::isfinite(tg->prior_scale))
+            return fail(HMC_E_INVALID, "prior_scale must be finite and > 0");
+        if (tg->x_dtype != HMC_F32 && tg->x_dtype != HMC_BF16)
+            return fail(HMC_E_UNSUPPORTED, "X must be HMC_F32 or HMC_BF16");
+        if (cfg->state_dtype != HMC_F32) return fail(HMC_E_UNSUPPORTED, "logistic regression runs in FP32 state");
+        if (tg->dim > 512) return fail(HMC_E_UNSUPPORTED, "logistic regression supports D <= 512");
+        t.x_bf16 = tg->x_dtype == HMC_BF16;
+        t.inv_var = 1.0 / (tg->prior_scale * tg->prior_scale);
+        break;
+    default:
+        return fail(HMC_E_INVALID, "unknown target kind");
+    }
+    if (cfg->grad_dtype == HMC_BF16 && !(tg->kind == HMC_TGT_LOGREG && tg->x_dtype == HMC_BF16))
+        return fail(HMC_E_UNSUPPORTED, "BF16 gradients need a logistic-regression target with BF16 X");
+    if (out) *out = t;
+    return HMC_OK;
+}
+
+extern "C" {
+
+const char* hmc_last_error(void) { return g_last_error.c_str(); }
+
+hmc_status hmc_workspace_size(const hmc_target* target, const hmc_config* config, size_t* bytes) {
+    TargetDev t;
+    hmc_status st = validate(target, config, &t);
+    if (st != HMC_OK) return st;
+    if (!bytes) return fail(HMC_E_INVALID, "bytes must not be NULL");
+    carve_workspace(nullptr, t, *config, bytes);
+    return HMC_OK;
+}
+
+static hmc_status upload_eps(hmc_ctx* ctx, const double* step_size, int64_t len) {
+    const int64_t C = ctx->a.C;
+    std::vector<double> eps((size_t)C);
+    for (int64_t c = 0; c < C; ++c) eps[(size_t)c] = step_size[len == 1 ? 0 : c];
+    hmc_status st = check_hip(hipMemcpyAsync(ctx->a.ws.eps, eps.data(), (size_t)C * 8, hipMemcpyHostToDevice,
+                                             ctx->stream), "upload step sizes");
+    if (st != HMC_OK) return st;
+    return check_hip(hipStreamSynchronize(ctx->stream), "upload step sizes");
+}
+
+static Ctrl base_ctrl(const hmc_ctx* ctx) {
+    Ctrl c;
+    memset(&c, 0, sizeof(c));
+    c.t = ctx->t;
+    c.t_begin = ctx->t;
+    return c;
+}
+
+hmc_status hmc_init(const hmc_target* target, const hmc_config* config, const void* init_state,
+                    const double* step_size, int64_t step_size_len, void* workspace, size_t workspace_bytes,
+                    void* hip_stream, hmc_ctx** out) {
+    TargetDev t;
+    hmc_status st = validate(target, config, &t);
+    if (st != HMC_OK) return st;
+    if (!out) return fail(HMC_E_INVALID, "out must not be NULL");
+    if (!init_state) return fail(HMC_E_INVALID, "init_state must not be NULL");
+    if (!step_size) return fail(HMC_E_INVALID, "step_size must not be NULL");
+    if (step_size_len != 1 && step_size_len != config->num_chains)
+        return fail(HMC_E_INVALID, "step_size_len must be 1 or num_chains");
+    for (int64_t i = 0; i < step_size_len; ++i)
+        if (!(step_size[i] > 0.0) || !std::isfinite(step_size[i]))
+            return fail(HMC_E_INVALID, "step sizes must be finite and > 0");
+    size_t need = 0;
+    carve_workspace(nullptr, t, *config, &need);
+    if (!workspace) return fail(HMC_E_INVALID, "workspace must not be NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(HMC_E_INVALID, "workspace must be 256-byte aligned");
+    if (workspace_bytes < need) return fail(HMC_E_NOMEM, "workspace smaller than hmc_workspace_size()");
+
+    hmc_ctx* ctx = new hmc_ctx();
+    ctx->cfg = *config;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->t = 0;
+    ctx->graph_ready = false;
+    ctx->graph_exec = nullptr;
+    PlainArgs& a = ctx->a;
+    a.tg = t;
+    a.C = config->num_chains;
+    a.L = config->num_leapfrog_steps;
+    a.f64 = config->state_dtype == HMC_F64;
+    a.bf16_grad = config->grad_dtype == HMC_BF16;
+    a.key = make_key(config->seed);
+    a.ws = carve_workspace(workspace, t, *config, nullptr);
+
+    const bool can_fuse = fused_supported(a);
+    switch (config->form) {
+    case HMC_FORM_AUTO: ctx->form = can_fuse ? HMC_FORM_FUSED : HMC_FORM_PLAIN; break;
+    case HMC_FORM_FUSED:
+        if (!can_fuse) {
+            delete ctx;
+            return fail(HMC_E_UNSUPPORTED, "no fused kernel for this target shape");
+        }
+        ctx->form = HMC_FORM_FUSED;
+        break;
+    default: ctx->form = config->form;
+    }
+    if (a.bf16_grad && ctx->form != HMC_FORM_FUSED) {
+        // BF16 MFMA operands exist only in the fused logistic kernels
+        delete ctx;
+        return fail(HMC_E_UNSUPPORTED, "BF16 gradients need the fused form");
+    }
+
+    st = upload_eps(ctx, step_size, step_size_len);
+    if (st == HMC_OK) st = check_hip(launch_set_ctrl(base_ctrl(ctx), a.ws.ctrl, ctx->stream), "init control");
+    if (st == HMC_OK) st = check_hip(launch_da_init(a, ctx->stream), "init adaptation");
+    if (st == HMC_OK) st = check_hip(launch_bootstrap(a, init_state, ctx->stream), "bootstrap");
+    if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "bootstrap");
+    if (st != HMC_OK) {
+        delete ctx;
+        return st;
+    }
+    *out = ctx;
+    return HMC_OK;
+}
+
+int32_t hmc_effective_form(const hmc_ctx* ctx) { return ctx ? ctx->form : -1; }
+
+static hmc_status ensure_graph(hmc_ctx* ctx) {
+    if (ctx->graph_ready) return HMC_OK;
+    hipStream_t cs;
+    hmc_status st = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "graph stream");
+    if (st != HMC_OK) return st;
+    hipGraph_t graph = nullptr;
+    st = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (st == HMC_OK) {
+        hipError_t le = launch_plain_transition(ctx->a, false, cs);
+        hipError_t ee = hipStreamEndCapture(cs, &graph);
+        st = check_hip(le != hipSuccess ? le : ee, "capture transition");
+    }
+    if (st == HMC_OK) st = check_hip(hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0), "instantiate");
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (st == HMC_OK) ctx->graph_ready = true;
+    return st;
+}
+
+static hmc_status run_transitions(hmc_ctx* ctx, int64_t n, bool copy_proposal) {
+    if (ctx->form == HMC_FORM_GRAPH && !copy_proposal) {
+        hmc_status st = ensure_graph(ctx);
+        if (st != HMC_OK) return st;
+        for (int64_t i = 0; i < n; ++i) {
+            st = check_hip(hipGraphLaunch(ctx->graph_exec, ctx->stream), "graph launch");
+            if (st != HMC_OK) return st;
+        }
+        return HMC_OK;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        hmc_status st = check_hip(launch_plain_transition(ctx->a, copy_proposal, ctx->stream), "transition");
+        if (st != HMC_OK) return st;
+    }
+    return HMC_OK;
+}
+
+hmc_status hmc_step(hmc_ctx* ctx, const hmc_step_out* out) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    hmc_step_out o;
+    memset(&o, 0, sizeof(o));
+    if (out) o = *out;
+    hmc_status st;
+    if (ctx->form == HMC_FORM_FUSED) {
+        FusedRun r;
+        memset(&r, 0, sizeof(r));
+        r.t_begin = ctx->t;
+        r.n_transitions = 1;
+        r.out = o;
+        st = check_hip(launch_fused(ctx->a, r, ctx->stream), "fused step");
+    } else {
+        Ctrl c = base_ctrl(ctx);
+        c.out_acc = o.is_accepted;
+        c.out_lar = o.log_accept_ratio;
+        c.out_logp = o.target_log_prob;
+        c.out_xprop = o.proposed_state;
+        c.out_pprop = o.proposed_momentum;
+        c.out_dh = o.delta_h;
+        st = check_hip(launch_set_ctrl(c, ctx->a.ws.ctrl, ctx->stream), "step control");
+        if (st == HMC_OK) st = run_transitions(ctx, 1, o.proposed_state || o.proposed_momentum);
+    }
+    if (st == HMC_OK) ctx->t += 1;
+    return st;
+}
+
+hmc_status hmc_sample_chain(hmc_ctx* ctx, int64_t num_results, int64_t num_burnin_steps, const hmc_adapt* adapt,
+                            void* samples, const hmc_trace* trace) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (num_results < 0 || num_burnin_steps < 0) return fail(HMC_E_INVALID, "negative transition count");
+    const bool ad = adapt && adapt->enabled;
+    if (ad) {
+        if (!(adapt->target_accept > 0.0 && adapt->target_accept < 1.0) || !(adapt->gamma > 0.0) ||
+            !(adapt->t0 >= 0.0) || !(adapt->kappa > 0.0))
+            return fail(HMC_E_INVALID, "adaptation parameters out of range");
+    }
+    const int64_t total = num_results + num_burnin_steps;
+    if (ctx->t + (uint64_t)total > 0xffffffffull) return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
+    hmc_trace tr;
+    memset(&tr, 0, sizeof(tr));
+    if (trace) tr = *trace;
+    hmc_status st = HMC_OK;
+    if (ad) st = check_hip(launch_da_init(ctx->a, ctx->stream), "adaptation init");
+    if (st != HMC_OK) return st;
+    if (total == 0) return HMC_OK;
+    if (ctx->form == HMC_FORM_FUSED) {
+        FusedRun r;
+        memset(&r, 0, sizeof(r));
+        r.t_begin = ctx->t;
+        r.n_transitions = total;
+        r.n_burnin = num_burnin_steps;
+        r.adapt = ad;
+        if (ad) {
+            r.target_accept = adapt->target_accept;
+            r.gamma = adapt->gamma;
+            r.t0 = adapt->t0;
+            r.kappa = adapt->kappa;
+        }
+        r.samples = samples;
+        r.trace = tr;
+        st = check_hip(launch_fused(ctx->a, r, ctx->stream), "fused sample_chain");
+    } else {
+        Ctrl c = base_ctrl(ctx);
+        c.n_burnin = num_burnin_steps;
+        c.n_results = num_results;
+        c.adapt = ad;
+        if (ad) {
+            c.target_accept = adapt->target_accept;
+            c.gamma = adapt->gamma;
+            c.t0 = adapt->t0;
+            c.kappa = adapt->kappa;
+        }
+        c.samples = samples;
+        c.tr_step = tr.step_size;
+        c.tr_acc = tr.is_accepted;
+        c.tr_lar = tr.log_accept_ratio;
+        c.tr_logp = tr.target_log_prob;
+        st = check_hip(launch_set_ctrl(c, ctx->a.ws.ctrl, ctx->stream), "sample_chain control");
+        if (st == HMC_OK) st = run_transitions(ctx, total, false);
+    }
+    if (st == HMC_OK) ctx->t += (uint64_t)total;
+    return st;
+}
+
+hmc_status hmc_get_state(hmc_ctx* ctx, void* state, double* step_size, uint64_t* t) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    const size_t es = ctx->a.f64 ? 8 : 4;
+    hmc_status st = HMC_OK;
+    if (state)
+        st = check_hip(hipMemcpyAsync(state, ctx->a.ws.x, (size_t)ctx->a.C * ctx->a.tg.D * es,
+                                      hipMemcpyDeviceToDevice, ctx->stream), "copy state");
+    if (st == HMC_OK && step_size)
+        st = check_hip(hipMemcpyAsync(step_size, ctx->a.ws.eps, (size_t)ctx->a.C * 8, hipMemcpyDeviceToDevice,
+                                      ctx->stream), "copy step size");
+    if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "get_state");
+    if (st == HMC_OK && t) *t = ctx->t;
+    return st;
+}
+
+hmc_status hmc_set_state(hmc_ctx* ctx, const void* state, const double* step_size, uint64_t t) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (!state) return fail(HMC_E_INVALID, "state must not be NULL");
+    if (t > 0xffffffffull) return fail(HMC_E_INVALID, "t must be < 2^32");
+    hmc_status st = HMC_OK;
+    if (step_size)
+        st = check_hip(hipMemcpyAsync(ctx->a.ws.eps, step_size, (size_t)ctx->a.C * 8, hipMemcpyDeviceToDevice,
+                                      ctx->stream), "set step size");
+    ctx->t = t;
+    if (st == HMC_OK) st = check_hip(launch_set_ctrl(base_ctrl(ctx), ctx->a.ws.ctrl, ctx->stream), "set control");
+    if (st == HMC_OK) st = check_hip(launch_bootstrap(ctx->a, state, ctx->stream), "bootstrap");
+    return st;
+}
+
+hmc_status hmc_destroy(hmc_ctx* ctx) {
+    if (!ctx) return HMC_OK;
+    hmc_status st = check_hip(hipStreamSynchronize(ctx->stream), "destroy");
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    delete ctx;
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// hmc_device.hpp -- device-side building blocks shared by the HMC kernels.
+//
+// Counter-based random numbers (Philox4x32-10, Salmon et al., SC'11), the
+// uniform and normal maps of the ABI (include/hmc.h), wavefront reductions,
+// and the per-chain accept / dual-averaging step.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hmc {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10: ten rounds of two 32x32->64 multiplies; round multipliers
+// and Weyl key increments from the SC'11 paper (Sec. 3.2, Table 2).
+// ---------------------------------------------------------------------------
+struct Key {
+    uint32_t k0, k1;
+};
+
+__host__ __device__ inline Key make_key(uint64_t seed) {
+    return Key{(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+}
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, Key key) {
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+enum : uint32_t { TAG_MOMENTUM = 0, TAG_ACCEPT = 1 };
+
+// (k + 1/2) 2^-23 with k the top 23 bits: exact in binary32 and binary64.
+__device__ __forceinline__ float u23_f32(uint32_t w) {
+    return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+__device__ __forceinline__ double u23_f64(uint32_t w) {
+    return ((double)(w >> 9) + 0.5) * 0x1p-23;
+}
+
+// Box-Muller on one pair: r = sqrt(-2 log u1), angle = 2 pi u2 (sincospi of 2 u2,
+// exact argument).
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z0, float& z1) {
+    const float r = sqrtf(-2.0f * logf(u23_f32(wa)));
+    float s, c;
+    sincospif(2.0f * u23_f32(wb), &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& z0, double& z1) {
+    const double r = sqrt(-2.0 * log(u23_f64(wa)));
+    double s, c;
+    sincospi(2.0 * u23_f64(wb), &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// Four momenta of chain c at transition t for dimensions 4*block .. 4*block+3.
+template <typename T>
+__device__ __forceinline__ void momentum4(Key key, uint32_t chain, uint32_t t, uint32_t block, T z[4]) {
+    const uint4 w = philox(chain, t, block, TAG_MOMENTUM, key);
+    box_muller(w.x, w.y, z[0], z[1]);
+    box_muller(w.z, w.w, z[2], z[3]);
+}
+
+// log of the accept uniform ((w0>>6) 2^26 + (w1>>6) + 1/2) 2^-52, in FP64.
+__device__ __forceinline__ double log_accept_uniform(Key key, uint32_t chain, uint32_t t) {
+    const uint4 w = philox(chain, t, 0u, TAG_ACCEPT, key);
+    const double k = (double)(w.x >> 6) * 67108864.0 + (double)(w.y >> 6);
+    return log((k + 0.5) * 0x1p-52);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions across a power-of-two group of G lanes (G <= 64) of a wavefront.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T as_state(float v);
+template <>
+__device__ __forceinline__ float as_state<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ double as_state<double>(float v) { return (double)v; }
+
+// BF16 <-> FP32 (round to nearest even; inputs finite).
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+    return __uint_as_float(((uint32_t)b) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// Per-chain decision (Metropolis-Hastings on dH) and dual averaging
+// (Hoffman & Gelman 2014, eq. 6).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double log_accept_ratio_of(double dh) {
+    // -dH, with NaN and +inf dH mapped to -inf (reject)
+    return (isnan(dh) || (isinf(dh) && dh > 0.0)) ? -INFINITY : -dh;
+}
+
+struct DualAvg {
+    double hbar, log_eps_bar, mu;
+};
+
+// Iteration m >= 1 with accept statistic alpha; returns the new log step size.
+__device__ __forceinline__ double dual_avg_update(DualAvg& s, double m, double alpha, double delta,
+                                                  double gamma, double t0, double kappa) {
+    const double w = 1.0 / (m + t0);
+    s.hbar = (1.0 - w) * s.hbar + w * (delta - alpha);
+    const double log_eps = s.mu - sqrt(m) / gamma * s.hbar;
+    const double eta = pow(m, -kappa);
+    s.log_eps_bar = eta * log_eps + (1.0 - eta) * s.log_eps_bar;
+    return log_eps;
+}
+
+// Control block of the plain/graph path (device resident, written by a
+// one-thread kernel so that a captured graph can be replayed unchanged).
+struct Ctrl {
+    uint64_t t;               // current transition index
+    uint64_t t_begin;         // first transition of the current sample_chain call
+    int64_t n_burnin;
+    int64_t n_results;
+    int32_t adapt;
+    int32_t reserved;
+    double target_accept, gamma, t0, kappa;
+    void* samples;            // [R, C, D] state dtype or null
+    double* tr_step;
+    uint8_t* tr_acc;
+    double* tr_lar;
+    double* tr_logp;
+    uint8_t* out_acc;         // hmc_step outputs ([C] / [C, D]) or null
+    double* out_lar;
+    double* out_logp;
+    void* out_xprop;
+    void* out_pprop;
+    double* out_dh;
+};
+
+}  // namespace hmc

