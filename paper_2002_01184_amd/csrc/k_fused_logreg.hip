@@ -41,20 +41,26 @@ __device__ __forceinline__ float dpp_ror(float v, int n) {
     // rotate right within a row of 16 lanes
     int r;
     if (n == 4)
-        r = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xf, 0xf, false);
+        r = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xf, 0xf, true);
     else
-        r = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, false);
+        r = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, true);
     return __int_as_float(r);
 }
 
-__device__ __forceinline__ float sigmoid_f(float s) {
-    const float e = expf(-fabsf(s));
-    const float r = 1.0f / (1.0f + e);
-    return s >= 0.f ? r : e * r;
+// 1 / (1 + e^-s) with the hardware exp2 and reciprocal (about 1 ulp each);
+// e^-s overflowing to +inf gives the correct limit 0.
+__device__ __forceinline__ float sigmoid_fast(float s) {
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * s);
+    return __builtin_amdgcn_rcpf(1.0f + e);
 }
 
+// log(1 + e^s) = max(s, 0) + log1p(e^-|s|); log1p(e) for e in (0, 1] from the
+// hardware log2 when e >= 2^-10, else its series e - e^2/2 + e^3/3 (error < e^4/4).
 __device__ __forceinline__ float softplus_f(float s) {
-    return fmaxf(s, 0.f) + log1pf(expf(-fabsf(s)));
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * fabsf(s));
+    const float l = e >= 0x1p-10f ? 0.69314718055994531f * __builtin_amdgcn_logf(1.0f + e)
+                                  : e * (1.0f - e * (0.5f - e * 0.33333333f));
+    return fmaxf(s, 0.f) + l;
 }
 
 // stored column of dim d and its inverse
@@ -70,46 +76,39 @@ template <int TPW, int QQ, typename XT>
 __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) {
     extern __shared__ float lds[];
     constexpr int NW = LR_NW;
-    constexpr int NPAD = NW * TPW * 64;
     const int64_t D = a.tg.D, N = a.tg.N, C = a.C;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int q4 = lane & 3, b16 = lane >> 2;
     const int64_t c0 = (int64_t)blockIdx.x * 4;
     const float inv_var = (float)a.tg.inv_var;
 
-    float* xs = lds;                         // [NPAD][32]
-    float* ys = xs + NPAD * 32;              // [NPAD]
-    float* th = ys + NPAD;                   // [4][32]
-    float* part = th + 128;                  // [NW][LR_PART]
+    float* th = lds;                         // [4][32] theta of the 4 chains (dim order)
+    float* part = th + 128;                  // [NW][4 rows][4 j][32]: row partials, (q, i) inner
     double* lpp = (double*)(part + NW * LR_PART);   // [NW][4]
 
-    // ---- stage X (permuted columns) and y ----
+    // ---- X and y of this wave's tiles, in the two operand layouts, kept in VGPRs ----
     const XT* X = (const XT*)a.tg.X;
-    for (int idx = threadIdx.x; idx < NPAD * 32; idx += blockDim.x) {
-        const int row = idx >> 5, k = idx & 31;
-        const int d = lr_dim(k);
-        float v = 0.f;
-        if (row < N && d < D) {
-            if constexpr (sizeof(XT) == 2) v = bf16_to_f32(((const uint16_t*)X)[(int64_t)row * D + d]);
-            else v = ((const float*)X)[(int64_t)row * D + d];
-        }
-        xs[idx] = v;
-    }
-    for (int row = threadIdx.x; row < NPAD; row += blockDim.x) ys[row] = row < N ? (float)a.tg.y[row] : 0.f;
-    __syncthreads();
-
-    // first-contraction operands of this wave's tiles, kept in VGPRs
-    float xa[TPW][32];
+    auto ldx = [&](int64_t row, int64_t d) -> float {
+        if (row >= N || d >= D) return 0.f;
+        if constexpr (sizeof(XT) == 2) return bf16_to_f32(((const uint16_t*)X)[row * D + d]);
+        else return ((const float*)X)[row * D + d];
+    };
+    float xa[TPW][4 * QQ];     // first contraction: X[row0 + lane][d]
+    float xb[TPW][4][QQ];      // second contraction: X[row0 + 4 b16 + v][4 q + q4]
+    float yv[TPW][4];
+    bool rv[TPW][4];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        const int row = (w + NW * t) * 64 + lane;
+    for (int tt = 0; tt < TPW; ++tt) {
+        const int64_t row0 = (int64_t)(w + NW * tt) * 64;
 #pragma unroll
-        for (int k = 0; k < 32; k += 4) {
-            const float4 v = *(const float4*)&xs[row * 32 + k];
-            xa[t][k] = v.x;
-            xa[t][k + 1] = v.y;
-            xa[t][k + 2] = v.z;
-            xa[t][k + 3] = v.w;
+        for (int d = 0; d < 4 * QQ; ++d) xa[tt][d] = ldx(row0 + lane, d);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = row0 + 4 * b16 + v;
+            rv[tt][v] = row < N;
+            yv[tt][v] = row < N ? (float)a.tg.y[row] : 0.f;
+#pragma unroll
+            for (int q = 0; q < QQ; ++q) xb[tt][v][q] = ldx(row, 4 * q + q4);
         }
     }
 
@@ -136,7 +135,9 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
         if (owner) {
             float z[4];
             momentum4<float>(a.key, (uint32_t)occ, t, (uint32_t)(od >> 2), z);
-            const float p0 = ovalid ? z[od & 3] : 0.f;
+            const int jj = od & 3;
+            const float zj = jj == 0 ? z[0] : (jj == 1 ? z[1] : (jj == 2 ? z[2] : z[3]));
+            const float p0 = ovalid ? zj : 0.f;
             dk = -0.5 * (double)p0 * (double)p0;
             p = fmaf(half, g0, p0);
         }
@@ -144,71 +145,65 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
             const bool last = l == a.L - 1;
             if (owner) {
                 thq = fmaf(eps, p, thq);
-                th[oi * 32 + lr_col(od)] = ovalid ? thq : 0.f;
+                th[oi * 32 + od] = ovalid ? thq : 0.f;
             }
             __syncthreads();
-            // theta of chain q4 in stored-column order
-            float tb[32];
+            float tb[4 * QQ];
 #pragma unroll
-            for (int k = 0; k < 32; k += 4) {
+            for (int k = 0; k < 4 * QQ; k += 4) {
                 const float4 v = *(const float4*)&th[q4 * 32 + k];
                 tb[k] = v.x;
                 tb[k + 1] = v.y;
                 tb[k + 2] = v.z;
                 tb[k + 3] = v.w;
             }
-            floatx4 gacc[8];
+            floatx4 gacc[QQ];
 #pragma unroll
-            for (int qq = 0; qq < 8; ++qq) gacc[qq] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int q = 0; q < QQ; ++q) gacc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
             double lp = 0.0;
+            // S = X theta for all tiles, four independent accumulation chains per tile
+            floatx4 sa[TPW][4];
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sa[tt][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int d = 0; d < 4 * QQ; d += 4)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int tt = 0; tt < TPW; ++tt)
+                        sa[tt][u] = __builtin_amdgcn_mfma_f32_4x4x1f32(xa[tt][d + u], tb[d + u], sa[tt][u], 0, 0, 0);
 #pragma unroll
             for (int tt = 0; tt < TPW; ++tt) {
-                const int rowbase = (w + NW * tt) * 64;
-                if (rowbase >= N) break;
-                floatx4 sacc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int k = 0; k < 32; ++k)
-                    if ((k & 7) < QQ) sacc = __builtin_amdgcn_mfma_f32_4x4x1f32(xa[tt][k], tb[k], sacc, 0, 0, 0);
-                const int rb = rowbase + 4 * b16;
-                const float4 yv = *(const float4*)&ys[rb];
-                const float yy[4] = {yv.x, yv.y, yv.z, yv.w};
+                if ((w + NW * tt) * 64 >= N) break;
                 float rr[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    rr[v] = yy[v] - sigmoid_f(sacc[v]);
-                    if (last && rb + v < N) lp -= (double)softplus_f(yy[v] > 0.5f ? -sacc[v] : sacc[v]);
+                    const float sv = (sa[tt][0][v] + sa[tt][1][v]) + (sa[tt][2][v] + sa[tt][3][v]);
+                    rr[v] = yv[tt][v] - sigmoid_fast(sv);
+                    if (last && rv[tt][v]) lp -= (double)softplus_f(yv[tt][v] > 0.5f ? -sv : sv);
                 }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float* xr = &xs[(rb + v) * 32 + q4 * 8];
-                    const float4 xlo = *(const float4*)xr;
-                    const float4 xhi = *(const float4*)(xr + 4);
-                    const float xb[8] = {xlo.x, xlo.y, xlo.z, xlo.w, xhi.x, xhi.y, xhi.z, xhi.w};
+                for (int v = 0; v < 4; ++v)
 #pragma unroll
-                    for (int qq = 0; qq < 8; ++qq)
-                        if (qq < QQ) gacc[qq] = __builtin_amdgcn_mfma_f32_4x4x1f32(rr[v], xb[qq], gacc[qq], 0, 0, 0);
-                }
+                    for (int q = 0; q < QQ; ++q)
+                        gacc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(rr[v], xb[tt][v][q], gacc[q], 0, 0, 0);
             }
             // sum the 4 blocks of each 16-lane row (lanes of equal j), write row partials
 #pragma unroll
-            for (int qq = 0; qq < 8; ++qq) {
-                if (qq >= QQ) break;
+            for (int q = 0; q < QQ; ++q)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    float v = gacc[qq][i];
+                    float v = gacc[q][i];
                     v += dpp_ror(v, 4);
                     v += dpp_ror(v, 8);
-                    gacc[qq][i] = v;
+                    gacc[q][i] = v;
                 }
-            }
             if ((lane & 15) < 4) {
-                const int rrow = lane >> 4;
+                float* dst = part + w * LR_PART + ((lane >> 4) * 4 + q4) * 32;
 #pragma unroll
-                for (int qq = 0; qq < 8; ++qq) {
-                    if (qq >= QQ) break;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) part[w * LR_PART + (rrow * 8 + qq) * 16 + i * 4 + q4] = gacc[qq][i];
-                }
+                for (int q = 0; q < QQ; ++q) *(floatx4*)(dst + 4 * q) = gacc[q];
             }
             if (last) {
                 lp += __shfl_xor(lp, 4, 64);
@@ -220,12 +215,20 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
             __syncthreads();
             if (owner) {
                 float gs = 0.f;
-                if (od < D) {
-                    const int qq = od >> 2, j = od & 3;
+                if (od < 4 * QQ) {
+                    // fixed-order pairwise tree over the NW x 4 row partials
+                    const int q = od >> 2, j = od & 3;
+                    float v[NW * 4];
 #pragma unroll
                     for (int ww = 0; ww < NW; ++ww)
 #pragma unroll
-                        for (int rrow = 0; rrow < 4; ++rrow) gs += part[ww * LR_PART + (rrow * 8 + qq) * 16 + oi * 4 + j];
+                        for (int rrow = 0; rrow < 4; ++rrow)
+                            v[ww * 4 + rrow] = part[ww * LR_PART + (rrow * 4 + j) * 32 + 4 * q + oi];
+#pragma unroll
+                    for (int h = NW * 2; h >= 1; h >>= 1)
+#pragma unroll
+                        for (int k = 0; k < h; ++k) v[k] = v[2 * k] + v[2 * k + 1];
+                    gs = v[0];
                 }
                 gq = gs - thq * inv_var;
                 p = fmaf(last ? half : eps, gq, p);
@@ -293,9 +296,8 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     }
 }
 
-static size_t logreg4_lds(int tpw) {
-    const int npad = LR_NW * tpw * 64;
-    return (size_t)(npad * 32 + npad + 128 + LR_NW * LR_PART) * sizeof(float) + LR_NW * 4 * sizeof(double);
+static size_t logreg4_lds(int) {
+    return (size_t)(128 + LR_NW * LR_PART) * sizeof(float) + LR_NW * 4 * sizeof(double);
 }
 
 bool fused_logreg_supported(const PlainArgs& a) {
@@ -305,9 +307,6 @@ bool fused_logreg_supported(const PlainArgs& a) {
 template <int TPW, int QQ, typename XT>
 static hipError_t launch_lr4(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     const size_t lds = logreg4_lds(TPW);
-    hipError_t e = hipFuncSetAttribute((const void*)k_fused_logreg4<TPW, QQ, XT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((a.C + 3) / 4));
     hipLaunchKernelGGL((k_fused_logreg4<TPW, QQ, XT>), grid, dim3(64 * LR_NW), lds, s, a, r);
     return hipGetLastError();
