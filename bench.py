@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diagnostics", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--grad", default="f32", choices=["f32", "bf16"],
+                    help="bf16: BF16 MFMA gradient contractions (logistic regression with BF16 X)")
+    ap.add_argument("--transitions", type=int, default=None,
+                    help="override burn-in + results (split evenly) for the large configurations")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -104,9 +108,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     w = W.CONFIGS[args.config]()
+    if args.transitions is not None:
+        w.num_burnin = args.transitions // 2
+        w.num_results = args.transitions - w.num_burnin
     form = {"auto": hmc.HMC_FORM_AUTO, "plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_GRAPH,
             "fused": hmc.HMC_FORM_FUSED}[args.form]
-    s = hmc.sampler_for(w, device=dev, form=form)
+    s = hmc.sampler_for(w, device=dev, form=form, grad_bf16=args.grad == "bf16")
     x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).to(dev)
     eps0 = torch.full((w.num_chains,), float(w.step_size), dtype=torch.float64, device=dev)
     T = w.num_burnin + w.num_results
@@ -138,7 +145,7 @@ def main():
 
     bound, per_cs, unit = algorithmic_work(w)
     if bound == "mfma":
-        peak = PEAK["bf16_mfma"] if (w.X_bf16 is not None and False) else PEAK["fp32_mfma"]
+        peak = PEAK["bf16_mfma"] if args.grad == "bf16" else PEAK["fp32_mfma"]
         achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None}
@@ -154,7 +161,8 @@ def main():
     result = {
         "metric": METRIC, "value": value, "unit": "leapfrog chain-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if w.state_dtype == "f64" else "f32",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if w.state_dtype == "f64" else ("bf16/f32" if args.grad == "bf16" else "f32"),
         "data": "synthetic (seeded; shapes of the paper's workloads)",
         "config": {"workload": w.name, "num_chains": w.num_chains, "dim": w.dim, "n_rows": w.n_rows,
                    "num_leapfrog_steps": w.num_leapfrog_steps, "num_burnin": w.num_burnin,

@@ -42,7 +42,13 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
     const int64_t C = cfg.num_chains, D = tg.D;
     const size_t es = elem_size(cfg.state_dtype);
     const size_t state = (size_t)C * D * es;
-    const int64_t nsplit = tg.kind == HMC_TGT_LOGREG ? logreg_nsplit(tg.N, C) : 0;
+    const bool bf16 = cfg.grad_dtype == HMC_BF16;
+    int64_t nsplit = tg.kind == HMC_TGT_LOGREG ? logreg_nsplit(tg.N, C) : 0;
+    int64_t nsplit_lp = nsplit;
+    if (bf16) {
+        nsplit = nsplit > lb_grad_nsplit(tg.N, C) ? nsplit : lb_grad_nsplit(tg.N, C);
+        nsplit_lp = nsplit > lb_logp_nsplit(tg.N, C) ? nsplit : lb_logp_nsplit(tg.N, C);
+    }
     char* p = (char*)base;
     size_t off = 0;
     auto take = [&](size_t n) {
@@ -62,7 +68,8 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
     w.lpq = (double*)take((size_t)C * 8);
     w.h0 = (double*)take((size_t)C * 8);
     w.part_g = (float*)take((size_t)nsplit * C * D * 4);
-    w.part_lp = (double*)take((size_t)nsplit * C * 8);
+    w.part_lp = (double*)take((size_t)nsplit_lp * C * 8);
+    w.xt = bf16 ? take((size_t)tg.N * D * 2) : nullptr;
     w.ctrl = (Ctrl*)take(sizeof(Ctrl));
     w.bytes = off;
     if (total) *total = off;
@@ -120,6 +127,10 @@ static hmc_status validate(const hmc_target* tg, const hmc_config* cfg, TargetDe
     }
     if (cfg->grad_dtype == HMC_BF16 && !(tg->kind == HMC_TGT_LOGREG && tg->x_dtype == HMC_BF16))
         return fail(HMC_E_UNSUPPORTED, "BF16 gradients need a logistic-regression target with BF16 X");
+    if (cfg->grad_dtype == HMC_BF16 && !bf16_grad_supported(t))
+        return fail(HMC_E_UNSUPPORTED, "BF16 gradients support D <= 256");
+    if (cfg->grad_dtype == HMC_BF16 && cfg->form == HMC_FORM_FUSED)
+        return fail(HMC_E_UNSUPPORTED, "BF16 gradients run in the plain or graph form");
     if (out) *out = t;
     return HMC_OK;
 }
@@ -202,13 +213,9 @@ hmc_status hmc_init(const hmc_target* target, const hmc_config* config, const vo
         break;
     default: ctx->form = config->form;
     }
-    if (a.bf16_grad && ctx->form != HMC_FORM_FUSED) {
-        // BF16 MFMA operands exist only in the fused logistic kernels
-        delete ctx;
-        return fail(HMC_E_UNSUPPORTED, "BF16 gradients need the fused form");
-    }
 
     st = upload_eps(ctx, step_size, step_size_len);
+    if (st == HMC_OK && a.bf16_grad) st = check_hip(launch_transpose_bf16(a, a.ws.xt, ctx->stream), "transpose X");
     if (st == HMC_OK) st = check_hip(launch_set_ctrl(base_ctrl(ctx), a.ws.ctrl, ctx->stream), "init control");
     if (st == HMC_OK) st = check_hip(launch_da_init(a, ctx->stream), "init adaptation");
     if (st == HMC_OK) st = check_hip(launch_bootstrap(a, init_state, ctx->stream), "bootstrap");

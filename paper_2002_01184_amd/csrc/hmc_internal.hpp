@@ -38,11 +38,15 @@ struct Workspace {
     double* h0;    // [C] initial energy
     float* part_g;     // [nsplit, C, D] split-N gradient partials (LOGREG plain)
     double* part_lp;   // [nsplit, C]
+    void* xt;          // [D, N] BF16 transposed copy of X (BF16 gradients only)
     Ctrl* ctrl;
     size_t bytes;
 };
 
 int64_t logreg_nsplit(int64_t N, int64_t C);
+int lb_grad_nsplit(int64_t N, int64_t C);
+int lb_logp_nsplit(int64_t N, int64_t C);
+bool bf16_grad_supported(const TargetDev& tg);
 Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg, size_t* total);
 size_t elem_size(int32_t dtype);
 
@@ -60,6 +64,12 @@ hipError_t launch_set_ctrl(const Ctrl& c, Ctrl* dst, hipStream_t s);
 hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s);
 hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipStream_t s);
 hipError_t launch_da_init(const PlainArgs& a, hipStream_t s);
+
+// ---- BF16 gradients (k_logreg_bf16.hip) -------------------------------------
+hipError_t launch_transpose_bf16(const PlainArgs& a, void* Xt, hipStream_t s);
+hipError_t launch_lr16_grad(const PlainArgs& a, const float* x, const float* p, int drift, const void* Xt,
+                            hipStream_t s);
+hipError_t launch_lr16_logp(const PlainArgs& a, const float* x, hipStream_t s);
 
 // ---- fused path (k_fused.hip) -----------------------------------------------
 struct FusedRun {

@@ -560,7 +560,14 @@ hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s
         (void)launch_dense(a, (const float*)a.ws.x, nullptr, nullptr, (float*)a.ws.g, 0, 0.0, s);
         break;
     case HMC_TGT_LOGREG:
-        (void)launch_logreg(a, (float*)a.ws.x, nullptr, (float*)a.ws.g, 0, 0, 0.0, 1, s);
+        if (a.bf16_grad) {
+            (void)launch_lr16_grad(a, (const float*)a.ws.x, nullptr, 0, a.ws.xt, s);
+            hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, (float*)a.ws.x,
+                               (float*)nullptr, (float*)a.ws.g, lb_grad_nsplit(a.tg.N, a.C), 0, 0, 0.0, 0);
+            (void)launch_lr16_logp(a, (const float*)a.ws.x, s);
+        } else {
+            (void)launch_logreg(a, (float*)a.ws.x, nullptr, (float*)a.ws.g, 0, 0, 0.0, 1, s);
+        }
         break;
     }
     if (a.f64) HMC_GROUP_DISPATCH(k_logp_finish, double, a, s);
@@ -591,6 +598,14 @@ hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipSt
                          last ? (float*)a.ws.gq : nullptr, 3, ks, s);
             break;
         case HMC_TGT_LOGREG:
+            if (a.bf16_grad) {
+                (void)launch_lr16_grad(a, (const float*)a.ws.xq, (const float*)a.ws.pq, 1, a.ws.xt, s);
+                hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, (float*)a.ws.xq,
+                                   (float*)a.ws.pq, last ? (float*)a.ws.gq : (float*)nullptr,
+                                   lb_grad_nsplit(a.tg.N, a.C), 1, 1, ks, 0);
+                if (last) (void)launch_lr16_logp(a, (const float*)a.ws.xq, s);
+                break;
+            }
             (void)launch_logreg(a, (float*)a.ws.xq, (float*)a.ws.pq, last ? (float*)a.ws.gq : nullptr, 1, 1, ks,
                           last ? 1 : 0, s);
             break;
