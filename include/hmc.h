@@ -177,6 +177,75 @@ const char* hmc_last_error(void);
  * (HMC_FORM_PLAIN, HMC_FORM_FUSED or HMC_FORM_GRAPH). */
 int32_t hmc_effective_form(const hmc_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of sampling requests (one sample_chain each)
+ * of differing target, dimension, data size and chain count on one GPU.
+ *
+ * The server owns one device pool of hbm_budget_bytes (allocated at creation)
+ * and a worker thread.  A request is admitted when its device memory
+ * (workspace, plus its sample buffer when the caller passes samples = NULL)
+ * fits in the free part of the pool; admitted requests keep their chain state
+ * and adaptation state resident in the pool until they finish.  Each tick the
+ * worker advances every active request by up to transitions_per_tick
+ * transitions: requests of the elementwise families that share a shape class
+ * run in one ragged launch, the others run concurrently on a pool of HIP
+ * streams.  A request's result does not depend on which other requests run
+ * with it (its random streams are keyed by its own seed and chain ids and its
+ * kernels touch only its own memory), and equals the hmc_sample_chain result
+ * of the same request.  Requests are admitted in arrival order; a request that
+ * does not fit waits while later, smaller ones may be admitted.
+ * ------------------------------------------------------------------------- */
+typedef struct hmc_request {
+    hmc_target target;           /* device arrays, borrowed until the request is done */
+    hmc_config config;           /* form AUTO, PLAIN or FUSED */
+    const void* init_state;      /* device [C, D]; read at admission */
+    double step_size;            /* eps0 for every chain */
+    int64_t num_results;
+    int64_t num_burnin;
+    hmc_adapt adapt;             /* enabled = 0 for a fixed step size */
+    void* samples;               /* device [R, C, D], or NULL: the server keeps them (counted in the budget)
+                                    until hmc_server_take */
+    hmc_trace trace;             /* device [R, C] arrays or NULL */
+} hmc_request;
+
+typedef struct hmc_server hmc_server;
+
+typedef struct hmc_server_stats {
+    int64_t submitted, admitted, completed, failed;
+    int64_t active, pending;
+    int64_t ticks;
+    int64_t batched_launches;    /* ragged launches that covered >= 2 requests */
+    int64_t max_active;          /* most requests resident at once */
+    size_t pool_bytes, bytes_in_use, peak_bytes_in_use;
+} hmc_server_stats;
+
+enum { HMC_REQ_QUEUED = 0, HMC_REQ_RUNNING = 1, HMC_REQ_DONE = 2, HMC_REQ_FAILED = 3 };
+
+/* Creates the server: allocates the pool (hbm_budget_bytes of device memory)
+ * and starts the worker.  transitions_per_tick >= 1. */
+hmc_status hmc_server_create(size_t hbm_budget_bytes, int32_t transitions_per_tick, hmc_server** out);
+
+/* Queues a copy of *req.  Fails with HMC_E_INVALID / HMC_E_UNSUPPORTED for a
+ * request hmc_init would reject and with HMC_E_NOMEM when its memory exceeds
+ * the whole pool.  *id identifies the request. */
+hmc_status hmc_server_submit(hmc_server* srv, const hmc_request* req, uint64_t* id);
+
+/* State of a request (HMC_REQ_*) and, once done, its latency from submission
+ * to completion in seconds (host clock).  Either output may be NULL. */
+hmc_status hmc_server_poll(hmc_server* srv, uint64_t id, int32_t* state, double* latency_s);
+
+/* Blocks until the request is done or failed; then as hmc_server_poll. */
+hmc_status hmc_server_wait(hmc_server* srv, uint64_t id, int32_t* state, double* latency_s);
+
+/* For a done request submitted with samples = NULL: copies its samples
+ * [R, C, D] into dst (device) and releases them from the pool. */
+hmc_status hmc_server_take(hmc_server* srv, uint64_t id, void* dst_samples);
+
+hmc_status hmc_server_get_stats(hmc_server* srv, hmc_server_stats* out);
+
+/* Waits for every request, stops the worker and frees the pool. */
+hmc_status hmc_server_destroy(hmc_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

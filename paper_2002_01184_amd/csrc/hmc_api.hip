@@ -10,11 +10,17 @@
 
 namespace {
 thread_local std::string g_last_error;
+}  // namespace
 
+namespace hmc {
 hmc_status fail(hmc_status st, const std::string& msg) {
     g_last_error = msg;
     return st;
 }
+}  // namespace hmc
+using hmc::fail;
+
+namespace {
 
 hmc_status check_hip(hipError_t e, const char* what) {
     if (e == hipSuccess) return HMC_OK;
@@ -80,7 +86,7 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
 
 using namespace hmc;
 
-static hmc_status validate(const hmc_target* tg, const hmc_config* cfg, TargetDev* out) {
+hmc_status hmc::validate_args(const hmc_target* tg, const hmc_config* cfg, TargetDev* out) {
     if (!tg || !cfg) return fail(HMC_E_INVALID, "target and config must not be NULL");
     if (tg->dim < 1) return fail(HMC_E_INVALID, "target dim must be >= 1");
     if (cfg->num_chains < 1) return fail(HMC_E_INVALID, "num_chains must be >= 1");
@@ -141,7 +147,7 @@ const char* hmc_last_error(void) { return g_last_error.c_str(); }
 
 hmc_status hmc_workspace_size(const hmc_target* target, const hmc_config* config, size_t* bytes) {
     TargetDev t;
-    hmc_status st = validate(target, config, &t);
+    hmc_status st = validate_args(target, config, &t);
     if (st != HMC_OK) return st;
     if (!bytes) return fail(HMC_E_INVALID, "bytes must not be NULL");
     carve_workspace(nullptr, t, *config, bytes);
@@ -170,7 +176,7 @@ hmc_status hmc_init(const hmc_target* target, const hmc_config* config, const vo
                     const double* step_size, int64_t step_size_len, void* workspace, size_t workspace_bytes,
                     void* hip_stream, hmc_ctx** out) {
     TargetDev t;
-    hmc_status st = validate(target, config, &t);
+    hmc_status st = validate_args(target, config, &t);
     if (st != HMC_OK) return st;
     if (!out) return fail(HMC_E_INVALID, "out must not be NULL");
     if (!init_state) return fail(HMC_E_INVALID, "init_state must not be NULL");
@@ -319,6 +325,8 @@ hmc_status hmc_sample_chain(hmc_ctx* ctx, int64_t num_results, int64_t num_burni
         r.t_begin = ctx->t;
         r.n_transitions = total;
         r.n_burnin = num_burnin_steps;
+        r.m_offset = 0;
+        r.adapt_total = num_burnin_steps;
         r.adapt = ad;
         if (ad) {
             r.target_accept = adapt->target_accept;

@@ -43,6 +43,8 @@ struct Workspace {
     size_t bytes;
 };
 
+hmc_status fail(hmc_status st, const std::string& msg);
+hmc_status validate_args(const hmc_target* tg, const hmc_config* cfg, TargetDev* out);
 int64_t logreg_nsplit(int64_t N, int64_t C);
 int lb_grad_nsplit(int64_t N, int64_t C);
 int lb_logp_nsplit(int64_t N, int64_t C);
@@ -75,7 +77,9 @@ hipError_t launch_lr16_logp(const PlainArgs& a, const float* x, hipStream_t s);
 struct FusedRun {
     uint64_t t_begin;
     int64_t n_transitions;   // total transitions in this launch
-    int64_t n_burnin;        // of which the first n_burnin are burn-in
+    int64_t n_burnin;        // of which the first n_burnin are burn-in (not stored)
+    int64_t m_offset;        // dual-averaging iterations done before this launch
+    int64_t adapt_total;     // burn-in length of the whole run: at iteration m == adapt_total switch to eps_bar
     int32_t adapt;
     double target_accept, gamma, t0, kappa;
     void* samples;
@@ -85,5 +89,17 @@ struct FusedRun {
 // Returns hipErrorNotSupported when no fused kernel covers this target/shape.
 bool fused_supported(const PlainArgs& a);
 hipError_t launch_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s);
+
+// Ragged multi-request launch of the fused elementwise kernel: jobs of one
+// shape class (state dtype, lanes per chain, blocks per lane) in one grid.
+struct ElemJob {
+    PlainArgs a;
+    FusedRun r;
+    int64_t block_begin;     // first block of this job in the grid
+};
+int elem_class(const PlainArgs& a);                 // -1 if the elementwise kernel does not apply
+int64_t elem_blocks(const PlainArgs& a);
+hipError_t launch_fused_elem_multi(int cls, const ElemJob* jobs_dev, int njobs, int64_t total_blocks,
+                                   hipStream_t s);
 
 }  // namespace hmc

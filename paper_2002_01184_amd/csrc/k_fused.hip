@@ -28,9 +28,9 @@ __device__ __forceinline__ void after_decision(const FusedRun& r, int64_t C, int
     const double eps_used = s.eps;
     if (r.adapt && i < r.n_burnin) {
         const double alpha = lar < 0.0 ? exp(lar) : 1.0;
-        const double log_eps = dual_avg_update(s.da, (double)(i + 1), alpha, r.target_accept, r.gamma, r.t0,
-                                               r.kappa);
-        s.eps = (i + 1 < r.n_burnin) ? exp(log_eps) : exp(s.da.log_eps_bar);
+        const int64_t m = r.m_offset + i + 1;
+        const double log_eps = dual_avg_update(s.da, (double)m, alpha, r.target_accept, r.gamma, r.t0, r.kappa);
+        s.eps = (m < r.adapt_total) ? exp(log_eps) : exp(s.da.log_eps_bar);
     }
     if (!writer) return;
     if (i >= r.n_burnin) {
@@ -51,8 +51,8 @@ __device__ __forceinline__ void after_decision(const FusedRun& r, int64_t C, int
 // blocks j, j + G, ...
 // ---------------------------------------------------------------------------
 template <typename T, int G, int NB>
-__global__ __launch_bounds__(256) void k_fused_elem(PlainArgs a, FusedRun r) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedRun& r, int64_t lblock) {
+    const int64_t gid = lblock * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % G;
     const int64_t c = gid / G;
     const bool active = c < a.C;
@@ -170,6 +170,26 @@ __global__ __launch_bounds__(256) void k_fused_elem(PlainArgs a, FusedRun r) {
         a.ws.eps[c] = s.eps;
         a.ws.da[c] = s.da;
     }
+}
+
+template <typename T, int G, int NB>
+__global__ __launch_bounds__(256) void k_fused_elem(PlainArgs a, FusedRun r) {
+    fused_elem_body<T, G, NB>(a, r, blockIdx.x);
+}
+
+// Several requests of one shape class in one grid: block b runs job j with
+// jobs[j].block_begin <= b < jobs[j + 1].block_begin.
+template <typename T, int G, int NB>
+__global__ __launch_bounds__(256) void k_fused_elem_multi(const ElemJob* __restrict__ jobs, int njobs) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block_begin <= (int64_t)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const PlainArgs a = jobs[lo].a;
+    const FusedRun r = jobs[lo].r;
+    fused_elem_body<T, G, NB>(a, r, (int64_t)blockIdx.x - jobs[lo].block_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,21 +406,60 @@ bool fused_supported(const PlainArgs& a) {
     return false;
 }
 
-template <typename T>
-static hipError_t launch_elem(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
+static int elem_class_of(int G, int NB) {
+    if (G == 1) return 0;
+    if (G == 4) return 1;
+    if (G == 16) return 2;
+    return NB == 1 ? 3 : (NB == 2 ? 4 : (NB == 4 ? 5 : 6));
+}
+
+int elem_class(const PlainArgs& a) {
+    if (a.tg.kind != HMC_TGT_STD_NORMAL && a.tg.kind != HMC_TGT_GAUSS_DIAG) return -1;
     int G;
     const int NB = elem_nb(a.tg.D, &G);
-    const int64_t threads = a.C * G;
-    const dim3 grid((unsigned)((threads + 255) / 256));
+    if (NB == 0) return -1;
+    return (a.f64 ? 8 : 0) + elem_class_of(G, NB);
+}
+
+int64_t elem_blocks(const PlainArgs& a) {
+    int G;
+    elem_nb(a.tg.D, &G);
+    return (a.C * G + 255) / 256;
+}
+
+#define HMC_ELEM_DISPATCH(CLS, MACRO)                  \
+    switch ((CLS) & 7) {                               \
+    case 0: MACRO(1, 1); break;                        \
+    case 1: MACRO(4, 1); break;                        \
+    case 2: MACRO(16, 1); break;                       \
+    case 3: MACRO(64, 1); break;                       \
+    case 4: MACRO(64, 2); break;                       \
+    case 5: MACRO(64, 4); break;                       \
+    default: MACRO(64, 8); break;                      \
+    }
+
+template <typename T>
+static hipError_t launch_elem(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
+    const int cls = elem_class(a);
+    const dim3 grid((unsigned)elem_blocks(a));
 #define HMC_ELEM(GG, NN) hipLaunchKernelGGL((k_fused_elem<T, GG, NN>), grid, dim3(256), 0, s, a, r)
-    if (G == 1) HMC_ELEM(1, 1);
-    else if (G == 4) HMC_ELEM(4, 1);
-    else if (G == 16) HMC_ELEM(16, 1);
-    else if (NB == 1) HMC_ELEM(64, 1);
-    else if (NB == 2) HMC_ELEM(64, 2);
-    else if (NB == 4) HMC_ELEM(64, 4);
-    else HMC_ELEM(64, 8);
+    HMC_ELEM_DISPATCH(cls, HMC_ELEM)
 #undef HMC_ELEM
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_elem_multi(int cls, const ElemJob* jobs_dev, int njobs, int64_t total_blocks,
+                                   hipStream_t s) {
+    const dim3 grid((unsigned)total_blocks);
+    if (cls & 8) {
+#define HMC_ELEM_M(GG, NN) hipLaunchKernelGGL((k_fused_elem_multi<double, GG, NN>), grid, dim3(256), 0, s, jobs_dev, njobs)
+        HMC_ELEM_DISPATCH(cls, HMC_ELEM_M)
+#undef HMC_ELEM_M
+    } else {
+#define HMC_ELEM_M(GG, NN) hipLaunchKernelGGL((k_fused_elem_multi<float, GG, NN>), grid, dim3(256), 0, s, jobs_dev, njobs)
+        HMC_ELEM_DISPATCH(cls, HMC_ELEM_M)
+#undef HMC_ELEM_M
+    }
     return hipGetLastError();
 }
 

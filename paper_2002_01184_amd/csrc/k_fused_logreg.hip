@@ -266,9 +266,10 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
             const double eps_used = s.eps;
             if (r.adapt && itr < r.n_burnin) {
                 const double alpha = lar < 0.0 ? exp(lar) : 1.0;
-                const double log_eps = dual_avg_update(s.da, (double)(itr + 1), alpha, r.target_accept, r.gamma,
-                                                       r.t0, r.kappa);
-                s.eps = (itr + 1 < r.n_burnin) ? exp(log_eps) : exp(s.da.log_eps_bar);
+                const int64_t m = r.m_offset + itr + 1;
+                const double log_eps = dual_avg_update(s.da, (double)m, alpha, r.target_accept, r.gamma, r.t0,
+                                                       r.kappa);
+                s.eps = (m < r.adapt_total) ? exp(log_eps) : exp(s.da.log_eps_bar);
             }
             if (od == 0) {
                 if (itr >= r.n_burnin) {

@@ -56,8 +56,24 @@ class hmc_step_out(ctypes.Structure):
                 ("proposed_momentum", ctypes.c_void_p), ("delta_h", ctypes.c_void_p)]
 
 
+class hmc_request(ctypes.Structure):
+    _fields_ = [("target", hmc_target), ("config", hmc_config), ("init_state", ctypes.c_void_p),
+                ("step_size", ctypes.c_double), ("num_results", ctypes.c_int64), ("num_burnin", ctypes.c_int64),
+                ("adapt", hmc_adapt), ("samples", ctypes.c_void_p), ("trace", hmc_trace)]
+
+
+class hmc_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "admitted", "completed", "failed", "active", "pending",
+                                              "ticks", "batched_launches", "max_active")] + \
+               [(n, ctypes.c_size_t) for n in ("pool_bytes", "bytes_in_use", "peak_bytes_in_use")]
+
+
+HMC_REQ_QUEUED, HMC_REQ_RUNNING, HMC_REQ_DONE, HMC_REQ_FAILED = range(4)
+
 EXPORTED = ["hmc_workspace_size", "hmc_init", "hmc_step", "hmc_sample_chain", "hmc_get_state", "hmc_set_state",
-            "hmc_destroy", "hmc_last_error", "hmc_effective_form"]
+            "hmc_destroy", "hmc_last_error", "hmc_effective_form", "hmc_server_create", "hmc_server_submit",
+            "hmc_server_poll", "hmc_server_wait", "hmc_server_take", "hmc_server_get_stats",
+            "hmc_server_destroy"]
 
 _lib = None
 
@@ -93,6 +109,19 @@ def lib():
     L.hmc_last_error.restype = ctypes.c_char_p
     L.hmc_effective_form.argtypes = [vp]
     L.hmc_effective_form.restype = ctypes.c_int32
+    L.hmc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
+    L.hmc_server_create.restype = st
+    L.hmc_server_submit.argtypes = [vp, ctypes.POINTER(hmc_request), ctypes.POINTER(ctypes.c_uint64)]
+    L.hmc_server_submit.restype = st
+    for n in ("hmc_server_poll", "hmc_server_wait"):
+        getattr(L, n).argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+        getattr(L, n).restype = st
+    L.hmc_server_take.argtypes = [vp, ctypes.c_uint64, vp]
+    L.hmc_server_take.restype = st
+    L.hmc_server_get_stats.argtypes = [vp, ctypes.POINTER(hmc_server_stats)]
+    L.hmc_server_get_stats.restype = st
+    L.hmc_server_destroy.argtypes = [vp]
+    L.hmc_server_destroy.restype = st
     _lib = L
     return L
 
@@ -150,6 +179,44 @@ def hmc_destroy(ctx):
 
 def hmc_effective_form(ctx) -> int:
     return lib().hmc_effective_form(ctx)
+
+
+def hmc_server_create(hbm_budget_bytes: int, transitions_per_tick: int):
+    srv = ctypes.c_void_p()
+    _check(lib().hmc_server_create(hbm_budget_bytes, transitions_per_tick, ctypes.byref(srv)))
+    return srv
+
+
+def hmc_server_submit(srv, req: hmc_request) -> int:
+    rid = ctypes.c_uint64(0)
+    _check(lib().hmc_server_submit(srv, ctypes.byref(req), ctypes.byref(rid)))
+    return rid.value
+
+
+def hmc_server_poll(srv, rid: int):
+    state, lat = ctypes.c_int32(0), ctypes.c_double(0)
+    _check(lib().hmc_server_poll(srv, rid, ctypes.byref(state), ctypes.byref(lat)))
+    return state.value, lat.value
+
+
+def hmc_server_wait(srv, rid: int):
+    state, lat = ctypes.c_int32(0), ctypes.c_double(0)
+    _check(lib().hmc_server_wait(srv, rid, ctypes.byref(state), ctypes.byref(lat)))
+    return state.value, lat.value
+
+
+def hmc_server_take(srv, rid: int, dst_ptr):
+    _check(lib().hmc_server_take(srv, rid, dst_ptr))
+
+
+def hmc_server_get_stats(srv) -> dict:
+    s = hmc_server_stats()
+    _check(lib().hmc_server_get_stats(srv, ctypes.byref(s)))
+    return {n: getattr(s, n) for n, _ in hmc_server_stats._fields_}
+
+
+def hmc_server_destroy(srv):
+    _check(lib().hmc_server_destroy(srv))
 
 
 # ---- convenience wrapper over torch tensors --------------------------------
@@ -274,3 +341,90 @@ def sampler_for(w, device="cuda", form=HMC_FORM_AUTO, grad_bf16=False, num_chain
                 prior_scale=w.prior_scale, x_bf16=x_bf16, seed=w.seed if seed is None else seed, form=form,
                 grad_bf16=grad_bf16)
     return s
+
+
+class Server:
+    """Continuous-batching sampling server over torch tensors.  submit() keeps
+    references to every tensor of a request until it is collected."""
+
+    def __init__(self, hbm_budget_bytes: int, transitions_per_tick: int = 10, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.srv = hmc_server_create(hbm_budget_bytes, transitions_per_tick)
+        self.keep = {}
+
+    def submit(self, w, **kw):
+        """Queue a workloads.Workload as one sampling request; returns its id."""
+        return self.submit_prepared(self.prepare(w, **kw))
+
+    def submit_prepared(self, prep):
+        req, keep = prep
+        rid = hmc_server_submit(self.srv, req)
+        self.keep[rid] = keep
+        return rid
+
+    def prepare(self, w, num_chains=None, seed=None, form=HMC_FORM_AUTO, grad_bf16=False, server_samples=False,
+                trace=True):
+        """Upload a request's inputs and allocate its outputs; submit_prepared queues it."""
+        import numpy as np
+        torch = self.torch
+        dev = self.device
+        C = w.num_chains if num_chains is None else num_chains
+        init = torch.from_numpy(np.ascontiguousarray(w.x0[:C])).to(dev)
+        prec = X = y = None
+        x_bf16 = False
+        if w.prec is not None:
+            prec = torch.from_numpy(np.ascontiguousarray(w.prec)).to(dev)
+        if w.X is not None:
+            if w.X_bf16 is not None:
+                X = torch.from_numpy(w.X_bf16.view(np.int16)).to(dev)
+                x_bf16 = True
+            else:
+                X = torch.from_numpy(np.ascontiguousarray(w.X)).to(dev)
+            y = torch.from_numpy(w.y).to(dev)
+        dt = torch.float64 if w.state_dtype == "f64" else torch.float32
+        R = w.num_results
+        samples = None if server_samples else torch.empty(R, C, w.dim, dtype=dt, device=dev)
+        outs = {}
+        tr = hmc_trace()
+        if trace:
+            outs = dict(step_size=torch.empty(R, C, dtype=torch.float64, device=dev),
+                        is_accepted=torch.empty(R, C, dtype=torch.uint8, device=dev),
+                        log_accept_ratio=torch.empty(R, C, dtype=torch.float64, device=dev),
+                        target_log_prob=torch.empty(R, C, dtype=torch.float64, device=dev))
+            tr = hmc_trace(*[_ptr(outs[k]) for k in ("step_size", "is_accepted", "log_accept_ratio",
+                                                      "target_log_prob")])
+        target = hmc_target(w.kind, 0, w.dim, _ptr(prec), _ptr(X), HMC_BF16 if x_bf16 else HMC_F32, 0,
+                            0 if X is None else X.shape[0], _ptr(y), float(w.prior_scale))
+        config = hmc_config(C, w.num_leapfrog_steps, HMC_F64 if w.state_dtype == "f64" else HMC_F32,
+                            HMC_BF16 if grad_bf16 else HMC_F32, form, w.seed if seed is None else seed)
+        adapt = hmc_adapt(1 if w.adapt else 0, 0, 0.8, 0.05, 10.0, 0.75)
+        torch.cuda.synchronize(dev)    # inputs are on the device before the worker reads them
+        req = hmc_request(target, config, _ptr(init), float(w.step_size), R, w.num_burnin, adapt, _ptr(samples), tr)
+        outs["samples"] = samples
+        keep = dict(tensors=[t for t in (init, prec, X, y) if t is not None], outs=outs, shape=(R, C, w.dim),
+                    dtype=dt)
+        return req, keep
+
+    def poll(self, rid):
+        return hmc_server_poll(self.srv, rid)
+
+    def wait(self, rid):
+        """Block until done; returns (outputs dict, latency seconds)."""
+        state, lat = hmc_server_wait(self.srv, rid)
+        k = self.keep[rid]
+        out = k["outs"]
+        if out.get("samples") is None and k["shape"][0] > 0:
+            dst = self.torch.empty(*k["shape"], dtype=k["dtype"], device=self.device)
+            hmc_server_take(self.srv, rid, _ptr(dst))
+            out["samples"] = dst
+        return out, lat
+
+    def stats(self):
+        return hmc_server_get_stats(self.srv)
+
+    def close(self):
+        if self.srv is not None:
+            hmc_server_destroy(self.srv)
+            self.srv = None

@@ -1,0 +1,94 @@
+"""Serving form: continuous batching of sampling requests of differing target,
+dimension, data size and chain count.  A request's samples are bitwise the
+same alone, in a mix of concurrent requests, and as one hmc_sample_chain call
+(its random streams are keyed by its own seed and chain ids, its kernels read
+and write only its own memory, and the fused kernels resume exactly between
+ticks).  Admission follows the HBM budget."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import gpu_available, to_np
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import torch  # noqa: E402
+
+from paper_2002_01184_amd import hmc  # noqa: E402
+
+
+def _requests():
+    a = W.std_normal_1d(num_chains=300, dim=7, state_dtype="f32", L=5, step_size=0.4, burnin=30, results=20, seed=11)
+    b = W.gauss_diag(dim=100, num_chains=200, L=8, step_size=0.05, burnin=200, results=250, seed=12)
+    b2 = W.gauss_diag(dim=90, num_chains=77, L=6, step_size=0.05, burnin=130, results=170, seed=13, adapt=True)
+    c = W.std_normal_1d(num_chains=100, burnin=40, results=20, seed=14)
+    d = W.gauss_dense(dim=37, num_chains=45, L=7, step_size=0.1, burnin=10, results=12, seed=15)
+    e = W.logreg(1000, 25, 64, L=5, step_size=0.05, burnin=25, results=15, seed=16)
+    f = W.logreg(3000, 40, 100, L=4, step_size=0.01, burnin=6, results=9, seed=17, init=0.3)
+    return [a, b, b2, c, d, e, f]
+
+
+def _reference(w):
+    s = hmc.sampler_for(w)
+    out = s.sample_chain(w.num_results, w.num_burnin, adapt=w.adapt)
+    torch.cuda.synchronize()
+    res = {k: v.clone() for k, v in out.items() if v is not None}
+    s.close()
+    return res
+
+
+def test_server_results_equal_sample_chain_alone_and_in_mix():
+    reqs = _requests()
+    refs = [_reference(w) for w in reqs]
+    # alone: one request at a time
+    srv = hmc.Server(2 << 30, transitions_per_tick=7)
+    alone = []
+    for w in reqs:
+        rid = srv.submit(w)
+        out, lat = srv.wait(rid)
+        assert lat > 0
+        alone.append(out)
+    # mix: the long diagonal Gaussians first, the rest arriving while they run,
+    # some with server-held samples
+    order = [1, 2, 0, 3, 4, 5, 6]
+    preps = {i: srv.prepare(reqs[i], server_samples=(n % 2 == 1)) for n, i in enumerate(order)}
+    mix_ids = {}
+    for i in order:
+        mix_ids[i] = srv.submit_prepared(preps[i])
+    mix = [srv.wait(mix_ids[i])[0] for i in range(len(reqs))]
+    st = srv.stats()
+    srv.close()
+    print("server stats:", st)
+    for w, r, al, mx in zip(reqs, refs, alone, mix):
+        for k in ["samples", "is_accepted", "step_size", "target_log_prob"]:
+            assert torch.equal(al[k], r[k]), (w.name, k, "alone vs sample_chain")
+            assert torch.equal(mx[k], r[k]), (w.name, k, "mix vs sample_chain")
+    assert st["completed"] == 2 * len(reqs) and st["failed"] == 0
+    assert st["max_active"] >= 3
+    assert st["batched_launches"] >= 1         # the two diagonal Gaussians share a ragged launch
+
+
+def test_server_admission_follows_budget():
+    w = W.gauss_diag(dim=64, num_chains=512, L=5, step_size=0.05, burnin=10, results=10, seed=3)
+    t = hmc.hmc_target(w.kind, 0, w.dim, None, None, hmc.HMC_F32, 0, 0, None, 1.0)
+    t.prec = 1      # any non-null pointer for the size query
+    cfg = hmc.hmc_config(w.num_chains, w.num_leapfrog_steps, hmc.HMC_F32, hmc.HMC_F32, 0, 0)
+    ws = hmc.hmc_workspace_size(t, cfg)
+    smp = w.num_results * w.num_chains * w.dim * 4
+    one = ((ws + 255) // 256 + (smp + 255) // 256) * 256
+    srv = hmc.Server(int(one * 1.5), transitions_per_tick=5)     # room for one request at a time
+    ids = [srv.submit(w, seed=s, server_samples=True) for s in range(4)]
+    outs = [srv.wait(i)[0] for i in ids]
+    st = srv.stats()
+    assert st["max_active"] == 1 and st["completed"] == 4
+    assert st["peak_bytes_in_use"] <= st["pool_bytes"]
+    big = W.gauss_diag(dim=64, num_chains=4096, L=5, step_size=0.05, burnin=10, results=10)
+    with pytest.raises(hmc.HMCError) as e:
+        srv.submit(big, server_samples=True)
+    assert e.value.status == hmc.HMC_E_NOMEM
+    srv.close()
+    # different seeds give different chains; same seed reproduces
+    assert not torch.equal(outs[0]["samples"], outs[1]["samples"])
