@@ -77,6 +77,54 @@ def cpu_baseline(w, budget_s=12.0):
                       f"FP64, {el:.1f} s wall"}
 
 
+def bench_served(args):
+    """Served stream: requests arrive by a seeded Poisson process; each is
+    submitted to the continuous-batching server at its arrival time.  Reports
+    p50/p99 request latency (submission to completion) and whole-stream
+    leapfrog chain-steps/s."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2002_01184_amd import hmc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    stream = W.served_stream(n_requests=args.requests, rate=args.rate, seed=0, scale=args.scale)
+    srv = hmc.Server(int(args.budget_gb * (1 << 30)), transitions_per_tick=args.tick)
+    # inputs of every request uploaded before the clock starts (arrivals then cost one C call)
+    preps = []
+    for _, w in stream:
+        bf = w.kind == W.LOGREG and w.dim <= 256
+        preps.append(srv.prepare(w, grad_bf16=bf, server_samples=True, trace=False))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ids = []
+    for (ta, w), p in zip(stream, preps):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        ids.append(srv.submit_prepared(p))
+    lats = []
+    for rid in ids:
+        state, lat = hmc.hmc_server_wait(srv.srv, rid)
+        lats.append(lat)
+    makespan = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lats = np.array(lats)
+    chain_steps = sum(w.chain_steps() for _, w in stream)
+    return {
+        "metric": METRIC, "value": chain_steps / makespan, "unit": "leapfrog chain-steps/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": makespan * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (Gaussian), bf16/f32 (logistic)", "data": "synthetic (seeded stream)",
+        "config": {"workload": f"served_stream_{args.scale}", "requests": args.requests, "rate_per_s": args.rate,
+                   "transitions_per_tick": args.tick, "hbm_budget_gb": args.budget_gb},
+        "latency_p50_s": float(np.percentile(lats, 50)), "latency_p99_s": float(np.percentile(lats, 99)),
+        "latency_max_s": float(lats.max()), "offered_chain_steps": chain_steps,
+        "server": {k: int(v) for k, v in st.items()},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +139,12 @@ def main():
                     help="bf16: BF16 MFMA gradient contractions (logistic regression with BF16 X)")
     ap.add_argument("--transitions", type=int, default=None,
                     help="override burn-in + results (split evenly) for the large configurations")
+    ap.add_argument("--requests", type=int, default=64, help="served_stream: number of requests")
+    ap.add_argument("--rate", type=float, default=50.0, help="served_stream: arrivals per second")
+    ap.add_argument("--scale", default="small", choices=["small", "full"], help="served_stream request sizes")
+    ap.add_argument("--tick", type=int, default=10, help="served_stream: transitions per server tick")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="served_stream: server HBM pool")
+    ap.add_argument("--autotune", action="store_true", help="run the library's autotuner before timing")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -106,6 +160,9 @@ def main():
     from paper_2002_01184_amd import hmc
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.config == "served_stream":
+        print(json.dumps(bench_served(args)), flush=True)
+        return
     dev = torch.device("cuda:0")
     w = W.CONFIGS[args.config]()
     if args.transitions is not None:
@@ -114,6 +171,7 @@ def main():
     form = {"auto": hmc.HMC_FORM_AUTO, "plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_GRAPH,
             "fused": hmc.HMC_FORM_FUSED}[args.form]
     s = hmc.sampler_for(w, device=dev, form=form, grad_bf16=args.grad == "bf16")
+    tune_report = s.autotune(2) if args.autotune else None
     x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).to(dev)
     eps0 = torch.full((w.num_chains,), float(w.step_size), dtype=torch.float64, device=dev)
     T = w.num_burnin + w.num_results
@@ -170,6 +228,8 @@ def main():
                    "form": s.form, "parallelism": "chains (1 GPU)"},
         "roofline": roof,
     }
+    if tune_report is not None:
+        result["autotune"] = tune_report.strip().splitlines()
     if not args.no_diagnostics and out.get("samples") is not None:
         smp = out["samples"].float().cpu().numpy()
         summ = dg.summarize(smp)

@@ -177,6 +177,19 @@ const char* hmc_last_error(void);
  * (HMC_FORM_PLAIN, HMC_FORM_FUSED or HMC_FORM_GRAPH). */
 int32_t hmc_effective_form(const hmc_ctx* ctx);
 
+/* Autotuner: times every launch configuration that applies to this context
+ * (form fused / plain / graph when the context was created with
+ * HMC_FORM_AUTO; lanes per chain of the fused elementwise kernel; row splits
+ * of the logistic-regression kernels) over trial_transitions transitions
+ * each, with HIP events on the context's stream, and keeps the fastest.  The
+ * chain state, step sizes and t are restored after every trial, so the
+ * sampled chain is unchanged apart from the arithmetic order of the chosen
+ * kernels.  Choices are cached per (target family, D, log2 N, log2 C, dtypes,
+ * L, requested form) for the process and appended to the file named by the
+ * environment variable HMC_AUTOTUNE_CACHE when set.  report (host, may be
+ * NULL) receives one line per candidate.  Synchronizes the stream. */
+hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char* report, size_t report_len);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of sampling requests (one sample_chain each)
  * of differing target, dimension, data size and chain count on one GPU.

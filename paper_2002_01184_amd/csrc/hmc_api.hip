@@ -2,7 +2,13 @@
 // workspace layout, form selection and stream-ordered launches.
 #include <cmath>
 #include <cstdio>
+#include <chrono>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -49,10 +55,10 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
     const size_t es = elem_size(cfg.state_dtype);
     const size_t state = (size_t)C * D * es;
     const bool bf16 = cfg.grad_dtype == HMC_BF16;
-    int64_t nsplit = tg.kind == HMC_TGT_LOGREG ? logreg_nsplit(tg.N, C) : 0;
+    int64_t nsplit = tg.kind == HMC_TGT_LOGREG ? logreg_nsplit_cap(tg.N, C) : 0;
     int64_t nsplit_lp = nsplit;
     if (bf16) {
-        nsplit = nsplit > lb_grad_nsplit(tg.N, C) ? nsplit : lb_grad_nsplit(tg.N, C);
+        nsplit = nsplit > 8 ? nsplit : 8;          // BF16 split counts 1, 2, 4, 8
         nsplit_lp = nsplit > lb_logp_nsplit(tg.N, C) ? nsplit : lb_logp_nsplit(tg.N, C);
     }
     char* p = (char*)base;
@@ -76,6 +82,11 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
     w.part_g = (float*)take((size_t)nsplit * C * D * 4);
     w.part_lp = (double*)take((size_t)nsplit_lp * C * 8);
     w.xt = bf16 ? take((size_t)tg.N * D * 2) : nullptr;
+    w.bk_x = take(state);
+    w.bk_g = take(state);
+    w.bk_logp = (double*)take((size_t)C * 8);
+    w.bk_eps = (double*)take((size_t)C * 8);
+    w.bk_da = (DualAvg*)take((size_t)C * sizeof(DualAvg));
     w.ctrl = (Ctrl*)take(sizeof(Ctrl));
     w.bytes = off;
     if (total) *total = off;
@@ -398,3 +409,194 @@ hmc_status hmc_destroy(hmc_ctx* ctx) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner: times the launch configurations that apply to this context with
+// HIP events on its stream, restores the chain state after every trial, and
+// keeps the fastest.  Choices are cached per (target family, D, log2 N,
+// log2 C, dtypes, L, requested form) in memory and, when HMC_AUTOTUNE_CACHE
+// names a file, on disk (one "key form lr_nsplit lr16_nsplit elem_gmult" line
+// per entry).
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneChoice {
+    int32_t form;
+    Tune tune;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune_cache;
+bool g_tune_loaded = false;
+
+int ilog2(int64_t v) {
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+std::string tune_key(const hmc_ctx* ctx) {
+    std::ostringstream k;
+    k << ctx->a.tg.kind << ":" << ctx->a.tg.D << ":" << ilog2(ctx->a.tg.N + 1) << ":" << ilog2(ctx->a.C) << ":"
+      << ctx->cfg.state_dtype << ":" << ctx->cfg.grad_dtype << ":" << ctx->a.L << ":" << ctx->cfg.form;
+    return k.str();
+}
+
+void load_cache_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("HMC_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string key;
+    TuneChoice c;
+    while (f >> key >> c.form >> c.tune.lr_nsplit >> c.tune.lr16_nsplit >> c.tune.elem_gmult) g_tune_cache[key] = c;
+}
+
+void store_cache_locked(const std::string& key, const TuneChoice& c) {
+    g_tune_cache[key] = c;
+    const char* path = std::getenv("HMC_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << c.form << " " << c.tune.lr_nsplit << " " << c.tune.lr16_nsplit << " " << c.tune.elem_gmult
+      << "\n";
+}
+
+hipError_t save_state(hmc_ctx* ctx, bool restore) {
+    const Workspace& w = ctx->a.ws;
+    const size_t state = (size_t)ctx->a.C * ctx->a.tg.D * (ctx->a.f64 ? 8 : 4);
+    const size_t C = (size_t)ctx->a.C;
+    struct {
+        void* live;
+        void* bk;
+        size_t n;
+    } parts[] = {{w.x, w.bk_x, state}, {w.g, w.bk_g, state}, {w.logp, w.bk_logp, C * 8},
+                 {w.eps, w.bk_eps, C * 8}, {w.da, w.bk_da, C * sizeof(DualAvg)}};
+    for (auto& p : parts) {
+        hipError_t e = restore ? hipMemcpyAsync(p.live, p.bk, p.n, hipMemcpyDeviceToDevice, ctx->stream)
+                               : hipMemcpyAsync(p.bk, p.live, p.n, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void drop_graph(hmc_ctx* ctx) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+    ctx->graph_ready = false;
+}
+
+// n burn-in transitions without adaptation, samples or traces (the state is restored afterwards)
+hmc_status trial_run(hmc_ctx* ctx, int64_t n) {
+    if (ctx->form == HMC_FORM_FUSED) {
+        FusedRun r;
+        memset(&r, 0, sizeof(r));
+        r.t_begin = ctx->t;
+        r.n_transitions = n;
+        r.n_burnin = n;
+        return check_hip(launch_fused(ctx->a, r, ctx->stream), "autotune trial");
+    }
+    Ctrl c = base_ctrl(ctx);
+    c.n_burnin = n;
+    hmc_status st = check_hip(launch_set_ctrl(c, ctx->a.ws.ctrl, ctx->stream), "autotune control");
+    if (st == HMC_OK) st = run_transitions(ctx, n, false);
+    return st;
+}
+}  // namespace
+
+extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char* report, size_t report_len) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (trial_transitions < 1) return fail(HMC_E_INVALID, "trial_transitions must be >= 1");
+    const std::string key = tune_key(ctx);
+    std::ostringstream rep;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_cache_locked();
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            ctx->form = it->second.form;
+            ctx->a.tune = it->second.tune;
+            drop_graph(ctx);
+            rep << "cached " << key << " form=" << ctx->form;
+            if (report && report_len) snprintf(report, report_len, "%s", rep.str().c_str());
+            return HMC_OK;
+        }
+    }
+    std::vector<TuneChoice> cands;
+    std::vector<int32_t> forms;
+    if (ctx->cfg.form == HMC_FORM_AUTO) {
+        if (fused_supported(ctx->a)) forms.push_back(HMC_FORM_FUSED);
+        forms.push_back(HMC_FORM_PLAIN);
+        forms.push_back(HMC_FORM_GRAPH);
+    } else {
+        forms.push_back(ctx->form);
+    }
+    const bool elem = ctx->a.tg.kind == HMC_TGT_STD_NORMAL || ctx->a.tg.kind == HMC_TGT_GAUSS_DIAG;
+    for (int32_t f : forms) {
+        TuneChoice c{f, Tune{0, 0, 0}};
+        if (f == HMC_FORM_FUSED && elem) {
+            cands.push_back(c);
+            c.tune.elem_gmult = 2;
+            cands.push_back(c);
+        } else if (f != HMC_FORM_FUSED && ctx->a.tg.kind == HMC_TGT_LOGREG && ctx->a.bf16_grad) {
+            for (int s : {1, 2, 4, 8}) {
+                c.tune.lr16_nsplit = s;
+                cands.push_back(c);
+            }
+        } else if (f != HMC_FORM_FUSED && ctx->a.tg.kind == HMC_TGT_LOGREG) {
+            const int64_t d = logreg_nsplit(ctx->a.tg.N, ctx->a.C);
+            for (int64_t s : {d / 2, d, 2 * d})
+                if (s >= 1 && s <= 64) {
+                    c.tune.lr_nsplit = (int32_t)s;
+                    cands.push_back(c);
+                }
+        } else {
+            cands.push_back(c);
+        }
+    }
+    const int32_t form0 = ctx->form;
+    const Tune tune0 = ctx->a.tune;
+    hmc_status st = check_hip(save_state(ctx, false), "autotune backup");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == HMC_OK) st = check_hip(hipEventCreate(&e0), "event");
+    if (st == HMC_OK) st = check_hip(hipEventCreate(&e1), "event");
+    float best = 1e30f;
+    TuneChoice bestc{form0, tune0};
+    for (size_t i = 0; st == HMC_OK && i < cands.size(); ++i) {
+        ctx->form = cands[i].form;
+        ctx->a.tune = cands[i].tune;
+        drop_graph(ctx);
+        st = trial_run(ctx, 1);   // warm-up (graph capture, code load)
+        if (st == HMC_OK) st = check_hip(save_state(ctx, true), "autotune restore");
+        if (st == HMC_OK) st = check_hip(hipEventRecord(e0, ctx->stream), "event");
+        if (st == HMC_OK) st = trial_run(ctx, trial_transitions);
+        if (st == HMC_OK) st = check_hip(hipEventRecord(e1, ctx->stream), "event");
+        if (st == HMC_OK) st = check_hip(hipEventSynchronize(e1), "event");
+        float ms = 0.f;
+        if (st == HMC_OK) st = check_hip(hipEventElapsedTime(&ms, e0, e1), "event");
+        if (st == HMC_OK) st = check_hip(save_state(ctx, true), "autotune restore");
+        if (st != HMC_OK) break;
+        rep << "form=" << cands[i].form << " lr_nsplit=" << cands[i].tune.lr_nsplit
+            << " lr16_nsplit=" << cands[i].tune.lr16_nsplit << " elem_gmult=" << cands[i].tune.elem_gmult << ": "
+            << ms / trial_transitions << " ms/transition\n";
+        if (ms < best) {
+            best = ms;
+            bestc = cands[i];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    ctx->form = st == HMC_OK ? bestc.form : form0;
+    ctx->a.tune = st == HMC_OK ? bestc.tune : tune0;
+    drop_graph(ctx);
+    if (st == HMC_OK) st = check_hip(launch_set_ctrl(base_ctrl(ctx), ctx->a.ws.ctrl, ctx->stream), "control");
+    if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "autotune");
+    if (st == HMC_OK) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        store_cache_locked(key, bestc);
+    }
+    rep << "chosen form=" << ctx->form;
+    if (report && report_len) snprintf(report, report_len, "%s", rep.str().c_str());
+    return st;
+}

@@ -39,6 +39,11 @@ struct Workspace {
     float* part_g;     // [nsplit, C, D] split-N gradient partials (LOGREG plain)
     double* part_lp;   // [nsplit, C]
     void* xt;          // [D, N] BF16 transposed copy of X (BF16 gradients only)
+    void* bk_x;        // autotuner backup of the chain state: [C, D] x and g, [C] logp and eps, [C] da
+    void* bk_g;
+    double* bk_logp;
+    double* bk_eps;
+    DualAvg* bk_da;
     Ctrl* ctrl;
     size_t bytes;
 };
@@ -46,15 +51,24 @@ struct Workspace {
 hmc_status fail(hmc_status st, const std::string& msg);
 hmc_status validate_args(const hmc_target* tg, const hmc_config* cfg, TargetDev* out);
 int64_t logreg_nsplit(int64_t N, int64_t C);
+int64_t logreg_nsplit_cap(int64_t N, int64_t C);
 int lb_grad_nsplit(int64_t N, int64_t C);
 int lb_logp_nsplit(int64_t N, int64_t C);
 bool bf16_grad_supported(const TargetDev& tg);
 Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg, size_t* total);
 size_t elem_size(int32_t dtype);
 
+// Launch-shape choices (0 = built-in heuristic), set by the autotuner.
+struct Tune {
+    int32_t lr_nsplit;     // row splits of the FP32 logistic plain kernel
+    int32_t lr16_nsplit;   // row splits of the BF16 logistic kernel (1, 2, 4, 8)
+    int32_t elem_gmult;    // lanes per chain multiplier of the fused elementwise kernel (1 or 2)
+};
+
 // ---- plain path launchers (k_plain.hip) -----------------------------------
 struct PlainArgs {
     TargetDev tg;
+    Tune tune;
     int64_t C;
     int32_t L;
     bool f64;          // state dtype
@@ -62,6 +76,8 @@ struct PlainArgs {
     Key key;
     Workspace ws;
 };
+int64_t logreg_nsplit_t(const PlainArgs& a);
+int lb_grad_nsplit_t(const PlainArgs& a);
 hipError_t launch_set_ctrl(const Ctrl& c, Ctrl* dst, hipStream_t s);
 hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s);
 hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipStream_t s);

@@ -413,17 +413,26 @@ static int elem_class_of(int G, int NB) {
     return NB == 1 ? 3 : (NB == 2 ? 4 : (NB == 4 ? 5 : 6));
 }
 
+// lanes per chain G and 4-blocks per lane NB, after the tuned multiplier
+// (doubling G halves NB when the blocks still cover D)
+static int elem_shape(const PlainArgs& a, int* G) {
+    int NB = elem_nb(a.tg.D, G);
+    if (NB == 0) return 0;
+    if (a.tune.elem_gmult == 2 && *G < 64) *G = *G == 1 ? 4 : 4 * *G;   // next wider lane group
+    return NB;
+}
+
 int elem_class(const PlainArgs& a) {
     if (a.tg.kind != HMC_TGT_STD_NORMAL && a.tg.kind != HMC_TGT_GAUSS_DIAG) return -1;
     int G;
-    const int NB = elem_nb(a.tg.D, &G);
+    const int NB = elem_shape(a, &G);
     if (NB == 0) return -1;
     return (a.f64 ? 8 : 0) + elem_class_of(G, NB);
 }
 
 int64_t elem_blocks(const PlainArgs& a) {
     int G;
-    elem_nb(a.tg.D, &G);
+    elem_shape(a, &G);
     return (a.C * G + 255) / 256;
 }
 

@@ -417,6 +417,9 @@ static int pow2_split(int ntile, int64_t N) {
 }
 
 int lb_grad_nsplit(int64_t N, int64_t C) { return pow2_split((int)((C + LB_CT - 1) / LB_CT), N); }
+int lb_grad_nsplit_t(const PlainArgs& a) {
+    return a.tune.lr16_nsplit > 0 ? a.tune.lr16_nsplit : lb_grad_nsplit(a.tg.N, a.C);
+}
 int lb_logp_nsplit(int64_t N, int64_t C) { return pow2_split((int)((C + 63) / 64), N); }
 
 static int64_t rows_for(int64_t N, int nsplit) {
@@ -437,7 +440,7 @@ template <int KS>
 static hipError_t lb_grad_k(const PlainArgs& a, const float* x, const float* p, int drift, const void* Xt,
                             hipStream_t s) {
     const int ntile = (int)((a.C + LB_CT - 1) / LB_CT);
-    const int nsplit = lb_grad_nsplit(a.tg.N, a.C);
+    const int nsplit = lb_grad_nsplit_t(a);
     const size_t lds = (size_t)(2 * LB_RS * (32 * KS + LB_XPAD) + 2 * 32 * KS * (LB_RS + LB_TPAD)) * 2 +
                        2 * LB_RS * sizeof(float);
     if (lds > 65536)

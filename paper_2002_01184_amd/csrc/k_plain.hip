@@ -514,9 +514,26 @@ static void launch_logreg_partial_t(const PlainArgs& a, dim3 grid, size_t lds, h
 }
 
 // x (in place, drifted when drift), p (kicked when kick), g into gd if not null
+// largest split count the workspace is sized for (the autotuner tries up to 2x the default)
+int64_t logreg_nsplit_cap(int64_t N, int64_t C) {
+    int64_t cap = 2 * logreg_nsplit(N, C);
+    const int64_t maxs = (N + 63) / 64;
+    if (cap > maxs) cap = maxs;
+    if (cap > 64) cap = 64;
+    return cap < 1 ? 1 : cap;
+}
+
+int64_t logreg_nsplit_t(const PlainArgs& a) {
+    if (a.tune.lr_nsplit > 0) {
+        const int64_t cap = logreg_nsplit_cap(a.tg.N, a.C);
+        return a.tune.lr_nsplit < cap ? a.tune.lr_nsplit : cap;
+    }
+    return logreg_nsplit(a.tg.N, a.C);
+}
+
 static hipError_t launch_logreg(const PlainArgs& a, float* x, float* p, float* gd, int drift, int kick, double ks,
                                 int want_logp, hipStream_t s) {
-    const int64_t nsplit = logreg_nsplit(a.tg.N, a.C);
+    const int64_t nsplit = logreg_nsplit_t(a);
     const int64_t rows = (a.tg.N + nsplit - 1) / nsplit;
     const size_t lds = logreg_lds(a.tg.D);
     const dim3 grid((unsigned)((a.C + 15) / 16), (unsigned)nsplit);
@@ -563,7 +580,7 @@ hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s
         if (a.bf16_grad) {
             (void)launch_lr16_grad(a, (const float*)a.ws.x, nullptr, 0, a.ws.xt, s);
             hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, (float*)a.ws.x,
-                               (float*)nullptr, (float*)a.ws.g, lb_grad_nsplit(a.tg.N, a.C), 0, 0, 0.0, 0);
+                               (float*)nullptr, (float*)a.ws.g, lb_grad_nsplit_t(a), 0, 0, 0.0, 0);
             (void)launch_lr16_logp(a, (const float*)a.ws.x, s);
         } else {
             (void)launch_logreg(a, (float*)a.ws.x, nullptr, (float*)a.ws.g, 0, 0, 0.0, 1, s);
@@ -602,7 +619,7 @@ hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipSt
                 (void)launch_lr16_grad(a, (const float*)a.ws.xq, (const float*)a.ws.pq, 1, a.ws.xt, s);
                 hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, (float*)a.ws.xq,
                                    (float*)a.ws.pq, last ? (float*)a.ws.gq : (float*)nullptr,
-                                   lb_grad_nsplit(a.tg.N, a.C), 1, 1, ks, 0);
+                                   lb_grad_nsplit_t(a), 1, 1, ks, 0);
                 if (last) (void)launch_lr16_logp(a, (const float*)a.ws.xq, s);
                 break;
             }

@@ -71,7 +71,7 @@ class hmc_server_stats(ctypes.Structure):
 HMC_REQ_QUEUED, HMC_REQ_RUNNING, HMC_REQ_DONE, HMC_REQ_FAILED = range(4)
 
 EXPORTED = ["hmc_workspace_size", "hmc_init", "hmc_step", "hmc_sample_chain", "hmc_get_state", "hmc_set_state",
-            "hmc_destroy", "hmc_last_error", "hmc_effective_form", "hmc_server_create", "hmc_server_submit",
+            "hmc_destroy", "hmc_last_error", "hmc_effective_form", "hmc_autotune", "hmc_server_create", "hmc_server_submit",
             "hmc_server_poll", "hmc_server_wait", "hmc_server_take", "hmc_server_get_stats",
             "hmc_server_destroy"]
 
@@ -109,6 +109,8 @@ def lib():
     L.hmc_last_error.restype = ctypes.c_char_p
     L.hmc_effective_form.argtypes = [vp]
     L.hmc_effective_form.restype = ctypes.c_int32
+    L.hmc_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]
+    L.hmc_autotune.restype = st
     L.hmc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
     L.hmc_server_create.restype = st
     L.hmc_server_submit.argtypes = [vp, ctypes.POINTER(hmc_request), ctypes.POINTER(ctypes.c_uint64)]
@@ -179,6 +181,12 @@ def hmc_destroy(ctx):
 
 def hmc_effective_form(ctx) -> int:
     return lib().hmc_effective_form(ctx)
+
+
+def hmc_autotune(ctx, trial_transitions: int = 3) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().hmc_autotune(ctx, trial_transitions, buf, len(buf)))
+    return buf.value.decode()
 
 
 def hmc_server_create(hbm_budget_bytes: int, transitions_per_tick: int):
@@ -258,6 +266,9 @@ class Sampler:
     @property
     def form(self) -> str:
         return FORM_NAMES.get(hmc_effective_form(self.ctx), "?")
+
+    def autotune(self, trial_transitions: int = 3) -> str:
+        return hmc_autotune(self.ctx, trial_transitions)
 
     def step(self, want_proposal=False):
         torch = self.torch

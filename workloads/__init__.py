@@ -181,3 +181,39 @@ CONFIGS = {
     "gauss_dense_100": cfg_gauss_dense_100,
     "logreg_100000x256": cfg_logreg_100000x256,
 }
+
+
+def served_stream(n_requests=64, rate=50.0, seed=0, scale="small"):
+    """Seeded stream of sampling requests with Poisson arrivals.
+
+    Mix: 50% diagonal-Gaussian requests (D ~ U{10..1000}), 50% logistic
+    regression (BF16 X, N ~ U{n_lo..n_hi}, D ~ U{25..d_hi}); chains per request
+    log-uniform in [64, c_hi]; L = 10; burn-in + kept transitions per request.
+    scale="full" is the configuration as stated (N up to 1e5, D up to 512,
+    chains up to 16384, 500 + 500 transitions); scale="small" keeps the mix and
+    the arrival process but bounds N <= 1e4, D <= 128, chains <= 2048 and uses
+    100 + 100 transitions, so that a stream finishes in seconds.
+    Returns a list of (arrival_time_s, Workload)."""
+    rng = _rng(seed, 41)
+    if scale == "full":
+        n_lo, n_hi, d_hi, c_hi, B, R = 1000, 100000, 512, 16384, 500, 500
+    else:
+        n_lo, n_hi, d_hi, c_hi, B, R = 1000, 10000, 128, 2048, 100, 100
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        C = int(round(np.exp(rng.uniform(np.log(64), np.log(c_hi)))))
+        rseed = int(rng.integers(0, 2**31))
+        if rng.uniform() < 0.5:
+            D = int(rng.integers(10, 1001))
+            w = gauss_diag(dim=D, num_chains=C, L=10, step_size=0.05, burnin=B, results=R, seed=rseed,
+                           adapt=True)
+        else:
+            N = int(rng.integers(n_lo, n_hi + 1))
+            D = int(rng.integers(25, d_hi + 1))
+            w = logreg(N, D, C, L=10, step_size=0.01, burnin=B, results=R, seed=rseed, bf16=True, adapt=True,
+                       init=0.1)
+        w.name = f"req{i}_{w.name}"
+        out.append((t, w))
+    return out
