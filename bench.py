@@ -163,6 +163,18 @@ def main():
     if args.config == "served_stream":
         print(json.dumps(bench_served(args)), flush=True)
         return
+    if args.config == "copy_calibration":
+        # a plain device-to-device copy of known size: the reference for scaling
+        # the FETCH_SIZE / WRITE_SIZE counters of the sampler kernels
+        n = 1 << 28                       # 256 Mi float32 = 1 GiB each way
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup + args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"config": "copy_calibration", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
+                          "copies": args.warmup + args.steps}), flush=True)
+        return
     dev = torch.device("cuda:0")
     w = W.CONFIGS[args.config]()
     if args.transitions is not None:

@@ -118,9 +118,9 @@ __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __r
     constexpr int XCH = LB_RS * DP / 8;     // 16-byte chunks of an X sub-tile
     constexpr int TCH = DP * LB_RS / 8;     // 16-byte chunks of an X^T sub-tile
     constexpr int XPT = (XCH + 255) / 256, TPT = (TCH + 255) / 256;
-    uint4 px[XPT], pt[TPT];
-    float py = 0.f;
-    auto fetch = [&](int sidx) {
+    uint4 pxs[2][XPT], pts[2][TPT];
+    float pys[2] = {0.f, 0.f};
+    auto fetch = [&](int sidx, uint4* px, uint4* pt, float& py) {
         const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __r
             py = gr < r_end ? (float)a.tg.y[gr] : 0.f;
         }
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf, const uint4* px, const uint4* pt, float py) {
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
             const int ch = threadIdx.x + 256 * u;
@@ -189,14 +189,18 @@ __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __r
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) gacc[cs][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    // pipeline: sub-tile s is in LDS buffer s % 2 while the loads of s + 1 and
+    // s + 2 are in flight in the two register stages
     if (nsub > 0) {
-        fetch(0);
-        stash(0);
+        fetch(0, pxs[0], pts[0], pys[0]);
+        stash(0, pxs[0], pts[0], pys[0]);
     }
+    if (nsub > 1) fetch(1, pxs[1], pts[1], pys[1]);
     __syncthreads();
-    for (int sidx = 0; sidx < nsub; ++sidx) {
+    auto body = [&](int sidx, uint4* pn, uint4* tn, float& yn, uint4* pf, uint4* tf, float& yf) {
+        // pn/tn/yn: stage holding sub-tile sidx + 1; pf/tf/yf: stage to receive sidx + 2
         const int buf = sidx & 1;
-        if (sidx + 1 < nsub) fetch(sidx + 1);
+        if (sidx + 2 < nsub) fetch(sidx + 2, pf, tf, yf);
         const uint16_t* xb = xs + buf * LB_RS * XS;
         const uint16_t* tb = xts + buf * DP * TS;
         const float* yb = ys + buf * LB_RS;
@@ -243,8 +247,13 @@ __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __r
             for (int cs = 0; cs < 2; ++cs)
                 gacc[cs][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[cs], bx, gacc[cs][nt], 0, 0, 0);
         }
-        if (sidx + 1 < nsub) stash(buf ^ 1);
+        if (sidx + 1 < nsub) stash(buf ^ 1, pn, tn, yn);
         __syncthreads();
+    };
+    for (int sidx = 0; sidx < nsub; sidx += 2) {
+        // stage 1 holds sidx + 1; stage 0 receives sidx + 2
+        body(sidx, pxs[1], pts[1], pys[1], pxs[0], pts[0], pys[0]);
+        if (sidx + 1 < nsub) body(sidx + 1, pxs[0], pts[0], pys[0], pxs[1], pts[1], pys[1]);
     }
     // partial G[chain][dim] for this row chunk
 #pragma unroll
