@@ -77,6 +77,25 @@ def cpu_baseline(w, budget_s=12.0):
                       f"FP64, {el:.1f} s wall"}
 
 
+def ess_run(s, w, x0, eps0, n_results, stream):
+    """One further run from the same start with the same burn-in and n_results
+    kept draws, long enough for split R-hat <= 1.01; ESS/s is the minimum bulk
+    ESS over coordinates divided by the run's wall time (burn-in included)."""
+    import torch
+    from paper_2002_01184_amd import diagnostics as dg
+    s.set_state(x0, eps0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = s.sample_chain(n_results, w.num_burnin, adapt=w.adapt)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    summ = dg.t_summarize(out["samples"])
+    del out
+    return {"num_burnin": w.num_burnin, "num_results": n_results, "seconds": dt,
+            "max_rhat": summ["max_rhat"], "min_ess_bulk": summ["min_ess_bulk"],
+            "ess_per_sec": summ["min_ess_bulk"] / dt if summ["max_rhat"] <= 1.01 else None}
+
+
 def bench_served(args):
     """Served stream: requests arrive by a seeded Poisson process; each is
     submitted to the continuous-batching server at its arrival time.  Reports
@@ -145,6 +164,8 @@ def main():
     ap.add_argument("--tick", type=int, default=10, help="served_stream: transitions per server tick")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="served_stream: server HBM pool")
     ap.add_argument("--autotune", action="store_true", help="run the library's autotuner before timing")
+    ap.add_argument("--ess-results", type=int, default=9000,
+                    help="kept draws of the separate ESS run (same burn-in); 0 skips it")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -243,12 +264,20 @@ def main():
     if tune_report is not None:
         result["autotune"] = tune_report.strip().splitlines()
     if not args.no_diagnostics and out.get("samples") is not None:
-        smp = out["samples"].float().cpu().numpy()
-        summ = dg.summarize(smp)
+        summ = dg.t_summarize(out["samples"])
         result["max_rhat"] = summ["max_rhat"]
         result["min_ess_bulk"] = summ["min_ess_bulk"]
         result["ess_per_sec"] = (summ["min_ess_bulk"] / (elapsed / args.steps)) if summ["max_rhat"] <= 1.01 else None
         result["accept_rate"] = float(out["is_accepted"].float().mean().item())
+        out = None
+        T_long = w.num_burnin + args.ess_results
+        est_s = elapsed / args.steps * T_long / T
+        sample_bytes = args.ess_results * w.num_chains * w.dim * (8 if w.state_dtype == "f64" else 4)
+        if args.ess_results > 0 and result["ess_per_sec"] is None:
+            if est_s <= 60 and sample_bytes <= (16 << 30):
+                result["ess_run"] = ess_run(s, w, x0, eps0, args.ess_results, stream)
+            else:
+                result["ess_run"] = {"skipped": f"estimated {est_s:.0f} s / {sample_bytes / 2**30:.1f} GiB of samples"}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     s.close()

@@ -125,15 +125,27 @@ struct DualAvg {
     double hbar, log_eps_bar, mu;
 };
 
+// The factors of iteration m that do not depend on the chain: the averaging
+// weight 1/(m + t0), the shrinkage sqrt(m)/gamma and the iterate weight m^-kappa.
+struct DaConst {
+    double w, k, eta;
+};
+__device__ __forceinline__ DaConst dual_avg_const(double m, double gamma, double t0, double kappa) {
+    return DaConst{1.0 / (m + t0), sqrt(m) / gamma, pow(m, -kappa)};
+}
+
+// Iteration with accept statistic alpha; returns the new log step size.
+__device__ __forceinline__ double dual_avg_apply(DualAvg& s, const DaConst& c, double alpha, double delta) {
+    s.hbar = (1.0 - c.w) * s.hbar + c.w * (delta - alpha);
+    const double log_eps = s.mu - c.k * s.hbar;
+    s.log_eps_bar = c.eta * log_eps + (1.0 - c.eta) * s.log_eps_bar;
+    return log_eps;
+}
+
 // Iteration m >= 1 with accept statistic alpha; returns the new log step size.
 __device__ __forceinline__ double dual_avg_update(DualAvg& s, double m, double alpha, double delta,
                                                   double gamma, double t0, double kappa) {
-    const double w = 1.0 / (m + t0);
-    s.hbar = (1.0 - w) * s.hbar + w * (delta - alpha);
-    const double log_eps = s.mu - sqrt(m) / gamma * s.hbar;
-    const double eta = pow(m, -kappa);
-    s.log_eps_bar = eta * log_eps + (1.0 - eta) * s.log_eps_bar;
-    return log_eps;
+    return dual_avg_apply(s, dual_avg_const(m, gamma, t0, kappa), alpha, delta);
 }
 
 // Control block of the plain/graph path (device resident, written by a

@@ -13,21 +13,24 @@
 // Lane layouts (wave64, lane = 4 b + j, b = 0..15 block, j = 0..3):
 //   first contraction, one instruction per dim d:
 //     A[b][i] = X[row0 + 4b + i][d]   (lane l holds its own row l)
-//     B[b][j] = theta[chain j][d]
+//     B[b][j] = theta[chain j][d]     (one lane group broadcast to all by BLGP)
 //     D[b][i][j] -> VGPR i of lane 4b + j = S[row0 + 4b + i][chain j]
 //   second contraction, one instruction per (row offset v, dim group q):
 //     A[b][i] = R[row0 + 4b + v][chain i]   = VGPR v of the S result (no shuffles)
 //     B[b][j] = X[row0 + 4b + v][4q + j]
 //     D[b][i][j] accumulates G[chain i][4q + j] over the rows of block b
-// Block partials are summed across a 16-lane row with DPP rotates, across
-// rows and waves in LDS in a fixed order (bitwise-reproducible).
+// The 16 block partials of G are summed inside the wave: a reduce-scatter over
+// the four 16-lane rows (v_permlane32_swap, v_permlane16_swap) leaves chain i's
+// values in row i, and two DPP rotates finish each row.  The 8 wave partials are
+// summed in LDS in a fixed order, so results are bitwise reproducible.
 //
-// X lives in LDS with permuted columns (stored column (d % 4) * 8 + d / 4) so
-// that the 8 dims 4q + j a lane needs for the second contraction are two
-// 16-byte reads; each wave keeps the first-contraction rows of its tiles in
-// VGPRs for the whole kernel.  Threads 0..127 own (chain i = t / 32,
-// dim d = t % 32) of the chain state: theta, momentum, gradient, the accepted
-// state, and do the momentum draw, kicks, drifts and the accept test.
+// Each wave keeps the X rows of its tiles in VGPRs, in both operand layouts,
+// for the whole kernel.  Threads 0..127 own (chain i = t / 32, dim d = t % 32)
+// of the chain state: theta, momentum, gradient and the accepted state; they
+// sum the wave partials, kick, drift and take the accept decision.  The other
+// waves draw momenta for the next 32 transitions, and accept uniforms and
+// dual-averaging factors for the next 128, into LDS whenever a block of them
+// runs out; they would otherwise wait for the owners at the transition boundary.
 #include "hmc_internal.hpp"
 
 namespace hmc {
@@ -35,7 +38,9 @@ namespace hmc {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int LR_NW = 8;          // waves per workgroup
-constexpr int LR_PART = 512;      // floats per wave in the gradient partial buffer: 4 rows x 8 q x 16
+constexpr int LR_PS = 36;         // row stride (floats) of the per-wave gradient partials
+constexpr int LR_ZT = 32;         // transitions of momenta drawn at a time
+constexpr int LR_UT = 128;        // transitions of accept uniforms / DA factors drawn at a time
 
 __device__ __forceinline__ float dpp_ror(float v, int n) {
     // rotate right within a row of 16 lanes
@@ -45,6 +50,70 @@ __device__ __forceinline__ float dpp_ror(float v, int n) {
     else
         r = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, true);
     return __int_as_float(r);
+}
+
+// 4x4x1 MFMA whose B operand is lane group g (lanes 16g..16g+15) broadcast to
+// all four groups (BLGP = 4 + g); g is a constant after unrolling.
+__device__ __forceinline__ floatx4 mfma4_bgroup(int g, float a, float b, floatx4 c) {
+    switch (g) {
+    case 0: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 4);
+    case 1: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 5);
+    case 2: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 6);
+    default: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 7);
+    }
+}
+
+// Row k (lanes 16k..16k+15) of the result holds, per lane position, the sum
+// of input k over the four rows.  permlane32_swap(x, y) gives
+// ([x.lo, y.lo], [x.hi, y.hi]) and permlane16_swap(x, y) gives rows
+// ([x0, y0, x2, y2], [x1, y1, x3, y3]).
+__device__ __forceinline__ float rows4_scatter(float a0, float a1, float a2, float a3) {
+    const auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(a0), __float_as_uint(a2), false, false);
+    const auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(a1), __float_as_uint(a3), false, false);
+    const float c02 = __uint_as_float(s02[0]) + __uint_as_float(s02[1]);
+    const float c13 = __uint_as_float(s13[0]) + __uint_as_float(s13[1]);
+    const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(c02), __float_as_uint(c13), false, false);
+    return __uint_as_float(t[0]) + __uint_as_float(t[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum of rows 2k and 2k+1 (k = 0, 1), in both rows.
+__device__ __forceinline__ double rows2_sum(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+    const double a = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+    const double b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+    return a + b;
+}
+
+// Sum over the 32 lanes of each half wave, as a butterfly: every step adds a
+// lane's value and its partner's, so all 32 lanes end with the same bits.
+__device__ __forceinline__ double half_wave_sum(double v) {
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]: partner lane ^ 1
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]: partner lane ^ 2
+    v += dpp_f64<0x141>(v);   // row_half_mirror: the two quads of each 8 lanes
+    v += dpp_f64<0x140>(v);   // row_mirror: the two halves of each row
+    return rows2_sum(v);
+}
+
+// Sum over the 16 lanes of equal lane % 4; lanes 0..3 hold the result.
+__device__ __forceinline__ double same_j_sum(double v) {
+    v += dpp_f64<0x124>(v);   // row_ror 4
+    v += dpp_f64<0x128>(v);   // row_ror 8
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)u, (uint32_t)u, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+    v = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0])) +
+        __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+    return rows2_sum(v);
 }
 
 // 1 / (1 + e^-s) with the hardware exp2 and reciprocal (about 1 ulp each);
@@ -58,33 +127,42 @@ __device__ __forceinline__ float sigmoid_fast(float s) {
 // hardware log2 when e >= 2^-10, else its series e - e^2/2 + e^3/3 (error < e^4/4).
 __device__ __forceinline__ float softplus_f(float s) {
     const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * fabsf(s));
-    const float l = e >= 0x1p-10f ? 0.69314718055994531f * __builtin_amdgcn_logf(1.0f + e)
-                                  : e * (1.0f - e * (0.5f - e * 0.33333333f));
-    return fmaxf(s, 0.f) + l;
+    const float big = 0.69314718055994531f * __builtin_amdgcn_logf(1.0f + e);
+    const float small = e * (1.0f - e * (0.5f - e * 0.33333333f));
+    return fmaxf(s, 0.f) + (e >= 0x1p-10f ? big : small);
 }
 
-// stored column of dim d and its inverse
-__device__ __forceinline__ int lr_col(int d) { return (d & 3) * 8 + (d >> 2); }
-__device__ __forceinline__ int lr_dim(int k) { return (k & 7) * 4 + (k >> 3); }
-
-struct ChainCtlL {
+struct ChainSt {       // per-chain scalars of the owners, kept in LDS
     double logp, eps;
     DualAvg da;
+};
+
+// Output pointers, kept in LDS: read where a transition ends instead of
+// occupying registers through the leapfrog steps.
+struct OutPtrs {
+    float* samples;
+    hmc_trace trace;
+    hmc_step_out out;
 };
 
 template <int TPW, int QQ, typename XT>
 __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) {
     extern __shared__ float lds[];
-    constexpr int NW = LR_NW;
-    const int64_t D = a.tg.D, N = a.tg.N, C = a.C;
+    constexpr int NW = LR_NW, PS = LR_PS, ZT = LR_ZT, UT = LR_UT;
+    const int64_t D = a.tg.D, N = a.tg.N, C = a.C, T = r.n_transitions;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int q4 = lane & 3, b16 = lane >> 2;
     const int64_t c0 = (int64_t)blockIdx.x * 4;
     const float inv_var = (float)a.tg.inv_var;
 
-    float* th = lds;                         // [4][32] theta of the 4 chains (dim order)
-    float* part = th + 128;                  // [NW][4 rows][4 j][32]: row partials, (q, i) inner
-    double* lpp = (double*)(part + NW * LR_PART);   // [NW][4]
+    float* th = lds;                                    // [4][32] theta of the 4 chains (dim order)
+    float* part = th + 128;                             // [NW][4][PS] wave partials of G
+    float* zb = part + NW * 4 * PS;                     // [ZT][4][32] momenta
+    double* lpp = (double*)(zb + ZT * 128);             // [NW][4] wave partials of the data log-likelihood
+    double* lub = lpp + NW * 4;                         // [2][UT][4] log accept uniforms, two blocks
+    double* dac = lub + 2 * UT * 4;                     // [2][UT][4] dual-averaging factors (w, k, eta)
+    ChainSt* cst = (ChainSt*)(dac + 2 * UT * 4);        // [4]
+    OutPtrs* optr = (OutPtrs*)(cst + 4);
 
     // ---- X and y of this wave's tiles, in the two operand layouts, kept in VGPRs ----
     const XT* X = (const XT*)a.tg.X;
@@ -95,8 +173,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     };
     float xa[TPW][4 * QQ];     // first contraction: X[row0 + lane][d]
     float xb[TPW][4][QQ];      // second contraction: X[row0 + 4 b16 + v][4 q + q4]
-    float yv[TPW][4];
-    bool rv[TPW][4];
+    uint32_t ybits = 0, rbits = 0;   // bit 4 tt + v: label of row 4 b16 + v of tile tt is 1 / row exists
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
         const int64_t row0 = (int64_t)(w + NW * tt) * 64;
@@ -105,11 +182,48 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t row = row0 + 4 * b16 + v;
-            rv[tt][v] = row < N;
-            yv[tt][v] = row < N ? (float)a.tg.y[row] : 0.f;
+            if (row < N) {
+                rbits |= 1u << (4 * tt + v);
+                if (a.tg.y[row]) ybits |= 1u << (4 * tt + v);
+            }
 #pragma unroll
             for (int q = 0; q < QQ; ++q) xb[tt][v][q] = ldx(row, 4 * q + q4);
         }
+    }
+
+    // ---- draws, by waves 2..7 ----
+    auto draw_momenta = [&](int64_t i0) {               // transitions i0 .. i0 + ZT - 1
+        const int nb = (int)((D + 3) / 4);
+        for (int task = (int)threadIdx.x - 128; task < ZT * 32; task += 384) {
+            const int k = task >> 5, ci = (task >> 3) & 3, blk = task & 7;
+            float z[4] = {0.f, 0.f, 0.f, 0.f};
+            if (i0 + k < T && c0 + ci < C && blk < nb)
+                momentum4<float>(a.key, (uint32_t)(c0 + ci), (uint32_t)(r.t_begin + i0 + k), (uint32_t)blk, z);
+            *(float4*)&zb[(k * 4 + ci) * 32 + 4 * blk] = make_float4(z[0], z[1], z[2], z[3]);
+        }
+    };
+    auto draw_accept = [&](int64_t i0) {                // transitions i0 .. i0 + UT - 1, block (i0 / UT) % 2
+        const int hb = (int)((i0 / UT) & 1);
+        for (int task = (int)threadIdx.x - 128; task < UT * 4; task += 384) {
+            const int k = task >> 2, ci = task & 3;
+            double lu = 0.0;
+            if (i0 + k < T && c0 + ci < C)
+                lu = log_accept_uniform(a.key, (uint32_t)(c0 + ci), (uint32_t)(r.t_begin + i0 + k));
+            lub[(hb * UT + k) * 4 + ci] = lu;
+        }
+        if (r.adapt)
+            for (int k = (int)threadIdx.x - 128; k < UT; k += 384)
+                if (i0 + k < T) {
+                    const DaConst f = dual_avg_const((double)(r.m_offset + i0 + k + 1), r.gamma, r.t0, r.kappa);
+                    double* o = dac + (hb * UT + k) * 4;
+                    o[0] = f.w;
+                    o[1] = f.k;
+                    o[2] = f.eta;
+                }
+    };
+    if (threadIdx.x >= 128 && T > 0) {
+        draw_momenta(0);
+        draw_accept(0);
     }
 
     // ---- owners: thread t < 128 holds (chain oi, dim od) ----
@@ -122,183 +236,193 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     float* Gw = (float*)a.ws.g;
     float th0 = ovalid ? Xw[occ * D + od] : 0.f;
     float g0 = ovalid ? Gw[occ * D + od] : 0.f;
-    ChainCtlL s;
-    s.logp = a.ws.logp[occ];
-    s.eps = a.ws.eps[occ];
-    s.da = a.ws.da[occ];
+    // step size of the owner's chain in FP32; half steps are eps / 2 (halving
+    // commutes with rounding to float)
+    float eps = owner ? (float)a.ws.eps[occ] : 0.f;
+    if (owner && od == 0 && oc < C) cst[oi] = ChainSt{a.ws.logp[oc], a.ws.eps[oc], a.ws.da[oc]};
+    if (threadIdx.x == 0) *optr = OutPtrs{(float*)r.samples, r.trace, r.out};
+    float p = 0.f, thq = th0, gq = 0.f;
+    __syncthreads();
 
-    for (int64_t itr = 0; itr < r.n_transitions; ++itr) {
-        const uint32_t t = (uint32_t)(r.t_begin + itr);
-        const float eps = (float)s.eps, half = (float)(0.5 * s.eps);
-        float p = 0.f, thq = th0, gq = 0.f;
-        double dk = 0.0, lpdata = 0.0;
+    auto step = [&](auto last_c) {
+        constexpr bool LAST = decltype(last_c)::value;
         if (owner) {
-            float z[4];
-            momentum4<float>(a.key, (uint32_t)occ, t, (uint32_t)(od >> 2), z);
-            const int jj = od & 3;
-            const float zj = jj == 0 ? z[0] : (jj == 1 ? z[1] : (jj == 2 ? z[2] : z[3]));
-            const float p0 = ovalid ? zj : 0.f;
-            dk = -0.5 * (double)p0 * (double)p0;
-            p = fmaf(half, g0, p0);
+            thq = fmaf(eps, p, thq);
+            th[oi * 32 + od] = ovalid ? thq : 0.f;
         }
-        for (int l = 0; l < a.L; ++l) {
-            const bool last = l == a.L - 1;
-            if (owner) {
-                thq = fmaf(eps, p, thq);
-                th[oi * 32 + od] = ovalid ? thq : 0.f;
+        __syncthreads();
+        // B operands of the first contraction: lane 16 g + 4 b + j of tb[k] holds
+        // theta[chain j][4 k + g]; the MFMA for dim 4 k + g broadcasts lane group g
+        // to all four groups (BLGP = 4 + g)
+        float tb[QQ];
+#pragma unroll
+        for (int k = 0; k < QQ; ++k) tb[k] = th[q4 * 32 + 4 * k + (lane >> 4)];
+        // S = X theta (two accumulation chains per tile); tile tt + 1's S, tile tt's
+        // residuals and tile tt's G contribution form one scheduling region, so MFMA
+        // and VALU work of neighbouring tiles interleave
+        const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+        floatx4 sa[TPW][2];
+        float sv[TPW][4], rr[TPW][4];
+        floatx4 gacc[QQ];
+        double lp = 0.0;
+#pragma unroll
+        for (int d = 0; d < 4 * QQ; d += 4)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                sa[0][u & 1] = mfma4_bgroup(u, xa[0][d + u], tb[d / 4], (d == 0 && u < 2) ? zero : sa[0][u & 1]);
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+            __builtin_amdgcn_sched_barrier(0);
+            if (tt + 1 < TPW) {
+#pragma unroll
+                for (int d = 0; d < 4 * QQ; d += 4)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        sa[tt + 1][u & 1] = mfma4_bgroup(u, xa[tt + 1][d + u], tb[d / 4],
+                                                         (d == 0 && u < 2) ? zero : sa[tt + 1][u & 1]);
             }
-            __syncthreads();
-            float tb[4 * QQ];
+            // residuals y - sigmoid(S); padded rows have X = 0 and add nothing to G
 #pragma unroll
-            for (int k = 0; k < 4 * QQ; k += 4) {
-                const float4 v = *(const float4*)&th[q4 * 32 + k];
-                tb[k] = v.x;
-                tb[k + 1] = v.y;
-                tb[k + 2] = v.z;
-                tb[k + 3] = v.w;
-            }
-            floatx4 gacc[QQ];
-#pragma unroll
-            for (int q = 0; q < QQ; ++q) gacc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-            double lp = 0.0;
-            // S = X theta for all tiles, four independent accumulation chains per tile
-            floatx4 sa[TPW][4];
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt)
-#pragma unroll
-                for (int u = 0; u < 4; ++u) sa[tt][u] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int d = 0; d < 4 * QQ; d += 4)
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int tt = 0; tt < TPW; ++tt)
-                        sa[tt][u] = __builtin_amdgcn_mfma_f32_4x4x1f32(xa[tt][d + u], tb[d + u], sa[tt][u], 0, 0, 0);
-#pragma unroll
-            for (int tt = 0; tt < TPW; ++tt) {
-                if ((w + NW * tt) * 64 >= N) break;
-                float rr[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float sv = (sa[tt][0][v] + sa[tt][1][v]) + (sa[tt][2][v] + sa[tt][3][v]);
-                    rr[v] = yv[tt][v] - sigmoid_fast(sv);
-                    if (last && rv[tt][v]) lp -= (double)softplus_f(yv[tt][v] > 0.5f ? -sv : sv);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int q = 0; q < QQ; ++q)
-                        gacc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(rr[v], xb[tt][v][q], gacc[q], 0, 0, 0);
-            }
-            // sum the 4 blocks of each 16-lane row (lanes of equal j), write row partials
-#pragma unroll
-            for (int q = 0; q < QQ; ++q)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    float v = gacc[q][i];
-                    v += dpp_ror(v, 4);
-                    v += dpp_ror(v, 8);
-                    gacc[q][i] = v;
-                }
-            if ((lane & 15) < 4) {
-                float* dst = part + w * LR_PART + ((lane >> 4) * 4 + q4) * 32;
-#pragma unroll
-                for (int q = 0; q < QQ; ++q) *(floatx4*)(dst + 4 * q) = gacc[q];
-            }
-            if (last) {
-                lp += __shfl_xor(lp, 4, 64);
-                lp += __shfl_xor(lp, 8, 64);
-                lp += __shfl_xor(lp, 16, 64);
-                lp += __shfl_xor(lp, 32, 64);
-                if (lane < 4) lpp[w * 4 + lane] = lp;
-            }
-            __syncthreads();
-            if (owner) {
-                float gs = 0.f;
-                if (od < 4 * QQ) {
-                    // fixed-order pairwise tree over the NW x 4 row partials
-                    const int q = od >> 2, j = od & 3;
-                    float v[NW * 4];
-#pragma unroll
-                    for (int ww = 0; ww < NW; ++ww)
-#pragma unroll
-                        for (int rrow = 0; rrow < 4; ++rrow)
-                            v[ww * 4 + rrow] = part[ww * LR_PART + (rrow * 4 + j) * 32 + 4 * q + oi];
-#pragma unroll
-                    for (int h = NW * 2; h >= 1; h >>= 1)
-#pragma unroll
-                        for (int k = 0; k < h; ++k) v[k] = v[2 * k] + v[2 * k + 1];
-                    gs = v[0];
-                }
-                gq = gs - thq * inv_var;
-                p = fmaf(last ? half : eps, gq, p);
-                if (last) {
-#pragma unroll
-                    for (int ww = 0; ww < NW; ++ww) lpdata += lpp[ww * 4 + oi];
+            for (int v = 0; v < 4; ++v) {
+                const int bit = 4 * tt + v;
+                sv[tt][v] = sa[tt][0][v] + sa[tt][1][v];
+                const float y = ((ybits >> bit) & 1u) ? 1.f : 0.f;
+                rr[tt][v] = y - sigmoid_fast(sv[tt][v]);
+                if constexpr (LAST) {
+                    const float sp = softplus_f(y > 0.5f ? -sv[tt][v] : sv[tt][v]);
+                    lp -= ((rbits >> bit) & 1u) ? (double)sp : 0.0;
                 }
             }
-        }
-        if (!owner) continue;
-        // energy change and decision (the 32 lanes of a chain agree)
-        double prior = ovalid ? -0.5 * (double)thq * (double)thq * a.tg.inv_var : 0.0;
-        dk += ovalid ? 0.5 * (double)p * (double)p : 0.0;
 #pragma unroll
-        for (int off = 1; off < 32; off <<= 1) {
-            dk += __shfl_xor(dk, off, 64);
-            prior += __shfl_xor(prior, off, 64);
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int q = 0; q < QQ; ++q)
+                    gacc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(rr[tt][v], xb[tt][v][q],
+                                                                 (tt == 0 && v == 0) ? zero : gacc[q], 0, 0, 0);
         }
-        const double lp1 = lpdata + prior;
-        const double dh = -lp1 + s.logp + dk;
-        const double lar = log_accept_ratio_of(dh);
-        const bool acc = log_accept_uniform(a.key, (uint32_t)occ, t) < lar;
-        if (acc) {
-            th0 = thq;
-            g0 = gq;
-            s.logp = lp1;
+        __builtin_amdgcn_sched_barrier(0);
+        // block sums: chain i to row i, then the 4 blocks of each row (dims 4q + lane % 4)
+        float gsum[QQ];
+#pragma unroll
+        for (int q = 0; q < QQ; ++q) {
+            float v = rows4_scatter(gacc[q][0], gacc[q][1], gacc[q][2], gacc[q][3]);
+            v += dpp_ror(v, 4);
+            v += dpp_ror(v, 8);
+            gsum[q] = v;
         }
-        if (oc < C) {
-            if (ovalid) {
-                if (r.samples && itr >= r.n_burnin) ((float*)r.samples)[((itr - r.n_burnin) * C + oc) * D + od] = th0;
-                if (r.out.proposed_state) ((float*)r.out.proposed_state)[oc * D + od] = thq;
-                if (r.out.proposed_momentum) ((float*)r.out.proposed_momentum)[oc * D + od] = p;
+        if ((lane & 15) < 4) {
+            float* dst = part + (w * 4 + (lane >> 4)) * PS + q4;
+#pragma unroll
+            for (int q = 0; q < QQ; ++q) dst[4 * q] = gsum[q];
+        }
+        if constexpr (LAST) {
+            lp = same_j_sum(lp);
+            if (lane < 4) lpp[w * 4 + lane] = lp;
+        }
+        __syncthreads();
+        if (owner) {
+            float gs = 0.f;
+            if (od < 4 * QQ) {
+                // fixed-order pairwise sum over the wave partials
+                float v[NW];
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) v[ww] = part[(ww * 4 + oi) * PS + od];
+#pragma unroll
+                for (int hh = NW / 2; hh >= 1; hh >>= 1)
+#pragma unroll
+                    for (int k = 0; k < hh; ++k) v[k] = v[2 * k] + v[2 * k + 1];
+                gs = v[0];
             }
-            // dual averaging, traces and step outputs (lane od == 0 writes)
-            const double eps_used = s.eps;
-            if (r.adapt && itr < r.n_burnin) {
-                const double alpha = lar < 0.0 ? exp(lar) : 1.0;
-                const int64_t m = r.m_offset + itr + 1;
-                const double log_eps = dual_avg_update(s.da, (double)m, alpha, r.target_accept, r.gamma, r.t0,
-                                                       r.kappa);
-                s.eps = (m < r.adapt_total) ? exp(log_eps) : exp(s.da.log_eps_bar);
+            gq = gs - thq * inv_var;
+            p = fmaf(LAST ? 0.5f * eps : eps, gq, p);
+        }
+    };
+
+    for (int64_t itr = 0; itr < T; ++itr) {
+        double dk = 0.0;
+        if (owner) {
+            const float z = ovalid ? zb[((int)(itr % ZT) * 4 + oi) * 32 + od] : 0.f;
+            dk = -0.5 * (double)z * (double)z;
+            thq = th0;
+            p = fmaf(0.5f * eps, g0, z);
+        }
+        for (int l = 0; l + 1 < a.L; ++l) step(std::false_type{});
+        step(std::true_type{});
+
+        const bool refill_z = itr + 1 < T && (itr + 1) % ZT == 0;
+        if (owner) {
+            // energy change and decision (the 32 lanes of a chain agree bitwise)
+            const int hb = (int)((itr / UT) & 1), ku = (int)(itr % UT);
+            ChainSt cs = cst[oi];
+            double prior = ovalid ? -0.5 * (double)thq * (double)thq * a.tg.inv_var : 0.0;
+            dk += ovalid ? 0.5 * (double)p * (double)p : 0.0;
+            dk = half_wave_sum(dk);
+            prior = half_wave_sum(prior);
+            double lpdata = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) lpdata += lpp[ww * 4 + oi];
+            const double lp1 = lpdata + prior;
+            const double dh = -lp1 + cs.logp + dk;
+            const double lar = log_accept_ratio_of(dh);
+            const bool acc = lub[(hb * UT + ku) * 4 + oi] < lar;
+            if (acc) {
+                th0 = thq;
+                g0 = gq;
+                cs.logp = lp1;
             }
-            if (od == 0) {
-                if (itr >= r.n_burnin) {
-                    const int64_t k = (itr - r.n_burnin) * C + oc;
-                    if (r.trace.step_size) r.trace.step_size[k] = eps_used;
-                    if (r.trace.is_accepted) r.trace.is_accepted[k] = acc ? 1 : 0;
-                    if (r.trace.log_accept_ratio) r.trace.log_accept_ratio[k] = lar;
-                    if (r.trace.target_log_prob) r.trace.target_log_prob[k] = s.logp;
+            if (oc < C) {
+                const OutPtrs o = *optr;
+                if (ovalid) {
+                    if (o.samples && itr >= r.n_burnin) o.samples[((itr - r.n_burnin) * C + oc) * D + od] = th0;
+                    if (o.out.proposed_state) ((float*)o.out.proposed_state)[oc * D + od] = thq;
+                    if (o.out.proposed_momentum) ((float*)o.out.proposed_momentum)[oc * D + od] = p;
                 }
-                if (r.out.is_accepted) r.out.is_accepted[oc] = acc ? 1 : 0;
-                if (r.out.log_accept_ratio) r.out.log_accept_ratio[oc] = lar;
-                if (r.out.target_log_prob) r.out.target_log_prob[oc] = s.logp;
-                if (r.out.delta_h) r.out.delta_h[oc] = dh;
+                const double eps_used = cs.eps;
+                if (r.adapt && itr < r.n_burnin) {
+                    const double alpha = lar < 0.0 ? exp(lar) : 1.0;
+                    const int64_t m = r.m_offset + itr + 1;
+                    const double* f = dac + (hb * UT + ku) * 4;
+                    const double log_eps = dual_avg_apply(cs.da, DaConst{f[0], f[1], f[2]}, alpha, r.target_accept);
+                    cs.eps = (m < r.adapt_total) ? exp(log_eps) : exp(cs.da.log_eps_bar);
+                }
+                eps = (float)cs.eps;
+                if (od == 0) {
+                    if (itr >= r.n_burnin) {
+                        const int64_t k = (itr - r.n_burnin) * C + oc;
+                        if (o.trace.step_size) o.trace.step_size[k] = eps_used;
+                        if (o.trace.is_accepted) o.trace.is_accepted[k] = acc ? 1 : 0;
+                        if (o.trace.log_accept_ratio) o.trace.log_accept_ratio[k] = lar;
+                        if (o.trace.target_log_prob) o.trace.target_log_prob[k] = cs.logp;
+                    }
+                    if (o.out.is_accepted) o.out.is_accepted[oc] = acc ? 1 : 0;
+                    if (o.out.log_accept_ratio) o.out.log_accept_ratio[oc] = lar;
+                    if (o.out.target_log_prob) o.out.target_log_prob[oc] = cs.logp;
+                    if (o.out.delta_h) o.out.delta_h[oc] = dh;
+                    cst[oi] = cs;
+                }
             }
+        } else if (itr + 1 < T) {
+            if (refill_z) draw_momenta(itr + 1);
+            if ((itr + 1) % UT == 0) draw_accept(itr + 1);
         }
+        // the owners read the next momenta before the next barrier of a step
+        if (refill_z) __syncthreads();
     }
     if (ovalid) {
         Xw[oc * D + od] = th0;
         Gw[oc * D + od] = g0;
     }
     if (owner && od == 0 && oc < C) {
-        a.ws.logp[oc] = s.logp;
-        a.ws.eps[oc] = s.eps;
-        a.ws.da[oc] = s.da;
+        const ChainSt cs = cst[oi];
+        a.ws.logp[oc] = cs.logp;
+        a.ws.eps[oc] = cs.eps;
+        a.ws.da[oc] = cs.da;
     }
 }
 
 static size_t logreg4_lds(int) {
-    return (size_t)(128 + LR_NW * LR_PART) * sizeof(float) + LR_NW * 4 * sizeof(double);
+    return (size_t)(128 + LR_NW * 4 * LR_PS + LR_ZT * 128) * sizeof(float) +
+           (size_t)(LR_NW * 4 + 4 * LR_UT * 4) * sizeof(double) + 4 * sizeof(ChainSt) + sizeof(OutPtrs);
 }
 
 bool fused_logreg_supported(const PlainArgs& a) {

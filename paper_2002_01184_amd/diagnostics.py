@@ -106,3 +106,80 @@ def summarize(samples: np.ndarray, max_dims: int | None = None) -> dict:
     r = [rhat(samples[:, :, d]) for d in dims]
     return dict(min_ess_bulk=float(np.min(e)), max_rhat=float(np.max(r)),
                 ess_bulk=np.array(e), rhat=np.array(r))
+
+
+# ---------------------------------------------------------------------------
+# The same estimators over torch tensors (any device), for long runs whose
+# samples stay on the GPU.  Identical arithmetic to the numpy versions above.
+# ---------------------------------------------------------------------------
+def _t_rank_normalize(x):
+    import torch
+    flat = x.reshape(-1)
+    S = flat.numel()
+    order = torch.argsort(flat, stable=True)
+    sorted_vals = flat[order]
+    ranks = torch.empty(S, dtype=torch.float64, device=x.device)
+    ranks[order] = torch.arange(1, S + 1, dtype=torch.float64, device=x.device)
+    # average ranks of ties
+    uniq, inv, counts = torch.unique_consecutive(sorted_vals, return_inverse=True, return_counts=True)
+    if uniq.numel() < S:
+        first = torch.cumsum(counts, 0) - counts + 1
+        avg = first.double() + (counts.double() - 1) / 2
+        ranks[order] = avg[inv]
+    z = torch.special.ndtri((ranks - 0.375) / (S + 0.25))
+    return z.reshape(x.shape)
+
+
+def _t_split(x):
+    import torch
+    n = x.shape[0] // 2
+    return torch.cat([x[:n], x[x.shape[0] - n:]], dim=1)
+
+
+def _t_rhat_basic(x):
+    n = x.shape[0]
+    W = x.var(0, unbiased=True).mean()
+    B = n * x.mean(0).var(unbiased=True)
+    return float(((n - 1) / n * W + B / n).div(W).sqrt())
+
+
+def t_rhat(x):
+    import torch
+    xs = _t_split(x.double())
+    bulk = _t_rhat_basic(_t_rank_normalize(xs))
+    folded = (xs - xs.median()).abs()
+    return max(bulk, _t_rhat_basic(_t_rank_normalize(folded)))
+
+
+def t_ess(x):
+    import torch
+    x = x.double()
+    n, M = x.shape
+    xc = x - x.mean(0)
+    nfft = 1 << int(np.ceil(np.log2(2 * n)))
+    f = torch.fft.rfft(xc, n=nfft, dim=0)
+    acov = torch.fft.irfft(f * f.conj(), n=nfft, dim=0)[:n] / n
+    chain_var = acov[0] * n / (n - 1.0)
+    W = chain_var.mean()
+    var_plus = W * (n - 1.0) / n + (x.mean(0).var(unbiased=True) if M > 1 else 0.0)
+    rho = 1.0 - (W - acov.mean(1)) / var_plus
+    rho = rho.cpu().numpy()
+    rho[0] = 1.0
+    npairs = n // 2
+    P = rho[0:2 * npairs:2] + rho[1:2 * npairs:2]
+    k = 0
+    while k < npairs and P[k] > 0:
+        k += 1
+    P = np.minimum.accumulate(P[:k]) if k > 0 else P[:0]
+    tau = max(-1.0 + 2.0 * P.sum(), 1.0 / np.log10(n * M))
+    return float(n * M / tau)
+
+
+def t_summarize(samples) -> dict:
+    """samples: torch tensor [R, C, D] (any device) -> min bulk-ESS, max R-hat."""
+    e, r = [], []
+    for d in range(samples.shape[2]):
+        x = samples[:, :, d]
+        e.append(t_ess(_t_rank_normalize(_t_split(x.double()))))
+        r.append(t_rhat(x))
+    return dict(min_ess_bulk=float(np.min(e)), max_rhat=float(np.max(r)), ess_bulk=np.array(e), rhat=np.array(r))

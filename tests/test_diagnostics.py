@@ -55,3 +55,14 @@ def test_summarize_shapes():
     out = dg.summarize(s)
     assert out["ess_bulk"].shape == (2,) and out["max_rhat"] < 1.05
     assert out["ess_bulk"][0] == pytest.approx(out["ess_bulk"][1])   # rank-based: scale-free
+
+
+def test_torch_estimators_equal_numpy():
+    import torch
+    x = _ar1(600, 12, 0.6, seed=9)
+    x[:, :3] += 0.2
+    s = np.stack([x, x ** 2, np.round(x, 1)], axis=-1)          # includes ties
+    a = dg.summarize(s)
+    b = dg.t_summarize(torch.from_numpy(s))
+    assert np.allclose(a["ess_bulk"], b["ess_bulk"], rtol=1e-9)
+    assert np.allclose(a["rhat"], b["rhat"], rtol=1e-12)
