@@ -28,6 +28,32 @@ sys.path.insert(0, ROOT)
 METRIC = "leapfrog chain-steps/sec and ESS/sec at R-hat≤1.01; p50/p99 request latency"
 PEAK = {"fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12}
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs (profiles/hbm_traffic_counters.md), scaled by what the same
+# counters read for a 1 GiB copy: read = 2 x FETCH_SIZE, write = WRITE_SIZE.
+# A figure is reported only while the kernel's sources still hash to the value
+# recorded with it; otherwise traffic is null until the counters are taken again.
+MEASURED_TRAFFIC = {
+    # (workload, form, gradient dtype, burn-in, results)
+    ("logreg_1000x25", "fused", "f32", 1000, 1000): {
+        "sources": ["k_fused_logreg.hip", "hmc_device.hpp", "hmc_internal.hpp"],
+        "sha256_16": "1a27643a618f20a9", "read": 11271808, "write": 152447488},
+}
+
+
+def measured_traffic(w, form, grad):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get((w.name, form, grad, w.num_burnin, w.num_results))
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for fn in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_2002_01184_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != rec["sha256_16"]:
+        return None
+    return rec["read"] + rec["write"]
+
 
 def algorithmic_work(w):
     """(kind, per chain-step amount, unit) of the dominant contraction / traffic."""
@@ -244,6 +270,9 @@ def main():
         achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
                 "frac": achieved / PEAK["hbm"], "traffic": None}
+    tb = measured_traffic(w, s.form, args.grad)
+    roof["traffic"] = None if tb is None else tb / 1e9        # GB per launch
+    roof["traffic_unit"] = "GB per launch"
     roof["kernel"] = {hmc.HMC_FORM_FUSED: "fused transition kernel", hmc.HMC_FORM_PLAIN: "plain kernels",
                       hmc.HMC_FORM_GRAPH: "plain kernels (graph)"}.get(hmc.hmc_effective_form(s.ctx))
     roof["kernel_ms_per_launch"] = kernel_ms

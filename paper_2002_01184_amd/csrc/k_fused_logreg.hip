@@ -116,20 +116,23 @@ __device__ __forceinline__ double same_j_sum(double v) {
     return rows2_sum(v);
 }
 
-// 1 / (1 + e^-s) with the hardware exp2 and reciprocal (about 1 ulp each);
-// e^-s overflowing to +inf gives the correct limit 0.
-__device__ __forceinline__ float sigmoid_fast(float s) {
-    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * s);
-    return __builtin_amdgcn_rcpf(1.0f + e);
-}
-
-// log(1 + e^s) = max(s, 0) + log1p(e^-|s|); log1p(e) for e in (0, 1] from the
-// hardware log2 when e >= 2^-10, else its series e - e^2/2 + e^3/3 (error < e^4/4).
-__device__ __forceinline__ float softplus_f(float s) {
+// The logistic link of one row from e = e^-|s| (hardware exp2, about 1 ulp):
+// sigmoid(s) = 1 / (1 + e) for s >= 0 and e / (1 + e) below, and
+// log1p(e), from which softplus(+-s) = max(+-s, 0) + log1p(e).  log1p(e) for
+// e in (0, 1] is the hardware log2 of 1 + e when e >= 2^-10, else the series
+// e - e^2/2 + e^3/3 (error < e^4/4).
+struct Link {
+    float e, rc;     // e^-|s|, 1 / (1 + e^-|s|)
+};
+__device__ __forceinline__ Link link_of(float s) {
     const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * fabsf(s));
-    const float big = 0.69314718055994531f * __builtin_amdgcn_logf(1.0f + e);
-    const float small = e * (1.0f - e * (0.5f - e * 0.33333333f));
-    return fmaxf(s, 0.f) + (e >= 0x1p-10f ? big : small);
+    return Link{e, __builtin_amdgcn_rcpf(1.0f + e)};
+}
+__device__ __forceinline__ float sigmoid_of(float s, Link k) { return s >= 0.f ? k.rc : k.e * k.rc; }
+__device__ __forceinline__ float log1p_of(Link k) {
+    const float big = 0.69314718055994531f * __builtin_amdgcn_logf(1.0f + k.e);
+    const float small = k.e * (1.0f - k.e * (0.5f - k.e * 0.33333333f));
+    return k.e >= 0x1p-10f ? big : small;
 }
 
 struct ChainSt {       // per-chain scalars of the owners, kept in LDS
@@ -138,12 +141,44 @@ struct ChainSt {       // per-chain scalars of the owners, kept in LDS
 };
 
 // Output pointers, kept in LDS: read where a transition ends instead of
-// occupying registers through the leapfrog steps.
+// occupying registers through the leapfrog steps.  They are global-memory
+// pointers, so stores through them are global stores, not flat ones.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
 struct OutPtrs {
-    float* samples;
-    hmc_trace trace;
-    hmc_step_out out;
+    gptr<float> samples;
+    gptr<double> tr_step;
+    gptr<uint8_t> tr_acc;
+    gptr<double> tr_lar;
+    gptr<double> tr_tlp;
+    gptr<float> ps;
+    gptr<float> pm;
+    gptr<uint8_t> acc;
+    gptr<double> lar;
+    gptr<double> tlp;
+    gptr<double> dh;
 };
+
+// e^x in FP64 with its polynomial coefficients read from LDS (a table the
+// loop cannot keep in registers): x = k ln2 + r with a two-part ln2 and
+// |r| <= ln2 / 2, e^r from its Taylor series through r^13 (the remainder is
+// below 2^-56 e^r), times 2^k.  x below -745.2 gives 0, +inf gives +inf.
+constexpr int EXP_NC = 14;
+__host__ __device__ constexpr double exp_coef(int n) {   // 1 / n!
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= (double)i;
+    return 1.0 / f;
+}
+__device__ __forceinline__ double exp_lds(double x, const double* cf) {
+    if (!(x > -745.2)) return x != x ? x : 0.0;
+    if (x > 709.8) return INFINITY;
+    const double k = rint(x * 1.4426950408889634);
+    const double r = fma(-k, 1.9082149292705877e-10, fma(-k, 0.6931471803691238, x));
+    double s = cf[EXP_NC - 1];
+#pragma unroll
+    for (int n = EXP_NC - 2; n >= 0; --n) s = fma(s, r, cf[n]);
+    return ldexp(s, (int)k);
+}
 
 template <int TPW, int QQ, typename XT>
 __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) {
@@ -163,6 +198,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     double* dac = lub + 2 * UT * 4;                     // [2][UT][4] dual-averaging factors (w, k, eta)
     ChainSt* cst = (ChainSt*)(dac + 2 * UT * 4);        // [4]
     OutPtrs* optr = (OutPtrs*)(cst + 4);
+    double* ecf = (double*)(optr + 1);                  // [EXP_NC] 1 / n!
 
     // ---- X and y of this wave's tiles, in the two operand layouts, kept in VGPRs ----
     const XT* X = (const XT*)a.tg.X;
@@ -240,7 +276,14 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     // commutes with rounding to float)
     float eps = owner ? (float)a.ws.eps[occ] : 0.f;
     if (owner && od == 0 && oc < C) cst[oi] = ChainSt{a.ws.logp[oc], a.ws.eps[oc], a.ws.da[oc]};
-    if (threadIdx.x == 0) *optr = OutPtrs{(float*)r.samples, r.trace, r.out};
+    if (threadIdx.x == 0)
+        *optr = OutPtrs{(gptr<float>)r.samples,          (gptr<double>)r.trace.step_size,
+                        (gptr<uint8_t>)r.trace.is_accepted, (gptr<double>)r.trace.log_accept_ratio,
+                        (gptr<double>)r.trace.target_log_prob, (gptr<float>)r.out.proposed_state,
+                        (gptr<float>)r.out.proposed_momentum, (gptr<uint8_t>)r.out.is_accepted,
+                        (gptr<double>)r.out.log_accept_ratio, (gptr<double>)r.out.target_log_prob,
+                        (gptr<double>)r.out.delta_h};
+    if (threadIdx.x < EXP_NC) ecf[threadIdx.x] = exp_coef((int)threadIdx.x);
     float p = 0.f, thq = th0, gq = 0.f;
     __syncthreads();
 
@@ -264,7 +307,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
         floatx4 sa[TPW][2];
         float sv[TPW][4], rr[TPW][4];
         floatx4 gacc[QQ];
-        double lp = 0.0;
+        float ll[TPW][4];        // log-likelihood terms of the rows (last step)
 #pragma unroll
         for (int d = 0; d < 4 * QQ; d += 4)
 #pragma unroll
@@ -286,11 +329,13 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
             for (int v = 0; v < 4; ++v) {
                 const int bit = 4 * tt + v;
                 sv[tt][v] = sa[tt][0][v] + sa[tt][1][v];
-                const float y = ((ybits >> bit) & 1u) ? 1.f : 0.f;
-                rr[tt][v] = y - sigmoid_fast(sv[tt][v]);
+                const bool yb = (ybits >> bit) & 1u;
+                const Link k = link_of(sv[tt][v]);
+                rr[tt][v] = (yb ? 1.f : 0.f) - sigmoid_of(sv[tt][v], k);
                 if constexpr (LAST) {
-                    const float sp = softplus_f(y > 0.5f ? -sv[tt][v] : sv[tt][v]);
-                    lp -= ((rbits >> bit) & 1u) ? (double)sp : 0.0;
+                    // y log sigmoid(s) + (1 - y) log(1 - sigmoid(s)) = -softplus(y ? -s : s)
+                    const float sp = fmaxf(yb ? -sv[tt][v] : sv[tt][v], 0.f) + log1p_of(k);
+                    ll[tt][v] = ((rbits >> bit) & 1u) ? -sp : 0.f;
                 }
             }
 #pragma unroll
@@ -316,7 +361,15 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
             for (int q = 0; q < QQ; ++q) dst[4 * q] = gsum[q];
         }
         if constexpr (LAST) {
-            lp = same_j_sum(lp);
+            // FP64 pairwise sum of the lane's rows, then over the 16 lanes of each chain
+            double t[TPW * 4];
+#pragma unroll
+            for (int k = 0; k < TPW * 4; ++k) t[k] = (double)ll[k / 4][k % 4];
+#pragma unroll
+            for (int hh = TPW * 2; hh >= 1; hh >>= 1)
+#pragma unroll
+                for (int k = 0; k < hh; ++k) t[k] = t[2 * k] + t[2 * k + 1];
+            const double lp = same_j_sum(t[0]);
             if (lane < 4) lpp[w * 4 + lane] = lp;
         }
         __syncthreads();
@@ -374,30 +427,30 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
                 const OutPtrs o = *optr;
                 if (ovalid) {
                     if (o.samples && itr >= r.n_burnin) o.samples[((itr - r.n_burnin) * C + oc) * D + od] = th0;
-                    if (o.out.proposed_state) ((float*)o.out.proposed_state)[oc * D + od] = thq;
-                    if (o.out.proposed_momentum) ((float*)o.out.proposed_momentum)[oc * D + od] = p;
+                    if (o.ps) o.ps[oc * D + od] = thq;
+                    if (o.pm) o.pm[oc * D + od] = p;
                 }
                 const double eps_used = cs.eps;
                 if (r.adapt && itr < r.n_burnin) {
-                    const double alpha = lar < 0.0 ? exp(lar) : 1.0;
+                    const double alpha = lar < 0.0 ? exp_lds(lar, ecf) : 1.0;
                     const int64_t m = r.m_offset + itr + 1;
                     const double* f = dac + (hb * UT + ku) * 4;
                     const double log_eps = dual_avg_apply(cs.da, DaConst{f[0], f[1], f[2]}, alpha, r.target_accept);
-                    cs.eps = (m < r.adapt_total) ? exp(log_eps) : exp(cs.da.log_eps_bar);
+                    cs.eps = exp_lds((m < r.adapt_total) ? log_eps : cs.da.log_eps_bar, ecf);
                 }
                 eps = (float)cs.eps;
                 if (od == 0) {
                     if (itr >= r.n_burnin) {
                         const int64_t k = (itr - r.n_burnin) * C + oc;
-                        if (o.trace.step_size) o.trace.step_size[k] = eps_used;
-                        if (o.trace.is_accepted) o.trace.is_accepted[k] = acc ? 1 : 0;
-                        if (o.trace.log_accept_ratio) o.trace.log_accept_ratio[k] = lar;
-                        if (o.trace.target_log_prob) o.trace.target_log_prob[k] = cs.logp;
+                        if (o.tr_step) o.tr_step[k] = eps_used;
+                        if (o.tr_acc) o.tr_acc[k] = acc ? 1 : 0;
+                        if (o.tr_lar) o.tr_lar[k] = lar;
+                        if (o.tr_tlp) o.tr_tlp[k] = cs.logp;
                     }
-                    if (o.out.is_accepted) o.out.is_accepted[oc] = acc ? 1 : 0;
-                    if (o.out.log_accept_ratio) o.out.log_accept_ratio[oc] = lar;
-                    if (o.out.target_log_prob) o.out.target_log_prob[oc] = cs.logp;
-                    if (o.out.delta_h) o.out.delta_h[oc] = dh;
+                    if (o.acc) o.acc[oc] = acc ? 1 : 0;
+                    if (o.lar) o.lar[oc] = lar;
+                    if (o.tlp) o.tlp[oc] = cs.logp;
+                    if (o.dh) o.dh[oc] = dh;
                     cst[oi] = cs;
                 }
             }
@@ -422,7 +475,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
 
 static size_t logreg4_lds(int) {
     return (size_t)(128 + LR_NW * 4 * LR_PS + LR_ZT * 128) * sizeof(float) +
-           (size_t)(LR_NW * 4 + 4 * LR_UT * 4) * sizeof(double) + 4 * sizeof(ChainSt) + sizeof(OutPtrs);
+           (size_t)(LR_NW * 4 + 4 * LR_UT * 4 + EXP_NC) * sizeof(double) + 4 * sizeof(ChainSt) + sizeof(OutPtrs);
 }
 
 bool fused_logreg_supported(const PlainArgs& a) {
