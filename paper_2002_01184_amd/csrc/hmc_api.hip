@@ -540,7 +540,11 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
             c.tune.elem_gmult = 2;
             cands.push_back(c);
         } else if (f != HMC_FORM_FUSED && ctx->a.tg.kind == HMC_TGT_LOGREG && ctx->a.bf16_grad) {
-            for (int s : {1, 2, 4, 8}) {
+            const int d = lb_grad_nsplit(ctx->a.tg.N, ctx->a.C, ctx->a.tg.D);
+            for (int s : {d, 1, 2, 4, 8}) {
+                bool seen = false;
+                for (const TuneChoice& o : cands) seen |= o.form == f && o.tune.lr16_nsplit == s;
+                if (seen) continue;
                 c.tune.lr16_nsplit = s;
                 cands.push_back(c);
             }

@@ -52,7 +52,7 @@ hmc_status fail(hmc_status st, const std::string& msg);
 hmc_status validate_args(const hmc_target* tg, const hmc_config* cfg, TargetDev* out);
 int64_t logreg_nsplit(int64_t N, int64_t C);
 int64_t logreg_nsplit_cap(int64_t N, int64_t C);
-int lb_grad_nsplit(int64_t N, int64_t C);
+int lb_grad_nsplit(int64_t N, int64_t C, int64_t D);
 int lb_logp_nsplit(int64_t N, int64_t C);
 bool bf16_grad_supported(const TargetDev& tg);
 Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg, size_t* total);

@@ -10,12 +10,16 @@
 // the trajectory stays reversible and volume preserving; with dH taken from the
 // accurate log-probability the accept test keeps detailed balance.
 //
-// Work decomposition: a workgroup (4 waves) owns 128 chains (32 per wave) and a
-// chunk of rows; each wave computes S and G^T for its own 32 chains, so the R
-// values never leave registers (K index 8 g + e of the second contraction is
-// mapped to the rows the lane already holds: 4 g + e and 16 + 4 g + e - 4).
-// 32-row sub-tiles of X (row-major) and X^T (pre-transposed copy) are staged
-// in LDS, double buffered with a register prefetch, one barrier per sub-tile.
+// Work decomposition: a workgroup (4 waves) owns 4 CW chains (CW = 64 per wave,
+// four 16-chain tiles; 48 when D > 128, where 64 x D accumulators plus those of
+// S would exceed the 256 AGPRs) and a chunk of rows; each wave computes S and G^T for its own
+// chains, so the R values never leave registers (K index 8 g + e of the second
+// contraction is mapped to the rows the lane already holds: 4 g + e and
+// 16 + 4 g + e - 4).  theta stays in VGPRs as the B operands of the first
+// contraction, the G^T accumulators (CW chains x D) in AGPRs; every LDS operand
+// fragment feeds CW / 16 MFMAs.  32-row sub-tiles of X (row-major) and X^T
+// (pre-transposed copy) are staged in LDS, double buffered, with the global
+// loads of sub-tile s + 2 in flight while sub-tile s is multiplied.
 // Row chunks are mapped XCD-aware: blocks on the same XCD work on the same
 // chunk, so the 32 CUs of an XCD stream X through their shared L2 together.
 // Partials per chunk are summed in a fixed order by k_logreg_finish.
@@ -31,7 +35,6 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int LB_NW = 4;      // waves per workgroup
-constexpr int LB_CT = 128;    // chains per workgroup (32 per wave)
 constexpr int LB_RS = 32;     // rows per sub-tile
 constexpr int LB_XPAD = 8;    // bf16 padding of an LDS row of X
 constexpr int LB_TPAD = 8;    // bf16 padding of an LDS row of X^T
@@ -50,6 +53,13 @@ __device__ __forceinline__ float softplus_hw(float s) {
 
 __device__ __forceinline__ short bf16_bits(float f) { return (short)f32_to_bf16(f); }
 
+typedef float floatx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+// eight floats to BF16, round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ bf16x8 pack_bf16(floatx8 f) {
+    return __builtin_bit_cast(bf16x8, __builtin_convertvector(f, bf16x8v));
+}
+
 // block -> (chain tile, row chunk): blocks b and b + 8k run on the same XCD
 __device__ __forceinline__ void lb_map(int b, int ntile, int nsplit, int* tile, int* split) {
     if (nsplit <= 8 && (8 % nsplit) == 0 && ((ntile * nsplit) % 8) == 0) {
@@ -65,11 +75,16 @@ __device__ __forceinline__ void lb_map(int b, int ntile, int nsplit, int* tile, 
 // ---------------------------------------------------------------------------
 // Gradient partials.  KS = ceil(D / 32) k-steps, NT = 2 KS dim tiles.
 // ---------------------------------------------------------------------------
+// 16-chain tiles per wave for KS k-steps of 32 dims
+__host__ __device__ constexpr int lb_cs(int KS) { return KS > 4 ? 3 : 4; }
+
 template <int KS>
 __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __restrict__ xsrc,
                                                    const float* __restrict__ psrc, int drift, int64_t rows_per_split,
                                                    int nsplit, const uint16_t* __restrict__ Xt) {
-    constexpr int NT = 2 * KS;
+    constexpr int NT = 2 * KS;                  // 16-dim tiles of G
+    constexpr int CS = lb_cs(KS);               // 16-chain tiles per wave
+    constexpr int CW = 16 * CS, CT = LB_NW * CW;   // chains per wave / per workgroup
     constexpr int DP = 32 * KS;                 // padded dims
     constexpr int XS = DP + LB_XPAD;            // LDS row stride of X (bf16)
     constexpr int TS = LB_RS + LB_TPAD;         // LDS row stride of X^T (bf16)
@@ -79,33 +94,50 @@ __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __r
     float* ys = (float*)(xts + 2 * DP * TS);                // [2][32]
 
     const int64_t D = a.tg.D, N = a.tg.N, C = a.C;
-    const int ntile = (int)((C + LB_CT - 1) / LB_CT);
+    const int ntile = (int)((C + CT - 1) / CT);
     int tile, split;
     lb_map(blockIdx.x, ntile, nsplit, &tile, &split);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int l16 = lane & 15, g = lane >> 4;
-    const int64_t cw = (int64_t)tile * LB_CT + 32 * w;   // first chain of this wave
+    const int64_t cw = (int64_t)tile * CT + CW * w;     // first chain of this wave
     const uint16_t* X = (const uint16_t*)a.tg.X;
 
     // theta (drifted) as BF16 B operands: B[k][j] = theta[chain j][dim k]
-    bf16x8 thb[2][KS];
+    bf16x8 thb[CS][KS];
 #pragma unroll
-    for (int cs = 0; cs < 2; ++cs) {
+    for (int cs = 0; cs < CS; ++cs) {
         const int64_t c = cw + 16 * cs + l16;
         const bool cok = c < C;
         const float eps = cok ? (float)a.ws.eps[c] : 0.f;
+        const float* xr = xsrc + (cok ? c : 0) * D;
+        const float* pr = psrc + (cok ? c : 0) * D;
+        const bool vec = (D % 4) == 0;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
+            const int d0 = 32 * ks + 8 * g;
+            floatx8 v;
+            if (vec && cok && d0 + 8 <= D) {
+                const float4 x0 = *(const float4*)(xr + d0), x1 = *(const float4*)(xr + d0 + 4);
+                v = floatx8{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+                if (drift) {
+                    const float4 p0 = *(const float4*)(pr + d0), p1 = *(const float4*)(pr + d0 + 4);
+                    const floatx8 pv = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int64_t d = 32 * ks + 8 * g + e;
-                float v = 0.f;
-                if (cok && d < D) {
-                    v = xsrc[c * D + d];
-                    if (drift) v = fmaf(eps, psrc[c * D + d], v);
+                    for (int e = 0; e < 8; ++e) v[e] = fmaf(eps, pv[e], v[e]);
                 }
-                thb[cs][ks][e] = bf16_bits(v);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int d = d0 + e;
+                    float t = 0.f;
+                    if (cok && d < D) {
+                        t = xr[d];
+                        if (drift) t = fmaf(eps, pr[d], t);
+                    }
+                    v[e] = t;
+                }
             }
+            thb[cs][ks] = pack_bf16(v);
         }
     }
 
@@ -118,9 +150,9 @@ __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __r
     constexpr int XCH = LB_RS * DP / 8;     // 16-byte chunks of an X sub-tile
     constexpr int TCH = DP * LB_RS / 8;     // 16-byte chunks of an X^T sub-tile
     constexpr int XPT = (XCH + 255) / 256, TPT = (TCH + 255) / 256;
-    uint4 pxs[2][XPT], pts[2][TPT];
-    float pys[2] = {0.f, 0.f};
-    auto fetch = [&](int sidx, uint4* px, uint4* pt, float& py) {
+    uint4 px[XPT], pt[TPT];
+    float py = 0.f;
+    auto fetch = [&](int sidx) {
         const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
@@ -163,7 +195,7 @@ __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __r
             py = gr < r_end ? (float)a.tg.y[gr] : 0.f;
         }
     };
-    auto stash = [&](int buf, const uint4* px, const uint4* pt, float py) {
+    auto stash = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
             const int ch = threadIdx.x + 256 * u;
@@ -183,81 +215,335 @@ __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __r
         if (threadIdx.x < LB_RS) ys[buf * LB_RS + threadIdx.x] = py;
     };
 
-    floatx4 gacc[2][NT];
+    floatx4 gacc[CS][NT];
 #pragma unroll
-    for (int cs = 0; cs < 2; ++cs)
+    for (int cs = 0; cs < CS; ++cs)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) gacc[cs][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    // pipeline: sub-tile s is in LDS buffer s % 2 while the loads of s + 1 and
-    // s + 2 are in flight in the two register stages
+    // sub-tile s sits in LDS buffer s % 2; the loads of s + 1 are in flight in
+    // registers while s is multiplied and are stored to the other buffer after it
     if (nsub > 0) {
-        fetch(0, pxs[0], pts[0], pys[0]);
-        stash(0, pxs[0], pts[0], pys[0]);
+        fetch(0);
+        stash(0);
     }
-    if (nsub > 1) fetch(1, pxs[1], pts[1], pys[1]);
+    if (nsub > 1) fetch(1);
     __syncthreads();
-    auto body = [&](int sidx, uint4* pn, uint4* tn, float& yn, uint4* pf, uint4* tf, float& yf) {
-        // pn/tn/yn: stage holding sub-tile sidx + 1; pf/tf/yf: stage to receive sidx + 2
+    for (int sidx = 0; sidx < nsub; ++sidx) {
         const int buf = sidx & 1;
-        if (sidx + 2 < nsub) fetch(sidx + 2, pf, tf, yf);
         const uint16_t* xb = xs + buf * LB_RS * XS;
         const uint16_t* tb = xts + buf * DP * TS;
         const float* yb = ys + buf * LB_RS;
-        // S for two 16-row tiles x two 16-chain tiles
-        floatx4 sacc[2][2];
+        // S for two 16-row tiles x four 16-chain tiles; each X fragment feeds four MFMAs
+        floatx4 sacc[2][CS];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int cs = 0; cs < 2; ++cs) sacc[mt][cs] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int cs = 0; cs < CS; ++cs) sacc[mt][cs] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
                 const bf16x8 ax = *(const bf16x8*)&xb[(mt * 16 + l16) * XS + 32 * ks + 8 * g];
 #pragma unroll
-                for (int cs = 0; cs < 2; ++cs)
+                for (int cs = 0; cs < CS; ++cs)
                     sacc[mt][cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, thb[cs][ks], sacc[mt][cs], 0, 0, 0);
             }
         // R = y - sigmoid(S) (rows past the chunk contribute 0), packed as the A operand of G^T
         const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
-        bf16x8 ra[2];
+        bf16x8 ra[CS];
 #pragma unroll
-        for (int cs = 0; cs < 2; ++cs)
+        for (int cs = 0; cs < CS; ++cs) {
+            floatx8 rv;
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = mt * 16 + 4 * g + v;
-                    const float rv = (r0 + row < r_end) ? yb[row] - sigmoid_hw(sacc[mt][cs][v]) : 0.f;
-                    ra[cs][4 * mt + v] = bf16_bits(rv);
+                    rv[4 * mt + v] = (r0 + row < r_end) ? yb[row] - sigmoid_hw(sacc[mt][cs][v]) : 0.f;
                 }
-        // G^T += R^T X: B[k][j] = X[row(k)][dim 16 nt + j]
+            ra[cs] = pack_bf16(rv);
+        }
+        // G^T += R^T X: B[k][j] = X[row(k)][dim 16 nt + j]; each X^T fragment feeds four MFMAs
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const uint16_t* tr = &tb[(16 * nt + l16) * TS];
             const uint2 lo = *(const uint2*)&tr[4 * g];
             const uint2 hi = *(const uint2*)&tr[16 + 4 * g];
-            bf16x8 bx;
-            bx[0] = (short)(lo.x & 0xffff); bx[1] = (short)(lo.x >> 16);
-            bx[2] = (short)(lo.y & 0xffff); bx[3] = (short)(lo.y >> 16);
-            bx[4] = (short)(hi.x & 0xffff); bx[5] = (short)(hi.x >> 16);
-            bx[6] = (short)(hi.y & 0xffff); bx[7] = (short)(hi.y >> 16);
+            const bf16x8 bx = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
 #pragma unroll
-            for (int cs = 0; cs < 2; ++cs)
+            for (int cs = 0; cs < CS; ++cs)
                 gacc[cs][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[cs], bx, gacc[cs][nt], 0, 0, 0);
         }
-        if (sidx + 1 < nsub) stash(buf ^ 1, pn, tn, yn);
+        if (sidx + 1 < nsub) stash(buf ^ 1);
         __syncthreads();
-    };
-    for (int sidx = 0; sidx < nsub; sidx += 2) {
-        // stage 1 holds sidx + 1; stage 0 receives sidx + 2
-        body(sidx, pxs[1], pts[1], pys[1], pxs[0], pts[0], pys[0]);
-        if (sidx + 1 < nsub) body(sidx + 1, pxs[0], pts[0], pys[0], pxs[1], pts[1], pys[1]);
+        if (sidx + 2 < nsub) fetch(sidx + 2);
     }
     // partial G[chain][dim] for this row chunk
 #pragma unroll
-    for (int cs = 0; cs < 2; ++cs)
+    for (int cs = 0; cs < CS; ++cs)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t c = cw + 16 * cs + 4 * g + v;
+                const int64_t d = 16 * nt + l16;
+                if (c < C && d < D) a.ws.part_g[((int64_t)split * C + c) * D + d] = gacc[cs][nt][v];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// The same gradient partials with the sub-tiles copied global -> LDS by the
+// load-to-LDS instructions (global_load_lds_dwordx4: lane i of an instruction
+// writes bytes 16 i .. 16 i + 15 of a 1 KB block), for D and N multiples of 8.
+// A ring of LD_NB sub-tile buffers keeps three sub-tiles in flight without
+// staging registers; the barrier between sub-tiles waits for LDS only, each
+// wave first waiting (vmcnt) for its own copies of the sub-tile it is about
+// to read.  Both tiles use 16-byte slots XOR-swizzled by row so that the
+// operand reads of the MFMAs spread over the LDS banks:
+//   X   [32 rows][DP / 8 slots]: slot c of row r at position c ^ (r & XM)
+//   X^T [DP dims][4 slots of 8 rows]: slot c of dim d at position c ^ ((d >> 1) & 3)
+// ---------------------------------------------------------------------------
+constexpr int LD_NB = 4;      // sub-tile buffers
+#ifndef LD_XM_MAX
+#define LD_XM_MAX 8
+#endif
+#ifndef LD_TSHIFT
+#define LD_TSHIFT 1
+#endif
+// X swizzle mask for SR slots per row; X^T slot swizzle of dim d
+__host__ __device__ constexpr int ld_xmask(int SR) { return (SR < LD_XM_MAX ? SR : LD_XM_MAX) - 1; }
+__device__ __forceinline__ int ld_tsw(int d) { return (d >> LD_TSHIFT) & 3; }
+constexpr int LD_YB = 256;    // bytes reserved for the labels of a sub-tile (32 used)
+
+template <int KS>
+__host__ __device__ constexpr int ld_buf_bytes() { return 2 * LB_RS * 32 * KS * 2 + LD_YB; }
+
+// s_waitcnt vmcnt(n) leaving the other counters unconstrained (gfx9 encoding)
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(n >= 0 && n < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// workgroup barrier that orders LDS accesses only (in-flight global->LDS copies
+// of later sub-tiles stay in flight)
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// shapes the load-to-LDS kernels take: 16-byte aligned rows of X and X^T, at
+// least 64 rows, and X^T byte offsets within 32 bits
+static bool ld_copy_ok(const TargetDev& tg) {
+    return tg.D % 8 == 0 && tg.N % 8 == 0 && tg.N >= 64 && (uint64_t)tg.D * (uint64_t)tg.N * 2u < (1ull << 32);
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_lr16_grad_dma(PlainArgs a, const float* __restrict__ xsrc,
+                                                       const float* __restrict__ psrc, int drift,
+                                                       int64_t rows_per_split, int nsplit,
+                                                       const uint16_t* __restrict__ Xt) {
+    constexpr int NT = 2 * KS;
+    constexpr int CS = lb_cs(KS);
+    constexpr int CW = 16 * CS, CT = LB_NW * CW;
+    constexpr int DP = 32 * KS;
+    constexpr int SR = DP / 8;                  // 16-byte slots per X row
+    constexpr int XM = ld_xmask(SR);            // swizzle mask of X
+    constexpr int XB = LB_RS * DP * 2;          // bytes of an X sub-tile
+    constexpr int TB = DP * LB_RS * 2;          // bytes of an X^T sub-tile
+    constexpr int BUF = ld_buf_bytes<KS>();
+    constexpr int XI = XB / 1024, TI = TB / 1024;      // copy instructions per tile (multiples of 2)
+    constexpr int JW = (XI + TI) / LB_NW;              // tile copy instructions per wave
+    constexpr int J = JW + 1;                          // plus the labels
+    static_assert((XI + TI) % LB_NW == 0, "copies must split evenly over the waves");
+    extern __shared__ __align__(16) uint8_t ldsb[];
+
+    const int64_t D = a.tg.D, N = a.tg.N, C = a.C;
+    const int ntile = (int)((C + CT - 1) / CT);
+    int tile, split;
+    lb_map(blockIdx.x, ntile, nsplit, &tile, &split);
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l16 = lane & 15, g = lane >> 4;
+    const int64_t cw = (int64_t)tile * CT + CW * w;
+    const uint16_t* X = (const uint16_t*)a.tg.X;
+    const uint8_t* Y = a.tg.y;
+
+    bf16x8 thb[CS][KS];
+#pragma unroll
+    for (int cs = 0; cs < CS; ++cs) {
+        const int64_t c = cw + 16 * cs + l16;
+        const bool cok = c < C;
+        const float eps = cok ? (float)a.ws.eps[c] : 0.f;
+        const float* xr = xsrc + (cok ? c : 0) * D;
+        const float* pr = psrc + (cok ? c : 0) * D;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int d0 = 32 * ks + 8 * g;
+            floatx8 v = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (cok && d0 < D) {      // D % 8 == 0: the 8 dims are all in range
+                const float4 x0 = *(const float4*)(xr + d0), x1 = *(const float4*)(xr + d0 + 4);
+                v = floatx8{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+                if (drift) {
+                    const float4 p0 = *(const float4*)(pr + d0), p1 = *(const float4*)(pr + d0 + 4);
+                    const floatx8 pv = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) v[e] = fmaf(eps, pv[e], v[e]);
+                }
+            }
+            thb[cs][ks] = pack_bf16(v);
+        }
+    }
+
+    const int64_t r_begin = (int64_t)split * rows_per_split;
+    int64_t r_end = r_begin + rows_per_split;
+    if (r_end > N) r_end = N;
+    const int nsub = r_begin < r_end ? (int)((r_end - r_begin + LB_RS - 1) / LB_RS) : 0;
+
+    // copies of sub-tile sidx into buffer sidx % LD_NB; rows past the chunk and
+    // dims past D read in-range data whose products are masked or discarded
+    // sources: a sub-tile base (uniform) plus a 32-bit per-lane byte offset
+    auto copy_in = [&](int sidx, uint8_t* __restrict__ base) {
+        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
+        const int nrow = (int)(r_end - r0 < LB_RS ? r_end - r0 : LB_RS);   // rows of this sub-tile (multiple of 8)
+        const char* xsrc_t = (const char*)(X + r0 * D);
+        const char* tsrc_t = (const char*)(Xt + r0);
+#pragma unroll
+        for (int k = 0; k < JW; ++k) {
+            const int i = w + LB_NW * k;
+            if (i < XI) {
+                const int q = i * 64 + lane;
+                const int row = q / SR, c = (q % SR) ^ (row & XM);
+                const int rowc = row < nrow ? row : nrow - 1;
+                const uint32_t off = (uint32_t)(rowc * (int)D + (8 * c < D ? 8 * c : 0)) * 2u;
+                __builtin_amdgcn_global_load_lds((const void*)(xsrc_t + off), (lds_void_t*)(base + i * 1024), 16, 0,
+                                                 0);
+            } else {
+                const int ii = i - XI;
+                const int q = ii * 64 + lane;
+                const int dim = q >> 2, c = (q & 3) ^ ld_tsw(dim);
+                const int rr = 8 * c + 8 <= nrow ? 8 * c : 0;
+                const uint32_t off = ((uint32_t)(dim < D ? dim : 0) * (uint32_t)N + (uint32_t)rr) * 2u;
+                __builtin_amdgcn_global_load_lds((const void*)(tsrc_t + off), (lds_void_t*)(base + XB + ii * 1024), 16,
+                                                 0, 0);
+            }
+        }
+        // labels: dword (lane % 8) of the 32 rows when all of them exist, else a dummy copy
+        const int64_t yo = r0 + LB_RS <= r_end ? r0 + 4 * (lane & 7) : 0;
+        __builtin_amdgcn_global_load_lds((const void*)(Y + yo), (lds_void_t*)(base + XB + TB), 4, 0, 0);
+    };
+
+    floatx4 gacc[CS][NT];
+#pragma unroll
+    for (int cs = 0; cs < CS; ++cs)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) gacc[cs][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    if (nsub > 0) copy_in(0, ldsb);
+    if (nsub > 1) copy_in(1, ldsb + BUF);
+    if (nsub > 2) copy_in(2, ldsb + 2 * BUF);
+    // one sub-tile: the copy of sub-tile sidx + 3 into nxt and the products of
+    // sub-tile sidx from cur, two distinct buffers (restrict: the LDS reads need
+    // not wait for the copy; the explicit vmcnt waits order the sub-tiles)
+    auto step = [&](int sidx, uint8_t* __restrict__ nxt, const uint8_t* __restrict__ base) {
+        if (sidx + 3 < nsub) copy_in(sidx + 3, nxt);
+        const uint8_t* tb = base + XB;
+        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
+        floatx4 sacc[2][CS];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int cs = 0; cs < CS; ++cs) sacc[mt][cs] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // X fragments read three k-steps ahead of their MFMAs (LDS latency off the MFMA path)
+        auto xfrag = [&](int idx) {
+            const int ks = idx >> 1, row = (idx & 1) * 16 + l16;
+            return *(const bf16x8*)(base + row * (DP * 2) + (((4 * ks + g) ^ (row & XM)) * 16));
+        };
+        bf16x8 xf0 = xfrag(0), xf1 = xfrag(1), xf2 = xfrag(2);
+#pragma unroll
+        for (int idx = 0; idx < 2 * KS; ++idx) {
+            const bf16x8 ax = xf0;
+            xf0 = xf1;
+            xf1 = xf2;
+            if (idx + 3 < 2 * KS) xf2 = xfrag(idx + 3);
+            const int ks = idx >> 1, mt = idx & 1;
+#pragma unroll
+            for (int cs = 0; cs < CS; ++cs)
+                sacc[mt][cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, thb[cs][ks], sacc[mt][cs], 0, 0, 0);
+        }
+        // issue order: three fragment reads, then per k-step its MFMAs followed by the
+        // read three steps ahead (the LDS latency overlaps two steps of MFMAs)
+        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+#pragma unroll
+        for (int idx = 0; idx < 2 * KS; ++idx) {
+            __builtin_amdgcn_sched_group_barrier(0x008, CS, 0);
+            if (idx + 3 < 2 * KS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // labels of the lane's rows 4 g .. 4 g + 3 and 16 + 4 g .. 16 + 4 g + 3
+        uint32_t yw[2];
+        if (r0 + LB_RS <= r_end) {
+            yw[0] = *(const uint32_t*)(base + XB + TB + 4 * g);
+            yw[1] = *(const uint32_t*)(base + XB + TB + 16 + 4 * g);
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                uint32_t t = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t gr = r0 + mt * 16 + 4 * g + v;
+                    t |= (gr < r_end ? (uint32_t)Y[gr] : 0u) << (8 * v);
+                }
+                yw[mt] = t;
+            }
+        }
+        bf16x8 ra[CS];
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs) {
+            floatx8 rv;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = mt * 16 + 4 * g + v;
+                    const float y = (float)((yw[mt] >> (8 * v)) & 0xffu);
+                    rv[4 * mt + v] = (r0 + row < r_end) ? y - sigmoid_hw(sacc[mt][cs][v]) : 0.f;
+                }
+            ra[cs] = pack_bf16(rv);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        auto tfrag = [&](int nt) {
+            const int dim = 16 * nt + l16, sw = ld_tsw(dim);
+            const uint8_t* tr = tb + dim * 64 + (g & 1) * 8;
+            const uint2 lo = *(const uint2*)(tr + (((g >> 1)) ^ sw) * 16);
+            const uint2 hi = *(const uint2*)(tr + ((2 + (g >> 1)) ^ sw) * 16);
+            return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+        };
+        bf16x8 tf0 = tfrag(0), tf1 = tfrag(1);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bx = tf0;
+            tf0 = tf1;
+            if (nt + 2 < NT) tf1 = tfrag(nt + 2);
+#pragma unroll
+            for (int cs = 0; cs < CS; ++cs)
+                gacc[cs][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[cs], bx, gacc[cs][nt], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            __builtin_amdgcn_sched_group_barrier(0x008, CS, 0);
+            if (nt + 2 < NT) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        }
+    };
+    for (int sidx = 0; sidx < nsub; ++sidx) {
+        if (sidx + 2 < nsub) wait_vmcnt<2 * J>();
+        else if (sidx + 1 < nsub) wait_vmcnt<J>();
+        else wait_vmcnt<0>();
+        lds_barrier();
+        step(sidx, ldsb + ((sidx + 3) % LD_NB) * BUF, ldsb + (sidx % LD_NB) * BUF);
+    }
+#pragma unroll
+    for (int cs = 0; cs < CS; ++cs)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
@@ -392,6 +678,171 @@ __global__ __launch_bounds__(256) void k_lr16_logp(PlainArgs a, const float* __r
     if (g == 0 && cok) a.ws.part_lp[(int64_t)split * C + c] = lp;
 }
 
+// The accurate log-probability partials with global -> LDS copies of X (D and
+// N multiples of 8): 32 chains per wave (two 16-chain tiles), each X fragment
+// feeding six MFMAs (three theta terms x two tiles); ring of LD_NB sub-tiles.
+constexpr int LP_CW = 32;     // chains per wave
+
+template <int KS>
+__host__ __device__ constexpr int lp_buf_bytes() { return LB_RS * 32 * KS * 2 + LD_YB; }
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_lr16_logp_dma(PlainArgs a, const float* __restrict__ xsrc,
+                                                       int64_t rows_per_split, int nsplit) {
+    constexpr int DP = 32 * KS;
+    constexpr int SR = DP / 8;
+    constexpr int XM = ld_xmask(SR);
+    constexpr int XB = LB_RS * DP * 2;
+    constexpr int BUF = lp_buf_bytes<KS>();
+    constexpr int XI = XB / 1024;
+    constexpr int JW = (XI + LB_NW - 1) / LB_NW;       // X copy instructions per wave (some waves may repeat one)
+    constexpr int J = JW + 1;
+    constexpr int CS = LP_CW / 16, CT = LB_NW * LP_CW;
+    extern __shared__ __align__(16) uint8_t ldsb[];
+
+    const int64_t D = a.tg.D, N = a.tg.N, C = a.C;
+    const int ntile = (int)((C + CT - 1) / CT);
+    int tile, split;
+    lb_map(blockIdx.x, ntile, nsplit, &tile, &split);
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l16 = lane & 15, g = lane >> 4;
+    const int64_t cw = (int64_t)tile * CT + LP_CW * w;
+    const uint16_t* X = (const uint16_t*)a.tg.X;
+    const uint8_t* Y = a.tg.y;
+
+    // theta = hi + mid + lo, three BF16 B operands per chain tile and k-step
+    bf16x8 th[3][CS][KS];
+#pragma unroll
+    for (int cs = 0; cs < CS; ++cs) {
+        const int64_t c = cw + 16 * cs + l16;
+        const bool cok = c < C;
+        const float* xr = xsrc + (cok ? c : 0) * D;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int d0 = 32 * ks + 8 * g;
+            floatx8 v = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (cok && d0 < D) {
+                const float4 x0 = *(const float4*)(xr + d0), x1 = *(const float4*)(xr + d0 + 4);
+                v = floatx8{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            }
+            floatx8 r1, r2;
+            const bf16x8 h = pack_bf16(v);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) r1[e] = v[e] - bf16_to_f32((uint16_t)h[e]);
+            const bf16x8 m = pack_bf16(r1);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) r2[e] = r1[e] - bf16_to_f32((uint16_t)m[e]);
+            th[0][cs][ks] = h;
+            th[1][cs][ks] = m;
+            th[2][cs][ks] = pack_bf16(r2);
+        }
+    }
+    const int64_t r_begin = (int64_t)split * rows_per_split;
+    int64_t r_end = r_begin + rows_per_split;
+    if (r_end > N) r_end = N;
+    const int nsub = r_begin < r_end ? (int)((r_end - r_begin + LB_RS - 1) / LB_RS) : 0;
+
+    auto copy_in = [&](int sidx, uint8_t* __restrict__ base) {
+        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
+        const int nrow = (int)(r_end - r0 < LB_RS ? r_end - r0 : LB_RS);
+        const char* xsrc_t = (const char*)(X + r0 * D);
+#pragma unroll
+        for (int k = 0; k < JW; ++k) {
+            int i = w + LB_NW * k;
+            if (i >= XI) i = XI - 1;          // a repeated copy keeps the count equal over the waves
+            const int q = i * 64 + lane;
+            const int row = q / SR, c = (q % SR) ^ (row & XM);
+            const int rowc = row < nrow ? row : nrow - 1;
+            const uint32_t off = (uint32_t)(rowc * (int)D + (8 * c < D ? 8 * c : 0)) * 2u;
+            __builtin_amdgcn_global_load_lds((const void*)(xsrc_t + off), (lds_void_t*)(base + i * 1024), 16, 0, 0);
+        }
+        const int64_t yo = r0 + LB_RS <= r_end ? r0 + 4 * (lane & 7) : 0;
+        __builtin_amdgcn_global_load_lds((const void*)(Y + yo), (lds_void_t*)(base + XB), 4, 0, 0);
+    };
+    double lp[CS] = {};
+    if (nsub > 0) copy_in(0, ldsb);
+    if (nsub > 1) copy_in(1, ldsb + BUF);
+    if (nsub > 2) copy_in(2, ldsb + 2 * BUF);
+    auto step = [&](int sidx, uint8_t* __restrict__ nxt, const uint8_t* __restrict__ base) {
+        if (sidx + 3 < nsub) copy_in(sidx + 3, nxt);
+        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
+        floatx4 sacc[2][CS];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int cs = 0; cs < CS; ++cs) sacc[mt][cs] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // smallest terms first; X fragments read two steps ahead of their MFMAs
+        auto xfrag = [&](int idx) {
+            const int ks = idx >> 1, row = (idx & 1) * 16 + l16;
+            return *(const bf16x8*)(base + row * (DP * 2) + (((4 * ks + g) ^ (row & XM)) * 16));
+        };
+        bf16x8 xf0 = xfrag(0), xf1 = xfrag(1);
+#pragma unroll
+        for (int idx = 0; idx < 2 * KS; ++idx) {
+            const bf16x8 ax = xf0;
+            xf0 = xf1;
+            if (idx + 2 < 2 * KS) xf1 = xfrag(idx + 2);
+            const int ks = idx >> 1, mt = idx & 1;
+#pragma unroll
+            for (int term = 2; term >= 0; --term)
+#pragma unroll
+                for (int cs = 0; cs < CS; ++cs)
+                    sacc[mt][cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, th[term][cs][ks], sacc[mt][cs], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+        for (int idx = 0; idx < 2 * KS; ++idx) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 3 * CS, 0);
+            if (idx + 2 < 2 * KS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        uint32_t yw[2];
+        if (r0 + LB_RS <= r_end) {
+            yw[0] = *(const uint32_t*)(base + XB + 4 * g);
+            yw[1] = *(const uint32_t*)(base + XB + 16 + 4 * g);
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                uint32_t t = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t gr = r0 + mt * 16 + 4 * g + v;
+                    t |= (gr < r_end ? (uint32_t)Y[gr] : 0u) << (8 * v);
+                }
+                yw[mt] = t;
+            }
+        }
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs)
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = mt * 16 + 4 * g + v;
+                    const float s = sacc[mt][cs][v];
+                    const bool y1 = (yw[mt] >> (8 * v)) & 1u;
+                    const float sp = softplus_hw(y1 ? -s : s);
+                    lp[cs] -= (r0 + row < r_end) ? (double)sp : 0.0;
+                }
+    };
+    for (int sidx = 0; sidx < nsub; ++sidx) {
+        if (sidx + 2 < nsub) wait_vmcnt<2 * J>();
+        else if (sidx + 1 < nsub) wait_vmcnt<J>();
+        else wait_vmcnt<0>();
+        lds_barrier();
+        step(sidx, ldsb + ((sidx + 3) % LD_NB) * BUF, ldsb + (sidx % LD_NB) * BUF);
+    }
+    // lanes holding chain l16 of tile cs: l16, l16 + 16, + 32, + 48
+#pragma unroll
+    for (int cs = 0; cs < CS; ++cs) {
+        double t = lp[cs];
+        t += __shfl_xor(t, 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        const int64_t c = cw + 16 * cs + l16;
+        if (g == 0 && c < C) a.ws.part_lp[(int64_t)split * C + c] = t;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_lr16_lp_sum(PlainArgs a, int nsplit) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.C) return;
@@ -425,11 +876,29 @@ static int pow2_split(int ntile, int64_t N) {
     return s;
 }
 
-int lb_grad_nsplit(int64_t N, int64_t C) { return pow2_split((int)((C + LB_CT - 1) / LB_CT), N); }
+// chains per workgroup of the gradient kernel for D dims
+static int lb_grad_ct(int64_t D) { return LB_NW * 16 * lb_cs((int)((D + 31) / 32) > 4 ? 8 : 4); }
+
+// row splits: as many as fill the 256 CUs once (at most 8, at least 4 sub-tiles each)
+int lb_grad_nsplit(int64_t N, int64_t C, int64_t D) {
+    const int ntile = (int)((C + lb_grad_ct(D) - 1) / lb_grad_ct(D));
+    int s = ntile >= 256 ? 1 : 256 / ntile;
+    if (s > 8) s = 8;
+    while (s > 1 && (N + s - 1) / s < 4 * LB_RS) --s;
+    return s;
+}
 int lb_grad_nsplit_t(const PlainArgs& a) {
-    return a.tune.lr16_nsplit > 0 ? a.tune.lr16_nsplit : lb_grad_nsplit(a.tg.N, a.C);
+    return a.tune.lr16_nsplit > 0 ? a.tune.lr16_nsplit : lb_grad_nsplit(a.tg.N, a.C, a.tg.D);
 }
 int lb_logp_nsplit(int64_t N, int64_t C) { return pow2_split((int)((C + 63) / 64), N); }
+// row splits of the copy-staged log-probability kernel (128 chains per workgroup)
+static int lp_dma_nsplit(int64_t N, int64_t C) {
+    const int ntile = (int)((C + LB_NW * LP_CW - 1) / (LB_NW * LP_CW));
+    int s = ntile >= 256 ? 1 : 256 / ntile;
+    if (s > 8) s = 8;
+    while (s > 1 && (N + s - 1) / s < 4 * LB_RS) --s;
+    return s;
+}
 
 static int64_t rows_for(int64_t N, int nsplit) {
     const int64_t r = (N + nsplit - 1) / nsplit;
@@ -448,12 +917,22 @@ hipError_t launch_transpose_bf16(const PlainArgs& a, void* Xt, hipStream_t s) {
 template <int KS>
 static hipError_t lb_grad_k(const PlainArgs& a, const float* x, const float* p, int drift, const void* Xt,
                             hipStream_t s) {
-    const int ntile = (int)((a.C + LB_CT - 1) / LB_CT);
+    constexpr int CT = LB_NW * 16 * lb_cs(KS);
+    const int ntile = (int)((a.C + CT - 1) / CT);
     const int nsplit = lb_grad_nsplit_t(a);
     const size_t lds = (size_t)(2 * LB_RS * (32 * KS + LB_XPAD) + 2 * 32 * KS * (LB_RS + LB_TPAD)) * 2 +
                        2 * LB_RS * sizeof(float);
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_lr16_grad<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (ld_copy_ok(a.tg)) {
+        const size_t ldd = (size_t)LD_NB * ld_buf_bytes<KS>();
+        if (ldd > 65536)
+            (void)hipFuncSetAttribute((const void*)k_lr16_grad_dma<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)ldd);
+        hipLaunchKernelGGL(k_lr16_grad_dma<KS>, dim3((unsigned)(ntile * nsplit)), dim3(256), ldd, s, a, x, p, drift,
+                           rows_for(a.tg.N, nsplit), nsplit, (const uint16_t*)Xt);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_lr16_grad<KS>, dim3((unsigned)(ntile * nsplit)), dim3(256), lds, s, a, x, p, drift,
                        rows_for(a.tg.N, nsplit), nsplit, (const uint16_t*)Xt);
     return hipGetLastError();
@@ -461,6 +940,19 @@ static hipError_t lb_grad_k(const PlainArgs& a, const float* x, const float* p, 
 
 template <int KS>
 static hipError_t lb_logp_k(const PlainArgs& a, const float* x, hipStream_t s) {
+    if (ld_copy_ok(a.tg)) {
+        constexpr int CT = LB_NW * LP_CW;
+        const int ntile = (int)((a.C + CT - 1) / CT);
+        const int nsplit = lp_dma_nsplit(a.tg.N, a.C);
+        const size_t ldd = (size_t)LD_NB * lp_buf_bytes<KS>();
+        if (ldd > 65536)
+            (void)hipFuncSetAttribute((const void*)k_lr16_logp_dma<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)ldd);
+        hipLaunchKernelGGL(k_lr16_logp_dma<KS>, dim3((unsigned)(ntile * nsplit)), dim3(256), ldd, s, a, x,
+                           rows_for(a.tg.N, nsplit), nsplit);
+        hipLaunchKernelGGL(k_lr16_lp_sum, dim3((unsigned)((a.C + 255) / 256)), dim3(256), 0, s, a, nsplit);
+        return hipGetLastError();
+    }
     const int ntile = (int)((a.C + 63) / 64);
     const int nsplit = lb_logp_nsplit(a.tg.N, a.C);
     const size_t lds = (size_t)(2 * LB_RS * (32 * KS + LB_XPAD)) * 2 + 2 * LB_RS * sizeof(float);
