@@ -103,21 +103,21 @@ def cpu_baseline(w, budget_s=12.0):
                       f"FP64, {el:.1f} s wall"}
 
 
-def ess_run(s, w, x0, eps0, n_results, stream):
-    """One further run from the same start with the same burn-in and n_results
-    kept draws, long enough for split R-hat <= 1.01; ESS/s is the minimum bulk
-    ESS over coordinates divided by the run's wall time (burn-in included)."""
+def ess_run(s, w, x0, eps0, n_results, num_burnin, stream):
+    """One further run from the same start with the workload's burn-in and
+    n_results kept draws, long enough for split R-hat <= 1.01; ESS/s is the minimum
+    bulk ESS over coordinates divided by the run's wall time (burn-in included)."""
     import torch
     from paper_2002_01184_amd import diagnostics as dg
     s.set_state(x0, eps0, 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = s.sample_chain(n_results, w.num_burnin, adapt=w.adapt)
+    out = s.sample_chain(n_results, num_burnin, adapt=w.adapt)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     summ = dg.t_summarize(out["samples"])
     del out
-    return {"num_burnin": w.num_burnin, "num_results": n_results, "seconds": dt,
+    return {"num_burnin": num_burnin, "num_results": n_results, "seconds": dt,
             "max_rhat": summ["max_rhat"], "min_ess_bulk": summ["min_ess_bulk"],
             "ess_per_sec": summ["min_ess_bulk"] / dt if summ["max_rhat"] <= 1.01 else None}
 
@@ -224,6 +224,7 @@ def main():
         return
     dev = torch.device("cuda:0")
     w = W.CONFIGS[args.config]()
+    burnin_cfg = w.num_burnin           # the ESS run keeps the workload's own burn-in
     if args.transitions is not None:
         w.num_burnin = args.transitions // 2
         w.num_results = args.transitions - w.num_burnin
@@ -299,14 +300,15 @@ def main():
         result["ess_per_sec"] = (summ["min_ess_bulk"] / (elapsed / args.steps)) if summ["max_rhat"] <= 1.01 else None
         result["accept_rate"] = float(out["is_accepted"].float().mean().item())
         out = None
-        T_long = w.num_burnin + args.ess_results
-        est_s = elapsed / args.steps * T_long / T
-        sample_bytes = args.ess_results * w.num_chains * w.dim * (8 if w.state_dtype == "f64" else 4)
         if args.ess_results > 0 and result["ess_per_sec"] is None:
-            if est_s <= 60 and sample_bytes <= (16 << 30):
-                result["ess_run"] = ess_run(s, w, x0, eps0, args.ess_results, stream)
+            # as many kept draws as fit in ~60 s of this workload and 16 GiB of samples
+            per_tr = elapsed / args.steps / T
+            per_draw = w.num_chains * w.dim * (8 if w.state_dtype == "f64" else 4)
+            r_fit = min(args.ess_results, int((16 << 30) // per_draw), int(60.0 / per_tr) - burnin_cfg)
+            if r_fit >= 100:
+                result["ess_run"] = ess_run(s, w, x0, eps0, r_fit, burnin_cfg, stream)
             else:
-                result["ess_run"] = {"skipped": f"estimated {est_s:.0f} s / {sample_bytes / 2**30:.1f} GiB of samples"}
+                result["ess_run"] = {"skipped": f"fewer than 100 draws fit ({per_tr * 1e3:.1f} ms per transition)"}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     s.close()

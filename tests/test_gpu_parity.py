@@ -244,9 +244,9 @@ def _trajectory_compare(w, chains, form):
     oracle's run of a sample of chains (same chain ids, so the same Philox streams)."""
     s = hmc.sampler_for(w, form=form)
     out = s.sample_chain(w.num_results, w.num_burnin, adapt=w.adapt)
-    g_acc = to_np(out["is_accepted"])[:, chains].astype(bool)
-    g_smp = to_np(out["samples"])[:, chains]
-    g_eps = to_np(out["step_size"])[:, chains]
+    g_acc = to_np(out["is_accepted"][:, chains]).astype(bool)
+    g_smp = to_np(out["samples"][:, chains])
+    g_eps = to_np(out["step_size"][:, chains])
     s.close()
     o = oracle.sample_chain(oracle_target(w), w.num_leapfrog_steps, w.seed, w.x0[:max(chains) + 1].astype(np.float64),
                             w.step_size, w.num_burnin, w.num_results, adapt=w.adapt)
@@ -261,6 +261,25 @@ def test_full_size_paper_example_fp64():
     w = W.cfg_std_normal_1d()
     agree, err, _, _ = _trajectory_compare(w, list(range(100)), hmc.HMC_FORM_AUTO)
     assert agree == 1.0 and err.max() < 1e-12
+
+
+@pytest.mark.parametrize("form", ["plain", "auto"])
+def test_wide_std_normal_fp64_sampled_chains(form):
+    # the paper's target at 2^24 chains (the HBM-roofline shape), every chain on the
+    # GPU; the first chains against the oracle
+    w = W.cfg_std_normal_1d_wide()
+    w.num_burnin, w.num_results = 4, 4
+    agree, err, _, _ = _trajectory_compare(w, [0, 1, 2, 17, 63], FORMS[form])
+    assert agree == 1.0 and err.max() < 1e-12
+
+
+@pytest.mark.parametrize("form", ["plain", "auto"])
+def test_wide_gauss_diag_1000_sampled_chains(form):
+    # diagonal Gaussian D=1000 (variances 1e-2..1e2), 16384 chains, FP32 state
+    w = W.cfg_gauss_diag_1000()
+    w.num_burnin, w.num_results = 3, 3
+    agree, err, _, _ = _trajectory_compare(w, [0, 1, 7, 31], FORMS[form])
+    assert agree == 1.0 and err.max() < 1e-5
 
 
 def test_full_size_logreg_1000x25_fixed_step_sampled_chains():

@@ -17,6 +17,8 @@ results) and the synthetic shapes of the measured configurations:
                       lambda log-spaced 1e-2..1e2, Q Haar; 4096 chains, L=20
   logreg_100000x256   logistic regression, X 100000x256 stored BF16,
                       8192 chains, L=10
+and two wide shapes of the element-wise targets (1-D N(0,1) at 2^24 chains;
+diagonal Gaussian D=1000, 16384 chains) for the HBM-bound plain step.
 """
 from __future__ import annotations
 
@@ -175,8 +177,23 @@ def cfg_logreg_100000x256():
                   init=0.05)
 
 
+# Wide shapes of the element-wise targets, for the HBM roofline of the plain step:
+# the paper's 1-D example at 2^24 chains (FP64) and a diagonal Gaussian D=1000
+# (variances 1e-2..1e2) with 16384 chains (FP32).
+def cfg_std_normal_1d_wide():
+    w = std_normal_1d(num_chains=1 << 24, burnin=50, results=50)
+    w.name = "std_normal_1d_2^24"
+    return w
+
+
+def cfg_gauss_diag_1000():
+    return gauss_diag(dim=1000, num_chains=16384, L=10, step_size=0.1, burnin=100, results=100)
+
+
 CONFIGS = {
     "std_normal_1d": cfg_std_normal_1d,
+    "std_normal_1d_wide": cfg_std_normal_1d_wide,
+    "gauss_diag_1000": cfg_gauss_diag_1000,
     "logreg_1000x25": cfg_logreg_1000x25,
     "gauss_dense_100": cfg_gauss_dense_100,
     "logreg_100000x256": cfg_logreg_100000x256,
