@@ -108,3 +108,14 @@ def test_accept_uniform_distribution():
     z = oracle.momentum(0, 1000, 0, 4)
     uu = oracle.accept_uniform(0, 1000, 0)
     assert abs(np.corrcoef(z[:, 0], uu)[0, 1]) < 0.15
+
+
+def test_philox_known_answer_vectors():
+    # the published known-answer vectors of Philox4x32-10 (tests/golden/philox4x32_10_kat.txt)
+    path = os.path.join(HERE, "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        key, ctr, want = (v[0], v[1]), np.array([v[2:6]], np.uint32), v[6:10]
+        assert list(oracle.philox(ctr, key)[0]) == want
