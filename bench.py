@@ -103,20 +103,38 @@ def cpu_baseline(w, budget_s=12.0):
                       f"FP64, {el:.1f} s wall"}
 
 
-def ess_run(s, w, x0, eps0, n_results, num_burnin, stream):
+def ess_run(s, w, x0, eps0, n_results, num_burnin, chunk_s=20.0, per_tr=None):
     """One further run from the same start with the workload's burn-in and
     n_results kept draws, long enough for split R-hat <= 1.01; ESS/s is the minimum
-    bulk ESS over coordinates divided by the run's wall time (burn-in included)."""
+    bulk ESS over coordinates divided by the run's wall time (burn-in included).
+    The draws are taken in chunks of about chunk_s seconds (the step sizes are
+    frozen after the first chunk's burn-in and the transition counter carries
+    on, so the chunks form one chain) written straight into one sample array,
+    with a progress line on stderr after each chunk."""
     import torch
     from paper_2002_01184_amd import diagnostics as dg
+    dt_ = torch.float64 if w.state_dtype == "f64" else torch.float32
+    keep = torch.empty(n_results, w.num_chains, w.dim, dtype=dt_, device="cuda")
+    chunk = n_results if per_tr is None else max(100, int(chunk_s / per_tr))
     s.set_state(x0, eps0, 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = s.sample_chain(n_results, num_burnin, adapt=w.adapt)
-    torch.cuda.synchronize()
+    r = 0
+    while r < n_results:
+        k = min(chunk, n_results - r)
+        first = r == 0
+        s.sample_chain(k, num_burnin if first else 0, adapt=w.adapt and first, trace=False,
+                       out_samples=keep[r:r + k])
+        r += k
+        torch.cuda.synchronize()
+        print(f"ess run: {r}/{n_results} draws, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dt = time.perf_counter() - t0
-    summ = dg.t_summarize(out["samples"])
-    del out
+
+    def progress(d, D):
+        if d % 32 == 0 or d == D:
+            print(f"ess run: diagnostics {d}/{D} coordinates", file=sys.stderr, flush=True)
+    summ = dg.t_summarize(keep, progress=progress)
+    del keep
     return {"num_burnin": num_burnin, "num_results": n_results, "seconds": dt,
             "max_rhat": summ["max_rhat"], "min_ess_bulk": summ["min_ess_bulk"],
             "ess_per_sec": summ["min_ess_bulk"] / dt if summ["max_rhat"] <= 1.01 else None}
@@ -192,6 +210,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="run the library's autotuner before timing")
     ap.add_argument("--ess-results", type=int, default=9000,
                     help="kept draws of the separate ESS run (same burn-in); 0 skips it")
+    ap.add_argument("--ess-seconds", type=float, default=60.0,
+                    help="time budget of the separate ESS run (burn-in included)")
+    ap.add_argument("--ess-gb", type=float, default=16.0, help="memory budget of its kept samples (GiB)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -301,12 +322,13 @@ def main():
         result["accept_rate"] = float(out["is_accepted"].float().mean().item())
         out = None
         if args.ess_results > 0 and result["ess_per_sec"] is None:
-            # as many kept draws as fit in ~60 s of this workload and 16 GiB of samples
+            # as many kept draws as fit in the time and memory budgets
             per_tr = elapsed / args.steps / T
             per_draw = w.num_chains * w.dim * (8 if w.state_dtype == "f64" else 4)
-            r_fit = min(args.ess_results, int((16 << 30) // per_draw), int(60.0 / per_tr) - burnin_cfg)
+            r_fit = min(args.ess_results, int(args.ess_gb * (1 << 30) // per_draw),
+                        int(args.ess_seconds / per_tr) - burnin_cfg)
             if r_fit >= 100:
-                result["ess_run"] = ess_run(s, w, x0, eps0, r_fit, burnin_cfg, stream)
+                result["ess_run"] = ess_run(s, w, x0, eps0, r_fit, burnin_cfg, per_tr=per_tr)
             else:
                 result["ess_run"] = {"skipped": f"fewer than 100 draws fit ({per_tr * 1e3:.1f} ms per transition)"}
     if not args.no_cpu_baseline:

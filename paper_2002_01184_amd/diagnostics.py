@@ -175,11 +175,14 @@ def t_ess(x):
     return float(n * M / tau)
 
 
-def t_summarize(samples) -> dict:
-    """samples: torch tensor [R, C, D] (any device) -> min bulk-ESS, max R-hat."""
+def t_summarize(samples, progress=None) -> dict:
+    """samples: torch tensor [R, C, D] (any device) -> min bulk-ESS, max R-hat.
+    progress: optional callable(d, D) invoked after each coordinate."""
     e, r = [], []
     for d in range(samples.shape[2]):
         x = samples[:, :, d]
         e.append(t_ess(_t_rank_normalize(_t_split(x.double()))))
         r.append(t_rhat(x))
+        if progress is not None:
+            progress(d + 1, samples.shape[2])
     return dict(min_ess_bulk=float(np.min(e)), max_rhat=float(np.max(r)), ess_bulk=np.array(e), rhat=np.array(r))

@@ -286,10 +286,18 @@ class Sampler:
         return out
 
     def sample_chain(self, num_results, num_burnin_steps, adapt=False, target_accept=0.8, gamma=0.05, t0=10.0,
-                     kappa=0.75, store_samples=True, trace=True):
+                     kappa=0.75, store_samples=True, trace=True, out_samples=None):
+        """out_samples: optional contiguous [R, C, D] device tensor of the state
+        dtype that receives the samples (else one is allocated)."""
         torch = self.torch
         C, D, R = self.C, self.D, num_results
-        samples = torch.empty(R, C, D, dtype=self.dtype, device=self.device) if store_samples else None
+        if out_samples is not None:
+            if (tuple(out_samples.shape) != (R, C, D) or out_samples.dtype != self.dtype
+                    or not out_samples.is_contiguous() or out_samples.device.type != "cuda"):
+                raise ValueError("out_samples must be a contiguous [R, C, D] device tensor of the state dtype")
+            samples = out_samples
+        else:
+            samples = torch.empty(R, C, D, dtype=self.dtype, device=self.device) if store_samples else None
         tr = None
         outs = {}
         if trace:

@@ -125,6 +125,26 @@ def test_resume_is_bitwise(form):
 
 
 @pytest.mark.parametrize("form", ["plain", "auto"])
+def test_adapted_run_in_chunks_is_bitwise(form):
+    # burn-in with dual averaging and 3 kept draws, then two calls without burn-in:
+    # the step sizes stay frozen at exp(log eps_bar) and the counter carries on,
+    # so the chunks equal one uninterrupted call (also written into slices of one array)
+    w = W.logreg(200, 9, 96, L=5, step_size=0.05, seed=4)
+    s = hmc.sampler_for(w, form=FORMS[form])
+    full = s.sample_chain(10, 6, adapt=True)
+    s.close()
+    s1 = hmc.sampler_for(w, form=FORMS[form])
+    keep = torch.empty(10, w.num_chains, w.dim, dtype=torch.float32, device="cuda")
+    parts = [s1.sample_chain(3, 6, adapt=True, out_samples=keep[0:3]),
+             s1.sample_chain(4, 0, out_samples=keep[3:7]),
+             s1.sample_chain(3, 0, out_samples=keep[7:10])]
+    s1.close()
+    assert torch.equal(keep, full["samples"])
+    for k in ["is_accepted", "log_accept_ratio", "step_size", "target_log_prob"]:
+        assert torch.equal(torch.cat([p[k] for p in parts]), full[k]), k
+
+
+@pytest.mark.parametrize("form", ["plain", "auto"])
 def test_batch_semantics_and_determinism(form):
     w = W.logreg(300, 6, 96, L=5, step_size=0.1, seed=7)
     s = hmc.sampler_for(w, form=FORMS[form])
