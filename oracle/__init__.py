@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 STD_NORMAL, GAUSS_DIAG, GAUSS_DENSE, LOGREG = 0, 1, 2, 3
-TAG_MOMENTUM, TAG_ACCEPT = 0, 1
+TAG_MOMENTUM, TAG_ACCEPT, TAG_SWAP = 0, 1, 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -28,7 +28,7 @@ _u32p = ctypes.POINTER(ctypes.c_uint32)
 class _Target(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("dim", ctypes.c_int64),
                 ("prec", _dp), ("X", _dp), ("y", _dp), ("n_rows", ctypes.c_int64),
-                ("prior_scale", ctypes.c_double)]
+                ("prior_scale", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class _DualAvg(ctypes.Structure):
@@ -73,6 +73,14 @@ def lib():
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        _dp, _dp, _u8p, _dp, _dp, ctypes.c_int32]
         L.orc_sample_chain.restype = ctypes.c_int
+        L.orc_remc_swap.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                    ctypes.c_uint32, _dp, _dp, _dp, _u8p]
+        L.orc_remc_sample_chain.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, _dp, _dp,
+                                            ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _u8p, _u8p,
+                                            ctypes.c_int32]
+        L.orc_remc_sample_chain.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -96,6 +104,7 @@ class Target:
     X: np.ndarray | None = None
     y: np.ndarray | None = None
     prior_scale: float = 1.0
+    beta: float = 1.0          # inverse temperature (replica exchange): beta * logp
 
     def __post_init__(self):
         if self.prec is not None:
@@ -106,7 +115,11 @@ class Target:
             self.y = _f64(self.y)
         n = 0 if self.X is None else self.X.shape[0]
         self._c = _Target(self.kind, 0, self.dim, _p(self.prec), _p(self.X), _p(self.y), n,
-                          float(self.prior_scale))
+                          float(self.prior_scale), float(self.beta))
+
+    def tempered(self, beta: float) -> "Target":
+        """The same target at inverse temperature beta (shares the arrays)."""
+        return Target(self.kind, self.dim, self.prec, self.X, self.y, self.prior_scale, float(beta))
 
     @property
     def c(self):
@@ -232,3 +245,57 @@ def sample_chain(tg: Target, L: int, seed: int, x0, eps0, num_burnin: int, num_r
                            _p(samples), _p(st), _p(acc, _u8p), _p(lar), _p(lp), nthreads)
     return dict(samples=samples, step_size=st, is_accepted=acc.astype(bool), log_accept_ratio=lar,
                 target_log_prob=lp, final_x=x, final_eps=eps)
+
+
+# ------------------------------------------------------ replica exchange --
+def _replica_targets(tg: Target, betas):
+    tgs = [tg.tempered(b) for b in betas]
+    arr = (_Target * len(tgs))(*[t._c for t in tgs])
+    return tgs, arr
+
+
+def remc_swap(tg: Target, betas, seed: int, t: int, x, logp=None, g=None):
+    """One exchange step (swap index t) over K = len(betas) replicas of M chains,
+    x [K*M, D] replica-major.  logp/g are each chain's tempered values (recomputed
+    if None).  Returns dict(x, logp, g, swapped)."""
+    betas = list(betas)
+    K = len(betas)
+    x = _f64(x).copy()
+    C, D = x.shape
+    M = C // K
+    tgs, arr = _replica_targets(tg, betas)
+    if logp is None or g is None:
+        logp = np.empty(C)
+        g = np.empty_like(x)
+        for c in range(C):
+            logp[c] = lib().orc_logp_grad(tgs[c // M].c, _p(x[c]), _p(g[c]))
+    logp = _f64(logp).copy()
+    g = _f64(g).copy()
+    sw = np.empty(C, dtype=np.uint8)
+    lib().orc_remc_swap(arr, K, M, seed, t, _p(x), _p(logp), _p(g), _p(sw, _u8p))
+    return dict(x=x, logp=logp, g=g, swapped=sw.astype(bool))
+
+
+def remc_sample_chain(tg: Target, betas, L: int, seed: int, x0, eps0, num_burnin: int, num_results: int,
+                      adapt: bool = False, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75,
+                      t_begin: int = 0, store_samples: bool = True, nthreads: int = 0):
+    """Oracle replica-exchange sample_chain.  x0 [K*M, D] replica-major.
+    Returns dict(samples [R, K*M, D] (post-exchange states), is_accepted, swapped
+    [R, K*M], final_x, final_eps)."""
+    betas = list(betas)
+    K = len(betas)
+    x = _f64(x0).copy()
+    C, D = x.shape
+    assert C % K == 0
+    M = C // K
+    eps = np.broadcast_to(_f64(eps0), (C,)).copy()
+    R = num_results
+    tgs, arr = _replica_targets(tg, betas)
+    samples = np.empty((R, C, D)) if store_samples else None
+    acc = np.empty((R, C), dtype=np.uint8)
+    sw = np.empty((R, C), dtype=np.uint8)
+    lib().orc_remc_sample_chain(arr, K, M, L, seed, t_begin, _p(x), _p(eps), num_burnin, num_results,
+                                1 if adapt else 0, target_accept, gamma, t0, kappa, _p(samples),
+                                _p(acc, _u8p), _p(sw, _u8p), nthreads)
+    return dict(samples=samples, is_accepted=acc.astype(bool), swapped=sw.astype(bool), final_x=x,
+                final_eps=eps)

@@ -90,13 +90,18 @@ void orc_momentum(uint64_t seed, uint32_t chain, uint32_t t, int64_t D, double *
 }
 
 /* Uniform in (0,1) with 52 random bits: (k + 1/2) / 2^52, k from the top
- * 26 bits of the first two words of the block (chain, t, 0, ACCEPT). */
-double orc_accept_uniform(uint64_t seed, uint32_t chain, uint32_t t)
+ * 26 bits of the first two words of the block (chain, t, 0, tag). */
+static double uniform52(uint64_t seed, uint32_t chain, uint32_t t, uint32_t tag)
 {
     uint32_t w[4];
-    philox_block(seed, chain, t, 0, ORC_TAG_ACCEPT, w);
+    philox_block(seed, chain, t, 0, tag, w);
     double k = (double)(w[0] >> 6) * 67108864.0 + (double)(w[1] >> 6);
     return (k + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+double orc_accept_uniform(uint64_t seed, uint32_t chain, uint32_t t)
+{
+    return uniform52(seed, chain, t, ORC_TAG_ACCEPT);
 }
 
 void orc_philox_many(int64_t n, const uint32_t *ctr, const uint32_t key[2], uint32_t *out)
@@ -188,6 +193,12 @@ double orc_logp_grad(const orc_target *tg, const double *x, double *g)
     }
     default:
         logp = NAN;
+    }
+    /* tempered target (replica exchange, paper Sec. 3.1): beta * logp */
+    if (tg->beta != 1.0) {
+        logp *= tg->beta;
+        for (int64_t i = 0; i < D; ++i)
+            g[i] *= tg->beta;
     }
     return logp;
 }
@@ -380,5 +391,94 @@ int orc_sample_chain(const orc_target *tg, int64_t C, int32_t L, uint64_t seed,
         eps[c] = step;
         free(gc);
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Replica exchange (paper Sec. 3.1): replica k targets p(x)^beta_k; the
+ * exchange of the states x_a (replica a) and x_b (replica b) is a
+ * Metropolis-Hastings move on the product of the replica targets, with ratio
+ *   p(x_b)^beta_a p(x_a)^beta_b / (p(x_a)^beta_a p(x_b)^beta_b)
+ *   = exp((beta_a - beta_b) (l(x_b) - l(x_a))).
+ * ---------------------------------------------------------------------- */
+void orc_remc_swap(const orc_target *tgs, int64_t K, int64_t M, uint64_t seed, uint32_t t,
+                   double *x, double *logp, double *g, uint8_t *swapped)
+{
+    const int64_t D = tgs[0].dim;
+    orc_target base = tgs[0];
+    base.beta = 1.0;
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)D);
+    if (swapped)
+        memset(swapped, 0, (size_t)(K * M));
+    for (int64_t k = (int64_t)(t % 2); k + 1 < K; k += 2) {
+        for (int64_t m = 0; m < M; ++m) {
+            const int64_t a = k * M + m, b = (k + 1) * M + m;
+            double la = orc_logp_grad(&base, x + a * D, tmp);   /* untempered l(x_a) */
+            double lb = orc_logp_grad(&base, x + b * D, tmp);
+            double log_ratio = (tgs[k].beta - tgs[k + 1].beta) * (lb - la);
+            double u = uniform52(seed, (uint32_t)a, t, ORC_TAG_SWAP);
+            if (!(log(u) < log_ratio))
+                continue;   /* rejected (also when the ratio is NaN) */
+            for (int64_t i = 0; i < D; ++i) {
+                double v = x[a * D + i];
+                x[a * D + i] = x[b * D + i];
+                x[b * D + i] = v;
+            }
+            /* each chain's cached values belong to its own replica's target */
+            logp[a] = orc_logp_grad(&tgs[k], x + a * D, g + a * D);
+            logp[b] = orc_logp_grad(&tgs[k + 1], x + b * D, g + b * D);
+            if (swapped)
+                swapped[a] = swapped[b] = 1;
+        }
+    }
+    free(tmp);
+}
+
+int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L, uint64_t seed,
+                          uint32_t t_begin, double *x, double *eps, int64_t num_burnin,
+                          int64_t num_results, int32_t adapt, double target_accept, double gamma,
+                          double t0, double kappa, double *samples, uint8_t *tr_acc,
+                          uint8_t *tr_swap, int32_t nthreads)
+{
+    const int64_t D = tgs[0].dim, C = K * M;
+    double *logp = (double *)malloc(sizeof(double) * (size_t)C);
+    double *g = (double *)malloc(sizeof(double) * (size_t)(C * D));
+    orc_dual_avg *da = (orc_dual_avg *)malloc(sizeof(orc_dual_avg) * (size_t)C);
+    uint8_t *acc = (uint8_t *)malloc((size_t)C);
+    uint8_t *swp = (uint8_t *)malloc((size_t)C);
+    set_threads(nthreads);
+    for (int64_t c = 0; c < C; ++c) {   /* bootstrap on each chain's own replica */
+        logp[c] = orc_logp_grad(&tgs[c / M], x + c * D, g + c * D);
+        orc_dual_avg_init(&da[c], eps[c]);
+    }
+    for (int64_t i = 0; i < num_burnin + num_results; ++i) {
+        const uint32_t t = t_begin + (uint32_t)i;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t c = 0; c < C; ++c) {
+            double lar;
+            acc[c] = (uint8_t)orc_transition(&tgs[c / M], seed, (uint32_t)c, t, L, eps[c], x + c * D,
+                                             &logp[c], g + c * D, NULL, NULL, NULL, NULL, &lar);
+            if (adapt && i < num_burnin) {
+                double alpha = lar < 0.0 ? exp(lar) : 1.0;
+                orc_dual_avg_update(&da[c], i + 1, alpha, target_accept, gamma, t0, kappa);
+                eps[c] = (i + 1 < num_burnin) ? exp(da[c].log_eps) : exp(da[c].log_eps_bar);
+            }
+        }
+        orc_remc_swap(tgs, K, M, seed, t, x, logp, g, swp);
+        if (i >= num_burnin) {
+            const int64_t r = i - num_burnin;
+            if (samples)
+                memcpy(samples + r * C * D, x, sizeof(double) * (size_t)(C * D));
+            if (tr_acc)
+                memcpy(tr_acc + r * C, acc, (size_t)C);
+            if (tr_swap)
+                memcpy(tr_swap + r * C, swp, (size_t)C);
+        }
+    }
+    free(logp);
+    free(g);
+    free(da);
+    free(acc);
+    free(swp);
     return 0;
 }

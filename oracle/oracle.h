@@ -42,7 +42,7 @@ extern "C" {
 #endif
 
 enum { ORC_STD_NORMAL = 0, ORC_GAUSS_DIAG = 1, ORC_GAUSS_DENSE = 2, ORC_LOGREG = 3 };
-enum { ORC_TAG_MOMENTUM = 0, ORC_TAG_ACCEPT = 1 };
+enum { ORC_TAG_MOMENTUM = 0, ORC_TAG_ACCEPT = 1, ORC_TAG_SWAP = 2 };
 
 typedef struct {
     int32_t kind;          /* ORC_* target family */
@@ -53,6 +53,9 @@ typedef struct {
     const double *y;       /* LOGREG: [N] labels in {0, 1} */
     int64_t n_rows;        /* LOGREG: N */
     double prior_scale;    /* LOGREG: prior N(0, prior_scale^2 I) */
+    double beta;           /* inverse temperature: the log-probability and its
+                              gradient are multiplied by beta (1 = untempered;
+                              replica exchange, paper Sec. 3.1) */
 } orc_target;
 
 /* Philox4x32-10 block function (SC'11, Sec. 3.2): 10 rounds, key bumped
@@ -129,6 +132,37 @@ int orc_sample_chain(const orc_target *tg, int64_t C, int32_t L, uint64_t seed,
                      int32_t adapt, double target_accept, double gamma, double t0, double kappa,
                      double *samples, double *tr_step, uint8_t *tr_acc, double *tr_lar,
                      double *tr_logp, int32_t nthreads);
+
+/* ---- Replica exchange Monte Carlo (paper Sec. 3.1, case study REMC) ----
+ * K replicas of M chains each, replica-major: chain c = k*M + m is chain m of
+ * replica k, whose target is tgs[k] (the same target with inverse temperature
+ * beta_k; replica k's log-probability is beta_k times the target's).
+ *
+ * orc_remc_swap: the exchange step with swap index t.  The pairs (k, k+1)
+ * with k = (t mod 2), (t mod 2) + 2, ... (k + 1 < K) exchange the states of
+ * their chain m with probability min(1, exp((beta_k - beta_{k+1}) (l(x_{k+1,m})
+ * - l(x_{k,m})))), l the untempered log-probability: accept iff
+ * log u < that exponent, u the 52-bit uniform of block (k*M + m, t, 0, SWAP).
+ * x [K*M*D], logp [K*M] and g [K*M*D] are each chain's state with the
+ * log-probability and gradient of its own replica's target; after an
+ * exchange both are recomputed for the chain's replica.  swapped [K*M]
+ * (may be NULL) gets 1 for both chains of an exchanged pair, 0 elsewhere. */
+void orc_remc_swap(const orc_target *tgs, int64_t K, int64_t M, uint64_t seed, uint32_t t,
+                   double *x, double *logp, double *g, uint8_t *swapped);
+
+/* REMC driver: transitions t_begin .. t_begin + burnin + results - 1; each is
+ * one HMC transition of every chain on its replica's target (chain c uses
+ * tgs[c / M], step eps[c], the counters of chain c) followed by the exchange
+ * step with swap index t.  Dual averaging (adapt != 0) works per chain on
+ * the burn-in as in orc_sample_chain; step sizes stay with the chain slot.
+ * samples [R*C*D] hold the states after the exchange of transition
+ * burnin + r; tr_acc [R*C] the HMC accept flags, tr_swap [R*C] the exchange
+ * flags (each may be NULL).  x and eps hold the final state / step sizes. */
+int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L, uint64_t seed,
+                          uint32_t t_begin, double *x, double *eps, int64_t num_burnin,
+                          int64_t num_results, int32_t adapt, double target_accept, double gamma,
+                          double t0, double kappa, double *samples, uint8_t *tr_acc,
+                          uint8_t *tr_swap, int32_t nthreads);
 
 #ifdef __cplusplus
 }
