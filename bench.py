@@ -140,6 +140,86 @@ def ess_run(s, w, x0, eps0, n_results, num_burnin, chunk_s=20.0, per_tr=None):
             "ess_per_sec": summ["min_ess_bulk"] / dt if summ["max_rhat"] <= 1.01 else None}
 
 
+def bench_remc(args):
+    """Replica exchange (paper Sec. 3.1) on a workload: its chains split into
+    K replicas on a geometric inverse-temperature ladder 1 .. beta_min; one
+    run of burn-in + results REMC steps (a transition of every chain, then an
+    exchange step) on the plain kernels, timed with HIP events."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2002_01184_amd import diagnostics as dg
+    from paper_2002_01184_amd import hmc
+
+    w = W.CONFIGS[args.config]()
+    K = args.remc
+    if w.num_chains % K:
+        raise SystemExit(f"--remc {K} must divide the {w.num_chains} chains of {args.config}")
+    if args.transitions is not None:
+        w.num_burnin = min(w.num_burnin, args.transitions // 2)
+        w.num_results = args.transitions - w.num_burnin
+    M = w.num_chains // K
+    betas = [args.remc_beta_min ** (k / max(K - 1, 1)) for k in range(K)]
+    form = hmc.HMC_FORM_GRAPH if args.form == "graph" else hmc.HMC_FORM_PLAIN
+    s = hmc.sampler_for(w, form=form, grad_bf16=args.grad == "bf16")
+    s.set_inverse_temperature(torch.tensor(np.repeat(betas, M), dtype=torch.float64, device="cuda"))
+    x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).cuda()
+    eps0 = torch.full((w.num_chains,), w.step_size, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run(ev=None):
+        s.set_state(x0, eps0, 0)
+        if ev is not None:
+            ev[0].record(stream)
+        out = s.remc_sample_chain(K, w.num_results, w.num_burnin, adapt=w.adapt)
+        if ev is not None:
+            ev[1].record(stream)
+        return out
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    out = None
+    for k in range(args.steps):
+        out = run(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    value = w.chain_steps() * args.steps / elapsed
+    bound, per_cs, unit = algorithmic_work(w)
+    achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
+    peak = PEAK["hbm"] if bound == "hbm" else (PEAK["bf16_mfma"] if args.grad == "bf16" else PEAK["fp32_mfma"])
+    scale = 1e9 if bound == "hbm" else 1e12
+    result = {
+        "metric": METRIC, "value": value, "unit": "leapfrog chain-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if w.state_dtype == "f64" else ("bf16/f32" if args.grad == "bf16" else "f32"),
+        "data": "synthetic (seeded; shapes of the paper's workloads)",
+        "config": {"workload": f"remc_{w.name}_K{K}", "num_chains": w.num_chains, "replicas": K,
+                   "inverse_temperatures": betas, "dim": w.dim, "n_rows": w.n_rows,
+                   "num_leapfrog_steps": w.num_leapfrog_steps, "num_burnin": w.num_burnin,
+                   "num_results": w.num_results, "adapt": "dual averaging to 0.8" if w.adapt else "none",
+                   "form": {hmc.HMC_FORM_PLAIN: "plain", hmc.HMC_FORM_GRAPH: "graph"}[hmc.hmc_effective_form(s.ctx)],
+                   "parallelism": "chains (1 GPU)"},
+        "roofline": {"bound": bound, "achieved": achieved / scale, "peak": peak / scale,
+                     "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": "plain kernels + exchange step", "kernel_ms_per_launch": kernel_ms,
+                     "work_per_launch": per_cs * w.chain_steps()},
+        "swap_rate": float(out["swapped"].float().mean().item()),
+        "accept_rate": float(out["is_accepted"].float().mean().item()),
+    }
+    if not args.no_diagnostics:
+        summ = dg.t_summarize(out["samples"][:, :M])     # the beta = 1 replica
+        result["max_rhat_beta1"] = summ["max_rhat"]
+        result["min_ess_bulk_beta1"] = summ["min_ess_bulk"]
+    s.close()
+    return result
+
+
 def bench_served(args):
     """Served stream: requests arrive by a seeded Poisson process; each is
     submitted to the continuous-batching server at its arrival time.  Reports
@@ -210,6 +290,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="run the library's autotuner before timing")
     ap.add_argument("--ess-results", type=int, default=9000,
                     help="kept draws of the separate ESS run (same burn-in); 0 skips it")
+    ap.add_argument("--remc", type=int, default=0,
+                    help="replica exchange with this many replicas (divides the workload's chains)")
+    ap.add_argument("--remc-beta-min", type=float, default=0.1, help="smallest inverse temperature of the ladder")
     ap.add_argument("--ess-seconds", type=float, default=60.0,
                     help="time budget of the separate ESS run (burn-in included)")
     ap.add_argument("--ess-gb", type=float, default=16.0, help="memory budget of its kept samples (GiB)")
@@ -230,6 +313,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.config == "served_stream":
         print(json.dumps(bench_served(args)), flush=True)
+        return
+    if args.remc > 0:
+        print(json.dumps(bench_remc(args)), flush=True)
         return
     if args.config == "copy_calibration":
         # a plain device-to-device copy of known size: the reference for scaling
@@ -288,6 +374,20 @@ def main():
         achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None}
+    elif hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED:
+        # the fused element-wise kernel keeps x, p, g on chip: its HBM bytes are
+        # the state read and written once per launch plus the kept samples and
+        # trace rows; its time goes to the random draws (Philox, Box-Muller) and
+        # the FP64 energy, so the HBM fraction it reports is small by design
+        es = 8 if w.state_dtype == "f64" else 4
+        per_chain = 2 * (2 * es * w.dim + 40) + w.num_results * (es * w.dim + 25)
+        moved = per_chain * w.num_chains
+        achieved = moved / (kernel_ms * 1e-3)
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK["hbm"], "traffic": None,
+                "note": "fused element-wise kernel: bytes it must move (state in/out, samples, traces); "
+                        "it is bound by the random draws and FP64 energy arithmetic, not by HBM"}
+        per_cs = moved / w.chain_steps()
     else:
         achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",

@@ -191,6 +191,48 @@ int32_t hmc_effective_form(const hmc_ctx* ctx);
 hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char* report, size_t report_len);
 
 /* ---------------------------------------------------------------------------
+ * Replica exchange Monte Carlo (paper Sec. 3.1, case study REMC).
+ *
+ * The chains of a context form K replicas of M = C / K chains, replica-major:
+ * chain c = k M + m is chain m of replica k.  Chain c targets beta_c logp(x)
+ * (the tempered target of the paper: the log-probability times the inverse
+ * temperature, by broadcasting); the replicas of one temperature ladder
+ * 1 = beta_0 > beta_1 > ... hold the same beta in all M chains.  Tempering
+ * runs on the plain and graph forms.
+ * ------------------------------------------------------------------------- */
+
+/* Sets per-chain inverse temperatures: beta (device, FP64, [C]) is copied;
+ * every value must be finite and > 0 (HMC_E_INVALID otherwise, nothing
+ * changed).  NULL restores beta = 1 for every chain.  A context of the
+ * fused form returns HMC_E_UNSUPPORTED (create it with HMC_FORM_PLAIN or
+ * HMC_FORM_GRAPH); the autotuner then keeps to the plain and graph forms.
+ * The cached log-probability, traced target_log_prob and the state stay those
+ * of the untempered target.  Synchronizes the stream. */
+hmc_status hmc_set_inverse_temperature(hmc_ctx* ctx, const double* beta);
+
+/* One exchange step with swap index t (< 2^32): for every m and every pair
+ * (k, k+1) with k = t mod 2, t mod 2 + 2, ..., k + 1 < K, the states of chains
+ * k M + m and (k+1) M + m are exchanged with probability
+ * min(1, exp((beta_k - beta_{k+1}) (logp(x_{k+1}) - logp(x_k)))): the
+ * Metropolis-Hastings test on the product of the replica targets, with the
+ * 52-bit uniform of the Philox block (k M + m, t, 0, tag 2).  Step sizes and
+ * adaptation state stay with the chain slot.  swapped (device [C], may be
+ * NULL) receives 1 for both chains of an exchanged pair and 0 elsewhere.
+ * HMC_E_INVALID if num_replicas does not divide C.  Asynchronous. */
+hmc_status hmc_remc_swap(hmc_ctx* ctx, int64_t num_replicas, uint64_t swap_index, uint8_t* swapped);
+
+/* Replica-exchange sample_chain: num_burnin + num_results times, one
+ * transition of every chain (as hmc_sample_chain, with the same adaptation
+ * and traces) followed by the exchange step whose swap index is that
+ * transition's t.  samples [R, C, D] (device, may be NULL) receive the states
+ * after the exchange of transition burnin + r; swapped (device [R, C], may be
+ * NULL) the exchange flags of the kept transitions; the trace rows hold the
+ * transition's results before the exchange.  Asynchronous. */
+hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num_results, int64_t num_burnin_steps,
+                                 const hmc_adapt* adapt, void* samples, const hmc_trace* trace,
+                                 uint8_t* swapped);
+
+/* ---------------------------------------------------------------------------
  * Serving: continuous batching of sampling requests (one sample_chain each)
  * of differing target, dimension, data size and chain count on one GPU.
  *

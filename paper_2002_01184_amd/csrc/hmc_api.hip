@@ -88,6 +88,8 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
     w.bk_eps = (double*)take((size_t)C * 8);
     w.bk_da = (DualAvg*)take((size_t)C * sizeof(DualAvg));
     w.ctrl = (Ctrl*)take(sizeof(Ctrl));
+    w.beta_buf = (double*)take((size_t)C * 8);
+    w.beta = nullptr;
     w.bytes = off;
     if (total) *total = off;
     return w;
@@ -514,7 +516,7 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache_locked();
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
+        if (it != g_tune_cache.end() && !(ctx->a.ws.beta && it->second.form == HMC_FORM_FUSED)) {
             ctx->form = it->second.form;
             ctx->a.tune = it->second.tune;
             drop_graph(ctx);
@@ -526,7 +528,7 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
     std::vector<TuneChoice> cands;
     std::vector<int32_t> forms;
     if (ctx->cfg.form == HMC_FORM_AUTO) {
-        if (fused_supported(ctx->a)) forms.push_back(HMC_FORM_FUSED);
+        if (fused_supported(ctx->a) && !ctx->a.ws.beta) forms.push_back(HMC_FORM_FUSED);   // tempered: plain kernels
         forms.push_back(HMC_FORM_PLAIN);
         forms.push_back(HMC_FORM_GRAPH);
     } else {
@@ -604,3 +606,107 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
     if (report && report_len) snprintf(report, report_len, "%s", rep.str().c_str());
     return st;
 }
+
+// ---------------------------------------------------------------------------
+// Replica exchange (paper Sec. 3.1): per-chain inverse temperatures on the
+// plain / graph forms, the exchange step, and the driver that alternates one
+// transition of every chain with one exchange step.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+hmc_status hmc_set_inverse_temperature(hmc_ctx* ctx, const double* beta) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (!beta) {
+        ctx->a.ws.beta = nullptr;
+        drop_graph(ctx);
+        return HMC_OK;
+    }
+    if (ctx->form == HMC_FORM_FUSED)
+        return fail(HMC_E_UNSUPPORTED,
+                    "inverse temperatures run on the plain or graph form: create the context with "
+                    "HMC_FORM_PLAIN or HMC_FORM_GRAPH");
+    std::vector<double> h((size_t)ctx->a.C);
+    hmc_status st = check_hip(hipMemcpyAsync(h.data(), beta, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream),
+                              "read inverse temperatures");
+    if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "read inverse temperatures");
+    if (st != HMC_OK) return st;
+    for (double b : h)
+        if (!(b > 0.0) || !std::isfinite(b)) return fail(HMC_E_INVALID, "inverse temperatures must be finite and > 0");
+    st = check_hip(hipMemcpyAsync(ctx->a.ws.beta_buf, h.data(), h.size() * 8, hipMemcpyHostToDevice, ctx->stream),
+                   "set inverse temperatures");
+    if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "set inverse temperatures");
+    if (st != HMC_OK) return st;
+    ctx->a.ws.beta = ctx->a.ws.beta_buf;
+    drop_graph(ctx);    // captured launches hold the workspace pointers by value
+    return HMC_OK;
+}
+
+static hmc_status remc_check(const hmc_ctx* ctx, int64_t num_replicas) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (num_replicas < 1 || ctx->a.C % num_replicas != 0)
+        return fail(HMC_E_INVALID, "num_replicas must be >= 1 and divide the number of chains");
+    if (ctx->form == HMC_FORM_FUSED)
+        return fail(HMC_E_UNSUPPORTED, "replica exchange runs on the plain or graph form");
+    return HMC_OK;
+}
+
+hmc_status hmc_remc_swap(hmc_ctx* ctx, int64_t num_replicas, uint64_t swap_index, uint8_t* swapped) {
+    hmc_status st = remc_check(ctx, num_replicas);
+    if (st != HMC_OK) return st;
+    if (swap_index > 0xffffffffull) return fail(HMC_E_INVALID, "swap_index must be < 2^32");
+    st = check_hip(launch_remc_swap(ctx->a, num_replicas, ctx->a.C / num_replicas, (uint32_t)swap_index,
+                                        swapped, ctx->stream), "exchange step");
+    return st;
+}
+
+hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num_results, int64_t num_burnin_steps,
+                                 const hmc_adapt* adapt, void* samples, const hmc_trace* trace,
+                                 uint8_t* swapped) {
+    hmc_status st = remc_check(ctx, num_replicas);
+    if (st != HMC_OK) return st;
+    if (num_results < 0 || num_burnin_steps < 0) return fail(HMC_E_INVALID, "negative transition count");
+    const bool ad = adapt && adapt->enabled;
+    if (ad && (!(adapt->target_accept > 0.0 && adapt->target_accept < 1.0) || !(adapt->gamma > 0.0) ||
+               !(adapt->t0 >= 0.0) || !(adapt->kappa > 0.0)))
+        return fail(HMC_E_INVALID, "adaptation parameters out of range");
+    const int64_t total = num_results + num_burnin_steps;
+    if (ctx->t + (uint64_t)total > 0xffffffffull) return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
+    const int64_t C = ctx->a.C, M = C / num_replicas;
+    const size_t row = (size_t)C * ctx->a.tg.D * (ctx->a.f64 ? 8 : 4);
+    hmc_trace tr;
+    memset(&tr, 0, sizeof(tr));
+    if (trace) tr = *trace;
+    if (ad) st = check_hip(launch_da_init(ctx->a, ctx->stream), "adaptation init");
+    // the transitions write the traces; the samples are taken after each exchange
+    Ctrl c = base_ctrl(ctx);
+    c.n_burnin = num_burnin_steps;
+    c.n_results = num_results;
+    c.adapt = ad;
+    if (ad) {
+        c.target_accept = adapt->target_accept;
+        c.gamma = adapt->gamma;
+        c.t0 = adapt->t0;
+        c.kappa = adapt->kappa;
+    }
+    c.samples = nullptr;
+    c.tr_step = tr.step_size;
+    c.tr_acc = tr.is_accepted;
+    c.tr_lar = tr.log_accept_ratio;
+    c.tr_logp = tr.target_log_prob;
+    if (st == HMC_OK) st = check_hip(launch_set_ctrl(c, ctx->a.ws.ctrl, ctx->stream), "remc control");
+    for (int64_t i = 0; i < total && st == HMC_OK; ++i) {
+        const uint64_t t = ctx->t + (uint64_t)i;
+        const bool kept = i >= num_burnin_steps;
+        uint8_t* sw = (kept && swapped) ? swapped + (size_t)(i - num_burnin_steps) * C : nullptr;
+        st = run_transitions(ctx, 1, false);
+        if (st == HMC_OK)
+            st = check_hip(launch_remc_swap(ctx->a, num_replicas, M, (uint32_t)t, sw, ctx->stream), "exchange step");
+        if (st == HMC_OK && kept && samples)
+            st = check_hip(hipMemcpyAsync((char*)samples + (size_t)(i - num_burnin_steps) * row, ctx->a.ws.x, row,
+                                          hipMemcpyDeviceToDevice, ctx->stream), "sample copy");
+    }
+    if (st == HMC_OK) ctx->t += (uint64_t)total;
+    return st;
+}
+
+}  // extern "C"

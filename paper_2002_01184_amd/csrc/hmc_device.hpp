@@ -42,7 +42,7 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return make_uint4(c0, c1, c2, c3);
 }
 
-enum : uint32_t { TAG_MOMENTUM = 0, TAG_ACCEPT = 1 };
+enum : uint32_t { TAG_MOMENTUM = 0, TAG_ACCEPT = 1, TAG_SWAP = 2 };
 
 // (k + 1/2) 2^-23 with k the top 23 bits: exact in binary32 and binary64.
 __device__ __forceinline__ float u23_f32(uint32_t w) {
@@ -70,18 +70,33 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& z0,
 }
 
 // Four momenta of chain c at transition t for dimensions 4*block .. 4*block+3.
+// need_hi = false when dimensions 4*block+2 and +3 lie beyond D: the second
+// Box-Muller pair is then not evaluated (its values would be discarded; the
+// first pair does not depend on it) and z[2], z[3] are set to 0.
 template <typename T>
-__device__ __forceinline__ void momentum4(Key key, uint32_t chain, uint32_t t, uint32_t block, T z[4]) {
+__device__ __forceinline__ void momentum4(Key key, uint32_t chain, uint32_t t, uint32_t block, T z[4],
+                                          bool need_hi = true) {
     const uint4 w = philox(chain, t, block, TAG_MOMENTUM, key);
     box_muller(w.x, w.y, z[0], z[1]);
-    box_muller(w.z, w.w, z[2], z[3]);
+    if (need_hi) {
+        asm volatile("" ::: );   // keeps the pair behind the branch (not computed and selected)
+        box_muller(w.z, w.w, z[2], z[3]);
+    } else {
+        z[2] = (T)0;
+        z[3] = (T)0;
+    }
 }
 
-// log of the accept uniform ((w0>>6) 2^26 + (w1>>6) + 1/2) 2^-52, in FP64.
-__device__ __forceinline__ double log_accept_uniform(Key key, uint32_t chain, uint32_t t) {
-    const uint4 w = philox(chain, t, 0u, TAG_ACCEPT, key);
+// log of the uniform ((w0>>6) 2^26 + (w1>>6) + 1/2) 2^-52 of block
+// (chain, t, 0, tag), in FP64: the Metropolis test (tag ACCEPT) and the
+// replica-exchange test (tag SWAP).
+__device__ __forceinline__ double log_uniform52(Key key, uint32_t chain, uint32_t t, uint32_t tag) {
+    const uint4 w = philox(chain, t, 0u, tag, key);
     const double k = (double)(w.x >> 6) * 67108864.0 + (double)(w.y >> 6);
     return log((k + 0.5) * 0x1p-52);
+}
+__device__ __forceinline__ double log_accept_uniform(Key key, uint32_t chain, uint32_t t) {
+    return log_uniform52(key, chain, t, TAG_ACCEPT);
 }
 
 // ---------------------------------------------------------------------------

@@ -45,6 +45,8 @@ struct Workspace {
     double* bk_eps;
     DualAvg* bk_da;
     Ctrl* ctrl;
+    double* beta_buf;  // [C] inverse temperatures (replica exchange)
+    double* beta;      // beta_buf once temperatures are set, else NULL (every chain at beta = 1)
     size_t bytes;
 };
 
@@ -82,6 +84,9 @@ hipError_t launch_set_ctrl(const Ctrl& c, Ctrl* dst, hipStream_t s);
 hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s);
 hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipStream_t s);
 hipError_t launch_da_init(const PlainArgs& a, hipStream_t s);
+// Replica exchange step (K replicas of M chains, replica-major) with swap index t.
+hipError_t launch_remc_swap(const PlainArgs& a, int64_t K, int64_t M, uint32_t t, uint8_t* swapped,
+                            hipStream_t s);
 
 // ---- BF16 gradients (k_logreg_bf16.hip) -------------------------------------
 hipError_t launch_transpose_bf16(const PlainArgs& a, void* Xt, hipStream_t s);

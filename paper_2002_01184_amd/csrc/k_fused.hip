@@ -89,7 +89,8 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             T z[4];
-            momentum4<T>(a.key, (uint32_t)cc, t, (uint32_t)(lane + G * k), z);
+            momentum4<T>(a.key, (uint32_t)cc, t, (uint32_t)(lane + G * k), z,
+                         4 * (lane + (int64_t)G * k) + 2 < D);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const T p0 = ok[k][j] ? z[j] : (T)0;
@@ -197,29 +198,44 @@ __global__ __launch_bounds__(256) void k_fused_elem_multi(const ElemJob* __restr
 // owns M-tiles w, w + NW, ...; lane (g4 = lane/16, i16 = lane%16) holds rows
 // 16 mt + 4 g4 + v (v = 0..3) of chain i16 -- exactly the 4 dims of Philox
 // block 4 mt + g4, so each lane draws its own momenta.
+//
+// NT = ceil(D / 16) tiles is a template parameter, so the contraction over
+// the 4 NT k-steps is fully unrolled with no guards: P is zero-padded in the
+// A operands and rows D .. 16 NT of x stay exactly zero, so the padding adds
+// zeros.  Every wave runs MT tiles (a wave's tiles past NT multiply zeros on
+// its own SIMD while the other SIMDs finish theirs), and each tile keeps two
+// accumulators (even / odd k-steps) so that consecutive MFMAs are independent.
+//
+// The contraction index is assigned as k = g4 KM + ks (lane group g4 supplies
+// dims g4 KM .. g4 KM + KM - 1 over the k-steps ks), so with x staged chain-
+// major in LDS ([16 chains][16 NT + 4], the pad making the 16 chains of a
+// lane group hit distinct bank quads) each lane fetches the B operands of 4
+// consecutive k-steps with one ds_read_b128 and writes its own 4 dims of a
+// tile with one ds_write_b128.
 // ---------------------------------------------------------------------------
 constexpr int DENSE_NW = 4;
 
-template <int MT, int KM>
+template <int NT>
 __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
+    constexpr int MT = (NT + DENSE_NW - 1) / DENSE_NW;
+    constexpr int KM = 4 * NT;
     extern __shared__ float lds[];
     const int64_t D = a.tg.D;
-    const int ntiles = (int)((D + 15) / 16);
-    const int K4 = (int)((D + 3) / 4);
+    const int ntiles = NT;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i16 = lane & 15, g4 = lane >> 4;
     const int64_t c = (int64_t)blockIdx.x * 16 + i16;
     const bool cvalid = c < a.C;
     const int64_t cc = cvalid ? c : 0;
-    const int rows_lds = 16 * ntiles;
-    float* xs0 = lds;                               // [rows_lds][17] x 2 buffers
-    float* xs1 = lds + rows_lds * 17;
-    double* red = (double*)(lds + 2 * rows_lds * 17);   // [2][NW][16] (dk, lp)
+    constexpr int XS = 16 * NT + 4;                 // floats per chain row in LDS
+    float* xs0 = lds;                               // [16][XS] x 2 buffers
+    float* xs1 = lds + 16 * XS;
+    double* red = (double*)(lds + 2 * 16 * XS);     // [2][NW][16] (dk, lp)
     const float* P = (const float*)a.tg.prec;
     float* X = (float*)a.ws.x;
     float* Gr = (float*)a.ws.g;
 
-    // P as A operands: pa[m][ks] = P[16 mt + i16][4 ks + g4]
+    // P as A operands: pa[m][ks] = P[16 mt + i16][g4 KM + ks]
     float pa[MT][KM];
     bool tile_ok[MT];
 #pragma unroll
@@ -229,8 +245,8 @@ __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
         const int64_t row = 16 * mt + i16;
 #pragma unroll
         for (int ks = 0; ks < KM; ++ks) {
-            const int64_t col = 4 * ks + g4;
-            pa[m][ks] = (tile_ok[m] && row < D && col < D && ks < K4) ? P[row * D + col] : 0.f;
+            const int64_t col = (int64_t)g4 * KM + ks;
+            pa[m][ks] = (tile_ok[m] && row < D && col < D) ? P[row * D + col] : 0.f;
         }
     }
     float x[MT][4], g[MT][4];
@@ -273,31 +289,39 @@ __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
             float* xs = buf ? xs1 : xs0;
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
-                if (!tile_ok[m]) continue;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    xn[m][v] = fmaf(eps, pn[m][v], xn[m][v]);
-                    xs[(16 * (w + DENSE_NW * m) + 4 * g4 + v) * 17 + i16] = xn[m][v];
-                }
+                for (int v = 0; v < 4; ++v) xn[m][v] = fmaf(eps, pn[m][v], xn[m][v]);
+                if (tile_ok[m])
+                    *(floatx4*)(xs + i16 * XS + 16 * (w + DENSE_NW * m) + 4 * g4) =
+                        floatx4{xn[m][0], xn[m][1], xn[m][2], xn[m][3]};
             }
             __syncthreads();
+            floatx4 bq[NT];
+#pragma unroll
+            for (int q = 0; q < NT; ++q) bq[q] = *(const floatx4*)(xs + i16 * XS + g4 * KM + 4 * q);
+            floatx4 acc[MT][2];
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
-                if (!tile_ok[m]) continue;
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                acc[m][0] = floatx4{0.f, 0.f, 0.f, 0.f};
+                acc[m][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
 #pragma unroll
-                for (int ks = 0; ks < KM; ++ks) {
-                    if (ks < K4) {
-                        const float bv = xs[(4 * ks + g4) * 17 + i16];
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[m][ks], bv, acc, 0, 0, 0);
-                    }
-                }
+            for (int ks = 0; ks < KM; ++ks) {
+                const float bv = bq[ks >> 2][ks & 3];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    acc[m][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[m][ks], bv, acc[m][ks & 1], 0, 0, 0);
+            }
+            // all operand reads first (one LDS latency per step), then the MFMAs
+            __builtin_amdgcn_sched_group_barrier(0x100, NT, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, KM * MT, 0);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    gn[m][v] = -acc[v];
+                    gn[m][v] = -(acc[m][0][v] + acc[m][1][v]);
                     pn[m][v] = fmaf(ke, gn[m][v], pn[m][v]);
                 }
-            }
             buf ^= 1;
         }
         double lp = 0.0;
@@ -474,10 +498,16 @@ hipError_t launch_fused_elem_multi(int cls, const ElemJob* jobs_dev, int njobs, 
 
 static hipError_t launch_dense_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     const int ntiles = (int)((a.tg.D + 15) / 16);
-    const size_t lds = (size_t)2 * 16 * ntiles * 17 * sizeof(float) + 2 * 2 * DENSE_NW * 16 * sizeof(double);
+    const size_t lds = (size_t)2 * 16 * (16 * ntiles + 4) * sizeof(float) + 2 * 2 * DENSE_NW * 16 * sizeof(double);
     const dim3 grid((unsigned)((a.C + 15) / 16));
-    if (ntiles <= 4) hipLaunchKernelGGL((k_fused_dense<1, 16>), grid, dim3(256), lds, s, a, r);
-    else hipLaunchKernelGGL((k_fused_dense<2, 32>), grid, dim3(256), lds, s, a, r);
+    switch (ntiles) {
+#define HMC_DENSE_NT(N) \
+    case N: hipLaunchKernelGGL((k_fused_dense<N>), grid, dim3(256), lds, s, a, r); break;
+        HMC_DENSE_NT(1) HMC_DENSE_NT(2) HMC_DENSE_NT(3) HMC_DENSE_NT(4)
+        HMC_DENSE_NT(5) HMC_DENSE_NT(6) HMC_DENSE_NT(7) HMC_DENSE_NT(8)
+#undef HMC_DENSE_NT
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -6,6 +6,13 @@
 //   k_end         energy at the trajectory end, dH, Metropolis test,
 //                 per-chain select, dual averaging, sample/trace writes  (Sec. 2.1, 4.2)
 //   k_tick        t += 1 (device-resident, so a captured graph replays unchanged)
+//   k_remc_swap   replica exchange between neighbouring temperatures (Sec. 3.1)
+//
+// Inverse temperatures (replica exchange): chain c targets beta_c logp.  The
+// cached logp and gradient stay those of the untempered target; beta_c
+// multiplies the gradient in every kick and logp in both energies, so the
+// exchange step moves states without recomputing anything.  With no
+// temperatures set (ws.beta == NULL) every factor is exactly 1.
 //
 // Gradient kernels:
 //   elementwise   N(0, I) and diagonal Gaussians: one thread per (chain, dim)
@@ -42,13 +49,14 @@ __global__ __launch_bounds__(256) void k_begin(PlainArgs a) {
     const T* g = (const T*)a.ws.g;
     T* xq = (T*)a.ws.xq;
     T* pq = (T*)a.ws.pq;
-    const T half_eps = active ? (T)(0.5 * a.ws.eps[c]) : (T)0;
+    const double bt = (active && a.ws.beta) ? a.ws.beta[c] : 1.0;
+    const T half_eps = active ? (T)(0.5 * a.ws.eps[c] * bt) : (T)0;
     double k0 = 0.0;
     const int64_t nblk = (D + 3) / 4;
     if (active) {
         for (int64_t b = lane; b < nblk; b += G) {
             T z[4];
-            momentum4<T>(a.key, (uint32_t)c, t, (uint32_t)b, z);
+            momentum4<T>(a.key, (uint32_t)c, t, (uint32_t)b, z, 4 * b + 2 < D);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t d = 4 * b + j;
@@ -62,7 +70,7 @@ __global__ __launch_bounds__(256) void k_begin(PlainArgs a) {
         }
     }
     k0 = group_sum<G>(k0);
-    if (active && lane == 0) a.ws.h0[c] = -a.ws.logp[c] + k0;
+    if (active && lane == 0) a.ws.h0[c] = -(bt * a.ws.logp[c]) + k0;
 }
 
 // logp at (x, g) from the closed form that remains after the gradient kernel:
@@ -123,7 +131,8 @@ __global__ __launch_bounds__(256) void k_end(PlainArgs a) {
     const double lp1 = chain_logp<T, G>(a, c, active, xq, gq, lane);
     if (!active) return;
 
-    const double dh = (-lp1 + k1) - a.ws.h0[c];
+    const double bt = a.ws.beta ? a.ws.beta[c] : 1.0;
+    const double dh = (-(bt * lp1) + k1) - a.ws.h0[c];
     const double lar = log_accept_ratio_of(dh);
     const bool acc = log_accept_uniform(a.key, (uint32_t)c, (uint32_t)t) < lar;
 
@@ -176,6 +185,45 @@ __global__ __launch_bounds__(256) void k_copy_proposal(PlainArgs a) {
     }
 }
 
+// Replica exchange (Sec. 3.1): chain c = k M + m is chain m of replica k.  One
+// wavefront per pair (k, k+1) of the parity class of t: it exchanges the
+// states (x, g, logp) of chains k M + m and (k+1) M + m with probability
+// min(1, exp((beta_k - beta_{k+1}) (logp_{k+1} - logp_k))) (untempered logp),
+// testing log u < that exponent with the 52-bit uniform of block
+// (k M + m, t, 0, SWAP).  Step sizes and adaptation state stay with the slot.
+template <typename T>
+__global__ __launch_bounds__(256) void k_remc_swap(PlainArgs a, int64_t M, int64_t npairs, int32_t parity,
+                                                   uint32_t t, uint8_t* swapped) {
+    const int64_t pair = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (pair >= npairs * M) return;
+    const int64_t k = parity + 2 * (pair / M), m = pair % M;
+    const int64_t ca = k * M + m, cb = (k + 1) * M + m;
+    const double ba = a.ws.beta ? a.ws.beta[ca] : 1.0, bb = a.ws.beta ? a.ws.beta[cb] : 1.0;
+    const double la = a.ws.logp[ca], lb = a.ws.logp[cb];
+    const bool acc = log_uniform52(a.key, (uint32_t)ca, t, TAG_SWAP) < (ba - bb) * (lb - la);
+    if (swapped && lane == 0) {
+        swapped[ca] = acc ? 1 : 0;
+        swapped[cb] = acc ? 1 : 0;
+    }
+    if (!acc) return;
+    const int64_t D = a.tg.D;
+    T* x = (T*)a.ws.x;
+    T* g = (T*)a.ws.g;
+    for (int64_t d = lane; d < D; d += 64) {
+        const T xa = x[ca * D + d], xb = x[cb * D + d];
+        x[ca * D + d] = xb;
+        x[cb * D + d] = xa;
+        const T ga = g[ca * D + d], gb = g[cb * D + d];
+        g[ca * D + d] = gb;
+        g[cb * D + d] = ga;
+    }
+    if (lane == 0) {
+        a.ws.logp[ca] = lb;
+        a.ws.logp[cb] = la;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_da_init(PlainArgs a) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -206,7 +254,7 @@ __global__ __launch_bounds__(256) void k_elem_leapfrog(PlainArgs a, const T* __r
         T p = (mode & 3) ? pd[i] : (T)0;
         if (mode & 1) x = fma(eps, p, x);
         const T gv = diag ? -prec[i - c * D] * x : -x;
-        if (mode & 2) p = fma((T)(kick_scale * a.ws.eps[c]), gv, p);
+        if (mode & 2) p = fma((T)(kick_scale * a.ws.eps[c] * (a.ws.beta ? a.ws.beta[c] : 1.0)), gv, p);
         if (mode & 1) xd[i] = x;
         if (mode & 2) pd[i] = p;
         if (gd) gd[i] = gv;
@@ -233,7 +281,7 @@ __global__ __launch_bounds__(256) void k_dense_leapfrog(PlainArgs a, const float
     const bool cvalid = c < a.C;
     const float* P = (const float*)a.tg.prec;
     const float eps = cvalid ? (float)a.ws.eps[c] : 0.f;
-    const float keps = cvalid ? (float)(kick_scale * a.ws.eps[c]) : 0.f;
+    const float keps = cvalid ? (float)(kick_scale * a.ws.eps[c] * (a.ws.beta ? a.ws.beta[c] : 1.0)) : 0.f;
     float* xs = lds;   // [16 * ntiles][17]
 
     float xr[MT][4], pr[MT][4];
@@ -253,24 +301,28 @@ __global__ __launch_bounds__(256) void k_dense_leapfrog(PlainArgs a, const float
         }
     }
     __syncthreads();
-    const int K4 = (int)((D + 3) / 4);
+    const int KM = 4 * ntiles;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         const int mt = w + 4 * m;
         if (mt >= ntiles) break;
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        // k-step ks, lane group g4 takes dim g4 KM + ks, with KM = 4 ntiles; even
+        // and odd k-steps in two accumulators: the same MFMA sequence as the
+        // fused kernel, so both forms give bitwise the same gradient
+        floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
         const int64_t row = 16 * mt + i16;
-        for (int ks = 0; ks < K4; ++ks) {
-            const int64_t col = 4 * ks + g4;
-            const float av = (row < D && col < D) ? P[row * D + col] : 0.f;
-            const float bv = xs[(4 * ks + g4) * 17 + i16];
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        for (int ks = 0; ks < KM; ks += 2) {
+            const int64_t col = (int64_t)g4 * KM + ks;
+            const float av0 = (row < D && col < D) ? P[row * D + col] : 0.f;
+            const float av1 = (row < D && col + 1 < D) ? P[row * D + col + 1] : 0.f;
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av0, xs[col * 17 + i16], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av1, xs[(col + 1) * 17 + i16], acc1, 0, 0, 0);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t d = 16 * mt + 4 * g4 + v;
             if (!(d < D && cvalid)) continue;
-            const float gv = -acc[v];
+            const float gv = -(acc0[v] + acc1[v]);
             if (mode & 1) xdst[c * D + d] = xr[m][v];
             if (mode & 2) pd[c * D + d] = fmaf(keps, gv, pr[m][v]);
             if (gd) gd[c * D + d] = gv;
@@ -424,7 +476,7 @@ __global__ __launch_bounds__(256) void k_logreg_finish(PlainArgs a, float* __res
         float gsum = 0.f;
         for (int s = 0; s < nsplit; ++s) gsum += a.ws.part_g[(int64_t)s * n + i];
         const float gv = gsum - x * (float)a.tg.inv_var;
-        if (kick) pd[i] = fmaf((float)(kick_scale * a.ws.eps[c]), gv, p);
+        if (kick) pd[i] = fmaf((float)(kick_scale * a.ws.eps[c] * (a.ws.beta ? a.ws.beta[c] : 1.0)), gv, p);
         if (gd) gd[i] = gv;
         if (want_logp && i - c * D == 0) {
             double l = 0.0;
@@ -553,6 +605,26 @@ hipError_t launch_set_ctrl(const Ctrl& c, Ctrl* dst, hipStream_t s) {
 
 hipError_t launch_da_init(const PlainArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_da_init<float>, dim3((unsigned)((a.C + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ void k_clear_u8(uint8_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_remc_swap(const PlainArgs& a, int64_t K, int64_t M, uint32_t t, uint8_t* swapped,
+                            hipStream_t s) {
+    // flags of chains outside this step's pairs are 0 (a fill kernel, so the
+    // sequence stays valid inside a captured graph)
+    if (swapped) hipLaunchKernelGGL(k_clear_u8, dim3((unsigned)((a.C + 255) / 256 < 1024 ? (a.C + 255) / 256 : 1024)),
+                                    dim3(256), 0, s, swapped, a.C);
+    const int32_t parity = (int32_t)(t & 1u);
+    const int64_t npairs = (K - parity) / 2;      // k = parity, parity + 2, ... with k + 1 < K
+    if (npairs <= 0 || M <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((npairs * M + 3) / 4));
+    if (a.f64) hipLaunchKernelGGL(k_remc_swap<double>, grid, dim3(256), 0, s, a, M, npairs, parity, t, swapped);
+    else hipLaunchKernelGGL(k_remc_swap<float>, grid, dim3(256), 0, s, a, M, npairs, parity, t, swapped);
     return hipGetLastError();
 }
 

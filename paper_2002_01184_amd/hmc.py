@@ -71,7 +71,8 @@ class hmc_server_stats(ctypes.Structure):
 HMC_REQ_QUEUED, HMC_REQ_RUNNING, HMC_REQ_DONE, HMC_REQ_FAILED = range(4)
 
 EXPORTED = ["hmc_workspace_size", "hmc_init", "hmc_step", "hmc_sample_chain", "hmc_get_state", "hmc_set_state",
-            "hmc_destroy", "hmc_last_error", "hmc_effective_form", "hmc_autotune", "hmc_server_create", "hmc_server_submit",
+            "hmc_destroy", "hmc_last_error", "hmc_effective_form", "hmc_autotune", "hmc_set_inverse_temperature",
+            "hmc_remc_swap", "hmc_remc_sample_chain", "hmc_server_create", "hmc_server_submit",
             "hmc_server_poll", "hmc_server_wait", "hmc_server_take", "hmc_server_get_stats",
             "hmc_server_destroy"]
 
@@ -111,6 +112,13 @@ def lib():
     L.hmc_effective_form.restype = ctypes.c_int32
     L.hmc_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]
     L.hmc_autotune.restype = st
+    L.hmc_set_inverse_temperature.argtypes = [vp, vp]
+    L.hmc_set_inverse_temperature.restype = st
+    L.hmc_remc_swap.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp]
+    L.hmc_remc_swap.restype = st
+    L.hmc_remc_sample_chain.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.POINTER(hmc_adapt), vp, ctypes.POINTER(hmc_trace), vp]
+    L.hmc_remc_sample_chain.restype = st
     L.hmc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
     L.hmc_server_create.restype = st
     L.hmc_server_submit.argtypes = [vp, ctypes.POINTER(hmc_request), ctypes.POINTER(ctypes.c_uint64)]
@@ -163,6 +171,21 @@ def hmc_sample_chain(ctx, num_results, num_burnin_steps, adapt: hmc_adapt | None
     _check(lib().hmc_sample_chain(ctx, num_results, num_burnin_steps,
                                   ctypes.byref(adapt) if adapt is not None else None, samples_ptr,
                                   ctypes.byref(trace) if trace is not None else None))
+
+
+def hmc_set_inverse_temperature(ctx, beta_ptr):
+    _check(lib().hmc_set_inverse_temperature(ctx, beta_ptr))
+
+
+def hmc_remc_swap(ctx, num_replicas: int, swap_index: int, swapped_ptr=None):
+    _check(lib().hmc_remc_swap(ctx, num_replicas, swap_index, swapped_ptr))
+
+
+def hmc_remc_sample_chain(ctx, num_replicas, num_results, num_burnin_steps, adapt: hmc_adapt | None, samples_ptr,
+                          trace: hmc_trace | None, swapped_ptr):
+    _check(lib().hmc_remc_sample_chain(ctx, num_replicas, num_results, num_burnin_steps,
+                                       ctypes.byref(adapt) if adapt is not None else None, samples_ptr,
+                                       ctypes.byref(trace) if trace is not None else None, swapped_ptr))
 
 
 def hmc_get_state(ctx, state_ptr, step_size_ptr) -> int:
@@ -310,6 +333,44 @@ class Sampler:
         ad = hmc_adapt(1, 0, target_accept, gamma, t0, kappa) if adapt else None
         hmc_sample_chain(self.ctx, R, num_burnin_steps, ad, _ptr(samples), tr)
         outs["samples"] = samples
+        return outs
+
+    def set_inverse_temperature(self, beta):
+        """beta: [C] FP64 device tensor (one value per chain), or None for 1."""
+        if beta is None:
+            hmc_set_inverse_temperature(self.ctx, None)
+            return
+        beta = beta.to(device=self.device, dtype=self.torch.float64).contiguous()
+        self.keep.append(beta)
+        hmc_set_inverse_temperature(self.ctx, _ptr(beta))
+
+    def remc_swap(self, num_replicas, swap_index, swapped=True):
+        torch = self.torch
+        sw = torch.empty(self.C, dtype=torch.uint8, device=self.device) if swapped else None
+        hmc_remc_swap(self.ctx, num_replicas, swap_index, _ptr(sw))
+        return sw
+
+    def remc_sample_chain(self, num_replicas, num_results, num_burnin_steps, adapt=False, target_accept=0.8,
+                          gamma=0.05, t0=10.0, kappa=0.75, store_samples=True, trace=True, swapped=True):
+        """Replica exchange: chains are num_replicas blocks of C / num_replicas
+        (replica-major); returns samples (after each exchange), traces and the
+        exchange flags [R, C]."""
+        torch = self.torch
+        C, D, R = self.C, self.D, num_results
+        samples = torch.empty(R, C, D, dtype=self.dtype, device=self.device) if store_samples else None
+        outs, tr = {}, None
+        if trace:
+            outs = dict(step_size=torch.empty(R, C, dtype=torch.float64, device=self.device),
+                        is_accepted=torch.empty(R, C, dtype=torch.uint8, device=self.device),
+                        log_accept_ratio=torch.empty(R, C, dtype=torch.float64, device=self.device),
+                        target_log_prob=torch.empty(R, C, dtype=torch.float64, device=self.device))
+            tr = hmc_trace(*[_ptr(outs[k]) for k in ("step_size", "is_accepted", "log_accept_ratio",
+                                                      "target_log_prob")])
+        sw = torch.empty(R, C, dtype=torch.uint8, device=self.device) if swapped else None
+        ad = hmc_adapt(1, 0, target_accept, gamma, t0, kappa) if adapt else None
+        hmc_remc_sample_chain(self.ctx, num_replicas, R, num_burnin_steps, ad, _ptr(samples), tr, _ptr(sw))
+        outs["samples"] = samples
+        outs["swapped"] = sw
         return outs
 
     def get_state(self):
