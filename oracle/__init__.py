@@ -19,6 +19,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 STD_NORMAL, GAUSS_DIAG, GAUSS_DENSE, LOGREG = 0, 1, 2, 3
 TAG_MOMENTUM, TAG_ACCEPT, TAG_SWAP = 0, 1, 2
+ADAPT_NONE, ADAPT_DUAL_AVERAGING, ADAPT_SIMPLE = 0, 1, 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -71,15 +72,17 @@ def lib():
         L.orc_sample_chain.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                                        ctypes.c_uint32, _dp, _dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                       _dp, _dp, _u8p, _dp, _dp, ctypes.c_int32]
+                                       ctypes.c_double, _dp, _dp, _u8p, _dp, _dp, ctypes.c_int32]
+        L.orc_simple_adapt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_simple_adapt.restype = ctypes.c_double
         L.orc_sample_chain.restype = ctypes.c_int
         L.orc_remc_swap.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_uint32, _dp, _dp, _dp, _u8p]
         L.orc_remc_sample_chain.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int64,
                                             ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, _dp, _dp,
                                             ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
-                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _u8p, _u8p,
-                                            ctypes.c_int32]
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            _dp, _u8p, _u8p, ctypes.c_int32]
         L.orc_remc_sample_chain.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -226,11 +229,28 @@ def dual_avg_run(eps0: float, alphas, target_accept=0.8, gamma=0.05, t0=10.0, ka
     return out[:, 0], out[:, 1], out[:, 2], s.mu
 
 
+def _adapt_code(adapt) -> int:
+    """adapt: False / True (dual averaging) / "dual_averaging" / "simple"."""
+    if adapt is False or adapt is None:
+        return ADAPT_NONE
+    if adapt is True or adapt == "dual_averaging":
+        return ADAPT_DUAL_AVERAGING
+    if adapt == "simple":
+        return ADAPT_SIMPLE
+    raise ValueError(f"unknown adaptation {adapt!r}")
+
+
+def simple_adapt(eps: float, alpha: float, target_accept: float = 0.8, rate: float = 0.01) -> float:
+    return lib().orc_simple_adapt(eps, alpha, target_accept, rate)
+
+
 def sample_chain(tg: Target, L: int, seed: int, x0, eps0, num_burnin: int, num_results: int,
-                 adapt: bool = False, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75,
+                 adapt=False, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75, rate=0.01,
                  t_begin: int = 0, store_samples: bool = True, nthreads: int = 0):
-    """Oracle sample_chain.  Returns dict(samples [R,C,D] or None, step_size, is_accepted,
-    log_accept_ratio, target_log_prob [R,C], final_x [C,D], final_eps [C])."""
+    """Oracle sample_chain.  adapt: False, True / "dual_averaging", or "simple"
+    (multiplicative rule with the given rate).  Returns dict(samples [R,C,D] or
+    None, step_size, is_accepted, log_accept_ratio, target_log_prob [R,C],
+    final_x [C,D], final_eps [C])."""
     x = _f64(x0).copy()
     C, D = x.shape
     eps = np.broadcast_to(_f64(eps0), (C,)).copy()
@@ -241,7 +261,7 @@ def sample_chain(tg: Target, L: int, seed: int, x0, eps0, num_burnin: int, num_r
     lar = np.empty((R, C))
     lp = np.empty((R, C))
     lib().orc_sample_chain(tg.c, C, L, seed, t_begin, _p(x), _p(eps), num_burnin, num_results,
-                           1 if adapt else 0, target_accept, gamma, t0, kappa,
+                           _adapt_code(adapt), target_accept, gamma, t0, kappa, rate,
                            _p(samples), _p(st), _p(acc, _u8p), _p(lar), _p(lp), nthreads)
     return dict(samples=samples, step_size=st, is_accepted=acc.astype(bool), log_accept_ratio=lar,
                 target_log_prob=lp, final_x=x, final_eps=eps)
@@ -277,7 +297,7 @@ def remc_swap(tg: Target, betas, seed: int, t: int, x, logp=None, g=None):
 
 
 def remc_sample_chain(tg: Target, betas, L: int, seed: int, x0, eps0, num_burnin: int, num_results: int,
-                      adapt: bool = False, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75,
+                      adapt=False, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75, rate=0.01,
                       t_begin: int = 0, store_samples: bool = True, nthreads: int = 0):
     """Oracle replica-exchange sample_chain.  x0 [K*M, D] replica-major.
     Returns dict(samples [R, K*M, D] (post-exchange states), is_accepted, swapped
@@ -295,7 +315,7 @@ def remc_sample_chain(tg: Target, betas, L: int, seed: int, x0, eps0, num_burnin
     acc = np.empty((R, C), dtype=np.uint8)
     sw = np.empty((R, C), dtype=np.uint8)
     lib().orc_remc_sample_chain(arr, K, M, L, seed, t_begin, _p(x), _p(eps), num_burnin, num_results,
-                                1 if adapt else 0, target_accept, gamma, t0, kappa, _p(samples),
+                                _adapt_code(adapt), target_accept, gamma, t0, kappa, rate, _p(samples),
                                 _p(acc, _u8p), _p(sw, _u8p), nthreads)
     return dict(samples=samples, is_accepted=acc.astype(bool), swapped=sw.astype(bool), final_x=x,
                 final_eps=eps)

@@ -285,6 +285,14 @@ int orc_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uint32_t
  *   log ebar_m = m^-kappa log eps_m + (1 - m^-kappa) log ebar_{m-1}
  * with mu = log(10 eps0), Hbar_0 = 0, ebar_0 = 1.
  * ---------------------------------------------------------------------- */
+/* Paper Sec. 4.1 names SimpleStepSizeAdaptation as a wrapper that tunes the
+ * inner kernel's step size during burn-in: grow it after a transition whose
+ * accept statistic is above the target, shrink it otherwise. */
+double orc_simple_adapt(double eps, double alpha, double target_accept, double rate)
+{
+    return alpha > target_accept ? eps * (1.0 + rate) : eps / (1.0 + rate);
+}
+
 void orc_dual_avg_init(orc_dual_avg *s, double eps0)
 {
     s->log_eps = log(eps0);
@@ -354,7 +362,7 @@ int orc_sample_chain(const orc_target *tg, int64_t C, int32_t L, uint64_t seed,
                      uint32_t t_begin, double *x, double *eps,
                      int64_t num_burnin, int64_t num_results,
                      int32_t adapt, double target_accept, double gamma, double t0, double kappa,
-                     double *samples, double *tr_step, uint8_t *tr_acc, double *tr_lar,
+                     double rate, double *samples, double *tr_step, uint8_t *tr_acc, double *tr_lar,
                      double *tr_logp, int32_t nthreads)
 {
     const int64_t D = tg->dim;
@@ -375,8 +383,12 @@ int orc_sample_chain(const orc_target *tg, int64_t C, int32_t L, uint64_t seed,
             double used = step;
             if (adapt && i < num_burnin) {
                 double alpha = lar < 0.0 ? exp(lar) : 1.0;   /* min(1, e^-dH); 0 for NaN */
-                orc_dual_avg_update(&da, i + 1, alpha, target_accept, gamma, t0, kappa);
-                step = (i + 1 < num_burnin) ? exp(da.log_eps) : exp(da.log_eps_bar);
+                if (adapt == ORC_ADAPT_SIMPLE) {
+                    step = orc_simple_adapt(step, alpha, target_accept, rate);
+                } else {
+                    orc_dual_avg_update(&da, i + 1, alpha, target_accept, gamma, t0, kappa);
+                    step = (i + 1 < num_burnin) ? exp(da.log_eps) : exp(da.log_eps_bar);
+                }
             }
             if (i >= num_burnin) {
                 int64_t r = i - num_burnin;
@@ -437,7 +449,7 @@ void orc_remc_swap(const orc_target *tgs, int64_t K, int64_t M, uint64_t seed, u
 int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L, uint64_t seed,
                           uint32_t t_begin, double *x, double *eps, int64_t num_burnin,
                           int64_t num_results, int32_t adapt, double target_accept, double gamma,
-                          double t0, double kappa, double *samples, uint8_t *tr_acc,
+                          double t0, double kappa, double rate, double *samples, uint8_t *tr_acc,
                           uint8_t *tr_swap, int32_t nthreads)
 {
     const int64_t D = tgs[0].dim, C = K * M;
@@ -460,8 +472,12 @@ int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L
                                              &logp[c], g + c * D, NULL, NULL, NULL, NULL, &lar);
             if (adapt && i < num_burnin) {
                 double alpha = lar < 0.0 ? exp(lar) : 1.0;
-                orc_dual_avg_update(&da[c], i + 1, alpha, target_accept, gamma, t0, kappa);
-                eps[c] = (i + 1 < num_burnin) ? exp(da[c].log_eps) : exp(da[c].log_eps_bar);
+                if (adapt == ORC_ADAPT_SIMPLE) {
+                    eps[c] = orc_simple_adapt(eps[c], alpha, target_accept, rate);
+                } else {
+                    orc_dual_avg_update(&da[c], i + 1, alpha, target_accept, gamma, t0, kappa);
+                    eps[c] = (i + 1 < num_burnin) ? exp(da[c].log_eps) : exp(da[c].log_eps_bar);
+                }
             }
         }
         orc_remc_swap(tgs, K, M, seed, t, x, logp, g, swp);

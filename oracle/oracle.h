@@ -106,6 +106,12 @@ typedef struct {
     double mu;           /* shrinkage point log(10 * eps0) */
 } orc_dual_avg;
 
+/* Multiplicative step-size adaptation (the paper's SimpleStepSizeAdaptation
+ * example of the wrapper pattern, Sec. 4.1), one chain, one burn-in
+ * transition: eps (1 + rate) when the accept statistic alpha exceeds
+ * target_accept, eps / (1 + rate) otherwise. */
+double orc_simple_adapt(double eps, double alpha, double target_accept, double rate);
+
 void orc_dual_avg_init(orc_dual_avg *s, double eps0);
 /* Iteration m >= 1 with acceptance statistic alpha in [0, 1]. */
 void orc_dual_avg_update(orc_dual_avg *s, int64_t m, double alpha, double target_accept,
@@ -123,14 +129,17 @@ void orc_step(const orc_target *tg, int64_t C, int32_t L, uint64_t seed, uint32_
 
 /* sample_chain: transitions t_begin .. t_begin + burnin + results - 1.
  * x [C*D] and eps [C] are read as the start and hold the final state / step
- * size on return.  With adapt != 0 each chain runs dual averaging during the
- * burn-in (iteration m = 1..burnin) and then uses exp(log_eps_bar).
+ * size on return.  adapt: 0 fixed step size; ORC_ADAPT_DUAL_AVERAGING: each
+ * chain runs dual averaging during the burn-in (iteration m = 1..burnin) and
+ * then uses exp(log_eps_bar); ORC_ADAPT_SIMPLE: orc_simple_adapt after every
+ * burn-in transition (rate), the last value kept afterwards.
  * samples [R*C*D] and traces [R*C] may be NULL.  Returns 0. */
+enum { ORC_ADAPT_DUAL_AVERAGING = 1, ORC_ADAPT_SIMPLE = 2 };
 int orc_sample_chain(const orc_target *tg, int64_t C, int32_t L, uint64_t seed,
                      uint32_t t_begin, double *x, double *eps,
                      int64_t num_burnin, int64_t num_results,
                      int32_t adapt, double target_accept, double gamma, double t0, double kappa,
-                     double *samples, double *tr_step, uint8_t *tr_acc, double *tr_lar,
+                     double rate, double *samples, double *tr_step, uint8_t *tr_acc, double *tr_lar,
                      double *tr_logp, int32_t nthreads);
 
 /* ---- Replica exchange Monte Carlo (paper Sec. 3.1, case study REMC) ----
@@ -153,15 +162,16 @@ void orc_remc_swap(const orc_target *tgs, int64_t K, int64_t M, uint64_t seed, u
 /* REMC driver: transitions t_begin .. t_begin + burnin + results - 1; each is
  * one HMC transition of every chain on its replica's target (chain c uses
  * tgs[c / M], step eps[c], the counters of chain c) followed by the exchange
- * step with swap index t.  Dual averaging (adapt != 0) works per chain on
- * the burn-in as in orc_sample_chain; step sizes stay with the chain slot.
+ * step with swap index t.  Step-size adaptation (adapt as in
+ * orc_sample_chain) works per chain on the burn-in; step sizes stay with the
+ * chain slot.
  * samples [R*C*D] hold the states after the exchange of transition
  * burnin + r; tr_acc [R*C] the HMC accept flags, tr_swap [R*C] the exchange
  * flags (each may be NULL).  x and eps hold the final state / step sizes. */
 int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L, uint64_t seed,
                           uint32_t t_begin, double *x, double *eps, int64_t num_burnin,
                           int64_t num_results, int32_t adapt, double target_accept, double gamma,
-                          double t0, double kappa, double *samples, uint8_t *tr_acc,
+                          double t0, double kappa, double rate, double *samples, uint8_t *tr_acc,
                           uint8_t *tr_swap, int32_t nthreads);
 
 #ifdef __cplusplus
