@@ -96,17 +96,25 @@ typedef struct hmc_config {
     uint64_t seed;               /* Philox key */
 } hmc_config;
 
-/* Dual averaging of the per-chain step size during burn-in (Hoffman &
- * Gelman 2014, Sec. 3.2, eq. 6), adaptation wrapper pattern of the paper's
- * Sec. 4.1.  mu = log(10 eps0) with eps0 each chain's step size at the start
- * of hmc_sample_chain; after burn-in each chain uses exp(log eps_bar). */
+/* Per-chain step-size adaptation during burn-in, the adaptation wrapper
+ * pattern of the paper's Sec. 4.1, with the accept statistic
+ * alpha = min(1, exp(-dH)) of each burn-in transition:
+ *   HMC_ADAPT_DUAL_AVERAGING (kind 0): Hoffman & Gelman 2014, Sec. 3.2,
+ *     eq. 6, with mu = log(10 eps0), eps0 each chain's step size at the start
+ *     of the call; after burn-in each chain uses exp(log eps_bar);
+ *   HMC_ADAPT_SIMPLE (kind 1): the multiplicative rule of the paper's
+ *     SimpleStepSizeAdaptation example: eps (1 + rate) when alpha >
+ *     target_accept, eps / (1 + rate) otherwise; the last value is kept
+ *     after burn-in. */
+enum { HMC_ADAPT_DUAL_AVERAGING = 0, HMC_ADAPT_SIMPLE = 1 };
 typedef struct hmc_adapt {
     int32_t enabled;
-    int32_t reserved;
+    int32_t kind;                /* HMC_ADAPT_* */
     double target_accept;        /* delta, e.g. 0.8 */
-    double gamma;                /* 0.05 */
-    double t0;                   /* 10 */
-    double kappa;                /* 0.75 */
+    double gamma;                /* dual averaging: 0.05 */
+    double t0;                   /* dual averaging: 10 */
+    double kappa;                /* dual averaging: 0.75 */
+    double rate;                 /* simple: adaptation rate in (0, 1], e.g. 0.01 */
 } hmc_adapt;
 
 /* Trace of kept transitions (paper Sec. 4.2 "tracing"): each pointer is a

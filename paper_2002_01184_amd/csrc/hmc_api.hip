@@ -50,6 +50,22 @@ namespace hmc {
 
 size_t elem_size(int32_t dtype) { return dtype == HMC_F64 ? 8 : (dtype == HMC_BF16 ? 2 : 4); }
 
+hmc_status check_adapt(const hmc_adapt* ad) {
+    if (!ad || !ad->enabled) return HMC_OK;
+    if (!(ad->target_accept > 0.0 && ad->target_accept < 1.0))
+        return fail(HMC_E_INVALID, "adaptation target_accept must be in (0, 1)");
+    if (ad->kind == HMC_ADAPT_DUAL_AVERAGING) {
+        if (!(ad->gamma > 0.0) || !(ad->t0 >= 0.0) || !(ad->kappa > 0.0))
+            return fail(HMC_E_INVALID, "dual-averaging parameters out of range");
+        return HMC_OK;
+    }
+    if (ad->kind == HMC_ADAPT_SIMPLE) {
+        if (!(ad->rate > 0.0 && ad->rate <= 1.0)) return fail(HMC_E_INVALID, "adaptation rate must be in (0, 1]");
+        return HMC_OK;
+    }
+    return fail(HMC_E_INVALID, "unknown adaptation kind");
+}
+
 Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg, size_t* total) {
     const int64_t C = cfg.num_chains, D = tg.D;
     const size_t es = elem_size(cfg.state_dtype);
@@ -318,11 +334,7 @@ hmc_status hmc_sample_chain(hmc_ctx* ctx, int64_t num_results, int64_t num_burni
     if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
     if (num_results < 0 || num_burnin_steps < 0) return fail(HMC_E_INVALID, "negative transition count");
     const bool ad = adapt && adapt->enabled;
-    if (ad) {
-        if (!(adapt->target_accept > 0.0 && adapt->target_accept < 1.0) || !(adapt->gamma > 0.0) ||
-            !(adapt->t0 >= 0.0) || !(adapt->kappa > 0.0))
-            return fail(HMC_E_INVALID, "adaptation parameters out of range");
-    }
+    if (ad && check_adapt(adapt) != HMC_OK) return HMC_E_INVALID;
     const int64_t total = num_results + num_burnin_steps;
     if (ctx->t + (uint64_t)total > 0xffffffffull) return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
     hmc_trace tr;
@@ -340,13 +352,7 @@ hmc_status hmc_sample_chain(hmc_ctx* ctx, int64_t num_results, int64_t num_burni
         r.n_burnin = num_burnin_steps;
         r.m_offset = 0;
         r.adapt_total = num_burnin_steps;
-        r.adapt = ad;
-        if (ad) {
-            r.target_accept = adapt->target_accept;
-            r.gamma = adapt->gamma;
-            r.t0 = adapt->t0;
-            r.kappa = adapt->kappa;
-        }
+        set_adapt(r, adapt);
         r.samples = samples;
         r.trace = tr;
         st = check_hip(launch_fused(ctx->a, r, ctx->stream), "fused sample_chain");
@@ -354,13 +360,7 @@ hmc_status hmc_sample_chain(hmc_ctx* ctx, int64_t num_results, int64_t num_burni
         Ctrl c = base_ctrl(ctx);
         c.n_burnin = num_burnin_steps;
         c.n_results = num_results;
-        c.adapt = ad;
-        if (ad) {
-            c.target_accept = adapt->target_accept;
-            c.gamma = adapt->gamma;
-            c.t0 = adapt->t0;
-            c.kappa = adapt->kappa;
-        }
+        set_adapt(c, adapt);
         c.samples = samples;
         c.tr_step = tr.step_size;
         c.tr_acc = tr.is_accepted;
@@ -666,9 +666,7 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
     if (st != HMC_OK) return st;
     if (num_results < 0 || num_burnin_steps < 0) return fail(HMC_E_INVALID, "negative transition count");
     const bool ad = adapt && adapt->enabled;
-    if (ad && (!(adapt->target_accept > 0.0 && adapt->target_accept < 1.0) || !(adapt->gamma > 0.0) ||
-               !(adapt->t0 >= 0.0) || !(adapt->kappa > 0.0)))
-        return fail(HMC_E_INVALID, "adaptation parameters out of range");
+    if (ad && check_adapt(adapt) != HMC_OK) return HMC_E_INVALID;
     const int64_t total = num_results + num_burnin_steps;
     if (ctx->t + (uint64_t)total > 0xffffffffull) return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
     const int64_t C = ctx->a.C, M = C / num_replicas;
@@ -681,13 +679,7 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
     Ctrl c = base_ctrl(ctx);
     c.n_burnin = num_burnin_steps;
     c.n_results = num_results;
-    c.adapt = ad;
-    if (ad) {
-        c.target_accept = adapt->target_accept;
-        c.gamma = adapt->gamma;
-        c.t0 = adapt->t0;
-        c.kappa = adapt->kappa;
-    }
+    set_adapt(c, adapt);
     c.samples = nullptr;
     c.tr_step = tr.step_size;
     c.tr_acc = tr.is_accepted;

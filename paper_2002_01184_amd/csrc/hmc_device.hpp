@@ -157,6 +157,13 @@ __device__ __forceinline__ double dual_avg_apply(DualAvg& s, const DaConst& c, d
     return log_eps;
 }
 
+// Multiplicative rule (SimpleStepSizeAdaptation example of the wrapper
+// pattern): grow after a transition whose accept statistic is above the
+// target, shrink otherwise.
+__device__ __forceinline__ double simple_adapt(double eps, double alpha, double target, double rate) {
+    return alpha > target ? eps * (1.0 + rate) : eps / (1.0 + rate);
+}
+
 // Iteration m >= 1 with accept statistic alpha; returns the new log step size.
 __device__ __forceinline__ double dual_avg_update(DualAvg& s, double m, double alpha, double delta,
                                                   double gamma, double t0, double kappa) {
@@ -171,8 +178,8 @@ struct Ctrl {
     int64_t n_burnin;
     int64_t n_results;
     int32_t adapt;
-    int32_t reserved;
-    double target_accept, gamma, t0, kappa;
+    int32_t adapt_kind;       // HMC_ADAPT_DUAL_AVERAGING or HMC_ADAPT_SIMPLE
+    double target_accept, gamma, t0, kappa, rate;
     void* samples;            // [R, C, D] state dtype or null
     double* tr_step;
     uint8_t* tr_acc;

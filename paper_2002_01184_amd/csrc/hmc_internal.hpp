@@ -102,11 +102,28 @@ struct FusedRun {
     int64_t m_offset;        // dual-averaging iterations done before this launch
     int64_t adapt_total;     // burn-in length of the whole run: at iteration m == adapt_total switch to eps_bar
     int32_t adapt;
-    double target_accept, gamma, t0, kappa;
+    int32_t adapt_kind;      // HMC_ADAPT_DUAL_AVERAGING or HMC_ADAPT_SIMPLE
+    double target_accept, gamma, t0, kappa, rate;
     void* samples;
     hmc_trace trace;
     hmc_step_out out;        // only for single-transition launches
 };
+// Adaptation parameters of an hmc_adapt (NULL or disabled: none) into a
+// plain-path control block or a fused run.
+template <typename R>
+inline void set_adapt(R& r, const hmc_adapt* ad) {
+    r.adapt = (ad && ad->enabled) ? 1 : 0;
+    if (!r.adapt) return;
+    r.adapt_kind = ad->kind;
+    r.target_accept = ad->target_accept;
+    r.gamma = ad->gamma;
+    r.t0 = ad->t0;
+    r.kappa = ad->kappa;
+    r.rate = ad->rate;
+}
+// HMC_E_INVALID with a message when enabled parameters are out of range.
+hmc_status check_adapt(const hmc_adapt* ad);
+
 // Returns hipErrorNotSupported when no fused kernel covers this target/shape.
 bool fused_supported(const PlainArgs& a);
 hipError_t launch_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s);

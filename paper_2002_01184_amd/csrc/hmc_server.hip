@@ -140,11 +140,7 @@ hipError_t admit(Request* q, void* pool, hipStream_t s) {
     memset(&c, 0, sizeof(c));
     c.n_burnin = q->req.num_burnin;
     c.n_results = q->req.num_results;
-    c.adapt = q->req.adapt.enabled;
-    c.target_accept = q->req.adapt.target_accept;
-    c.gamma = q->req.adapt.gamma;
-    c.t0 = q->req.adapt.t0;
-    c.kappa = q->req.adapt.kappa;
+    set_adapt(c, &q->req.adapt);
     c.samples = q->samples;
     c.tr_step = q->req.trace.step_size;
     c.tr_acc = q->req.trace.is_accepted;
@@ -166,11 +162,7 @@ FusedRun tick_run(const Request* q, int64_t n) {
     r.n_burnin = std::max<int64_t>(0, std::min<int64_t>(n, B - q->done));
     r.m_offset = std::min<int64_t>(q->done, B);
     r.adapt_total = B;
-    r.adapt = q->req.adapt.enabled;
-    r.target_accept = q->req.adapt.target_accept;
-    r.gamma = q->req.adapt.gamma;
-    r.t0 = q->req.adapt.t0;
-    r.kappa = q->req.adapt.kappa;
+    set_adapt(r, &q->req.adapt);
     const int64_t kept_before = std::max<int64_t>(0, q->done - B);
     if (q->samples) r.samples = (char*)q->samples + (size_t)kept_before * C * D * es;
     const hmc_trace& tr = q->req.trace;
@@ -362,6 +354,7 @@ hmc_status hmc_server_submit(hmc_server* srv, const hmc_request* req, uint64_t* 
     if (!(req->step_size > 0.0) || !std::isfinite(req->step_size)) return fail(HMC_E_INVALID, "bad step size");
     if (req->num_results < 0 || req->num_burnin < 0) return fail(HMC_E_INVALID, "negative transition count");
     if (req->num_results + req->num_burnin > 0xffffffffll) return fail(HMC_E_INVALID, "too many transitions");
+    if (check_adapt(&req->adapt) != HMC_OK) return HMC_E_INVALID;
     if (req->config.form == HMC_FORM_GRAPH) return fail(HMC_E_UNSUPPORTED, "serving runs the plain or fused form");
     Request* q = new Request();
     q->req = *req;

@@ -28,9 +28,13 @@ __device__ __forceinline__ void after_decision(const FusedRun& r, int64_t C, int
     const double eps_used = s.eps;
     if (r.adapt && i < r.n_burnin) {
         const double alpha = lar < 0.0 ? exp(lar) : 1.0;
-        const int64_t m = r.m_offset + i + 1;
-        const double log_eps = dual_avg_update(s.da, (double)m, alpha, r.target_accept, r.gamma, r.t0, r.kappa);
-        s.eps = (m < r.adapt_total) ? exp(log_eps) : exp(s.da.log_eps_bar);
+        if (r.adapt_kind == HMC_ADAPT_SIMPLE) {
+            s.eps = simple_adapt(s.eps, alpha, r.target_accept, r.rate);
+        } else {
+            const int64_t m = r.m_offset + i + 1;
+            const double log_eps = dual_avg_update(s.da, (double)m, alpha, r.target_accept, r.gamma, r.t0, r.kappa);
+            s.eps = (m < r.adapt_total) ? exp(log_eps) : exp(s.da.log_eps_bar);
+        }
     }
     if (!writer) return;
     if (i >= r.n_burnin) {

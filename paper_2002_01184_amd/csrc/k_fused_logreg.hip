@@ -433,10 +433,15 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
                 const double eps_used = cs.eps;
                 if (r.adapt && itr < r.n_burnin) {
                     const double alpha = lar < 0.0 ? exp_lds(lar, ecf) : 1.0;
-                    const int64_t m = r.m_offset + itr + 1;
-                    const double* f = dac + (hb * UT + ku) * 4;
-                    const double log_eps = dual_avg_apply(cs.da, DaConst{f[0], f[1], f[2]}, alpha, r.target_accept);
-                    cs.eps = exp_lds((m < r.adapt_total) ? log_eps : cs.da.log_eps_bar, ecf);
+                    if (r.adapt_kind == HMC_ADAPT_SIMPLE) {
+                        cs.eps = simple_adapt(cs.eps, alpha, r.target_accept, r.rate);
+                    } else {
+                        const int64_t m = r.m_offset + itr + 1;
+                        const double* f = dac + (hb * UT + ku) * 4;
+                        const double log_eps =
+                            dual_avg_apply(cs.da, DaConst{f[0], f[1], f[2]}, alpha, r.target_accept);
+                        cs.eps = exp_lds((m < r.adapt_total) ? log_eps : cs.da.log_eps_bar, ecf);
+                    }
                 }
                 eps = (float)cs.eps;
                 if (od == 0) {

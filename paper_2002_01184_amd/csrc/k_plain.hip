@@ -155,11 +155,15 @@ __global__ __launch_bounds__(256) void k_end(PlainArgs a) {
     a.ws.logp[c] = lp_new;
     if (ct.adapt && i < ct.n_burnin) {
         const double alpha = lar < 0.0 ? exp(lar) : 1.0;
-        DualAvg s = a.ws.da[c];
-        const double log_eps = dual_avg_update(s, (double)(i + 1), alpha, ct.target_accept, ct.gamma, ct.t0,
-                                               ct.kappa);
-        a.ws.da[c] = s;
-        a.ws.eps[c] = (i + 1 < ct.n_burnin) ? exp(log_eps) : exp(s.log_eps_bar);
+        if (ct.adapt_kind == HMC_ADAPT_SIMPLE) {
+            a.ws.eps[c] = simple_adapt(eps_used, alpha, ct.target_accept, ct.rate);
+        } else {
+            DualAvg s = a.ws.da[c];
+            const double log_eps = dual_avg_update(s, (double)(i + 1), alpha, ct.target_accept, ct.gamma, ct.t0,
+                                                   ct.kappa);
+            a.ws.da[c] = s;
+            a.ws.eps[c] = (i + 1 < ct.n_burnin) ? exp(log_eps) : exp(s.log_eps_bar);
+        }
     }
     if (i >= ct.n_burnin && i < ct.n_burnin + ct.n_results) {
         const int64_t r = i - ct.n_burnin;

@@ -40,9 +40,26 @@ class hmc_config(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+HMC_ADAPT_DUAL_AVERAGING, HMC_ADAPT_SIMPLE = 0, 1
+
+
 class hmc_adapt(ctypes.Structure):
-    _fields_ = [("enabled", ctypes.c_int32), ("reserved", ctypes.c_int32), ("target_accept", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("t0", ctypes.c_double), ("kappa", ctypes.c_double)]
+    _fields_ = [("enabled", ctypes.c_int32), ("kind", ctypes.c_int32), ("target_accept", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("t0", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("rate", ctypes.c_double)]
+
+
+def make_adapt(adapt, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75, rate=0.01):
+    """adapt: False / None (fixed step), True or "dual_averaging", "simple"."""
+    if adapt is False or adapt is None:
+        return None
+    if adapt is True or adapt == "dual_averaging":
+        kind = HMC_ADAPT_DUAL_AVERAGING
+    elif adapt == "simple":
+        kind = HMC_ADAPT_SIMPLE
+    else:
+        raise ValueError(f"unknown adaptation {adapt!r}")
+    return hmc_adapt(1, kind, target_accept, gamma, t0, kappa, rate)
 
 
 class hmc_trace(ctypes.Structure):
@@ -309,7 +326,7 @@ class Sampler:
         return out
 
     def sample_chain(self, num_results, num_burnin_steps, adapt=False, target_accept=0.8, gamma=0.05, t0=10.0,
-                     kappa=0.75, store_samples=True, trace=True, out_samples=None):
+                     kappa=0.75, store_samples=True, trace=True, out_samples=None, rate=0.01):
         """out_samples: optional contiguous [R, C, D] device tensor of the state
         dtype that receives the samples (else one is allocated)."""
         torch = self.torch
@@ -330,7 +347,7 @@ class Sampler:
                         target_log_prob=torch.empty(R, C, dtype=torch.float64, device=self.device))
             tr = hmc_trace(*[_ptr(outs[k]) for k in ("step_size", "is_accepted", "log_accept_ratio",
                                                       "target_log_prob")])
-        ad = hmc_adapt(1, 0, target_accept, gamma, t0, kappa) if adapt else None
+        ad = make_adapt(adapt, target_accept, gamma, t0, kappa, rate)
         hmc_sample_chain(self.ctx, R, num_burnin_steps, ad, _ptr(samples), tr)
         outs["samples"] = samples
         return outs
@@ -351,7 +368,8 @@ class Sampler:
         return sw
 
     def remc_sample_chain(self, num_replicas, num_results, num_burnin_steps, adapt=False, target_accept=0.8,
-                          gamma=0.05, t0=10.0, kappa=0.75, store_samples=True, trace=True, swapped=True):
+                          gamma=0.05, t0=10.0, kappa=0.75, store_samples=True, trace=True, swapped=True,
+                          rate=0.01):
         """Replica exchange: chains are num_replicas blocks of C / num_replicas
         (replica-major); returns samples (after each exchange), traces and the
         exchange flags [R, C]."""
@@ -367,7 +385,7 @@ class Sampler:
             tr = hmc_trace(*[_ptr(outs[k]) for k in ("step_size", "is_accepted", "log_accept_ratio",
                                                       "target_log_prob")])
         sw = torch.empty(R, C, dtype=torch.uint8, device=self.device) if swapped else None
-        ad = hmc_adapt(1, 0, target_accept, gamma, t0, kappa) if adapt else None
+        ad = make_adapt(adapt, target_accept, gamma, t0, kappa, rate)
         hmc_remc_sample_chain(self.ctx, num_replicas, R, num_burnin_steps, ad, _ptr(samples), tr, _ptr(sw))
         outs["samples"] = samples
         outs["swapped"] = sw
@@ -479,7 +497,7 @@ class Server:
                             0 if X is None else X.shape[0], _ptr(y), float(w.prior_scale))
         config = hmc_config(C, w.num_leapfrog_steps, HMC_F64 if w.state_dtype == "f64" else HMC_F32,
                             HMC_BF16 if grad_bf16 else HMC_F32, form, w.seed if seed is None else seed)
-        adapt = hmc_adapt(1 if w.adapt else 0, 0, 0.8, 0.05, 10.0, 0.75)
+        adapt = hmc_adapt(1 if w.adapt else 0, HMC_ADAPT_DUAL_AVERAGING, 0.8, 0.05, 10.0, 0.75, 0.01)
         torch.cuda.synchronize(dev)    # inputs are on the device before the worker reads them
         req = hmc_request(target, config, _ptr(init), float(w.step_size), R, w.num_burnin, adapt, _ptr(samples), tr)
         outs["samples"] = samples
