@@ -29,7 +29,7 @@ _u32p = ctypes.POINTER(ctypes.c_uint32)
 class _Target(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("dim", ctypes.c_int64),
                 ("prec", _dp), ("X", _dp), ("y", _dp), ("n_rows", ctypes.c_int64),
-                ("prior_scale", ctypes.c_double), ("beta", ctypes.c_double)]
+                ("prior_scale", ctypes.c_double), ("beta", ctypes.c_double), ("scale", _dp), ("shift", _dp)]
 
 
 class _DualAvg(ctypes.Structure):
@@ -108,6 +108,8 @@ class Target:
     y: np.ndarray | None = None
     prior_scale: float = 1.0
     beta: float = 1.0          # inverse temperature (replica exchange): beta * logp
+    scale: np.ndarray | None = None   # transformed kernel: x = shift + scale * z
+    shift: np.ndarray | None = None
 
     def __post_init__(self):
         if self.prec is not None:
@@ -116,13 +118,24 @@ class Target:
             self.X = _f64(self.X)
         if self.y is not None:
             self.y = _f64(self.y)
+        if self.scale is not None:
+            self.scale = _f64(self.scale)
+        if self.shift is not None:
+            self.shift = _f64(self.shift)
         n = 0 if self.X is None else self.X.shape[0]
         self._c = _Target(self.kind, 0, self.dim, _p(self.prec), _p(self.X), _p(self.y), n,
-                          float(self.prior_scale), float(self.beta))
+                          float(self.prior_scale), float(self.beta), _p(self.scale), _p(self.shift))
 
     def tempered(self, beta: float) -> "Target":
         """The same target at inverse temperature beta (shares the arrays)."""
-        return Target(self.kind, self.dim, self.prec, self.X, self.y, self.prior_scale, float(beta))
+        return Target(self.kind, self.dim, self.prec, self.X, self.y, self.prior_scale, float(beta),
+                      self.scale, self.shift)
+
+    def transformed(self, scale, shift=None) -> "Target":
+        """The pulled-back target of the diagonal affine bijector x = shift + scale * z."""
+        return Target(self.kind, self.dim, self.prec, self.X, self.y, self.prior_scale, self.beta,
+                      np.broadcast_to(_f64(scale), (self.dim,)).copy(),
+                      None if shift is None else np.broadcast_to(_f64(shift), (self.dim,)).copy())
 
     @property
     def c(self):
@@ -319,3 +332,20 @@ def remc_sample_chain(tg: Target, betas, L: int, seed: int, x0, eps0, num_burnin
                                 _p(acc, _u8p), _p(sw, _u8p), nthreads)
     return dict(samples=samples, is_accepted=acc.astype(bool), swapped=sw.astype(bool), final_x=x,
                 final_eps=eps)
+
+
+# ------------------------------------------------- transformed kernel --
+def transformed_sample_chain(tg: Target, scale, shift, L: int, seed: int, x0, eps0, num_burnin: int,
+                             num_results: int, **kw):
+    """TransformedTransitionKernel (paper Sec. 4.1) with x = shift + scale * z:
+    the HMC chain runs on z (initial z0 = (x0 - shift) / scale) against the
+    pulled-back target and its samples are pushed forward to x."""
+    tz = tg.transformed(scale, shift)
+    mu = np.zeros(tg.dim) if shift is None else np.broadcast_to(_f64(shift), (tg.dim,))
+    s = tz.scale
+    z0 = (_f64(x0) - mu) / s
+    r = sample_chain(tz, L, seed, z0, eps0, num_burnin, num_results, **kw)
+    if r["samples"] is not None:
+        r["samples"] = mu + s * r["samples"]
+    r["final_x"] = mu + s * r["final_x"]
+    return r

@@ -141,7 +141,27 @@ static double sigmoid(double s)
     return e / (1.0 + e);
 }
 
-double orc_logp_grad(const orc_target *tg, const double *x, double *g)
+static double logp_grad_x(const orc_target *tg, const double *x, double *g);
+
+/* TransformedTransitionKernel (paper Sec. 4.1) with the diagonal affine
+ * bijector x = shift + scale z: the inner kernel sees the pulled-back target
+ * l(x(z)) (+ the constant log-det), whose gradient is scale * grad_x l. */
+double orc_logp_grad(const orc_target *tg, const double *z, double *g)
+{
+    if (!tg->scale)
+        return logp_grad_x(tg, z, g);
+    const int64_t D = tg->dim;
+    double *x = (double *)calloc((size_t)(D > 0 ? D : 1), sizeof(double));
+    for (int64_t i = 0; i < D; ++i)
+        x[i] = (tg->shift ? tg->shift[i] : 0.0) + tg->scale[i] * z[i];
+    double lp = logp_grad_x(tg, x, g);
+    for (int64_t i = 0; i < D; ++i)
+        g[i] *= tg->scale[i];
+    free(x);
+    return lp;
+}
+
+static double logp_grad_x(const orc_target *tg, const double *x, double *g)
 {
     const int64_t D = tg->dim;
     double logp = 0.0;

@@ -56,6 +56,12 @@ typedef struct {
     double beta;           /* inverse temperature: the log-probability and its
                               gradient are multiplied by beta (1 = untempered;
                               replica exchange, paper Sec. 3.1) */
+    const double *scale;   /* transformed kernel (paper Sec. 4.1): when not NULL the
+                              chain moves in z with x = shift + scale * z (diagonal
+                              affine bijector); logp is evaluated at x(z) and the
+                              gradient is scale * grad_x.  The log-det term is
+                              constant and dropped. */
+    const double *shift;   /* [D] or NULL (zero) */
 } orc_target;
 
 /* Philox4x32-10 block function (SC'11, Sec. 3.2): 10 rounds, key bumped

@@ -66,3 +66,42 @@ def test_torch_estimators_equal_numpy():
     b = dg.t_summarize(torch.from_numpy(s))
     assert np.allclose(a["ess_bulk"], b["ess_bulk"], rtol=1e-9)
     assert np.allclose(a["rhat"], b["rhat"], rtol=1e-12)
+
+
+def _half_moments(x):
+    """x [R, C, D] -> two-pass mean / m2 [2, C, D] of the halves r < R//2 and r >= R//2."""
+    h = x.shape[0] // 2
+    parts = [x[:h], x[h:]]
+    mean = np.stack([p.mean(0) for p in parts])
+    m2 = np.stack([((p - p.mean(0)) ** 2).sum(0) for p in parts])
+    return mean, m2
+
+
+def test_split_rhat_from_moments_equals_split_rhat_of_samples():
+    rng = np.random.default_rng(5)
+    x = _ar1(600, 12, 0.6, seed=3)[:, :, None] + rng.normal(0, 0.05, size=(1, 12, 1))
+    x = np.concatenate([x, 2 * x + 1], axis=2)                     # two coordinates
+    mean, m2 = _half_moments(x)
+    got = dg.moments_rhat(mean, m2, x.shape[0])
+    for d in range(2):
+        assert got[d] == pytest.approx(dg._rhat_basic(dg._split(x[:, :, d])), rel=1e-12)
+    # a shifted chain raises it
+    y = x.copy()
+    y[:, 0] += 3.0
+    assert np.all(dg.moments_rhat(*_half_moments(y), x.shape[0]) > 1.05)
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.7])
+def test_batch_means_ess_ar1(rho):
+    n, M, blen = 20000, 16, 400
+    x = _ar1(n, M, rho, seed=11)[:, :, None]
+    mean, m2 = _half_moments(x)
+    bsum = x.reshape(n // blen, blen, M, 1).sum(1)
+    got = dg.moments_ess_batch(mean, m2, bsum, n, blen)[0]
+    expected = n * M * (1 - rho) / (1 + rho)
+    assert abs(got / expected - 1) < 0.15, (got, expected)
+    # the pooled within-chain variance recombined from the halves is the sample variance
+    h = n // 2
+    d = mean[1] - mean[0]
+    m2c = m2[0] + m2[1] + d * d * h * (n - h) / n
+    assert np.allclose(m2c / (n - 1), x.var(0, ddof=1), rtol=1e-10)
