@@ -220,6 +220,87 @@ def bench_remc(args):
     return result
 
 
+def bench_moments(args):
+    """Streaming expectations on a workload: the same transitions as the
+    default run with the kept states folded into per-chain moments and batch
+    sums through a ring of --ring-rows states instead of stored; reports the
+    throughput, split R-hat and batch-means ESS from the moments."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2002_01184_amd import diagnostics as dg
+    from paper_2002_01184_amd import hmc
+
+    w = W.CONFIGS[args.config]()
+    if args.transitions is not None:
+        w.num_burnin = min(w.num_burnin, args.transitions // 2)
+        w.num_results = args.transitions - w.num_burnin
+    R = w.num_results
+    nb = 20 if R % 20 == 0 and R >= 40 else 0
+    form = {"auto": hmc.HMC_FORM_AUTO, "plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_GRAPH,
+            "fused": hmc.HMC_FORM_FUSED}[args.form]
+    s = hmc.sampler_for(w, form=form, grad_bf16=args.grad == "bf16")
+    x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).cuda()
+    eps0 = torch.full((w.num_chains,), w.step_size, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run(ev=None):
+        s.set_state(x0, eps0, 0)
+        if ev is not None:
+            ev[0].record(stream)
+        out = s.sample_chain_moments(R, w.num_burnin, adapt=w.adapt, ring_rows=args.ring_rows,
+                                     batch_len=R // nb if nb else None)
+        if ev is not None:
+            ev[1].record(stream)
+        return out
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    out = None
+    for k in range(args.steps):
+        out = run(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    bound, per_cs, unit = algorithmic_work(w)
+    achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
+    peak = PEAK["hbm"] if bound == "hbm" else (PEAK["bf16_mfma"] if args.grad == "bf16" else PEAK["fp32_mfma"])
+    scale = 1e9 if bound == "hbm" else 1e12
+    es = 8 if w.state_dtype == "f64" else 4
+    summ = dg.moments_summary(to_host(out["mean"]), to_host(out["m2"]), R,
+                              None if out["batch_sum"] is None else to_host(out["batch_sum"]), R // nb if nb else None)
+    result = {
+        "metric": METRIC, "value": w.chain_steps() * args.steps / elapsed, "unit": "leapfrog chain-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if w.state_dtype == "f64" else ("bf16/f32" if args.grad == "bf16" else "f32"),
+        "data": "synthetic (seeded; shapes of the paper's workloads)",
+        "config": {"workload": f"moments_{w.name}", "num_chains": w.num_chains, "dim": w.dim, "n_rows": w.n_rows,
+                   "num_leapfrog_steps": w.num_leapfrog_steps, "num_burnin": w.num_burnin, "num_results": R,
+                   "adapt": "dual averaging to 0.8" if w.adapt else "none", "ring_rows": args.ring_rows,
+                   "form": {hmc.HMC_FORM_PLAIN: "plain", hmc.HMC_FORM_GRAPH: "graph",
+                            hmc.HMC_FORM_FUSED: "fused"}[hmc.hmc_effective_form(s.ctx)],
+                   "parallelism": "chains (1 GPU)"},
+        "roofline": {"bound": bound, "achieved": achieved / scale, "peak": peak / scale,
+                     "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": "transition kernels + moment fold", "kernel_ms_per_launch": kernel_ms,
+                     "work_per_launch": per_cs * w.chain_steps()},
+        "moments": {"max_split_rhat": summ["max_rhat"], "min_ess_batch": summ.get("min_ess_batch"),
+                    "batches": nb, "sample_bytes_not_stored": R * w.num_chains * w.dim * es,
+                    "ring_bytes": args.ring_rows * w.num_chains * w.dim * es},
+    }
+    s.close()
+    return result
+
+
+def to_host(t):
+    return t.detach().cpu().numpy()
+
+
 def bench_served(args):
     """Served stream: requests arrive by a seeded Poisson process; each is
     submitted to the continuous-batching server at its arrival time.  Reports
@@ -290,6 +371,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="run the library's autotuner before timing")
     ap.add_argument("--ess-results", type=int, default=9000,
                     help="kept draws of the separate ESS run (same burn-in); 0 skips it")
+    ap.add_argument("--moments", action="store_true",
+                    help="streaming expectations: moments through a ring instead of stored samples")
+    ap.add_argument("--ring-rows", type=int, default=64, help="--moments: kept states per fold")
     ap.add_argument("--remc", type=int, default=0,
                     help="replica exchange with this many replicas (divides the workload's chains)")
     ap.add_argument("--remc-beta-min", type=float, default=0.1, help="smallest inverse temperature of the ladder")
@@ -316,6 +400,9 @@ def main():
         return
     if args.remc > 0:
         print(json.dumps(bench_remc(args)), flush=True)
+        return
+    if args.moments:
+        print(json.dumps(bench_moments(args)), flush=True)
         return
     if args.config == "copy_calibration":
         # a plain device-to-device copy of known size: the reference for scaling

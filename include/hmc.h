@@ -240,6 +240,48 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
                                  const hmc_adapt* adapt, void* samples, const hmc_trace* trace,
                                  uint8_t* swapped);
 
+/* Transformed kernel (the paper's TransformedTransitionKernel, Sec. 4.1) with
+ * the diagonal affine bijector x = shift + scale * z: the chain moves in z
+ * with identity mass against the pulled-back target and reports x.  Run in
+ * x, scale_d multiplies the step size in the drift and in the kick of
+ * dimension d (a diagonal preconditioner); the shift drops out of the
+ * dynamics.  scale (device, FP64, [D]) is copied; every value finite and
+ * > 0.  NULL restores the identity.  Plain and graph forms with FP32
+ * gradients (HMC_E_UNSUPPORTED otherwise).  Synchronizes the stream. */
+hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale);
+
+/* ---------------------------------------------------------------------------
+ * Streaming expectations: the driver the paper plans (Sec. 4.2) for runs
+ * whose full trace would be too large to store.  sample_chain keeps no
+ * samples; per chain c and state variable d it accumulates over the kept
+ * draws r = 0 .. R-1, in FP64:
+ *   mean[h, c, d], m2[h, c, d]  mean and sum of squared deviations of the
+ *       draws of half h (h = 0: r < R/2, h = 1: r >= R/2, R/2 rounded down),
+ *       by Welford's update in draw order;
+ *   batch_sum[b, c, d]  (optional) the sum of the draws of batch
+ *       b = r / batch_len (R a multiple of batch_len).
+ * The kept states pass through ring (caller-provided, [ring_rows, C, D] of
+ * the state dtype): the transitions write up to ring_rows states into it and
+ * one kernel folds them into the accumulators in order, so the result does
+ * not depend on ring_rows.  The accumulators are cleared by the call.
+ * ------------------------------------------------------------------------- */
+typedef struct hmc_moments {
+    double* mean;                /* [2, C, D] device */
+    double* m2;                  /* [2, C, D] device */
+    double* batch_sum;           /* [R / batch_len, C, D] device, or NULL */
+    int64_t batch_len;           /* draws per batch when batch_sum is set */
+    void* ring;                  /* [ring_rows, C, D] device, state dtype */
+    int64_t ring_rows;           /* >= 1 */
+} hmc_moments;
+
+/* As hmc_sample_chain (same transitions, adaptation and traces; t advances by
+ * burn-in + R) with the kept states reduced into moments instead of stored.
+ * HMC_E_INVALID for missing buffers, ring_rows < 1, batch_len not dividing
+ * R.  Asynchronous. */
+hmc_status hmc_sample_chain_moments(hmc_ctx* ctx, int64_t num_results, int64_t num_burnin_steps,
+                                    const hmc_adapt* adapt, const hmc_moments* moments,
+                                    const hmc_trace* trace);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of sampling requests (one sample_chain each)
  * of differing target, dimension, data size and chain count on one GPU.

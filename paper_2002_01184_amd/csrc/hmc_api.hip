@@ -1,5 +1,6 @@
 // hmc_api.hip -- the C ABI of libhmc.so (include/hmc.h): argument checks,
 // workspace layout, form selection and stream-ordered launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <chrono>
@@ -106,6 +107,8 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
     w.ctrl = (Ctrl*)take(sizeof(Ctrl));
     w.beta_buf = (double*)take((size_t)C * 8);
     w.beta = nullptr;
+    w.scale_buf = (double*)take((size_t)D * 8);
+    w.scale = nullptr;
     w.bytes = off;
     if (total) *total = off;
     return w;
@@ -516,7 +519,7 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache_locked();
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end() && !(ctx->a.ws.beta && it->second.form == HMC_FORM_FUSED)) {
+        if (it != g_tune_cache.end() && !((ctx->a.ws.beta || ctx->a.ws.scale) && it->second.form == HMC_FORM_FUSED)) {
             ctx->form = it->second.form;
             ctx->a.tune = it->second.tune;
             drop_graph(ctx);
@@ -528,7 +531,8 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
     std::vector<TuneChoice> cands;
     std::vector<int32_t> forms;
     if (ctx->cfg.form == HMC_FORM_AUTO) {
-        if (fused_supported(ctx->a) && !ctx->a.ws.beta) forms.push_back(HMC_FORM_FUSED);   // tempered: plain kernels
+        if (fused_supported(ctx->a) && !ctx->a.ws.beta && !ctx->a.ws.scale)   // tempered / transformed: plain kernels
+        forms.push_back(HMC_FORM_FUSED);
         forms.push_back(HMC_FORM_PLAIN);
         forms.push_back(HMC_FORM_GRAPH);
     } else {
@@ -702,3 +706,81 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Streaming expectations: burn-in, then the kept transitions in chunks of the
+// ring's rows, each chunk written into the ring by the form's own kernels and
+// folded into the moments by k_moments.
+// ---------------------------------------------------------------------------
+extern "C" hmc_status hmc_sample_chain_moments(hmc_ctx* ctx, int64_t num_results, int64_t num_burnin_steps,
+                                               const hmc_adapt* adapt, const hmc_moments* moments,
+                                               const hmc_trace* trace) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (!moments || !moments->mean || !moments->m2 || !moments->ring)
+        return fail(HMC_E_INVALID, "moments, mean, m2 and ring must not be NULL");
+    if (moments->ring_rows < 1) return fail(HMC_E_INVALID, "ring_rows must be >= 1");
+    if (num_results < 0 || num_burnin_steps < 0) return fail(HMC_E_INVALID, "negative transition count");
+    if (moments->batch_sum && (moments->batch_len < 1 || num_results % moments->batch_len != 0))
+        return fail(HMC_E_INVALID, "batch_len must be >= 1 and divide num_results");
+    if (adapt && adapt->enabled && check_adapt(adapt) != HMC_OK) return HMC_E_INVALID;
+    if (ctx->t + (uint64_t)(num_results + num_burnin_steps) > 0xffffffffull)
+        return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
+    const int64_t n_el = ctx->a.C * ctx->a.tg.D;
+    hmc_status st = check_hip(launch_fill_f64(moments->mean, 2 * n_el, ctx->stream), "clear moments");
+    if (st == HMC_OK) st = check_hip(launch_fill_f64(moments->m2, 2 * n_el, ctx->stream), "clear moments");
+    if (st == HMC_OK && moments->batch_sum)
+        st = check_hip(launch_fill_f64(moments->batch_sum, (num_results / moments->batch_len) * n_el, ctx->stream),
+                       "clear batch sums");
+    if (st == HMC_OK && num_burnin_steps > 0) st = hmc_sample_chain(ctx, 0, num_burnin_steps, adapt, nullptr, nullptr);
+    for (int64_t r0 = 0; r0 < num_results && st == HMC_OK; r0 += moments->ring_rows) {
+        const int64_t q = std::min<int64_t>(moments->ring_rows, num_results - r0);
+        hmc_trace tr;
+        memset(&tr, 0, sizeof(tr));
+        if (trace) {
+            const size_t off = (size_t)r0 * ctx->a.C;
+            tr.step_size = trace->step_size ? trace->step_size + off : nullptr;
+            tr.is_accepted = trace->is_accepted ? trace->is_accepted + off : nullptr;
+            tr.log_accept_ratio = trace->log_accept_ratio ? trace->log_accept_ratio + off : nullptr;
+            tr.target_log_prob = trace->target_log_prob ? trace->target_log_prob + off : nullptr;
+        }
+        st = hmc_sample_chain(ctx, q, 0, nullptr, moments->ring, &tr);
+        if (st == HMC_OK)
+            st = check_hip(launch_moments(ctx->a, moments->ring, q, r0, num_results, *moments, ctx->stream),
+                           "fold moments");
+    }
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// Transformed kernel (paper Sec. 4.1) with the diagonal affine bijector
+// x = shift + scale z, run in x: the momentum lives in z, so scale multiplies
+// the momentum in every drift and the gradient in every kick (the shift drops
+// out).  Plain and graph forms, FP32 gradients.
+// ---------------------------------------------------------------------------
+extern "C" hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (!scale) {
+        ctx->a.ws.scale = nullptr;
+        drop_graph(ctx);
+        return HMC_OK;
+    }
+    if (ctx->form == HMC_FORM_FUSED)
+        return fail(HMC_E_UNSUPPORTED,
+                    "the transformed kernel runs on the plain or graph form: create the context with "
+                    "HMC_FORM_PLAIN or HMC_FORM_GRAPH");
+    if (ctx->a.bf16_grad) return fail(HMC_E_UNSUPPORTED, "the transformed kernel needs FP32 gradients");
+    std::vector<double> h((size_t)ctx->a.tg.D);
+    hmc_status st = check_hip(hipMemcpyAsync(h.data(), scale, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream),
+                              "read scale");
+    if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "read scale");
+    if (st != HMC_OK) return st;
+    for (double v : h)
+        if (!(v > 0.0) || !std::isfinite(v)) return fail(HMC_E_INVALID, "scale must be finite and > 0");
+    st = check_hip(hipMemcpyAsync(ctx->a.ws.scale_buf, h.data(), h.size() * 8, hipMemcpyHostToDevice, ctx->stream),
+                   "set scale");
+    if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "set scale");
+    if (st != HMC_OK) return st;
+    ctx->a.ws.scale = ctx->a.ws.scale_buf;
+    drop_graph(ctx);
+    return HMC_OK;
+}

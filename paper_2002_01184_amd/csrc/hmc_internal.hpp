@@ -47,6 +47,8 @@ struct Workspace {
     Ctrl* ctrl;
     double* beta_buf;  // [C] inverse temperatures (replica exchange)
     double* beta;      // beta_buf once temperatures are set, else NULL (every chain at beta = 1)
+    double* scale_buf; // [D] diagonal scale of the transformed kernel
+    double* scale;     // scale_buf once a transform is set, else NULL (identity)
     size_t bytes;
 };
 
@@ -84,6 +86,11 @@ hipError_t launch_set_ctrl(const Ctrl& c, Ctrl* dst, hipStream_t s);
 hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s);
 hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipStream_t s);
 hipError_t launch_da_init(const PlainArgs& a, hipStream_t s);
+// Streaming moments: fold q kept states (ring rows 0..q-1 = draws r0..r0+q-1
+// of R) into the per-half Welford accumulators and the batch sums.
+hipError_t launch_moments(const PlainArgs& a, const void* ring, int64_t q, int64_t r0, int64_t R,
+                          const hmc_moments& m, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s);
 // Replica exchange step (K replicas of M chains, replica-major) with swap index t.
 hipError_t launch_remc_swap(const PlainArgs& a, int64_t K, int64_t M, uint32_t t, uint8_t* swapped,
                             hipStream_t s);

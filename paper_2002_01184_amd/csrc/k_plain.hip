@@ -14,6 +14,10 @@
 // exchange step moves states without recomputing anything.  With no
 // temperatures set (ws.beta == NULL) every factor is exactly 1.
 //
+// Transformed kernel (diagonal affine bijector x = shift + scale z, Sec. 4.1):
+// the momentum is that of z, so scale_d multiplies eps in the drift and the
+// kick of dimension d; with no transform (ws.scale == NULL) nothing changes.
+//
 // Gradient kernels:
 //   elementwise   N(0, I) and diagonal Gaussians: one thread per (chain, dim)
 //   dense         g = -P x on MFMA (v_mfma_f32_16x16x4f32), 16 chains per workgroup
@@ -64,7 +68,8 @@ __global__ __launch_bounds__(256) void k_begin(PlainArgs a) {
                     const int64_t i = c * D + d;
                     xq[i] = x[i];
                     k0 += 0.5 * (double)z[j] * (double)z[j];
-                    pq[i] = z[j] + half_eps * g[i];
+                    const T hk = a.ws.scale ? (T)(0.5 * a.ws.eps[c] * bt * a.ws.scale[d]) : half_eps;
+                    pq[i] = z[j] + hk * g[i];
                 }
             }
         }
@@ -253,12 +258,13 @@ __global__ __launch_bounds__(256) void k_elem_leapfrog(PlainArgs a, const T* __r
     const bool diag = a.tg.kind == HMC_TGT_GAUSS_DIAG;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = i / D;
-        const T eps = (T)a.ws.eps[c];
+        const double sd = a.ws.scale ? a.ws.scale[i - c * D] : 1.0;
+        const T eps = a.ws.scale ? (T)(a.ws.eps[c] * sd) : (T)a.ws.eps[c];
         T x = xs[i];
         T p = (mode & 3) ? pd[i] : (T)0;
         if (mode & 1) x = fma(eps, p, x);
         const T gv = diag ? -prec[i - c * D] * x : -x;
-        if (mode & 2) p = fma((T)(kick_scale * a.ws.eps[c] * (a.ws.beta ? a.ws.beta[c] : 1.0)), gv, p);
+        if (mode & 2) p = fma((T)(kick_scale * a.ws.eps[c] * (a.ws.beta ? a.ws.beta[c] : 1.0) * sd), gv, p);
         if (mode & 1) xd[i] = x;
         if (mode & 2) pd[i] = p;
         if (gd) gd[i] = gv;
@@ -298,7 +304,8 @@ __global__ __launch_bounds__(256) void k_dense_leapfrog(PlainArgs a, const float
             const bool ok = mt < ntiles && d < D && cvalid;
             float xv = ok ? xsrc[c * D + d] : 0.f;
             float pv = (ok && (mode & 3)) ? pd[c * D + d] : 0.f;
-            if (mode & 1) xv = fmaf(eps, pv, xv);
+            const float ed = (ok && a.ws.scale) ? (float)(a.ws.eps[c] * a.ws.scale[d]) : eps;
+            if (mode & 1) xv = fmaf(ed, pv, xv);
             xr[m][v] = xv;
             pr[m][v] = pv;
             if (mt < ntiles) xs[(16 * mt + 4 * g4 + v) * 17 + i16] = xv;
@@ -327,8 +334,11 @@ __global__ __launch_bounds__(256) void k_dense_leapfrog(PlainArgs a, const float
             const int64_t d = 16 * mt + 4 * g4 + v;
             if (!(d < D && cvalid)) continue;
             const float gv = -(acc0[v] + acc1[v]);
+            const float kd = a.ws.scale ? (float)(kick_scale * a.ws.eps[c] * (a.ws.beta ? a.ws.beta[c] : 1.0) *
+                                                  a.ws.scale[d])
+                                        : keps;
             if (mode & 1) xdst[c * D + d] = xr[m][v];
-            if (mode & 2) pd[c * D + d] = fmaf(keps, gv, pr[m][v]);
+            if (mode & 2) pd[c * D + d] = fmaf(kd, gv, pr[m][v]);
             if (gd) gd[c * D + d] = gv;
         }
     }
@@ -387,7 +397,8 @@ __global__ __launch_bounds__(256) void k_logreg_partial(PlainArgs a, const float
         if (d < D && c < C) {
             v = xsrc[c * D + d];
             // the drift is recomputed (same fmaf) and stored by k_logreg_finish
-            if (drift) v = fmaf((float)a.ws.eps[c], psrc[c * D + d], v);
+            if (drift)
+                v = fmaf(a.ws.scale ? (float)(a.ws.eps[c] * a.ws.scale[d]) : (float)a.ws.eps[c], psrc[c * D + d], v);
         }
         th[d * 17 + j] = v;
     }
@@ -471,16 +482,17 @@ __global__ __launch_bounds__(256) void k_logreg_finish(PlainArgs a, float* __res
     const int64_t n = C * D;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = i / D;
+        const double sd = a.ws.scale ? a.ws.scale[i - c * D] : 1.0;
         float x = xd[i];
         const float p = (drift || kick) ? pd[i] : 0.f;
         if (drift) {
-            x = fmaf((float)a.ws.eps[c], p, x);
+            x = fmaf(a.ws.scale ? (float)(a.ws.eps[c] * sd) : (float)a.ws.eps[c], p, x);
             xd[i] = x;
         }
         float gsum = 0.f;
         for (int s = 0; s < nsplit; ++s) gsum += a.ws.part_g[(int64_t)s * n + i];
         const float gv = gsum - x * (float)a.tg.inv_var;
-        if (kick) pd[i] = fmaf((float)(kick_scale * a.ws.eps[c] * (a.ws.beta ? a.ws.beta[c] : 1.0)), gv, p);
+        if (kick) pd[i] = fmaf((float)(kick_scale * a.ws.eps[c] * (a.ws.beta ? a.ws.beta[c] : 1.0) * sd), gv, p);
         if (gd) gd[i] = gv;
         if (want_logp && i - c * D == 0) {
             double l = 0.0;
@@ -609,6 +621,71 @@ hipError_t launch_set_ctrl(const Ctrl& c, Ctrl* dst, hipStream_t s) {
 
 hipError_t launch_da_init(const PlainArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_da_init<float>, dim3((unsigned)((a.C + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Streaming expectations: element e = (c, d) of q kept states in draw order.
+// Welford (1962): n-th draw of a half, delta = x - mean, mean += delta / n,
+// m2 += delta (x - mean); batch sums accumulate in a register and are added
+// to memory when the batch changes (a batch may span chunks).
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments(const T* __restrict__ ring, int64_t n_el, int64_t q, int64_t r0,
+                                                 int64_t R, double* __restrict__ mean, double* __restrict__ m2,
+                                                 double* __restrict__ bsum, int64_t blen) {
+    const int64_t half = R / 2;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_el; e += (int64_t)gridDim.x * blockDim.x) {
+        double mu[2] = {mean[e], mean[n_el + e]};
+        double ss[2] = {m2[e], m2[n_el + e]};
+        int64_t cur_b = -1;
+        double bacc = 0.0;
+        for (int64_t j = 0; j < q; ++j) {
+            const int64_t r = r0 + j;
+            const double x = (double)ring[j * n_el + e];
+            const int h = r < half ? 0 : 1;
+            const double n = (double)(h ? r - half + 1 : r + 1);
+            const double delta = x - mu[h];
+            mu[h] += delta / n;
+            ss[h] += delta * (x - mu[h]);
+            if (bsum) {
+                const int64_t b = r / blen;
+                if (b != cur_b) {
+                    if (cur_b >= 0) bsum[cur_b * n_el + e] += bacc;
+                    cur_b = b;
+                    bacc = 0.0;
+                }
+                bacc += x;
+            }
+        }
+        if (bsum && cur_b >= 0) bsum[cur_b * n_el + e] += bacc;
+        mean[e] = mu[0];
+        mean[n_el + e] = mu[1];
+        m2[e] = ss[0];
+        m2[n_el + e] = ss[1];
+    }
+}
+
+__global__ void k_fill_f64(double* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const PlainArgs& a, const void* ring, int64_t q, int64_t r0, int64_t R,
+                          const hmc_moments& m, hipStream_t s) {
+    const int64_t n_el = a.C * a.tg.D;
+    const int64_t blocks = (n_el + 255) / 256 < 8192 ? (n_el + 255) / 256 : 8192;
+    if (a.f64)
+        hipLaunchKernelGGL(k_moments<double>, dim3((unsigned)blocks), dim3(256), 0, s, (const double*)ring, n_el, q, r0,
+                           R, m.mean, m.m2, m.batch_sum, m.batch_len);
+    else
+        hipLaunchKernelGGL(k_moments<float>, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)ring, n_el, q, r0,
+                           R, m.mean, m.m2, m.batch_sum, m.batch_len);
     return hipGetLastError();
 }
 

@@ -186,3 +186,50 @@ def t_summarize(samples, progress=None) -> dict:
         if progress is not None:
             progress(d + 1, samples.shape[2])
     return dict(min_ess_bulk=float(np.min(e)), max_rhat=float(np.max(r)), ess_bulk=np.array(e), rhat=np.array(r))
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics from streamed moments (no stored samples): per chain and
+# coordinate the mean and sum of squared deviations of each half of the kept
+# draws, and optionally the sums of equal batches.
+# ---------------------------------------------------------------------------
+def moments_rhat(mean, m2, R: int) -> np.ndarray:
+    """Split R-hat per coordinate (Gelman et al. 2013, eq. 11.4, on the 2C half
+    chains; not rank-normalized) from mean/m2 [2, C, D] of halves of n = R // 2
+    draws (R even).  Equals the split R-hat of the samples themselves."""
+    mean = np.asarray(mean, dtype=np.float64)
+    m2 = np.asarray(m2, dtype=np.float64)
+    if R % 2:
+        raise ValueError("split R-hat from moments needs an even number of draws")
+    n = R // 2
+    mh = mean.reshape(-1, mean.shape[-1])          # [2C, D] half-chain means
+    s2 = m2.reshape(-1, m2.shape[-1]) / (n - 1)    # half-chain variances
+    W = s2.mean(0)
+    B = n * mh.var(0, ddof=1)
+    return np.sqrt(((n - 1) / n * W + B / n) / W)
+
+
+def moments_ess_batch(mean, m2, batch_sum, R: int, batch_len: int) -> np.ndarray:
+    """Batch-means ESS per coordinate, pooled over chains: M R s^2 / sigma2_BM with
+    s^2 the average within-chain variance and sigma2_BM = batch_len times the
+    variance of the batch means about their chain's mean (Flegal & Jones 2010)."""
+    mean = np.asarray(mean, dtype=np.float64)
+    m2 = np.asarray(m2, dtype=np.float64)
+    bs = np.asarray(batch_sum, dtype=np.float64)   # [a, C, D]
+    a = bs.shape[0]
+    h0 = R // 2
+    chain_mean = (h0 * mean[0] + (R - h0) * mean[1]) / R                      # [C, D]
+    # within-chain variance from the two halves (parallel-variance combination)
+    d = mean[1] - mean[0]
+    m2c = m2[0] + m2[1] + d * d * h0 * (R - h0) / R
+    s2 = (m2c / (R - 1)).mean(0)
+    bm = bs / batch_len
+    sig2 = batch_len * ((bm - chain_mean[None]) ** 2).sum(0).sum(0) / (bs.shape[1] * (a - 1))
+    return bs.shape[1] * R * s2 / sig2
+
+
+def moments_summary(mean, m2, R: int, batch_sum=None, batch_len=None) -> dict:
+    out = dict(max_rhat=float(np.max(moments_rhat(mean, m2, R))))
+    if batch_sum is not None:
+        out["min_ess_batch"] = float(np.min(moments_ess_batch(mean, m2, batch_sum, R, batch_len)))
+    return out

@@ -62,6 +62,11 @@ def make_adapt(adapt, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75, rate=0
     return hmc_adapt(1, kind, target_accept, gamma, t0, kappa, rate)
 
 
+class hmc_moments(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_void_p), ("m2", ctypes.c_void_p), ("batch_sum", ctypes.c_void_p),
+                ("batch_len", ctypes.c_int64), ("ring", ctypes.c_void_p), ("ring_rows", ctypes.c_int64)]
+
+
 class hmc_trace(ctypes.Structure):
     _fields_ = [("step_size", ctypes.c_void_p), ("is_accepted", ctypes.c_void_p),
                 ("log_accept_ratio", ctypes.c_void_p), ("target_log_prob", ctypes.c_void_p)]
@@ -89,7 +94,9 @@ HMC_REQ_QUEUED, HMC_REQ_RUNNING, HMC_REQ_DONE, HMC_REQ_FAILED = range(4)
 
 EXPORTED = ["hmc_workspace_size", "hmc_init", "hmc_step", "hmc_sample_chain", "hmc_get_state", "hmc_set_state",
             "hmc_destroy", "hmc_last_error", "hmc_effective_form", "hmc_autotune", "hmc_set_inverse_temperature",
-            "hmc_remc_swap", "hmc_remc_sample_chain", "hmc_server_create", "hmc_server_submit",
+            "hmc_remc_swap", "hmc_remc_sample_chain", "hmc_sample_chain_moments", "hmc_set_transform_scale",
+            "hmc_server_create",
+            "hmc_server_submit",
             "hmc_server_poll", "hmc_server_wait", "hmc_server_take", "hmc_server_get_stats",
             "hmc_server_destroy"]
 
@@ -129,6 +136,11 @@ def lib():
     L.hmc_effective_form.restype = ctypes.c_int32
     L.hmc_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]
     L.hmc_autotune.restype = st
+    L.hmc_sample_chain_moments.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(hmc_adapt),
+                                           ctypes.POINTER(hmc_moments), ctypes.POINTER(hmc_trace)]
+    L.hmc_sample_chain_moments.restype = st
+    L.hmc_set_transform_scale.argtypes = [vp, vp]
+    L.hmc_set_transform_scale.restype = st
     L.hmc_set_inverse_temperature.argtypes = [vp, vp]
     L.hmc_set_inverse_temperature.restype = st
     L.hmc_remc_swap.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp]
@@ -188,6 +200,13 @@ def hmc_sample_chain(ctx, num_results, num_burnin_steps, adapt: hmc_adapt | None
     _check(lib().hmc_sample_chain(ctx, num_results, num_burnin_steps,
                                   ctypes.byref(adapt) if adapt is not None else None, samples_ptr,
                                   ctypes.byref(trace) if trace is not None else None))
+
+
+def hmc_sample_chain_moments(ctx, num_results, num_burnin_steps, adapt: hmc_adapt | None, moments: hmc_moments,
+                             trace: hmc_trace | None):
+    _check(lib().hmc_sample_chain_moments(ctx, num_results, num_burnin_steps,
+                                          ctypes.byref(adapt) if adapt is not None else None, ctypes.byref(moments),
+                                          ctypes.byref(trace) if trace is not None else None))
 
 
 def hmc_set_inverse_temperature(ctx, beta_ptr):
@@ -351,6 +370,44 @@ class Sampler:
         hmc_sample_chain(self.ctx, R, num_burnin_steps, ad, _ptr(samples), tr)
         outs["samples"] = samples
         return outs
+
+    def sample_chain_moments(self, num_results, num_burnin_steps, adapt=False, target_accept=0.8, gamma=0.05,
+                             t0=10.0, kappa=0.75, rate=0.01, ring_rows=64, batch_len=None, trace=True):
+        """Streaming expectations: returns dict(mean [2, C, D], m2 [2, C, D] (FP64,
+        per half of the kept draws), batch_sum [R / batch_len, C, D] or None, and the
+        traces); no samples are stored."""
+        torch = self.torch
+        C, D, R = self.C, self.D, num_results
+        mean = torch.empty(2, C, D, dtype=torch.float64, device=self.device)
+        m2 = torch.empty(2, C, D, dtype=torch.float64, device=self.device)
+        bsum = None
+        if batch_len:
+            bsum = torch.empty(R // batch_len, C, D, dtype=torch.float64, device=self.device)
+        ring = torch.empty(max(1, min(ring_rows, max(R, 1))), C, D, dtype=self.dtype, device=self.device)
+        outs, tr = {}, None
+        if trace:
+            outs = dict(step_size=torch.empty(R, C, dtype=torch.float64, device=self.device),
+                        is_accepted=torch.empty(R, C, dtype=torch.uint8, device=self.device),
+                        log_accept_ratio=torch.empty(R, C, dtype=torch.float64, device=self.device),
+                        target_log_prob=torch.empty(R, C, dtype=torch.float64, device=self.device))
+            tr = hmc_trace(*[_ptr(outs[k]) for k in ("step_size", "is_accepted", "log_accept_ratio",
+                                                      "target_log_prob")])
+        mo = hmc_moments(_ptr(mean).value, _ptr(m2).value, None if bsum is None else _ptr(bsum).value,
+                         int(batch_len or 0), _ptr(ring).value, ring.shape[0])
+        ad = make_adapt(adapt, target_accept, gamma, t0, kappa, rate)
+        hmc_sample_chain_moments(self.ctx, R, num_burnin_steps, ad, mo, tr)
+        outs.update(mean=mean, m2=m2, batch_sum=bsum, ring=ring)
+        return outs
+
+    def set_transform_scale(self, scale):
+        """Diagonal affine bijector x = shift + scale * z (the shift does not enter
+        the dynamics): scale [D] (any array-like), or None for the identity."""
+        if scale is None:
+            _check(lib().hmc_set_transform_scale(self.ctx, None))
+            return
+        sc = self.torch.as_tensor(scale, dtype=self.torch.float64).to(self.device).contiguous()
+        self.keep.append(sc)
+        _check(lib().hmc_set_transform_scale(self.ctx, _ptr(sc)))
 
     def set_inverse_temperature(self, beta):
         """beta: [C] FP64 device tensor (one value per chain), or None for 1."""
