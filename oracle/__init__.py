@@ -19,11 +19,13 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 STD_NORMAL, GAUSS_DIAG, GAUSS_DENSE, LOGREG = 0, 1, 2, 3
 TAG_MOMENTUM, TAG_ACCEPT, TAG_SWAP = 0, 1, 2
+TAG_NUTS_MERGE, TAG_NUTS_DIR, TAG_NUTS_TOP, TAG_NUTS_SLICE = 3, 4, 5, 6
 ADAPT_NONE, ADAPT_DUAL_AVERAGING, ADAPT_SIMPLE = 0, 1, 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
+_i32p = ctypes.POINTER(ctypes.c_int32)
 
 
 class _Target(ctypes.Structure):
@@ -76,6 +78,13 @@ def lib():
         L.orc_simple_adapt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_simple_adapt.restype = ctypes.c_double
         L.orc_sample_chain.restype = ctypes.c_int
+        L.orc_nuts_transition.argtypes = [ctypes.POINTER(_Target), ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_double, ctypes.c_int32, _dp, _dp, _dp, _i32p, _i32p]
+        L.orc_nuts_transition.restype = ctypes.c_int
+        L.orc_nuts_sample_chain.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+                                            _dp, _dp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _dp, _i32p,
+                                            _i32p, ctypes.c_int32]
+        L.orc_nuts_sample_chain.restype = ctypes.c_int
         L.orc_remc_swap.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_uint32, _dp, _dp, _dp, _u8p]
         L.orc_remc_sample_chain.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int64,
@@ -349,3 +358,34 @@ def transformed_sample_chain(tg: Target, scale, shift, L: int, seed: int, x0, ep
         r["samples"] = mu + s * r["samples"]
     r["final_x"] = mu + s * r["final_x"]
     return r
+
+
+# ------------------------------------------------------------------- NUTS --
+def nuts_transition(tg: Target, seed: int, chain: int, t: int, eps: float, max_depth: int, x, logp=None, g=None):
+    """One NUTS transition of one chain.  Returns dict(x, logp, g, moved, depth, n_leapfrog)."""
+    x = _f64(x).copy()
+    if logp is None or g is None:
+        logp, g = logp_grad(tg, x)
+    g = _f64(g).copy()
+    lp = ctypes.c_double(float(logp))
+    dep = ctypes.c_int32(0)
+    nl = ctypes.c_int32(0)
+    moved = lib().orc_nuts_transition(tg.c, seed, chain, t, eps, max_depth, _p(x), ctypes.byref(lp), _p(g),
+                                      ctypes.byref(dep), ctypes.byref(nl))
+    return dict(x=x, logp=lp.value, g=g, moved=bool(moved), depth=dep.value, n_leapfrog=nl.value)
+
+
+def nuts_sample_chain(tg: Target, seed: int, x0, eps0, num_burnin: int, num_results: int, max_depth: int = 10,
+                      t_begin: int = 0, nthreads: int = 0):
+    """Oracle NUTS sample_chain (fixed step size).  Returns dict(samples [R,C,D],
+    depth [R,C], n_leapfrog [R,C], final_x)."""
+    x = _f64(x0).copy()
+    C, D = x.shape
+    eps = np.broadcast_to(_f64(eps0), (C,)).copy()
+    R = num_results
+    samples = np.empty((R, C, D))
+    dep = np.empty((R, C), dtype=np.int32)
+    nl = np.empty((R, C), dtype=np.int32)
+    lib().orc_nuts_sample_chain(tg.c, C, seed, t_begin, _p(x), _p(eps), max_depth, num_burnin, num_results,
+                                _p(samples), _p(dep, _i32p), _p(nl, _i32p), nthreads)
+    return dict(samples=samples, depth=dep, n_leapfrog=nl, final_x=x)

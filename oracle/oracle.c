@@ -518,3 +518,187 @@ int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L
     free(swp);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * No-U-Turn sampler, Hoffman & Gelman (2014), Algorithm 3 (the paper's
+ * Sec. 3.2 case study vectorises this recursion).  A state carries its
+ * position, momentum, gradient and log-probability so that each leapfrog
+ * step starts from the cached gradient.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double *x, *r, *g;
+    double logp;
+} nuts_pt;
+
+typedef struct {
+    const orc_target *tg;
+    uint64_t seed;
+    uint32_t chain, t;
+    int32_t doubling;      /* j of the top-level loop */
+    int32_t leaves;        /* leaves built so far in this doubling */
+    int32_t n_leapfrog;
+    double eps, log_u;
+    int64_t D;
+} nuts_ctx;
+
+static nuts_pt pt_new(int64_t D)
+{
+    nuts_pt p;
+    p.x = (double *)malloc(sizeof(double) * (size_t)D);
+    p.r = (double *)malloc(sizeof(double) * (size_t)D);
+    p.g = (double *)malloc(sizeof(double) * (size_t)D);
+    p.logp = 0.0;
+    return p;
+}
+
+static void pt_free(nuts_pt *p)
+{
+    free(p->x);
+    free(p->r);
+    free(p->g);
+}
+
+static void pt_copy(nuts_pt *dst, const nuts_pt *src, int64_t D)
+{
+    memcpy(dst->x, src->x, sizeof(double) * (size_t)D);
+    memcpy(dst->r, src->r, sizeof(double) * (size_t)D);
+    memcpy(dst->g, src->g, sizeof(double) * (size_t)D);
+    dst->logp = src->logp;
+}
+
+/* 52-bit uniform of block (chain, t, block, tag), as the accept uniform */
+static double uniform52_block(uint64_t seed, uint32_t chain, uint32_t t, uint32_t block, uint32_t tag)
+{
+    uint32_t w[4];
+    philox_block(seed, chain, t, block, tag, w);
+    double k = (double)(w[0] >> 6) * 67108864.0 + (double)(w[1] >> 6);
+    return (k + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+/* no-U-turn indicator of a span from its backward end m to its forward end p */
+static int no_uturn(const nuts_pt *m, const nuts_pt *p, int64_t D)
+{
+    double dm = 0.0, dp = 0.0;
+    for (int64_t i = 0; i < D; ++i) {
+        double dx = p->x[i] - m->x[i];
+        dm += dx * m->r[i];
+        dp += dx * p->r[i];
+    }
+    return dm >= 0.0 && dp >= 0.0;
+}
+
+/* BuildTree(state, v, depth): extends from `edge` (updated in place to the
+ * subtree's far end in direction v); `cand` receives the subtree's candidate;
+ * the subtree's near end (first leaf) is written to `first` when not NULL. */
+static void nuts_build(nuts_ctx *c, nuts_pt *edge, int v, int depth, nuts_pt *cand, nuts_pt *first,
+                       int32_t *n_out, int32_t *s_out)
+{
+    const int64_t D = c->D;
+    if (depth == 0) {
+        orc_leapfrog(c->tg, v * c->eps, 1, edge->x, edge->r, edge->g, &edge->logp);
+        c->n_leapfrog += 1;
+        c->leaves += 1;
+        double H = -edge->logp + kinetic(edge->r, D);
+        *n_out = (c->log_u <= -H) ? 1 : 0;
+        *s_out = (c->log_u < 1000.0 - H) ? 1 : 0;     /* NaN H fails both */
+        pt_copy(cand, edge, D);
+        if (first)
+            pt_copy(first, edge, D);
+        return;
+    }
+    nuts_pt first_half_start = pt_new(D);
+    int32_t n1, s1;
+    nuts_build(c, edge, v, depth - 1, cand, &first_half_start, &n1, &s1);
+    if (first)
+        pt_copy(first, &first_half_start, D);
+    if (s1) {
+        nuts_pt cand2 = pt_new(D);
+        int32_t n2, s2;
+        nuts_build(c, edge, v, depth - 1, &cand2, NULL, &n2, &s2);
+        /* merged at the last leaf of the second half */
+        const uint32_t i = (uint32_t)(c->leaves - 1);
+        const uint32_t block = ((uint32_t)c->doubling * 1024u + i) * 16u + (uint32_t)depth;
+        const double u = uniform52_block(c->seed, c->chain, c->t, block, ORC_TAG_NUTS_MERGE);
+        if (n1 + n2 > 0 && u < (double)n2 / (double)(n1 + n2))
+            pt_copy(cand, &cand2, D);
+        /* span of the merged subtree: from its first leaf to its last (= edge) */
+        const nuts_pt *m = (v > 0) ? &first_half_start : edge;
+        const nuts_pt *p = (v > 0) ? edge : &first_half_start;
+        s1 = s2 && no_uturn(m, p, D);
+        n1 += n2;
+        pt_free(&cand2);
+    }
+    pt_free(&first_half_start);
+    *n_out = n1;
+    *s_out = s1;
+}
+
+int orc_nuts_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uint32_t t, double eps,
+                        int32_t max_depth, double *x, double *logp, double *g, int32_t *depth,
+                        int32_t *n_leapfrog)
+{
+    const int64_t D = tg->dim;
+    nuts_ctx c = {tg, seed, chain, t, 0, 0, 0, eps, 0.0, D};
+    nuts_pt minus = pt_new(D), plus = pt_new(D), cand = pt_new(D), chosen = pt_new(D);
+    memcpy(minus.x, x, sizeof(double) * (size_t)D);
+    memcpy(minus.g, g, sizeof(double) * (size_t)D);
+    minus.logp = *logp;
+    orc_momentum(seed, chain, t, D, minus.r);
+    pt_copy(&plus, &minus, D);
+    pt_copy(&chosen, &minus, D);
+    const double H0 = -(*logp) + kinetic(minus.r, D);
+    c.log_u = log(uniform52_block(seed, chain, t, 0, ORC_TAG_NUTS_SLICE)) - H0;
+    int32_t n = 1, s = 1, j = 0, moved = 0;
+    while (s && j < max_depth) {
+        const int v = uniform52_block(seed, chain, t, (uint32_t)j, ORC_TAG_NUTS_DIR) < 0.5 ? -1 : 1;
+        c.doubling = j;
+        c.leaves = 0;
+        int32_t n1, s1;
+        nuts_build(&c, v > 0 ? &plus : &minus, v, j, &cand, NULL, &n1, &s1);
+        if (s1 && uniform52_block(seed, chain, t, (uint32_t)j, ORC_TAG_NUTS_TOP) < (double)n1 / (double)n) {
+            pt_copy(&chosen, &cand, D);
+            moved = 1;
+        }
+        n += n1;
+        s = s1 && no_uturn(&minus, &plus, D);
+        j += 1;
+    }
+    memcpy(x, chosen.x, sizeof(double) * (size_t)D);
+    memcpy(g, chosen.g, sizeof(double) * (size_t)D);
+    *logp = chosen.logp;
+    if (depth) *depth = j;
+    if (n_leapfrog) *n_leapfrog = c.n_leapfrog;
+    pt_free(&minus);
+    pt_free(&plus);
+    pt_free(&cand);
+    pt_free(&chosen);
+    return moved;
+}
+
+int orc_nuts_sample_chain(const orc_target *tg, int64_t C, uint64_t seed, uint32_t t_begin, double *x,
+                          const double *eps, int32_t max_depth, int64_t num_burnin, int64_t num_results,
+                          double *samples, int32_t *tr_depth, int32_t *tr_nleap, int32_t nthreads)
+{
+    const int64_t D = tg->dim;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < C; ++c) {
+        double *xc = x + c * D;
+        double *gc = (double *)malloc(sizeof(double) * (size_t)D);
+        double lp = orc_logp_grad(tg, xc, gc);
+        for (int64_t i = 0; i < num_burnin + num_results; ++i) {
+            int32_t dep, nl;
+            orc_nuts_transition(tg, seed, (uint32_t)c, t_begin + (uint32_t)i, eps[c], max_depth, xc, &lp, gc,
+                                &dep, &nl);
+            if (i >= num_burnin) {
+                int64_t r = i - num_burnin;
+                if (samples)
+                    memcpy(samples + (r * C + c) * D, xc, sizeof(double) * (size_t)D);
+                if (tr_depth) tr_depth[r * C + c] = dep;
+                if (tr_nleap) tr_nleap[r * C + c] = nl;
+            }
+        }
+        free(gc);
+    }
+    return 0;
+}

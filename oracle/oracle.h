@@ -180,6 +180,36 @@ int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L
                           double t0, double kappa, double rate, double *samples, uint8_t *tr_acc,
                           uint8_t *tr_swap, int32_t nthreads);
 
+/* ---- No-U-Turn sampler (paper Sec. 3.2; Hoffman & Gelman 2014, Algorithm 3,
+ * "efficient NUTS") ----
+ * One transition of one chain from (x, *logp, g): momentum r0 as HMC's;
+ * slice log u = log U - H0 with U the uniform of block (chain, t, 0, tag 6);
+ * doubling j = 0, 1, ... picks direction v = -1 when the uniform of block
+ * (chain, t, j, tag 4) is below 1/2, else +1, and builds a subtree of 2^j
+ * leapfrog steps of size v eps from the trajectory's end in that direction by
+ * the recursive BuildTree; a leaf counts (n' = 1) when log u <= -H and
+ * continues (s' = 1) when log u < 1000 - H; merging two halves of a subtree
+ * takes the second half's candidate with probability n''/(n' + n'') (uniform
+ * of block (chain, t, (j * 1024 + i) * 16 + k, tag 3), i the index of the
+ * subtree's last leaf within doubling j, k the merged subtree's depth) and
+ * ends the subtree when (x+ - x-).r- < 0 or (x+ - x-).r+ < 0; the transition
+ * takes the subtree's candidate with probability min(1, n'/n) (uniform of block
+ * (chain, t, j, tag 5)) when s' = 1, then stops when s' = 0, the whole
+ * trajectory makes a U-turn, or j reaches max_depth.  (x, logp, g) become the
+ * chosen state's; *depth receives the number of doublings, *n_leapfrog the
+ * leapfrog steps taken.  Returns 1 if the state moved. */
+enum { ORC_TAG_NUTS_MERGE = 3, ORC_TAG_NUTS_DIR = 4, ORC_TAG_NUTS_TOP = 5, ORC_TAG_NUTS_SLICE = 6 };
+int orc_nuts_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uint32_t t, double eps,
+                        int32_t max_depth, double *x, double *logp, double *g, int32_t *depth,
+                        int32_t *n_leapfrog);
+
+/* NUTS sample_chain with a fixed step size per chain (eps [C]): transitions
+ * t_begin .. t_begin + burnin + results - 1; samples [R*C*D], depth and
+ * n_leapfrog traces [R*C] (each may be NULL).  x holds the final state. */
+int orc_nuts_sample_chain(const orc_target *tg, int64_t C, uint64_t seed, uint32_t t_begin, double *x,
+                          const double *eps, int32_t max_depth, int64_t num_burnin, int64_t num_results,
+                          double *samples, int32_t *tr_depth, int32_t *tr_nleap, int32_t nthreads);
+
 #ifdef __cplusplus
 }
 #endif
