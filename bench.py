@@ -297,6 +297,82 @@ def bench_moments(args):
     return result
 
 
+def bench_nuts(args):
+    """No-U-Turn sampler (paper Sec. 3.2) on a workload with its step size:
+    burn-in + results transitions of the unrolled tree on the plain kernels,
+    timed with HIP events; value = leapfrog chain-steps actually taken per
+    second (chains stop at different depths; the lockstep schedule runs the
+    deepest chain's leaves for all)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2002_01184_amd import diagnostics as dg
+    from paper_2002_01184_amd import hmc
+
+    w = W.CONFIGS[args.config]()
+    if args.transitions is not None:
+        w.num_burnin = min(w.num_burnin, args.transitions // 2)
+        w.num_results = args.transitions - w.num_burnin
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN, grad_bf16=args.grad == "bf16")
+    x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).cuda()
+    eps0 = torch.full((w.num_chains,), w.step_size, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run(ev=None):
+        s.set_state(x0, eps0, 0)
+        if ev is not None:
+            ev[0].record(stream)
+        out = s.nuts_sample_chain(w.num_results, w.num_burnin, max_depth=args.nuts)
+        if ev is not None:
+            ev[1].record(stream)
+        return out
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    out = None
+    for k in range(args.steps):
+        out = run(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    nleap = to_host(out["n_leapfrog"]).astype(np.float64)
+    depth = to_host(out["tree_depth"])
+    # leapfrog steps of the kept transitions, scaled to the whole run by its length
+    steps_run = nleap.mean() * w.num_chains * (w.num_burnin + w.num_results)
+    bound, per_cs, unit = algorithmic_work(w)
+    achieved = per_cs * steps_run / (kernel_ms * 1e-3)
+    peak = PEAK["hbm"] if bound == "hbm" else (PEAK["bf16_mfma"] if args.grad == "bf16" else PEAK["fp32_mfma"])
+    scale = 1e9 if bound == "hbm" else 1e12
+    result = {
+        "metric": METRIC, "value": steps_run * args.steps / elapsed, "unit": "leapfrog chain-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if w.state_dtype == "f64" else ("bf16/f32" if args.grad == "bf16" else "f32"),
+        "data": "synthetic (seeded; shapes of the paper's workloads)",
+        "config": {"workload": f"nuts_{w.name}", "num_chains": w.num_chains, "dim": w.dim, "n_rows": w.n_rows,
+                   "max_tree_depth": args.nuts, "step_size": w.step_size, "num_burnin": w.num_burnin,
+                   "num_results": w.num_results, "form": "plain (unrolled tree, lockstep)",
+                   "parallelism": "chains (1 GPU)"},
+        "roofline": {"bound": bound, "achieved": achieved / scale, "peak": peak / scale,
+                     "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": "NUTS kernels + plain leapfrog kernels", "kernel_ms_per_launch": kernel_ms,
+                     "work_per_launch": per_cs * steps_run},
+        "nuts": {"mean_leapfrog_per_transition": float(nleap.mean()), "max_leapfrog": int(nleap.max()),
+                 "depth_histogram": np.bincount(depth.ravel()).tolist()},
+    }
+    if not args.no_diagnostics:
+        summ = dg.t_summarize(out["samples"])
+        result["max_rhat"] = summ["max_rhat"]
+        result["min_ess_bulk"] = summ["min_ess_bulk"]
+        result["ess_per_sec"] = summ["min_ess_bulk"] / (elapsed / args.steps) if summ["max_rhat"] <= 1.01 else None
+    s.close()
+    return result
+
+
 def to_host(t):
     return t.detach().cpu().numpy()
 
@@ -374,6 +450,7 @@ def main():
     ap.add_argument("--moments", action="store_true",
                     help="streaming expectations: moments through a ring instead of stored samples")
     ap.add_argument("--ring-rows", type=int, default=64, help="--moments: kept states per fold")
+    ap.add_argument("--nuts", type=int, default=0, help="No-U-Turn sampler with this max tree depth (1..10)")
     ap.add_argument("--remc", type=int, default=0,
                     help="replica exchange with this many replicas (divides the workload's chains)")
     ap.add_argument("--remc-beta-min", type=float, default=0.1, help="smallest inverse temperature of the ladder")
@@ -403,6 +480,9 @@ def main():
         return
     if args.moments:
         print(json.dumps(bench_moments(args)), flush=True)
+        return
+    if args.nuts > 0:
+        print(json.dumps(bench_nuts(args)), flush=True)
         return
     if args.config == "copy_calibration":
         # a plain device-to-device copy of known size: the reference for scaling

@@ -251,6 +251,37 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
 hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale);
 
 /* ---------------------------------------------------------------------------
+ * No-U-Turn sampler (paper Sec. 3.2: NUTS with its recursion unrolled into a
+ * fixed O(max_tree_depth) per-chain memory; the algorithm is Hoffman & Gelman
+ * 2014, Algorithm 3, "efficient NUTS").  Each transition draws the momentum as
+ * HMC does, a slice variable log u = log U - H0, and doubles the trajectory
+ * (direction v = -1 or +1 per doubling) until the trajectory or one of its
+ * subtrees makes a U-turn, a leaf diverges (log u >= 1000 - H) or
+ * max_tree_depth doublings are done; the next state is drawn from the valid
+ * points of the trajectory by the algorithm's progressive sampling.  Random
+ * numbers: Philox4x32-10 with counter (chain, t, block, tag): momentum as
+ * HMC (tag 0), slice (block 0, tag 6), direction of doubling j (block j,
+ * tag 4), take of doubling j's subtree (block j, tag 5), merge of the level-k
+ * subtree ending at leaf i of doubling j (block (1024 j + i) 16 + k, tag 3).
+ * The step size is each chain's current step size (fixed; no adaptation).
+ * Chains run in lockstep on the plain kernels of the target; a chain whose
+ * trajectory has stopped is masked.  The context must have no inverse
+ * temperatures or transform (HMC_E_UNSUPPORTED).
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of the caller-allocated NUTS workspace for this context (256-byte
+ * aligned base).  max_depth in 0..10. */
+hmc_status hmc_nuts_workspace_size(const hmc_ctx* ctx, int32_t max_depth, size_t* bytes);
+
+/* burn-in + R NUTS transitions from the context's state; samples [R, C, D]
+ * (device, state dtype), tree_depth and n_leapfrog [R, C] (device int32: the
+ * doublings and leapfrog steps of each kept transition) may be NULL.  t
+ * advances by burn-in + R.  Synchronizes the stream after every doubling. */
+hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int64_t num_results, int64_t num_burnin_steps,
+                                 void* nuts_workspace, size_t nuts_workspace_bytes, void* samples,
+                                 int32_t* tree_depth, int32_t* n_leapfrog);
+
+/* ---------------------------------------------------------------------------
  * Streaming expectations: the driver the paper plans (Sec. 4.2) for runs
  * whose full trace would be too large to store.  sample_chain keeps no
  * samples; per chain c and state variable d it accumulates over the kept

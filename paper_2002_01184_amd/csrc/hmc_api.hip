@@ -784,3 +784,61 @@ extern "C" hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale)
     drop_graph(ctx);
     return HMC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// No-U-Turn sampler (paper Sec. 3.2): the unrolled tree on the plain kernels,
+// all chains in lockstep, a chain masked once its trajectory stops; the host
+// reads the number of chains still running after every doubling.
+// ---------------------------------------------------------------------------
+extern "C" hmc_status hmc_nuts_workspace_size(const hmc_ctx* ctx, int32_t max_depth, size_t* bytes) {
+    if (!ctx || !bytes) return fail(HMC_E_INVALID, "ctx and bytes must not be NULL");
+    if (max_depth < 0 || max_depth > 10) return fail(HMC_E_INVALID, "max_depth must be in 0..10");
+    carve_nuts(nullptr, ctx->a.C, ctx->a.tg.D, max_depth, ctx->a.f64 ? 8 : 4, bytes);
+    return HMC_OK;
+}
+
+extern "C" hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int64_t num_results,
+                                            int64_t num_burnin_steps, void* nuts_workspace,
+                                            size_t nuts_workspace_bytes, void* samples, int32_t* tree_depth,
+                                            int32_t* n_leapfrog) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (max_depth < 0 || max_depth > 10) return fail(HMC_E_INVALID, "max_depth must be in 0..10");
+    if (num_results < 0 || num_burnin_steps < 0) return fail(HMC_E_INVALID, "negative transition count");
+    if (ctx->a.ws.beta || ctx->a.ws.scale)
+        return fail(HMC_E_UNSUPPORTED, "NUTS runs without inverse temperatures or a transform");
+    if (!nuts_workspace) return fail(HMC_E_INVALID, "nuts_workspace must not be NULL");
+    size_t need = 0;
+    NutsWs nw = carve_nuts(nuts_workspace, ctx->a.C, ctx->a.tg.D, max_depth, ctx->a.f64 ? 8 : 4, &need);
+    if (nuts_workspace_bytes < need) return fail(HMC_E_NOMEM, "NUTS workspace smaller than hmc_nuts_workspace_size");
+    const int64_t total = num_results + num_burnin_steps;
+    if (ctx->t + (uint64_t)total > 0xffffffffull) return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
+    PlainArgs leap = ctx->a;
+    leap.ws.eps = nw.seps;             // signed step v eps of each chain's current doubling
+    hmc_status st = HMC_OK;
+    for (int64_t it = 0; it < total && st == HMC_OK; ++it) {
+        const uint32_t t = (uint32_t)(ctx->t + (uint64_t)it);
+        st = check_hip(launch_nuts_begin(ctx->a, nw, t, ctx->stream), "nuts begin");
+        for (int32_t j = 0; j < max_depth && st == HMC_OK; ++j) {
+            st = check_hip(launch_nuts_dir(ctx->a, nw, t, j, ctx->stream), "nuts direction");
+            for (int32_t i = 0; i < (1 << j) && st == HMC_OK; ++i) {
+                st = check_hip(launch_nuts_halfkick(leap, nw, ctx->stream), "nuts half kick");
+                if (st == HMC_OK) st = check_hip(launch_leapfrog_step(leap, 0.5, ctx->stream), "nuts leapfrog");
+                if (st == HMC_OK) st = check_hip(launch_nuts_leaf(ctx->a, nw, t, j, i, ctx->stream), "nuts leaf");
+            }
+            if (st == HMC_OK) st = check_hip(launch_nuts_doubling_end(ctx->a, nw, t, j, ctx->stream), "nuts doubling");
+            int32_t running = 0;
+            if (st == HMC_OK)
+                st = check_hip(hipMemcpyAsync(&running, nw.n_active, 4, hipMemcpyDeviceToHost, ctx->stream),
+                               "nuts count");
+            if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "nuts count");
+            if (st != HMC_OK || running == 0) break;
+        }
+        const bool kept = it >= num_burnin_steps;
+        if (st == HMC_OK)
+            st = check_hip(launch_nuts_end(ctx->a, nw, kept ? samples : nullptr, kept ? it - num_burnin_steps : 0,
+                                           kept ? tree_depth : nullptr, kept ? n_leapfrog : nullptr, ctx->stream),
+                           "nuts end");
+    }
+    if (st == HMC_OK) ctx->t += (uint64_t)total;
+    return st;
+}

@@ -86,6 +86,31 @@ hipError_t launch_set_ctrl(const Ctrl& c, Ctrl* dst, hipStream_t s);
 hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s);
 hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipStream_t s);
 hipError_t launch_da_init(const PlainArgs& a, hipStream_t s);
+hipError_t launch_leapfrog_step(const PlainArgs& a, double ks, hipStream_t s);
+
+// ---- No-U-Turn sampler (k_nuts.hip) ----------------------------------------
+// Per-chain buffers of the unrolled tree (state dtype T for vectors).
+struct NutsWs {
+    void *mx, *mr, *mg;        // [C, D] backward end of the trajectory: x, r, g
+    void *px, *pr, *pg;        // [C, D] forward end
+    void *lf_x, *lf_r;         // [MD, C, D] first leaf of the pending left subtree of level k
+    void *lc_x, *lc_g;         // [MD, C, D] candidate of that subtree
+    void *rc_x, *rc_g;         // [C, D] candidate of the finished doubling
+    double *mlogp, *plogp, *wlogp, *lc_logp, *rc_logp;   // [C], [C], [C], [MD, C], [C]
+    double *log_u, *seps, *ntot;                         // [C] slice, signed step, points in the tree
+    int32_t *lc_n;             // [MD, C]
+    int32_t *active, *alive, *rc_n, *depth, *nleap, *moved, *dir;   // [C]
+    int32_t *n_active;         // [1]
+    size_t bytes;
+};
+NutsWs carve_nuts(void* base, int64_t C, int64_t D, int32_t max_depth, size_t es, size_t* total);
+hipError_t launch_nuts_begin(const PlainArgs& a, const NutsWs& n, uint32_t t, hipStream_t s);
+hipError_t launch_nuts_dir(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, hipStream_t s);
+hipError_t launch_nuts_halfkick(const PlainArgs& a, const NutsWs& n, hipStream_t s);
+hipError_t launch_nuts_leaf(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, int32_t i, hipStream_t s);
+hipError_t launch_nuts_doubling_end(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, hipStream_t s);
+hipError_t launch_nuts_end(const PlainArgs& a, const NutsWs& n, void* samples, int64_t r, int32_t* tr_depth,
+                           int32_t* tr_nleap, hipStream_t s);
 // Streaming moments: fold q kept states (ring rows 0..q-1 = draws r0..r0+q-1
 // of R) into the per-half Welford accumulators and the batch sums.
 hipError_t launch_moments(const PlainArgs& a, const void* ring, int64_t q, int64_t r0, int64_t R,

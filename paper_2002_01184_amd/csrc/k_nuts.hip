@@ -1,0 +1,357 @@
+// k_nuts.hip -- the No-U-Turn sampler with its recursion unrolled (paper
+// Sec. 3.2; Hoffman & Gelman 2014, Algorithm 3, "efficient NUTS").
+//
+// All chains advance in lockstep through the same schedule: doubling j builds
+// a subtree of 2^j leaves; leaf i is one leapfrog step (a half kick here, then
+// the plain drift + gradient + half kick kernels of the target) from the end of
+// the trajectory in the chain's direction.  The recursion's stack is replaced
+// by one record per tree level k (the paper's O(max_tree_depth) memory): the
+// first leaf and the candidate of the pending left subtree of level k.  After
+// leaf i the subtrees that end at i are merged bottom-up -- the levels k with
+// bit k-1 of i set -- exactly where the recursive BuildTree merges them, with
+// the same counter-keyed uniforms, and the first unset bit parks the finished
+// subtree as the pending left of its level.  A chain whose leaf diverges or
+// whose merged subtree makes a U-turn stops for the rest of the transition
+// (masked), as the recursion would.
+//
+// Random numbers (Philox4x32-10, counter (chain, t, block, tag)): momentum as
+// HMC (tag 0), slice u (block 0, tag 6), direction of doubling j (block j,
+// tag 4), take of doubling j's subtree (block j, tag 5), merge of level k at
+// leaf i of doubling j (block (1024 j + i) 16 + k, tag 3).
+#include "hmc_internal.hpp"
+
+namespace hmc {
+
+enum : uint32_t { TAG_NUTS_MERGE = 3, TAG_NUTS_DIR = 4, TAG_NUTS_TOP = 5, TAG_NUTS_SLICE = 6 };
+
+// (k + 1/2) 2^-52 uniform of block (chain, t, block, tag), as the accept uniform
+__device__ __forceinline__ double nuts_u52(Key key, uint32_t chain, uint32_t t, uint32_t block, uint32_t tag) {
+    const uint4 w = philox(chain, t, block, tag, key);
+    const double k = (double)(w.x >> 6) * 67108864.0 + (double)(w.y >> 6);
+    return (k + 0.5) * 0x1p-52;
+}
+
+static size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+NutsWs carve_nuts(void* base, int64_t C, int64_t D, int32_t max_depth, size_t es, size_t* total) {
+    char* p = (char*)base;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        void* r = p ? (void*)(p + off) : nullptr;
+        off += al256(n);
+        return r;
+    };
+    const size_t vec = (size_t)C * D * es, lev = (size_t)(max_depth > 0 ? max_depth : 1) * C * D * es;
+    const size_t md = (size_t)(max_depth > 0 ? max_depth : 1);
+    NutsWs n;
+    n.mx = take(vec); n.mr = take(vec); n.mg = take(vec);
+    n.px = take(vec); n.pr = take(vec); n.pg = take(vec);
+    n.lf_x = take(lev); n.lf_r = take(lev); n.lc_x = take(lev); n.lc_g = take(lev);
+    n.rc_x = take(vec); n.rc_g = take(vec);
+    n.mlogp = (double*)take((size_t)C * 8); n.plogp = (double*)take((size_t)C * 8);
+    n.wlogp = (double*)take((size_t)C * 8); n.lc_logp = (double*)take(md * C * 8);
+    n.rc_logp = (double*)take((size_t)C * 8);
+    n.log_u = (double*)take((size_t)C * 8); n.seps = (double*)take((size_t)C * 8);
+    n.ntot = (double*)take((size_t)C * 8);
+    n.lc_n = (int32_t*)take(md * C * 4);
+    n.active = (int32_t*)take((size_t)C * 4); n.alive = (int32_t*)take((size_t)C * 4);
+    n.rc_n = (int32_t*)take((size_t)C * 4); n.depth = (int32_t*)take((size_t)C * 4);
+    n.nleap = (int32_t*)take((size_t)C * 4); n.moved = (int32_t*)take((size_t)C * 4);
+    n.dir = (int32_t*)take((size_t)C * 4);
+    n.n_active = (int32_t*)take(4);
+    n.bytes = off;
+    if (total) *total = off;
+    return n;
+}
+
+// One wavefront per chain, four chains per 256-thread block.
+#define NUTS_CHAIN                                                   \
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); \
+    const int lane = threadIdx.x & 63;                               \
+    if (c >= a.C) return;                                            \
+    const int64_t D = a.tg.D;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nuts_begin(PlainArgs a, NutsWs n, uint32_t t) {
+    NUTS_CHAIN
+    const T* x = (const T*)a.ws.x;
+    const T* g = (const T*)a.ws.g;
+    T *mx = (T*)n.mx, *mr = (T*)n.mr, *mg = (T*)n.mg, *px = (T*)n.px, *pr = (T*)n.pr, *pg = (T*)n.pg;
+    double k0 = 0.0;
+    const int64_t nblk = (D + 3) / 4;
+    for (int64_t b = lane; b < nblk; b += 64) {
+        T z[4];
+        momentum4<T>(a.key, (uint32_t)c, t, (uint32_t)b, z, 4 * b + 2 < D);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t d = 4 * b + j;
+            if (d < D) {
+                const int64_t i = c * D + d;
+                mx[i] = px[i] = x[i];
+                mg[i] = pg[i] = g[i];
+                mr[i] = pr[i] = z[j];
+                k0 += 0.5 * (double)z[j] * (double)z[j];
+            }
+        }
+    }
+    k0 = group_sum<64>(k0);
+    if (lane == 0) {
+        const double lp = a.ws.logp[c];
+        n.mlogp[c] = n.plogp[c] = lp;
+        n.log_u[c] = log(nuts_u52(a.key, (uint32_t)c, t, 0u, TAG_NUTS_SLICE)) - (-lp + k0);
+        n.ntot[c] = 1.0;
+        n.active[c] = 1;
+        n.depth[c] = 0;
+        n.nleap[c] = 0;
+        n.moved[c] = 0;
+    }
+}
+
+// direction of doubling j; the trajectory end in that direction becomes the
+// working leaf state (xq, pq, gq)
+template <typename T>
+__global__ __launch_bounds__(256) void k_nuts_dir(PlainArgs a, NutsWs n, uint32_t t, int32_t j) {
+    NUTS_CHAIN
+    const bool act = n.active[c] != 0;
+    const int v = (act && nuts_u52(a.key, (uint32_t)c, t, (uint32_t)j, TAG_NUTS_DIR) < 0.5) ? -1 : 1;
+    const T* sx = (const T*)(v > 0 ? n.px : n.mx);
+    const T* sr = (const T*)(v > 0 ? n.pr : n.mr);
+    const T* sg = (const T*)(v > 0 ? n.pg : n.mg);
+    T *xq = (T*)a.ws.xq, *pq = (T*)a.ws.pq, *gq = (T*)a.ws.gq;
+    for (int64_t d = lane; d < D; d += 64) {
+        const int64_t i = c * D + d;
+        xq[i] = sx[i];
+        pq[i] = sr[i];
+        gq[i] = sg[i];
+    }
+    if (lane == 0) {
+        n.dir[c] = v;
+        n.seps[c] = act ? (double)v * a.ws.eps[c] : 0.0;
+        n.alive[c] = act ? 1 : 0;
+        n.wlogp[c] = v > 0 ? n.plogp[c] : n.mlogp[c];
+    }
+}
+
+// first half kick of a leaf's leapfrog step: p += (v eps / 2) g
+template <typename T>
+__global__ __launch_bounds__(256) void k_nuts_halfkick(PlainArgs a, NutsWs n) {
+    const int64_t D = a.tg.D, tot = a.C * D;
+    T* pq = (T*)a.ws.pq;
+    const T* gq = (const T*)a.ws.gq;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x)
+        pq[i] = pq[i] + (T)(0.5 * n.seps[i / D]) * gq[i];
+}
+
+// leaf i of doubling j: its energy, then the merges of the subtrees that end here
+template <typename T>
+__global__ __launch_bounds__(256) void k_nuts_leaf(PlainArgs a, NutsWs n, uint32_t t, int32_t j, int32_t i) {
+    NUTS_CHAIN
+    if (!n.alive[c]) return;
+    const T *xq = (const T*)a.ws.xq, *pq = (const T*)a.ws.pq, *gq = (const T*)a.ws.gq;
+    const bool logreg = a.tg.kind == HMC_TGT_LOGREG;
+    double lp = 0.0, kin = 0.0;
+    for (int64_t d = lane; d < D; d += 64) {
+        const int64_t e = c * D + d;
+        const double xv = (double)xq[e], pv = (double)pq[e];
+        kin += 0.5 * pv * pv;
+        lp += logreg ? -0.5 * xv * xv * a.tg.inv_var : 0.5 * xv * (double)gq[e];
+    }
+    lp = group_sum<64>(lp);
+    kin = group_sum<64>(kin);
+    if (logreg) lp += a.ws.lpq[c];
+    const double H = -lp + kin, lu = n.log_u[c];
+    int32_t n_node = (lu <= -H) ? 1 : 0;
+    const bool s_leaf = lu < 1000.0 - H;        // NaN H fails
+    if (lane == 0) {
+        n.nleap[c] += 1;
+        n.wlogp[c] = lp;
+    }
+    if (!s_leaf) {
+        if (lane == 0) n.alive[c] = 0;
+        return;
+    }
+    const int64_t C = a.C;
+    const int v = n.dir[c];
+    T *lfx = (T*)n.lf_x, *lfr = (T*)n.lf_r, *lcx = (T*)n.lc_x, *lcg = (T*)n.lc_g;
+    int cand = -1, first = -1;                  // -1: the leaf itself, k: the record of level k
+    double cand_lp = lp;
+    for (int k = 1; k <= j; ++k) {
+        const int64_t rk = ((int64_t)k * C + c) * D;
+        if (((i >> (k - 1)) & 1) == 0) {
+            // the finished subtree is the left child at level k: park it
+            const int64_t rf = first < 0 ? 0 : ((int64_t)first * C + c) * D;
+            const int64_t rc = cand < 0 ? 0 : ((int64_t)cand * C + c) * D;
+            for (int64_t d = lane; d < D; d += 64) {
+                lfx[rk + d] = first < 0 ? xq[c * D + d] : lfx[rf + d];
+                lfr[rk + d] = first < 0 ? pq[c * D + d] : lfr[rf + d];
+                lcx[rk + d] = cand < 0 ? xq[c * D + d] : lcx[rc + d];
+                lcg[rk + d] = cand < 0 ? gq[c * D + d] : lcg[rc + d];
+            }
+            if (lane == 0) {
+                n.lc_n[k * C + c] = n_node;
+                n.lc_logp[k * C + c] = cand_lp;
+            }
+            return;
+        }
+        // the finished subtree is the right child at level k: merge with the parked left
+        const int32_t nl = n.lc_n[k * C + c];
+        const uint32_t block = ((uint32_t)j * 1024u + (uint32_t)i) * 16u + (uint32_t)k;
+        const double u = nuts_u52(a.key, (uint32_t)c, t, block, TAG_NUTS_MERGE);
+        const bool keep_right = (nl + n_node > 0) && u < (double)n_node / (double)(nl + n_node);
+        if (!keep_right) {
+            cand = k;
+            cand_lp = n.lc_logp[k * C + c];
+        }
+        n_node += nl;
+        // U-turn over the merged span: from its first leaf (level k's record) to this leaf
+        double dm = 0.0, dp = 0.0;
+        for (int64_t d = lane; d < D; d += 64) {
+            const double fx = (double)lfx[rk + d], fr = (double)lfr[rk + d];
+            const double lx = (double)xq[c * D + d], lr = (double)pq[c * D + d];
+            const double dx = v > 0 ? lx - fx : fx - lx;     // forward end minus backward end
+            dm += dx * (v > 0 ? fr : lr);
+            dp += dx * (v > 0 ? lr : fr);
+        }
+        dm = group_sum<64>(dm);
+        dp = group_sum<64>(dp);
+        first = k;
+        if (!(dm >= 0.0 && dp >= 0.0)) {
+            if (lane == 0) n.alive[c] = 0;
+            return;
+        }
+    }
+    // every subtree of doubling j ends at this leaf: the doubling's tree is complete
+    T *rcx = (T*)n.rc_x, *rcg = (T*)n.rc_g;
+    const int64_t rc = cand < 0 ? 0 : ((int64_t)cand * C + c) * D;
+    for (int64_t d = lane; d < D; d += 64) {
+        rcx[c * D + d] = cand < 0 ? xq[c * D + d] : lcx[rc + d];
+        rcg[c * D + d] = cand < 0 ? gq[c * D + d] : lcg[rc + d];
+    }
+    if (lane == 0) {
+        n.rc_n[c] = n_node;
+        n.rc_logp[c] = cand_lp;
+    }
+}
+
+// end of doubling j: the working state becomes the trajectory end, the
+// subtree's candidate is taken with probability min(1, n'/n), and the whole
+// trajectory's U-turn decides whether the chain continues
+template <typename T>
+__global__ __launch_bounds__(256) void k_nuts_doubling_end(PlainArgs a, NutsWs n, uint32_t t, int32_t j) {
+    NUTS_CHAIN
+    if (!n.active[c]) return;
+    const int v = n.dir[c];
+    T* ex = (T*)(v > 0 ? n.px : n.mx);
+    T* er = (T*)(v > 0 ? n.pr : n.mr);
+    T* eg = (T*)(v > 0 ? n.pg : n.mg);
+    const T *xq = (const T*)a.ws.xq, *pq = (const T*)a.ws.pq, *gq = (const T*)a.ws.gq;
+    for (int64_t d = lane; d < D; d += 64) {
+        const int64_t e = c * D + d;
+        ex[e] = xq[e];
+        er[e] = pq[e];
+        eg[e] = gq[e];
+    }
+    if (lane == 0) (v > 0 ? n.plogp : n.mlogp)[c] = n.wlogp[c];
+    bool s = false;
+    if (n.alive[c]) {
+        const double ntot = n.ntot[c];
+        const int32_t nsub = n.rc_n[c];
+        if (nuts_u52(a.key, (uint32_t)c, t, (uint32_t)j, TAG_NUTS_TOP) < (double)nsub / ntot) {
+            T* x = (T*)a.ws.x;
+            T* g = (T*)a.ws.g;
+            const T *rcx = (const T*)n.rc_x, *rcg = (const T*)n.rc_g;
+            for (int64_t d = lane; d < D; d += 64) {
+                x[c * D + d] = rcx[c * D + d];
+                g[c * D + d] = rcg[c * D + d];
+            }
+            if (lane == 0) {
+                a.ws.logp[c] = n.rc_logp[c];
+                n.moved[c] = 1;
+            }
+        }
+        if (lane == 0) n.ntot[c] = ntot + (double)nsub;
+        // U-turn of the whole trajectory (each lane reads the elements it wrote)
+        const T *mx = (const T*)n.mx, *mr = (const T*)n.mr, *px = (const T*)n.px, *pr = (const T*)n.pr;
+        double dm = 0.0, dp = 0.0;
+        for (int64_t d = lane; d < D; d += 64) {
+            const int64_t e = c * D + d;
+            const double dx = (double)px[e] - (double)mx[e];
+            dm += dx * (double)mr[e];
+            dp += dx * (double)pr[e];
+        }
+        dm = group_sum<64>(dm);
+        dp = group_sum<64>(dp);
+        s = dm >= 0.0 && dp >= 0.0;
+    }
+    if (lane == 0) {
+        n.depth[c] = j + 1;
+        if (s) atomicAdd(n.n_active, 1);
+        else n.active[c] = 0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nuts_end(PlainArgs a, NutsWs n, T* samples, int64_t r, int32_t* tr_depth,
+                                                  int32_t* tr_nleap) {
+    NUTS_CHAIN
+    if (samples) {
+        const T* x = (const T*)a.ws.x;
+        for (int64_t d = lane; d < D; d += 64) samples[(r * a.C + c) * D + d] = x[c * D + d];
+    }
+    if (lane == 0) {
+        if (tr_depth) tr_depth[r * a.C + c] = n.depth[c];
+        if (tr_nleap) tr_nleap[r * a.C + c] = n.nleap[c];
+    }
+}
+
+__global__ void k_nuts_zero(int32_t* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+static dim3 nuts_grid(int64_t C) { return dim3((unsigned)((C + 3) / 4)); }
+
+hipError_t launch_nuts_begin(const PlainArgs& a, const NutsWs& n, uint32_t t, hipStream_t s) {
+    if (a.f64) hipLaunchKernelGGL(k_nuts_begin<double>, nuts_grid(a.C), dim3(256), 0, s, a, n, t);
+    else hipLaunchKernelGGL(k_nuts_begin<float>, nuts_grid(a.C), dim3(256), 0, s, a, n, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_dir(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, hipStream_t s) {
+    if (a.f64) hipLaunchKernelGGL(k_nuts_dir<double>, nuts_grid(a.C), dim3(256), 0, s, a, n, t, j);
+    else hipLaunchKernelGGL(k_nuts_dir<float>, nuts_grid(a.C), dim3(256), 0, s, a, n, t, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_halfkick(const PlainArgs& a, const NutsWs& n, hipStream_t s) {
+    const int64_t tot = a.C * a.tg.D;
+    const dim3 grid((unsigned)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536));
+    if (a.f64) hipLaunchKernelGGL(k_nuts_halfkick<double>, grid, dim3(256), 0, s, a, n);
+    else hipLaunchKernelGGL(k_nuts_halfkick<float>, grid, dim3(256), 0, s, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_leaf(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, int32_t i, hipStream_t s) {
+    if (a.f64) hipLaunchKernelGGL(k_nuts_leaf<double>, nuts_grid(a.C), dim3(256), 0, s, a, n, t, j, i);
+    else hipLaunchKernelGGL(k_nuts_leaf<float>, nuts_grid(a.C), dim3(256), 0, s, a, n, t, j, i);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_doubling_end(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, hipStream_t s) {
+    hipLaunchKernelGGL(k_nuts_zero, dim3(1), dim3(64), 0, s, n.n_active);
+    if (a.f64) hipLaunchKernelGGL(k_nuts_doubling_end<double>, nuts_grid(a.C), dim3(256), 0, s, a, n, t, j);
+    else hipLaunchKernelGGL(k_nuts_doubling_end<float>, nuts_grid(a.C), dim3(256), 0, s, a, n, t, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_nuts_end(const PlainArgs& a, const NutsWs& n, void* samples, int64_t r, int32_t* tr_depth,
+                           int32_t* tr_nleap, hipStream_t s) {
+    if (a.f64)
+        hipLaunchKernelGGL(k_nuts_end<double>, nuts_grid(a.C), dim3(256), 0, s, a, n, (double*)samples, r, tr_depth,
+                           tr_nleap);
+    else
+        hipLaunchKernelGGL(k_nuts_end<float>, nuts_grid(a.C), dim3(256), 0, s, a, n, (float*)samples, r, tr_depth,
+                           tr_nleap);
+    return hipGetLastError();
+}
+
+}  // namespace hmc

@@ -745,6 +745,37 @@ hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s
     return hipGetLastError();
 }
 
+// One leapfrog drift + gradient + kick (scale ks) on the trajectory buffers
+// (xq, pq, gq), the gradient always written to gq and, for logistic
+// regression, the data part of logp to lpq.  Used by the NUTS leaves.
+hipError_t launch_leapfrog_step(const PlainArgs& a, double ks, hipStream_t s) {
+    switch (a.tg.kind) {
+    case HMC_TGT_STD_NORMAL:
+    case HMC_TGT_GAUSS_DIAG:
+        if (a.f64)
+            hipLaunchKernelGGL(k_elem_leapfrog<double>, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a,
+                               (const double*)a.ws.xq, (double*)a.ws.xq, (double*)a.ws.pq, (double*)a.ws.gq, 3, ks);
+        else
+            hipLaunchKernelGGL(k_elem_leapfrog<float>, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a,
+                               (const float*)a.ws.xq, (float*)a.ws.xq, (float*)a.ws.pq, (float*)a.ws.gq, 3, ks);
+        break;
+    case HMC_TGT_GAUSS_DENSE:
+        (void)launch_dense(a, (const float*)a.ws.xq, (float*)a.ws.xq, (float*)a.ws.pq, (float*)a.ws.gq, 3, ks, s);
+        break;
+    case HMC_TGT_LOGREG:
+        if (a.bf16_grad) {
+            (void)launch_lr16_grad(a, (const float*)a.ws.xq, (const float*)a.ws.pq, 1, a.ws.xt, s);
+            hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, (float*)a.ws.xq,
+                               (float*)a.ws.pq, (float*)a.ws.gq, lb_grad_nsplit_t(a), 1, 1, ks, 0);
+            (void)launch_lr16_logp(a, (const float*)a.ws.xq, s);
+            break;
+        }
+        (void)launch_logreg(a, (float*)a.ws.xq, (float*)a.ws.pq, (float*)a.ws.gq, 1, 1, ks, 1, s);
+        break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipStream_t s) {
     if (a.f64) HMC_GROUP_DISPATCH(k_begin, double, a, s);
     else HMC_GROUP_DISPATCH(k_begin, float, a, s);

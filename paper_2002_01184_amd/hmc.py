@@ -95,8 +95,7 @@ HMC_REQ_QUEUED, HMC_REQ_RUNNING, HMC_REQ_DONE, HMC_REQ_FAILED = range(4)
 EXPORTED = ["hmc_workspace_size", "hmc_init", "hmc_step", "hmc_sample_chain", "hmc_get_state", "hmc_set_state",
             "hmc_destroy", "hmc_last_error", "hmc_effective_form", "hmc_autotune", "hmc_set_inverse_temperature",
             "hmc_remc_swap", "hmc_remc_sample_chain", "hmc_sample_chain_moments", "hmc_set_transform_scale",
-            "hmc_server_create",
-            "hmc_server_submit",
+            "hmc_nuts_workspace_size", "hmc_nuts_sample_chain", "hmc_server_create", "hmc_server_submit",
             "hmc_server_poll", "hmc_server_wait", "hmc_server_take", "hmc_server_get_stats",
             "hmc_server_destroy"]
 
@@ -139,6 +138,11 @@ def lib():
     L.hmc_sample_chain_moments.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(hmc_adapt),
                                            ctypes.POINTER(hmc_moments), ctypes.POINTER(hmc_trace)]
     L.hmc_sample_chain_moments.restype = st
+    L.hmc_nuts_workspace_size.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.hmc_nuts_workspace_size.restype = st
+    L.hmc_nuts_sample_chain.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_size_t,
+                                        vp, vp, vp]
+    L.hmc_nuts_sample_chain.restype = st
     L.hmc_set_transform_scale.argtypes = [vp, vp]
     L.hmc_set_transform_scale.restype = st
     L.hmc_set_inverse_temperature.argtypes = [vp, vp]
@@ -398,6 +402,21 @@ class Sampler:
         hmc_sample_chain_moments(self.ctx, R, num_burnin_steps, ad, mo, tr)
         outs.update(mean=mean, m2=m2, batch_sum=bsum, ring=ring)
         return outs
+
+    def nuts_sample_chain(self, num_results, num_burnin_steps, max_depth=10, store_samples=True):
+        """No-U-Turn sampler from the current state with each chain's step size.
+        Returns dict(samples [R, C, D] or None, tree_depth [R, C], n_leapfrog [R, C])."""
+        torch = self.torch
+        C, D, R = self.C, self.D, num_results
+        nb = ctypes.c_size_t(0)
+        _check(lib().hmc_nuts_workspace_size(self.ctx, max_depth, ctypes.byref(nb)))
+        ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=self.device)
+        samples = torch.empty(R, C, D, dtype=self.dtype, device=self.device) if store_samples else None
+        depth = torch.empty(R, C, dtype=torch.int32, device=self.device)
+        nleap = torch.empty(R, C, dtype=torch.int32, device=self.device)
+        _check(lib().hmc_nuts_sample_chain(self.ctx, max_depth, R, num_burnin_steps, _ptr(ws), nb.value,
+                                           _ptr(samples), _ptr(depth), _ptr(nleap)))
+        return dict(samples=samples, tree_depth=depth, n_leapfrog=nleap)
 
     def set_transform_scale(self, scale):
         """Diagonal affine bijector x = shift + scale * z (the shift does not enter

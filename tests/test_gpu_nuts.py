@@ -1,0 +1,95 @@
+"""GPU parity of the unrolled No-U-Turn sampler (paper Sec. 3.2) against the
+oracle's recursive NUTS (Hoffman & Gelman 2014, Algorithm 3) on the same
+counter-keyed random numbers.
+
+Bars: FP64 element-wise targets agree with the oracle over whole runs (states
+to 1e-12, tree depths and leapfrog counts exactly); FP32 targets, one
+transition from given states: >= 99% of chains take the same tree (depth,
+leapfrog count, moved) and those chains' states agree to 1e-5 relative; the
+FP32 chain samples N(0, 1) with the right variance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import gpu_available, oracle_target, rel_err_rows, to_np
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import torch  # noqa: E402
+
+from paper_2002_01184_amd import hmc  # noqa: E402
+
+
+@pytest.mark.parametrize("case", ["std1", "diag5"])
+def test_fp64_runs_match_oracle(case):
+    if case == "std1":
+        w = W.std_normal_1d(num_chains=64, step_size=0.5)
+        w.x0 = np.random.default_rng(0).normal(size=(64, 1))
+    else:
+        w = W.gauss_diag(dim=5, num_chains=48, step_size=0.3, state_dtype="f64", lam_lo=0.3, lam_hi=3.0)
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    g = s.nuts_sample_chain(40, 10, max_depth=6)
+    s.close()
+    o = oracle.nuts_sample_chain(oracle_target(w), w.seed, w.x0.astype(np.float64), w.step_size, 10, 40, max_depth=6)
+    assert np.array_equal(to_np(g["tree_depth"]), o["depth"])
+    assert np.array_equal(to_np(g["n_leapfrog"]), o["n_leapfrog"])
+    assert np.max(np.abs(to_np(g["samples"]) - o["samples"])) <= 1e-12
+    assert o["depth"].min() >= 1 and o["depth"].max() > 1
+
+
+def _fp32_cases():
+    return {
+        "std_normal_7d": W.std_normal_1d(num_chains=60, dim=7, state_dtype="f32", step_size=0.4),
+        "gauss_diag_101": W.gauss_diag(dim=101, num_chains=40, step_size=0.08),
+        "gauss_dense_37": W.gauss_dense(dim=37, num_chains=45, step_size=0.1, seed=3),
+        "logreg_77x3": W.logreg(77, 3, 33, step_size=0.2, seed=5),
+        "logreg_1000x25": W.logreg(1000, 25, 64, step_size=0.05),
+    }
+
+
+@pytest.mark.parametrize("name", list(_fp32_cases()))
+def test_fp32_one_transition_parity(name):
+    w = _fp32_cases()[name]
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    g = s.nuts_sample_chain(1, 0, max_depth=8)
+    xg, _, t = s.get_state()
+    s.close()
+    assert t == 1
+    tg = oracle_target(w)
+    same, errs = [], []
+    gd, gn = to_np(g["tree_depth"])[0], to_np(g["n_leapfrog"])[0]
+    xg = to_np(xg)
+    for c in range(w.num_chains):
+        r = oracle.nuts_transition(tg, w.seed, c, 0, w.step_size, 8, w.x0[c].astype(np.float64))
+        ok = r["depth"] == gd[c] and r["n_leapfrog"] == gn[c]
+        same.append(ok)
+        if ok:
+            errs.append(rel_err_rows(xg[c:c + 1], r["x"][None])[0])
+    assert np.mean(same) >= 0.99, np.mean(same)
+    assert max(errs) <= 1e-5, max(errs)
+
+
+def test_fp32_standard_normal_moments():
+    w = W.std_normal_1d(num_chains=256, dim=3, state_dtype="f32", step_size=0.3)
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    g = s.nuts_sample_chain(300, 30, max_depth=8)
+    s.close()
+    x = to_np(g["samples"]).reshape(-1, 3)
+    assert np.all(np.abs(x.mean(0)) < 0.02)
+    assert np.allclose(x.var(0), 1.0, atol=0.04)
+
+
+def test_nuts_errors():
+    w = W.std_normal_1d(num_chains=8)
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    with pytest.raises(hmc.HMCError, match="max_depth"):
+        s.nuts_sample_chain(1, 0, max_depth=11)
+    s.set_inverse_temperature(torch.ones(8, dtype=torch.float64, device="cuda"))
+    with pytest.raises(hmc.HMCError, match="NUTS"):
+        s.nuts_sample_chain(1, 0)
+    s.close()
