@@ -302,6 +302,16 @@ def test_wide_gauss_diag_1000_sampled_chains(form):
     assert agree == 1.0 and err.max() < 1e-5
 
 
+@pytest.mark.parametrize("form", ["plain", "auto"])
+def test_full_size_gauss_dense_100_sampled_chains(form):
+    # the dense Gaussian workload at full size (4096 chains, L=20) in bench's launch
+    # configuration (fused for auto), fixed step size, sampled chains against the oracle
+    w = W.cfg_gauss_dense_100()
+    w.num_burnin, w.num_results, w.adapt = 3, 3, False
+    agree, err, _, _ = _trajectory_compare(w, [0, 1, 100, 2047, 4095], FORMS[form])
+    assert agree == 1.0 and err.max() < 1e-5, err.max()
+
+
 def test_full_size_logreg_1000x25_fixed_step_sampled_chains():
     # the benchmark workload at full size (1024 chains) in bench's launch
     # configuration, fixed step size: trajectories on sampled chains match the oracle
