@@ -314,7 +314,12 @@ def bench_nuts(args):
     if args.transitions is not None:
         w.num_burnin = min(w.num_burnin, args.transitions // 2)
         w.num_results = args.transitions - w.num_burnin
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN, grad_bf16=args.grad == "bf16")
+    form = {"auto": hmc.HMC_FORM_AUTO, "plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_PLAIN,
+            "fused": hmc.HMC_FORM_FUSED}[args.form]
+    s = hmc.sampler_for(w, form=form, grad_bf16=args.grad == "bf16")
+    # the persistent NUTS kernel covers element-wise targets up to 64 (FP64) or 128 (FP32) 4-dim blocks per chain
+    persistent = (hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED and w.kind in (W.STD_NORMAL, W.GAUSS_DIAG)
+                  and (w.dim + 3) // 4 <= (64 if w.state_dtype == "f64" else 128))
     x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).cuda()
     eps0 = torch.full((w.num_chains,), w.step_size, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -355,11 +360,13 @@ def bench_nuts(args):
         "data": "synthetic (seeded; shapes of the paper's workloads)",
         "config": {"workload": f"nuts_{w.name}", "num_chains": w.num_chains, "dim": w.dim, "n_rows": w.n_rows,
                    "max_tree_depth": args.nuts, "step_size": w.step_size, "num_burnin": w.num_burnin,
-                   "num_results": w.num_results, "form": "plain (unrolled tree, lockstep)",
+                   "num_results": w.num_results,
+                   "form": "persistent (unrolled tree in registers)" if persistent else "plain (unrolled tree, lockstep)",
                    "parallelism": "chains (1 GPU)"},
         "roofline": {"bound": bound, "achieved": achieved / scale, "peak": peak / scale,
                      "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "NUTS kernels + plain leapfrog kernels", "kernel_ms_per_launch": kernel_ms,
+                     "kernel": "persistent NUTS kernel" if persistent else "NUTS kernels + plain leapfrog kernels",
+                     "kernel_ms_per_launch": kernel_ms,
                      "work_per_launch": per_cs * steps_run},
         "nuts": {"mean_leapfrog_per_transition": float(nleap.mean()), "max_leapfrog": int(nleap.max()),
                  "depth_histogram": np.bincount(depth.ravel()).tolist()},

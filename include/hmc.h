@@ -264,9 +264,13 @@ hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale);
  * tag 4), take of doubling j's subtree (block j, tag 5), merge of the level-k
  * subtree ending at leaf i of doubling j (block (1024 j + i) 16 + k, tag 3).
  * The step size is each chain's current step size (fixed; no adaptation).
- * Chains run in lockstep on the plain kernels of the target; a chain whose
- * trajectory has stopped is masked.  The context must have no inverse
- * temperatures or transform (HMC_E_UNSUPPORTED).
+ * On a context of the fused form with an element-wise target (N(0, I),
+ * diagonal Gaussian; D <= 256 in FP64, <= 512 in FP32) one persistent kernel
+ * runs every transition with each chain's tree in its lanes' registers;
+ * otherwise the chains run in lockstep on the plain kernels of the target and
+ * a chain whose trajectory has stopped is masked.  Both build the same trees.
+ * The context must have no inverse temperatures or transform
+ * (HMC_E_UNSUPPORTED).
  * ------------------------------------------------------------------------- */
 
 /* Bytes of the caller-allocated NUTS workspace for this context (256-byte
@@ -276,7 +280,8 @@ hmc_status hmc_nuts_workspace_size(const hmc_ctx* ctx, int32_t max_depth, size_t
 /* burn-in + R NUTS transitions from the context's state; samples [R, C, D]
  * (device, state dtype), tree_depth and n_leapfrog [R, C] (device int32: the
  * doublings and leapfrog steps of each kept transition) may be NULL.  t
- * advances by burn-in + R.  Synchronizes the stream after every doubling. */
+ * advances by burn-in + R.  The lockstep path synchronizes the stream after
+ * every doubling; the persistent one is asynchronous. */
 hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int64_t num_results, int64_t num_burnin_steps,
                                  void* nuts_workspace, size_t nuts_workspace_bytes, void* samples,
                                  int32_t* tree_depth, int32_t* n_leapfrog);

@@ -812,6 +812,14 @@ extern "C" hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int
     if (nuts_workspace_bytes < need) return fail(HMC_E_NOMEM, "NUTS workspace smaller than hmc_nuts_workspace_size");
     const int64_t total = num_results + num_burnin_steps;
     if (ctx->t + (uint64_t)total > 0xffffffffull) return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
+    if (ctx->form == HMC_FORM_FUSED && nuts_fused_supported(ctx->a)) {
+        // element-wise targets: one persistent launch for all transitions
+        hmc_status st = check_hip(launch_nuts_fused(ctx->a, nw, (uint32_t)ctx->t, total, num_burnin_steps, max_depth,
+                                                    samples, tree_depth, n_leapfrog, ctx->stream),
+                                  "nuts persistent");
+        if (st == HMC_OK) ctx->t += (uint64_t)total;
+        return st;
+    }
     PlainArgs leap = ctx->a;
     leap.ws.eps = nw.seps;             // signed step v eps of each chain's current doubling
     hmc_status st = HMC_OK;

@@ -109,6 +109,9 @@ hipError_t launch_nuts_dir(const PlainArgs& a, const NutsWs& n, uint32_t t, int3
 hipError_t launch_nuts_halfkick(const PlainArgs& a, const NutsWs& n, hipStream_t s);
 hipError_t launch_nuts_leaf(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, int32_t i, hipStream_t s);
 hipError_t launch_nuts_doubling_end(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, hipStream_t s);
+bool nuts_fused_supported(const PlainArgs& a);
+hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, uint32_t t_begin, int64_t n_trans, int64_t n_burnin,
+                             int32_t max_depth, void* samples, int32_t* tr_depth, int32_t* tr_nleap, hipStream_t s);
 hipError_t launch_nuts_end(const PlainArgs& a, const NutsWs& n, void* samples, int64_t r, int32_t* tr_depth,
                            int32_t* tr_nleap, hipStream_t s);
 // Streaming moments: fold q kept states (ring rows 0..q-1 = draws r0..r0+q-1

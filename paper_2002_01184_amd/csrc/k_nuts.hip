@@ -304,6 +304,302 @@ __global__ __launch_bounds__(256) void k_nuts_end(PlainArgs a, NutsWs n, T* samp
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent NUTS for the element-wise targets (N(0, I), diagonal Gaussian):
+// a group of G lanes owns one chain (NB blocks of 4 dims per lane) and runs
+// whole transitions -- every doubling and leaf -- in registers, so a chain
+// waits only for the chains of its own wavefront, not for the whole batch.
+// The levels' parked first leaves and candidates live in the NutsWs buffers
+// (each lane touches only its own dims); their counts and log-probabilities
+// in registers (levels unrolled).  Same tree, same uniforms, same arithmetic
+// order per leaf as the lockstep kernels.
+// ---------------------------------------------------------------------------
+constexpr int NUTS_MAXD = 10;
+
+template <typename T, int G, int NB>
+__global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, uint32_t t_begin, int64_t n_trans,
+                                                         int64_t n_burnin, int32_t max_depth, T* samples,
+                                                         int32_t* tr_depth, int32_t* tr_nleap) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x % G;
+    const int64_t c = gid / G;
+    const bool active = c < a.C;
+    const int64_t cc = active ? c : 0;
+    const int64_t C = a.C, D = a.tg.D;
+    const bool diag = a.tg.kind == HMC_TGT_GAUSS_DIAG;
+    const T* X = (const T*)a.ws.x;
+    const T* Gr = (const T*)a.ws.g;
+    const T* prec = (const T*)a.tg.prec;
+    T *lfx = (T*)n.lf_x, *lfr = (T*)n.lf_r, *lcx = (T*)n.lc_x, *lcg = (T*)n.lc_g;
+
+    T pc[NB][4], x[NB][4], g[NB][4];
+    bool ok[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t d = 4 * (lane + (int64_t)G * b) + e;
+            ok[b][e] = active && d < D;
+            x[b][e] = ok[b][e] ? X[cc * D + d] : (T)0;
+            g[b][e] = ok[b][e] ? Gr[cc * D + d] : (T)0;
+            pc[b][e] = ok[b][e] ? (diag ? prec[d] : (T)1) : (T)0;
+        }
+    auto dim_of = [&](int b, int e) -> int64_t { return 4 * (lane + (int64_t)G * b) + e; };
+    double logp = a.ws.logp[cc];
+    const double eps = a.ws.eps[cc];
+
+    for (int64_t it = 0; it < n_trans; ++it) {
+        const uint32_t t = t_begin + (uint32_t)it;
+        T mx[NB][4], mr[NB][4], mg[NB][4], px[NB][4], pr[NB][4], pg[NB][4];
+        double k0 = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            T z[4];
+            momentum4<T>(a.key, (uint32_t)cc, t, (uint32_t)(lane + G * b), z, 4 * (lane + (int64_t)G * b) + 2 < D);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T r0 = ok[b][e] ? z[e] : (T)0;
+                k0 += 0.5 * (double)r0 * (double)r0;
+                mx[b][e] = px[b][e] = x[b][e];
+                mg[b][e] = pg[b][e] = g[b][e];
+                mr[b][e] = pr[b][e] = r0;
+            }
+        }
+        k0 = group_sum<G>(k0);
+        const double log_u = log(nuts_u52(a.key, (uint32_t)cc, t, 0u, TAG_NUTS_SLICE)) - (-logp + k0);
+        double mlogp = logp, plogp = logp, ntot = 1.0;
+        int32_t depth = 0, nleap = 0;
+        bool s = active;                        // lanes past the last chain build no tree
+        for (int j = 0; j < max_depth && s; ++j) {
+            const int v = nuts_u52(a.key, (uint32_t)cc, t, (uint32_t)j, TAG_NUTS_DIR) < 0.5 ? -1 : 1;
+            const T se = (T)((double)v * eps), hse = (T)(0.5 * ((double)v * eps));
+            T wx[NB][4], wr[NB][4], wg[NB][4];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    wx[b][e] = v > 0 ? px[b][e] : mx[b][e];
+                    wr[b][e] = v > 0 ? pr[b][e] : mr[b][e];
+                    wg[b][e] = v > 0 ? pg[b][e] : mg[b][e];
+                }
+            double wlogp = v > 0 ? plogp : mlogp;
+            bool alive = true, complete = false;
+            int32_t lcn[NUTS_MAXD];
+            double lclp[NUTS_MAXD];
+            T rcx[NB][4], rcg[NB][4];
+            double rclp = 0.0;
+            int32_t rcn = 0;
+            const int nleaves = 1 << j;
+            for (int i = 0; i < nleaves; ++i) {
+                double lp = 0.0, kin = 0.0;
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        wr[b][e] = wr[b][e] + hse * wg[b][e];
+                        wx[b][e] = fma(se, wr[b][e], wx[b][e]);
+                        wg[b][e] = -pc[b][e] * wx[b][e];
+                        wr[b][e] = fma(hse, wg[b][e], wr[b][e]);
+                        lp += 0.5 * (double)wx[b][e] * (double)wg[b][e];
+                        kin += 0.5 * (double)wr[b][e] * (double)wr[b][e];
+                    }
+                lp = group_sum<G>(lp);
+                kin = group_sum<G>(kin);
+                wlogp = lp;
+                nleap += 1;
+                const double H = -lp + kin;
+                int32_t n_node = (log_u <= -H) ? 1 : 0;
+                if (!(log_u < 1000.0 - H)) {
+                    alive = false;
+                    break;
+                }
+                int cand = -1, first = -1;
+                double cand_lp = lp;
+                bool parked = false;
+#pragma unroll
+                for (int k = 1; k <= NUTS_MAXD; ++k) {
+                    if (k > j) break;
+                    const int64_t rk = ((int64_t)k * C + cc) * D;
+                    if (((i >> (k - 1)) & 1) == 0) {
+                        const int64_t rf = ((int64_t)(first < 0 ? 0 : first) * C + cc) * D;
+                        const int64_t rc = ((int64_t)(cand < 0 ? 0 : cand) * C + cc) * D;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (ok[b][e]) {
+                                    const int64_t d = dim_of(b, e);
+                                    lfx[rk + d] = first < 0 ? wx[b][e] : lfx[rf + d];
+                                    lfr[rk + d] = first < 0 ? wr[b][e] : lfr[rf + d];
+                                    lcx[rk + d] = cand < 0 ? wx[b][e] : lcx[rc + d];
+                                    lcg[rk + d] = cand < 0 ? wg[b][e] : lcg[rc + d];
+                                }
+                        lcn[k - 1] = n_node;
+                        lclp[k - 1] = cand_lp;
+                        parked = true;
+                        break;
+                    }
+                    const int32_t nl = lcn[k - 1];
+                    const uint32_t block = ((uint32_t)j * 1024u + (uint32_t)i) * 16u + (uint32_t)k;
+                    const double u = nuts_u52(a.key, (uint32_t)cc, t, block, TAG_NUTS_MERGE);
+                    if (!((nl + n_node > 0) && u < (double)n_node / (double)(nl + n_node))) {
+                        cand = k;
+                        cand_lp = lclp[k - 1];
+                    }
+                    n_node += nl;
+                    double dm = 0.0, dp = 0.0;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (ok[b][e]) {
+                                const int64_t d = dim_of(b, e);
+                                const double fx = (double)lfx[rk + d], fr = (double)lfr[rk + d];
+                                const double lx = (double)wx[b][e], lr = (double)wr[b][e];
+                                const double dx = v > 0 ? lx - fx : fx - lx;
+                                dm += dx * (v > 0 ? fr : lr);
+                                dp += dx * (v > 0 ? lr : fr);
+                            }
+                    dm = group_sum<G>(dm);
+                    dp = group_sum<G>(dp);
+                    first = k;
+                    if (!(dm >= 0.0 && dp >= 0.0)) {
+                        alive = false;
+                        break;
+                    }
+                }
+                if (!alive) break;
+                if (!parked) {          // the last leaf: every subtree of doubling j ends here
+                    const int64_t rc = ((int64_t)(cand < 0 ? 0 : cand) * C + cc) * D;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int64_t d = dim_of(b, e);
+                            rcx[b][e] = cand < 0 ? wx[b][e] : (ok[b][e] ? lcx[rc + d] : (T)0);
+                            rcg[b][e] = cand < 0 ? wg[b][e] : (ok[b][e] ? lcg[rc + d] : (T)0);
+                        }
+                    rclp = cand_lp;
+                    rcn = n_node;
+                    complete = true;
+                }
+            }
+            // the working state becomes the trajectory end in direction v
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (v > 0) {
+                        px[b][e] = wx[b][e];
+                        pr[b][e] = wr[b][e];
+                        pg[b][e] = wg[b][e];
+                    } else {
+                        mx[b][e] = wx[b][e];
+                        mr[b][e] = wr[b][e];
+                        mg[b][e] = wg[b][e];
+                    }
+                }
+            if (v > 0) plogp = wlogp;
+            else mlogp = wlogp;
+            depth = j + 1;
+            s = false;
+            if (alive && complete) {
+                if (nuts_u52(a.key, (uint32_t)cc, t, (uint32_t)j, TAG_NUTS_TOP) < (double)rcn / ntot) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            x[b][e] = rcx[b][e];
+                            g[b][e] = rcg[b][e];
+                        }
+                    logp = rclp;
+                }
+                ntot += (double)rcn;
+                double dm = 0.0, dp = 0.0;
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double dx = (double)px[b][e] - (double)mx[b][e];
+                        dm += dx * (double)mr[b][e];
+                        dp += dx * (double)pr[b][e];
+                    }
+                dm = group_sum<G>(dm);
+                dp = group_sum<G>(dp);
+                s = dm >= 0.0 && dp >= 0.0;
+            }
+        }
+        if (active && it >= n_burnin) {
+            const int64_t r = it - n_burnin;
+            if (samples)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (ok[b][e]) samples[(r * C + c) * D + dim_of(b, e)] = x[b][e];
+            if (lane == 0) {
+                if (tr_depth) tr_depth[r * C + c] = depth;
+                if (tr_nleap) tr_nleap[r * C + c] = nleap;
+            }
+        }
+    }
+    if (!active) return;
+    T* Xw = (T*)a.ws.x;
+    T* Gw = (T*)a.ws.g;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (ok[b][e]) {
+                Xw[c * D + dim_of(b, e)] = x[b][e];
+                Gw[c * D + dim_of(b, e)] = g[b][e];
+            }
+    if (lane == 0) a.ws.logp[c] = logp;
+}
+
+// lanes per chain and 4-dim blocks per lane of the persistent kernel, 0 if it
+// does not apply (registers: FP64 keeps one block per lane, FP32 two)
+static int nuts_elem_shape(const PlainArgs& a, int* G) {
+    if (a.tg.kind != HMC_TGT_STD_NORMAL && a.tg.kind != HMC_TGT_GAUSS_DIAG) return 0;
+    const int64_t nblk = (a.tg.D + 3) / 4;
+    if (nblk <= 1) { *G = 1; return 1; }
+    if (nblk <= 4) { *G = 4; return 1; }
+    if (nblk <= 16) { *G = 16; return 1; }
+    if (nblk <= 64) { *G = 64; return 1; }
+    if (nblk <= 128 && !a.f64) { *G = 64; return 2; }
+    return 0;
+}
+
+bool nuts_fused_supported(const PlainArgs& a) {
+    int G;
+    return nuts_elem_shape(a, &G) > 0;
+}
+
+hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, uint32_t t_begin, int64_t n_trans, int64_t n_burnin,
+                             int32_t max_depth, void* samples, int32_t* tr_depth, int32_t* tr_nleap, hipStream_t s) {
+    int G = 0;
+    const int NB = nuts_elem_shape(a, &G);
+    if (NB == 0) return hipErrorNotSupported;
+    const dim3 grid((unsigned)((a.C * G + 255) / 256));
+#define HMC_NUTS_F(TT, GG, NN)                                                                                      \
+    hipLaunchKernelGGL((k_nuts_fused_elem<TT, GG, NN>), grid, dim3(256), 0, s, a, n, t_begin, n_trans, n_burnin, \
+                       max_depth, (TT*)samples, tr_depth, tr_nleap)
+    if (a.f64) {
+        if (G == 1) HMC_NUTS_F(double, 1, 1);
+        else if (G == 4) HMC_NUTS_F(double, 4, 1);
+        else if (G == 16) HMC_NUTS_F(double, 16, 1);
+        else HMC_NUTS_F(double, 64, 1);
+    } else {
+        if (G == 1) HMC_NUTS_F(float, 1, 1);
+        else if (G == 4) HMC_NUTS_F(float, 4, 1);
+        else if (G == 16) HMC_NUTS_F(float, 16, 1);
+        else if (NB == 1) HMC_NUTS_F(float, 64, 1);
+        else HMC_NUTS_F(float, 64, 2);
+    }
+#undef HMC_NUTS_F
+    return hipGetLastError();
+}
+
 __global__ void k_nuts_zero(int32_t* p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }

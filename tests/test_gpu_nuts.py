@@ -25,14 +25,18 @@ import torch  # noqa: E402
 from paper_2002_01184_amd import hmc  # noqa: E402
 
 
+FORMS = {"lockstep": hmc.HMC_FORM_PLAIN, "persistent": hmc.HMC_FORM_AUTO}
+
+
 @pytest.mark.parametrize("case", ["std1", "diag5"])
-def test_fp64_runs_match_oracle(case):
+@pytest.mark.parametrize("form", ["lockstep", "persistent"])
+def test_fp64_runs_match_oracle(case, form):
     if case == "std1":
         w = W.std_normal_1d(num_chains=64, step_size=0.5)
         w.x0 = np.random.default_rng(0).normal(size=(64, 1))
     else:
         w = W.gauss_diag(dim=5, num_chains=48, step_size=0.3, state_dtype="f64", lam_lo=0.3, lam_hi=3.0)
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    s = hmc.sampler_for(w, form=FORMS[form])
     g = s.nuts_sample_chain(40, 10, max_depth=6)
     s.close()
     o = oracle.nuts_sample_chain(oracle_target(w), w.seed, w.x0.astype(np.float64), w.step_size, 10, 40, max_depth=6)
@@ -53,9 +57,10 @@ def _fp32_cases():
 
 
 @pytest.mark.parametrize("name", list(_fp32_cases()))
-def test_fp32_one_transition_parity(name):
+@pytest.mark.parametrize("form", ["lockstep", "persistent"])
+def test_fp32_one_transition_parity(name, form):
     w = _fp32_cases()[name]
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    s = hmc.sampler_for(w, form=FORMS[form])
     g = s.nuts_sample_chain(1, 0, max_depth=8)
     xg, _, t = s.get_state()
     s.close()
@@ -74,9 +79,10 @@ def test_fp32_one_transition_parity(name):
     assert max(errs) <= 1e-5, max(errs)
 
 
-def test_fp32_standard_normal_moments():
+@pytest.mark.parametrize("form", ["lockstep", "persistent"])
+def test_fp32_standard_normal_moments(form):
     w = W.std_normal_1d(num_chains=256, dim=3, state_dtype="f32", step_size=0.3)
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    s = hmc.sampler_for(w, form=FORMS[form])
     g = s.nuts_sample_chain(300, 30, max_depth=8)
     s.close()
     x = to_np(g["samples"]).reshape(-1, 3)
@@ -93,3 +99,14 @@ def test_nuts_errors():
     with pytest.raises(hmc.HMCError, match="NUTS"):
         s.nuts_sample_chain(1, 0)
     s.close()
+
+
+def test_persistent_and_lockstep_build_the_same_trees():
+    w = W.gauss_diag(dim=300, num_chains=70, step_size=0.05)      # 64 lanes x 2 blocks per chain, FP32
+    out = []
+    for form in (hmc.HMC_FORM_PLAIN, hmc.HMC_FORM_AUTO):
+        s = hmc.sampler_for(w, form=form)
+        out.append(s.nuts_sample_chain(6, 2, max_depth=7))
+        s.close()
+    same = (out[0]["tree_depth"] == out[1]["tree_depth"]) & (out[0]["n_leapfrog"] == out[1]["n_leapfrog"])
+    assert same.float().mean().item() >= 0.99
