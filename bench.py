@@ -161,7 +161,9 @@ def bench_remc(args):
         w.num_results = args.transitions - w.num_burnin
     M = w.num_chains // K
     betas = [args.remc_beta_min ** (k / max(K - 1, 1)) for k in range(K)]
-    form = hmc.HMC_FORM_GRAPH if args.form == "graph" else hmc.HMC_FORM_PLAIN
+    # tempering runs on the fused kernels for the Gaussian targets, on the plain ones for logistic regression
+    form = {"graph": hmc.HMC_FORM_GRAPH, "plain": hmc.HMC_FORM_PLAIN}.get(
+        args.form, hmc.HMC_FORM_PLAIN if w.kind == W.LOGREG else hmc.HMC_FORM_AUTO)
     s = hmc.sampler_for(w, form=form, grad_bf16=args.grad == "bf16")
     s.set_inverse_temperature(torch.tensor(np.repeat(betas, M), dtype=torch.float64, device="cuda"))
     x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).cuda()
@@ -203,11 +205,12 @@ def bench_remc(args):
                    "inverse_temperatures": betas, "dim": w.dim, "n_rows": w.n_rows,
                    "num_leapfrog_steps": w.num_leapfrog_steps, "num_burnin": w.num_burnin,
                    "num_results": w.num_results, "adapt": "dual averaging to 0.8" if w.adapt else "none",
-                   "form": {hmc.HMC_FORM_PLAIN: "plain", hmc.HMC_FORM_GRAPH: "graph"}[hmc.hmc_effective_form(s.ctx)],
+                   "form": {hmc.HMC_FORM_PLAIN: "plain", hmc.HMC_FORM_GRAPH: "graph",
+                            hmc.HMC_FORM_FUSED: "fused (one launch per transition)"}[hmc.hmc_effective_form(s.ctx)],
                    "parallelism": "chains (1 GPU)"},
         "roofline": {"bound": bound, "achieved": achieved / scale, "peak": peak / scale,
                      "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "plain kernels + exchange step", "kernel_ms_per_launch": kernel_ms,
+                     "kernel": "transition kernels + exchange step", "kernel_ms_per_launch": kernel_ms,
                      "work_per_launch": per_cs * w.chain_steps()},
         "swap_rate": float(out["swapped"].float().mean().item()),
         "accept_rate": float(out["is_accepted"].float().mean().item()),

@@ -206,14 +206,16 @@ hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char* report, s
  * (the tempered target of the paper: the log-probability times the inverse
  * temperature, by broadcasting); the replicas of one temperature ladder
  * 1 = beta_0 > beta_1 > ... hold the same beta in all M chains.  Tempering
- * runs on the plain and graph forms.
+ * runs on every form for the Gaussian targets and on the plain and graph
+ * forms for logistic regression.
  * ------------------------------------------------------------------------- */
 
 /* Sets per-chain inverse temperatures: beta (device, FP64, [C]) is copied;
  * every value must be finite and > 0 (HMC_E_INVALID otherwise, nothing
- * changed).  NULL restores beta = 1 for every chain.  A context of the
- * fused form returns HMC_E_UNSUPPORTED (create it with HMC_FORM_PLAIN or
- * HMC_FORM_GRAPH); the autotuner then keeps to the plain and graph forms.
+ * changed).  NULL restores beta = 1 for every chain.  A fused-form context
+ * of logistic regression returns HMC_E_UNSUPPORTED (create it with
+ * HMC_FORM_PLAIN or HMC_FORM_GRAPH), and the autotuner keeps tempered
+ * logistic contexts to the plain and graph forms.
  * The cached log-probability, traced target_log_prob and the state stay those
  * of the untempered target.  Synchronizes the stream. */
 hmc_status hmc_set_inverse_temperature(hmc_ctx* ctx, const double* beta);
@@ -231,8 +233,8 @@ hmc_status hmc_remc_swap(hmc_ctx* ctx, int64_t num_replicas, uint64_t swap_index
 
 /* Replica-exchange sample_chain: num_burnin + num_results times, one
  * transition of every chain (as hmc_sample_chain, with the same adaptation
- * and traces) followed by the exchange step whose swap index is that
- * transition's t.  samples [R, C, D] (device, may be NULL) receive the states
+ * and traces; on the fused form one launch per transition) followed by the
+ * exchange step whose swap index is that transition's t.  samples [R, C, D] (device, may be NULL) receive the states
  * after the exchange of transition burnin + r; swapped (device [R, C], may be
  * NULL) the exchange flags of the kept transitions; the trace rows hold the
  * transition's results before the exchange.  Asynchronous. */

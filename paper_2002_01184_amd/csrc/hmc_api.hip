@@ -519,7 +519,9 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache_locked();
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end() && !((ctx->a.ws.beta || ctx->a.ws.scale) && it->second.form == HMC_FORM_FUSED)) {
+        if (it != g_tune_cache.end() &&
+            !((ctx->a.ws.scale || (ctx->a.ws.beta && ctx->a.tg.kind == HMC_TGT_LOGREG)) &&
+              it->second.form == HMC_FORM_FUSED)) {
             ctx->form = it->second.form;
             ctx->a.tune = it->second.tune;
             drop_graph(ctx);
@@ -531,7 +533,8 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
     std::vector<TuneChoice> cands;
     std::vector<int32_t> forms;
     if (ctx->cfg.form == HMC_FORM_AUTO) {
-        if (fused_supported(ctx->a) && !ctx->a.ws.beta && !ctx->a.ws.scale)   // tempered / transformed: plain kernels
+        // transformed contexts, and tempered logistic ones, keep to the plain kernels
+    if (fused_supported(ctx->a) && !ctx->a.ws.scale && !(ctx->a.ws.beta && ctx->a.tg.kind == HMC_TGT_LOGREG))
         forms.push_back(HMC_FORM_FUSED);
         forms.push_back(HMC_FORM_PLAIN);
         forms.push_back(HMC_FORM_GRAPH);
@@ -625,10 +628,10 @@ hmc_status hmc_set_inverse_temperature(hmc_ctx* ctx, const double* beta) {
         drop_graph(ctx);
         return HMC_OK;
     }
-    if (ctx->form == HMC_FORM_FUSED)
+    if (ctx->form == HMC_FORM_FUSED && ctx->a.tg.kind == HMC_TGT_LOGREG)
         return fail(HMC_E_UNSUPPORTED,
-                    "inverse temperatures run on the plain or graph form: create the context with "
-                    "HMC_FORM_PLAIN or HMC_FORM_GRAPH");
+                    "inverse temperatures on logistic regression run on the plain or graph form: create the "
+                    "context with HMC_FORM_PLAIN or HMC_FORM_GRAPH");
     std::vector<double> h((size_t)ctx->a.C);
     hmc_status st = check_hip(hipMemcpyAsync(h.data(), beta, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream),
                               "read inverse temperatures");
@@ -649,8 +652,8 @@ static hmc_status remc_check(const hmc_ctx* ctx, int64_t num_replicas) {
     if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
     if (num_replicas < 1 || ctx->a.C % num_replicas != 0)
         return fail(HMC_E_INVALID, "num_replicas must be >= 1 and divide the number of chains");
-    if (ctx->form == HMC_FORM_FUSED)
-        return fail(HMC_E_UNSUPPORTED, "replica exchange runs on the plain or graph form");
+    if (ctx->form == HMC_FORM_FUSED && ctx->a.tg.kind == HMC_TGT_LOGREG)
+        return fail(HMC_E_UNSUPPORTED, "replica exchange on logistic regression runs on the plain or graph form");
     return HMC_OK;
 }
 
@@ -674,11 +677,42 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
     const int64_t total = num_results + num_burnin_steps;
     if (ctx->t + (uint64_t)total > 0xffffffffull) return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
     const int64_t C = ctx->a.C, M = C / num_replicas;
-    const size_t row = (size_t)C * ctx->a.tg.D * (ctx->a.f64 ? 8 : 4);
+    const size_t rowb = (size_t)C * ctx->a.tg.D * (ctx->a.f64 ? 8 : 4);
     hmc_trace tr;
     memset(&tr, 0, sizeof(tr));
     if (trace) tr = *trace;
     if (ad) st = check_hip(launch_da_init(ctx->a, ctx->stream), "adaptation init");
+    if (ctx->form == HMC_FORM_FUSED) {
+        // one fused launch per transition (its trace row), then the exchange and the sample copy
+        for (int64_t i = 0; i < total && st == HMC_OK; ++i) {
+            const uint64_t t = ctx->t + (uint64_t)i;
+            const bool kept = i >= num_burnin_steps;
+            const size_t row = kept ? (size_t)(i - num_burnin_steps) * C : 0;
+            FusedRun r;
+            memset(&r, 0, sizeof(r));
+            r.t_begin = t;
+            r.n_transitions = 1;
+            r.n_burnin = kept ? 0 : 1;
+            r.m_offset = i;
+            r.adapt_total = num_burnin_steps;
+            set_adapt(r, adapt);
+            if (kept) {
+                r.trace.step_size = tr.step_size ? tr.step_size + row : nullptr;
+                r.trace.is_accepted = tr.is_accepted ? tr.is_accepted + row : nullptr;
+                r.trace.log_accept_ratio = tr.log_accept_ratio ? tr.log_accept_ratio + row : nullptr;
+                r.trace.target_log_prob = tr.target_log_prob ? tr.target_log_prob + row : nullptr;
+            }
+            st = check_hip(launch_fused(ctx->a, r, ctx->stream), "fused remc transition");
+            uint8_t* sw = (kept && swapped) ? swapped + row : nullptr;
+            if (st == HMC_OK)
+                st = check_hip(launch_remc_swap(ctx->a, num_replicas, M, (uint32_t)t, sw, ctx->stream), "exchange step");
+            if (st == HMC_OK && kept && samples)
+                st = check_hip(hipMemcpyAsync((char*)samples + (size_t)(i - num_burnin_steps) * rowb, ctx->a.ws.x, rowb,
+                                              hipMemcpyDeviceToDevice, ctx->stream), "sample copy");
+        }
+        if (st == HMC_OK) ctx->t += (uint64_t)total;
+        return st;
+    }
     // the transitions write the traces; the samples are taken after each exchange
     Ctrl c = base_ctrl(ctx);
     c.n_burnin = num_burnin_steps;
@@ -698,7 +732,7 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
         if (st == HMC_OK)
             st = check_hip(launch_remc_swap(ctx->a, num_replicas, M, (uint32_t)t, sw, ctx->stream), "exchange step");
         if (st == HMC_OK && kept && samples)
-            st = check_hip(hipMemcpyAsync((char*)samples + (size_t)(i - num_burnin_steps) * row, ctx->a.ws.x, row,
+            st = check_hip(hipMemcpyAsync((char*)samples + (size_t)(i - num_burnin_steps) * rowb, ctx->a.ws.x, rowb,
                                           hipMemcpyDeviceToDevice, ctx->stream), "sample copy");
     }
     if (st == HMC_OK) ctx->t += (uint64_t)total;

@@ -83,11 +83,13 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
     s.logp = a.ws.logp[cc];
     s.eps = a.ws.eps[cc];
     s.da = a.ws.da[cc];
+    const double bt = a.ws.beta ? a.ws.beta[cc] : 1.0;   // inverse temperature of the chain
 
     for (int64_t i = 0; i < r.n_transitions; ++i) {
         const uint32_t t = (uint32_t)(r.t_begin + i);
-        const T eps = (T)s.eps;
-        const T half = (T)(0.5 * s.eps);
+        const T eps = (T)s.eps;                   // drift
+        const T half = (T)(0.5 * s.eps * bt);     // kicks: beta eps (replica exchange; beta = 1 otherwise)
+        const T keps = (T)(s.eps * bt);
         T xn[NB][4], pn[NB][4], gn[NB][4];
         double dk = 0.0;
 #pragma unroll
@@ -104,7 +106,7 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
             }
         }
         for (int l = 0; l < a.L; ++l) {
-            const T ke = (l == a.L - 1) ? half : eps;
+            const T ke = (l == a.L - 1) ? half : keps;
 #pragma unroll
             for (int k = 0; k < NB; ++k)
 #pragma unroll
@@ -124,7 +126,7 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
             }
         dk = group_sum<G>(dk);
         lp = group_sum<G>(lp);
-        const double dh = -lp + s.logp + dk;
+        const double dh = -(bt * lp) + bt * s.logp + dk;
         const double lar = log_accept_ratio_of(dh);
         const bool acc = log_accept_uniform(a.key, (uint32_t)cc, t) < lar;
         if (acc) {
@@ -268,11 +270,12 @@ __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
     s.logp = a.ws.logp[cc];
     s.eps = a.ws.eps[cc];
     s.da = a.ws.da[cc];
+    const double bt = a.ws.beta ? a.ws.beta[cc] : 1.0;   // inverse temperature of the chain
     int buf = 0;
 
     for (int64_t i = 0; i < r.n_transitions; ++i) {
         const uint32_t t = (uint32_t)(r.t_begin + i);
-        const float eps = (float)s.eps, half = (float)(0.5 * s.eps);
+        const float eps = (float)s.eps, half = (float)(0.5 * s.eps * bt), keps = (float)(s.eps * bt);
         float xn[MT][4], pn[MT][4], gn[MT][4];
         double dk = 0.0;
 #pragma unroll
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
             }
         }
         for (int l = 0; l < a.L; ++l) {
-            const float ke = (l == a.L - 1) ? half : eps;
+            const float ke = (l == a.L - 1) ? half : keps;
             float* xs = buf ? xs1 : xs0;
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
@@ -354,7 +357,7 @@ __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
             dk += rb[(2 * ww) * 16 + i16];
             lp += rb[(2 * ww + 1) * 16 + i16];
         }
-        const double dh = -lp + s.logp + dk;
+        const double dh = -(bt * lp) + bt * s.logp + dk;
         const double lar = log_accept_ratio_of(dh);
         const bool acc = log_accept_uniform(a.key, (uint32_t)cc, t) < lar;
         if (acc) {

@@ -30,11 +30,14 @@ def _betas_per_chain(betas, M):
     return torch.tensor(np.repeat(np.asarray(betas, dtype=np.float64), M), device="cuda")
 
 
-@pytest.mark.parametrize("form", ["plain", "graph"])
+FORMS = {"plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_GRAPH, "fused": hmc.HMC_FORM_FUSED}
+
+
+@pytest.mark.parametrize("form", ["plain", "graph", "fused"])
 def test_remc_paper_example_fp64_full_run_matches_oracle(form):
     K, M = len(BETAS), 25
     w = W.std_normal_1d(num_chains=K * M)
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN if form == "plain" else hmc.HMC_FORM_GRAPH)
+    s = hmc.sampler_for(w, form=FORMS[form])
     s.set_inverse_temperature(_betas_per_chain(BETAS, M))
     g = s.remc_sample_chain(K, 40, 30)
     s.close()
@@ -45,13 +48,14 @@ def test_remc_paper_example_fp64_full_run_matches_oracle(form):
     assert o["swapped"].any() and not o["swapped"].all()
 
 
-def test_remc_adapted_run_matches_oracle_in_distribution():
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_remc_adapted_run_matches_oracle_in_distribution(form):
     # dual averaging per chain slot during the burn-in, then frozen; FP64 1-D.
     # Adapted runs are compared in distribution (the recursion amplifies
     # rounding differences of the early iterations).
     K, M = len(BETAS), 50
     w = W.std_normal_1d(num_chains=K * M, step_size=0.8)
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    s = hmc.sampler_for(w, form=FORMS[form])
     s.set_inverse_temperature(_betas_per_chain(BETAS, M))
     g = s.remc_sample_chain(K, 300, 100, adapt=True)
     _, eps, t = s.get_state()
@@ -86,11 +90,14 @@ def _tempered_cases():
 
 
 @pytest.mark.parametrize("name", list(_tempered_cases()))
-def test_tempered_one_step_parity(name):
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_tempered_one_step_parity(name, form):
     w, K = _tempered_cases()[name]
+    if form == "fused" and w.kind == W.LOGREG:
+        pytest.skip("tempered logistic regression runs on the plain and graph forms")
     M = w.num_chains // K
     betas = [0.9 ** (3 * k) for k in range(K)]
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    s = hmc.sampler_for(w, form=FORMS[form])
     s.set_inverse_temperature(_betas_per_chain(betas, M))
     rng = np.random.default_rng(11)
     x = w.x0.copy()
@@ -134,12 +141,13 @@ def test_exchange_step_matches_oracle_exactly_fp64():
     s.close()
 
 
-def test_unit_temperatures_are_bitwise_the_untempered_run():
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_unit_temperatures_are_bitwise_the_untempered_run(form):
     w = W.gauss_dense(dim=30, num_chains=64, L=8, step_size=0.15, seed=1)
-    a = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    a = hmc.sampler_for(w, form=FORMS[form])
     ra = a.sample_chain(6, 4)
     a.close()
-    b = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    b = hmc.sampler_for(w, form=FORMS[form])
     b.set_inverse_temperature(torch.ones(64, dtype=torch.float64, device="cuda"))
     rb = b.sample_chain(6, 4)
     b.close()
