@@ -54,7 +54,7 @@ __device__ __forceinline__ void after_decision(const FusedRun& r, int64_t C, int
 // Elementwise targets.  NB blocks of 4 dims per lane; lane j of a group owns
 // blocks j, j + G, ...
 // ---------------------------------------------------------------------------
-template <typename T, int G, int NB>
+template <typename T, int G, int NB, bool TR>
 __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedRun& r, int64_t lblock) {
     const int64_t gid = lblock * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % G;
@@ -67,6 +67,18 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
     T* Gr = (T*)a.ws.g;
     const T* prec = (const T*)a.tg.prec;
 
+    // Transformed kernel (x = shift + scale z, TR): the chain runs in
+    // z = x / scale, whose precision is prec scale^2; states are converted at
+    // load and store.  A template parameter, so that the untransformed
+    // kernels carry none of it.
+    const double* sc = TR ? a.ws.scale : nullptr;
+    // the scale in the state's precision, staged once in LDS for the stores
+    // of x (a lane group covers 4 G NB >= D dims)
+    __shared__ T sc_lds[TR ? 4 * G * NB : 1];
+    if (TR) {
+        for (int64_t d = threadIdx.x; d < D; d += blockDim.x) sc_lds[d] = (T)sc[d];
+        __syncthreads();
+    }
     T x[NB][4], g[NB][4], pr[NB][4];
     bool ok[NB][4];
 #pragma unroll
@@ -78,6 +90,12 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
             x[k][j] = ok[k][j] ? X[cc * D + d] : (T)0;
             g[k][j] = ok[k][j] ? Gr[cc * D + d] : (T)0;
             pr[k][j] = ok[k][j] ? (diag ? prec[d] : (T)1) : (T)0;
+            if (sc && ok[k][j]) {
+                const double sd = sc[d];
+                pr[k][j] = (T)((double)pr[k][j] * sd * sd);
+                x[k][j] = (T)((double)x[k][j] / sd);
+                g[k][j] = (T)((double)g[k][j] * sd);
+            }
         }
     ChainCtl s;
     s.logp = a.ws.logp[cc];
@@ -142,20 +160,36 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
         if (active) {
             if (r.samples && i >= r.n_burnin) {
                 T* smp = (T*)r.samples + ((i - r.n_burnin) * a.C + c) * D;
+                if (TR) {
+                    // an index the compiler cannot see through keeps the LDS
+                    // reads here: hoisted out of the transition loop they
+                    // would hold NB 4 registers for the whole run
+                    int l4 = 4 * lane;
+                    asm volatile("" : "+v"(l4));
 #pragma unroll
-                for (int k = 0; k < NB; ++k)
+                    for (int k = 0; k < NB; ++k)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (ok[k][j]) smp[4 * (lane + (int64_t)G * k) + j] = x[k][j];
+                        for (int j = 0; j < 4; ++j)
+                            if (ok[k][j]) smp[4 * (lane + (int64_t)G * k) + j] = x[k][j] * sc_lds[l4 + 4 * G * k + j];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NB; ++k)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (ok[k][j]) smp[4 * (lane + (int64_t)G * k) + j] = x[k][j];
+                }
             }
             if (r.out.proposed_state || r.out.proposed_momentum) {
+                int l4 = 4 * lane;
+                if (TR) asm volatile("" : "+v"(l4));
 #pragma unroll
                 for (int k = 0; k < NB; ++k)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         if (ok[k][j]) {
                             const int64_t d = 4 * (lane + (int64_t)G * k) + j;
-                            if (r.out.proposed_state) ((T*)r.out.proposed_state)[c * D + d] = xn[k][j];
+                            if (r.out.proposed_state)
+                                ((T*)r.out.proposed_state)[c * D + d] = TR ? xn[k][j] * sc_lds[l4 + 4 * G * k + j] : xn[k][j];
                             if (r.out.proposed_momentum) ((T*)r.out.proposed_momentum)[c * D + d] = pn[k][j];
                         }
             }
@@ -163,14 +197,17 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
         }
     }
     if (!active) return;
+    // a fresh read of the scale: reusing the values loaded before the loop
+    // would hold them in registers for the whole run
+    if (TR) asm volatile("" ::: "memory");
 #pragma unroll
     for (int k = 0; k < NB; ++k)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (ok[k][j]) {
                 const int64_t d = 4 * (lane + (int64_t)G * k) + j;
-                X[c * D + d] = x[k][j];
-                Gr[c * D + d] = g[k][j];
+                X[c * D + d] = TR ? (T)((double)x[k][j] * sc[d]) : x[k][j];
+                Gr[c * D + d] = TR ? (T)((double)g[k][j] / sc[d]) : g[k][j];
             }
     if (lane == 0) {
         a.ws.logp[c] = s.logp;
@@ -179,9 +216,9 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
     }
 }
 
-template <typename T, int G, int NB>
+template <typename T, int G, int NB, bool TR>
 __global__ __launch_bounds__(256) void k_fused_elem(PlainArgs a, FusedRun r) {
-    fused_elem_body<T, G, NB>(a, r, blockIdx.x);
+    fused_elem_body<T, G, NB, TR>(a, r, blockIdx.x);
 }
 
 // Several requests of one shape class in one grid: block b runs job j with
@@ -196,7 +233,7 @@ __global__ __launch_bounds__(256) void k_fused_elem_multi(const ElemJob* __restr
     }
     const PlainArgs a = jobs[lo].a;
     const FusedRun r = jobs[lo].r;
-    fused_elem_body<T, G, NB>(a, r, (int64_t)blockIdx.x - jobs[lo].block_begin);
+    fused_elem_body<T, G, NB, false>(a, r, (int64_t)blockIdx.x - jobs[lo].block_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -221,7 +258,7 @@ __global__ __launch_bounds__(256) void k_fused_elem_multi(const ElemJob* __restr
 // ---------------------------------------------------------------------------
 constexpr int DENSE_NW = 4;
 
-template <int NT>
+template <int NT, bool TR>
 __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
     constexpr int MT = (NT + DENSE_NW - 1) / DENSE_NW;
     constexpr int KM = 4 * NT;
@@ -241,6 +278,15 @@ __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
     float* X = (float*)a.ws.x;
     float* Gr = (float*)a.ws.g;
 
+    // Transformed kernel (x = shift + scale z, TR): the chain runs in
+    // z = x / scale, whose precision matrix is S P S (S = diag(scale)); states
+    // are converted at load and store.
+    const double* sc = TR ? a.ws.scale : nullptr;
+    __shared__ float sc_lds[TR ? 16 * NT : 1];     // the scale, for the stores of x
+    if (TR) {
+        for (int d = threadIdx.x; d < D; d += blockDim.x) sc_lds[d] = (float)sc[d];
+        __syncthreads();
+    }
     // P as A operands: pa[m][ks] = P[16 mt + i16][g4 KM + ks]
     float pa[MT][KM];
     bool tile_ok[MT];
@@ -252,7 +298,9 @@ __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
 #pragma unroll
         for (int ks = 0; ks < KM; ++ks) {
             const int64_t col = (int64_t)g4 * KM + ks;
-            pa[m][ks] = (tile_ok[m] && row < D && col < D) ? P[row * D + col] : 0.f;
+            const bool in = tile_ok[m] && row < D && col < D;
+            pa[m][ks] = in ? P[row * D + col] : 0.f;
+            if (sc && in) pa[m][ks] = (float)((double)pa[m][ks] * sc[row] * sc[col]);
         }
     }
     float x[MT][4], g[MT][4];
@@ -265,6 +313,10 @@ __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
             ok[m][v] = tile_ok[m] && cvalid && d < D;
             x[m][v] = ok[m][v] ? X[cc * D + d] : 0.f;
             g[m][v] = ok[m][v] ? Gr[cc * D + d] : 0.f;
+            if (sc && ok[m][v]) {
+                x[m][v] = (float)((double)x[m][v] / sc[d]);
+                g[m][v] = (float)((double)g[m][v] * sc[d]);
+            }
         }
     ChainCtl s;
     s.logp = a.ws.logp[cc];
@@ -372,28 +424,34 @@ __global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
         }
         if (cvalid) {
             const bool want_smp = r.samples && i >= r.n_burnin;
+            int q = 16 * w + 4 * g4;                 // opaque: keeps the LDS reads of the scale here
+            if (TR) asm volatile("" : "+v"(q));
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     if (ok[m][v]) {
                         const int64_t d = 16 * (w + DENSE_NW * m) + 4 * g4 + v;
-                        if (want_smp) ((float*)r.samples)[((i - r.n_burnin) * a.C + c) * D + d] = x[m][v];
-                        if (r.out.proposed_state) ((float*)r.out.proposed_state)[c * D + d] = xn[m][v];
+                        const float sd = TR ? sc_lds[q + 16 * DENSE_NW * m + v] : 1.f;
+                        if (want_smp)
+                            ((float*)r.samples)[((i - r.n_burnin) * a.C + c) * D + d] = TR ? x[m][v] * sd : x[m][v];
+                        if (r.out.proposed_state)
+                            ((float*)r.out.proposed_state)[c * D + d] = TR ? xn[m][v] * sd : xn[m][v];
                         if (r.out.proposed_momentum) ((float*)r.out.proposed_momentum)[c * D + d] = pn[m][v];
                     }
             after_decision(r, a.C, c, i, acc, lar, dh, s.logp, s, w == 0 && g4 == 0);
         }
     }
     if (!cvalid) return;
+    if (TR) asm volatile("" ::: "memory");   // a fresh read of the scale (see the element-wise kernel)
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             if (ok[m][v]) {
                 const int64_t d = 16 * (w + DENSE_NW * m) + 4 * g4 + v;
-                X[c * D + d] = x[m][v];
-                Gr[c * D + d] = g[m][v];
+                X[c * D + d] = sc ? (float)((double)x[m][v] * sc[d]) : x[m][v];
+                Gr[c * D + d] = sc ? (float)((double)g[m][v] / sc[d]) : g[m][v];
             }
     if (w == 0 && g4 == 0) {
         a.ws.logp[c] = s.logp;
@@ -482,9 +540,15 @@ template <typename T>
 static hipError_t launch_elem(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     const int cls = elem_class(a);
     const dim3 grid((unsigned)elem_blocks(a));
-#define HMC_ELEM(GG, NN) hipLaunchKernelGGL((k_fused_elem<T, GG, NN>), grid, dim3(256), 0, s, a, r)
-    HMC_ELEM_DISPATCH(cls, HMC_ELEM)
+    if (a.ws.scale) {
+#define HMC_ELEM(GG, NN) hipLaunchKernelGGL((k_fused_elem<T, GG, NN, true>), grid, dim3(256), 0, s, a, r)
+        HMC_ELEM_DISPATCH(cls, HMC_ELEM)
 #undef HMC_ELEM
+    } else {
+#define HMC_ELEM(GG, NN) hipLaunchKernelGGL((k_fused_elem<T, GG, NN, false>), grid, dim3(256), 0, s, a, r)
+        HMC_ELEM_DISPATCH(cls, HMC_ELEM)
+#undef HMC_ELEM
+    }
     return hipGetLastError();
 }
 
@@ -508,8 +572,11 @@ static hipError_t launch_dense_fused(const PlainArgs& a, const FusedRun& r, hipS
     const size_t lds = (size_t)2 * 16 * (16 * ntiles + 4) * sizeof(float) + 2 * 2 * DENSE_NW * 16 * sizeof(double);
     const dim3 grid((unsigned)((a.C + 15) / 16));
     switch (ntiles) {
-#define HMC_DENSE_NT(N) \
-    case N: hipLaunchKernelGGL((k_fused_dense<N>), grid, dim3(256), lds, s, a, r); break;
+#define HMC_DENSE_NT(N)                                                                   \
+    case N:                                                                               \
+        if (a.ws.scale) hipLaunchKernelGGL((k_fused_dense<N, true>), grid, dim3(256), lds, s, a, r); \
+        else hipLaunchKernelGGL((k_fused_dense<N, false>), grid, dim3(256), lds, s, a, r);            \
+        break;
         HMC_DENSE_NT(1) HMC_DENSE_NT(2) HMC_DENSE_NT(3) HMC_DENSE_NT(4)
         HMC_DENSE_NT(5) HMC_DENSE_NT(6) HMC_DENSE_NT(7) HMC_DENSE_NT(8)
 #undef HMC_DENSE_NT
@@ -526,6 +593,8 @@ hipError_t launch_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     case HMC_TGT_GAUSS_DENSE:
         return launch_dense_fused(a, r, s);
     case HMC_TGT_LOGREG:
+        // the fused logistic kernel takes neither a transform nor temperatures
+        if (a.ws.scale || a.ws.beta) return hipErrorNotSupported;
         return launch_fused_logreg(a, r, s);
     }
     return hipErrorNotSupported;

@@ -1,8 +1,9 @@
 """GPU parity of the transformed kernel (paper Sec. 4.1, TransformedTransitionKernel
 with the diagonal affine bijector x = shift + scale * z) against the oracle,
 which runs plain HMC on z against the pulled-back target and pushes the
-samples forward.  The GPU runs in x with scale multiplying the step in every
-drift and kick.
+samples forward.  The plain form runs in x with scale multiplying the step in
+every drift and kick; the fused Gaussian kernels run in z = x / scale against
+the pulled-back precision.
 
 Bars as for the plain transition: the paper's FP64 example agrees with the
 oracle to 1e-12 with identical decisions over a whole run; FP32 one-step
@@ -26,7 +27,7 @@ import torch  # noqa: E402
 from paper_2002_01184_amd import hmc  # noqa: E402
 
 
-@pytest.mark.parametrize("form", [hmc.HMC_FORM_PLAIN, hmc.HMC_FORM_GRAPH])
+@pytest.mark.parametrize("form", [hmc.HMC_FORM_PLAIN, hmc.HMC_FORM_GRAPH, hmc.HMC_FORM_FUSED])
 def test_paper_example_transformed_run_matches_oracle(form):
     w = W.std_normal_1d()
     s = hmc.sampler_for(w, form=form)
@@ -49,11 +50,22 @@ def _cases():
     }
 
 
-@pytest.mark.parametrize("name", list(_cases()))
-def test_transformed_one_step_parity(name):
+def _form_cases():
+    # the fused form takes the transform for the Gaussian targets
+    out = []
+    for name in _cases():
+        out.append((name, "plain"))
+        if not name.startswith("logreg"):
+            out.append((name, "fused"))
+    return out
+
+
+@pytest.mark.parametrize("name,form", _form_cases())
+def test_transformed_one_step_parity(name, form):
     w = _cases()[name]
     scale = np.linspace(0.5, 1.5, w.dim)
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN if form == "plain" else hmc.HMC_FORM_FUSED)
+    assert hmc.hmc_effective_form(s.ctx) == (hmc.HMC_FORM_PLAIN if form == "plain" else hmc.HMC_FORM_FUSED)
     s.set_transform_scale(scale)
     tz = oracle_target(w).transformed(scale)
     rng = np.random.default_rng(7)
@@ -73,24 +85,38 @@ def test_transformed_one_step_parity(name):
     assert np.concatenate(agree).mean() >= 0.999
 
 
-def test_unit_scale_is_bitwise_the_untransformed_run():
-    w = W.logreg(300, 12, 48, L=6, step_size=0.05, seed=2)
-    a = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+def _unit_cases():
+    return {
+        "logreg_plain": (W.logreg(300, 12, 48, L=6, step_size=0.05, seed=2), hmc.HMC_FORM_PLAIN),
+        "dense_fused": (W.gauss_dense(dim=37, num_chains=45, L=7, step_size=0.1, seed=3), hmc.HMC_FORM_FUSED),
+        "diag_fused": (W.gauss_diag(dim=101, num_chains=40, L=6, step_size=0.08), hmc.HMC_FORM_FUSED),
+        "std_fp64_fused": (W.std_normal_1d(), hmc.HMC_FORM_FUSED),
+    }
+
+
+@pytest.mark.parametrize("name", list(_unit_cases()))
+def test_unit_scale_is_bitwise_the_untransformed_run(name):
+    w, form = _unit_cases()[name]
+    a = hmc.sampler_for(w, form=form)
     ra = a.sample_chain(8, 6, adapt=True)
+    xa = a.get_state()[0]
     a.close()
-    b = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
-    b.set_transform_scale(np.ones(12))
+    b = hmc.sampler_for(w, form=form)
+    b.set_transform_scale(np.ones(w.dim))
     rb = b.sample_chain(8, 6, adapt=True)
+    xb = b.get_state()[0]
     b.close()
     for k in ("samples", "is_accepted", "log_accept_ratio", "step_size"):
         assert torch.equal(ra[k], rb[k]), k
+    assert torch.equal(xa, xb)
 
 
-def test_whitening_speeds_up_an_ill_conditioned_gaussian():
+@pytest.mark.parametrize("form", [hmc.HMC_FORM_PLAIN, hmc.HMC_FORM_FUSED])
+def test_whitening_speeds_up_an_ill_conditioned_gaussian(form):
     # variances 1e-2 .. 1e2: with scale = sqrt(lambda) every mode has unit precision in z
     w = W.gauss_diag(dim=50, num_chains=512, L=5, step_size=0.3, burnin=50, results=200)
     lam = w.extra["lam"]
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    s = hmc.sampler_for(w, form=form)
     s.set_transform_scale(np.sqrt(lam))
     g = s.sample_chain(200, 50)
     s.close()
