@@ -45,7 +45,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        srcs = [os.path.join(os.path.dirname(_LIB_PATH), f) for f in ("oracle.c", "oracle.h")]
+        if not os.path.exists(_LIB_PATH) or max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(_LIB_PATH):
             from . import build as _b  # noqa: F401  (build script beside the source)
             _b.build()
         L = ctypes.CDLL(_LIB_PATH)
@@ -79,11 +80,13 @@ def lib():
         L.orc_simple_adapt.restype = ctypes.c_double
         L.orc_sample_chain.restype = ctypes.c_int
         L.orc_nuts_transition.argtypes = [ctypes.POINTER(_Target), ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-                                          ctypes.c_double, ctypes.c_int32, _dp, _dp, _dp, _i32p, _i32p]
+                                          ctypes.c_double, ctypes.c_int32, _dp, _dp, _dp, _i32p, _i32p, _dp, _dp,
+                                          _i32p]
         L.orc_nuts_transition.restype = ctypes.c_int
         L.orc_nuts_sample_chain.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
-                                            _dp, _dp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _dp, _i32p,
-                                            _i32p, ctypes.c_int32]
+                                            _dp, _dp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, _dp, _i32p, _i32p, _dp, ctypes.c_int32]
         L.orc_nuts_sample_chain.restype = ctypes.c_int
         L.orc_remc_swap.argtypes = [ctypes.POINTER(_Target), ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_uint32, _dp, _dp, _dp, _u8p]
@@ -361,8 +364,11 @@ def transformed_sample_chain(tg: Target, scale, shift, L: int, seed: int, x0, ep
 
 
 # ------------------------------------------------------------------- NUTS --
-def nuts_transition(tg: Target, seed: int, chain: int, t: int, eps: float, max_depth: int, x, logp=None, g=None):
-    """One NUTS transition of one chain.  Returns dict(x, logp, g, moved, depth, n_leapfrog)."""
+def nuts_transition(tg: Target, seed: int, chain: int, t: int, eps: float, max_depth: int, x, logp=None, g=None,
+                    record_leaves=False):
+    """One NUTS transition of one chain.  Returns dict(x, logp, g, moved, depth,
+    n_leapfrog, accept_stat); with record_leaves also leaf_x [n_leapfrog, D] and
+    leaf_j [n_leapfrog] (every leaf's position and doubling, in build order)."""
     x = _f64(x).copy()
     if logp is None or g is None:
         logp, g = logp_grad(tg, x)
@@ -370,15 +376,28 @@ def nuts_transition(tg: Target, seed: int, chain: int, t: int, eps: float, max_d
     lp = ctypes.c_double(float(logp))
     dep = ctypes.c_int32(0)
     nl = ctypes.c_int32(0)
+    stat = ctypes.c_double(0.0)
+    nmax = (1 << max_depth) - 1
+    leaf_x = np.zeros((max(nmax, 1), x.shape[0])) if record_leaves else None
+    leaf_j = np.zeros(max(nmax, 1), dtype=np.int32) if record_leaves else None
     moved = lib().orc_nuts_transition(tg.c, seed, chain, t, eps, max_depth, _p(x), ctypes.byref(lp), _p(g),
-                                      ctypes.byref(dep), ctypes.byref(nl))
-    return dict(x=x, logp=lp.value, g=g, moved=bool(moved), depth=dep.value, n_leapfrog=nl.value)
+                                      ctypes.byref(dep), ctypes.byref(nl), ctypes.byref(stat),
+                                      _p(leaf_x) if record_leaves else None,
+                                      _p(leaf_j, _i32p) if record_leaves else None)
+    out = dict(x=x, logp=lp.value, g=g, moved=bool(moved), depth=dep.value, n_leapfrog=nl.value,
+               accept_stat=stat.value)
+    if record_leaves:
+        out["leaf_x"] = leaf_x[:nl.value]
+        out["leaf_j"] = leaf_j[:nl.value]
+    return out
 
 
 def nuts_sample_chain(tg: Target, seed: int, x0, eps0, num_burnin: int, num_results: int, max_depth: int = 10,
-                      t_begin: int = 0, nthreads: int = 0):
-    """Oracle NUTS sample_chain (fixed step size).  Returns dict(samples [R,C,D],
-    depth [R,C], n_leapfrog [R,C], final_x)."""
+                      t_begin: int = 0, nthreads: int = 0, adapt=False, target_accept=0.8, gamma=0.05, t0=10.0,
+                      kappa=0.75, rate=0.01):
+    """Oracle NUTS sample_chain.  adapt as sample_chain's (the statistic is
+    Algorithm 6's accept_stat).  Returns dict(samples [R,C,D], depth [R,C],
+    n_leapfrog [R,C], accept_stat [R,C], final_x, final_eps)."""
     x = _f64(x0).copy()
     C, D = x.shape
     eps = np.broadcast_to(_f64(eps0), (C,)).copy()
@@ -386,6 +405,8 @@ def nuts_sample_chain(tg: Target, seed: int, x0, eps0, num_burnin: int, num_resu
     samples = np.empty((R, C, D))
     dep = np.empty((R, C), dtype=np.int32)
     nl = np.empty((R, C), dtype=np.int32)
+    stat = np.empty((R, C))
     lib().orc_nuts_sample_chain(tg.c, C, seed, t_begin, _p(x), _p(eps), max_depth, num_burnin, num_results,
-                                _p(samples), _p(dep, _i32p), _p(nl, _i32p), nthreads)
-    return dict(samples=samples, depth=dep, n_leapfrog=nl, final_x=x)
+                                _adapt_code(adapt), target_accept, gamma, t0, kappa, rate,
+                                _p(samples), _p(dep, _i32p), _p(nl, _i32p), _p(stat), nthreads)
+    return dict(samples=samples, depth=dep, n_leapfrog=nl, accept_stat=stat, final_x=x, final_eps=eps)

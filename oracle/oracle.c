@@ -539,6 +539,11 @@ typedef struct {
     int32_t n_leapfrog;
     double eps, log_u;
     int64_t D;
+    double H0;             /* energy of the starting point */
+    double alpha;          /* sum of min(1, exp(H0 - H)) over this doubling's leaves */
+    int32_t n_alpha;       /* and their number */
+    double *leaf_x;        /* optional record of every leaf's position, in build order */
+    int32_t *leaf_j;       /* and the doubling it belongs to */
 } nuts_ctx;
 
 static nuts_pt pt_new(int64_t D)
@@ -601,6 +606,14 @@ static void nuts_build(nuts_ctx *c, nuts_pt *edge, int v, int depth, nuts_pt *ca
         double H = -edge->logp + kinetic(edge->r, D);
         *n_out = (c->log_u <= -H) ? 1 : 0;
         *s_out = (c->log_u < 1000.0 - H) ? 1 : 0;     /* NaN H fails both */
+        /* Algorithm 6's per-leaf acceptance probability (NaN H counts 0) */
+        double dh0 = c->H0 - H;
+        c->alpha += isnan(dh0) ? 0.0 : (dh0 >= 0.0 ? 1.0 : exp(dh0));
+        c->n_alpha += 1;
+        if (c->leaf_x) {
+            memcpy(c->leaf_x + (int64_t)(c->n_leapfrog - 1) * D, edge->x, sizeof(double) * (size_t)D);
+            c->leaf_j[c->n_leapfrog - 1] = c->doubling;
+        }
         pt_copy(cand, edge, D);
         if (first)
             pt_copy(first, edge, D);
@@ -635,10 +648,10 @@ static void nuts_build(nuts_ctx *c, nuts_pt *edge, int v, int depth, nuts_pt *ca
 
 int orc_nuts_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uint32_t t, double eps,
                         int32_t max_depth, double *x, double *logp, double *g, int32_t *depth,
-                        int32_t *n_leapfrog)
+                        int32_t *n_leapfrog, double *accept_stat, double *leaf_x, int32_t *leaf_j)
 {
     const int64_t D = tg->dim;
-    nuts_ctx c = {tg, seed, chain, t, 0, 0, 0, eps, 0.0, D};
+    nuts_ctx c = {tg, seed, chain, t, 0, 0, 0, eps, 0.0, D, 0.0, 0.0, 0, leaf_x, leaf_j};
     nuts_pt minus = pt_new(D), plus = pt_new(D), cand = pt_new(D), chosen = pt_new(D);
     memcpy(minus.x, x, sizeof(double) * (size_t)D);
     memcpy(minus.g, g, sizeof(double) * (size_t)D);
@@ -647,12 +660,15 @@ int orc_nuts_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uin
     pt_copy(&plus, &minus, D);
     pt_copy(&chosen, &minus, D);
     const double H0 = -(*logp) + kinetic(minus.r, D);
+    c.H0 = H0;
     c.log_u = log(uniform52_block(seed, chain, t, 0, ORC_TAG_NUTS_SLICE)) - H0;
     int32_t n = 1, s = 1, j = 0, moved = 0;
     while (s && j < max_depth) {
         const int v = uniform52_block(seed, chain, t, (uint32_t)j, ORC_TAG_NUTS_DIR) < 0.5 ? -1 : 1;
         c.doubling = j;
         c.leaves = 0;
+        c.alpha = 0.0;             /* the statistic is the last doubling's */
+        c.n_alpha = 0;
         int32_t n1, s1;
         nuts_build(&c, v > 0 ? &plus : &minus, v, j, &cand, NULL, &n1, &s1);
         if (s1 && uniform52_block(seed, chain, t, (uint32_t)j, ORC_TAG_NUTS_TOP) < (double)n1 / (double)n) {
@@ -668,6 +684,7 @@ int orc_nuts_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uin
     *logp = chosen.logp;
     if (depth) *depth = j;
     if (n_leapfrog) *n_leapfrog = c.n_leapfrog;
+    if (accept_stat) *accept_stat = c.n_alpha > 0 ? c.alpha / (double)c.n_alpha : 0.0;
     pt_free(&minus);
     pt_free(&plus);
     pt_free(&cand);
@@ -676,8 +693,10 @@ int orc_nuts_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uin
 }
 
 int orc_nuts_sample_chain(const orc_target *tg, int64_t C, uint64_t seed, uint32_t t_begin, double *x,
-                          const double *eps, int32_t max_depth, int64_t num_burnin, int64_t num_results,
-                          double *samples, int32_t *tr_depth, int32_t *tr_nleap, int32_t nthreads)
+                          double *eps, int32_t max_depth, int64_t num_burnin, int64_t num_results,
+                          int32_t adapt, double target_accept, double gamma, double t0, double kappa,
+                          double rate, double *samples, int32_t *tr_depth, int32_t *tr_nleap, double *tr_stat,
+                          int32_t nthreads)
 {
     const int64_t D = tg->dim;
     set_threads(nthreads);
@@ -686,16 +705,30 @@ int orc_nuts_sample_chain(const orc_target *tg, int64_t C, uint64_t seed, uint32
         double *xc = x + c * D;
         double *gc = (double *)malloc(sizeof(double) * (size_t)D);
         double lp = orc_logp_grad(tg, xc, gc);
+        orc_dual_avg da;
+        orc_dual_avg_init(&da, eps[c]);
         for (int64_t i = 0; i < num_burnin + num_results; ++i) {
             int32_t dep, nl;
+            double stat;
             orc_nuts_transition(tg, seed, (uint32_t)c, t_begin + (uint32_t)i, eps[c], max_depth, xc, &lp, gc,
-                                &dep, &nl);
+                                &dep, &nl, &stat, NULL, NULL);
+            /* Algorithm 6: the step size of the next transition from the
+             * statistic of this one, during burn-in only */
+            if (adapt && i < num_burnin) {
+                if (adapt == ORC_ADAPT_SIMPLE) {
+                    eps[c] = orc_simple_adapt(eps[c], stat, target_accept, rate);
+                } else {
+                    orc_dual_avg_update(&da, i + 1, stat, target_accept, gamma, t0, kappa);
+                    eps[c] = (i + 1 < num_burnin) ? exp(da.log_eps) : exp(da.log_eps_bar);
+                }
+            }
             if (i >= num_burnin) {
                 int64_t r = i - num_burnin;
                 if (samples)
                     memcpy(samples + (r * C + c) * D, xc, sizeof(double) * (size_t)D);
                 if (tr_depth) tr_depth[r * C + c] = dep;
                 if (tr_nleap) tr_nleap[r * C + c] = nl;
+                if (tr_stat) tr_stat[r * C + c] = stat;
             }
         }
         free(gc);

@@ -197,18 +197,29 @@ int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L
  * (chain, t, j, tag 5)) when s' = 1, then stops when s' = 0, the whole
  * trajectory makes a U-turn, or j reaches max_depth.  (x, logp, g) become the
  * chosen state's; *depth receives the number of doublings, *n_leapfrog the
- * leapfrog steps taken.  Returns 1 if the state moved. */
+ * leapfrog steps taken, *accept_stat the step-size adaptation statistic of
+ * Hoffman & Gelman's Algorithm 6: the mean of min(1, exp(H0 - H)) over the
+ * leaves built in the last doubling (0 when none was built).  leaf_x
+ * [(2^max_depth - 1) * D] and leaf_j [2^max_depth - 1], when not NULL,
+ * receive every leaf's position and doubling in build order (a check of the
+ * statistic against closed forms).  Returns 1 if the state moved. */
 enum { ORC_TAG_NUTS_MERGE = 3, ORC_TAG_NUTS_DIR = 4, ORC_TAG_NUTS_TOP = 5, ORC_TAG_NUTS_SLICE = 6 };
 int orc_nuts_transition(const orc_target *tg, uint64_t seed, uint32_t chain, uint32_t t, double eps,
                         int32_t max_depth, double *x, double *logp, double *g, int32_t *depth,
-                        int32_t *n_leapfrog);
+                        int32_t *n_leapfrog, double *accept_stat, double *leaf_x, int32_t *leaf_j);
 
-/* NUTS sample_chain with a fixed step size per chain (eps [C]): transitions
- * t_begin .. t_begin + burnin + results - 1; samples [R*C*D], depth and
- * n_leapfrog traces [R*C] (each may be NULL).  x holds the final state. */
+/* NUTS sample_chain (eps [C] in: initial step sizes; out: final ones):
+ * transitions t_begin .. t_begin + burnin + results - 1; samples [R*C*D],
+ * depth, n_leapfrog and accept-statistic traces [R*C] (each may be NULL).
+ * adapt (0 none, ORC_ADAPT_DUAL_AVERAGING, ORC_ADAPT_SIMPLE): during burn-in
+ * each transition's statistic updates the chain's step size as in
+ * orc_sample_chain (Hoffman & Gelman Algorithm 6 for dual averaging).
+ * x holds the final state. */
 int orc_nuts_sample_chain(const orc_target *tg, int64_t C, uint64_t seed, uint32_t t_begin, double *x,
-                          const double *eps, int32_t max_depth, int64_t num_burnin, int64_t num_results,
-                          double *samples, int32_t *tr_depth, int32_t *tr_nleap, int32_t nthreads);
+                          double *eps, int32_t max_depth, int64_t num_burnin, int64_t num_results,
+                          int32_t adapt, double target_accept, double gamma, double t0, double kappa,
+                          double rate, double *samples, int32_t *tr_depth, int32_t *tr_nleap, double *tr_stat,
+                          int32_t nthreads);
 
 #ifdef __cplusplus
 }

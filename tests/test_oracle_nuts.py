@@ -91,3 +91,76 @@ def test_stationary_moments(case):
     # 100000 draws, NUTS draws nearly independent: 4-sigma bounds
     assert np.all(np.abs(s.mean(0)) < 4 * np.sqrt(np.diag(cov) / 1e4))
     assert np.allclose(np.cov(s.T).reshape(D, D), cov, atol=0.04 * np.max(np.diag(cov)))
+
+
+# ------------------------------------------------- step-size adaptation --
+# Hoffman & Gelman (2014) Algorithm 6: the statistic that drives the step size
+# is the mean of min(1, exp(H0 - H)) over the leaves of the last doubling.
+# On N(0, I) leapfrog conserves r.r/2 + (1 - eps^2/4) x.x/2 exactly, so a
+# leaf's energy error is (eps^2 / 8)(|x|^2 - |x0|^2): the statistic follows
+# from the leaves' positions alone, without the oracle's energy code.
+
+@pytest.mark.parametrize("eps", [0.3, 0.9, 1.6])
+def test_accept_stat_is_the_last_doublings_mean_in_closed_form(eps):
+    D = 3
+    tg = Target(oracle.STD_NORMAL, D)
+    rng = np.random.default_rng(11)
+    checked = 0
+    for t in range(40):
+        x0 = rng.normal(size=D) * 1.5
+        r = oracle.nuts_transition(tg, 9, t % 5, t, eps, 6, x0, record_leaves=True)
+        assert r["leaf_x"].shape == (r["n_leapfrog"], D)
+        if r["n_leapfrog"] == 0:
+            continue
+        last = r["leaf_j"] == r["depth"] - 1
+        assert last.any() and np.all(np.diff(r["leaf_j"]) >= 0)
+        dh = eps * eps / 8.0 * (np.sum(r["leaf_x"][last] ** 2, axis=1) - np.sum(x0 ** 2))
+        expect = np.mean(np.minimum(1.0, np.exp(-dh)))
+        assert abs(r["accept_stat"] - expect) <= 1e-10 * max(1.0, expect), (t, r["accept_stat"], expect)
+        # the whole trajectory's mean differs whenever there is more than one doubling
+        checked += 1
+    assert checked >= 30
+
+
+def test_accept_stat_edge_values_and_simple_adaptation_closed_forms():
+    # flat target (zero precision): H is constant along the trajectory, statistic exactly 1,
+    # so the multiplicative rule grows the step by exactly (1 + rate) per burn-in transition
+    flat = Target(oracle.GAUSS_DIAG, 2, prec=np.zeros(2))
+    B, rate, eps0 = 12, 0.03, 0.2
+    o = oracle.nuts_sample_chain(flat, 4, np.zeros((3, 2)), eps0, B, 2, max_depth=3, adapt="simple", rate=rate)
+    assert np.all(o["accept_stat"] == 1.0)
+    expect = eps0
+    for _ in range(B):
+        expect = expect * (1 + rate)
+    assert np.all(o["final_eps"] == expect)
+    # NaN state: the first leaf diverges with statistic 0; the step shrinks by exactly 1 / (1 + rate)
+    tg = Target(oracle.STD_NORMAL, 2)
+    x0 = np.full((3, 2), np.nan)
+    o = oracle.nuts_sample_chain(tg, 4, x0, eps0, B, 2, max_depth=5, adapt="simple", rate=rate)
+    assert np.all(o["accept_stat"] == 0.0) and np.all(o["n_leapfrog"] == 1)
+    expect = eps0
+    for _ in range(B):
+        expect = expect / (1 + rate)
+    assert np.all(o["final_eps"] == expect)
+
+
+def test_dual_averaging_brings_the_statistic_to_the_target():
+    tg = Target(oracle.STD_NORMAL, 20)
+    x0 = np.random.default_rng(3).normal(size=(32, 20))
+    means = {}
+    for delta in (0.65, 0.9):
+        o = oracle.nuts_sample_chain(tg, 21, x0, 1.0, 300, 200, max_depth=8, adapt=True, target_accept=delta)
+        means[delta] = o["accept_stat"].mean()
+        assert abs(means[delta] - delta) < 0.06, (delta, means[delta])
+        assert np.all(np.isfinite(o["final_eps"])) and np.all(o["final_eps"] > 0)
+        # after burn-in the step size is frozen at the averaged iterate
+        assert np.ptp(o["final_eps"]) > 0
+    assert means[0.9] > means[0.65]
+
+
+def test_fixed_step_run_is_unchanged_by_the_statistic():
+    tg = Target(oracle.STD_NORMAL, 4)
+    x0 = np.random.default_rng(5).normal(size=(6, 4))
+    a = oracle.nuts_sample_chain(tg, 2, x0, 0.5, 10, 20, max_depth=6)
+    assert np.all(a["final_eps"] == 0.5)
+    assert np.all((a["accept_stat"] >= 0) & (a["accept_stat"] <= 1))
