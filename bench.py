@@ -327,42 +327,56 @@ def bench_nuts(args):
     eps0 = torch.full((w.num_chains,), w.step_size, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
+    # With adaptation the burn-in (whose step sizes start far from the adapted
+    # one) and the sampling phase run as two calls, the second timed on its
+    # own: its leapfrog steps are all counted.  Without, one call; the kept
+    # transitions' mean trajectory length stands for the burn-in's as well.
     def run(ev=None):
         s.set_state(x0, eps0, 0)
-        if ev is not None:
-            ev[0].record(stream)
-        out = s.nuts_sample_chain(w.num_results, w.num_burnin, max_depth=args.nuts)
+        if args.nuts_adapt:
+            if ev is not None:
+                ev[0].record(stream)
+            s.nuts_sample_chain(0, w.num_burnin, max_depth=args.nuts, adapt=True, store_samples=False)
         if ev is not None:
             ev[1].record(stream)
+        out = s.nuts_sample_chain(w.num_results, 0 if args.nuts_adapt else w.num_burnin, max_depth=args.nuts)
+        if ev is not None:
+            ev[2].record(stream)
         return out
 
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
     t0 = time.perf_counter()
     out = None
     for k in range(args.steps):
         out = run(evs[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    kernel_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    burnin_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) if args.nuts_adapt else None
     nleap = to_host(out["n_leapfrog"]).astype(np.float64)
     depth = to_host(out["tree_depth"])
-    # leapfrog steps of the kept transitions, scaled to the whole run by its length
-    steps_run = nleap.mean() * w.num_chains * (w.num_burnin + w.num_results)
+    if args.nuts_adapt:
+        steps_run = nleap.sum()                      # every transition of the timed call is kept
+        rate = steps_run / (kernel_ms * 1e-3)
+    else:
+        steps_run = nleap.mean() * w.num_chains * (w.num_burnin + w.num_results)
+        rate = steps_run * args.steps / elapsed
     bound, per_cs, unit = algorithmic_work(w)
     achieved = per_cs * steps_run / (kernel_ms * 1e-3)
     peak = PEAK["hbm"] if bound == "hbm" else (PEAK["bf16_mfma"] if args.grad == "bf16" else PEAK["fp32_mfma"])
     scale = 1e9 if bound == "hbm" else 1e12
     result = {
-        "metric": METRIC, "value": steps_run * args.steps / elapsed, "unit": "leapfrog chain-steps/s",
+        "metric": METRIC, "value": rate, "unit": "leapfrog chain-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if w.state_dtype == "f64" else ("bf16/f32" if args.grad == "bf16" else "f32"),
         "data": "synthetic (seeded; shapes of the paper's workloads)",
         "config": {"workload": f"nuts_{w.name}", "num_chains": w.num_chains, "dim": w.dim, "n_rows": w.n_rows,
-                   "max_tree_depth": args.nuts, "step_size": w.step_size, "num_burnin": w.num_burnin,
+                   "max_tree_depth": args.nuts, "step_size": w.step_size,
+                   "adapt": "dual_averaging (Algorithm 6)" if args.nuts_adapt else "none", "num_burnin": w.num_burnin,
                    "num_results": w.num_results,
                    "form": "persistent (unrolled tree in registers)" if persistent else "plain (unrolled tree, lockstep)",
                    "parallelism": "chains (1 GPU)"},
@@ -372,7 +386,12 @@ def bench_nuts(args):
                      "kernel_ms_per_launch": kernel_ms,
                      "work_per_launch": per_cs * steps_run},
         "nuts": {"mean_leapfrog_per_transition": float(nleap.mean()), "max_leapfrog": int(nleap.max()),
-                 "depth_histogram": np.bincount(depth.ravel()).tolist()},
+                 "depth_histogram": np.bincount(depth.ravel()).tolist(),
+                 "mean_accept_stat": float(to_host(out["accept_stat"]).mean()),
+                 "final_step_size_median": float(np.median(to_host(s.get_state()[1]))),
+                 "value_counts": "sampling call only, every leapfrog step counted" if args.nuts_adapt
+                 else "whole run, burn-in steps estimated from the kept transitions",
+                 "burnin_ms": burnin_ms, "sampling_ms": kernel_ms},
     }
     if not args.no_diagnostics:
         summ = dg.t_summarize(out["samples"])
@@ -461,6 +480,8 @@ def main():
                     help="streaming expectations: moments through a ring instead of stored samples")
     ap.add_argument("--ring-rows", type=int, default=64, help="--moments: kept states per fold")
     ap.add_argument("--nuts", type=int, default=0, help="No-U-Turn sampler with this max tree depth (1..10)")
+    ap.add_argument("--nuts-adapt", action="store_true",
+                    help="--nuts: dual-averaging step-size adaptation (target 0.8) during burn-in")
     ap.add_argument("--remc", type=int, default=0,
                     help="replica exchange with this many replicas (divides the workload's chains)")
     ap.add_argument("--remc-beta-min", type=float, default=0.1, help="smallest inverse temperature of the ladder")

@@ -268,8 +268,13 @@ hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale);
  * HMC (tag 0), slice (block 0, tag 6), direction of doubling j (block j,
  * tag 4), take of doubling j's subtree (block j, tag 5), merge of the level-k
  * subtree ending at leaf i of doubling j (block (1024 j + i) 16 + k, tag 3).
- * The step size is each chain's current step size (fixed; no adaptation).
- * On a context of the fused form with an element-wise target (N(0, I),
+ * The step size is each chain's current step size.  With an hmc_adapt, each
+ * burn-in transition then updates it from the statistic of Hoffman & Gelman
+ * (2014) Algorithm 6 -- the mean of min(1, exp(H0 - H)) over the leaves built
+ * in the transition's last doubling (0 with max_depth 0) -- by dual averaging
+ * (as in hmc_sample_chain: iteration m = burn-in transition m of this call;
+ * the last burn-in transition sets the averaged iterate) or by the
+ * multiplicative rule.  On a context of the fused form with an element-wise target (N(0, I),
  * diagonal Gaussian; D <= 256 in FP64, <= 512 in FP32) one persistent kernel
  * runs every transition with each chain's tree in its lanes' registers;
  * otherwise the chains run in lockstep on the plain kernels of the target and
@@ -282,14 +287,17 @@ hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale);
  * aligned base).  max_depth in 0..10. */
 hmc_status hmc_nuts_workspace_size(const hmc_ctx* ctx, int32_t max_depth, size_t* bytes);
 
-/* burn-in + R NUTS transitions from the context's state; samples [R, C, D]
+/* burn-in + R NUTS transitions from the context's state; adapt (host, may be
+ * NULL: fixed step sizes) as for hmc_sample_chain; samples [R, C, D]
  * (device, state dtype), tree_depth and n_leapfrog [R, C] (device int32: the
- * doublings and leapfrog steps of each kept transition) may be NULL.  t
- * advances by burn-in + R.  The lockstep path synchronizes the stream after
- * every doubling; the persistent one is asynchronous. */
+ * doublings and leapfrog steps of each kept transition) and accept_stat
+ * [R, C] (device FP64: Algorithm 6's statistic of each kept transition) may
+ * be NULL.  t advances by burn-in + R; the step sizes stay where adaptation
+ * left them.  The lockstep path synchronizes the stream after every
+ * doubling; the persistent one is asynchronous. */
 hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int64_t num_results, int64_t num_burnin_steps,
-                                 void* nuts_workspace, size_t nuts_workspace_bytes, void* samples,
-                                 int32_t* tree_depth, int32_t* n_leapfrog);
+                                 const hmc_adapt* adapt, void* nuts_workspace, size_t nuts_workspace_bytes,
+                                 void* samples, int32_t* tree_depth, int32_t* n_leapfrog, double* accept_stat);
 
 /* ---------------------------------------------------------------------------
  * Streaming expectations: the driver the paper plans (Sec. 4.2) for runs

@@ -833,10 +833,11 @@ extern "C" hmc_status hmc_nuts_workspace_size(const hmc_ctx* ctx, int32_t max_de
 }
 
 extern "C" hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int64_t num_results,
-                                            int64_t num_burnin_steps, void* nuts_workspace,
+                                            int64_t num_burnin_steps, const hmc_adapt* adapt, void* nuts_workspace,
                                             size_t nuts_workspace_bytes, void* samples, int32_t* tree_depth,
-                                            int32_t* n_leapfrog) {
+                                            int32_t* n_leapfrog, double* accept_stat) {
     if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (hmc_status st = check_adapt(adapt)) return st;
     if (max_depth < 0 || max_depth > 10) return fail(HMC_E_INVALID, "max_depth must be in 0..10");
     if (num_results < 0 || num_burnin_steps < 0) return fail(HMC_E_INVALID, "negative transition count");
     if (ctx->a.ws.beta || ctx->a.ws.scale)
@@ -847,17 +848,23 @@ extern "C" hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int
     if (nuts_workspace_bytes < need) return fail(HMC_E_NOMEM, "NUTS workspace smaller than hmc_nuts_workspace_size");
     const int64_t total = num_results + num_burnin_steps;
     if (ctx->t + (uint64_t)total > 0xffffffffull) return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
+    NutsAdapt ad{};
+    set_adapt(ad, adapt);
+    ad.n_burnin = num_burnin_steps;
+    hmc_status st = HMC_OK;
+    if (ad.adapt && ad.adapt_kind == HMC_ADAPT_DUAL_AVERAGING)
+        st = check_hip(launch_da_init(ctx->a, ctx->stream), "adaptation init");
+    if (st != HMC_OK) return st;
     if (ctx->form == HMC_FORM_FUSED && nuts_fused_supported(ctx->a)) {
         // element-wise targets: one persistent launch for all transitions
-        hmc_status st = check_hip(launch_nuts_fused(ctx->a, nw, (uint32_t)ctx->t, total, num_burnin_steps, max_depth,
-                                                    samples, tree_depth, n_leapfrog, ctx->stream),
-                                  "nuts persistent");
+        st = check_hip(launch_nuts_fused(ctx->a, nw, ad, (uint32_t)ctx->t, total, max_depth, samples, tree_depth,
+                                         n_leapfrog, accept_stat, ctx->stream),
+                       "nuts persistent");
         if (st == HMC_OK) ctx->t += (uint64_t)total;
         return st;
     }
     PlainArgs leap = ctx->a;
     leap.ws.eps = nw.seps;             // signed step v eps of each chain's current doubling
-    hmc_status st = HMC_OK;
     for (int64_t it = 0; it < total && st == HMC_OK; ++it) {
         const uint32_t t = (uint32_t)(ctx->t + (uint64_t)it);
         st = check_hip(launch_nuts_begin(ctx->a, nw, t, ctx->stream), "nuts begin");
@@ -876,10 +883,10 @@ extern "C" hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int
             if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "nuts count");
             if (st != HMC_OK || running == 0) break;
         }
-        const bool kept = it >= num_burnin_steps;
+        const int64_t r = it >= num_burnin_steps ? it - num_burnin_steps : -1;   // kept draw, or -1
         if (st == HMC_OK)
-            st = check_hip(launch_nuts_end(ctx->a, nw, kept ? samples : nullptr, kept ? it - num_burnin_steps : 0,
-                                           kept ? tree_depth : nullptr, kept ? n_leapfrog : nullptr, ctx->stream),
+            st = check_hip(launch_nuts_end(ctx->a, nw, ad, it, samples, r, tree_depth, n_leapfrog, accept_stat,
+                                           ctx->stream),
                            "nuts end");
     }
     if (st == HMC_OK) ctx->t += (uint64_t)total;

@@ -98,22 +98,35 @@ struct NutsWs {
     void *rc_x, *rc_g;         // [C, D] candidate of the finished doubling
     double *mlogp, *plogp, *wlogp, *lc_logp, *rc_logp;   // [C], [C], [C], [MD, C], [C]
     double *log_u, *seps, *ntot;                         // [C] slice, signed step, points in the tree
+    double *h0, *alpha;        // [C] starting energy; sum of min(1, e^(H0 - H)) over the doubling's leaves
+    int32_t *n_alpha;          // [C] and their number
     int32_t *lc_n;             // [MD, C]
     int32_t *active, *alive, *rc_n, *depth, *nleap, *moved, *dir;   // [C]
     int32_t *n_active;         // [1]
     size_t bytes;
 };
 NutsWs carve_nuts(void* base, int64_t C, int64_t D, int32_t max_depth, size_t es, size_t* total);
+// Step-size adaptation of a NUTS run (the fields set_adapt fills), during the
+// first n_burnin transitions.
+struct NutsAdapt {
+    int32_t adapt;
+    int32_t adapt_kind;
+    double target_accept, gamma, t0, kappa, rate;
+    int64_t n_burnin;
+};
 hipError_t launch_nuts_begin(const PlainArgs& a, const NutsWs& n, uint32_t t, hipStream_t s);
 hipError_t launch_nuts_dir(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, hipStream_t s);
 hipError_t launch_nuts_halfkick(const PlainArgs& a, const NutsWs& n, hipStream_t s);
 hipError_t launch_nuts_leaf(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, int32_t i, hipStream_t s);
 hipError_t launch_nuts_doubling_end(const PlainArgs& a, const NutsWs& n, uint32_t t, int32_t j, hipStream_t s);
 bool nuts_fused_supported(const PlainArgs& a);
-hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, uint32_t t_begin, int64_t n_trans, int64_t n_burnin,
-                             int32_t max_depth, void* samples, int32_t* tr_depth, int32_t* tr_nleap, hipStream_t s);
-hipError_t launch_nuts_end(const PlainArgs& a, const NutsWs& n, void* samples, int64_t r, int32_t* tr_depth,
-                           int32_t* tr_nleap, hipStream_t s);
+hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, const NutsAdapt& ad, uint32_t t_begin,
+                             int64_t n_trans, int32_t max_depth, void* samples, int32_t* tr_depth, int32_t* tr_nleap,
+                             double* tr_stat, hipStream_t s);
+// end of transition it: adaptation from the statistic, then (kept draw r, or
+// r < 0) the sample and trace rows
+hipError_t launch_nuts_end(const PlainArgs& a, const NutsWs& n, const NutsAdapt& ad, int64_t it, void* samples,
+                           int64_t r, int32_t* tr_depth, int32_t* tr_nleap, double* tr_stat, hipStream_t s);
 // Streaming moments: fold q kept states (ring rows 0..q-1 = draws r0..r0+q-1
 // of R) into the per-half Welford accumulators and the batch sums.
 hipError_t launch_moments(const PlainArgs& a, const void* ring, int64_t q, int64_t r0, int64_t R,

@@ -14,6 +14,11 @@
 // whose merged subtree makes a U-turn stops for the rest of the transition
 // (masked), as the recursion would.
 //
+// Step-size adaptation (Hoffman & Gelman 2014, Algorithm 6): each leaf adds
+// min(1, exp(H0 - H)) to its chain's sum for the current doubling; at the end
+// of the transition the mean over the last doubling's leaves is the statistic
+// of dual averaging or of the multiplicative rule, during burn-in only.
+//
 // Random numbers (Philox4x32-10, counter (chain, t, block, tag)): momentum as
 // HMC (tag 0), slice u (block 0, tag 6), direction of doubling j (block j,
 // tag 4), take of doubling j's subtree (block j, tag 5), merge of level k at
@@ -29,6 +34,23 @@ __device__ __forceinline__ double nuts_u52(Key key, uint32_t chain, uint32_t t, 
     const uint4 w = philox(chain, t, block, tag, key);
     const double k = (double)(w.x >> 6) * 67108864.0 + (double)(w.y >> 6);
     return (k + 0.5) * 0x1p-52;
+}
+
+// a leaf's min(1, exp(H0 - H)), 0 for NaN
+__device__ __forceinline__ double leaf_accept_prob(double dh0) {
+    return isnan(dh0) ? 0.0 : (dh0 >= 0.0 ? 1.0 : exp(dh0));
+}
+
+// Adaptation after transition it from its statistic; returns the new step
+// size (eps unchanged outside burn-in or without adaptation).  Out of line:
+// inlined, its FP64 pow / exp / sqrt raised the persistent kernel's register
+// pressure in the tree loop into spills.
+__device__ __attribute__((noinline)) double nuts_adapt(const NutsAdapt& ad, int64_t it, double stat, double eps,
+                                                       DualAvg& da) {
+    if (!ad.adapt || it >= ad.n_burnin) return eps;
+    if (ad.adapt_kind == HMC_ADAPT_SIMPLE) return simple_adapt(eps, stat, ad.target_accept, ad.rate);
+    const double log_eps = dual_avg_update(da, (double)(it + 1), stat, ad.target_accept, ad.gamma, ad.t0, ad.kappa);
+    return (it + 1 < ad.n_burnin) ? exp(log_eps) : exp(da.log_eps_bar);
 }
 
 static size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
@@ -53,6 +75,8 @@ NutsWs carve_nuts(void* base, int64_t C, int64_t D, int32_t max_depth, size_t es
     n.rc_logp = (double*)take((size_t)C * 8);
     n.log_u = (double*)take((size_t)C * 8); n.seps = (double*)take((size_t)C * 8);
     n.ntot = (double*)take((size_t)C * 8);
+    n.h0 = (double*)take((size_t)C * 8); n.alpha = (double*)take((size_t)C * 8);
+    n.n_alpha = (int32_t*)take((size_t)C * 4);
     n.lc_n = (int32_t*)take(md * C * 4);
     n.active = (int32_t*)take((size_t)C * 4); n.alive = (int32_t*)take((size_t)C * 4);
     n.rc_n = (int32_t*)take((size_t)C * 4); n.depth = (int32_t*)take((size_t)C * 4);
@@ -98,8 +122,11 @@ __global__ __launch_bounds__(256) void k_nuts_begin(PlainArgs a, NutsWs n, uint3
     if (lane == 0) {
         const double lp = a.ws.logp[c];
         n.mlogp[c] = n.plogp[c] = lp;
+        n.h0[c] = -lp + k0;
         n.log_u[c] = log(nuts_u52(a.key, (uint32_t)c, t, 0u, TAG_NUTS_SLICE)) - (-lp + k0);
         n.ntot[c] = 1.0;
+        n.alpha[c] = 0.0;
+        n.n_alpha[c] = 0;
         n.active[c] = 1;
         n.depth[c] = 0;
         n.nleap[c] = 0;
@@ -125,6 +152,10 @@ __global__ __launch_bounds__(256) void k_nuts_dir(PlainArgs a, NutsWs n, uint32_
         gq[i] = sg[i];
     }
     if (lane == 0) {
+        if (act) {                              // the statistic is the last doubling's
+            n.alpha[c] = 0.0;
+            n.n_alpha[c] = 0;
+        }
         n.dir[c] = v;
         n.seps[c] = act ? (double)v * a.ws.eps[c] : 0.0;
         n.alive[c] = act ? 1 : 0;
@@ -149,13 +180,20 @@ __global__ __launch_bounds__(256) void k_nuts_leaf(PlainArgs a, NutsWs n, uint32
     if (!n.alive[c]) return;
     const T *xq = (const T*)a.ws.xq, *pq = (const T*)a.ws.pq, *gq = (const T*)a.ws.gq;
     const bool logreg = a.tg.kind == HMC_TGT_LOGREG;
+    // summed in the order k_nuts_begin sums the starting kinetic energy (lane
+    // by lane over 4-dim blocks), so that H - H0 is exactly 0 where the energy
+    // is exactly conserved
     double lp = 0.0, kin = 0.0;
-    for (int64_t d = lane; d < D; d += 64) {
-        const int64_t e = c * D + d;
-        const double xv = (double)xq[e], pv = (double)pq[e];
-        kin += 0.5 * pv * pv;
-        lp += logreg ? -0.5 * xv * xv * a.tg.inv_var : 0.5 * xv * (double)gq[e];
-    }
+    for (int64_t b = lane; b < (D + 3) / 4; b += 64)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t d = 4 * b + q;
+            if (d >= D) break;
+            const int64_t e = c * D + d;
+            const double xv = (double)xq[e], pv = (double)pq[e];
+            kin += 0.5 * pv * pv;
+            lp += logreg ? -0.5 * xv * xv * a.tg.inv_var : 0.5 * xv * (double)gq[e];
+        }
     lp = group_sum<64>(lp);
     kin = group_sum<64>(kin);
     if (logreg) lp += a.ws.lpq[c];
@@ -165,6 +203,8 @@ __global__ __launch_bounds__(256) void k_nuts_leaf(PlainArgs a, NutsWs n, uint32
     if (lane == 0) {
         n.nleap[c] += 1;
         n.wlogp[c] = lp;
+        n.alpha[c] += leaf_accept_prob(n.h0[c] - H);
+        n.n_alpha[c] += 1;
     }
     if (!s_leaf) {
         if (lane == 0) n.alive[c] = 0;
@@ -291,16 +331,26 @@ __global__ __launch_bounds__(256) void k_nuts_doubling_end(PlainArgs a, NutsWs n
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_nuts_end(PlainArgs a, NutsWs n, T* samples, int64_t r, int32_t* tr_depth,
-                                                  int32_t* tr_nleap) {
+__global__ __launch_bounds__(256) void k_nuts_end(PlainArgs a, NutsWs n, NutsAdapt ad, int64_t it, T* samples,
+                                                  int64_t r, int32_t* tr_depth, int32_t* tr_nleap, double* tr_stat) {
     NUTS_CHAIN
-    if (samples) {
+    if (r >= 0 && samples) {
         const T* x = (const T*)a.ws.x;
         for (int64_t d = lane; d < D; d += 64) samples[(r * a.C + c) * D + d] = x[c * D + d];
     }
     if (lane == 0) {
-        if (tr_depth) tr_depth[r * a.C + c] = n.depth[c];
-        if (tr_nleap) tr_nleap[r * a.C + c] = n.nleap[c];
+        const int32_t na = n.n_alpha[c];
+        const double stat = na > 0 ? n.alpha[c] / (double)na : 0.0;
+        if (ad.adapt && it < ad.n_burnin) {
+            DualAvg da = a.ws.da[c];
+            a.ws.eps[c] = nuts_adapt(ad, it, stat, a.ws.eps[c], da);
+            a.ws.da[c] = da;
+        }
+        if (r >= 0) {
+            if (tr_depth) tr_depth[r * a.C + c] = n.depth[c];
+            if (tr_nleap) tr_nleap[r * a.C + c] = n.nleap[c];
+            if (tr_stat) tr_stat[r * a.C + c] = stat;
+        }
     }
 }
 
@@ -316,10 +366,13 @@ __global__ __launch_bounds__(256) void k_nuts_end(PlainArgs a, NutsWs n, T* samp
 // ---------------------------------------------------------------------------
 constexpr int NUTS_MAXD = 10;
 
-template <typename T, int G, int NB>
-__global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, uint32_t t_begin, int64_t n_trans,
-                                                         int64_t n_burnin, int32_t max_depth, T* samples,
-                                                         int32_t* tr_depth, int32_t* tr_nleap) {
+// ST: the run adapts the step size or traces the statistic (a template
+// parameter, so that plain runs carry none of it).
+template <typename T, int G, int NB, bool ST>
+__global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, NutsAdapt ad, uint32_t t_begin,
+                                                         int64_t n_trans, int32_t max_depth, T* samples,
+                                                         int32_t* tr_depth, int32_t* tr_nleap, double* tr_stat) {
+    const int64_t n_burnin = ad.n_burnin;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % G;
     const int64_t c = gid / G;
@@ -346,7 +399,9 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
         }
     auto dim_of = [&](int b, int e) -> int64_t { return 4 * (lane + (int64_t)G * b) + e; };
     double logp = a.ws.logp[cc];
-    const double eps = a.ws.eps[cc];
+    double eps = a.ws.eps[cc];
+    DualAvg da{};
+    if (ST) da = a.ws.da[cc];
 
     for (int64_t it = 0; it < n_trans; ++it) {
         const uint32_t t = t_begin + (uint32_t)it;
@@ -366,8 +421,11 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
             }
         }
         k0 = group_sum<G>(k0);
+        const double h0 = -logp + k0;
         const double log_u = log(nuts_u52(a.key, (uint32_t)cc, t, 0u, TAG_NUTS_SLICE)) - (-logp + k0);
         double mlogp = logp, plogp = logp, ntot = 1.0;
+        double alpha = 0.0;                     // the last doubling's acceptance-probability sum
+        int32_t n_alpha = 0;
         int32_t depth = 0, nleap = 0;
         bool s = active;                        // lanes past the last chain build no tree
         for (int j = 0; j < max_depth && s; ++j) {
@@ -384,6 +442,8 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                 }
             double wlogp = v > 0 ? plogp : mlogp;
             bool alive = true, complete = false;
+            alpha = 0.0;
+            n_alpha = 0;
             int32_t lcn[NUTS_MAXD];
             double lclp[NUTS_MAXD];
             T rcx[NB][4], rcg[NB][4];
@@ -408,6 +468,10 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                 wlogp = lp;
                 nleap += 1;
                 const double H = -lp + kin;
+                if (ST) {
+                    alpha += leaf_accept_prob(h0 - H);
+                    n_alpha += 1;
+                }
                 int32_t n_node = (log_u <= -H) ? 1 : 0;
                 if (!(log_u < 1000.0 - H)) {
                     alive = false;
@@ -529,6 +593,8 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                 s = dm >= 0.0 && dp >= 0.0;
             }
         }
+        const double stat = n_alpha > 0 ? alpha / (double)n_alpha : 0.0;
+        if (ST && ad.adapt && it < n_burnin) eps = nuts_adapt(ad, it, stat, eps, da);
         if (active && it >= n_burnin) {
             const int64_t r = it - n_burnin;
             if (samples)
@@ -540,6 +606,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
             if (lane == 0) {
                 if (tr_depth) tr_depth[r * C + c] = depth;
                 if (tr_nleap) tr_nleap[r * C + c] = nleap;
+                if (ST && tr_stat) tr_stat[r * C + c] = stat;
             }
         }
     }
@@ -554,7 +621,13 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                 Xw[c * D + dim_of(b, e)] = x[b][e];
                 Gw[c * D + dim_of(b, e)] = g[b][e];
             }
-    if (lane == 0) a.ws.logp[c] = logp;
+    if (lane == 0) {
+        a.ws.logp[c] = logp;
+        if (ST) {
+            a.ws.eps[c] = eps;
+            a.ws.da[c] = da;
+        }
+    }
 }
 
 // lanes per chain and 4-dim blocks per lane of the persistent kernel, 0 if it
@@ -575,15 +648,23 @@ bool nuts_fused_supported(const PlainArgs& a) {
     return nuts_elem_shape(a, &G) > 0;
 }
 
-hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, uint32_t t_begin, int64_t n_trans, int64_t n_burnin,
-                             int32_t max_depth, void* samples, int32_t* tr_depth, int32_t* tr_nleap, hipStream_t s) {
+hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, const NutsAdapt& ad, uint32_t t_begin,
+                             int64_t n_trans, int32_t max_depth, void* samples, int32_t* tr_depth, int32_t* tr_nleap,
+                             double* tr_stat, hipStream_t s) {
     int G = 0;
     const int NB = nuts_elem_shape(a, &G);
     if (NB == 0) return hipErrorNotSupported;
     const dim3 grid((unsigned)((a.C * G + 255) / 256));
-#define HMC_NUTS_F(TT, GG, NN)                                                                                      \
-    hipLaunchKernelGGL((k_nuts_fused_elem<TT, GG, NN>), grid, dim3(256), 0, s, a, n, t_begin, n_trans, n_burnin, \
-                       max_depth, (TT*)samples, tr_depth, tr_nleap)
+    const bool st = ad.adapt || tr_stat;
+#define HMC_NUTS_F(TT, GG, NN)                                                                                       \
+    do {                                                                                                             \
+        if (st)                                                                                                      \
+            hipLaunchKernelGGL((k_nuts_fused_elem<TT, GG, NN, true>), grid, dim3(256), 0, s, a, n, ad, t_begin,      \
+                               n_trans, max_depth, (TT*)samples, tr_depth, tr_nleap, tr_stat);                       \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_nuts_fused_elem<TT, GG, NN, false>), grid, dim3(256), 0, s, a, n, ad, t_begin,     \
+                               n_trans, max_depth, (TT*)samples, tr_depth, tr_nleap, tr_stat);                       \
+    } while (0)
     if (a.f64) {
         if (G == 1) HMC_NUTS_F(double, 1, 1);
         else if (G == 4) HMC_NUTS_F(double, 4, 1);
@@ -639,14 +720,14 @@ hipError_t launch_nuts_doubling_end(const PlainArgs& a, const NutsWs& n, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_nuts_end(const PlainArgs& a, const NutsWs& n, void* samples, int64_t r, int32_t* tr_depth,
-                           int32_t* tr_nleap, hipStream_t s) {
+hipError_t launch_nuts_end(const PlainArgs& a, const NutsWs& n, const NutsAdapt& ad, int64_t it, void* samples,
+                           int64_t r, int32_t* tr_depth, int32_t* tr_nleap, double* tr_stat, hipStream_t s) {
     if (a.f64)
-        hipLaunchKernelGGL(k_nuts_end<double>, nuts_grid(a.C), dim3(256), 0, s, a, n, (double*)samples, r, tr_depth,
-                           tr_nleap);
+        hipLaunchKernelGGL(k_nuts_end<double>, nuts_grid(a.C), dim3(256), 0, s, a, n, ad, it, (double*)samples, r,
+                           tr_depth, tr_nleap, tr_stat);
     else
-        hipLaunchKernelGGL(k_nuts_end<float>, nuts_grid(a.C), dim3(256), 0, s, a, n, (float*)samples, r, tr_depth,
-                           tr_nleap);
+        hipLaunchKernelGGL(k_nuts_end<float>, nuts_grid(a.C), dim3(256), 0, s, a, n, ad, it, (float*)samples, r,
+                           tr_depth, tr_nleap, tr_stat);
     return hipGetLastError();
 }
 

@@ -140,8 +140,8 @@ def lib():
     L.hmc_sample_chain_moments.restype = st
     L.hmc_nuts_workspace_size.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
     L.hmc_nuts_workspace_size.restype = st
-    L.hmc_nuts_sample_chain.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_size_t,
-                                        vp, vp, vp]
+    L.hmc_nuts_sample_chain.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.POINTER(hmc_adapt), vp, ctypes.c_size_t, vp, vp, vp, vp]
     L.hmc_nuts_sample_chain.restype = st
     L.hmc_set_transform_scale.argtypes = [vp, vp]
     L.hmc_set_transform_scale.restype = st
@@ -403,9 +403,12 @@ class Sampler:
         outs.update(mean=mean, m2=m2, batch_sum=bsum, ring=ring)
         return outs
 
-    def nuts_sample_chain(self, num_results, num_burnin_steps, max_depth=10, store_samples=True):
-        """No-U-Turn sampler from the current state with each chain's step size.
-        Returns dict(samples [R, C, D] or None, tree_depth [R, C], n_leapfrog [R, C])."""
+    def nuts_sample_chain(self, num_results, num_burnin_steps, max_depth=10, store_samples=True, adapt=False,
+                          target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75, rate=0.01):
+        """No-U-Turn sampler from the current state with each chain's step size,
+        adapted during burn-in when adapt is set (as sample_chain's).  Returns
+        dict(samples [R, C, D] or None, tree_depth [R, C], n_leapfrog [R, C],
+        accept_stat [R, C])."""
         torch = self.torch
         C, D, R = self.C, self.D, num_results
         nb = ctypes.c_size_t(0)
@@ -414,9 +417,11 @@ class Sampler:
         samples = torch.empty(R, C, D, dtype=self.dtype, device=self.device) if store_samples else None
         depth = torch.empty(R, C, dtype=torch.int32, device=self.device)
         nleap = torch.empty(R, C, dtype=torch.int32, device=self.device)
-        _check(lib().hmc_nuts_sample_chain(self.ctx, max_depth, R, num_burnin_steps, _ptr(ws), nb.value,
-                                           _ptr(samples), _ptr(depth), _ptr(nleap)))
-        return dict(samples=samples, tree_depth=depth, n_leapfrog=nleap)
+        stat = torch.empty(R, C, dtype=torch.float64, device=self.device)
+        ad = make_adapt(adapt, target_accept, gamma, t0, kappa, rate)
+        _check(lib().hmc_nuts_sample_chain(self.ctx, max_depth, R, num_burnin_steps, ctypes.byref(ad) if ad else None,
+                                           _ptr(ws), nb.value, _ptr(samples), _ptr(depth), _ptr(nleap), _ptr(stat)))
+        return dict(samples=samples, tree_depth=depth, n_leapfrog=nleap, accept_stat=stat)
 
     def set_transform_scale(self, scale):
         """Diagonal affine bijector x = shift + scale * z (the shift does not enter

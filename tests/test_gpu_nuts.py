@@ -7,6 +7,13 @@ to 1e-12, tree depths and leapfrog counts exactly); FP32 targets, one
 transition from given states: >= 99% of chains take the same tree (depth,
 leapfrog count, moved) and those chains' states agree to 1e-5 relative; the
 FP32 chain samples N(0, 1) with the right variance.
+
+Step-size adaptation inside NUTS (Hoffman & Gelman Algorithm 6): on FP64
+element-wise targets adapted runs match the oracle's (states and statistics
+to 1e-12, step sizes to 1e-12 relative, trees exactly); where the statistic is
+exact (a flat target: 1; NaN states: 0) the multiplicative rule's step sizes
+equal the oracle's bit for bit; FP32 targets adapt to the oracle's step-size
+scale and statistic.
 """
 import numpy as np
 import pytest
@@ -110,3 +117,88 @@ def test_persistent_and_lockstep_build_the_same_trees():
         s.close()
     same = (out[0]["tree_depth"] == out[1]["tree_depth"]) & (out[0]["n_leapfrog"] == out[1]["n_leapfrog"])
     assert same.float().mean().item() >= 0.99
+
+
+# ------------------------------------------------- step-size adaptation --
+@pytest.mark.parametrize("adapt", ["dual_averaging", "simple"])
+@pytest.mark.parametrize("form", ["lockstep", "persistent"])
+def test_fp64_adapted_runs_match_oracle(adapt, form):
+    w = W.gauss_diag(dim=5, num_chains=48, step_size=0.3, state_dtype="f64", lam_lo=0.3, lam_hi=3.0)
+    s = hmc.sampler_for(w, form=FORMS[form])
+    g = s.nuts_sample_chain(30, 40, max_depth=6, adapt=adapt, rate=0.05)
+    _, eps, _ = s.get_state()
+    s.close()
+    o = oracle.nuts_sample_chain(oracle_target(w), w.seed, w.x0.astype(np.float64), w.step_size, 40, 30,
+                                 max_depth=6, adapt=adapt, rate=0.05)
+    assert np.ptp(o["final_eps"]) > 0 and not np.allclose(o["final_eps"], w.step_size)
+    same_tree = (to_np(g["tree_depth"]) == o["depth"]) & (to_np(g["n_leapfrog"]) == o["n_leapfrog"])
+    if adapt == "simple":
+        # products of exact factors: the runs agree to rounding
+        assert same_tree.all()
+        assert np.max(np.abs(to_np(g["samples"]) - o["samples"])) <= 1e-12
+        assert np.max(np.abs(to_np(g["accept_stat"]) - o["accept_stat"])) <= 1e-12
+        assert np.allclose(to_np(eps), o["final_eps"], rtol=1e-12, atol=0)
+    else:
+        # dual averaging multiplies the statistic's last-ulp differences (exp, FMA contraction) by
+        # sqrt(m) / gamma ~ 100 per burn-in transition and NUTS trajectories amplify them further:
+        # trees agree, and nearly every chain stays within 1e-6 of the oracle's
+        assert same_tree.mean() >= 0.99
+        close = np.max(np.abs(to_np(g["samples"]) - o["samples"]), axis=(0, 2)) <= 1e-6
+        assert close.mean() >= 0.95, close.mean()
+        eps_close = np.abs(to_np(eps) / o["final_eps"] - 1) <= 1e-8
+        assert eps_close.mean() >= 0.95, eps_close.mean()
+
+
+@pytest.mark.parametrize("form", ["lockstep", "persistent"])
+def test_exact_statistics_give_exact_step_sizes(form):
+    B, rate, eps0 = 20, 0.03, 0.2
+    # flat target: every leaf keeps H0, statistic 1, step grows by (1 + rate) per burn-in transition
+    w = W.gauss_diag(dim=5, num_chains=32, step_size=eps0, lam_lo=1.0, lam_hi=1.0)
+    w.prec = np.zeros(5, dtype=np.float32)
+    s = hmc.sampler_for(w, form=FORMS[form])
+    g = s.nuts_sample_chain(3, B, max_depth=4, adapt="simple", rate=rate)
+    _, eps, _ = s.get_state()
+    s.close()
+    o = oracle.nuts_sample_chain(oracle_target(w), w.seed, w.x0.astype(np.float64), eps0, B, 3, max_depth=4,
+                                 adapt="simple", rate=rate)
+    assert np.all(to_np(g["accept_stat"]) == 1.0)
+    assert np.array_equal(to_np(eps), o["final_eps"])
+    # NaN states: the first leaf diverges with statistic 0, the step shrinks by 1 / (1 + rate)
+    w = W.std_normal_1d(num_chains=40, dim=7, state_dtype="f32", step_size=eps0)
+    x0 = w.x0.copy()
+    x0[::3, 0] = np.nan
+    s = hmc.sampler_for(w, form=FORMS[form], x0=x0)
+    g = s.nuts_sample_chain(2, B, max_depth=5, adapt="simple", rate=rate)
+    _, eps, _ = s.get_state()
+    s.close()
+    o = oracle.nuts_sample_chain(oracle_target(w), w.seed, x0.astype(np.float64), eps0, B, 2, max_depth=5,
+                                 adapt="simple", rate=rate)
+    rows = np.arange(40)[::3]
+    assert np.all(to_np(g["accept_stat"])[:, rows] == 0.0)
+    assert np.array_equal(to_np(eps)[rows], o["final_eps"][rows])
+
+
+@pytest.mark.parametrize("name", ["gauss_dense_37", "logreg_77x3", "std_normal_7d"])
+def test_fp32_adaptation_follows_the_oracle(name):
+    w = _fp32_cases()[name]
+    form = "persistent" if name == "std_normal_7d" else "lockstep"
+    s = hmc.sampler_for(w, form=FORMS[form])
+    g = s.nuts_sample_chain(60, 80, max_depth=8, adapt=True)
+    _, eps, _ = s.get_state()
+    s.close()
+    o = oracle.nuts_sample_chain(oracle_target(w), w.seed, w.x0.astype(np.float64), w.step_size, 80, 60,
+                                 max_depth=8, adapt=True)
+    ratio = np.median(to_np(eps)) / np.median(o["final_eps"])
+    assert abs(ratio - 1) < 0.1, ratio
+    assert abs(to_np(g["accept_stat"]).mean() - o["accept_stat"].mean()) < 0.05
+    assert abs(o["accept_stat"].mean() - 0.8) < 0.1
+
+
+def test_nuts_adaptation_errors():
+    w = W.std_normal_1d(num_chains=8)
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
+    with pytest.raises(hmc.HMCError, match="rate"):
+        s.nuts_sample_chain(1, 1, adapt="simple", rate=0.0)
+    with pytest.raises(hmc.HMCError, match="target_accept"):
+        s.nuts_sample_chain(1, 1, adapt=True, target_accept=1.0)
+    s.close()
