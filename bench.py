@@ -320,9 +320,12 @@ def bench_nuts(args):
     form = {"auto": hmc.HMC_FORM_AUTO, "plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_PLAIN,
             "fused": hmc.HMC_FORM_FUSED}[args.form]
     s = hmc.sampler_for(w, form=form, grad_bf16=args.grad == "bf16")
-    # the persistent NUTS kernel covers element-wise targets up to 64 (FP64) or 128 (FP32) 4-dim blocks per chain
-    persistent = (hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED and w.kind in (W.STD_NORMAL, W.GAUSS_DIAG)
-                  and (w.dim + 3) // 4 <= (64 if w.state_dtype == "f64" else 128))
+    # the persistent NUTS kernels cover element-wise targets up to 64 (FP64) or 128 (FP32) 4-dim blocks per
+    # chain and the dense Gaussian up to D = 128 (FP32)
+    fused = hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED
+    persistent = fused and ((w.kind in (W.STD_NORMAL, W.GAUSS_DIAG)
+                             and (w.dim + 3) // 4 <= (64 if w.state_dtype == "f64" else 128))
+                            or (w.kind == W.GAUSS_DENSE and w.state_dtype == "f32" and w.dim <= 128))
     x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).cuda()
     eps0 = torch.full((w.num_chains,), w.step_size, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()

@@ -27,6 +27,8 @@
 
 namespace hmc {
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 enum : uint32_t { TAG_NUTS_MERGE = 3, TAG_NUTS_DIR = 4, TAG_NUTS_TOP = 5, TAG_NUTS_SLICE = 6 };
 
 // (k + 1/2) 2^-52 uniform of block (chain, t, block, tag), as the accept uniform
@@ -630,6 +632,378 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent NUTS for the dense Gaussian on MFMA (FP32, D <= 128).  A
+// workgroup of 4 waves owns 16 chains in the layout of the fused dense HMC
+// kernel: P as the A operands of v_mfma_f32_16x16x4f32 in VGPRs, x staged
+// chain-major in LDS as the B operands, lane (g4, i16) of wave w holding dims
+// 16 (w + 4 m) + 4 g4 + v of chain i16.  The 16 chains build their trees in
+// lockstep -- the same doubling and leaf at a time, a chain that has stopped
+// masked -- and the tile moves on as soon as none of them is running, so a
+// chain waits for the 15 others of its tile only, and there is one launch for
+// the whole run.  A chain's sums over its dims (energies, U-turn products)
+// are reduced across its 16 lane positions by shuffles and one LDS exchange;
+// every reduction and vote sits where the control flow is uniform across the
+// workgroup (their count depends on the leaf index only).  The trajectory
+// ends, the levels' parked first leaves and candidates and the doubling's
+// candidate live in the NutsWs buffers, each lane touching only its own dims.
+// Same tree, uniforms and arithmetic order per lane as the lockstep kernels
+// up to the order of the FP64 sums.
+// ---------------------------------------------------------------------------
+constexpr int ND_NW = 4;
+
+template <int NT, bool ST>
+__global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n, NutsAdapt ad, uint32_t t_begin,
+                                                          int64_t n_trans, int32_t max_depth, float* samples,
+                                                          int32_t* tr_depth, int32_t* tr_nleap, double* tr_stat) {
+    constexpr int MT = (NT + ND_NW - 1) / ND_NW;
+    constexpr int KM = 4 * NT;
+    constexpr int XS = 16 * NT + 4;
+    extern __shared__ float lds[];
+    const int64_t C = a.C, D = a.tg.D;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i16 = lane & 15, g4 = lane >> 4;
+    const int64_t c = (int64_t)blockIdx.x * 16 + i16;
+    const bool cvalid = c < C;
+    const int64_t cc = cvalid ? c : 0;
+    float* xs0 = lds;
+    float* xs1 = lds + 16 * XS;
+    double* red = (double*)(lds + 2 * 16 * XS);          // [2 parity][2 values][NW][16]
+    int* vote = (int*)(red + 2 * 2 * ND_NW * 16);        // [2 parity][16]
+    const float* P = (const float*)a.tg.prec;
+    float *mx = (float*)n.mx, *mr = (float*)n.mr, *mg = (float*)n.mg;
+    float *px = (float*)n.px, *pr = (float*)n.pr, *pg = (float*)n.pg;
+    float *lfx = (float*)n.lf_x, *lfr = (float*)n.lf_r, *lcx = (float*)n.lc_x, *lcg = (float*)n.lc_g;
+    float *rcx = (float*)n.rc_x, *rcg = (float*)n.rc_g;
+
+    float pa[MT][KM];
+    bool tile_ok[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int mt = w + ND_NW * m;
+        tile_ok[m] = mt < NT;
+        const int64_t row = 16 * mt + i16;
+#pragma unroll
+        for (int ks = 0; ks < KM; ++ks) {
+            const int64_t col = (int64_t)g4 * KM + ks;
+            pa[m][ks] = (tile_ok[m] && row < D && col < D) ? P[row * D + col] : 0.f;
+        }
+    }
+    auto dim_of = [&](int m, int v) -> int64_t { return 16 * (w + ND_NW * m) + 4 * g4 + v; };
+    float x[MT][4], g[MT][4];
+    bool ok[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            ok[m][v] = tile_ok[m] && cvalid && dim_of(m, v) < D;
+            x[m][v] = ok[m][v] ? ((const float*)a.ws.x)[cc * D + dim_of(m, v)] : 0.f;
+            g[m][v] = ok[m][v] ? ((const float*)a.ws.g)[cc * D + dim_of(m, v)] : 0.f;
+        }
+    double logp = a.ws.logp[cc];
+    double eps = a.ws.eps[cc];
+    DualAvg da{};
+    if (ST) da = a.ws.da[cc];
+    int buf = 0, rk = 0, vk = 0;
+
+    // sums over each chain's dims, returned to every lane of the chain
+    auto chain_sum2 = [&](double& s0, double& s1) {
+        s0 += __shfl_xor(s0, 16, 64);
+        s0 += __shfl_xor(s0, 32, 64);
+        s1 += __shfl_xor(s1, 16, 64);
+        s1 += __shfl_xor(s1, 32, 64);
+        double* rb = red + (rk & 1) * (2 * ND_NW * 16);
+        if (g4 == 0) {
+            rb[(2 * w) * 16 + i16] = s0;
+            rb[(2 * w + 1) * 16 + i16] = s1;
+        }
+        __syncthreads();
+        s0 = 0.0;
+        s1 = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < ND_NW; ++ww) {
+            s0 += rb[(2 * ww) * 16 + i16];
+            s1 += rb[(2 * ww + 1) * 16 + i16];
+        }
+        ++rk;
+    };
+    // does any chain of the tile satisfy pred (one value per chain)
+    auto tile_any = [&](bool pred) -> bool {
+        int* vb = vote + (vk & 1) * 16;
+        if (w == 0 && g4 == 0) vb[i16] = pred ? 1 : 0;
+        __syncthreads();
+        int any = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) any |= vb[q];
+        ++vk;
+        return any != 0;
+    };
+
+    for (int64_t it = 0; it < n_trans; ++it) {
+        const uint32_t t = t_begin + (uint32_t)it;
+        double k0 = 0.0, unused = 0.0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            float z[4];
+            momentum4<float>(a.key, (uint32_t)cc, t, (uint32_t)(4 * (w + ND_NW * m) + g4), z);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float r0 = ok[m][v] ? z[v] : 0.f;
+                k0 += 0.5 * (double)r0 * (double)r0;
+                if (ok[m][v]) {
+                    const int64_t e = c * D + dim_of(m, v);
+                    mx[e] = px[e] = x[m][v];
+                    mr[e] = pr[e] = r0;
+                    mg[e] = pg[e] = g[m][v];
+                }
+            }
+        }
+        chain_sum2(k0, unused);
+        const double h0 = -logp + k0;
+        const double log_u = log(nuts_u52(a.key, (uint32_t)cc, t, 0u, TAG_NUTS_SLICE)) - h0;
+        double mlogp = logp, plogp = logp, ntot = 1.0;
+        bool active = cvalid;
+        int32_t depth = 0, nleap = 0;
+        double alpha = 0.0;
+        int32_t n_alpha = 0;
+        for (int j = 0; j < max_depth; ++j) {
+            if (!tile_any(active)) break;
+            const int dir = (active && nuts_u52(a.key, (uint32_t)cc, t, (uint32_t)j, TAG_NUTS_DIR) < 0.5) ? -1 : 1;
+            const float se = (float)((double)dir * eps), hse = (float)(0.5 * ((double)dir * eps));
+            float wx[MT][4], wr[MT][4], wg[MT][4];
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t e = cc * D + dim_of(m, v);
+                    wx[m][v] = ok[m][v] ? (dir > 0 ? px[e] : mx[e]) : 0.f;
+                    wr[m][v] = ok[m][v] ? (dir > 0 ? pr[e] : mr[e]) : 0.f;
+                    wg[m][v] = ok[m][v] ? (dir > 0 ? pg[e] : mg[e]) : 0.f;
+                }
+            double wlogp = dir > 0 ? plogp : mlogp;
+            bool alive = active, complete = false;
+            if (ST && active) {
+                alpha = 0.0;
+                n_alpha = 0;
+            }
+            int32_t lcn[NUTS_MAXD];
+            double lclp[NUTS_MAXD];
+            double rclp = 0.0;
+            int32_t rcn = 0;
+            const int nleaves = 1 << j;
+            for (int i = 0; i < nleaves; ++i) {
+                if (!tile_any(alive)) break;
+                // one leapfrog step of size dir eps for every chain of the tile
+                float* xs = buf ? xs1 : xs0;
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        wr[m][v] = wr[m][v] + hse * wg[m][v];
+                        wx[m][v] = fmaf(se, wr[m][v], wx[m][v]);
+                    }
+                    if (tile_ok[m])
+                        *(floatx4*)(xs + i16 * XS + 16 * (w + ND_NW * m) + 4 * g4) =
+                            floatx4{wx[m][0], wx[m][1], wx[m][2], wx[m][3]};
+                }
+                __syncthreads();
+                floatx4 bq[NT];
+#pragma unroll
+                for (int q = 0; q < NT; ++q) bq[q] = *(const floatx4*)(xs + i16 * XS + g4 * KM + 4 * q);
+                floatx4 acc[MT][2];
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    acc[m][0] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    acc[m][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+                for (int ks = 0; ks < KM; ++ks) {
+                    const float bv = bq[ks >> 2][ks & 3];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[m][ks], bv, acc[m][ks & 1], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x100, NT, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, KM * MT, 0);
+                double lp = 0.0, kin = 0.0;
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        wg[m][v] = -(acc[m][0][v] + acc[m][1][v]);
+                        wr[m][v] = fmaf(hse, wg[m][v], wr[m][v]);
+                        if (ok[m][v]) {
+                            kin += 0.5 * (double)wr[m][v] * (double)wr[m][v];
+                            lp += 0.5 * (double)wx[m][v] * (double)wg[m][v];
+                        }
+                    }
+                buf ^= 1;
+                chain_sum2(lp, kin);
+                int32_t n_node = 0;
+                if (alive) {
+                    wlogp = lp;
+                    nleap += 1;
+                    const double H = -lp + kin;
+                    if (ST) {
+                        alpha += leaf_accept_prob(h0 - H);
+                        n_alpha += 1;
+                    }
+                    n_node = (log_u <= -H) ? 1 : 0;
+                    if (!(log_u < 1000.0 - H)) alive = false;
+                }
+                // the subtrees that end at leaf i: merge levels k with bit k-1 of i
+                // set, park at the first unset bit (the same k for every chain)
+                int cand = -1, first = -1;
+                double cand_lp = lp;
+                bool parked = false;
+#pragma unroll
+                for (int k = 1; k <= NUTS_MAXD; ++k) {
+                    if (k > j) break;
+                    const int64_t rk0 = ((int64_t)k * C + cc) * D;
+                    if (((i >> (k - 1)) & 1) == 0) {
+                        if (alive) {
+                            const int64_t rf = ((int64_t)(first < 0 ? 0 : first) * C + cc) * D;
+                            const int64_t rc = ((int64_t)(cand < 0 ? 0 : cand) * C + cc) * D;
+#pragma unroll
+                            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v)
+                                    if (ok[m][v]) {
+                                        const int64_t d = dim_of(m, v);
+                                        lfx[rk0 + d] = first < 0 ? wx[m][v] : lfx[rf + d];
+                                        lfr[rk0 + d] = first < 0 ? wr[m][v] : lfr[rf + d];
+                                        lcx[rk0 + d] = cand < 0 ? wx[m][v] : lcx[rc + d];
+                                        lcg[rk0 + d] = cand < 0 ? wg[m][v] : lcg[rc + d];
+                                    }
+                            lcn[k - 1] = n_node;
+                            lclp[k - 1] = cand_lp;
+                        }
+                        parked = true;
+                        break;
+                    }
+                    double dm = 0.0, dp = 0.0;
+                    if (alive) {
+                        const int32_t nl = lcn[k - 1];
+                        const uint32_t block = ((uint32_t)j * 1024u + (uint32_t)i) * 16u + (uint32_t)k;
+                        const double u = nuts_u52(a.key, (uint32_t)cc, t, block, TAG_NUTS_MERGE);
+                        if (!((nl + n_node > 0) && u < (double)n_node / (double)(nl + n_node))) {
+                            cand = k;
+                            cand_lp = lclp[k - 1];
+                        }
+                        n_node += nl;
+#pragma unroll
+                        for (int m = 0; m < MT; ++m)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                if (ok[m][v]) {
+                                    const int64_t d = dim_of(m, v);
+                                    const double fx = (double)lfx[rk0 + d], fr = (double)lfr[rk0 + d];
+                                    const double lx = (double)wx[m][v], lr = (double)wr[m][v];
+                                    const double dx = dir > 0 ? lx - fx : fx - lx;
+                                    dm += dx * (dir > 0 ? fr : lr);
+                                    dp += dx * (dir > 0 ? lr : fr);
+                                }
+                    }
+                    chain_sum2(dm, dp);
+                    first = k;
+                    if (alive && !(dm >= 0.0 && dp >= 0.0)) alive = false;
+                }
+                if (!parked && alive) {     // the last leaf: every subtree of doubling j ends here
+                    const int64_t rc = ((int64_t)(cand < 0 ? 0 : cand) * C + cc) * D;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (ok[m][v]) {
+                                const int64_t d = dim_of(m, v);
+                                rcx[cc * D + d] = cand < 0 ? wx[m][v] : lcx[rc + d];
+                                rcg[cc * D + d] = cand < 0 ? wg[m][v] : lcg[rc + d];
+                            }
+                    rclp = cand_lp;
+                    rcn = n_node;
+                    complete = true;
+                }
+            }
+            // the working state becomes the trajectory end in direction dir
+            if (active) {
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (ok[m][v]) {
+                            const int64_t e = cc * D + dim_of(m, v);
+                            (dir > 0 ? px : mx)[e] = wx[m][v];
+                            (dir > 0 ? pr : mr)[e] = wr[m][v];
+                            (dir > 0 ? pg : mg)[e] = wg[m][v];
+                        }
+                if (dir > 0) plogp = wlogp;
+                else mlogp = wlogp;
+                depth = j + 1;
+            }
+            const bool grown = active && alive && complete;
+            double dm = 0.0, dp = 0.0;
+            if (grown) {
+                if (nuts_u52(a.key, (uint32_t)cc, t, (uint32_t)j, TAG_NUTS_TOP) < (double)rcn / ntot) {
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (ok[m][v]) {
+                                x[m][v] = rcx[cc * D + dim_of(m, v)];
+                                g[m][v] = rcg[cc * D + dim_of(m, v)];
+                            }
+                    logp = rclp;
+                }
+                ntot += (double)rcn;
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (ok[m][v]) {
+                            const int64_t e = cc * D + dim_of(m, v);
+                            const double dx = (double)px[e] - (double)mx[e];
+                            dm += dx * (double)mr[e];
+                            dp += dx * (double)pr[e];
+                        }
+            }
+            chain_sum2(dm, dp);
+            active = grown && dm >= 0.0 && dp >= 0.0;
+        }
+        const double stat = n_alpha > 0 ? alpha / (double)n_alpha : 0.0;
+        if (ST && ad.adapt && it < ad.n_burnin) eps = nuts_adapt(ad, it, stat, eps, da);
+        if (cvalid && it >= ad.n_burnin) {
+            const int64_t r = it - ad.n_burnin;
+            if (samples)
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (ok[m][v]) samples[(r * C + c) * D + dim_of(m, v)] = x[m][v];
+            if (w == 0 && g4 == 0) {
+                if (tr_depth) tr_depth[r * C + c] = depth;
+                if (tr_nleap) tr_nleap[r * C + c] = nleap;
+                if (ST && tr_stat) tr_stat[r * C + c] = stat;
+            }
+        }
+    }
+    if (!cvalid) return;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (ok[m][v]) {
+                ((float*)a.ws.x)[c * D + dim_of(m, v)] = x[m][v];
+                ((float*)a.ws.g)[c * D + dim_of(m, v)] = g[m][v];
+            }
+    if (w == 0 && g4 == 0) {
+        a.ws.logp[c] = logp;
+        if (ST) {
+            a.ws.eps[c] = eps;
+            a.ws.da[c] = da;
+        }
+    }
+}
+
 // lanes per chain and 4-dim blocks per lane of the persistent kernel, 0 if it
 // does not apply (registers: FP64 keeps one block per lane, FP32 two)
 static int nuts_elem_shape(const PlainArgs& a, int* G) {
@@ -643,14 +1017,47 @@ static int nuts_elem_shape(const PlainArgs& a, int* G) {
     return 0;
 }
 
+// the persistent dense kernel: FP32 states, D <= 128 (P resident in VGPRs)
+static bool nuts_dense_supported(const PlainArgs& a) {
+    return a.tg.kind == HMC_TGT_GAUSS_DENSE && !a.f64 && a.tg.D >= 1 && a.tg.D <= 128;
+}
+
 bool nuts_fused_supported(const PlainArgs& a) {
     int G;
-    return nuts_elem_shape(a, &G) > 0;
+    return nuts_elem_shape(a, &G) > 0 || nuts_dense_supported(a);
+}
+
+static hipError_t launch_nuts_dense(const PlainArgs& a, const NutsWs& n, const NutsAdapt& ad, uint32_t t_begin,
+                                    int64_t n_trans, int32_t max_depth, void* samples, int32_t* tr_depth,
+                                    int32_t* tr_nleap, double* tr_stat, hipStream_t s) {
+    const int nt = (int)((a.tg.D + 15) / 16);
+    const size_t lds = (size_t)2 * 16 * (16 * nt + 4) * sizeof(float) + (size_t)2 * 2 * ND_NW * 16 * sizeof(double) +
+                       2 * 16 * sizeof(int);
+    const dim3 grid((unsigned)((a.C + 15) / 16));
+    const bool st = ad.adapt || tr_stat;
+    switch (nt) {
+#define HMC_NUTS_D(N)                                                                                              \
+    case N:                                                                                                        \
+        if (st)                                                                                                    \
+            hipLaunchKernelGGL((k_nuts_fused_dense<N, true>), grid, dim3(256), lds, s, a, n, ad, t_begin, n_trans, \
+                               max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);                           \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_nuts_fused_dense<N, false>), grid, dim3(256), lds, s, a, n, ad, t_begin, n_trans,\
+                               max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);                           \
+        break;
+        HMC_NUTS_D(1) HMC_NUTS_D(2) HMC_NUTS_D(3) HMC_NUTS_D(4)
+        HMC_NUTS_D(5) HMC_NUTS_D(6) HMC_NUTS_D(7) HMC_NUTS_D(8)
+#undef HMC_NUTS_D
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, const NutsAdapt& ad, uint32_t t_begin,
                              int64_t n_trans, int32_t max_depth, void* samples, int32_t* tr_depth, int32_t* tr_nleap,
                              double* tr_stat, hipStream_t s) {
+    if (nuts_dense_supported(a))
+        return launch_nuts_dense(a, n, ad, t_begin, n_trans, max_depth, samples, tr_depth, tr_nleap, tr_stat, s);
     int G = 0;
     const int NB = nuts_elem_shape(a, &G);
     if (NB == 0) return hipErrorNotSupported;

@@ -8,6 +8,10 @@ transition from given states: >= 99% of chains take the same tree (depth,
 leapfrog count, moved) and those chains' states agree to 1e-5 relative; the
 FP32 chain samples N(0, 1) with the right variance.
 
+The persistent kernels (element-wise targets; the dense Gaussian on MFMA,
+16 chains per workgroup) build the lockstep path's trees (>= 99%), including a
+ragged tile and the largest dense shape.
+
 Step-size adaptation inside NUTS (Hoffman & Gelman Algorithm 6): on FP64
 element-wise targets adapted runs match the oracle's (states and statistics
 to 1e-12, step sizes to 1e-12 relative, trees exactly); where the statistic is
@@ -108,15 +112,29 @@ def test_nuts_errors():
     s.close()
 
 
-def test_persistent_and_lockstep_build_the_same_trees():
-    w = W.gauss_diag(dim=300, num_chains=70, step_size=0.05)      # 64 lanes x 2 blocks per chain, FP32
+def _persistent_cases():
+    return {
+        "diag_300": W.gauss_diag(dim=300, num_chains=70, step_size=0.05),     # 64 lanes x 2 blocks per chain
+        "dense_100": W.gauss_dense(dim=100, num_chains=80, step_size=0.1, seed=2),
+        "dense_ragged_17x17": W.gauss_dense(dim=17, num_chains=17, step_size=0.2, seed=4),
+        "dense_max_128": W.gauss_dense(dim=128, num_chains=33, step_size=0.05, seed=6),
+    }
+
+
+@pytest.mark.parametrize("name", list(_persistent_cases()))
+def test_persistent_and_lockstep_build_the_same_trees(name):
+    w = _persistent_cases()[name]
     out = []
-    for form in (hmc.HMC_FORM_PLAIN, hmc.HMC_FORM_AUTO):
+    for form in (hmc.HMC_FORM_PLAIN, hmc.HMC_FORM_FUSED):
         s = hmc.sampler_for(w, form=form)
-        out.append(s.nuts_sample_chain(6, 2, max_depth=7))
+        out.append(s.nuts_sample_chain(6, 2, max_depth=7, adapt=True))
+        out[-1]["eps"] = s.get_state()[1]
         s.close()
     same = (out[0]["tree_depth"] == out[1]["tree_depth"]) & (out[0]["n_leapfrog"] == out[1]["n_leapfrog"])
     assert same.float().mean().item() >= 0.99
+    assert out[1]["tree_depth"].min().item() >= 1
+    rel = ((out[0]["eps"] - out[1]["eps"]).abs() / out[0]["eps"]).cpu().numpy()
+    assert np.mean(rel <= 1e-6) >= 0.95
 
 
 # ------------------------------------------------- step-size adaptation --
@@ -178,10 +196,10 @@ def test_exact_statistics_give_exact_step_sizes(form):
     assert np.array_equal(to_np(eps)[rows], o["final_eps"][rows])
 
 
-@pytest.mark.parametrize("name", ["gauss_dense_37", "logreg_77x3", "std_normal_7d"])
-def test_fp32_adaptation_follows_the_oracle(name):
+@pytest.mark.parametrize("name,form", [("gauss_dense_37", "lockstep"), ("gauss_dense_37", "persistent"),
+                                       ("logreg_77x3", "lockstep"), ("std_normal_7d", "persistent")])
+def test_fp32_adaptation_follows_the_oracle(name, form):
     w = _fp32_cases()[name]
-    form = "persistent" if name == "std_normal_7d" else "lockstep"
     s = hmc.sampler_for(w, form=FORMS[form])
     g = s.nuts_sample_chain(60, 80, max_depth=8, adapt=True)
     _, eps, _ = s.get_state()
