@@ -646,11 +646,55 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
 // every reduction and vote sits where the control flow is uniform across the
 // workgroup (their count depends on the leaf index only).  The trajectory
 // ends, the levels' parked first leaves and candidates and the doubling's
-// candidate live in the NutsWs buffers, each lane touching only its own dims.
+// candidate live in the NutsWs buffers, each lane touching only its own dims,
+// except the parked records of the shallow levels 1 .. ND_LV (the merges of
+// all but 1 / 2^ND_LV of the leaves), which sit in LDS: with one wave per
+// SIMD a global read there is latency nothing hides.
 // Same tree, uniforms and arithmetic order per lane as the lockstep kernels
 // up to the order of the FP64 sums.
 // ---------------------------------------------------------------------------
 constexpr int ND_NW = 4;
+constexpr int ND_LDS_MAX = 163840;          // LDS bytes of a gfx950 workgroup
+constexpr int ND_RV = 2;                    // values per chain in one reduction
+
+template <int NT>
+constexpr int nd_xs() { return 16 * NT + 4; }
+// LDS bytes before the level records: x staging, reductions, votes
+template <int NT>
+constexpr int nd_fixed_bytes() { return 2 * 16 * nd_xs<NT>() * 4 + 2 * ND_RV * ND_NW * 16 * 8 + 2 * 16 * 4; }
+// levels whose records (first leaf x, r; candidate x, g of 16 chains) fit in LDS
+template <int NT>
+constexpr int nd_lds_levels() {
+    constexpr int lv = (ND_LDS_MAX - nd_fixed_bytes<NT>()) / (4 * 16 * nd_xs<NT>() * 4);
+    return lv > NUTS_MAXD - 1 ? NUTS_MAXD - 1 : lv;
+}
+template <int NT>
+constexpr int nd_lds_bytes() { return nd_fixed_bytes<NT>() + nd_lds_levels<NT>() * 4 * 16 * nd_xs<NT>() * 4; }
+
+// Sums over each chain's dims of NV values, returned to every lane of the
+// chain: two shuffles over the chain's 4 lane rows, then the 4 waves' partials
+// through LDS (parity rk alternates the buffer, so one barrier suffices).
+template <int NV>
+__device__ __forceinline__ void nd_chain_sum(double* sv, double* red, int& rk, int w, int g4, int i16) {
+    double* rb = red + (rk & 1) * (ND_RV * ND_NW * 16);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        sv[q] += __shfl_xor(sv[q], 16, 64);
+        sv[q] += __shfl_xor(sv[q], 32, 64);
+    }
+    if (g4 == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) rb[(q * ND_NW + w) * 16 + i16] = sv[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < ND_NW; ++ww) acc += rb[(q * ND_NW + ww) * 16 + i16];
+        sv[q] = acc;
+    }
+    ++rk;
+}
 
 template <int NT, bool ST>
 __global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n, NutsAdapt ad, uint32_t t_begin,
@@ -658,7 +702,8 @@ __global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n,
                                                           int32_t* tr_depth, int32_t* tr_nleap, double* tr_stat) {
     constexpr int MT = (NT + ND_NW - 1) / ND_NW;
     constexpr int KM = 4 * NT;
-    constexpr int XS = 16 * NT + 4;
+    constexpr int XS = nd_xs<NT>();
+    constexpr int LV = nd_lds_levels<NT>();
     extern __shared__ float lds[];
     const int64_t C = a.C, D = a.tg.D;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -668,8 +713,9 @@ __global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n,
     const int64_t cc = cvalid ? c : 0;
     float* xs0 = lds;
     float* xs1 = lds + 16 * XS;
-    double* red = (double*)(lds + 2 * 16 * XS);          // [2 parity][2 values][NW][16]
-    int* vote = (int*)(red + 2 * 2 * ND_NW * 16);        // [2 parity][16]
+    double* red = (double*)(lds + 2 * 16 * XS);          // [2 parity][ND_RV values][NW][16]
+    int* vote = (int*)(red + 2 * ND_RV * ND_NW * 16);    // [2 parity][16]
+    float* lvl = (float*)(vote + 2 * 16);                // [LV][4 records][16 chains][XS]
     const float* P = (const float*)a.tg.prec;
     float *mx = (float*)n.mx, *mr = (float*)n.mr, *mg = (float*)n.mg;
     float *px = (float*)n.px, *pr = (float*)n.pr, *pg = (float*)n.pg;
@@ -700,32 +746,43 @@ __global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n,
             x[m][v] = ok[m][v] ? ((const float*)a.ws.x)[cc * D + dim_of(m, v)] : 0.f;
             g[m][v] = ok[m][v] ? ((const float*)a.ws.g)[cc * D + dim_of(m, v)] : 0.f;
         }
+    // parked records of level k (1 ..): 0 first leaf x, 1 first leaf r, 2
+    // candidate x, 3 candidate g; the lane's 4 dims of tile m
+    float* const grec[4] = {lfx, lfr, lcx, lcg};
+    auto rec_load = [&](int k, int q, int m, float out[4]) {
+        if (k <= LV) {
+            const floatx4 v4 = *(const floatx4*)(lvl + (((k - 1) * 4 + q) * 16 + i16) * XS + 16 * (w + ND_NW * m) +
+                                                  4 * g4);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[v] = v4[v];
+        } else {
+            const float* gp = grec[q] + ((int64_t)k * C + cc) * D;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[v] = ok[m][v] ? gp[dim_of(m, v)] : 0.f;
+        }
+    };
+    auto rec_store = [&](int k, int q, int m, const float in[4]) {
+        if (k <= LV) {
+            *(floatx4*)(lvl + (((k - 1) * 4 + q) * 16 + i16) * XS + 16 * (w + ND_NW * m) + 4 * g4) =
+                floatx4{in[0], in[1], in[2], in[3]};
+        } else {
+            float* gp = grec[q] + ((int64_t)k * C + cc) * D;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (ok[m][v]) gp[dim_of(m, v)] = in[v];
+        }
+    };
     double logp = a.ws.logp[cc];
     double eps = a.ws.eps[cc];
     DualAvg da{};
     if (ST) da = a.ws.da[cc];
     int buf = 0, rk = 0, vk = 0;
 
-    // sums over each chain's dims, returned to every lane of the chain
     auto chain_sum2 = [&](double& s0, double& s1) {
-        s0 += __shfl_xor(s0, 16, 64);
-        s0 += __shfl_xor(s0, 32, 64);
-        s1 += __shfl_xor(s1, 16, 64);
-        s1 += __shfl_xor(s1, 32, 64);
-        double* rb = red + (rk & 1) * (2 * ND_NW * 16);
-        if (g4 == 0) {
-            rb[(2 * w) * 16 + i16] = s0;
-            rb[(2 * w + 1) * 16 + i16] = s1;
-        }
-        __syncthreads();
-        s0 = 0.0;
-        s1 = 0.0;
-#pragma unroll
-        for (int ww = 0; ww < ND_NW; ++ww) {
-            s0 += rb[(2 * ww) * 16 + i16];
-            s1 += rb[(2 * ww + 1) * 16 + i16];
-        }
-        ++rk;
+        double sv[2] = {s0, s1};
+        nd_chain_sum<2>(sv, red, rk, w, g4, i16);
+        s0 = sv[0];
+        s1 = sv[1];
     };
     // does any chain of the tile satisfy pred (one value per chain)
     auto tile_any = [&](bool pred) -> bool {
@@ -859,22 +916,37 @@ __global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n,
 #pragma unroll
                 for (int k = 1; k <= NUTS_MAXD; ++k) {
                     if (k > j) break;
-                    const int64_t rk0 = ((int64_t)k * C + cc) * D;
                     if (((i >> (k - 1)) & 1) == 0) {
                         if (alive) {
-                            const int64_t rf = ((int64_t)(first < 0 ? 0 : first) * C + cc) * D;
-                            const int64_t rc = ((int64_t)(cand < 0 ? 0 : cand) * C + cc) * D;
 #pragma unroll
-                            for (int m = 0; m < MT; ++m)
+                            for (int m = 0; m < MT; ++m) {
+                                if (!tile_ok[m]) continue;
+                                float f0[4], f1[4], c0[4], c1[4];
+                                if (first < 0) {
 #pragma unroll
-                                for (int v = 0; v < 4; ++v)
-                                    if (ok[m][v]) {
-                                        const int64_t d = dim_of(m, v);
-                                        lfx[rk0 + d] = first < 0 ? wx[m][v] : lfx[rf + d];
-                                        lfr[rk0 + d] = first < 0 ? wr[m][v] : lfr[rf + d];
-                                        lcx[rk0 + d] = cand < 0 ? wx[m][v] : lcx[rc + d];
-                                        lcg[rk0 + d] = cand < 0 ? wg[m][v] : lcg[rc + d];
+                                    for (int v = 0; v < 4; ++v) {
+                                        f0[v] = wx[m][v];
+                                        f1[v] = wr[m][v];
                                     }
+                                } else {
+                                    rec_load(first, 0, m, f0);
+                                    rec_load(first, 1, m, f1);
+                                }
+                                if (cand < 0) {
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) {
+                                        c0[v] = wx[m][v];
+                                        c1[v] = wg[m][v];
+                                    }
+                                } else {
+                                    rec_load(cand, 2, m, c0);
+                                    rec_load(cand, 3, m, c1);
+                                }
+                                rec_store(k, 0, m, f0);
+                                rec_store(k, 1, m, f1);
+                                rec_store(k, 2, m, c0);
+                                rec_store(k, 3, m, c1);
+                            }
                             lcn[k - 1] = n_node;
                             lclp[k - 1] = cand_lp;
                         }
@@ -892,33 +964,48 @@ __global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n,
                         }
                         n_node += nl;
 #pragma unroll
-                        for (int m = 0; m < MT; ++m)
+                        for (int m = 0; m < MT; ++m) {
+                            if (!tile_ok[m]) continue;
+                            float f0[4], f1[4];
+                            rec_load(k, 0, m, f0);
+                            rec_load(k, 1, m, f1);
 #pragma unroll
                             for (int v = 0; v < 4; ++v)
                                 if (ok[m][v]) {
-                                    const int64_t d = dim_of(m, v);
-                                    const double fx = (double)lfx[rk0 + d], fr = (double)lfr[rk0 + d];
+                                    const double fx = (double)f0[v], fr = (double)f1[v];
                                     const double lx = (double)wx[m][v], lr = (double)wr[m][v];
                                     const double dx = dir > 0 ? lx - fx : fx - lx;
                                     dm += dx * (dir > 0 ? fr : lr);
                                     dp += dx * (dir > 0 ? lr : fr);
                                 }
+                        }
                     }
                     chain_sum2(dm, dp);
                     first = k;
                     if (alive && !(dm >= 0.0 && dp >= 0.0)) alive = false;
                 }
                 if (!parked && alive) {     // the last leaf: every subtree of doubling j ends here
-                    const int64_t rc = ((int64_t)(cand < 0 ? 0 : cand) * C + cc) * D;
 #pragma unroll
-                    for (int m = 0; m < MT; ++m)
+                    for (int m = 0; m < MT; ++m) {
+                        if (!tile_ok[m]) continue;
+                        float c0[4], c1[4];
+                        if (cand < 0) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                c0[v] = wx[m][v];
+                                c1[v] = wg[m][v];
+                            }
+                        } else {
+                            rec_load(cand, 2, m, c0);
+                            rec_load(cand, 3, m, c1);
+                        }
 #pragma unroll
                         for (int v = 0; v < 4; ++v)
                             if (ok[m][v]) {
-                                const int64_t d = dim_of(m, v);
-                                rcx[cc * D + d] = cand < 0 ? wx[m][v] : lcx[rc + d];
-                                rcg[cc * D + d] = cand < 0 ? wg[m][v] : lcg[rc + d];
+                                rcx[cc * D + dim_of(m, v)] = c0[v];
+                                rcg[cc * D + dim_of(m, v)] = c1[v];
                             }
+                    }
                     rclp = cand_lp;
                     rcn = n_node;
                     complete = true;
@@ -1031,20 +1118,27 @@ static hipError_t launch_nuts_dense(const PlainArgs& a, const NutsWs& n, const N
                                     int64_t n_trans, int32_t max_depth, void* samples, int32_t* tr_depth,
                                     int32_t* tr_nleap, double* tr_stat, hipStream_t s) {
     const int nt = (int)((a.tg.D + 15) / 16);
-    const size_t lds = (size_t)2 * 16 * (16 * nt + 4) * sizeof(float) + (size_t)2 * 2 * ND_NW * 16 * sizeof(double) +
-                       2 * 16 * sizeof(int);
     const dim3 grid((unsigned)((a.C + 15) / 16));
     const bool st = ad.adapt || tr_stat;
     switch (nt) {
-#define HMC_NUTS_D(N)                                                                                              \
-    case N:                                                                                                        \
-        if (st)                                                                                                    \
-            hipLaunchKernelGGL((k_nuts_fused_dense<N, true>), grid, dim3(256), lds, s, a, n, ad, t_begin, n_trans, \
-                               max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);                           \
-        else                                                                                                       \
-            hipLaunchKernelGGL((k_nuts_fused_dense<N, false>), grid, dim3(256), lds, s, a, n, ad, t_begin, n_trans,\
-                               max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);                           \
-        break;
+#define HMC_NUTS_D(N)                                                                                               \
+    case N: {                                                                                                       \
+        constexpr size_t lds = nd_lds_bytes<N>();                                                                   \
+        if (st) {                                                                                                   \
+            if (lds > 65536)                                                                                        \
+                (void)hipFuncSetAttribute((const void*)k_nuts_fused_dense<N, true>,                                 \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
+            hipLaunchKernelGGL((k_nuts_fused_dense<N, true>), grid, dim3(256), lds, s, a, n, ad, t_begin, n_trans,  \
+                               max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);                            \
+        } else {                                                                                                    \
+            if (lds > 65536)                                                                                        \
+                (void)hipFuncSetAttribute((const void*)k_nuts_fused_dense<N, false>,                                \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
+            hipLaunchKernelGGL((k_nuts_fused_dense<N, false>), grid, dim3(256), lds, s, a, n, ad, t_begin, n_trans, \
+                               max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);                            \
+        }                                                                                                           \
+        break;                                                                                                      \
+    }
         HMC_NUTS_D(1) HMC_NUTS_D(2) HMC_NUTS_D(3) HMC_NUTS_D(4)
         HMC_NUTS_D(5) HMC_NUTS_D(6) HMC_NUTS_D(7) HMC_NUTS_D(8)
 #undef HMC_NUTS_D
