@@ -368,13 +368,58 @@ __global__ __launch_bounds__(256) void k_nuts_end(PlainArgs a, NutsWs n, NutsAda
 // ---------------------------------------------------------------------------
 constexpr int NUTS_MAXD = 10;
 
+// Logistic regression on the persistent path (GK = 1): one wavefront per
+// chain (G = 64, NB = 1: lane l holds dims 4 l .. 4 l + 3, D <= 4 LR_DQ), X
+// (FP32, rows padded to 4 DQ floats) and y staged once per workgroup in LDS
+// and shared by its 4 chains.  A leaf's gradient reads each row of X once:
+// s = x . theta with theta broadcast from LDS, r = y - sigmoid(s), the row's
+// term of the log-likelihood, then r x_row into per-lane partials, which the
+// wave sums column by column through LDS in a fixed order.
+constexpr int LR_DQ = 8;                    // 4-dim chunks of theta (D <= 32)
+constexpr int LR_SCR = 4 * LR_DQ + 1;       // row stride of the transposition scratch
+
+__device__ __forceinline__ float nuts_sigmoidf(float s) {
+    const float e = expf(-fabsf(s));
+    const float r = 1.0f / (1.0f + e);
+    return s >= 0.f ? r : e * r;
+}
+__device__ __forceinline__ float nuts_softplusf(float s) { return fmaxf(s, 0.f) + log1pf(expf(-fabsf(s))); }
+
+// LDS bytes of the logistic persistent kernel: X [N][4 DQ], y [N rounded up
+// to 4, keeping what follows 16-byte aligned], and per wave theta [4 DQ], the
+// gradient [4 DQ] and the scratch [64][LR_SCR]
+inline size_t nuts_lr_lds_bytes(int64_t N, int64_t D) {
+    const int64_t dp = 4 * ((D + 3) / 4);
+    return (size_t)(N * dp + ((N + 3) & ~(int64_t)3) + 4 * (2 * dp + 64 * LR_SCR)) * sizeof(float);
+}
+
 // ST: the run adapts the step size or traces the statistic (a template
-// parameter, so that plain runs carry none of it).
-template <typename T, int G, int NB, bool ST>
+// parameter, so that plain runs carry none of it).  GK: 0 element-wise
+// Gaussian gradient, 1 logistic regression through LDS.
+template <typename T, int G, int NB, bool ST, int GK>
 __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, NutsAdapt ad, uint32_t t_begin,
                                                          int64_t n_trans, int32_t max_depth, T* samples,
                                                          int32_t* tr_depth, int32_t* tr_nleap, double* tr_stat) {
     const int64_t n_burnin = ad.n_burnin;
+    extern __shared__ float lr_lds[];
+    const int64_t NR = GK == 1 ? a.tg.N : 0;
+    const int dq = GK == 1 ? (int)((a.tg.D + 3) / 4) : 0;
+    const int dp = 4 * dq;
+    float* xl = lr_lds;                                  // [N][dp]
+    float* yl = xl + NR * dp;                            // [N]
+    float* thl = yl + ((NR + 3) & ~(int64_t)3) + (threadIdx.x >> 6) * (2 * dp + 64 * LR_SCR);   // wave's theta [dp]
+    float* gsl = thl + dp;                               // gradient sums [dp]
+    float* scr = gsl + dp;                               // [64][LR_SCR]
+    if (GK == 1) {
+        const float* Xg = (const float*)a.tg.X;
+        const int64_t D0 = a.tg.D;
+        for (int64_t e = threadIdx.x; e < NR * dp; e += blockDim.x) {
+            const int64_t r = e / dp, d = e - r * dp;
+            xl[e] = d < D0 ? Xg[r * D0 + d] : 0.f;
+        }
+        for (int64_t r = threadIdx.x; r < NR; r += blockDim.x) yl[r] = a.tg.y[r] ? 1.f : 0.f;
+        __syncthreads();                                 // the only barrier: the chains are independent after it
+    }
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % G;
     const int64_t c = gid / G;
@@ -400,6 +445,59 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
             pc[b][e] = ok[b][e] ? (diag ? prec[d] : (T)1) : (T)0;
         }
     auto dim_of = [&](int b, int e) -> int64_t { return 4 * (lane + (int64_t)G * b) + e; };
+    // logistic data gradient X^T (y - sigmoid(X theta)) at theta = wxa into
+    // wga (the lane's dims), and the data log-likelihood (wave-uniform).  The
+    // LDS traffic between lanes stays inside the wave, whose LDS operations
+    // run in order; the empty asm statements keep the compiler from moving
+    // them across each other.
+    auto logreg_grad_lds = [&](T (&wxa)[NB][4], T (&wga)[NB][4]) -> double {
+        if (lane < dq) *(floatx4*)(thl + 4 * lane) = floatx4{(float)wxa[0][0], (float)wxa[0][1], (float)wxa[0][2],
+                                                            (float)wxa[0][3]};
+        asm volatile("" ::: "memory");
+        floatx4 th[LR_DQ];
+#pragma unroll
+        for (int q = 0; q < LR_DQ; ++q) th[q] = q < dq ? *(const floatx4*)(thl + 4 * q) : floatx4{0.f, 0.f, 0.f, 0.f};
+        floatx4 gacc[LR_DQ];
+#pragma unroll
+        for (int q = 0; q < LR_DQ; ++q) gacc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+        double lpd = 0.0;
+        for (int64_t r = lane; r < NR; r += 64) {
+            const float* xr = xl + r * dp;
+            floatx4 xq[LR_DQ];
+            float sv = 0.f;
+#pragma unroll
+            for (int q = 0; q < LR_DQ; ++q) {
+                xq[q] = q < dq ? *(const floatx4*)(xr + 4 * q) : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sv = fmaf(xq[q][e], th[q][e], sv);
+            }
+            const float yv = yl[r];
+            const float res = yv - nuts_sigmoidf(sv);
+            lpd -= (double)nuts_softplusf(yv > 0.5f ? -sv : sv);
+#pragma unroll
+            for (int q = 0; q < LR_DQ; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) gacc[q][e] = fmaf(xq[q][e], res, gacc[q][e]);
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int q = 0; q < LR_DQ; ++q)
+            if (q < dq)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) scr[lane * LR_SCR + 4 * q + e] = gacc[q][e];
+        asm volatile("" ::: "memory");
+        if (lane < dp) {
+            float col = 0.f;
+            for (int rr = 0; rr < 64; ++rr) col += scr[rr * LR_SCR + lane];
+            gsl[lane] = col;
+        }
+        asm volatile("" ::: "memory");
+        const floatx4 gq = lane < dq ? *(const floatx4*)(gsl + 4 * lane) : floatx4{0.f, 0.f, 0.f, 0.f};
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int e = 0; e < 4; ++e) wga[0][e] = (T)gq[e];
+        return group_sum<64>(lpd);
+    };
     double logp = a.ws.logp[cc];
     double eps = a.ws.eps[cc];
     DualAvg da{};
@@ -460,12 +558,28 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                     for (int e = 0; e < 4; ++e) {
                         wr[b][e] = wr[b][e] + hse * wg[b][e];
                         wx[b][e] = fma(se, wr[b][e], wx[b][e]);
-                        wg[b][e] = -pc[b][e] * wx[b][e];
-                        wr[b][e] = fma(hse, wg[b][e], wr[b][e]);
-                        lp += 0.5 * (double)wx[b][e] * (double)wg[b][e];
-                        kin += 0.5 * (double)wr[b][e] * (double)wr[b][e];
+                        if (GK == 0) {
+                            wg[b][e] = -pc[b][e] * wx[b][e];
+                            wr[b][e] = fma(hse, wg[b][e], wr[b][e]);
+                            lp += 0.5 * (double)wx[b][e] * (double)wg[b][e];
+                            kin += 0.5 * (double)wr[b][e] * (double)wr[b][e];
+                        }
                     }
-                lp = group_sum<G>(lp);
+                if (GK == 1) {
+                    const double lpd = logreg_grad_lds(wx, wg);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            wg[b][e] = ok[b][e] ? wg[b][e] - (float)wx[b][e] * (float)a.tg.inv_var : (T)0;
+                            wr[b][e] = fma(hse, wg[b][e], wr[b][e]);
+                            if (ok[b][e]) lp += -0.5 * (double)wx[b][e] * (double)wx[b][e] * a.tg.inv_var;
+                            kin += 0.5 * (double)wr[b][e] * (double)wr[b][e];
+                        }
+                    lp = group_sum<G>(lp) + lpd;
+                } else {
+                    lp = group_sum<G>(lp);
+                }
                 kin = group_sum<G>(kin);
                 wlogp = lp;
                 nleap += 1;
@@ -1093,7 +1207,14 @@ __global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n,
 
 // lanes per chain and 4-dim blocks per lane of the persistent kernel, 0 if it
 // does not apply (registers: FP64 keeps one block per lane, FP32 two)
+// the logistic persistent kernel: FP32 states and X, D <= 4 LR_DQ, X and y in LDS
+static bool nuts_lr_supported(const PlainArgs& a) {
+    return a.tg.kind == HMC_TGT_LOGREG && !a.f64 && !a.tg.x_bf16 && !a.bf16_grad && a.tg.D >= 1 &&
+           a.tg.D <= 4 * LR_DQ && nuts_lr_lds_bytes(a.tg.N, a.tg.D) <= (size_t)ND_LDS_MAX;
+}
+
 static int nuts_elem_shape(const PlainArgs& a, int* G) {
+    if (nuts_lr_supported(a)) { *G = 64; return 1; }
     if (a.tg.kind != HMC_TGT_STD_NORMAL && a.tg.kind != HMC_TGT_GAUSS_DIAG) return 0;
     const int64_t nblk = (a.tg.D + 3) / 4;
     if (nblk <= 1) { *G = 1; return 1; }
@@ -1160,13 +1281,28 @@ hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, const NutsAdap
 #define HMC_NUTS_F(TT, GG, NN)                                                                                       \
     do {                                                                                                             \
         if (st)                                                                                                      \
-            hipLaunchKernelGGL((k_nuts_fused_elem<TT, GG, NN, true>), grid, dim3(256), 0, s, a, n, ad, t_begin,      \
+            hipLaunchKernelGGL((k_nuts_fused_elem<TT, GG, NN, true, 0>), grid, dim3(256), 0, s, a, n, ad, t_begin,   \
                                n_trans, max_depth, (TT*)samples, tr_depth, tr_nleap, tr_stat);                       \
         else                                                                                                         \
-            hipLaunchKernelGGL((k_nuts_fused_elem<TT, GG, NN, false>), grid, dim3(256), 0, s, a, n, ad, t_begin,     \
+            hipLaunchKernelGGL((k_nuts_fused_elem<TT, GG, NN, false, 0>), grid, dim3(256), 0, s, a, n, ad, t_begin,  \
                                n_trans, max_depth, (TT*)samples, tr_depth, tr_nleap, tr_stat);                       \
     } while (0)
-    if (a.f64) {
+    if (nuts_lr_supported(a)) {
+        const size_t lds = nuts_lr_lds_bytes(a.tg.N, a.tg.D);
+        if (st) {
+            if (lds > 65536)
+                (void)hipFuncSetAttribute((const void*)k_nuts_fused_elem<float, 64, 1, true, 1>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL((k_nuts_fused_elem<float, 64, 1, true, 1>), grid, dim3(256), lds, s, a, n, ad, t_begin,
+                               n_trans, max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);
+        } else {
+            if (lds > 65536)
+                (void)hipFuncSetAttribute((const void*)k_nuts_fused_elem<float, 64, 1, false, 1>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL((k_nuts_fused_elem<float, 64, 1, false, 1>), grid, dim3(256), lds, s, a, n, ad,
+                               t_begin, n_trans, max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);
+        }
+    } else if (a.f64) {
         if (G == 1) HMC_NUTS_F(double, 1, 1);
         else if (G == 4) HMC_NUTS_F(double, 4, 1);
         else if (G == 16) HMC_NUTS_F(double, 16, 1);

@@ -9,8 +9,9 @@ leapfrog count, moved) and those chains' states agree to 1e-5 relative; the
 FP32 chain samples N(0, 1) with the right variance.
 
 The persistent kernels (element-wise targets; the dense Gaussian on MFMA,
-16 chains per workgroup) build the lockstep path's trees (>= 99%), including a
-ragged tile and the largest dense shape.
+16 chains per workgroup; logistic regression with X in LDS, a wavefront per
+chain) build the lockstep path's trees (>= 99%), including a ragged tile, the
+largest dense shape and the largest data set that fits in LDS.
 
 Step-size adaptation inside NUTS (Hoffman & Gelman Algorithm 6): on FP64
 element-wise targets adapted runs match the oracle's (states and statistics
@@ -118,6 +119,9 @@ def _persistent_cases():
         "dense_100": W.gauss_dense(dim=100, num_chains=80, step_size=0.1, seed=2),
         "dense_ragged_17x17": W.gauss_dense(dim=17, num_chains=17, step_size=0.2, seed=4),
         "dense_max_128": W.gauss_dense(dim=128, num_chains=33, step_size=0.05, seed=6),
+        "logreg_1000x25": W.logreg(1000, 25, 64, step_size=0.05),                  # X in LDS, a wave per chain
+        "logreg_77x3": W.logreg(77, 3, 33, step_size=0.2, seed=5),                 # N not a multiple of 4
+        "logreg_max_960x32": W.logreg(960, 32, 12, step_size=0.03, seed=8),        # the largest X that fits
     }
 
 
@@ -197,7 +201,8 @@ def test_exact_statistics_give_exact_step_sizes(form):
 
 
 @pytest.mark.parametrize("name,form", [("gauss_dense_37", "lockstep"), ("gauss_dense_37", "persistent"),
-                                       ("logreg_77x3", "lockstep"), ("std_normal_7d", "persistent")])
+                                       ("logreg_77x3", "lockstep"), ("logreg_77x3", "persistent"),
+                                       ("std_normal_7d", "persistent")])
 def test_fp32_adaptation_follows_the_oracle(name, form):
     w = _fp32_cases()[name]
     s = hmc.sampler_for(w, form=FORMS[form])
