@@ -378,19 +378,37 @@ constexpr int NUTS_MAXD = 10;
 constexpr int LR_DQ = 8;                    // 4-dim chunks of theta (D <= 32)
 constexpr int LR_SCR = 4 * LR_DQ + 1;       // row stride of the transposition scratch
 
-__device__ __forceinline__ float nuts_sigmoidf(float s) {
-    const float e = expf(-fabsf(s));
-    const float r = 1.0f / (1.0f + e);
-    return s >= 0.f ? r : e * r;
+// One row's residual y - sigmoid(s) and log-likelihood term
+// -softplus(y ? -s : s), from a single e = exp(-|s|) on the hardware exp2,
+// reciprocal and log2 (a few ulp; softplus(z) = max(z, 0) + ln(1 + e), where
+// ln(1 + e) loses e below 2^-24 relative to 1, an absolute error < 6e-8).
+__device__ __forceinline__ float nuts_lr_row(float s, float yv, double& lpd) {
+    const float e = __builtin_amdgcn_exp2f(-fabsf(s) * 1.44269504f);
+    const float inv = __builtin_amdgcn_rcpf(1.f + e);
+    const float sig = s >= 0.f ? inv : e * inv;
+    const float z = yv > 0.5f ? -s : s;
+    lpd -= (double)(fmaxf(z, 0.f) + __builtin_amdgcn_logf(1.f + e) * 0.693147181f);
+    return yv - sig;
 }
-__device__ __forceinline__ float nuts_softplusf(float s) { return fmaxf(s, 0.f) + log1pf(expf(-fabsf(s))); }
 
-// LDS bytes of the logistic persistent kernel: X [N][4 DQ], y [N rounded up
-// to 4, keeping what follows 16-byte aligned], and per wave theta [4 DQ], the
-// gradient [4 DQ] and the scratch [64][LR_SCR]
+// LDS floats of the logistic persistent kernel: X [N][4 DQ], y [N rounded up
+// to 4, keeping what follows 16-byte aligned], per wave theta [4 DQ], the
+// gradient [4 DQ] and the scratch [64][LR_SCR]; then, per wave, the parked
+// records (4 arrays of 4 DQ floats) of as many shallow tree levels as the
+// rest of the 160 KB holds (at most 9).
+__host__ __device__ inline int64_t nuts_lr_lds_fixed(int64_t N, int64_t D) {
+    const int64_t dp = 4 * ((D + 3) / 4);
+    return N * dp + ((N + 3) & ~(int64_t)3) + 4 * (2 * dp + 64 * LR_SCR);
+}
+__host__ __device__ inline int nuts_lr_lds_levels(int64_t N, int64_t D) {
+    const int64_t dp = 4 * ((D + 3) / 4);
+    const int64_t room = 163840 / 4 - nuts_lr_lds_fixed(N, D);
+    const int64_t lv = room > 0 ? room / (4 * 4 * dp) : 0;
+    return (int)(lv > 9 ? 9 : lv);
+}
 inline size_t nuts_lr_lds_bytes(int64_t N, int64_t D) {
     const int64_t dp = 4 * ((D + 3) / 4);
-    return (size_t)(N * dp + ((N + 3) & ~(int64_t)3) + 4 * (2 * dp + 64 * LR_SCR)) * sizeof(float);
+    return (size_t)(nuts_lr_lds_fixed(N, D) + (int64_t)nuts_lr_lds_levels(N, D) * 4 * 4 * dp) * sizeof(float);
 }
 
 // ST: the run adapts the step size or traces the statistic (a template
@@ -410,6 +428,9 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
     float* thl = yl + ((NR + 3) & ~(int64_t)3) + (threadIdx.x >> 6) * (2 * dp + 64 * LR_SCR);   // wave's theta [dp]
     float* gsl = thl + dp;                               // gradient sums [dp]
     float* scr = gsl + dp;                               // [64][LR_SCR]
+    const int nlv = GK == 1 ? nuts_lr_lds_levels(NR, a.tg.D) : 0;
+    float* lvl = lr_lds + (GK == 1 ? nuts_lr_lds_fixed(NR, a.tg.D) : 0) +
+                 (int64_t)(threadIdx.x >> 6) * nlv * 4 * dp;  // this wave's level records [nlv][4][dp]
     if (GK == 1) {
         const float* Xg = (const float*)a.tg.X;
         const int64_t D0 = a.tg.D;
@@ -445,6 +466,14 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
             pc[b][e] = ok[b][e] ? (diag ? prec[d] : (T)1) : (T)0;
         }
     auto dim_of = [&](int b, int e) -> int64_t { return 4 * (lane + (int64_t)G * b) + e; };
+    // level k's record q (0 first x, 1 first r, 2 candidate x, 3 candidate g),
+    // indexed by dim: the shallow levels of the logistic path in LDS (a flat
+    // pointer), the rest in the NutsWs buffers
+    T* const grec[4] = {lfx, lfr, lcx, lcg};
+    auto recp = [&](int k, int q) -> T* {
+        if (GK == 1 && k <= nlv) return (T*)(lvl + ((k - 1) * 4 + q) * dp);
+        return grec[q] + ((int64_t)k * C + cc) * D;
+    };
     // logistic data gradient X^T (y - sigmoid(X theta)) at theta = wxa into
     // wga (the lane's dims), and the data log-likelihood (wave-uniform).  The
     // LDS traffic between lanes stays inside the wave, whose LDS operations
@@ -461,7 +490,9 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
 #pragma unroll
         for (int q = 0; q < LR_DQ; ++q) gacc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
         double lpd = 0.0;
-        for (int64_t r = lane; r < NR; r += 64) {
+        const int nr = (int)NR;
+#pragma unroll 2
+        for (int r = lane; r < nr; r += 64) {
             const float* xr = xl + r * dp;
             floatx4 xq[LR_DQ];
             float sv = 0.f;
@@ -471,9 +502,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
 #pragma unroll
                 for (int e = 0; e < 4; ++e) sv = fmaf(xq[q][e], th[q][e], sv);
             }
-            const float yv = yl[r];
-            const float res = yv - nuts_sigmoidf(sv);
-            lpd -= (double)nuts_softplusf(yv > 0.5f ? -sv : sv);
+            const float res = nuts_lr_row(sv, yl[r], lpd);
 #pragma unroll
             for (int q = 0; q < LR_DQ; ++q)
 #pragma unroll
@@ -599,20 +628,22 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
 #pragma unroll
                 for (int k = 1; k <= NUTS_MAXD; ++k) {
                     if (k > j) break;
-                    const int64_t rk = ((int64_t)k * C + cc) * D;
+                    T *kfx = recp(k, 0), *kfr = recp(k, 1), *kcx = recp(k, 2), *kcg = recp(k, 3);
                     if (((i >> (k - 1)) & 1) == 0) {
-                        const int64_t rf = ((int64_t)(first < 0 ? 0 : first) * C + cc) * D;
-                        const int64_t rc = ((int64_t)(cand < 0 ? 0 : cand) * C + cc) * D;
+                        const T* ffx = recp(first < 0 ? 1 : first, 0);
+                        const T* ffr = recp(first < 0 ? 1 : first, 1);
+                        const T* ccx = recp(cand < 0 ? 1 : cand, 2);
+                        const T* ccg = recp(cand < 0 ? 1 : cand, 3);
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
 #pragma unroll
                             for (int e = 0; e < 4; ++e)
                                 if (ok[b][e]) {
                                     const int64_t d = dim_of(b, e);
-                                    lfx[rk + d] = first < 0 ? wx[b][e] : lfx[rf + d];
-                                    lfr[rk + d] = first < 0 ? wr[b][e] : lfr[rf + d];
-                                    lcx[rk + d] = cand < 0 ? wx[b][e] : lcx[rc + d];
-                                    lcg[rk + d] = cand < 0 ? wg[b][e] : lcg[rc + d];
+                                    kfx[d] = first < 0 ? wx[b][e] : ffx[d];
+                                    kfr[d] = first < 0 ? wr[b][e] : ffr[d];
+                                    kcx[d] = cand < 0 ? wx[b][e] : ccx[d];
+                                    kcg[d] = cand < 0 ? wg[b][e] : ccg[d];
                                 }
                         lcn[k - 1] = n_node;
                         lclp[k - 1] = cand_lp;
@@ -634,7 +665,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                         for (int e = 0; e < 4; ++e)
                             if (ok[b][e]) {
                                 const int64_t d = dim_of(b, e);
-                                const double fx = (double)lfx[rk + d], fr = (double)lfr[rk + d];
+                                const double fx = (double)kfx[d], fr = (double)kfr[d];
                                 const double lx = (double)wx[b][e], lr = (double)wr[b][e];
                                 const double dx = v > 0 ? lx - fx : fx - lx;
                                 dm += dx * (v > 0 ? fr : lr);
@@ -650,14 +681,15 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                 }
                 if (!alive) break;
                 if (!parked) {          // the last leaf: every subtree of doubling j ends here
-                    const int64_t rc = ((int64_t)(cand < 0 ? 0 : cand) * C + cc) * D;
+                    const T* ccx = recp(cand < 0 ? 1 : cand, 2);
+                    const T* ccg = recp(cand < 0 ? 1 : cand, 3);
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const int64_t d = dim_of(b, e);
-                            rcx[b][e] = cand < 0 ? wx[b][e] : (ok[b][e] ? lcx[rc + d] : (T)0);
-                            rcg[b][e] = cand < 0 ? wg[b][e] : (ok[b][e] ? lcg[rc + d] : (T)0);
+                            rcx[b][e] = cand < 0 ? wx[b][e] : (ok[b][e] ? ccx[d] : (T)0);
+                            rcg[b][e] = cand < 0 ? wg[b][e] : (ok[b][e] ? ccg[d] : (T)0);
                         }
                     rclp = cand_lp;
                     rcn = n_node;
