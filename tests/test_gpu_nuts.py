@@ -225,3 +225,54 @@ def test_nuts_adaptation_errors():
     with pytest.raises(hmc.HMCError, match="target_accept"):
         s.nuts_sample_chain(1, 1, adapt=True, target_accept=1.0)
     s.close()
+
+
+# ------------------------------------------------ persistent-kernel edges --
+def _edge_workloads():
+    return {
+        "dense_persistent": W.gauss_dense(dim=21, num_chains=18, step_size=0.15, seed=7),
+        "logreg_persistent": W.logreg(130, 6, 5, step_size=0.1, seed=9),
+    }
+
+
+@pytest.mark.parametrize("name", list(_edge_workloads()))
+@pytest.mark.parametrize("max_depth", [0, 1])
+def test_persistent_shallow_trees_match_oracle(name, max_depth):
+    # depth 0 never moves; depth 1 is one sliced leapfrog step: same outcome as the oracle's, chain by chain
+    w = _edge_workloads()[name]
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED)
+    g = s.nuts_sample_chain(3, 0, max_depth=max_depth)
+    xg = to_np(s.get_state()[0])
+    s.close()
+    o = oracle.nuts_sample_chain(oracle_target(w), w.seed, w.x0.astype(np.float64), w.step_size, 0, 3,
+                                 max_depth=max_depth)
+    assert np.array_equal(to_np(g["tree_depth"]), o["depth"])
+    assert np.array_equal(to_np(g["n_leapfrog"]), o["n_leapfrog"])
+    if max_depth == 0:
+        assert np.array_equal(xg, w.x0)
+        assert np.all(to_np(g["accept_stat"]) == 0.0)
+    assert np.max(rel_err_rows(xg, o["final_x"])) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(_edge_workloads()))
+def test_persistent_nan_chains_and_single_chain(name):
+    w = _edge_workloads()[name]
+    B, rate = 12, 0.04
+    x0 = w.x0.copy()
+    x0[1, 0] = np.nan
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED, x0=x0)
+    g = s.nuts_sample_chain(2, B, max_depth=6, adapt="simple", rate=rate)
+    eps = to_np(s.get_state()[1])
+    s.close()
+    o = oracle.nuts_sample_chain(oracle_target(w), w.seed, x0.astype(np.float64), w.step_size, B, 2, max_depth=6,
+                                 adapt="simple", rate=rate)
+    assert np.all(to_np(g["accept_stat"])[:, 1] == 0.0) and np.all(to_np(g["n_leapfrog"])[:, 1] == 1)
+    assert eps[1] == o["final_eps"][1]
+    # one chain alone in its workgroup
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED, num_chains=1)
+    g1 = s.nuts_sample_chain(4, 2, max_depth=6)
+    s.close()
+    o1 = oracle.nuts_sample_chain(oracle_target(w), w.seed, w.x0[:1].astype(np.float64), w.step_size, 2, 4,
+                                  max_depth=6)
+    assert np.array_equal(to_np(g1["tree_depth"]), o1["depth"])
+    assert np.max(rel_err_rows(to_np(g1["samples"]).reshape(-1, w.dim), o1["samples"].reshape(-1, w.dim))) <= 1e-5
