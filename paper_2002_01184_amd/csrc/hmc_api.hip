@@ -662,7 +662,7 @@ hmc_status hmc_remc_swap(hmc_ctx* ctx, int64_t num_replicas, uint64_t swap_index
     if (st != HMC_OK) return st;
     if (swap_index > 0xffffffffull) return fail(HMC_E_INVALID, "swap_index must be < 2^32");
     st = check_hip(launch_remc_swap(ctx->a, num_replicas, ctx->a.C / num_replicas, (uint32_t)swap_index,
-                                        swapped, ctx->stream), "exchange step");
+                                        swapped, nullptr, ctx->stream), "exchange step");
     return st;
 }
 
@@ -683,7 +683,7 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
     if (trace) tr = *trace;
     if (ad) st = check_hip(launch_da_init(ctx->a, ctx->stream), "adaptation init");
     if (ctx->form == HMC_FORM_FUSED) {
-        // one fused launch per transition (its trace row), then the exchange and the sample copy
+        // one fused launch per transition (its trace row), then the exchange, which writes the kept sample row
         for (int64_t i = 0; i < total && st == HMC_OK; ++i) {
             const uint64_t t = ctx->t + (uint64_t)i;
             const bool kept = i >= num_burnin_steps;
@@ -704,11 +704,10 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
             }
             st = check_hip(launch_fused(ctx->a, r, ctx->stream), "fused remc transition");
             uint8_t* sw = (kept && swapped) ? swapped + row : nullptr;
+            void* srow = (kept && samples) ? (char*)samples + (size_t)(i - num_burnin_steps) * rowb : nullptr;
             if (st == HMC_OK)
-                st = check_hip(launch_remc_swap(ctx->a, num_replicas, M, (uint32_t)t, sw, ctx->stream), "exchange step");
-            if (st == HMC_OK && kept && samples)
-                st = check_hip(hipMemcpyAsync((char*)samples + (size_t)(i - num_burnin_steps) * rowb, ctx->a.ws.x, rowb,
-                                              hipMemcpyDeviceToDevice, ctx->stream), "sample copy");
+                st = check_hip(launch_remc_swap(ctx->a, num_replicas, M, (uint32_t)t, sw, srow, ctx->stream),
+                               "exchange step");
         }
         if (st == HMC_OK) ctx->t += (uint64_t)total;
         return st;
@@ -728,12 +727,11 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
         const uint64_t t = ctx->t + (uint64_t)i;
         const bool kept = i >= num_burnin_steps;
         uint8_t* sw = (kept && swapped) ? swapped + (size_t)(i - num_burnin_steps) * C : nullptr;
+        void* srow = (kept && samples) ? (char*)samples + (size_t)(i - num_burnin_steps) * rowb : nullptr;
         st = run_transitions(ctx, 1, false);
         if (st == HMC_OK)
-            st = check_hip(launch_remc_swap(ctx->a, num_replicas, M, (uint32_t)t, sw, ctx->stream), "exchange step");
-        if (st == HMC_OK && kept && samples)
-            st = check_hip(hipMemcpyAsync((char*)samples + (size_t)(i - num_burnin_steps) * rowb, ctx->a.ws.x, rowb,
-                                          hipMemcpyDeviceToDevice, ctx->stream), "sample copy");
+            st = check_hip(launch_remc_swap(ctx->a, num_replicas, M, (uint32_t)t, sw, srow, ctx->stream),
+                           "exchange step");
     }
     if (st == HMC_OK) ctx->t += (uint64_t)total;
     return st;

@@ -132,9 +132,11 @@ hipError_t launch_nuts_end(const PlainArgs& a, const NutsWs& n, const NutsAdapt&
 hipError_t launch_moments(const PlainArgs& a, const void* ring, int64_t q, int64_t r0, int64_t R,
                           const hmc_moments& m, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s);
-// Replica exchange step (K replicas of M chains, replica-major) with swap index t.
+// Replica exchange step (K replicas of M chains, replica-major) with swap index
+// t: every chain's flag into swapped and, when sample_row is not NULL, every
+// chain's post-exchange state into sample_row [C, D] (both may be NULL).
 hipError_t launch_remc_swap(const PlainArgs& a, int64_t K, int64_t M, uint32_t t, uint8_t* swapped,
-                            hipStream_t s);
+                            void* sample_row, hipStream_t s);
 
 // ---- BF16 gradients (k_logreg_bf16.hip) -------------------------------------
 hipError_t launch_transpose_bf16(const PlainArgs& a, void* Xt, hipStream_t s);

@@ -6,7 +6,7 @@
 //   k_end         energy at the trajectory end, dH, Metropolis test,
 //                 per-chain select, dual averaging, sample/trace writes  (Sec. 2.1, 4.2)
 //   k_tick        t += 1 (device-resident, so a captured graph replays unchanged)
-//   k_remc_swap   replica exchange between neighbouring temperatures (Sec. 3.1)
+//   k_remc_exchange  replica exchange between neighbouring temperatures (Sec. 3.1)
 //
 // Inverse temperatures (replica exchange): chain c targets beta_c logp.  The
 // cached logp and gradient stay those of the untempered target; beta_c
@@ -194,43 +194,63 @@ __global__ __launch_bounds__(256) void k_copy_proposal(PlainArgs a) {
     }
 }
 
-// Replica exchange (Sec. 3.1): chain c = k M + m is chain m of replica k.  One
-// wavefront per pair (k, k+1) of the parity class of t: it exchanges the
-// states (x, g, logp) of chains k M + m and (k+1) M + m with probability
+// Replica exchange (Sec. 3.1): chain c = k M + m is chain m of replica k.  The
+// pairs (k, k+1) of the parity class of t exchange the states (x, g, logp) of
+// chains k M + m and (k+1) M + m with probability
 // min(1, exp((beta_k - beta_{k+1}) (logp_{k+1} - logp_k))) (untempered logp),
 // testing log u < that exponent with the 52-bit uniform of block
 // (k M + m, t, 0, SWAP).  Step sizes and adaptation state stay with the slot.
+// One wavefront per pair, then one per chain of the unpaired replicas (0 when
+// the parity is odd, the last ones when too few remain): every chain gets its
+// flag (0 outside the pairs) and, when sample_row is given, its post-exchange
+// state written there, so the step needs no fill or copy besides.
 template <typename T>
-__global__ __launch_bounds__(256) void k_remc_swap(PlainArgs a, int64_t M, int64_t npairs, int32_t parity,
-                                                   uint32_t t, uint8_t* swapped) {
-    const int64_t pair = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(256) void k_remc_exchange(PlainArgs a, int64_t K, int64_t M, int32_t parity, uint32_t t,
+                                                       uint8_t* swapped, T* sample_row) {
+    const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (pair >= npairs * M) return;
-    const int64_t k = parity + 2 * (pair / M), m = pair % M;
-    const int64_t ca = k * M + m, cb = (k + 1) * M + m;
-    const double ba = a.ws.beta ? a.ws.beta[ca] : 1.0, bb = a.ws.beta ? a.ws.beta[cb] : 1.0;
-    const double la = a.ws.logp[ca], lb = a.ws.logp[cb];
-    const bool acc = log_uniform52(a.key, (uint32_t)ca, t, TAG_SWAP) < (ba - bb) * (lb - la);
-    if (swapped && lane == 0) {
-        swapped[ca] = acc ? 1 : 0;
-        swapped[cb] = acc ? 1 : 0;
-    }
-    if (!acc) return;
+    const int64_t npairs = (K - parity) / 2;      // k = parity, parity + 2, ... with k + 1 < K
     const int64_t D = a.tg.D;
     T* x = (T*)a.ws.x;
     T* g = (T*)a.ws.g;
-    for (int64_t d = lane; d < D; d += 64) {
-        const T xa = x[ca * D + d], xb = x[cb * D + d];
-        x[ca * D + d] = xb;
-        x[cb * D + d] = xa;
-        const T ga = g[ca * D + d], gb = g[cb * D + d];
-        g[ca * D + d] = gb;
-        g[cb * D + d] = ga;
+    if (item < npairs * M) {
+        const int64_t k = parity + 2 * (item / M), m = item % M;
+        const int64_t ca = k * M + m, cb = (k + 1) * M + m;
+        const double ba = a.ws.beta ? a.ws.beta[ca] : 1.0, bb = a.ws.beta ? a.ws.beta[cb] : 1.0;
+        const double la = a.ws.logp[ca], lb = a.ws.logp[cb];
+        const bool acc = log_uniform52(a.key, (uint32_t)ca, t, TAG_SWAP) < (ba - bb) * (lb - la);
+        if (swapped && lane == 0) {
+            swapped[ca] = acc ? 1 : 0;
+            swapped[cb] = acc ? 1 : 0;
+        }
+        for (int64_t d = lane; d < D; d += 64) {
+            const T xa = x[ca * D + d], xb = x[cb * D + d];
+            if (acc) {
+                x[ca * D + d] = xb;
+                x[cb * D + d] = xa;
+                const T ga = g[ca * D + d], gb = g[cb * D + d];
+                g[ca * D + d] = gb;
+                g[cb * D + d] = ga;
+            }
+            if (sample_row) {
+                sample_row[ca * D + d] = acc ? xb : xa;
+                sample_row[cb * D + d] = acc ? xa : xb;
+            }
+        }
+        if (acc && lane == 0) {
+            a.ws.logp[ca] = lb;
+            a.ws.logp[cb] = la;
+        }
+        return;
     }
-    if (lane == 0) {
-        a.ws.logp[ca] = lb;
-        a.ws.logp[cb] = la;
-    }
+    // unpaired replicas: 0 if the parity is odd, then parity + 2 npairs .. K - 1
+    const int64_t u = item - npairs * M, kr = u / M, m = u % M;
+    if (kr >= K - 2 * npairs) return;
+    const int64_t k = parity ? (kr == 0 ? 0 : 1 + 2 * npairs + (kr - 1)) : 2 * npairs + kr;
+    const int64_t c = k * M + m;
+    if (swapped && lane == 0) swapped[c] = 0;
+    if (sample_row)
+        for (int64_t d = lane; d < D; d += 64) sample_row[c * D + d] = x[c * D + d];
 }
 
 template <typename T>
@@ -689,23 +709,19 @@ hipError_t launch_moments(const PlainArgs& a, const void* ring, int64_t q, int64
     return hipGetLastError();
 }
 
-__global__ void k_clear_u8(uint8_t* p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
-}
-
 hipError_t launch_remc_swap(const PlainArgs& a, int64_t K, int64_t M, uint32_t t, uint8_t* swapped,
-                            hipStream_t s) {
-    // flags of chains outside this step's pairs are 0 (a fill kernel, so the
-    // sequence stays valid inside a captured graph)
-    if (swapped) hipLaunchKernelGGL(k_clear_u8, dim3((unsigned)((a.C + 255) / 256 < 1024 ? (a.C + 255) / 256 : 1024)),
-                                    dim3(256), 0, s, swapped, a.C);
+                            void* sample_row, hipStream_t s) {
+    if (K <= 0 || M <= 0) return hipSuccess;
     const int32_t parity = (int32_t)(t & 1u);
-    const int64_t npairs = (K - parity) / 2;      // k = parity, parity + 2, ... with k + 1 < K
-    if (npairs <= 0 || M <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((npairs * M + 3) / 4));
-    if (a.f64) hipLaunchKernelGGL(k_remc_swap<double>, grid, dim3(256), 0, s, a, M, npairs, parity, t, swapped);
-    else hipLaunchKernelGGL(k_remc_swap<float>, grid, dim3(256), 0, s, a, M, npairs, parity, t, swapped);
+    const int64_t npairs = (K - parity) / 2;
+    const int64_t waves = (K - npairs) * M;       // one per pair, one per unpaired chain
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    if (a.f64)
+        hipLaunchKernelGGL(k_remc_exchange<double>, grid, dim3(256), 0, s, a, K, M, parity, t, swapped,
+                           (double*)sample_row);
+    else
+        hipLaunchKernelGGL(k_remc_exchange<float>, grid, dim3(256), 0, s, a, K, M, parity, t, swapped,
+                           (float*)sample_row);
     return hipGetLastError();
 }
 
