@@ -320,14 +320,13 @@ def bench_nuts(args):
     form = {"auto": hmc.HMC_FORM_AUTO, "plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_PLAIN,
             "fused": hmc.HMC_FORM_FUSED}[args.form]
     s = hmc.sampler_for(w, form=form, grad_bf16=args.grad == "bf16")
-    # the persistent NUTS kernels cover element-wise targets up to 64 (FP64) or 128 (FP32) 4-dim blocks per
-    # chain, the dense Gaussian up to D = 128 (FP32) and logistic regression with FP32 X, D <= 32 and X, y
-    # and the per-wave buffers within the 160 KB of LDS
+    # the persistent NUTS kernels cover element-wise targets up to 256 4-dim blocks per chain (beyond 64, or
+    # 128 in FP32, a workgroup per chain), the dense Gaussian up to D = 128 (FP32) and logistic regression
+    # with FP32 X, D <= 32 and X, y and the per-wave buffers within the 160 KB of LDS
     fused = hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED
     dp = 4 * ((w.dim + 3) // 4)
     lr_lds = 4 * (w.n_rows * dp + ((w.n_rows + 3) // 4) * 4 + 4 * (2 * dp + 64 * 33)) if w.kind == W.LOGREG else 0
-    persistent = fused and ((w.kind in (W.STD_NORMAL, W.GAUSS_DIAG)
-                             and (w.dim + 3) // 4 <= (64 if w.state_dtype == "f64" else 128))
+    persistent = fused and ((w.kind in (W.STD_NORMAL, W.GAUSS_DIAG) and (w.dim + 3) // 4 <= 256)
                             or (w.kind == W.GAUSS_DENSE and w.state_dtype == "f32" and w.dim <= 128)
                             or (w.kind == W.LOGREG and args.grad == "f32" and w.dim <= 32 and lr_lds <= 163840))
     x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).cuda()

@@ -368,6 +368,37 @@ __global__ __launch_bounds__(256) void k_nuts_end(PlainArgs a, NutsWs n, NutsAda
 // ---------------------------------------------------------------------------
 constexpr int NUTS_MAXD = 10;
 
+// Sums over a chain's lanes for the persistent element-wise kernel.  G <= 64:
+// shuffles inside the wavefront.  G = 256 (one chain per workgroup): the four
+// waves' shuffle sums through LDS (gsr [2 parity][2 values][4 waves]), one
+// barrier per call; every call is made by the whole workgroup, whose control
+// flow is the chain's.
+template <int G>
+__device__ __forceinline__ void nuts_gsum2(double& a0, double& a1, double* gsr, int& gk) {
+    if constexpr (G <= 64) {
+        a0 = group_sum<G>(a0);
+        a1 = group_sum<G>(a1);
+    } else {
+        constexpr int NWG = G / 64;
+        a0 = group_sum<64>(a0);
+        a1 = group_sum<64>(a1);
+        double* slot = gsr + (gk & 1) * 2 * NWG;
+        if ((threadIdx.x & 63) == 0) {
+            slot[threadIdx.x >> 6] = a0;
+            slot[NWG + (threadIdx.x >> 6)] = a1;
+        }
+        __syncthreads();
+        a0 = 0.0;
+        a1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < NWG; ++q) {
+            a0 += slot[q];
+            a1 += slot[NWG + q];
+        }
+        ++gk;
+    }
+}
+
 // Logistic regression on the persistent path (GK = 1): one wavefront per
 // chain (G = 64, NB = 1: lane l holds dims 4 l .. 4 l + 3, D <= 4 LR_DQ), X
 // (FP32, rows padded to 4 DQ floats) and y staged once per workgroup in LDS
@@ -402,7 +433,7 @@ __host__ __device__ inline int64_t nuts_lr_lds_fixed(int64_t N, int64_t D) {
 }
 __host__ __device__ inline int nuts_lr_lds_levels(int64_t N, int64_t D) {
     const int64_t dp = 4 * ((D + 3) / 4);
-    const int64_t room = 163840 / 4 - nuts_lr_lds_fixed(N, D);
+    const int64_t room = 163840 / 4 - 16 - nuts_lr_lds_fixed(N, D);   // 64 bytes kept for static LDS
     const int64_t lv = room > 0 ? room / (4 * 4 * dp) : 0;
     return (int)(lv > 9 ? 9 : lv);
 }
@@ -420,6 +451,8 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                                                          int32_t* tr_depth, int32_t* tr_nleap, double* tr_stat) {
     const int64_t n_burnin = ad.n_burnin;
     extern __shared__ float lr_lds[];
+    __shared__ double gsr[G > 64 ? 2 * 2 * (G / 64) : 1];
+    int gk = 0;
     const int64_t NR = GK == 1 ? a.tg.N : 0;
     const int dq = GK == 1 ? (int)((a.tg.D + 3) / 4) : 0;
     const int dp = 4 * dq;
@@ -549,7 +582,8 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                 mr[b][e] = pr[b][e] = r0;
             }
         }
-        k0 = group_sum<G>(k0);
+        double k0_unused = 0.0;
+        nuts_gsum2<G>(k0, k0_unused, gsr, gk);
         const double h0 = -logp + k0;
         const double log_u = log(nuts_u52(a.key, (uint32_t)cc, t, 0u, TAG_NUTS_SLICE)) - (-logp + k0);
         double mlogp = logp, plogp = logp, ntot = 1.0;
@@ -605,11 +639,11 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                             if (ok[b][e]) lp += -0.5 * (double)wx[b][e] * (double)wx[b][e] * a.tg.inv_var;
                             kin += 0.5 * (double)wr[b][e] * (double)wr[b][e];
                         }
-                    lp = group_sum<G>(lp) + lpd;
+                    nuts_gsum2<G>(lp, kin, gsr, gk);
+                    lp += lpd;
                 } else {
-                    lp = group_sum<G>(lp);
+                    nuts_gsum2<G>(lp, kin, gsr, gk);
                 }
-                kin = group_sum<G>(kin);
                 wlogp = lp;
                 nleap += 1;
                 const double H = -lp + kin;
@@ -671,8 +705,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                                 dm += dx * (v > 0 ? fr : lr);
                                 dp += dx * (v > 0 ? lr : fr);
                             }
-                    dm = group_sum<G>(dm);
-                    dp = group_sum<G>(dp);
+                    nuts_gsum2<G>(dm, dp, gsr, gk);
                     first = k;
                     if (!(dm >= 0.0 && dp >= 0.0)) {
                         alive = false;
@@ -736,8 +769,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                         dm += dx * (double)mr[b][e];
                         dp += dx * (double)pr[b][e];
                     }
-                dm = group_sum<G>(dm);
-                dp = group_sum<G>(dp);
+                nuts_gsum2<G>(dm, dp, gsr, gk);
                 s = dm >= 0.0 && dp >= 0.0;
             }
         }
@@ -1242,7 +1274,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n,
 // the logistic persistent kernel: FP32 states and X, D <= 4 LR_DQ, X and y in LDS
 static bool nuts_lr_supported(const PlainArgs& a) {
     return a.tg.kind == HMC_TGT_LOGREG && !a.f64 && !a.tg.x_bf16 && !a.bf16_grad && a.tg.D >= 1 &&
-           a.tg.D <= 4 * LR_DQ && nuts_lr_lds_bytes(a.tg.N, a.tg.D) <= (size_t)ND_LDS_MAX;
+           a.tg.D <= 4 * LR_DQ && nuts_lr_lds_bytes(a.tg.N, a.tg.D) <= (size_t)ND_LDS_MAX - 64;
 }
 
 static int nuts_elem_shape(const PlainArgs& a, int* G) {
@@ -1254,6 +1286,7 @@ static int nuts_elem_shape(const PlainArgs& a, int* G) {
     if (nblk <= 16) { *G = 16; return 1; }
     if (nblk <= 64) { *G = 64; return 1; }
     if (nblk <= 128 && !a.f64) { *G = 64; return 2; }
+    if (nblk <= 256) { *G = 256; return 1; }      // one chain per workgroup
     return 0;
 }
 
@@ -1338,13 +1371,15 @@ hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, const NutsAdap
         if (G == 1) HMC_NUTS_F(double, 1, 1);
         else if (G == 4) HMC_NUTS_F(double, 4, 1);
         else if (G == 16) HMC_NUTS_F(double, 16, 1);
-        else HMC_NUTS_F(double, 64, 1);
+        else if (G == 64) HMC_NUTS_F(double, 64, 1);
+        else HMC_NUTS_F(double, 256, 1);
     } else {
         if (G == 1) HMC_NUTS_F(float, 1, 1);
         else if (G == 4) HMC_NUTS_F(float, 4, 1);
         else if (G == 16) HMC_NUTS_F(float, 16, 1);
-        else if (NB == 1) HMC_NUTS_F(float, 64, 1);
-        else HMC_NUTS_F(float, 64, 2);
+        else if (G == 64 && NB == 1) HMC_NUTS_F(float, 64, 1);
+        else if (G == 64) HMC_NUTS_F(float, 64, 2);
+        else HMC_NUTS_F(float, 256, 1);
     }
 #undef HMC_NUTS_F
     return hipGetLastError();

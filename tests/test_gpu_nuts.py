@@ -40,14 +40,16 @@ from paper_2002_01184_amd import hmc  # noqa: E402
 FORMS = {"lockstep": hmc.HMC_FORM_PLAIN, "persistent": hmc.HMC_FORM_AUTO}
 
 
-@pytest.mark.parametrize("case", ["std1", "diag5"])
+@pytest.mark.parametrize("case", ["std1", "diag5", "diag300"])
 @pytest.mark.parametrize("form", ["lockstep", "persistent"])
 def test_fp64_runs_match_oracle(case, form):
     if case == "std1":
         w = W.std_normal_1d(num_chains=64, step_size=0.5)
         w.x0 = np.random.default_rng(0).normal(size=(64, 1))
-    else:
+    elif case == "diag5":
         w = W.gauss_diag(dim=5, num_chains=48, step_size=0.3, state_dtype="f64", lam_lo=0.3, lam_hi=3.0)
+    else:       # 75 4-dim blocks: the persistent kernel runs one chain per workgroup
+        w = W.gauss_diag(dim=300, num_chains=10, step_size=0.15, state_dtype="f64", lam_lo=0.3, lam_hi=3.0)
     s = hmc.sampler_for(w, form=FORMS[form])
     g = s.nuts_sample_chain(40, 10, max_depth=6)
     s.close()
@@ -116,6 +118,7 @@ def test_nuts_errors():
 def _persistent_cases():
     return {
         "diag_300": W.gauss_diag(dim=300, num_chains=70, step_size=0.05),     # 64 lanes x 2 blocks per chain
+        "diag_1000": W.gauss_diag(dim=1000, num_chains=20, step_size=0.05),   # a workgroup per chain
         "dense_100": W.gauss_dense(dim=100, num_chains=80, step_size=0.1, seed=2),
         "dense_ragged_17x17": W.gauss_dense(dim=17, num_chains=17, step_size=0.2, seed=4),
         "dense_max_128": W.gauss_dense(dim=128, num_chains=33, step_size=0.05, seed=6),
