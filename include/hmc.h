@@ -274,11 +274,15 @@ hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale);
  * in the transition's last doubling (0 with max_depth 0) -- by dual averaging
  * (as in hmc_sample_chain: iteration m = burn-in transition m of this call;
  * the last burn-in transition sets the averaged iterate) or by the
- * multiplicative rule.  On a context of the fused form with an element-wise target (N(0, I),
- * diagonal Gaussian; D <= 256 in FP64, <= 512 in FP32) one persistent kernel
- * runs every transition with each chain's tree in its lanes' registers;
- * otherwise the chains run in lockstep on the plain kernels of the target and
- * a chain whose trajectory has stopped is masked.  Both build the same trees.
+ * multiplicative rule.  On a context of the fused form one persistent kernel
+ * runs every transition of the call where one covers the target: N(0, I) and
+ * the diagonal Gaussian up to D = 1024 (a lane group, or above 256 (FP64) /
+ * 512 (FP32) dims a workgroup, per chain); the dense Gaussian in FP32 up to
+ * D = 128 (16 chains per workgroup on MFMA, building their trees in
+ * lockstep); logistic regression with FP32 X and states, D <= 32 and X and y
+ * within the workgroup's LDS (N <= 1000 at D = 25; a wavefront per chain).
+ * Otherwise the chains run in lockstep on the plain kernels of the target and
+ * a chain whose trajectory has stopped is masked.  All build the same trees.
  * The context must have no inverse temperatures or transform
  * (HMC_E_UNSUPPORTED).
  * ------------------------------------------------------------------------- */
