@@ -206,17 +206,13 @@ hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char* report, s
  * (the tempered target of the paper: the log-probability times the inverse
  * temperature, by broadcasting); the replicas of one temperature ladder
  * 1 = beta_0 > beta_1 > ... hold the same beta in all M chains.  Tempering
- * runs on every form for the Gaussian targets and on the plain and graph
- * forms for logistic regression.
+ * runs on every form and target (on the fused form the exchange sampler
+ * launches one fused transition per exchange).
  * ------------------------------------------------------------------------- */
 
 /* Sets per-chain inverse temperatures: beta (device, FP64, [C]) is copied;
  * every value must be finite and > 0 (HMC_E_INVALID otherwise, nothing
- * changed).  NULL restores beta = 1 for every chain.  A fused-form context
- * of logistic regression returns HMC_E_UNSUPPORTED (create it with
- * HMC_FORM_PLAIN or HMC_FORM_GRAPH), and the autotuner keeps tempered
- * logistic contexts to the plain and graph forms.
- * The cached log-probability, traced target_log_prob and the state stay those
+ * changed).  NULL restores beta = 1 for every chain.  The cached log-probability, traced target_log_prob and the state stay those
  * of the untempered target.  Synchronizes the stream. */
 hmc_status hmc_set_inverse_temperature(hmc_ctx* ctx, const double* beta);
 

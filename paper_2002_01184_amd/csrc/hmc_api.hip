@@ -520,7 +520,7 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
         load_cache_locked();
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end() &&
-            !((ctx->a.ws.scale || ctx->a.ws.beta) && ctx->a.tg.kind == HMC_TGT_LOGREG &&
+            !(ctx->a.ws.scale && ctx->a.tg.kind == HMC_TGT_LOGREG &&
               it->second.form == HMC_FORM_FUSED)) {
             ctx->form = it->second.form;
             ctx->a.tune = it->second.tune;
@@ -533,8 +533,8 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
     std::vector<TuneChoice> cands;
     std::vector<int32_t> forms;
     if (ctx->cfg.form == HMC_FORM_AUTO) {
-        // transformed or tempered logistic contexts keep to the plain kernels
-        if (fused_supported(ctx->a) && !((ctx->a.ws.scale || ctx->a.ws.beta) && ctx->a.tg.kind == HMC_TGT_LOGREG))
+        // transformed logistic contexts keep to the plain kernels
+        if (fused_supported(ctx->a) && !(ctx->a.ws.scale && ctx->a.tg.kind == HMC_TGT_LOGREG))
             forms.push_back(HMC_FORM_FUSED);
         forms.push_back(HMC_FORM_PLAIN);
         forms.push_back(HMC_FORM_GRAPH);
@@ -628,10 +628,6 @@ hmc_status hmc_set_inverse_temperature(hmc_ctx* ctx, const double* beta) {
         drop_graph(ctx);
         return HMC_OK;
     }
-    if (ctx->form == HMC_FORM_FUSED && ctx->a.tg.kind == HMC_TGT_LOGREG)
-        return fail(HMC_E_UNSUPPORTED,
-                    "inverse temperatures on logistic regression run on the plain or graph form: create the "
-                    "context with HMC_FORM_PLAIN or HMC_FORM_GRAPH");
     std::vector<double> h((size_t)ctx->a.C);
     hmc_status st = check_hip(hipMemcpyAsync(h.data(), beta, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream),
                               "read inverse temperatures");
@@ -652,8 +648,6 @@ static hmc_status remc_check(const hmc_ctx* ctx, int64_t num_replicas) {
     if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
     if (num_replicas < 1 || ctx->a.C % num_replicas != 0)
         return fail(HMC_E_INVALID, "num_replicas must be >= 1 and divide the number of chains");
-    if (ctx->form == HMC_FORM_FUSED && ctx->a.tg.kind == HMC_TGT_LOGREG)
-        return fail(HMC_E_UNSUPPORTED, "replica exchange on logistic regression runs on the plain or graph form");
     return HMC_OK;
 }
 

@@ -180,7 +180,9 @@ __device__ __forceinline__ double exp_lds(double x, const double* cf) {
     return ldexp(s, (int)k);
 }
 
-template <int TPW, int QQ, typename XT>
+// TP: the chains carry inverse temperatures (a template parameter, so that
+// untempered runs compile without them).
+template <int TPW, int QQ, typename XT, bool TP>
 __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) {
     extern __shared__ float lds[];
     constexpr int NW = LR_NW, PS = LR_PS, ZT = LR_ZT, UT = LR_UT;
@@ -275,6 +277,11 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     // step size of the owner's chain in FP32; half steps are eps / 2 (halving
     // commutes with rounding to float)
     float eps = owner ? (float)a.ws.eps[occ] : 0.f;
+    // inverse temperature of the owner's chain (replica exchange): it scales
+    // every kick (keps = beta eps) and both energies
+    const double btd = (TP && owner) ? a.ws.beta[occ] : 1.0;
+    float keps = TP ? (owner ? (float)(a.ws.eps[occ] * btd) : 0.f) : 0.f;
+    auto kick_eps = [&]() -> float { return TP ? keps : eps; };
     if (owner && od == 0 && oc < C) cst[oi] = ChainSt{a.ws.logp[oc], a.ws.eps[oc], a.ws.da[oc]};
     if (threadIdx.x == 0)
         *optr = OutPtrs{(gptr<float>)r.samples,          (gptr<double>)r.trace.step_size,
@@ -387,7 +394,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
                 gs = v[0];
             }
             gq = gs - thq * inv_var;
-            p = fmaf(LAST ? 0.5f * eps : eps, gq, p);
+            p = fmaf(LAST ? 0.5f * kick_eps() : kick_eps(), gq, p);
         }
     };
 
@@ -397,7 +404,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
             const float z = ovalid ? zb[((int)(itr % ZT) * 4 + oi) * 32 + od] : 0.f;
             dk = -0.5 * (double)z * (double)z;
             thq = th0;
-            p = fmaf(0.5f * eps, g0, z);
+            p = fmaf(0.5f * kick_eps(), g0, z);
         }
         for (int l = 0; l + 1 < a.L; ++l) step(std::false_type{});
         step(std::true_type{});
@@ -415,7 +422,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
 #pragma unroll
             for (int ww = 0; ww < NW; ++ww) lpdata += lpp[ww * 4 + oi];
             const double lp1 = lpdata + prior;
-            const double dh = -lp1 + cs.logp + dk;
+            const double dh = TP ? -(btd * lp1) + btd * cs.logp + dk : -lp1 + cs.logp + dk;
             const double lar = log_accept_ratio_of(dh);
             const bool acc = lub[(hb * UT + ku) * 4 + oi] < lar;
             if (acc) {
@@ -444,6 +451,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
                     }
                 }
                 eps = (float)cs.eps;
+                if (TP) keps = (float)(cs.eps * btd);
                 if (od == 0) {
                     if (itr >= r.n_burnin) {
                         const int64_t k = (itr - r.n_burnin) * C + oc;
@@ -491,7 +499,10 @@ template <int TPW, int QQ, typename XT>
 static hipError_t launch_lr4(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     const size_t lds = logreg4_lds(TPW);
     const dim3 grid((unsigned)((a.C + 3) / 4));
-    hipLaunchKernelGGL((k_fused_logreg4<TPW, QQ, XT>), grid, dim3(64 * LR_NW), lds, s, a, r);
+    if (a.ws.beta)
+        hipLaunchKernelGGL((k_fused_logreg4<TPW, QQ, XT, true>), grid, dim3(64 * LR_NW), lds, s, a, r);
+    else
+        hipLaunchKernelGGL((k_fused_logreg4<TPW, QQ, XT, false>), grid, dim3(64 * LR_NW), lds, s, a, r);
     return hipGetLastError();
 }
 

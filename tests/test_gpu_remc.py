@@ -93,8 +93,6 @@ def _tempered_cases():
 @pytest.mark.parametrize("form", ["plain", "fused"])
 def test_tempered_one_step_parity(name, form):
     w, K = _tempered_cases()[name]
-    if form == "fused" and w.kind == W.LOGREG:
-        pytest.skip("tempered logistic regression runs on the plain and graph forms")
     M = w.num_chains // K
     betas = [0.9 ** (3 * k) for k in range(K)]
     s = hmc.sampler_for(w, form=FORMS[form])
@@ -141,9 +139,13 @@ def test_exchange_step_matches_oracle_exactly_fp64():
     s.close()
 
 
+@pytest.mark.parametrize("target", ["dense", "logreg"])
 @pytest.mark.parametrize("form", ["plain", "fused"])
-def test_unit_temperatures_are_bitwise_the_untempered_run(form):
-    w = W.gauss_dense(dim=30, num_chains=64, L=8, step_size=0.15, seed=1)
+def test_unit_temperatures_are_bitwise_the_untempered_run(form, target):
+    if target == "dense":
+        w = W.gauss_dense(dim=30, num_chains=64, L=8, step_size=0.15, seed=1)
+    else:
+        w = W.logreg(300, 12, 64, L=6, step_size=0.05, seed=2)
     a = hmc.sampler_for(w, form=FORMS[form])
     ra = a.sample_chain(6, 4)
     a.close()
@@ -157,16 +159,31 @@ def test_unit_temperatures_are_bitwise_the_untempered_run(form):
 
 def test_temperature_errors():
     w = W.logreg(200, 9, 96, L=5, step_size=0.05, seed=4)
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_AUTO)     # fused-capable shape
-    if hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED:
-        with pytest.raises(hmc.HMCError, match="plain or graph"):
-            s.set_inverse_temperature(torch.ones(96, dtype=torch.float64, device="cuda"))
-        with pytest.raises(hmc.HMCError):
-            s.remc_sample_chain(4, 2, 0)
-    s.close()
     p = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
     with pytest.raises(hmc.HMCError, match="finite and > 0"):
         p.set_inverse_temperature(torch.zeros(96, dtype=torch.float64, device="cuda"))
     with pytest.raises(hmc.HMCError, match="divide"):
         p.remc_sample_chain(5, 2, 0)
     p.close()
+
+
+def test_fused_and_plain_logistic_exchange_agree_in_distribution():
+    # the fused logistic kernel takes temperatures: a whole exchange run on both forms,
+    # compared through the beta = 1 replica's posterior mean and the exchange rate
+    K, M = 3, 128
+    w = W.logreg(200, 5, K * M, L=8, step_size=0.08, seed=11)
+    betas = [1.0, 0.7, 0.5]
+    out = {}
+    for form in ("plain", "fused"):
+        s = hmc.sampler_for(w, form=FORMS[form])
+        assert hmc.hmc_effective_form(s.ctx) == FORMS[form]
+        s.set_inverse_temperature(_betas_per_chain(betas, M))
+        out[form] = s.remc_sample_chain(K, 200, 100, adapt=True)
+        s.close()
+    m = {f: to_np(out[f]["samples"])[:, :M].reshape(-1, 5).mean(0) for f in out}
+    sd = to_np(out["plain"]["samples"])[:, :M].reshape(-1, 5).std(0)
+    assert np.all(np.abs(m["fused"] - m["plain"]) < 0.1 * sd + 1e-3), (m, sd)
+    rates = {f: to_np(out[f]["swapped"]).mean() for f in out}
+    assert abs(rates["fused"] - rates["plain"]) < 0.05, rates
+    accs = {f: to_np(out[f]["is_accepted"]).mean() for f in out}
+    assert abs(accs["fused"] - accs["plain"]) < 0.05, accs
