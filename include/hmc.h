@@ -243,12 +243,12 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
  * with identity mass against the pulled-back target and reports x.  Run in
  * x, scale_d multiplies the step size in the drift and in the kick of
  * dimension d (a diagonal preconditioner); the shift drops out of the
- * dynamics.  The fused Gaussian kernels run in z = x / scale instead, with
- * the precision pulled back (prec scale^2, S P S); they agree with the plain
- * form to rounding.  scale (device, FP64, [D]) is copied; every value finite
- * and > 0.  NULL restores the identity.  All forms for the Gaussian targets,
- * plain and graph for the logistic one, FP32 gradients (HMC_E_UNSUPPORTED
- * otherwise).  Synchronizes the stream. */
+ * dynamics.  The fused kernels run in z = x / scale instead, with the
+ * target pulled back (prec scale^2, S P S; logistic: X S and the prior's
+ * precision times scale^2); they agree with the plain form to rounding.
+ * scale (device, FP64, [D]) is copied; every value finite and > 0.  NULL
+ * restores the identity.  All forms and targets with FP32 gradients
+ * (HMC_E_UNSUPPORTED with BF16 gradients).  Synchronizes the stream. */
 hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale);
 
 /* ---------------------------------------------------------------------------

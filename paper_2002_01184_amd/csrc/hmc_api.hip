@@ -519,9 +519,7 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache_locked();
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end() &&
-            !(ctx->a.ws.scale && ctx->a.tg.kind == HMC_TGT_LOGREG &&
-              it->second.form == HMC_FORM_FUSED)) {
+        if (it != g_tune_cache.end()) {
             ctx->form = it->second.form;
             ctx->a.tune = it->second.tune;
             drop_graph(ctx);
@@ -533,8 +531,7 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
     std::vector<TuneChoice> cands;
     std::vector<int32_t> forms;
     if (ctx->cfg.form == HMC_FORM_AUTO) {
-        // transformed logistic contexts keep to the plain kernels
-        if (fused_supported(ctx->a) && !(ctx->a.ws.scale && ctx->a.tg.kind == HMC_TGT_LOGREG))
+        if (fused_supported(ctx->a))
             forms.push_back(HMC_FORM_FUSED);
         forms.push_back(HMC_FORM_PLAIN);
         forms.push_back(HMC_FORM_GRAPH);
@@ -781,8 +778,9 @@ extern "C" hmc_status hmc_sample_chain_moments(hmc_ctx* ctx, int64_t num_results
 // Transformed kernel (paper Sec. 4.1) with the diagonal affine bijector
 // x = shift + scale z.  The plain kernels run in x: the momentum lives in z,
 // so scale multiplies the momentum in every drift and the gradient in every
-// kick (the shift drops out).  The fused Gaussian kernels run in z = x / scale
-// against the pulled-back precision.  FP32 gradients.
+// kick (the shift drops out).  The fused kernels run in z = x / scale against
+// the pulled-back target (precision S P S; logistic: X S and the prior's
+// precision scaled per dim).  FP32 gradients.
 // ---------------------------------------------------------------------------
 extern "C" hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale) {
     if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
@@ -791,10 +789,6 @@ extern "C" hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale)
         drop_graph(ctx);
         return HMC_OK;
     }
-    if (ctx->form == HMC_FORM_FUSED && ctx->a.tg.kind == HMC_TGT_LOGREG)
-        return fail(HMC_E_UNSUPPORTED,
-                    "the transformed logistic target runs on the plain or graph form: create the context with "
-                    "HMC_FORM_PLAIN or HMC_FORM_GRAPH");
     if (ctx->a.bf16_grad) return fail(HMC_E_UNSUPPORTED, "the transformed kernel needs FP32 gradients");
     std::vector<double> h((size_t)ctx->a.tg.D);
     hmc_status st = check_hip(hipMemcpyAsync(h.data(), scale, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream),

@@ -593,8 +593,6 @@ hipError_t launch_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     case HMC_TGT_GAUSS_DENSE:
         return launch_dense_fused(a, r, s);
     case HMC_TGT_LOGREG:
-        // the fused logistic kernel takes temperatures but no transform
-        if (a.ws.scale) return hipErrorNotSupported;
         return launch_fused_logreg(a, r, s);
     }
     return hipErrorNotSupported;

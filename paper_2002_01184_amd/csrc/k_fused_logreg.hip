@@ -180,8 +180,12 @@ __device__ __forceinline__ double exp_lds(double x, const double* cf) {
     return ldexp(s, (int)k);
 }
 
-// TP: the chains carry inverse temperatures (a template parameter, so that
-// untempered runs compile without them).
+// TP: the chains carry inverse temperatures and / or the context a transform
+// (a template parameter, so that plain runs compile without either).  The
+// transformed kernel (x = shift + scale z) runs in z: X scaled by column
+// where it is loaded into VGPRs (X S), the prior's precision inv_var scale^2
+// per dim, states divided by scale at load and multiplied back where x is
+// stored.
 template <int TPW, int QQ, typename XT, bool TP>
 __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) {
     extern __shared__ float lds[];
@@ -204,10 +208,13 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
 
     // ---- X and y of this wave's tiles, in the two operand layouts, kept in VGPRs ----
     const XT* X = (const XT*)a.tg.X;
+    const double* sc = TP ? a.ws.scale : nullptr;
     auto ldx = [&](int64_t row, int64_t d) -> float {
         if (row >= N || d >= D) return 0.f;
-        if constexpr (sizeof(XT) == 2) return bf16_to_f32(((const uint16_t*)X)[row * D + d]);
-        else return ((const float*)X)[row * D + d];
+        float v;
+        if constexpr (sizeof(XT) == 2) v = bf16_to_f32(((const uint16_t*)X)[row * D + d]);
+        else v = ((const float*)X)[row * D + d];
+        return sc ? (float)((double)v * sc[d]) : v;
     };
     float xa[TPW][4 * QQ];     // first contraction: X[row0 + lane][d]
     float xb[TPW][4][QQ];      // second contraction: X[row0 + 4 b16 + v][4 q + q4]
@@ -274,12 +281,19 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     float* Gw = (float*)a.ws.g;
     float th0 = ovalid ? Xw[occ * D + od] : 0.f;
     float g0 = ovalid ? Gw[occ * D + od] : 0.f;
+    // transform: this owner's scale and prior precision in z
+    const double sod = (sc && ovalid) ? sc[od] : 1.0;
+    const float pv_z = sc ? (float)((double)inv_var * sod * sod) : inv_var;
+    if (sc && ovalid) {
+        th0 = (float)((double)th0 / sod);
+        g0 = (float)((double)g0 * sod);
+    }
     // step size of the owner's chain in FP32; half steps are eps / 2 (halving
     // commutes with rounding to float)
     float eps = owner ? (float)a.ws.eps[occ] : 0.f;
     // inverse temperature of the owner's chain (replica exchange): it scales
     // every kick (keps = beta eps) and both energies
-    const double btd = (TP && owner) ? a.ws.beta[occ] : 1.0;
+    const double btd = (TP && owner && a.ws.beta) ? a.ws.beta[occ] : 1.0;
     float keps = TP ? (owner ? (float)(a.ws.eps[occ] * btd) : 0.f) : 0.f;
     auto kick_eps = [&]() -> float { return TP ? keps : eps; };
     if (owner && od == 0 && oc < C) cst[oi] = ChainSt{a.ws.logp[oc], a.ws.eps[oc], a.ws.da[oc]};
@@ -393,7 +407,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
                     for (int k = 0; k < hh; ++k) v[k] = v[2 * k] + v[2 * k + 1];
                 gs = v[0];
             }
-            gq = gs - thq * inv_var;
+            gq = gs - thq * (TP ? pv_z : inv_var);
             p = fmaf(LAST ? 0.5f * kick_eps() : kick_eps(), gq, p);
         }
     };
@@ -414,7 +428,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
             // energy change and decision (the 32 lanes of a chain agree bitwise)
             const int hb = (int)((itr / UT) & 1), ku = (int)(itr % UT);
             ChainSt cs = cst[oi];
-            double prior = ovalid ? -0.5 * (double)thq * (double)thq * a.tg.inv_var : 0.0;
+            double prior = ovalid ? -0.5 * (double)thq * (double)thq * a.tg.inv_var * (TP ? sod * sod : 1.0) : 0.0;
             dk += ovalid ? 0.5 * (double)p * (double)p : 0.0;
             dk = half_wave_sum(dk);
             prior = half_wave_sum(prior);
@@ -433,8 +447,9 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
             if (oc < C) {
                 const OutPtrs o = *optr;
                 if (ovalid) {
-                    if (o.samples && itr >= r.n_burnin) o.samples[((itr - r.n_burnin) * C + oc) * D + od] = th0;
-                    if (o.ps) o.ps[oc * D + od] = thq;
+                    if (o.samples && itr >= r.n_burnin)
+                        o.samples[((itr - r.n_burnin) * C + oc) * D + od] = TP && sc ? (float)((double)th0 * sod) : th0;
+                    if (o.ps) o.ps[oc * D + od] = TP && sc ? (float)((double)thq * sod) : thq;
                     if (o.pm) o.pm[oc * D + od] = p;
                 }
                 const double eps_used = cs.eps;
@@ -475,8 +490,8 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
         if (refill_z) __syncthreads();
     }
     if (ovalid) {
-        Xw[oc * D + od] = th0;
-        Gw[oc * D + od] = g0;
+        Xw[oc * D + od] = TP && sc ? (float)((double)th0 * sod) : th0;
+        Gw[oc * D + od] = TP && sc ? (float)((double)g0 / sod) : g0;
     }
     if (owner && od == 0 && oc < C) {
         const ChainSt cs = cst[oi];
@@ -499,7 +514,7 @@ template <int TPW, int QQ, typename XT>
 static hipError_t launch_lr4(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     const size_t lds = logreg4_lds(TPW);
     const dim3 grid((unsigned)((a.C + 3) / 4));
-    if (a.ws.beta)
+    if (a.ws.beta || a.ws.scale)
         hipLaunchKernelGGL((k_fused_logreg4<TPW, QQ, XT, true>), grid, dim3(64 * LR_NW), lds, s, a, r);
     else
         hipLaunchKernelGGL((k_fused_logreg4<TPW, QQ, XT, false>), grid, dim3(64 * LR_NW), lds, s, a, r);

@@ -51,13 +51,7 @@ def _cases():
 
 
 def _form_cases():
-    # the fused form takes the transform for the Gaussian targets
-    out = []
-    for name in _cases():
-        out.append((name, "plain"))
-        if not name.startswith("logreg"):
-            out.append((name, "fused"))
-    return out
+    return [(name, form) for name in _cases() for form in ("plain", "fused")]
 
 
 @pytest.mark.parametrize("name,form", _form_cases())
@@ -91,6 +85,7 @@ def _unit_cases():
         "dense_fused": (W.gauss_dense(dim=37, num_chains=45, L=7, step_size=0.1, seed=3), hmc.HMC_FORM_FUSED),
         "diag_fused": (W.gauss_diag(dim=101, num_chains=40, L=6, step_size=0.08), hmc.HMC_FORM_FUSED),
         "std_fp64_fused": (W.std_normal_1d(), hmc.HMC_FORM_FUSED),
+        "logreg_fused": (W.logreg(300, 12, 48, L=6, step_size=0.05, seed=2), hmc.HMC_FORM_FUSED),
     }
 
 
@@ -126,12 +121,24 @@ def test_whitening_speeds_up_an_ill_conditioned_gaussian(form):
 
 def test_transform_errors():
     w = W.logreg(200, 9, 96, L=5, step_size=0.05, seed=4)
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_AUTO)
-    if hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED:
-        with pytest.raises(hmc.HMCError, match="plain or graph"):
-            s.set_transform_scale(np.ones(9))
-    s.close()
     p = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
     with pytest.raises(hmc.HMCError, match="finite and > 0"):
         p.set_transform_scale(-np.ones(9))
     p.close()
+
+
+def test_fused_transformed_logistic_agrees_with_plain_in_distribution():
+    # whole transformed runs of the fused (z-space) and plain (x-space) logistic kernels
+    w = W.logreg(200, 5, 256, L=8, step_size=0.1, seed=12)
+    scale = np.array([0.5, 2.0, 1.0, 0.8, 1.5])
+    out = {}
+    for form in (hmc.HMC_FORM_PLAIN, hmc.HMC_FORM_FUSED):
+        s = hmc.sampler_for(w, form=form)
+        assert hmc.hmc_effective_form(s.ctx) == form
+        s.set_transform_scale(scale)
+        out[form] = to_np(s.sample_chain(200, 100, adapt=True)["samples"]).reshape(-1, 5)
+        s.close()
+    m_p, m_f = out[hmc.HMC_FORM_PLAIN].mean(0), out[hmc.HMC_FORM_FUSED].mean(0)
+    sd = out[hmc.HMC_FORM_PLAIN].std(0)
+    assert np.all(np.abs(m_f - m_p) < 0.1 * sd + 1e-3), (m_p, m_f, sd)
+    assert np.allclose(out[hmc.HMC_FORM_FUSED].std(0), sd, rtol=0.1)
