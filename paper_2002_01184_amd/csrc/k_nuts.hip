@@ -831,7 +831,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
 // Same tree, uniforms and arithmetic order per lane as the lockstep kernels
 // up to the order of the FP64 sums.
 // ---------------------------------------------------------------------------
-constexpr int ND_NW = 4;
+constexpr int ND_NW = 8;                    // waves per workgroup (2 per SIMD)
 constexpr int ND_LDS_MAX = 163840;          // LDS bytes of a gfx950 workgroup
 constexpr int ND_RV = 2;                    // values per chain in one reduction
 
@@ -875,7 +875,7 @@ __device__ __forceinline__ void nd_chain_sum(double* sv, double* red, int& rk, i
 }
 
 template <int NT, bool ST>
-__global__ __launch_bounds__(256) void k_nuts_fused_dense(PlainArgs a, NutsWs n, NutsAdapt ad, uint32_t t_begin,
+__global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, NutsWs n, NutsAdapt ad, uint32_t t_begin,
                                                           int64_t n_trans, int32_t max_depth, float* samples,
                                                           int32_t* tr_depth, int32_t* tr_nleap, double* tr_stat) {
     constexpr int MT = (NT + ND_NW - 1) / ND_NW;
@@ -1314,13 +1314,13 @@ static hipError_t launch_nuts_dense(const PlainArgs& a, const NutsWs& n, const N
             if (lds > 65536)                                                                                        \
                 (void)hipFuncSetAttribute((const void*)k_nuts_fused_dense<N, true>,                                 \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
-            hipLaunchKernelGGL((k_nuts_fused_dense<N, true>), grid, dim3(256), lds, s, a, n, ad, t_begin, n_trans,  \
+            hipLaunchKernelGGL((k_nuts_fused_dense<N, true>), grid, dim3(64 * ND_NW), lds, s, a, n, ad, t_begin, n_trans,  \
                                max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);                            \
         } else {                                                                                                    \
             if (lds > 65536)                                                                                        \
                 (void)hipFuncSetAttribute((const void*)k_nuts_fused_dense<N, false>,                                \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
-            hipLaunchKernelGGL((k_nuts_fused_dense<N, false>), grid, dim3(256), lds, s, a, n, ad, t_begin, n_trans, \
+            hipLaunchKernelGGL((k_nuts_fused_dense<N, false>), grid, dim3(64 * ND_NW), lds, s, a, n, ad, t_begin, n_trans, \
                                max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);                            \
         }                                                                                                           \
         break;                                                                                                      \
