@@ -237,8 +237,9 @@ __global__ __launch_bounds__(256) void k_fused_elem_multi(const ElemJob* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Dense Gaussian on MFMA.  16 chains per workgroup (the N dimension), wave w
-// owns M-tiles w, w + NW, ...; lane (g4 = lane/16, i16 = lane%16) holds rows
+// Dense Gaussian on MFMA.  16 chains per workgroup (the N dimension), 8 waves
+// (two per SIMD, so that one wave's MFMAs cover the other's LDS and barrier
+// waits), wave w owns M-tiles w, w + NW, ...; lane (g4 = lane/16, i16 = lane%16) holds rows
 // 16 mt + 4 g4 + v (v = 0..3) of chain i16 -- exactly the 4 dims of Philox
 // block 4 mt + g4, so each lane draws its own momenta.
 //
@@ -256,10 +257,10 @@ __global__ __launch_bounds__(256) void k_fused_elem_multi(const ElemJob* __restr
 // consecutive k-steps with one ds_read_b128 and writes its own 4 dims of a
 // tile with one ds_write_b128.
 // ---------------------------------------------------------------------------
-constexpr int DENSE_NW = 4;
+constexpr int DENSE_NW = 8;                 // waves per workgroup (2 per SIMD)
 
 template <int NT, bool TR>
-__global__ __launch_bounds__(256) void k_fused_dense(PlainArgs a, FusedRun r) {
+__global__ __launch_bounds__(64 * DENSE_NW) void k_fused_dense(PlainArgs a, FusedRun r) {
     constexpr int MT = (NT + DENSE_NW - 1) / DENSE_NW;
     constexpr int KM = 4 * NT;
     extern __shared__ float lds[];
@@ -574,8 +575,8 @@ static hipError_t launch_dense_fused(const PlainArgs& a, const FusedRun& r, hipS
     switch (ntiles) {
 #define HMC_DENSE_NT(N)                                                                   \
     case N:                                                                               \
-        if (a.ws.scale) hipLaunchKernelGGL((k_fused_dense<N, true>), grid, dim3(256), lds, s, a, r); \
-        else hipLaunchKernelGGL((k_fused_dense<N, false>), grid, dim3(256), lds, s, a, r);            \
+        if (a.ws.scale) hipLaunchKernelGGL((k_fused_dense<N, true>), grid, dim3(64 * DENSE_NW), lds, s, a, r); \
+        else hipLaunchKernelGGL((k_fused_dense<N, false>), grid, dim3(64 * DENSE_NW), lds, s, a, r);            \
         break;
         HMC_DENSE_NT(1) HMC_DENSE_NT(2) HMC_DENSE_NT(3) HMC_DENSE_NT(4)
         HMC_DENSE_NT(5) HMC_DENSE_NT(6) HMC_DENSE_NT(7) HMC_DENSE_NT(8)
