@@ -206,7 +206,8 @@ def bench_remc(args):
                    "num_leapfrog_steps": w.num_leapfrog_steps, "num_burnin": w.num_burnin,
                    "num_results": w.num_results, "adapt": "dual averaging to 0.8" if w.adapt else "none",
                    "form": {hmc.HMC_FORM_PLAIN: "plain", hmc.HMC_FORM_GRAPH: "graph",
-                            hmc.HMC_FORM_FUSED: "fused (one launch per transition)"}[hmc.hmc_effective_form(s.ctx)],
+                            hmc.HMC_FORM_FUSED: ("fused (exchanges inside one launch)" if w.kind == W.GAUSS_DENSE and 16 % K == 0
+                                                  else "fused (one launch per transition)")}[hmc.hmc_effective_form(s.ctx)],
                    "parallelism": "chains (1 GPU)"},
         "roofline": {"bound": bound, "achieved": achieved / scale, "peak": peak / scale,
                      "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak, "traffic": None,

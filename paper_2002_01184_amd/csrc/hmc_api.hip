@@ -673,6 +673,26 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
     memset(&tr, 0, sizeof(tr));
     if (trace) tr = *trace;
     if (ad) st = check_hip(launch_da_init(ctx->a, ctx->stream), "adaptation init");
+    if (ctx->form == HMC_FORM_FUSED && ctx->a.tg.kind == HMC_TGT_GAUSS_DENSE && num_replicas > 1 &&
+        16 % num_replicas == 0) {
+        // dense Gaussian: every replica of a chain index in one workgroup of the fused kernel, which
+        // exchanges between transitions itself -- one launch for the whole run
+        FusedRun r;
+        memset(&r, 0, sizeof(r));
+        r.t_begin = ctx->t;
+        r.n_transitions = total;
+        r.n_burnin = num_burnin_steps;
+        r.adapt_total = num_burnin_steps;
+        set_adapt(r, adapt);
+        r.samples = samples;
+        r.trace = tr;
+        r.remc_K = (int32_t)num_replicas;
+        r.remc_M = M;
+        r.swapped = swapped;
+        if (st == HMC_OK && total > 0) st = check_hip(launch_fused(ctx->a, r, ctx->stream), "fused replica exchange");
+        if (st == HMC_OK) ctx->t += (uint64_t)total;
+        return st;
+    }
     if (ctx->form == HMC_FORM_FUSED) {
         // one fused launch per transition (its trace row), then the exchange, which writes the kept sample row
         for (int64_t i = 0; i < total && st == HMC_OK; ++i) {

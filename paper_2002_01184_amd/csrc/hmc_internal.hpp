@@ -157,6 +157,13 @@ struct FusedRun {
     void* samples;
     hmc_trace trace;
     hmc_step_out out;        // only for single-transition launches
+    // replica exchange inside the launch (dense kernel; 0: none): remc_K
+    // replicas of remc_M chains (chain k M + m), all replicas of one m in one
+    // workgroup; after each transition the pairs of its parity exchange, and
+    // the kept transitions' flags go to swapped [R, C]
+    int32_t remc_K;
+    int64_t remc_M;
+    uint8_t* swapped;
 };
 // Adaptation parameters of an hmc_adapt (NULL or disabled: none) into a
 // plain-path control block or a fused run.

@@ -259,7 +259,12 @@ __global__ __launch_bounds__(256) void k_fused_elem_multi(const ElemJob* __restr
 // ---------------------------------------------------------------------------
 constexpr int DENSE_NW = 8;                 // waves per workgroup (2 per SIMD)
 
-template <int NT, bool TR>
+// EX: a transform and / or the replica exchange inside the launch (a template
+// parameter, so that plain runs carry neither).  With the exchange, slot i16
+// of the workgroup holds replica i16 % K of chain m = 16 / K * block + i16 / K,
+// so the two chains of every pair sit in neighbouring lanes of one wavefront
+// and exchange by shuffles.
+template <int NT, bool EX>
 __global__ __launch_bounds__(64 * DENSE_NW) void k_fused_dense(PlainArgs a, FusedRun r) {
     constexpr int MT = (NT + DENSE_NW - 1) / DENSE_NW;
     constexpr int KM = 4 * NT;
@@ -268,8 +273,11 @@ __global__ __launch_bounds__(64 * DENSE_NW) void k_fused_dense(PlainArgs a, Fuse
     const int ntiles = NT;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i16 = lane & 15, g4 = lane >> 4;
-    const int64_t c = (int64_t)blockIdx.x * 16 + i16;
-    const bool cvalid = c < a.C;
+    const int nrep = EX ? r.remc_K : 0;
+    const int krep = nrep > 1 ? i16 % nrep : 0;
+    const int64_t mrep = nrep > 1 ? (int64_t)blockIdx.x * (16 / nrep) + i16 / nrep : 0;
+    const int64_t c = nrep > 1 ? krep * r.remc_M + mrep : (int64_t)blockIdx.x * 16 + i16;
+    const bool cvalid = nrep > 1 ? mrep < r.remc_M : c < a.C;
     const int64_t cc = cvalid ? c : 0;
     constexpr int XS = 16 * NT + 4;                 // floats per chain row in LDS
     float* xs0 = lds;                               // [16][XS] x 2 buffers
@@ -279,13 +287,15 @@ __global__ __launch_bounds__(64 * DENSE_NW) void k_fused_dense(PlainArgs a, Fuse
     float* X = (float*)a.ws.x;
     float* Gr = (float*)a.ws.g;
 
-    // Transformed kernel (x = shift + scale z, TR): the chain runs in
+    // Transformed kernel (x = shift + scale z, EX): the chain runs in
     // z = x / scale, whose precision matrix is S P S (S = diag(scale)); states
     // are converted at load and store.
-    const double* sc = TR ? a.ws.scale : nullptr;
-    __shared__ float sc_lds[TR ? 16 * NT : 1];     // the scale, for the stores of x
-    if (TR) {
-        for (int d = threadIdx.x; d < D; d += blockDim.x) sc_lds[d] = (float)sc[d];
+    const double* sc = EX ? a.ws.scale : nullptr;
+    const bool trs = sc != nullptr;
+    __shared__ float sc_lds[EX ? 16 * NT : 1];     // the scale, for the stores of x
+    if (EX) {
+        if (trs)
+            for (int d = threadIdx.x; d < D; d += blockDim.x) sc_lds[d] = (float)sc[d];
         __syncthreads();
     }
     // P as A operands: pa[m][ks] = P[16 mt + i16][g4 KM + ks]
@@ -423,28 +433,59 @@ __global__ __launch_bounds__(64 * DENSE_NW) void k_fused_dense(PlainArgs a, Fuse
                 }
             s.logp = lp;
         }
+        // traces and adaptation record the transition; the exchange follows it,
+        // and the kept sample is the state after the exchange
+        if (cvalid) after_decision(r, a.C, c, i, acc, lar, dh, s.logp, s, w == 0 && g4 == 0);
+        if (EX && nrep > 1) {
+            const int par = (int)(t & 1u);
+            const bool a_side = krep >= par && ((krep - par) & 1) == 0 && krep + 1 < nrep;
+            const bool b_side = krep >= par + 1 && ((krep - 1 - par) & 1) == 0;
+            const int src = a_side ? lane + 1 : (b_side ? lane - 1 : lane);
+            const double lp_o = __shfl(s.logp, src, 64);
+            const double bt_o = __shfl(bt, src, 64);
+            bool swp = false;
+            if (cvalid && (a_side || b_side)) {
+                const int64_t ca = a_side ? c : c - r.remc_M;
+                const double la = a_side ? s.logp : lp_o, lb = a_side ? lp_o : s.logp;
+                const double ba = a_side ? bt : bt_o, bb = a_side ? bt_o : bt;
+                swp = log_uniform52(a.key, (uint32_t)ca, t, TAG_SWAP) < (ba - bb) * (lb - la);
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float xo = __shfl(x[m][v], src, 64), go = __shfl(g[m][v], src, 64);
+                    if (swp) {
+                        x[m][v] = xo;
+                        g[m][v] = go;
+                    }
+                }
+            if (swp) s.logp = lp_o;
+            if (cvalid && r.swapped && i >= r.n_burnin && w == 0 && g4 == 0)
+                r.swapped[(i - r.n_burnin) * a.C + c] = swp ? 1 : 0;
+        }
         if (cvalid) {
             const bool want_smp = r.samples && i >= r.n_burnin;
             int q = 16 * w + 4 * g4;                 // opaque: keeps the LDS reads of the scale here
-            if (TR) asm volatile("" : "+v"(q));
+            if (EX) asm volatile("" : "+v"(q));
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     if (ok[m][v]) {
                         const int64_t d = 16 * (w + DENSE_NW * m) + 4 * g4 + v;
-                        const float sd = TR ? sc_lds[q + 16 * DENSE_NW * m + v] : 1.f;
+                        const float sd = (EX && trs) ? sc_lds[q + 16 * DENSE_NW * m + v] : 1.f;
                         if (want_smp)
-                            ((float*)r.samples)[((i - r.n_burnin) * a.C + c) * D + d] = TR ? x[m][v] * sd : x[m][v];
+                            ((float*)r.samples)[((i - r.n_burnin) * a.C + c) * D + d] =
+                                (EX && trs) ? x[m][v] * sd : x[m][v];
                         if (r.out.proposed_state)
-                            ((float*)r.out.proposed_state)[c * D + d] = TR ? xn[m][v] * sd : xn[m][v];
+                            ((float*)r.out.proposed_state)[c * D + d] = (EX && trs) ? xn[m][v] * sd : xn[m][v];
                         if (r.out.proposed_momentum) ((float*)r.out.proposed_momentum)[c * D + d] = pn[m][v];
                     }
-            after_decision(r, a.C, c, i, acc, lar, dh, s.logp, s, w == 0 && g4 == 0);
         }
     }
     if (!cvalid) return;
-    if (TR) asm volatile("" ::: "memory");   // a fresh read of the scale (see the element-wise kernel)
+    if (EX) asm volatile("" ::: "memory");   // a fresh read of the scale (see the element-wise kernel)
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -571,11 +612,15 @@ hipError_t launch_fused_elem_multi(int cls, const ElemJob* jobs_dev, int njobs, 
 static hipError_t launch_dense_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     const int ntiles = (int)((a.tg.D + 15) / 16);
     const size_t lds = (size_t)2 * 16 * (16 * ntiles + 4) * sizeof(float) + 2 * 2 * DENSE_NW * 16 * sizeof(double);
-    const dim3 grid((unsigned)((a.C + 15) / 16));
+    if (r.remc_K > 1 && (16 % r.remc_K != 0 || r.remc_K * r.remc_M != a.C)) return hipErrorInvalidValue;
+    const int64_t per = r.remc_K > 1 ? 16 / r.remc_K : 16;      // values of m (or chains) per workgroup
+    const int64_t units = r.remc_K > 1 ? r.remc_M : a.C;
+    const dim3 grid((unsigned)((units + per - 1) / per));
+    const bool ex = a.ws.scale || r.remc_K > 1;
     switch (ntiles) {
 #define HMC_DENSE_NT(N)                                                                   \
     case N:                                                                               \
-        if (a.ws.scale) hipLaunchKernelGGL((k_fused_dense<N, true>), grid, dim3(64 * DENSE_NW), lds, s, a, r); \
+        if (ex) hipLaunchKernelGGL((k_fused_dense<N, true>), grid, dim3(64 * DENSE_NW), lds, s, a, r); \
         else hipLaunchKernelGGL((k_fused_dense<N, false>), grid, dim3(64 * DENSE_NW), lds, s, a, r);            \
         break;
         HMC_DENSE_NT(1) HMC_DENSE_NT(2) HMC_DENSE_NT(3) HMC_DENSE_NT(4)

@@ -187,3 +187,29 @@ def test_fused_and_plain_logistic_exchange_agree_in_distribution():
     assert abs(rates["fused"] - rates["plain"]) < 0.05, rates
     accs = {f: to_np(out[f]["is_accepted"]).mean() for f in out}
     assert abs(accs["fused"] - accs["plain"]) < 0.05, accs
+
+
+@pytest.mark.parametrize("K", [2, 4, 8])
+def test_dense_exchange_inside_the_launch_is_the_stepwise_run(K):
+    # on the fused form the dense kernel exchanges between transitions itself (all replicas of a
+    # chain index in one workgroup); the same chain, built from one fused transition at a time and
+    # the separate exchange step, must agree: decisions exactly, states to FP32 rounding
+    M, B, R = 12, 2, 5
+    w = W.gauss_dense(dim=20, num_chains=K * M, L=5, step_size=0.12, seed=4)
+    betas = [0.6 ** k for k in range(K)]
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED)
+    s.set_inverse_temperature(_betas_per_chain(betas, M))
+    g = s.remc_sample_chain(K, R, B)
+    s.close()
+    s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED)
+    s.set_inverse_temperature(_betas_per_chain(betas, M))
+    xs, sws, accs = [], [], []
+    for t in range(B + R):
+        out = s.sample_chain(1, 0)
+        sws.append(to_np(s.remc_swap(K, t)))
+        xs.append(to_np(s.get_state()[0]))
+        accs.append(to_np(out["is_accepted"])[0])
+    s.close()
+    assert np.array_equal(to_np(g["is_accepted"]).astype(bool), np.array(accs[B:]).astype(bool))
+    assert np.array_equal(to_np(g["swapped"]), np.array(sws[B:]))
+    assert np.max(np.abs(to_np(g["samples"]) - np.array(xs[B:]))) <= 1e-5
