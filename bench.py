@@ -37,7 +37,7 @@ MEASURED_TRAFFIC = {
     # (workload, form, gradient dtype, burn-in, results)
     ("logreg_1000x25", "fused", "f32", 1000, 1000): {
         "sources": ["k_fused_logreg.hip", "hmc_device.hpp", "hmc_internal.hpp"],
-        "sha256_16": "c1c9b3cce89a69fb", "read": 11306112, "write": 152446784},
+        "sha256_16": "58740d7baab17e84", "read": 11263104, "write": 152446080},
 }
 
 
@@ -206,7 +206,7 @@ def bench_remc(args):
                    "num_leapfrog_steps": w.num_leapfrog_steps, "num_burnin": w.num_burnin,
                    "num_results": w.num_results, "adapt": "dual averaging to 0.8" if w.adapt else "none",
                    "form": {hmc.HMC_FORM_PLAIN: "plain", hmc.HMC_FORM_GRAPH: "graph",
-                            hmc.HMC_FORM_FUSED: ("fused (exchanges inside one launch)" if w.kind == W.GAUSS_DENSE and 16 % K == 0
+                            hmc.HMC_FORM_FUSED: ("fused (exchanges inside one launch)" if inline_exchange(w, K)
                                                   else "fused (one launch per transition)")}[hmc.hmc_effective_form(s.ctx)],
                    "parallelism": "chains (1 GPU)"},
         "roofline": {"bound": bound, "achieved": achieved / scale, "peak": peak / scale,
@@ -407,6 +407,21 @@ def bench_nuts(args):
         result["ess_per_sec"] = summ["min_ess_bulk"] / (elapsed / args.steps) if summ["max_rhat"] <= 1.01 else None
     s.close()
     return result
+
+
+def inline_exchange(w, K):
+    """Whether the fused kernel of this workload runs K replicas with the exchange inside the launch
+    (dense: K divides the 16 chains of a workgroup; element-wise: K divides the lane groups of a wavefront)."""
+    import workloads as W
+    if K < 2 or w.num_chains % K:
+        return False
+    if w.kind == W.GAUSS_DENSE:
+        return 16 % K == 0
+    if w.kind in (W.STD_NORMAL, W.GAUSS_DIAG):
+        nblk = (w.dim + 3) // 4
+        g = 1 if nblk <= 1 else 4 if nblk <= 4 else 16 if nblk <= 16 else 64
+        return (64 // g) % K == 0
+    return False
 
 
 def to_host(t):

@@ -207,9 +207,11 @@ hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char* report, s
  * temperature, by broadcasting); the replicas of one temperature ladder
  * 1 = beta_0 > beta_1 > ... hold the same beta in all M chains.  Tempering
  * runs on every form and target (on the fused form the exchange sampler
- * launches one fused transition per exchange, except on the dense Gaussian
- * with K dividing 16, whose fused kernel exchanges between transitions
- * itself: one launch for the run).
+ * launches one fused transition per exchange, except on the Gaussian
+ * targets when K divides the chains a workgroup groups together (dense: 16;
+ * element-wise: the lane groups of a wavefront, 64 / lanes per chain), whose
+ * fused kernels exchange between transitions themselves: one launch for the
+ * run).
  * ------------------------------------------------------------------------- */
 
 /* Sets per-chain inverse temperatures: beta (device, FP64, [C]) is copied;

@@ -183,6 +183,10 @@ hmc_status check_adapt(const hmc_adapt* ad);
 
 // Returns hipErrorNotSupported when no fused kernel covers this target/shape.
 bool fused_supported(const PlainArgs& a);
+// The fused kernel of this target can run K replicas with the exchange inside
+// the launch (dense: K divides 16; element-wise: K divides the lane groups of
+// a wavefront).
+bool fused_remc_inline(const PlainArgs& a, int64_t K);
 hipError_t launch_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s);
 
 // Ragged multi-request launch of the fused elementwise kernel: jobs of one

@@ -54,12 +54,20 @@ __device__ __forceinline__ void after_decision(const FusedRun& r, int64_t C, int
 // Elementwise targets.  NB blocks of 4 dims per lane; lane j of a group owns
 // blocks j, j + G, ...
 // ---------------------------------------------------------------------------
-template <typename T, int G, int NB, bool TR>
+// EX: a transform and / or the replica exchange inside the launch (a template
+// parameter, so that plain runs carry neither).  With the exchange, lane group
+// (slot) s holds replica s % K of chain index s / K; K divides the 64 / G slots
+// of a wavefront, so the two chains of every pair exchange by shuffles G lanes
+// apart.
+template <typename T, int G, int NB, bool EX>
 __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedRun& r, int64_t lblock) {
     const int64_t gid = lblock * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % G;
-    const int64_t c = gid / G;
-    const bool active = c < a.C;
+    const int nrep = EX ? r.remc_K : 0;
+    const int64_t slot = gid / G;
+    const int krep = nrep > 1 ? (int)(slot % nrep) : 0;
+    const int64_t c = nrep > 1 ? krep * r.remc_M + slot / nrep : slot;
+    const bool active = slot < a.C;                  // with the exchange: chain index slot / K < M
     const int64_t cc = active ? c : 0;
     const int64_t D = a.tg.D;
     const bool diag = a.tg.kind == HMC_TGT_GAUSS_DIAG;
@@ -67,16 +75,16 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
     T* Gr = (T*)a.ws.g;
     const T* prec = (const T*)a.tg.prec;
 
-    // Transformed kernel (x = shift + scale z, TR): the chain runs in
-    // z = x / scale, whose precision is prec scale^2; states are converted at
-    // load and store.  A template parameter, so that the untransformed
-    // kernels carry none of it.
-    const double* sc = TR ? a.ws.scale : nullptr;
+    // Transformed kernel (x = shift + scale z): the chain runs in z = x / scale,
+    // whose precision is prec scale^2; states are converted at load and store.
+    const double* sc = EX ? a.ws.scale : nullptr;
+    const bool trs = sc != nullptr;
     // the scale in the state's precision, staged once in LDS for the stores
     // of x (a lane group covers 4 G NB >= D dims)
-    __shared__ T sc_lds[TR ? 4 * G * NB : 1];
-    if (TR) {
-        for (int64_t d = threadIdx.x; d < D; d += blockDim.x) sc_lds[d] = (T)sc[d];
+    __shared__ T sc_lds[EX ? 4 * G * NB : 1];
+    if (EX) {
+        if (trs)
+            for (int64_t d = threadIdx.x; d < D; d += blockDim.x) sc_lds[d] = (T)sc[d];
         __syncthreads();
     }
     T x[NB][4], g[NB][4], pr[NB][4];
@@ -157,10 +165,11 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
                 }
             s.logp = lp;
         }
-        if (active) {
+        // kept sample and proposal outputs of this transition
+        auto store_outputs = [&]() {
             if (r.samples && i >= r.n_burnin) {
                 T* smp = (T*)r.samples + ((i - r.n_burnin) * a.C + c) * D;
-                if (TR) {
+                if (EX && trs) {
                     // an index the compiler cannot see through keeps the LDS
                     // reads here: hoisted out of the transition loop they
                     // would hold NB 4 registers for the whole run
@@ -181,7 +190,7 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
             }
             if (r.out.proposed_state || r.out.proposed_momentum) {
                 int l4 = 4 * lane;
-                if (TR) asm volatile("" : "+v"(l4));
+                if (EX) asm volatile("" : "+v"(l4));
 #pragma unroll
                 for (int k = 0; k < NB; ++k)
 #pragma unroll
@@ -189,25 +198,62 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
                         if (ok[k][j]) {
                             const int64_t d = 4 * (lane + (int64_t)G * k) + j;
                             if (r.out.proposed_state)
-                                ((T*)r.out.proposed_state)[c * D + d] = TR ? xn[k][j] * sc_lds[l4 + 4 * G * k + j] : xn[k][j];
+                                ((T*)r.out.proposed_state)[c * D + d] = (EX && trs) ? xn[k][j] * sc_lds[l4 + 4 * G * k + j] : xn[k][j];
                             if (r.out.proposed_momentum) ((T*)r.out.proposed_momentum)[c * D + d] = pn[k][j];
                         }
             }
+        };
+        if (EX) {
+            // traces and adaptation record the transition; the exchange follows
+            // it, and the kept sample is the state after the exchange
+            if (active) after_decision(r, a.C, c, i, acc, lar, dh, s.logp, s, lane == 0);
+            if (nrep > 1) {
+                const int par = (int)(t & 1u);
+                const bool a_side = krep >= par && ((krep - par) & 1) == 0 && krep + 1 < nrep;
+                const bool b_side = krep >= par + 1 && ((krep - 1 - par) & 1) == 0;
+                const int wl = threadIdx.x & 63;
+                const int src = a_side ? wl + G : (b_side ? wl - G : wl);
+                const double lp_o = __shfl(s.logp, src, 64);
+                const double bt_o = __shfl(bt, src, 64);
+                bool swp = false;
+                if (active && (a_side || b_side)) {
+                    const int64_t ca = a_side ? c : c - r.remc_M;
+                    const double la = a_side ? s.logp : lp_o, lb = a_side ? lp_o : s.logp;
+                    const double ba = a_side ? bt : bt_o, bb = a_side ? bt_o : bt;
+                    swp = log_uniform52(a.key, (uint32_t)ca, t, TAG_SWAP) < (ba - bb) * (lb - la);
+                }
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const T xo = __shfl(x[k][j], src, 64), go = __shfl(g[k][j], src, 64);
+                        if (swp) {
+                            x[k][j] = xo;
+                            g[k][j] = go;
+                        }
+                    }
+                if (swp) s.logp = lp_o;
+                if (active && r.swapped && i >= r.n_burnin && lane == 0)
+                    r.swapped[(i - r.n_burnin) * a.C + c] = swp ? 1 : 0;
+            }
+            if (active) store_outputs();
+        } else if (active) {
+            store_outputs();
             after_decision(r, a.C, c, i, acc, lar, dh, s.logp, s, lane == 0);
         }
     }
     if (!active) return;
     // a fresh read of the scale: reusing the values loaded before the loop
     // would hold them in registers for the whole run
-    if (TR) asm volatile("" ::: "memory");
+    if (EX) asm volatile("" ::: "memory");
 #pragma unroll
     for (int k = 0; k < NB; ++k)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (ok[k][j]) {
                 const int64_t d = 4 * (lane + (int64_t)G * k) + j;
-                X[c * D + d] = TR ? (T)((double)x[k][j] * sc[d]) : x[k][j];
-                Gr[c * D + d] = TR ? (T)((double)g[k][j] / sc[d]) : g[k][j];
+                X[c * D + d] = (EX && trs) ? (T)((double)x[k][j] * sc[d]) : x[k][j];
+                Gr[c * D + d] = (EX && trs) ? (T)((double)g[k][j] / sc[d]) : g[k][j];
             }
     if (lane == 0) {
         a.ws.logp[c] = s.logp;
@@ -216,9 +262,9 @@ __device__ __forceinline__ void fused_elem_body(const PlainArgs& a, const FusedR
     }
 }
 
-template <typename T, int G, int NB, bool TR>
+template <typename T, int G, int NB, bool EX>
 __global__ __launch_bounds__(256) void k_fused_elem(PlainArgs a, FusedRun r) {
-    fused_elem_body<T, G, NB, TR>(a, r, blockIdx.x);
+    fused_elem_body<T, G, NB, EX>(a, r, blockIdx.x);
 }
 
 // Several requests of one shape class in one grid: block b runs job j with
@@ -567,6 +613,17 @@ int64_t elem_blocks(const PlainArgs& a) {
     return (a.C * G + 255) / 256;
 }
 
+bool fused_remc_inline(const PlainArgs& a, int64_t K) {
+    if (K < 2 || a.C % K != 0 || !fused_supported(a)) return false;
+    if (a.tg.kind == HMC_TGT_GAUSS_DENSE) return 16 % K == 0;
+    if (a.tg.kind == HMC_TGT_STD_NORMAL || a.tg.kind == HMC_TGT_GAUSS_DIAG) {
+        int G;
+        elem_shape(a, &G);
+        return G <= 64 && (64 / G) % K == 0;       // a pair's two lane groups in one wavefront
+    }
+    return false;
+}
+
 #define HMC_ELEM_DISPATCH(CLS, MACRO)                  \
     switch ((CLS) & 7) {                               \
     case 0: MACRO(1, 1); break;                        \
@@ -582,7 +639,8 @@ template <typename T>
 static hipError_t launch_elem(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     const int cls = elem_class(a);
     const dim3 grid((unsigned)elem_blocks(a));
-    if (a.ws.scale) {
+    if (r.remc_K > 1 && !fused_remc_inline(a, r.remc_K)) return hipErrorInvalidValue;
+    if (a.ws.scale || r.remc_K > 1) {
 #define HMC_ELEM(GG, NN) hipLaunchKernelGGL((k_fused_elem<T, GG, NN, true>), grid, dim3(256), 0, s, a, r)
         HMC_ELEM_DISPATCH(cls, HMC_ELEM)
 #undef HMC_ELEM
@@ -612,7 +670,7 @@ hipError_t launch_fused_elem_multi(int cls, const ElemJob* jobs_dev, int njobs, 
 static hipError_t launch_dense_fused(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     const int ntiles = (int)((a.tg.D + 15) / 16);
     const size_t lds = (size_t)2 * 16 * (16 * ntiles + 4) * sizeof(float) + 2 * 2 * DENSE_NW * 16 * sizeof(double);
-    if (r.remc_K > 1 && (16 % r.remc_K != 0 || r.remc_K * r.remc_M != a.C)) return hipErrorInvalidValue;
+    if (r.remc_K > 1 && (!fused_remc_inline(a, r.remc_K) || r.remc_K * r.remc_M != a.C)) return hipErrorInvalidValue;
     const int64_t per = r.remc_K > 1 ? 16 / r.remc_K : 16;      // values of m (or chains) per workgroup
     const int64_t units = r.remc_K > 1 ? r.remc_M : a.C;
     const dim3 grid((unsigned)((units + per - 1) / per));

@@ -189,13 +189,23 @@ def test_fused_and_plain_logistic_exchange_agree_in_distribution():
     assert abs(accs["fused"] - accs["plain"]) < 0.05, accs
 
 
-@pytest.mark.parametrize("K", [2, 4, 8])
-def test_dense_exchange_inside_the_launch_is_the_stepwise_run(K):
-    # on the fused form the dense kernel exchanges between transitions itself (all replicas of a
-    # chain index in one workgroup); the same chain, built from one fused transition at a time and
-    # the separate exchange step, must agree: decisions exactly, states to FP32 rounding
+def _inline_case(target, K, M):
+    if target == "dense":
+        return W.gauss_dense(dim=20, num_chains=K * M, L=5, step_size=0.12, seed=4)
+    if target == "diag":          # 16 lanes per chain: 4 chains per wavefront
+        return W.gauss_diag(dim=37, num_chains=K * M, L=5, step_size=0.1)
+    return W.std_normal_1d(num_chains=K * M, dim=7, state_dtype="f32", L=4, step_size=0.5)   # 4 lanes per chain
+
+
+@pytest.mark.parametrize("target,K", [("dense", 2), ("dense", 4), ("dense", 8), ("diag", 2), ("diag", 4),
+                                      ("std7", 4), ("std7", 16)])
+def test_exchange_inside_the_launch_is_the_stepwise_run(target, K):
+    # on the fused form the Gaussian kernels exchange between transitions themselves (all replicas
+    # of a chain index in one workgroup or wavefront); the same chain, built from one fused
+    # transition at a time and the separate exchange step, must agree: decisions exactly, states
+    # to FP32 rounding
     M, B, R = 12, 2, 5
-    w = W.gauss_dense(dim=20, num_chains=K * M, L=5, step_size=0.12, seed=4)
+    w = _inline_case(target, K, M)
     betas = [0.6 ** k for k in range(K)]
     s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED)
     s.set_inverse_temperature(_betas_per_chain(betas, M))
