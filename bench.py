@@ -37,7 +37,7 @@ MEASURED_TRAFFIC = {
     # (workload, form, gradient dtype, burn-in, results)
     ("logreg_1000x25", "fused", "f32", 1000, 1000): {
         "sources": ["k_fused_logreg.hip", "hmc_device.hpp", "hmc_internal.hpp"],
-        "sha256_16": "58740d7baab17e84", "read": 11263104, "write": 152446080},
+        "sha256_16": "09a4e0fc4db9e24a", "read": 11281280, "write": 152446144},
 }
 
 
@@ -411,7 +411,8 @@ def bench_nuts(args):
 
 def inline_exchange(w, K):
     """Whether the fused kernel of this workload runs K replicas with the exchange inside the launch
-    (dense: K divides the 16 chains of a workgroup; element-wise: K divides the lane groups of a wavefront)."""
+    (dense: K divides the 16 chains of a workgroup; element-wise: K divides the lane groups of a wavefront;
+    logistic: K divides the 4 chains of a workgroup)."""
     import workloads as W
     if K < 2 or w.num_chains % K:
         return False
@@ -421,6 +422,8 @@ def inline_exchange(w, K):
         nblk = (w.dim + 3) // 4
         g = 1 if nblk <= 1 else 4 if nblk <= 4 else 16 if nblk <= 16 else 64
         return (64 // g) % K == 0
+    if w.kind == W.LOGREG:
+        return 4 % K == 0
     return False
 
 

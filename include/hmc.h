@@ -206,12 +206,12 @@ hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char* report, s
  * (the tempered target of the paper: the log-probability times the inverse
  * temperature, by broadcasting); the replicas of one temperature ladder
  * 1 = beta_0 > beta_1 > ... hold the same beta in all M chains.  Tempering
- * runs on every form and target (on the fused form the exchange sampler
- * launches one fused transition per exchange, except on the Gaussian
- * targets when K divides the chains a workgroup groups together (dense: 16;
- * element-wise: the lane groups of a wavefront, 64 / lanes per chain), whose
+ * runs on every form and target.  On the fused form, when K divides the
+ * chains a workgroup groups together (dense Gaussian: 16; logistic: 4;
+ * element-wise: the lane groups of a wavefront, 64 / lanes per chain), the
  * fused kernels exchange between transitions themselves: one launch for the
- * run).
+ * run.  Otherwise the exchange sampler launches one fused transition per
+ * exchange.
  * ------------------------------------------------------------------------- */
 
 /* Sets per-chain inverse temperatures: beta (device, FP64, [C]) is copied;

@@ -674,8 +674,8 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
     if (trace) tr = *trace;
     if (ad) st = check_hip(launch_da_init(ctx->a, ctx->stream), "adaptation init");
     if (ctx->form == HMC_FORM_FUSED && fused_remc_inline(ctx->a, num_replicas)) {
-        // Gaussian targets: every replica of a chain index in one wavefront (element-wise) or workgroup
-        // (dense) of the fused kernel, which exchanges between transitions itself -- one launch for the run
+        // every replica of a chain index in one wavefront (element-wise) or workgroup (dense, logistic)
+        // of the fused kernel, which exchanges between transitions itself -- one launch for the run
         FusedRun r;
         memset(&r, 0, sizeof(r));
         r.t_begin = ctx->t;

@@ -621,6 +621,7 @@ bool fused_remc_inline(const PlainArgs& a, int64_t K) {
         elem_shape(a, &G);
         return G <= 64 && (64 / G) % K == 0;       // a pair's two lane groups in one wavefront
     }
+    if (a.tg.kind == HMC_TGT_LOGREG) return 4 % K == 0;   // 4 chains per workgroup
     return false;
 }
 

@@ -194,6 +194,16 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int q4 = lane & 3, b16 = lane >> 2;
     const int64_t c0 = (int64_t)blockIdx.x * 4;
+    // chain of slot s (0..3): s itself, or with the exchange inside the launch
+    // replica s % K of chain index 4 / K * block + s / K (chain k M + m), so
+    // that all replicas of a chain index share the workgroup
+    const int nrep = TP ? r.remc_K : 0;
+    auto chain_of = [&](int sl) -> int64_t {
+        return nrep > 1 ? (int64_t)(sl % nrep) * r.remc_M + (int64_t)blockIdx.x * (4 / nrep) + sl / nrep : c0 + sl;
+    };
+    auto slot_valid = [&](int sl) -> bool {
+        return nrep > 1 ? (int64_t)blockIdx.x * (4 / nrep) + sl / nrep < r.remc_M : c0 + sl < C;
+    };
     const float inv_var = (float)a.tg.inv_var;
 
     float* th = lds;                                    // [4][32] theta of the 4 chains (dim order)
@@ -242,8 +252,8 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
         for (int task = (int)threadIdx.x - 128; task < ZT * 32; task += 384) {
             const int k = task >> 5, ci = (task >> 3) & 3, blk = task & 7;
             float z[4] = {0.f, 0.f, 0.f, 0.f};
-            if (i0 + k < T && c0 + ci < C && blk < nb)
-                momentum4<float>(a.key, (uint32_t)(c0 + ci), (uint32_t)(r.t_begin + i0 + k), (uint32_t)blk, z);
+            if (i0 + k < T && slot_valid(ci) && blk < nb)
+                momentum4<float>(a.key, (uint32_t)chain_of(ci), (uint32_t)(r.t_begin + i0 + k), (uint32_t)blk, z);
             *(float4*)&zb[(k * 4 + ci) * 32 + 4 * blk] = make_float4(z[0], z[1], z[2], z[3]);
         }
     };
@@ -252,8 +262,8 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
         for (int task = (int)threadIdx.x - 128; task < UT * 4; task += 384) {
             const int k = task >> 2, ci = task & 3;
             double lu = 0.0;
-            if (i0 + k < T && c0 + ci < C)
-                lu = log_accept_uniform(a.key, (uint32_t)(c0 + ci), (uint32_t)(r.t_begin + i0 + k));
+            if (i0 + k < T && slot_valid(ci))
+                lu = log_accept_uniform(a.key, (uint32_t)chain_of(ci), (uint32_t)(r.t_begin + i0 + k));
             lub[(hb * UT + k) * 4 + ci] = lu;
         }
         if (r.adapt)
@@ -274,9 +284,10 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     // ---- owners: thread t < 128 holds (chain oi, dim od) ----
     const bool owner = threadIdx.x < 128;
     const int oi = (threadIdx.x >> 5) & 3, od = threadIdx.x & 31;
-    const int64_t oc = c0 + oi;
-    const bool ovalid = owner && oc < C && od < D;
-    const int64_t occ = (owner && oc < C) ? oc : 0;
+    const int64_t oc = chain_of(oi);
+    const bool cval = slot_valid(oi);
+    const bool ovalid = owner && cval && od < D;
+    const int64_t occ = (owner && cval) ? oc : 0;
     float* Xw = (float*)a.ws.x;
     float* Gw = (float*)a.ws.g;
     float th0 = ovalid ? Xw[occ * D + od] : 0.f;
@@ -296,7 +307,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     const double btd = (TP && owner && a.ws.beta) ? a.ws.beta[occ] : 1.0;
     float keps = TP ? (owner ? (float)(a.ws.eps[occ] * btd) : 0.f) : 0.f;
     auto kick_eps = [&]() -> float { return TP ? keps : eps; };
-    if (owner && od == 0 && oc < C) cst[oi] = ChainSt{a.ws.logp[oc], a.ws.eps[oc], a.ws.da[oc]};
+    if (owner && od == 0 && cval) cst[oi] = ChainSt{a.ws.logp[oc], a.ws.eps[oc], a.ws.da[oc]};
     if (threadIdx.x == 0)
         *optr = OutPtrs{(gptr<float>)r.samples,          (gptr<double>)r.trace.step_size,
                         (gptr<uint8_t>)r.trace.is_accepted, (gptr<double>)r.trace.log_accept_ratio,
@@ -444,10 +455,10 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
                 g0 = gq;
                 cs.logp = lp1;
             }
-            if (oc < C) {
+            if (cval) {
                 const OutPtrs o = *optr;
                 if (ovalid) {
-                    if (o.samples && itr >= r.n_burnin)
+                    if (o.samples && itr >= r.n_burnin && !(TP && nrep > 1))
                         o.samples[((itr - r.n_burnin) * C + oc) * D + od] = TP && sc ? (float)((double)th0 * sod) : th0;
                     if (o.ps) o.ps[oc * D + od] = TP && sc ? (float)((double)thq * sod) : thq;
                     if (o.pm) o.pm[oc * D + od] = p;
@@ -488,12 +499,64 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
         }
         // the owners read the next momenta before the next barrier of a step
         if (refill_z) __syncthreads();
+        if (TP && nrep > 1) {
+            // the exchange: the owners post their chains' states in the wave-partial
+            // buffer once both owner waves have read the last gradient partials from
+            // it, every owner reads its partner's state and both log-probabilities,
+            // and the swap is applied after another barrier
+            float* xth = part;                  // [4][32]
+            float* xgr = part + 128;            // [4][32]
+            if (!refill_z) __syncthreads();
+            if (owner) {
+                xth[oi * 32 + od] = th0;
+                xgr[oi * 32 + od] = g0;
+            }
+            __syncthreads();
+            bool swp = false;
+            float th_n = th0, g_n = g0;
+            double lp_n = 0.0;
+            const uint32_t tt = (uint32_t)(r.t_begin + itr);
+            if (owner && cval) {
+                const int krep = oi % nrep, par = (int)(tt & 1u);
+                const bool a_side = krep >= par && ((krep - par) & 1) == 0 && krep + 1 < nrep;
+                const bool b_side = krep >= par + 1 && ((krep - 1 - par) & 1) == 0;
+                if (a_side || b_side) {
+                    const int po = a_side ? oi + 1 : oi - 1;        // the partner's slot (same chain index)
+                    const int64_t pc = chain_of(po);
+                    const double lo = cst[oi].logp, lq = cst[po].logp;
+                    const double bq = a.ws.beta ? a.ws.beta[pc] : 1.0;
+                    const int64_t ca = a_side ? oc : pc;
+                    const double la = a_side ? lo : lq, lb = a_side ? lq : lo;
+                    const double ba = a_side ? btd : bq, bb = a_side ? bq : btd;
+                    swp = log_uniform52(a.key, (uint32_t)ca, tt, TAG_SWAP) < (ba - bb) * (lb - la);
+                    if (swp) {
+                        th_n = xth[po * 32 + od];
+                        g_n = xgr[po * 32 + od];
+                        lp_n = lq;
+                    }
+                }
+            }
+            __syncthreads();
+            if (owner && cval) {
+                if (swp) {
+                    th0 = th_n;
+                    g0 = g_n;
+                    if (od == 0) cst[oi].logp = lp_n;
+                }
+                const OutPtrs o = *optr;
+                if (itr >= r.n_burnin) {
+                    if (od == 0 && r.swapped) r.swapped[(itr - r.n_burnin) * C + oc] = swp ? 1 : 0;
+                    if (o.samples && od < D)
+                        o.samples[((itr - r.n_burnin) * C + oc) * D + od] = sc ? (float)((double)th0 * sod) : th0;
+                }
+            }
+        }
     }
     if (ovalid) {
         Xw[oc * D + od] = TP && sc ? (float)((double)th0 * sod) : th0;
         Gw[oc * D + od] = TP && sc ? (float)((double)g0 / sod) : g0;
     }
-    if (owner && od == 0 && oc < C) {
+    if (owner && od == 0 && cval) {
         const ChainSt cs = cst[oi];
         a.ws.logp[oc] = cs.logp;
         a.ws.eps[oc] = cs.eps;
@@ -513,8 +576,11 @@ bool fused_logreg_supported(const PlainArgs& a) {
 template <int TPW, int QQ, typename XT>
 static hipError_t launch_lr4(const PlainArgs& a, const FusedRun& r, hipStream_t s) {
     const size_t lds = logreg4_lds(TPW);
-    const dim3 grid((unsigned)((a.C + 3) / 4));
-    if (a.ws.beta || a.ws.scale)
+    if (r.remc_K > 1 && (4 % r.remc_K != 0 || r.remc_K * r.remc_M != a.C)) return hipErrorInvalidValue;
+    const int64_t per = r.remc_K > 1 ? 4 / r.remc_K : 4;      // chain indices (or chains) per workgroup
+    const int64_t units = r.remc_K > 1 ? r.remc_M : a.C;
+    const dim3 grid((unsigned)((units + per - 1) / per));
+    if (a.ws.beta || a.ws.scale || r.remc_K > 1)
         hipLaunchKernelGGL((k_fused_logreg4<TPW, QQ, XT, true>), grid, dim3(64 * LR_NW), lds, s, a, r);
     else
         hipLaunchKernelGGL((k_fused_logreg4<TPW, QQ, XT, false>), grid, dim3(64 * LR_NW), lds, s, a, r);

@@ -194,17 +194,19 @@ def _inline_case(target, K, M):
         return W.gauss_dense(dim=20, num_chains=K * M, L=5, step_size=0.12, seed=4)
     if target == "diag":          # 16 lanes per chain: 4 chains per wavefront
         return W.gauss_diag(dim=37, num_chains=K * M, L=5, step_size=0.1)
+    if target == "logreg":        # 4 chains per workgroup; 300 rows leave a ragged last tile
+        return W.logreg(n_rows=300, dim=7, num_chains=K * M, L=5, step_size=0.05, seed=6)
     return W.std_normal_1d(num_chains=K * M, dim=7, state_dtype="f32", L=4, step_size=0.5)   # 4 lanes per chain
 
 
 @pytest.mark.parametrize("target,K", [("dense", 2), ("dense", 4), ("dense", 8), ("diag", 2), ("diag", 4),
-                                      ("std7", 4), ("std7", 16)])
+                                      ("std7", 4), ("std7", 16), ("logreg", 2), ("logreg", 4)])
 def test_exchange_inside_the_launch_is_the_stepwise_run(target, K):
-    # on the fused form the Gaussian kernels exchange between transitions themselves (all replicas
-    # of a chain index in one workgroup or wavefront); the same chain, built from one fused
+    # on the fused form the kernels exchange between transitions themselves (all replicas of a
+    # chain index in one workgroup or wavefront); the same chain, built from one fused
     # transition at a time and the separate exchange step, must agree: decisions exactly, states
     # to FP32 rounding
-    M, B, R = 12, 2, 5
+    M, B, R = (13 if target == "logreg" else 12), 2, 5      # logistic, K = 2: half of the last workgroup idle
     w = _inline_case(target, K, M)
     betas = [0.6 ** k for k in range(K)]
     s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED)
@@ -223,3 +225,5 @@ def test_exchange_inside_the_launch_is_the_stepwise_run(target, K):
     assert np.array_equal(to_np(g["is_accepted"]).astype(bool), np.array(accs[B:]).astype(bool))
     assert np.array_equal(to_np(g["swapped"]), np.array(sws[B:]))
     assert np.max(np.abs(to_np(g["samples"]) - np.array(xs[B:]))) <= 1e-5
+    if target == "logreg":
+        assert np.array(sws).any()          # the LDS exchange path was taken at least once
