@@ -199,6 +199,31 @@ def _inline_case(target, K, M):
     return W.std_normal_1d(num_chains=K * M, dim=7, state_dtype="f32", L=4, step_size=0.5)   # 4 lanes per chain
 
 
+def _inline_vs_stepwise(target, K, scale=None):
+    M, B, R = (13 if target == "logreg" else 12), 2, 5      # logistic, K = 2: half of the last workgroup idle
+    w = _inline_case(target, K, M)
+    betas = [0.6 ** k for k in range(K)]
+    runs = []
+    for inline in (True, False):
+        s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED)
+        s.set_inverse_temperature(_betas_per_chain(betas, M))
+        if scale is not None:
+            s.set_transform_scale(scale(w.dim))
+        if inline:
+            g = s.remc_sample_chain(K, R, B)
+            runs.append((to_np(g["is_accepted"]).astype(bool), to_np(g["swapped"]), to_np(g["samples"])))
+        else:
+            xs, sws, accs = [], [], []
+            for t in range(B + R):
+                out = s.sample_chain(1, 0)
+                sws.append(to_np(s.remc_swap(K, t)))
+                xs.append(to_np(s.get_state()[0]))
+                accs.append(to_np(out["is_accepted"])[0])
+            runs.append((np.array(accs[B:]).astype(bool), np.array(sws[B:]), np.array(xs[B:])))
+        s.close()
+    return runs
+
+
 @pytest.mark.parametrize("target,K", [("dense", 2), ("dense", 4), ("dense", 8), ("diag", 2), ("diag", 4),
                                       ("std7", 4), ("std7", 16), ("logreg", 2), ("logreg", 4)])
 def test_exchange_inside_the_launch_is_the_stepwise_run(target, K):
@@ -206,24 +231,20 @@ def test_exchange_inside_the_launch_is_the_stepwise_run(target, K):
     # chain index in one workgroup or wavefront); the same chain, built from one fused
     # transition at a time and the separate exchange step, must agree: decisions exactly, states
     # to FP32 rounding
-    M, B, R = (13 if target == "logreg" else 12), 2, 5      # logistic, K = 2: half of the last workgroup idle
-    w = _inline_case(target, K, M)
-    betas = [0.6 ** k for k in range(K)]
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED)
-    s.set_inverse_temperature(_betas_per_chain(betas, M))
-    g = s.remc_sample_chain(K, R, B)
-    s.close()
-    s = hmc.sampler_for(w, form=hmc.HMC_FORM_FUSED)
-    s.set_inverse_temperature(_betas_per_chain(betas, M))
-    xs, sws, accs = [], [], []
-    for t in range(B + R):
-        out = s.sample_chain(1, 0)
-        sws.append(to_np(s.remc_swap(K, t)))
-        xs.append(to_np(s.get_state()[0]))
-        accs.append(to_np(out["is_accepted"])[0])
-    s.close()
-    assert np.array_equal(to_np(g["is_accepted"]).astype(bool), np.array(accs[B:]).astype(bool))
-    assert np.array_equal(to_np(g["swapped"]), np.array(sws[B:]))
-    assert np.max(np.abs(to_np(g["samples"]) - np.array(xs[B:]))) <= 1e-5
+    (acc_i, sw_i, x_i), (acc_s, sw_s, x_s) = _inline_vs_stepwise(target, K)
+    assert np.array_equal(acc_i, acc_s)
+    assert np.array_equal(sw_i, sw_s)
+    assert np.max(np.abs(x_i - x_s)) <= 1e-5
     if target == "logreg":
-        assert np.array(sws).any()          # the LDS exchange path was taken at least once
+        assert sw_s.any()          # the LDS exchange path was taken at least once
+
+
+@pytest.mark.parametrize("target,K", [("dense", 4), ("diag", 2), ("std7", 4), ("logreg", 2), ("logreg", 4)])
+def test_exchange_inside_the_launch_with_a_transform(target, K):
+    # the transformed kernel moves z = x / scale between chains inside the launch; the stepwise
+    # run stores x and reloads z at every launch, so its states may differ by a few FP32 roundings
+    (acc_i, sw_i, x_i), (acc_s, sw_s, x_s) = _inline_vs_stepwise(target, K, lambda d: np.linspace(0.6, 1.4, d))
+    assert np.array_equal(acc_i, acc_s)
+    assert np.array_equal(sw_i, sw_s)
+    assert np.allclose(x_i, x_s, rtol=1e-4, atol=1e-5)
+    assert sw_s.any()
