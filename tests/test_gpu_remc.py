@@ -194,13 +194,14 @@ def _inline_case(target, K, M):
         return W.gauss_dense(dim=20, num_chains=K * M, L=5, step_size=0.12, seed=4)
     if target == "diag":          # 16 lanes per chain: 4 chains per wavefront
         return W.gauss_diag(dim=37, num_chains=K * M, L=5, step_size=0.1)
-    if target == "logreg":        # 4 chains per workgroup; 300 rows leave a ragged last tile
-        return W.logreg(n_rows=300, dim=7, num_chains=K * M, L=5, step_size=0.05, seed=6)
+    if target in ("logreg", "logreg_bf16"):   # 4 chains per workgroup; 300 rows leave a ragged last tile
+        return W.logreg(n_rows=300, dim=7, num_chains=K * M, L=5, step_size=0.05, seed=6,
+                        bf16=target == "logreg_bf16")
     return W.std_normal_1d(num_chains=K * M, dim=7, state_dtype="f32", L=4, step_size=0.5)   # 4 lanes per chain
 
 
 def _inline_vs_stepwise(target, K, scale=None):
-    M, B, R = (13 if target == "logreg" else 12), 2, 5      # logistic, K = 2: half of the last workgroup idle
+    M, B, R = (13 if target.startswith("logreg") else 12), 2, 5   # logistic, K = 2: half of the last workgroup idle
     w = _inline_case(target, K, M)
     betas = [0.6 ** k for k in range(K)]
     runs = []
@@ -225,7 +226,7 @@ def _inline_vs_stepwise(target, K, scale=None):
 
 
 @pytest.mark.parametrize("target,K", [("dense", 2), ("dense", 4), ("dense", 8), ("diag", 2), ("diag", 4),
-                                      ("std7", 4), ("std7", 16), ("logreg", 2), ("logreg", 4)])
+                                      ("std7", 4), ("std7", 16), ("logreg", 2), ("logreg", 4), ("logreg_bf16", 4)])
 def test_exchange_inside_the_launch_is_the_stepwise_run(target, K):
     # on the fused form the kernels exchange between transitions themselves (all replicas of a
     # chain index in one workgroup or wavefront); the same chain, built from one fused
@@ -235,11 +236,12 @@ def test_exchange_inside_the_launch_is_the_stepwise_run(target, K):
     assert np.array_equal(acc_i, acc_s)
     assert np.array_equal(sw_i, sw_s)
     assert np.max(np.abs(x_i - x_s)) <= 1e-5
-    if target == "logreg":
+    if target.startswith("logreg"):
         assert sw_s.any()          # the LDS exchange path was taken at least once
 
 
-@pytest.mark.parametrize("target,K", [("dense", 4), ("diag", 2), ("std7", 4), ("logreg", 2), ("logreg", 4)])
+@pytest.mark.parametrize("target,K", [("dense", 4), ("diag", 2), ("std7", 4), ("logreg", 2), ("logreg", 4),
+                                      ("logreg_bf16", 2)])
 def test_exchange_inside_the_launch_with_a_transform(target, K):
     # the transformed kernel moves z = x / scale between chains inside the launch; the stepwise
     # run stores x and reloads z at every launch, so its states may differ by a few FP32 roundings
