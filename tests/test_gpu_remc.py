@@ -167,12 +167,13 @@ def test_temperature_errors():
     p.close()
 
 
-def test_fused_and_plain_logistic_exchange_agree_in_distribution():
-    # the fused logistic kernel takes temperatures: a whole exchange run on both forms,
-    # compared through the beta = 1 replica's posterior mean and the exchange rate
-    K, M = 3, 128
+@pytest.mark.parametrize("betas", [[1.0, 0.7, 0.5], [1.0, 0.8, 0.65, 0.5]])
+def test_fused_and_plain_logistic_exchange_agree_in_distribution(betas):
+    # the fused logistic kernel takes temperatures: a whole adapted exchange run on both forms,
+    # compared through the beta = 1 replica's posterior mean and the exchange rate (3 replicas:
+    # one fused launch per transition; 4: the exchanges inside one launch)
+    K, M = len(betas), 128
     w = W.logreg(200, 5, K * M, L=8, step_size=0.08, seed=11)
-    betas = [1.0, 0.7, 0.5]
     out = {}
     for form in ("plain", "fused"):
         s = hmc.sampler_for(w, form=FORMS[form])
