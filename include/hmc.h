@@ -233,8 +233,11 @@ hmc_status hmc_remc_swap(hmc_ctx* ctx, int64_t num_replicas, uint64_t swap_index
 
 /* Replica-exchange sample_chain: num_burnin + num_results times, one
  * transition of every chain (as hmc_sample_chain, with the same adaptation
- * and traces; on the fused form one launch per transition) followed by the
- * exchange step whose swap index is that transition's t.  samples [R, C, D] (device, may be NULL) receive the states
+ * and traces) followed by the exchange step whose swap index is that
+ * transition's t.  On the fused form the whole run is one launch when the
+ * replicas of a chain index fit in one workgroup or wavefront (see
+ * hmc_set_inverse_temperature), else one launch per transition plus the
+ * exchange step; both give the same decisions.  samples [R, C, D] (device, may be NULL) receive the states
  * after the exchange of transition burnin + r; swapped (device [R, C], may be
  * NULL) the exchange flags of the kept transitions; the trace rows hold the
  * transition's results before the exchange.  Asynchronous. */
