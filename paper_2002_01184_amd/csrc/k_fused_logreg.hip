@@ -215,6 +215,7 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
     ChainSt* cst = (ChainSt*)(dac + 2 * UT * 4);        // [4]
     OutPtrs* optr = (OutPtrs*)(cst + 4);
     double* ecf = (double*)(optr + 1);                  // [EXP_NC] 1 / n!
+    float* xgr = (float*)(ecf + EXP_NC);                // [4][32] gradients posted for the exchange
 
     // ---- X and y of this wave's tiles, in the two operand layouts, kept in VGPRs ----
     const XT* X = (const XT*)a.tg.X;
@@ -500,13 +501,12 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
         // the owners read the next momenta before the next barrier of a step
         if (refill_z) __syncthreads();
         if (TP && nrep > 1) {
-            // the exchange: the owners post their chains' states in the wave-partial
-            // buffer once both owner waves have read the last gradient partials from
-            // it, every owner reads its partner's state and both log-probabilities,
-            // and the swap is applied after another barrier
-            float* xth = part;                  // [4][32]
-            float* xgr = part + 128;            // [4][32]
-            if (!refill_z) __syncthreads();
+            // the exchange: the owners post their chains' states in the theta buffer
+            // (no wave reads it between the last barrier of a trajectory and the
+            // first drift of the next) and their gradients in a buffer of their own;
+            // after a barrier every owner reads its partner's state and both
+            // log-probabilities, and the swap is applied after another barrier
+            float* xth = th;                    // [4][32]
             if (owner) {
                 xth[oi * 32 + od] = th0;
                 xgr[oi * 32 + od] = g0;
@@ -566,7 +566,8 @@ __global__ __launch_bounds__(512) void k_fused_logreg4(PlainArgs a, FusedRun r) 
 
 static size_t logreg4_lds(int) {
     return (size_t)(128 + LR_NW * 4 * LR_PS + LR_ZT * 128) * sizeof(float) +
-           (size_t)(LR_NW * 4 + 4 * LR_UT * 4 + EXP_NC) * sizeof(double) + 4 * sizeof(ChainSt) + sizeof(OutPtrs);
+           (size_t)(LR_NW * 4 + 4 * LR_UT * 4 + EXP_NC) * sizeof(double) + 4 * sizeof(ChainSt) + sizeof(OutPtrs) +
+           128 * sizeof(float);
 }
 
 bool fused_logreg_supported(const PlainArgs& a) {
