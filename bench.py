@@ -141,7 +141,7 @@ def ess_run(s, w, x0, eps0, n_results, num_burnin, chunk_s=20.0, per_tr=None):
 
 
 def bench_remc(args):
-    """Replica exchange (paper Sec. 3.1) on a workload: its chains split into
+    """Replica exchange (paper Sec. 2.2) on a workload: its chains split into
     K replicas on a geometric inverse-temperature ladder 1 .. beta_min; one
     run of burn-in + results REMC steps (a transition of every chain, then an
     exchange step) on the plain kernels, timed with HIP events."""
@@ -302,7 +302,7 @@ def bench_moments(args):
 
 
 def bench_nuts(args):
-    """No-U-Turn sampler (paper Sec. 3.2) on a workload with its step size:
+    """No-U-Turn sampler (paper Sec. 2.3) on a workload with its step size:
     burn-in + results transitions of the unrolled tree on the plain kernels,
     timed with HIP events; value = leapfrog chain-steps actually taken per
     second (chains stop at different depths; the lockstep schedule runs the

@@ -199,7 +199,7 @@ int32_t hmc_effective_form(const hmc_ctx* ctx);
 hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char* report, size_t report_len);
 
 /* ---------------------------------------------------------------------------
- * Replica exchange Monte Carlo (paper Sec. 3.1, case study REMC).
+ * Replica exchange Monte Carlo (paper Sec. 2.2, case study REMC).
  *
  * The chains of a context form K replicas of M = C / K chains, replica-major:
  * chain c = k M + m is chain m of replica k.  Chain c targets beta_c logp(x)
@@ -259,7 +259,7 @@ hmc_status hmc_remc_sample_chain(hmc_ctx* ctx, int64_t num_replicas, int64_t num
 hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale);
 
 /* ---------------------------------------------------------------------------
- * No-U-Turn sampler (paper Sec. 3.2: NUTS with its recursion unrolled into a
+ * No-U-Turn sampler (paper Sec. 2.3: NUTS with its recursion unrolled into a
  * fixed O(max_tree_depth) per-chain memory; the algorithm is Hoffman & Gelman
  * 2014, Algorithm 3, "efficient NUTS").  Each transition draws the momentum as
  * HMC does, a slice variable log u = log U - H0, and doubles the trajectory

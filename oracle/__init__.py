@@ -15,7 +15,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB_PATH selects another build of oracle.c (the sanitizer build)
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIB_PATH")
+_LIB_PATH = _LIB_OVERRIDE or os.path.join(_HERE, "liboracle.so")
 
 STD_NORMAL, GAUSS_DIAG, GAUSS_DENSE, LOGREG = 0, 1, 2, 3
 TAG_MOMENTUM, TAG_ACCEPT, TAG_SWAP = 0, 1, 2
@@ -45,8 +47,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        srcs = [os.path.join(os.path.dirname(_LIB_PATH), f) for f in ("oracle.c", "oracle.h")]
-        if not os.path.exists(_LIB_PATH) or max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(_LIB_PATH):
+        srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "oracle.h")]
+        if not _LIB_OVERRIDE and (not os.path.exists(_LIB_PATH)
+                                  or max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(_LIB_PATH)):
             from . import build as _b  # noqa: F401  (build script beside the source)
             _b.build()
         L = ctypes.CDLL(_LIB_PATH)

@@ -214,7 +214,7 @@ static double logp_grad_x(const orc_target *tg, const double *x, double *g)
     default:
         logp = NAN;
     }
-    /* tempered target (replica exchange, paper Sec. 3.1): beta * logp */
+    /* tempered target (replica exchange, paper Sec. 2.2): beta * logp */
     if (tg->beta != 1.0) {
         logp *= tg->beta;
         for (int64_t i = 0; i < D; ++i)
@@ -427,7 +427,7 @@ int orc_sample_chain(const orc_target *tg, int64_t C, int32_t L, uint64_t seed,
 }
 
 /* ------------------------------------------------------------------------
- * Replica exchange (paper Sec. 3.1): replica k targets p(x)^beta_k; the
+ * Replica exchange (paper Sec. 2.2): replica k targets p(x)^beta_k; the
  * exchange of the states x_a (replica a) and x_b (replica b) is a
  * Metropolis-Hastings move on the product of the replica targets, with ratio
  *   p(x_b)^beta_a p(x_a)^beta_b / (p(x_a)^beta_a p(x_b)^beta_b)
@@ -521,7 +521,7 @@ int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L
 
 /* ------------------------------------------------------------------------
  * No-U-Turn sampler, Hoffman & Gelman (2014), Algorithm 3 (the paper's
- * Sec. 3.2 case study vectorises this recursion).  A state carries its
+ * Sec. 2.3 case study vectorises this recursion).  A state carries its
  * position, momentum, gradient and log-probability so that each leapfrog
  * step starts from the cached gradient.
  * ---------------------------------------------------------------------- */

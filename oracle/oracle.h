@@ -55,7 +55,7 @@ typedef struct {
     double prior_scale;    /* LOGREG: prior N(0, prior_scale^2 I) */
     double beta;           /* inverse temperature: the log-probability and its
                               gradient are multiplied by beta (1 = untempered;
-                              replica exchange, paper Sec. 3.1) */
+                              replica exchange, paper Sec. 2.2) */
     const double *scale;   /* transformed kernel (paper Sec. 4.1): when not NULL the
                               chain moves in z with x = shift + scale * z (diagonal
                               affine bijector); logp is evaluated at x(z) and the
@@ -148,7 +148,7 @@ int orc_sample_chain(const orc_target *tg, int64_t C, int32_t L, uint64_t seed,
                      double rate, double *samples, double *tr_step, uint8_t *tr_acc, double *tr_lar,
                      double *tr_logp, int32_t nthreads);
 
-/* ---- Replica exchange Monte Carlo (paper Sec. 3.1, case study REMC) ----
+/* ---- Replica exchange Monte Carlo (paper Sec. 2.2, case study REMC) ----
  * K replicas of M chains each, replica-major: chain c = k*M + m is chain m of
  * replica k, whose target is tgs[k] (the same target with inverse temperature
  * beta_k; replica k's log-probability is beta_k times the target's).
@@ -180,7 +180,7 @@ int orc_remc_sample_chain(const orc_target *tgs, int64_t K, int64_t M, int32_t L
                           double t0, double kappa, double rate, double *samples, uint8_t *tr_acc,
                           uint8_t *tr_swap, int32_t nthreads);
 
-/* ---- No-U-Turn sampler (paper Sec. 3.2; Hoffman & Gelman 2014, Algorithm 3,
+/* ---- No-U-Turn sampler (paper Sec. 2.3; Hoffman & Gelman 2014, Algorithm 3,
  * "efficient NUTS") ----
  * One transition of one chain from (x, *logp, g): momentum r0 as HMC's;
  * slice log u = log U - H0 with U the uniform of block (chain, t, 0, tag 6);

@@ -30,14 +30,23 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+# Host-runtime sanitizer build: AddressSanitizer and UndefinedBehaviorSanitizer on
+# the host side of every source only (the kernels are built as usual); the
+# resulting library needs the compiler's ASan runtime preloaded.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, jobs: int = 8, sanitize: bool = False, out: str = LIB,
+          build_dir: str = BUILD_DIR) -> str:
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
-    objs = [os.path.join(BUILD_DIR, os.path.basename(s) + ".o") for s in srcs]
+    objs = [os.path.join(build_dir, os.path.basename(s) + ".o") for s in srcs]
+    san = HOST_SANITIZE if sanitize else []
 
     def compile_one(pair):
         src, obj = pair
-        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+        cmd = [HIPCC, *FLAGS, *san, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,13 +58,14 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(compile_one, zip(srcs, objs)))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]
+    tmp = out + ".tmp"
+    link_san = [*HOST_SANITIZE[:4], "-shared-libsan"] if sanitize else []
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *link_san, "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -612,7 +612,7 @@ extern "C" hmc_status hmc_autotune(hmc_ctx* ctx, int32_t trial_transitions, char
 }
 
 // ---------------------------------------------------------------------------
-// Replica exchange (paper Sec. 3.1): per-chain inverse temperatures on the
+// Replica exchange (paper Sec. 2.2): per-chain inverse temperatures on the
 // plain / graph forms, the exchange step, and the driver that alternates one
 // transition of every chain with one exchange step.
 // ---------------------------------------------------------------------------
@@ -826,7 +826,7 @@ extern "C" hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale)
 }
 
 // ---------------------------------------------------------------------------
-// No-U-Turn sampler (paper Sec. 3.2): the unrolled tree on the plain kernels,
+// No-U-Turn sampler (paper Sec. 2.3): the unrolled tree on the plain kernels,
 // all chains in lockstep, a chain masked once its trajectory stops; the host
 // reads the number of chains still running after every doubling.
 // ---------------------------------------------------------------------------

@@ -31,6 +31,7 @@
 // waves draw momenta for the next 32 transitions, and accept uniforms and
 // dual-averaging factors for the next 128, into LDS whenever a block of them
 // runs out; they would otherwise wait for the owners at the transition boundary.
+#include "exp_f64.hpp"
 #include "hmc_internal.hpp"
 
 namespace hmc {
@@ -158,27 +159,6 @@ struct OutPtrs {
     gptr<double> tlp;
     gptr<double> dh;
 };
-
-// e^x in FP64 with its polynomial coefficients read from LDS (a table the
-// loop cannot keep in registers): x = k ln2 + r with a two-part ln2 and
-// |r| <= ln2 / 2, e^r from its Taylor series through r^13 (the remainder is
-// below 2^-56 e^r), times 2^k.  x below -745.2 gives 0, +inf gives +inf.
-constexpr int EXP_NC = 14;
-__host__ __device__ constexpr double exp_coef(int n) {   // 1 / n!
-    double f = 1.0;
-    for (int i = 2; i <= n; ++i) f *= (double)i;
-    return 1.0 / f;
-}
-__device__ __forceinline__ double exp_lds(double x, const double* cf) {
-    if (!(x > -745.2)) return x != x ? x : 0.0;
-    if (x > 709.8) return INFINITY;
-    const double k = rint(x * 1.4426950408889634);
-    const double r = fma(-k, 1.9082149292705877e-10, fma(-k, 0.6931471803691238, x));
-    double s = cf[EXP_NC - 1];
-#pragma unroll
-    for (int n = EXP_NC - 2; n >= 0; --n) s = fma(s, r, cf[n]);
-    return ldexp(s, (int)k);
-}
 
 // TP: the chains carry inverse temperatures and / or the context a transform
 // (a template parameter, so that plain runs compile without either).  The

@@ -1,5 +1,5 @@
 // k_nuts.hip -- the No-U-Turn sampler with its recursion unrolled (paper
-// Sec. 3.2; Hoffman & Gelman 2014, Algorithm 3, "efficient NUTS").
+// Sec. 2.3; Hoffman & Gelman 2014, Algorithm 3, "efficient NUTS").
 //
 // All chains advance in lockstep through the same schedule: doubling j builds
 // a subtree of 2^j leaves; leaf i is one leapfrog step (a half kick here, then

@@ -6,7 +6,7 @@
 //   k_end         energy at the trajectory end, dH, Metropolis test,
 //                 per-chain select, dual averaging, sample/trace writes  (Sec. 2.1, 4.2)
 //   k_tick        t += 1 (device-resident, so a captured graph replays unchanged)
-//   k_remc_exchange  replica exchange between neighbouring temperatures (Sec. 3.1)
+//   k_remc_exchange  replica exchange between neighbouring temperatures (Sec. 2.2)
 //
 // Inverse temperatures (replica exchange): chain c targets beta_c logp.  The
 // cached logp and gradient stay those of the untempered target; beta_c
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k_copy_proposal(PlainArgs a) {
     }
 }
 
-// Replica exchange (Sec. 3.1): chain c = k M + m is chain m of replica k.  The
+// Replica exchange (Sec. 2.2): chain c = k M + m is chain m of replica k.  The
 // pairs (k, k+1) of the parity class of t exchange the states (x, g, logp) of
 // chains k M + m and (k+1) M + m with probability
 // min(1, exp((beta_k - beta_{k+1}) (logp_{k+1} - logp_k))) (untempered logp),

@@ -14,7 +14,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhmc.so")
+# HMC_LIB_PATH selects another build of the same library (the sanitizer build of
+# the host runtime); there is no fallback when the file is missing.
+LIB_PATH = os.environ.get("HMC_LIB_PATH") or os.path.join(_HERE, "libhmc.so")
 
 # hmc_status
 HMC_OK, HMC_E_INVALID, HMC_E_UNSUPPORTED, HMC_E_NOMEM, HMC_E_DEVICE, HMC_E_BUSY = range(6)

@@ -1,4 +1,4 @@
-"""GPU parity of the unrolled No-U-Turn sampler (paper Sec. 3.2) against the
+"""GPU parity of the unrolled No-U-Turn sampler (paper Sec. 2.3) against the
 oracle's recursive NUTS (Hoffman & Gelman 2014, Algorithm 3) on the same
 counter-keyed random numbers.
 

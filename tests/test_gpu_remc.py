@@ -1,4 +1,4 @@
-"""GPU parity of replica exchange (paper Sec. 3.1) through the C ABI against the
+"""GPU parity of replica exchange (paper Sec. 2.2) through the C ABI against the
 FP64 oracle.
 
 Chains are K replicas of M chains, replica-major; chain c targets beta_c logp.

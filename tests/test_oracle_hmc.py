@@ -340,6 +340,48 @@ def test_dual_averaging_fixed_point_and_direction():
     assert hb3[-1] == pytest.approx(0.5 * 7 / (7 + 10), rel=1e-13)
 
 
+def test_dual_averaging_first_iterates_by_hand():
+    # Hoffman & Gelman (2014) eq. 6 with gamma 0.05, t0 10, kappa 0.75, delta 0.8, eps0 = 0.5 (mu = log 5,
+    # not 0) and scripted statistics 0.2, 0.9, 0.5. The values below were simplified by hand:
+    #   Hbar_1 = 0.6/11, Hbar_2 = 0.5/12, Hbar_3 = 0.8/13 (Hbar_m = sum_i (delta - alpha_i) / (m + t0)),
+    #   log eps_m = log 5 - 20 sqrt(m) Hbar_m = log 5 - 12/11, log 5 - 5 sqrt(2)/6, log 5 - 16 sqrt(3)/13,
+    #   log ebar_1 = log eps_1 (first weight 1^-kappa = 1), then the weight of the new iterate is m^-kappa.
+    le, hb, leb, mu = oracle.dual_avg_run(0.5, [0.2, 0.9, 0.5])
+    l5 = np.log(5.0)
+    assert mu == pytest.approx(l5, rel=1e-15)
+    assert hb == pytest.approx([0.6 / 11, 0.5 / 12, 0.8 / 13], rel=1e-14)
+    e1, e2, e3 = l5 - 12 / 11, l5 - 5 * np.sqrt(2) / 6, l5 - 16 * np.sqrt(3) / 13
+    assert le == pytest.approx([e1, e2, e3], rel=1e-14)
+    w2, w3 = 2.0 ** -0.75, 3.0 ** -0.75
+    b2 = w2 * e2 + (1 - w2) * e1
+    assert leb == pytest.approx([e1, b2, w3 * e3 + (1 - w3) * b2], rel=1e-14)
+    # numerically: log ebar = 0.51849..., 0.53167..., 0.38339... (iterates move, so a swapped weight shows)
+    assert leb[1] != pytest.approx(w2 * e1 + (1 - w2) * e2, rel=1e-3)
+
+
+def test_dual_averaging_iterate_average_special_cases():
+    # kappa = 1: the averaged iterate is the arithmetic (Polyak) mean of log eps_1..m;
+    # kappa = 0: it is the last iterate; any kappa in (0, 1]: a convex combination with weights
+    # w_i = i^-kappa prod_{j>i} (1 - j^-kappa), which sum to 1 (the unrolled recursion).
+    rng = np.random.default_rng(17)
+    alphas = rng.uniform(0, 1, size=60)
+    eps0 = 0.37
+    le, hb, leb, _ = oracle.dual_avg_run(eps0, alphas, kappa=1.0)
+    m = np.arange(1, 61)
+    assert leb == pytest.approx(np.cumsum(le) / m, rel=1e-12, abs=1e-13)
+    # Hbar_m is the t0-shrunk running mean of (delta - alpha)
+    assert hb == pytest.approx(np.cumsum(0.8 - alphas) / (m + 10.0), rel=1e-12, abs=1e-15)
+    le0, _, leb0, _ = oracle.dual_avg_run(eps0, alphas, kappa=0.0)
+    assert np.array_equal(leb0, le0)
+    le7, _, leb7, _ = oracle.dual_avg_run(eps0, alphas, kappa=0.75)
+    M = 60
+    w = np.array([i ** -0.75 * np.prod([1 - j ** -0.75 for j in range(i + 1, M + 1)]) for i in range(1, M + 1)])
+    assert w.sum() == pytest.approx(1.0, rel=1e-13)
+    assert leb7[-1] == pytest.approx(np.dot(w, le7), rel=1e-12)
+    # the log step sizes themselves vary by O(1) here, so these identities are not vacuous
+    assert np.ptp(le7) > 1.0
+
+
 def test_dual_averaging_reaches_target_acceptance():
     tg = Target(oracle.GAUSS_DIAG, 10, prec=np.linspace(1, 25, 10))
     C = 200

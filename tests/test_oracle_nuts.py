@@ -1,4 +1,4 @@
-"""Pins of the oracle's No-U-Turn sampler (paper Sec. 3.2; Hoffman & Gelman
+"""Pins of the oracle's No-U-Turn sampler (paper Sec. 2.3; Hoffman & Gelman
 2014, Algorithm 3).
 
   * max_depth 0 never moves; max_depth 1 is one leapfrog step of size v eps

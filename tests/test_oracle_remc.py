@@ -1,4 +1,4 @@
-"""Pins of the oracle's replica exchange (paper Sec. 3.1, case study REMC).
+"""Pins of the oracle's replica exchange (paper Sec. 2.2, case study REMC).
 
 Replica k targets p(x)^beta_k, i.e. beta_k times the log-probability (the
 paper's replica target function multiplies the log-probability by the
