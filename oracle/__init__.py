@@ -244,6 +244,36 @@ def step(tg: Target, L: int, seed: int, t: int, eps, x, logp=None, g=None, nthre
                 log_accept_ratio=lar, accepted=acc.astype(bool))
 
 
+def step_chains(tg: Target, L: int, seed: int, t: int, eps, x_rows, chain_ids, nthreads: int = 0):
+    """Transition t of the chains with the given ids only (rows of x_rows are their
+    states): the same Philox streams as `step` over all chains, for full-size
+    workloads whose every chain the oracle cannot afford.  Chains run on a
+    thread pool (the C call releases the GIL).  Returns the same fields as `step`."""
+    from concurrent.futures import ThreadPoolExecutor
+    x = _f64(x_rows).copy()
+    K, D = x.shape
+    ids = [int(c) for c in chain_ids]
+    assert len(ids) == K
+    eps = np.broadcast_to(_f64(eps), (K,)).copy()
+    logp, g = np.empty(K), np.empty_like(x)
+    xp, pp = np.empty_like(x), np.empty_like(x)
+    lpp, dh, lar = np.empty(K), np.empty(K), np.empty(K)
+    acc = np.empty(K, dtype=bool)
+
+    def one(i):
+        lp = ctypes.c_double(lib().orc_logp_grad(tg.c, _p(x[i]), _p(g[i])))
+        d = [ctypes.c_double() for _ in range(3)]
+        a = lib().orc_transition(tg.c, seed, ids[i], t, L, float(eps[i]), _p(x[i]), ctypes.byref(lp), _p(g[i]),
+                                 _p(xp[i]), _p(pp[i]), ctypes.byref(d[0]), ctypes.byref(d[1]), ctypes.byref(d[2]))
+        logp[i], lpp[i], dh[i], lar[i], acc[i] = lp.value, d[0].value, d[1].value, d[2].value, bool(a)
+
+    workers = nthreads if nthreads > 0 else min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(one, range(K)))
+    return dict(x=x, logp=logp, g=g, x_prop=xp, p_prop=pp, logp_prop=lpp, delta_h=dh,
+                log_accept_ratio=lar, accepted=acc)
+
+
 def dual_avg_run(eps0: float, alphas, target_accept=0.8, gamma=0.05, t0=10.0, kappa=0.75):
     """Run the dual-averaging recursion over a scripted alpha sequence; returns
     arrays (log_eps, hbar, log_eps_bar) after each iteration m = 1..len(alphas)."""

@@ -7,8 +7,9 @@ ticks).  Admission follows the HBM budget."""
 import numpy as np
 import pytest
 
+import oracle
 import workloads as W
-from gpu_helpers import gpu_available, to_np
+from gpu_helpers import gpu_available, oracle_target, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -28,7 +29,8 @@ def _requests():
     d = W.gauss_dense(dim=37, num_chains=45, L=7, step_size=0.1, burnin=10, results=12, seed=15)
     e = W.logreg(1000, 25, 64, L=5, step_size=0.05, burnin=25, results=15, seed=16)
     f = W.logreg(3000, 40, 100, L=4, step_size=0.01, burnin=6, results=9, seed=17, init=0.3)
-    return [a, b, b2, c, d, e, f]
+    g = W.logreg(2000, 300, 48, L=4, step_size=0.005, burnin=5, results=6, seed=18, bf16=True, init=0.1)
+    return [a, b, b2, c, d, e, f, g]
 
 
 def _reference(w):
@@ -53,7 +55,7 @@ def test_server_results_equal_sample_chain_alone_and_in_mix():
         alone.append(out)
     # mix: the long diagonal Gaussians first, the rest arriving while they run,
     # some with server-held samples
-    order = [1, 2, 0, 3, 4, 5, 6]
+    order = [1, 2, 0, 3, 4, 7, 5, 6]
     preps = {i: srv.prepare(reqs[i], server_samples=(n % 2 == 1)) for n, i in enumerate(order)}
     mix_ids = {}
     for i in order:
@@ -92,3 +94,32 @@ def test_server_admission_follows_budget():
     srv.close()
     # different seeds give different chains; same seed reproduces
     assert not torch.equal(outs[0]["samples"], outs[1]["samples"])
+
+
+def test_served_results_match_oracle():
+    # a mix served together (fixed step sizes, so trajectories are comparable chain by
+    # chain): the paper's FP64 example exactly, FP32 diagonal-Gaussian and logistic
+    # requests (one with D > 256 and BF16-stored X) to the FP32 trajectory tolerance
+    reqs = [W.std_normal_1d(num_chains=100, burnin=40, results=20, seed=21),
+            W.gauss_diag(dim=100, num_chains=200, L=8, step_size=0.05, burnin=30, results=30, seed=22),
+            W.logreg(1000, 25, 64, L=5, step_size=0.05, burnin=25, results=15, seed=23),
+            W.logreg(2000, 300, 48, L=4, step_size=0.005, burnin=8, results=8, seed=24, bf16=True, init=0.05)]
+    for w in reqs:
+        w.adapt = False
+    srv = hmc.Server(2 << 30, transitions_per_tick=6)
+    ids = [srv.submit(w) for w in reqs]
+    outs = [srv.wait(i)[0] for i in ids]
+    srv.close()
+    for w, out in zip(reqs, outs):
+        o = oracle.sample_chain(oracle_target(w), w.num_leapfrog_steps, w.seed, w.x0.astype(np.float64),
+                                w.step_size, w.num_burnin, w.num_results)
+        g_smp = to_np(out["samples"]).astype(np.float64)
+        g_acc = to_np(out["is_accepted"]).astype(bool)
+        agree = float(np.mean(g_acc == o["is_accepted"]))
+        err = np.linalg.norm(g_smp - o["samples"], axis=-1) / np.maximum(np.linalg.norm(o["samples"], axis=-1), 1e-30)
+        print(f"served {w.name}: decisions agree {agree:.5f}; sample rel err p50={np.median(err):.2e} "
+              f"max={err.max():.2e}")
+        if w.state_dtype == "f64":
+            assert agree == 1.0 and np.max(np.abs(g_smp - o["samples"])) <= 1e-12
+        else:
+            assert agree >= 0.999 and np.median(err) < 1e-5

@@ -393,3 +393,15 @@ def test_dual_averaging_reaches_target_acceptance():
     # step size frozen after burn-in, per chain
     assert np.all(out["step_size"] == out["step_size"][0:1])
     assert np.allclose(out["final_eps"], out["step_size"][-1])
+
+
+def test_step_on_selected_chains_equals_step_on_all():
+    # step_chains runs chosen chain ids only (for full-size workloads); the streams are
+    # keyed by chain id, so it equals the all-chain step on those rows, bitwise
+    tg = _logreg_target(N=40, D=5, seed=8)
+    x = np.random.default_rng(3).normal(size=(23, 5)) * 0.4
+    full = oracle.step(tg, 4, seed=6, t=9, eps=0.1, x=x)
+    ids = [0, 4, 5, 22]
+    sub = oracle.step_chains(tg, 4, 6, 9, 0.1, x[ids], ids, nthreads=3)
+    for k in ("x", "logp", "g", "x_prop", "p_prop", "logp_prop", "delta_h", "log_accept_ratio", "accepted"):
+        assert np.array_equal(full[k][ids], sub[k]), k
