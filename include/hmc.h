@@ -178,6 +178,32 @@ hmc_status hmc_set_state(hmc_ctx* ctx, const void* state, const double* step_siz
 /* Frees the context (synchronizes its stream first).  NULL is a no-op. */
 hmc_status hmc_destroy(hmc_ctx* ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hmc_init,
+ * hmc_sample_chain and hmc_get_state in one call, with the workspace taken
+ * from a library-owned static device array of HMC_NOALLOC_WORKSPACE_BYTES
+ * per GPU instead of a caller-allocated buffer.  No hipMalloc, hipFree or
+ * allocating library call is made.  Arguments as hmc_init (without the
+ * workspace) and hmc_sample_chain; final_state [C, D] (device, state dtype)
+ * and final_step_size [C] (device, FP64) receive the state and step sizes
+ * after the last transition and may be NULL.  The samples and traces equal
+ * those of hmc_init + hmc_sample_chain on the same inputs, bit for bit.
+ * Errors: HMC_E_NOMEM when hmc_workspace_size() exceeds the scratch (the
+ * message gives both sizes; nothing is launched), HMC_E_UNSUPPORTED for
+ * HMC_FORM_GRAPH (instantiating a graph allocates), HMC_E_INVALID when
+ * hip_stream belongs to a device other than the current one.  Synchronizes
+ * hip_stream before returning.  Every call on a GPU shares that GPU's scratch
+ * (the array keeps the last call's contents; each call initialises all it
+ * reads): calls that overlap on one GPU, from several threads or streams,
+ * race and must be serialised by the caller. */
+#define HMC_NOALLOC_WORKSPACE_BYTES (64ll << 20)
+hmc_status hmc_sample_chain_noalloc(const hmc_target* target, const hmc_config* config,
+                                    const void* init_state, const double* step_size,
+                                    int64_t step_size_len, int64_t num_results,
+                                    int64_t num_burnin_steps, const hmc_adapt* adapt,
+                                    void* samples, const hmc_trace* trace, void* final_state,
+                                    double* final_step_size, void* hip_stream);
+
 /* Message of the last non-OK status on this thread ("" if none). */
 const char* hmc_last_error(void);
 

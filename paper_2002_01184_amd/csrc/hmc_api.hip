@@ -204,13 +204,14 @@ static Ctrl base_ctrl(const hmc_ctx* ctx) {
     return c;
 }
 
-hmc_status hmc_init(const hmc_target* target, const hmc_config* config, const void* init_state,
-                    const double* step_size, int64_t step_size_len, void* workspace, size_t workspace_bytes,
-                    void* hip_stream, hmc_ctx** out) {
-    TargetDev t;
-    hmc_status st = validate_args(target, config, &t);
+}  // extern "C"
+
+// Argument checks of hmc_init that need no device: the target, the config,
+// the initial state pointer and the step sizes.
+static hmc_status check_init_args(const hmc_target* target, const hmc_config* config, const void* init_state,
+                                  const double* step_size, int64_t step_size_len, TargetDev* t) {
+    hmc_status st = validate_args(target, config, t);
     if (st != HMC_OK) return st;
-    if (!out) return fail(HMC_E_INVALID, "out must not be NULL");
     if (!init_state) return fail(HMC_E_INVALID, "init_state must not be NULL");
     if (!step_size) return fail(HMC_E_INVALID, "step_size must not be NULL");
     if (step_size_len != 1 && step_size_len != config->num_chains)
@@ -218,13 +219,14 @@ hmc_status hmc_init(const hmc_target* target, const hmc_config* config, const vo
     for (int64_t i = 0; i < step_size_len; ++i)
         if (!(step_size[i] > 0.0) || !std::isfinite(step_size[i]))
             return fail(HMC_E_INVALID, "step sizes must be finite and > 0");
-    size_t need = 0;
-    carve_workspace(nullptr, t, *config, &need);
-    if (!workspace) return fail(HMC_E_INVALID, "workspace must not be NULL");
-    if (((uintptr_t)workspace & 255) != 0) return fail(HMC_E_INVALID, "workspace must be 256-byte aligned");
-    if (workspace_bytes < need) return fail(HMC_E_NOMEM, "workspace smaller than hmc_workspace_size()");
+    return HMC_OK;
+}
 
-    hmc_ctx* ctx = new hmc_ctx();
+// hmc_init's device work on a context the caller owns: carve the workspace,
+// pick the form, upload step sizes, bootstrap.  Arguments already checked.
+static hmc_status init_ctx(hmc_ctx* ctx, const TargetDev& t, const hmc_config* config, const void* init_state,
+                           const double* step_size, int64_t step_size_len, void* workspace, void* hip_stream) {
+    hmc_status st = HMC_OK;
     ctx->cfg = *config;
     ctx->stream = (hipStream_t)hip_stream;
     ctx->t = 0;
@@ -243,10 +245,7 @@ hmc_status hmc_init(const hmc_target* target, const hmc_config* config, const vo
     switch (config->form) {
     case HMC_FORM_AUTO: ctx->form = can_fuse ? HMC_FORM_FUSED : HMC_FORM_PLAIN; break;
     case HMC_FORM_FUSED:
-        if (!can_fuse) {
-            delete ctx;
-            return fail(HMC_E_UNSUPPORTED, "no fused kernel for this target shape");
-        }
+        if (!can_fuse) return fail(HMC_E_UNSUPPORTED, "no fused kernel for this target shape");
         ctx->form = HMC_FORM_FUSED;
         break;
     default: ctx->form = config->form;
@@ -258,6 +257,25 @@ hmc_status hmc_init(const hmc_target* target, const hmc_config* config, const vo
     if (st == HMC_OK) st = check_hip(launch_da_init(a, ctx->stream), "init adaptation");
     if (st == HMC_OK) st = check_hip(launch_bootstrap(a, init_state, ctx->stream), "bootstrap");
     if (st == HMC_OK) st = check_hip(hipStreamSynchronize(ctx->stream), "bootstrap");
+    return st;
+}
+
+extern "C" {
+
+hmc_status hmc_init(const hmc_target* target, const hmc_config* config, const void* init_state,
+                    const double* step_size, int64_t step_size_len, void* workspace, size_t workspace_bytes,
+                    void* hip_stream, hmc_ctx** out) {
+    TargetDev t;
+    hmc_status st = check_init_args(target, config, init_state, step_size, step_size_len, &t);
+    if (st != HMC_OK) return st;
+    if (!out) return fail(HMC_E_INVALID, "out must not be NULL");
+    size_t need = 0;
+    carve_workspace(nullptr, t, *config, &need);
+    if (!workspace) return fail(HMC_E_INVALID, "workspace must not be NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(HMC_E_INVALID, "workspace must be 256-byte aligned");
+    if (workspace_bytes < need) return fail(HMC_E_NOMEM, "workspace smaller than hmc_workspace_size()");
+    hmc_ctx* ctx = new hmc_ctx();
+    st = init_ctx(ctx, t, config, init_state, step_size, step_size_len, workspace, hip_stream);
     if (st != HMC_OK) {
         delete ctx;
         return st;
@@ -411,6 +429,84 @@ hmc_status hmc_destroy(hmc_ctx* ctx) {
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     delete ctx;
     return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Sampling without device allocation: the workspace of hmc_sample_chain_noalloc
+// is this file-scope array, one copy per GPU, held until the process ends.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it is only a stand-in for the symbol): the device address of each GPU's copy
+// is looked up once per device with that device current and kept here.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[HMC_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+hmc_status scratch_for_device(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(HMC_E_DEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hmc_status st = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch address");
+        if (st != HMC_OK) return st;
+        if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(HMC_E_DEVICE, "scratch address not 256-byte aligned");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HMC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hmc_status hmc_sample_chain_noalloc(const hmc_target* target, const hmc_config* config, const void* init_state,
+                                    const double* step_size, int64_t step_size_len, int64_t num_results,
+                                    int64_t num_burnin_steps, const hmc_adapt* adapt, void* samples,
+                                    const hmc_trace* trace, void* final_state, double* final_step_size,
+                                    void* hip_stream) {
+    TargetDev t;
+    hmc_status st = check_init_args(target, config, init_state, step_size, step_size_len, &t);
+    if (st != HMC_OK) return st;
+    if (config->form == HMC_FORM_GRAPH)
+        return fail(HMC_E_UNSUPPORTED, "the graph form instantiates a graph, which allocates; use plain, fused or auto");
+    if (num_results < 0 || num_burnin_steps < 0) return fail(HMC_E_INVALID, "negative transition count");
+    if (num_results + num_burnin_steps > 0xffffffffll) return fail(HMC_E_INVALID, "more than 2^32 transitions");
+    if (adapt && adapt->enabled && check_adapt(adapt) != HMC_OK) return HMC_E_INVALID;
+    size_t need = 0;
+    carve_workspace(nullptr, t, *config, &need);
+    if (need > (size_t)HMC_NOALLOC_WORKSPACE_BYTES)
+        return fail(HMC_E_NOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the " +
+                                     std::to_string((long long)HMC_NOALLOC_WORKSPACE_BYTES) +
+                                     "-byte scratch of hmc_sample_chain_noalloc; use hmc_init with a workspace");
+
+    // the stream's device must be the current one: its scratch copy is the one looked up
+    int cur = -1, sdev = -1;
+    st = check_hip(hipGetDevice(&cur), "current device");
+    if (st == HMC_OK) st = check_hip(hipStreamGetDevice((hipStream_t)hip_stream, &sdev), "stream device");
+    if (st != HMC_OK) return st;
+    if (sdev != cur) return fail(HMC_E_INVALID, "hip_stream belongs to another device than the current one");
+    void* ws = nullptr;
+    st = scratch_for_device(cur, &ws);
+    if (st != HMC_OK) return st;
+
+    hmc_ctx ctx{};
+    st = init_ctx(&ctx, t, config, init_state, step_size, step_size_len, ws, hip_stream);
+    if (st == HMC_OK) st = hmc_sample_chain(&ctx, num_results, num_burnin_steps, adapt, samples, trace);
+    const size_t es = ctx.a.f64 ? 8 : 4;
+    if (st == HMC_OK && final_state)
+        st = check_hip(hipMemcpyAsync(final_state, ctx.a.ws.x, (size_t)ctx.a.C * t.D * es, hipMemcpyDeviceToDevice,
+                                      ctx.stream), "copy final state");
+    if (st == HMC_OK && final_step_size)
+        st = check_hip(hipMemcpyAsync(final_step_size, ctx.a.ws.eps, (size_t)ctx.a.C * 8, hipMemcpyDeviceToDevice,
+                                      ctx.stream), "copy final step sizes");
+    // the context ends with this call, so its work must have left the scratch
+    const hmc_status sync = check_hip(hipStreamSynchronize((hipStream_t)hip_stream), "sample_chain_noalloc");
+    return st != HMC_OK ? st : sync;
 }
 
 }  // extern "C"

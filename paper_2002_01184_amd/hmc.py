@@ -99,7 +99,9 @@ EXPORTED = ["hmc_workspace_size", "hmc_init", "hmc_step", "hmc_sample_chain", "h
             "hmc_remc_swap", "hmc_remc_sample_chain", "hmc_sample_chain_moments", "hmc_set_transform_scale",
             "hmc_nuts_workspace_size", "hmc_nuts_sample_chain", "hmc_server_create", "hmc_server_submit",
             "hmc_server_poll", "hmc_server_wait", "hmc_server_take", "hmc_server_get_stats",
-            "hmc_server_destroy"]
+            "hmc_server_destroy", "hmc_sample_chain_noalloc"]
+
+HMC_NOALLOC_WORKSPACE_BYTES = 64 << 20
 
 _lib = None
 
@@ -131,6 +133,11 @@ def lib():
     L.hmc_set_state.restype = st
     L.hmc_destroy.argtypes = [vp]
     L.hmc_destroy.restype = st
+    L.hmc_sample_chain_noalloc.argtypes = [ctypes.POINTER(hmc_target), ctypes.POINTER(hmc_config), vp,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.POINTER(hmc_adapt), vp, ctypes.POINTER(hmc_trace),
+                                           vp, vp, vp]
+    L.hmc_sample_chain_noalloc.restype = st
     L.hmc_last_error.argtypes = []
     L.hmc_last_error.restype = ctypes.c_char_p
     L.hmc_effective_form.argtypes = [vp]
@@ -206,6 +213,17 @@ def hmc_sample_chain(ctx, num_results, num_burnin_steps, adapt: hmc_adapt | None
     _check(lib().hmc_sample_chain(ctx, num_results, num_burnin_steps,
                                   ctypes.byref(adapt) if adapt is not None else None, samples_ptr,
                                   ctypes.byref(trace) if trace is not None else None))
+
+
+def hmc_sample_chain_noalloc(target, config, init_state_ptr, step_sizes, num_results, num_burnin_steps,
+                             adapt: hmc_adapt | None, samples_ptr, trace: hmc_trace | None, final_state_ptr,
+                             final_step_size_ptr, stream_ptr):
+    arr = (ctypes.c_double * len(step_sizes))(*[float(v) for v in step_sizes])
+    _check(lib().hmc_sample_chain_noalloc(ctypes.byref(target), ctypes.byref(config), init_state_ptr, arr,
+                                          len(step_sizes), num_results, num_burnin_steps,
+                                          ctypes.byref(adapt) if adapt is not None else None, samples_ptr,
+                                          ctypes.byref(trace) if trace is not None else None, final_state_ptr,
+                                          final_step_size_ptr, stream_ptr))
 
 
 def hmc_sample_chain_moments(ctx, num_results, num_burnin_steps, adapt: hmc_adapt | None, moments: hmc_moments,

@@ -100,3 +100,21 @@ def test_workspace_sizes_across_targets_and_forms():
         except hmc.HMCError as e:            # a combination the header lists as unsupported
             assert e.status == hmc.HMC_E_UNSUPPORTED, hmc.lib().hmc_last_error()
     assert len(sizes) >= len(cases) // 2 and all(s > 0 for s in sizes)
+
+
+def test_noalloc_rejects_without_device_work():
+    # the allocation-free entry point checks its size limit and form before any HIP call
+    fake = ctypes.c_void_p(1 << 20)
+    t = _target(kind=hmc.HMC_TGT_LOGREG, dim=256, X=fake, x_dtype=hmc.HMC_BF16, n_rows=100000, y=fake)
+    c = _config(C=8192, sd=hmc.HMC_F32, gd=hmc.HMC_BF16)
+    assert hmc.hmc_workspace_size(t, c) > hmc.HMC_NOALLOC_WORKSPACE_BYTES
+    with pytest.raises(hmc.HMCError) as e:
+        hmc.hmc_sample_chain_noalloc(t, c, fake, [0.005], 10, 10, None, None, None, None, None, None)
+    assert e.value.status == hmc.HMC_E_NOMEM and "exceeds" in str(e.value)
+    with pytest.raises(hmc.HMCError) as e:
+        hmc.hmc_sample_chain_noalloc(_target(), _config(form=hmc.HMC_FORM_GRAPH), fake, [1.5], 10, 10, None, None,
+                                     None, None, None, None)
+    assert e.value.status == hmc.HMC_E_UNSUPPORTED
+    with pytest.raises(hmc.HMCError) as e:
+        hmc.hmc_sample_chain_noalloc(_target(), _config(), fake, [1.5], -1, 10, None, None, None, None, None, None)
+    assert e.value.status == hmc.HMC_E_INVALID
