@@ -2,15 +2,21 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--form auto|plain|graph|fused]
 
-One step = one complete sample_chain pass over the workload: reset the chains
-to the seeded start (bootstrap of logp and gradient), then burn-in with
-dual-averaging adaptation and sampling, every chain doing momentum draw,
-L leapfrog steps, energy, accept/select, adaptation, sample and trace writes.
-`value` is leapfrog chain-steps per second over the K timed steps (inputs
-resident in HBM).  ESS/s (bulk ESS, min over coordinates) is reported when the
-max split R-hat <= 1.01.  The roofline object refers to the dominant kernel,
-timed with HIP events on the stream it runs on; the cpu_baseline object is the
-FP64 oracle on a bounded sample of the same workload on the host's cores.
+Default workload: Bayesian logistic regression at scale (X 100000 x 256 stored
+BF16, 8192 chains, L = 10, gradients on BF16 MFMA).  One step = one block of
+transitions from the seeded start: reset the chains (bootstrap of logp and
+gradient), then 25 burn-in transitions with dual-averaging adaptation and 25
+kept ones, every chain doing momentum draw, L leapfrog steps, energy,
+accept/select, adaptation, sample and trace writes.  Other workloads run
+their configured burn-in + sampling schedule per step.  `value` is leapfrog
+chain-steps per second over the K timed steps (inputs resident in HBM).
+ESS/s (bulk ESS, min over coordinates, over the run's wall time) is reported
+when the max split R-hat <= 1.01, from a separate run with the workload's own
+burn-in when the timed steps are shorter.  The roofline object refers to the
+dominant kernel, its mean launch time taken by the library's kernel timer
+(HIP events on the stream it runs on) over the timed steps; roofline_step is
+the whole step.  The cpu_baseline object is the FP64 oracle on a bounded
+sample of the same workload on the host's cores.
 
 Prints ONE JSON line.
 """
@@ -98,9 +104,17 @@ def cpu_baseline(w, budget_s=12.0):
                         B, Ts - B, adapt=w.adapt, store_samples=False, nthreads=ncores)
     el = time.perf_counter() - t0
     value = nchains * w.num_leapfrog_steps * Ts / el
+    # one thread: one chain over a schedule of about a fifth of the budget
+    T1 = int(max(1, min(Ts, 0.2 * budget_s / max(per_chain_step * w.num_leapfrog_steps, 1e-12))))
+    t0 = time.perf_counter()
+    oracle.sample_chain(tg, w.num_leapfrog_steps, w.seed, w.x0[:1].astype(np.float64), w.step_size,
+                        min(B, T1 // 2), T1 - min(B, T1 // 2), adapt=w.adapt, store_samples=False, nthreads=1)
+    el1 = time.perf_counter() - t0
     return {"value": value, "unit": "leapfrog chain-steps/s", "cores": ncores, "kind": "oracle",
             "sample": f"first {nchains} of {w.num_chains} chains x {Ts} transitions (L={w.num_leapfrog_steps}), "
-                      f"FP64, {el:.1f} s wall"}
+                      f"FP64, {el:.1f} s wall",
+            "cpu_model": cpu_model(), "single_thread_value": w.num_leapfrog_steps * T1 / el1,
+            "single_thread_sample": f"chain 0 x {T1} transitions, {el1:.1f} s"}
 
 
 def ess_run(s, w, x0, eps0, n_results, num_burnin, chunk_s=20.0, per_tr=None):
@@ -484,13 +498,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="logreg_1000x25")
+    ap.add_argument("--config", default="auto_default",
+                    help="workload (default: logistic regression 100000 x 256 with BF16 X, 8192 chains)")
     ap.add_argument("--form", default="auto", choices=["auto", "plain", "graph", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diagnostics", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--grad", default="f32", choices=["f32", "bf16"],
-                    help="bf16: BF16 MFMA gradient contractions (logistic regression with BF16 X)")
+    ap.add_argument("--grad", default="auto", choices=["auto", "f32", "bf16"],
+                    help="bf16: BF16 MFMA gradient contractions (logistic regression with BF16 X); auto: bf16 where "
+                         "the workload stores X in BF16 and D <= 256")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: skip the FP32-gradient and secondary-workload lines")
     ap.add_argument("--transitions", type=int, default=None,
                     help="override burn-in + results (split evenly) for the large configurations")
     ap.add_argument("--requests", type=int, default=64, help="served_stream: number of requests")
@@ -513,6 +531,7 @@ def main():
     ap.add_argument("--ess-seconds", type=float, default=60.0,
                     help="time budget of the separate ESS run (burn-in included)")
     ap.add_argument("--ess-gb", type=float, default=16.0, help="memory budget of its kept samples (GiB)")
+    ap.add_argument("--ess-min-results", type=int, default=100, help="fewest kept draws worth an ESS run")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -528,6 +547,11 @@ def main():
     from paper_2002_01184_amd import hmc
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.config == "auto_default":
+        special = args.remc > 0 or args.moments or args.nuts > 0
+        args.config = "logreg_1000x25" if special else DEFAULT_CONFIG
+    if args.grad == "auto":
+        args.grad = "bf16" if args.config in BF16_X_CONFIGS else "f32"
     if args.config == "served_stream":
         print(json.dumps(bench_served(args)), flush=True)
         return
@@ -552,20 +576,63 @@ def main():
         print(json.dumps({"config": "copy_calibration", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
                           "copies": args.warmup + args.steps}), flush=True)
         return
+    result = bench_workload(args, args.config, args.grad, args.form, args.steps, args.warmup, args.transitions,
+                            ess=not args.no_diagnostics, cpu=not args.no_cpu_baseline, autotune=args.autotune)
+    if args.config == DEFAULT_CONFIG and not args.no_extras:
+        result["extras"] = default_extras(args)
+    print(json.dumps(result), flush=True)
+
+
+# The headline workload: logistic regression at scale (X 100000 x 256 stored
+# BF16, 8192 chains, L = 10), its gradients on BF16 MFMA.  A timed step is one
+# block of 25 adapted burn-in + 25 kept transitions from the seeded start.
+DEFAULT_CONFIG = "logreg_100000x256"
+DEFAULT_TRANSITIONS = {"logreg_100000x256": 50}
+BF16_X_CONFIGS = ("logreg_100000x256",)      # workloads whose X is stored in BF16 (D <= 256)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def bench_workload(args, config, grad, form_name, steps, warmup, transitions, ess=True, cpu=True, autotune=False,
+                   ess_seconds=None):
+    """One workload: warmup + timed steps (each a full burn-in + sampling pass from
+    the seeded start), the dominant kernel's mean launch time from the library's
+    kernel timer over the timed steps, R-hat / ESS, and the oracle baseline."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2002_01184_amd import diagnostics as dg
+    from paper_2002_01184_amd import hmc
+
     dev = torch.device("cuda:0")
-    w = W.CONFIGS[args.config]()
-    burnin_cfg = w.num_burnin           # the ESS run keeps the workload's own burn-in
-    if args.transitions is not None:
-        w.num_burnin = args.transitions // 2
-        w.num_results = args.transitions - w.num_burnin
+    w = W.CONFIGS[config]()
+    burnin_cfg, results_cfg = w.num_burnin, w.num_results     # the ESS run keeps the workload's own burn-in
+    if transitions is None:
+        transitions = DEFAULT_TRANSITIONS.get(config)
+    if transitions is not None:
+        w.num_burnin = transitions // 2
+        w.num_results = transitions - w.num_burnin
+    if grad == "auto":
+        grad = "bf16" if (w.X_bf16 is not None and w.dim <= 256) else "f32"
     form = {"auto": hmc.HMC_FORM_AUTO, "plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_GRAPH,
-            "fused": hmc.HMC_FORM_FUSED}[args.form]
-    s = hmc.sampler_for(w, device=dev, form=form, grad_bf16=args.grad == "bf16")
-    tune_report = s.autotune(2) if args.autotune else None
+            "fused": hmc.HMC_FORM_FUSED}[form_name]
+    s = hmc.sampler_for(w, device=dev, form=form, grad_bf16=grad == "bf16")
+    tune_report = s.autotune(2) if autotune else None
     x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).to(dev)
     eps0 = torch.full((w.num_chains,), float(w.step_size), dtype=torch.float64, device=dev)
     T = w.num_burnin + w.num_results
     stream = torch.cuda.current_stream(dev)
+    effective = hmc.hmc_effective_form(s.ctx)
 
     def one_step(ev=None):
         s.set_state(x0, eps0, 0)
@@ -576,88 +643,134 @@ def main():
             ev[1].record(stream)
         return out
 
-    for _ in range(args.warmup):
+    print(f"bench: {w.name} ({grad} gradients, form {s.form}): {warmup} warmup + {steps} timed steps of {T} "
+          f"transitions", file=sys.stderr, flush=True)
+    for _ in range(warmup):
         one_step()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    timed_launches = steps * (1 if effective == hmc.HMC_FORM_FUSED else T * w.num_leapfrog_steps)
+    timer = effective != hmc.HMC_FORM_GRAPH
+    if timer:
+        hmc.hmc_kernel_timer_start(s.ctx, timed_launches)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = None
-    for k in range(args.steps):
+    for k in range(steps):
         out = one_step(evs[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    chain_steps = w.chain_steps() * args.steps
+    chain_steps = w.chain_steps() * steps
     value = chain_steps / elapsed
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    step_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    if timer:
+        kern_ms, kern_n, kern_name = hmc.hmc_kernel_timer_read(s.ctx)
+    else:
+        kern_ms, kern_n, kern_name = step_ms, steps, "plain kernels (graph)"
+    per_launch_cs = w.chain_steps() if effective == hmc.HMC_FORM_FUSED else w.num_chains
+    print(f"bench: {w.name}: {value:.3e} chain-steps/s, {kern_name} {kern_ms:.4f} ms x {kern_n}", file=sys.stderr,
+          flush=True)
 
     bound, per_cs, unit = algorithmic_work(w)
     if bound == "mfma":
-        peak = PEAK["bf16_mfma"] if args.grad == "bf16" else PEAK["fp32_mfma"]
-        achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None}
-    elif hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED:
+        peak = PEAK["bf16_mfma"] if grad == "bf16" else PEAK["fp32_mfma"]
+        work = per_cs * per_launch_cs
+        roof = {"bound": "mfma", "achieved": work / (kern_ms * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": work / (kern_ms * 1e-3) / peak, "traffic": None}
+        step_work = per_cs * w.chain_steps()
+        roof_step = {"bound": "mfma", "achieved": step_work / (step_ms * 1e-3) / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": step_work / (step_ms * 1e-3) / peak,
+                     "note": "whole timed step (all kernels of burn-in + sampling) against the gradient flops"}
+    elif effective == hmc.HMC_FORM_FUSED:
         # the fused element-wise kernel keeps x, p, g on chip: its HBM bytes are
         # the state read and written once per launch plus the kept samples and
         # trace rows; its time goes to the random draws (Philox, Box-Muller) and
         # the FP64 energy, so the HBM fraction it reports is small by design
         es = 8 if w.state_dtype == "f64" else 4
         per_chain = 2 * (2 * es * w.dim + 40) + w.num_results * (es * w.dim + 25)
-        moved = per_chain * w.num_chains
-        achieved = moved / (kernel_ms * 1e-3)
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
-                "frac": achieved / PEAK["hbm"], "traffic": None,
+        work = per_chain * w.num_chains
+        roof = {"bound": "hbm", "achieved": work / (kern_ms * 1e-3) / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                "frac": work / (kern_ms * 1e-3) / PEAK["hbm"], "traffic": None,
                 "note": "fused element-wise kernel: bytes it must move (state in/out, samples, traces); "
                         "it is bound by the random draws and FP64 energy arithmetic, not by HBM"}
-        per_cs = moved / w.chain_steps()
+        roof_step = None
     else:
-        achieved = per_cs * w.chain_steps() / (kernel_ms * 1e-3)
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
-                "frac": achieved / PEAK["hbm"], "traffic": None}
-    tb = measured_traffic(w, s.form, args.grad)
+        work = per_cs * per_launch_cs
+        roof = {"bound": "hbm", "achieved": work / (kern_ms * 1e-3) / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                "frac": work / (kern_ms * 1e-3) / PEAK["hbm"], "traffic": None}
+        step_work = per_cs * w.chain_steps()
+        roof_step = {"bound": "hbm", "achieved": step_work / (step_ms * 1e-3) / 1e9, "peak": PEAK["hbm"] / 1e9,
+                     "unit": "GB/s", "frac": step_work / (step_ms * 1e-3) / PEAK["hbm"],
+                     "note": "whole timed step (every kernel of the transitions) against 4 x state bytes per "
+                             "chain-step"}
+    tb = measured_traffic(w, s.form, grad)
     roof["traffic"] = None if tb is None else tb / 1e9        # GB per launch
     roof["traffic_unit"] = "GB per launch"
-    roof["kernel"] = {hmc.HMC_FORM_FUSED: "fused transition kernel", hmc.HMC_FORM_PLAIN: "plain kernels",
-                      hmc.HMC_FORM_GRAPH: "plain kernels (graph)"}.get(hmc.hmc_effective_form(s.ctx))
-    roof["kernel_ms_per_launch"] = kernel_ms
-    roof["work_per_launch"] = per_cs * w.chain_steps()
+    roof["kernel"] = kern_name
+    roof["kernel_ms_per_launch"] = kern_ms
+    roof["launches_timed"] = kern_n
+    roof["work_per_launch"] = work
 
     result = {
-        "metric": METRIC, "value": value, "unit": "leapfrog chain-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": value, "unit": "leapfrog chain-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if w.state_dtype == "f64" else ("bf16/f32" if args.grad == "bf16" else "f32"),
+        "dtype": "f64" if w.state_dtype == "f64" else ("bf16/f32" if grad == "bf16" else "f32"),
         "data": "synthetic (seeded; shapes of the paper's workloads)",
         "config": {"workload": w.name, "num_chains": w.num_chains, "dim": w.dim, "n_rows": w.n_rows,
-                   "num_leapfrog_steps": w.num_leapfrog_steps, "num_burnin": w.num_burnin,
-                   "num_results": w.num_results, "adapt": "dual averaging to 0.8" if w.adapt else "none",
+                   "x_storage": "bf16" if w.X_bf16 is not None else ("f32" if w.X is not None else None),
+                   "gradient_operands": grad, "num_leapfrog_steps": w.num_leapfrog_steps,
+                   "transitions_per_step": {"burnin_adapted": w.num_burnin, "kept": w.num_results},
+                   "configured_run": {"num_burnin": burnin_cfg, "num_results": results_cfg},
+                   "adapt": "dual averaging to 0.8" if w.adapt else "none",
                    "form": s.form, "parallelism": "chains (1 GPU)"},
         "roofline": roof,
     }
+    if roof_step is not None:
+        result["roofline_step"] = roof_step
     if tune_report is not None:
         result["autotune"] = tune_report.strip().splitlines()
-    if not args.no_diagnostics and out.get("samples") is not None:
-        summ = dg.t_summarize(out["samples"])
-        result["max_rhat"] = summ["max_rhat"]
-        result["min_ess_bulk"] = summ["min_ess_bulk"]
-        result["ess_per_sec"] = (summ["min_ess_bulk"] / (elapsed / args.steps)) if summ["max_rhat"] <= 1.01 else None
-        result["accept_rate"] = float(out["is_accepted"].float().mean().item())
+    result["accept_rate"] = float(out["is_accepted"].float().mean().item())
+    if ess and out.get("samples") is not None:
+        if T >= burnin_cfg + results_cfg:
+            summ = dg.t_summarize(out["samples"])
+            result["max_rhat"] = summ["max_rhat"]
+            result["min_ess_bulk"] = summ["min_ess_bulk"]
+            result["ess_per_sec"] = (summ["min_ess_bulk"] / (elapsed / steps)) if summ["max_rhat"] <= 1.01 else None
+        else:
+            result["ess_per_sec"] = None
         out = None
-        if args.ess_results > 0 and result["ess_per_sec"] is None:
-            # as many kept draws as fit in the time and memory budgets
-            per_tr = elapsed / args.steps / T
+        if args.ess_results > 0 and result.get("ess_per_sec") is None:
+            # the configured burn-in, then as many kept draws as fit in the time and memory budgets
+            per_tr = elapsed / steps / T
             per_draw = w.num_chains * w.dim * (8 if w.state_dtype == "f64" else 4)
-            r_fit = min(args.ess_results, int(args.ess_gb * (1 << 30) // per_draw),
-                        int(args.ess_seconds / per_tr) - burnin_cfg)
+            budget = args.ess_seconds if ess_seconds is None else ess_seconds
+            r_fit = min(args.ess_results, int(args.ess_gb * (1 << 30) // per_draw), int(budget / per_tr) - burnin_cfg)
             if r_fit >= 100:
                 result["ess_run"] = ess_run(s, w, x0, eps0, r_fit, burnin_cfg, per_tr=per_tr)
+                result["ess_per_sec"] = result["ess_run"]["ess_per_sec"]
             else:
                 result["ess_run"] = {"skipped": f"fewer than 100 draws fit ({per_tr * 1e3:.1f} ms per transition)"}
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    out = None
     s.close()
-    print(json.dumps(result), flush=True)
+    if cpu:
+        print(f"bench: {w.name}: oracle baseline on the host", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    return result
+
+
+def default_extras(args):
+    """Beside the headline: the same workload with FP32 gradient operands (a short
+    run), and the logistic 1000 x 25 and dense Gaussian D = 100 workloads on their
+    fused kernels with ESS at their configured run lengths."""
+    extras = {}
+    r = bench_workload(args, DEFAULT_CONFIG, "f32", "plain", 2, 1, 4, ess=False, cpu=False)
+    extras["fp32_gradients"] = {k: r[k] for k in ("value", "ms_per_step", "roofline", "roofline_step", "config")}
+    for cfg in ("logreg_1000x25", "gauss_dense_100"):
+        r = bench_workload(args, cfg, "f32", "auto", 5, 2, None, ess=True, cpu=False, ess_seconds=20.0)
+        keep = ("value", "ms_per_step", "roofline", "accept_rate", "max_rhat", "ess_per_sec", "ess_run", "config")
+        extras[cfg] = {k: r[k] for k in keep if k in r}
+    return extras
 
 
 if __name__ == "__main__":

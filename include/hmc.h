@@ -204,6 +204,21 @@ hmc_status hmc_sample_chain_noalloc(const hmc_target* target, const hmc_config* 
                                     void* samples, const hmc_trace* trace, void* final_state,
                                     double* final_step_size, void* hip_stream);
 
+/* Kernel timing (measurement): from this call on, HIP events are recorded on
+ * the context's stream around each of the next max_launches (1 .. 2^20)
+ * launches of the context's dominant kernel -- the gradient kernel of the plain
+ * form (the first contraction kernel of a split-N target), the transition kernel
+ * of the fused form; graph-form replays are not timed.  Synchronizes the
+ * stream; replaces a timer already running. */
+hmc_status hmc_kernel_timer_start(hmc_ctx* ctx, int64_t max_launches);
+
+/* Synchronizes, writes the mean duration of the recorded launches in ms, their
+ * number and the kernel's name (name, host, name_len bytes, NUL-terminated;
+ * each output may be NULL), and stops the timer.  HMC_E_INVALID when no timer
+ * was started. */
+hmc_status hmc_kernel_timer_read(hmc_ctx* ctx, double* mean_ms, int64_t* launches, char* name,
+                                 size_t name_len);
+
 /* Message of the last non-OK status on this thread ("" if none). */
 const char* hmc_last_error(void);
 

@@ -45,6 +45,7 @@ struct hmc_ctx {
     int32_t form;            // effective form
     hipGraphExec_t graph_exec;
     bool graph_ready;
+    hmc::KernelTimer timer;  // armed by hmc_kernel_timer_start (a.timer points here)
 };
 
 namespace hmc {
@@ -294,7 +295,9 @@ static hmc_status ensure_graph(hmc_ctx* ctx) {
     hipGraph_t graph = nullptr;
     st = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
     if (st == HMC_OK) {
-        hipError_t le = launch_plain_transition(ctx->a, false, cs);
+        PlainArgs ga = ctx->a;
+        ga.timer = nullptr;      // no event nodes in the graph
+        hipError_t le = launch_plain_transition(ga, false, cs);
         hipError_t ee = hipStreamEndCapture(cs, &graph);
         st = check_hip(le != hipSuccess ? le : ee, "capture transition");
     }
@@ -334,7 +337,9 @@ hmc_status hmc_step(hmc_ctx* ctx, const hmc_step_out* out) {
         r.t_begin = ctx->t;
         r.n_transitions = 1;
         r.out = o;
+        timer_begin(ctx->a, ctx->stream);
         st = check_hip(launch_fused(ctx->a, r, ctx->stream), "fused step");
+        timer_end(ctx->a, ctx->stream, "fused transition kernel");
     } else {
         Ctrl c = base_ctrl(ctx);
         c.out_acc = o.is_accepted;
@@ -376,7 +381,9 @@ hmc_status hmc_sample_chain(hmc_ctx* ctx, int64_t num_results, int64_t num_burni
         set_adapt(r, adapt);
         r.samples = samples;
         r.trace = tr;
+        timer_begin(ctx->a, ctx->stream);
         st = check_hip(launch_fused(ctx->a, r, ctx->stream), "fused sample_chain");
+        timer_end(ctx->a, ctx->stream, "fused transition kernel");
     } else {
         Ctrl c = base_ctrl(ctx);
         c.n_burnin = num_burnin_steps;
@@ -423,11 +430,63 @@ hmc_status hmc_set_state(hmc_ctx* ctx, const void* state, const double* step_siz
     return st;
 }
 
+static void timer_release(hmc_ctx* ctx) {
+    KernelTimer& t = ctx->timer;
+    if (t.ev) {
+        for (int64_t i = 0; i < 2 * t.cap; ++i) (void)hipEventDestroy(t.ev[i]);
+        delete[] t.ev;
+    }
+    t = KernelTimer{};
+    ctx->a.timer = nullptr;
+}
+
 hmc_status hmc_destroy(hmc_ctx* ctx) {
     if (!ctx) return HMC_OK;
     hmc_status st = check_hip(hipStreamSynchronize(ctx->stream), "destroy");
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    timer_release(ctx);
     delete ctx;
+    return st;
+}
+
+hmc_status hmc_kernel_timer_start(hmc_ctx* ctx, int64_t max_launches) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    if (max_launches < 1 || max_launches > (1 << 20)) return fail(HMC_E_INVALID, "max_launches must be in [1, 2^20]");
+    hmc_status st = check_hip(hipStreamSynchronize(ctx->stream), "kernel timer");
+    if (st != HMC_OK) return st;
+    timer_release(ctx);
+    KernelTimer& t = ctx->timer;
+    t.ev = new hipEvent_t[(size_t)(2 * max_launches)];
+    for (int64_t i = 0; i < 2 * max_launches; ++i) {
+        st = check_hip(hipEventCreate(&t.ev[i]), "kernel timer events");
+        if (st != HMC_OK) {
+            t.cap = i / 2;       // events 0 .. 2 cap - 1 exist (an odd one is leaked to keep the pairs whole)
+            timer_release(ctx);
+            return st;
+        }
+    }
+    t.cap = max_launches;
+    ctx->a.timer = &t;
+    return HMC_OK;
+}
+
+hmc_status hmc_kernel_timer_read(hmc_ctx* ctx, double* mean_ms, int64_t* launches, char* name, size_t name_len) {
+    if (!ctx) return fail(HMC_E_INVALID, "ctx must not be NULL");
+    KernelTimer& t = ctx->timer;
+    if (!t.ev) return fail(HMC_E_INVALID, "kernel timer not started");
+    hmc_status st = check_hip(hipStreamSynchronize(ctx->stream), "kernel timer");
+    double total = 0.0;
+    for (int64_t i = 0; st == HMC_OK && i < t.n; ++i) {
+        float ms = 0.f;
+        st = check_hip(hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]), "kernel timer elapsed");
+        total += ms;
+    }
+    if (st == HMC_OK) {
+        if (mean_ms) *mean_ms = t.n > 0 ? total / (double)t.n : 0.0;
+        if (launches) *launches = t.n;
+        if (name && name_len > 0) snprintf(name, name_len, "%s", t.name ? t.name : "");
+    }
+    timer_release(ctx);
     return st;
 }
 

@@ -69,6 +69,17 @@ struct Tune {
     int32_t elem_gmult;    // lanes per chain multiplier of the fused elementwise kernel (1 or 2)
 };
 
+// Events recorded on the launching stream around the launches of a context's
+// dominant kernel (the gradient kernel of the plain form, the transition kernel
+// of the fused form), for at most cap launches once armed (host-side only).
+struct KernelTimer {
+    hipEvent_t* ev;        // [2 cap]: start and end of launch i at 2 i, 2 i + 1
+    int64_t cap;
+    int64_t n;             // launches recorded
+    bool open;             // a start is recorded and its end is not
+    const char* name;      // kernel of the recorded launches
+};
+
 // ---- plain path launchers (k_plain.hip) -----------------------------------
 struct PlainArgs {
     TargetDev tg;
@@ -79,7 +90,23 @@ struct PlainArgs {
     bool bf16_grad;    // LOGREG MFMA operands in BF16
     Key key;
     Workspace ws;
+    KernelTimer* timer;   // host object or NULL (never read by a kernel)
 };
+
+inline void timer_begin(const PlainArgs& a, hipStream_t s) {
+    KernelTimer* t = a.timer;
+    if (!t || t->n >= t->cap) return;
+    t->open = hipEventRecord(t->ev[2 * t->n], s) == hipSuccess;
+}
+inline void timer_end(const PlainArgs& a, hipStream_t s, const char* name) {
+    KernelTimer* t = a.timer;
+    if (!t || !t->open) return;
+    t->open = false;
+    if (hipEventRecord(t->ev[2 * t->n + 1], s) == hipSuccess) {
+        t->name = name;
+        ++t->n;
+    }
+}
 int64_t logreg_nsplit_t(const PlainArgs& a);
 int lb_grad_nsplit_t(const PlainArgs& a);
 hipError_t launch_set_ctrl(const Ctrl& c, Ctrl* dst, hipStream_t s);

@@ -555,6 +555,311 @@ __global__ __launch_bounds__(256) void k_lr16_grad_dma(PlainArgs a, const float*
 }
 
 // ---------------------------------------------------------------------------
+// Gradient partials, software-pipelined (D and N multiples of 8): 64 chains per
+// wave (four 16-chain tiles, so 256 chains per workgroup and, at 8192 chains, 32
+// chain tiles x 8 row splits = one workgroup per CU with each split on its own
+// XCD).  The residuals of sub-tile s are formed on the vector ALUs while the
+// matrix cores run the other contraction, in three phases per sub-tile:
+//   1. S of rows 0..15 of sub-tile s          || sigmoids of rows 16..31 of s - 1
+//   2. G^T += R^T X^T of sub-tile s - 1       || sigmoids of rows 0..15 of s
+//   3. S of rows 16..31 of sub-tile s
+// X^T of sub-tile s - 1 is still read in the iteration of s, so the X^T tiles
+// (with their labels) sit in a ring of five buffers and the X tiles in a ring of
+// four; the copies run three sub-tiles ahead.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
+
+// four floats to BF16 (round to nearest even), packed in two dwords
+__device__ __forceinline__ uint2 pack4_bf16(floatx4 f) {
+    return __builtin_bit_cast(uint2, __builtin_convertvector(f, bf16x4v));
+}
+
+// y - sigmoid(s) of the lane's four rows row0 + v (v = 0..3, rows counted from the
+// sub-tile's first), labels packed one per byte in yw; rows at or past nvalid give 0
+__device__ __forceinline__ uint2 residual4(floatx4 s, uint32_t yw, int row0, int nvalid) {
+    floatx4 r;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const float y = (float)((yw >> (8 * v)) & 0xffu);
+        r[v] = (row0 + v < nvalid) ? y - sigmoid_hw(s[v]) : 0.f;
+    }
+    return pack4_bf16(r);
+}
+
+constexpr int LP_NBX = 4;     // X sub-tile buffers of the pipelined kernel
+constexpr int LP_NBT = 5;     // X^T sub-tile (+ labels) buffers
+
+template <int KS>
+__host__ __device__ constexpr int pipe_lds_bytes() {
+    return LP_NBX * LB_RS * 32 * KS * 2 + LP_NBT * (32 * KS * LB_RS * 2 + LD_YB);
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float* __restrict__ xsrc,
+                                                        const float* __restrict__ psrc, int drift,
+                                                        int64_t rows_per_split, int nsplit,
+                                                        const uint16_t* __restrict__ Xt) {
+    constexpr int NT = 2 * KS;
+    constexpr int CS = 4;
+    constexpr int CW = 16 * CS, CT = LB_NW * CW;
+    constexpr int DP = 32 * KS;
+    constexpr int SR = DP / 8;
+    constexpr int XM = ld_xmask(SR);
+    constexpr int XB = LB_RS * DP * 2;          // bytes of an X sub-tile
+    constexpr int TB = DP * LB_RS * 2;          // bytes of an X^T sub-tile
+    constexpr int TBY = TB + LD_YB;             // X^T sub-tile + labels
+    constexpr int XI = XB / 1024, TI = TB / 1024;
+    constexpr int JW = (XI + TI) / LB_NW;
+    constexpr int J = JW + 1;
+    static_assert((XI + TI) % LB_NW == 0, "copies must split evenly over the waves");
+    extern __shared__ __align__(16) uint8_t ldsb[];
+    uint8_t* xring = ldsb;                      // [LP_NBX][XB]
+    uint8_t* tring = ldsb + LP_NBX * XB;        // [LP_NBT][TBY]
+
+    const int64_t D = a.tg.D, N = a.tg.N, C = a.C;
+    const int ntile = (int)((C + CT - 1) / CT);
+    int tile, split;
+    lb_map(blockIdx.x, ntile, nsplit, &tile, &split);
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l16 = lane & 15, g = lane >> 4;
+    const int64_t cw = (int64_t)tile * CT + CW * w;
+    const uint16_t* X = (const uint16_t*)a.tg.X;
+    const uint8_t* Y = a.tg.y;
+
+    // theta (drifted) as BF16 B operands: B[k][j] = theta[chain j][dim k]
+    bf16x8 thb[CS][KS];
+#pragma unroll
+    for (int cs = 0; cs < CS; ++cs) {
+        const int64_t c = cw + 16 * cs + l16;
+        const bool cok = c < C;
+        const float eps = cok ? (float)a.ws.eps[c] : 0.f;
+        const float* xr = xsrc + (cok ? c : 0) * D;
+        const float* pr = psrc + (cok ? c : 0) * D;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int d0 = 32 * ks + 8 * g;
+            floatx8 v = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (cok && d0 < D) {      // D % 8 == 0: the 8 dims are all in range
+                const float4 x0 = *(const float4*)(xr + d0), x1 = *(const float4*)(xr + d0 + 4);
+                v = floatx8{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+                if (drift) {
+                    const float4 p0 = *(const float4*)(pr + d0), p1 = *(const float4*)(pr + d0 + 4);
+                    const floatx8 pv = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) v[e] = fmaf(eps, pv[e], v[e]);
+                }
+            }
+            thb[cs][ks] = pack_bf16(v);
+        }
+    }
+
+    const int64_t r_begin = (int64_t)split * rows_per_split;
+    int64_t r_end = r_begin + rows_per_split;
+    if (r_end > N) r_end = N;
+    const int nsub = r_begin < r_end ? (int)((r_end - r_begin + LB_RS - 1) / LB_RS) : 0;
+
+    // copies of sub-tile sidx: X into X buffer sidx % 4, X^T and the labels into
+    // X^T buffer sidx % 5; rows past the chunk and dims past D read in-range data
+    // whose products are masked (residual 0) or discarded
+    auto copy_in = [&](int sidx, uint8_t* __restrict__ xbase, uint8_t* __restrict__ tbase) {
+        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
+        const int nrow = (int)(r_end - r0 < LB_RS ? r_end - r0 : LB_RS);   // multiple of 8
+        const char* xsrc_t = (const char*)(X + r0 * D);
+        const char* tsrc_t = (const char*)(Xt + r0);
+        // the lane index through an empty asm: the per-lane offsets below are
+        // recomputed for every sub-tile instead of being hoisted out of the loop
+        // (and spilled: a reload's wait would also wait for the copies in flight)
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        if (nrow == LB_RS && D == DP) {
+            // whole sub-tile, rows of exactly DP dims: X rows are contiguous and the
+            // swizzle term of a wave's copies does not depend on k (likewise for X^T)
+            const int xrow = (64 / SR) * w + ln / SR;
+            const uint32_t xoff = (uint32_t)(ln / SR) * (uint32_t)(DP * 2) +
+                                  16u * (uint32_t)((ln % SR) ^ (xrow & XM));
+            const int tdim = 16 * w + (ln >> 2);
+            const uint32_t toff = (uint32_t)(ln >> 2) * (uint32_t)N * 2u + 16u * (uint32_t)((ln & 3) ^ ld_tsw(tdim));
+#pragma unroll
+            for (int k = 0; k < JW; ++k) {
+                const int i = w + LB_NW * k;
+                if (i < XI) {
+                    __builtin_amdgcn_global_load_lds((const void*)(xsrc_t + (uint32_t)i * 1024u + xoff),
+                                                     (lds_void_t*)(xbase + i * 1024), 16, 0, 0);
+                } else {
+                    const int ii = i - XI;
+                    __builtin_amdgcn_global_load_lds(
+                        (const void*)(tsrc_t + (uint32_t)(16 * ii) * (uint32_t)N * 2u + toff),
+                        (lds_void_t*)(tbase + ii * 1024), 16, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < JW; ++k) {
+                const int i = w + LB_NW * k;
+                if (i < XI) {
+                    const int q = i * 64 + ln;
+                    const int row = q / SR, c = (q % SR) ^ (row & XM);
+                    const int rowc = row < nrow ? row : nrow - 1;
+                    const uint32_t off = (uint32_t)(rowc * (int)D + (8 * c < D ? 8 * c : 0)) * 2u;
+                    __builtin_amdgcn_global_load_lds((const void*)(xsrc_t + off), (lds_void_t*)(xbase + i * 1024),
+                                                     16, 0, 0);
+                } else {
+                    const int ii = i - XI;
+                    const int q = ii * 64 + ln;
+                    const int dim = q >> 2, c = (q & 3) ^ ld_tsw(dim);
+                    const int rr = 8 * c + 8 <= nrow ? 8 * c : 0;
+                    const uint32_t off = ((uint32_t)(dim < D ? dim : 0) * (uint32_t)N + (uint32_t)rr) * 2u;
+                    __builtin_amdgcn_global_load_lds((const void*)(tsrc_t + off), (lds_void_t*)(tbase + ii * 1024),
+                                                     16, 0, 0);
+                }
+            }
+        }
+        // labels: dword (lane % 8) of the sub-tile's rows; the rows left in the chunk are a
+        // multiple of 8, so a dword that starts in range ends in range (else row r0's is read)
+        const int64_t yo = r0 + 4 * (ln & 7) < r_end ? r0 + 4 * (ln & 7) : r0;
+        __builtin_amdgcn_global_load_lds((const void*)(Y + yo), (lds_void_t*)(tbase + TB), 4, 0, 0);
+    };
+    auto xbuf = [&](int sidx) { return xring + (sidx % LP_NBX) * XB; };
+    auto tbuf = [&](int sidx) { return tring + (sidx % LP_NBT) * TBY; };
+    auto xfrag = [&](const uint8_t* xb, int ks, int mt) {
+        const int row = mt * 16 + l16;
+        return *(const bf16x8*)(xb + row * (DP * 2) + (((4 * ks + g) ^ (row & XM)) * 16));
+    };
+    auto tfrag = [&](const uint8_t* tb, int nt) {
+        const int dim = 16 * nt + l16, sw = ld_tsw(dim);
+        const uint8_t* tr = tb + dim * 64 + (g & 1) * 8;
+        const uint2 lo = *(const uint2*)(tr + (((g >> 1)) ^ sw) * 16);
+        const uint2 hi = *(const uint2*)(tr + ((2 + (g >> 1)) ^ sw) * 16);
+        return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+    };
+
+    floatx4 gacc[CS][NT];
+#pragma unroll
+    for (int cs = 0; cs < CS; ++cs)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) gacc[cs][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    if (nsub > 0) copy_in(0, xbuf(0), tbuf(0));
+    if (nsub > 1) copy_in(1, xbuf(1), tbuf(1));
+    if (nsub > 2) copy_in(2, xbuf(2), tbuf(2));
+
+    // pipeline registers: S of rows 16..31 of the previous sub-tile, the packed
+    // residuals of rows 0..15 of the previous (lo_p) and current (lo_c) sub-tile
+    floatx4 s1p[CS];
+    uint2 lo_p[CS];
+    uint32_t yprev[2] = {0u, 0u};
+    int nvp = 0;          // valid rows of the previous sub-tile
+
+    // G^T += R^T X^T of the sub-tile in tb with residual operands ra
+    auto gphase = [&](const uint8_t* __restrict__ tb, const bf16x8* ra) {
+        bf16x8 tf0 = tfrag(tb, 0), tf1 = tfrag(tb, 1);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bx = tf0;
+            tf0 = tf1;
+            if (nt + 2 < NT) tf1 = tfrag(tb, nt + 2);
+#pragma unroll
+            for (int cs = 0; cs < CS; ++cs)
+                gacc[cs][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[cs], bx, gacc[cs][nt], 0, 0, 0);
+        }
+    };
+
+    // one sub-tile; the copy targets (xdst, tdst) and the buffers read (xb, tprev,
+    // tcur) are distinct, which the restrict qualifiers tell the compiler, so the
+    // LDS reads need not wait for the copies in flight (the explicit vmcnt waits
+    // and the barrier order the sub-tiles)
+    auto iter = [&](int sidx, uint8_t* __restrict__ xdst, uint8_t* __restrict__ tdst, const uint8_t* __restrict__ xb,
+                    const uint8_t* __restrict__ tprev, const uint8_t* __restrict__ tcur) {
+        if (sidx + 3 < nsub) copy_in(sidx + 3, xdst, tdst);
+        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
+        const int nv = (int)(r_end - r0 < LB_RS ? r_end - r0 : LB_RS);
+        // labels of the lane's rows 4 g .. 4 g + 3 (half 0) and 16 + 4 g .. (half 1)
+        const uint32_t ycur0 = *(const uint32_t*)(tcur + TB + 4 * g);
+        const uint32_t ycur1 = *(const uint32_t*)(tcur + TB + 16 + 4 * g);
+
+        // phase 1: S of rows 0..15 || residuals of rows 16..31 of the previous sub-tile
+        floatx4 s0[CS];
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs) s0[cs] = floatx4{0.f, 0.f, 0.f, 0.f};
+        {
+            bf16x8 xf0 = xfrag(xb, 0, 0), xf1 = KS > 1 ? xfrag(xb, 1, 0) : xf0;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const bf16x8 ax = xf0;
+                xf0 = xf1;
+                if (ks + 2 < KS) xf1 = xfrag(xb, ks + 2, 0);
+#pragma unroll
+                for (int cs = 0; cs < CS; ++cs)
+                    s0[cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, thb[cs][ks], s0[cs], 0, 0, 0);
+            }
+        }
+        bf16x8 rp[CS];
+        if (sidx > 0) {
+#pragma unroll
+            for (int cs = 0; cs < CS; ++cs) {
+                const uint2 hi = residual4(s1p[cs], yprev[1], 16 + 4 * g, nvp);
+                rp[cs] = __builtin_bit_cast(bf16x8, make_uint4(lo_p[cs].x, lo_p[cs].y, hi.x, hi.y));
+            }
+        }
+        // phase 2: G of the previous sub-tile || residuals of rows 0..15 of this one
+        if (sidx > 0) gphase(tprev, rp);
+        uint2 lo_c[CS];
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs) lo_c[cs] = residual4(s0[cs], ycur0, 4 * g, nv);
+        // phase 3: S of rows 16..31
+        floatx4 s1[CS];
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs) s1[cs] = floatx4{0.f, 0.f, 0.f, 0.f};
+        {
+            bf16x8 xf0 = xfrag(xb, 0, 1), xf1 = KS > 1 ? xfrag(xb, 1, 1) : xf0;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const bf16x8 ax = xf0;
+                xf0 = xf1;
+                if (ks + 2 < KS) xf1 = xfrag(xb, ks + 2, 1);
+#pragma unroll
+                for (int cs = 0; cs < CS; ++cs)
+                    s1[cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, thb[cs][ks], s1[cs], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs) {
+            s1p[cs] = s1[cs];
+            lo_p[cs] = lo_c[cs];
+        }
+        yprev[0] = ycur0;
+        yprev[1] = ycur1;
+        nvp = nv;
+    };
+    for (int sidx = 0; sidx < nsub; ++sidx) {
+        if (sidx + 2 < nsub) wait_vmcnt<2 * J>();
+        else if (sidx + 1 < nsub) wait_vmcnt<J>();
+        else wait_vmcnt<0>();
+        lds_barrier();
+        iter(sidx, xbuf(sidx + 3), tbuf(sidx + 3), xbuf(sidx), tbuf(sidx + LP_NBT - 1), tbuf(sidx));
+    }
+    if (nsub > 0) {
+        bf16x8 rp[CS];
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs) {
+            const uint2 hi = residual4(s1p[cs], yprev[1], 16 + 4 * g, nvp);
+            rp[cs] = __builtin_bit_cast(bf16x8, make_uint4(lo_p[cs].x, lo_p[cs].y, hi.x, hi.y));
+        }
+        gphase(tbuf(nsub - 1), rp);
+    }
+#pragma unroll
+    for (int cs = 0; cs < CS; ++cs)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t c = cw + 16 * cs + 4 * g + v;
+                const int64_t d = 16 * nt + l16;
+                if (c < C && d < D) a.ws.part_g[((int64_t)split * C + c) * D + d] = gacc[cs][nt][v];
+            }
+}
+
+// ---------------------------------------------------------------------------
 // Accurate log-probability partials: theta = hi + mid + lo (three BF16 terms),
 // 64 chains per workgroup (16 per wave), softplus summed in FP64 per chain.
 // ---------------------------------------------------------------------------
@@ -876,15 +1181,24 @@ static int pow2_split(int ntile, int64_t N) {
     return s;
 }
 
-// chains per workgroup of the gradient kernel for D dims
-static int lb_grad_ct(int64_t D) { return LB_NW * 16 * lb_cs((int)((D + 31) / 32) > 4 ? 8 : 4); }
+// shapes the copy-staged kernels take (as ld_copy_ok, from the sizes alone)
+static bool ld_copy_shape(int64_t N, int64_t D) {
+    return D % 8 == 0 && N % 8 == 0 && N >= 64 && (uint64_t)D * (uint64_t)N * 2u < (1ull << 32);
+}
 
-// row splits: as many as fill the 256 CUs once (at most 8, at least 4 sub-tiles each)
+// chains per workgroup of the gradient kernel for N rows and D dims: 256 for the
+// pipelined kernel, else that of the register-staged one
+static int lb_grad_ct(int64_t N, int64_t D) {
+    return ld_copy_shape(N, D) ? LB_NW * 64 : LB_NW * 16 * lb_cs((int)((D + 31) / 32) > 4 ? 8 : 4);
+}
+
+// row splits: a power of two (so that blocks map to XCDs by split) filling the
+// 256 CUs once, at most 8, at least 4 sub-tiles each
 int lb_grad_nsplit(int64_t N, int64_t C, int64_t D) {
-    const int ntile = (int)((C + lb_grad_ct(D) - 1) / lb_grad_ct(D));
-    int s = ntile >= 256 ? 1 : 256 / ntile;
-    if (s > 8) s = 8;
-    while (s > 1 && (N + s - 1) / s < 4 * LB_RS) --s;
+    const int ct = lb_grad_ct(N, D);
+    const int ntile = (int)((C + ct - 1) / ct);
+    int s = 1;
+    while (s < 8 && ntile * 2 * s <= 256 && (N + 2 * s - 1) / (2 * s) >= 4 * LB_RS) s *= 2;
     return s;
 }
 int lb_grad_nsplit_t(const PlainArgs& a) {
@@ -925,11 +1239,13 @@ static hipError_t lb_grad_k(const PlainArgs& a, const float* x, const float* p, 
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_lr16_grad<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ld_copy_ok(a.tg)) {
-        const size_t ldd = (size_t)LD_NB * ld_buf_bytes<KS>();
+        constexpr int PCT = LB_NW * 64;
+        const int ptile = (int)((a.C + PCT - 1) / PCT);
+        const size_t ldd = (size_t)pipe_lds_bytes<KS>();
         if (ldd > 65536)
-            (void)hipFuncSetAttribute((const void*)k_lr16_grad_dma<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+            (void)hipFuncSetAttribute((const void*)k_lr16_grad_pipe<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)ldd);
-        hipLaunchKernelGGL(k_lr16_grad_dma<KS>, dim3((unsigned)(ntile * nsplit)), dim3(256), ldd, s, a, x, p, drift,
+        hipLaunchKernelGGL(k_lr16_grad_pipe<KS>, dim3((unsigned)(ptile * nsplit)), dim3(256), ldd, s, a, x, p, drift,
                            rows_for(a.tg.N, nsplit), nsplit, (const uint16_t*)Xt);
         return hipGetLastError();
     }

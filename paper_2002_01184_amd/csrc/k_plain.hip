@@ -625,10 +625,12 @@ static hipError_t launch_logreg(const PlainArgs& a, float* x, float* p, float* g
     const int64_t rows = (a.tg.N + nsplit - 1) / nsplit;
     const size_t lds = logreg_lds(a.tg.D);
     const dim3 grid((unsigned)((a.C + 15) / 16), (unsigned)nsplit);
+    timer_begin(a, s);
     if (a.tg.x_bf16)
         launch_logreg_partial_t<uint16_t>(a, grid, lds, s, x, p, drift, want_logp, rows);
     else
         launch_logreg_partial_t<float>(a, grid, lds, s, x, p, drift, want_logp, rows);
+    timer_end(a, s, "k_logreg_partial");
     hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, x, p, gd, (int)nsplit, drift,
                        kick, ks, want_logp);
     return hipGetLastError();
@@ -726,7 +728,9 @@ hipError_t launch_remc_swap(const PlainArgs& a, int64_t K, int64_t M, uint32_t t
 }
 
 // gradient (and logp) at ws.x into ws.g / ws.logp
-hipError_t launch_bootstrap(const PlainArgs& a, const void* x_src, hipStream_t s) {
+hipError_t launch_bootstrap(const PlainArgs& a_in, const void* x_src, hipStream_t s) {
+    PlainArgs a = a_in;
+    a.timer = nullptr;       // the kernel timer covers transitions only
     const size_t es = a.f64 ? 8 : 4;
     if (x_src && x_src != a.ws.x) {
         hipError_t e = hipMemcpyAsync(a.ws.x, x_src, (size_t)a.C * a.tg.D * es, hipMemcpyDeviceToDevice, s);
@@ -801,6 +805,7 @@ hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipSt
         switch (a.tg.kind) {
         case HMC_TGT_STD_NORMAL:
         case HMC_TGT_GAUSS_DIAG:
+            timer_begin(a, s);
             if (a.f64)
                 hipLaunchKernelGGL(k_elem_leapfrog<double>, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a,
                                    (const double*)a.ws.xq, (double*)a.ws.xq, (double*)a.ws.pq,
@@ -809,14 +814,19 @@ hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipSt
                 hipLaunchKernelGGL(k_elem_leapfrog<float>, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a,
                                    (const float*)a.ws.xq, (float*)a.ws.xq, (float*)a.ws.pq,
                                    last ? (float*)a.ws.gq : (float*)nullptr, 3, ks);
+            timer_end(a, s, "k_elem_leapfrog");
             break;
         case HMC_TGT_GAUSS_DENSE:
+            timer_begin(a, s);
             (void)launch_dense(a, (const float*)a.ws.xq, (float*)a.ws.xq, (float*)a.ws.pq,
                          last ? (float*)a.ws.gq : nullptr, 3, ks, s);
+            timer_end(a, s, "k_dense_leapfrog");
             break;
         case HMC_TGT_LOGREG:
             if (a.bf16_grad) {
+                timer_begin(a, s);
                 (void)launch_lr16_grad(a, (const float*)a.ws.xq, (const float*)a.ws.pq, 1, a.ws.xt, s);
+                timer_end(a, s, "k_lr16_grad");
                 hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, (float*)a.ws.xq,
                                    (float*)a.ws.pq, last ? (float*)a.ws.gq : (float*)nullptr,
                                    lb_grad_nsplit_t(a), 1, 1, ks, 0);

@@ -99,7 +99,7 @@ EXPORTED = ["hmc_workspace_size", "hmc_init", "hmc_step", "hmc_sample_chain", "h
             "hmc_remc_swap", "hmc_remc_sample_chain", "hmc_sample_chain_moments", "hmc_set_transform_scale",
             "hmc_nuts_workspace_size", "hmc_nuts_sample_chain", "hmc_server_create", "hmc_server_submit",
             "hmc_server_poll", "hmc_server_wait", "hmc_server_take", "hmc_server_get_stats",
-            "hmc_server_destroy", "hmc_sample_chain_noalloc"]
+            "hmc_server_destroy", "hmc_sample_chain_noalloc", "hmc_kernel_timer_start", "hmc_kernel_timer_read"]
 
 HMC_NOALLOC_WORKSPACE_BYTES = 64 << 20
 
@@ -138,6 +138,11 @@ def lib():
                                            ctypes.c_int64, ctypes.POINTER(hmc_adapt), vp, ctypes.POINTER(hmc_trace),
                                            vp, vp, vp]
     L.hmc_sample_chain_noalloc.restype = st
+    L.hmc_kernel_timer_start.argtypes = [vp, ctypes.c_int64]
+    L.hmc_kernel_timer_start.restype = st
+    L.hmc_kernel_timer_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.c_char_p, ctypes.c_size_t]
+    L.hmc_kernel_timer_read.restype = st
     L.hmc_last_error.argtypes = []
     L.hmc_last_error.restype = ctypes.c_char_p
     L.hmc_effective_form.argtypes = [vp]
@@ -224,6 +229,18 @@ def hmc_sample_chain_noalloc(target, config, init_state_ptr, step_sizes, num_res
                                           ctypes.byref(adapt) if adapt is not None else None, samples_ptr,
                                           ctypes.byref(trace) if trace is not None else None, final_state_ptr,
                                           final_step_size_ptr, stream_ptr))
+
+
+def hmc_kernel_timer_start(ctx, max_launches: int):
+    _check(lib().hmc_kernel_timer_start(ctx, max_launches))
+
+
+def hmc_kernel_timer_read(ctx):
+    """(mean ms per launch, launches recorded, kernel name); stops the timer."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    buf = ctypes.create_string_buffer(128)
+    _check(lib().hmc_kernel_timer_read(ctx, ctypes.byref(ms), ctypes.byref(n), buf, 128))
+    return ms.value, n.value, buf.value.decode()
 
 
 def hmc_sample_chain_moments(ctx, num_results, num_burnin_steps, adapt: hmc_adapt | None, moments: hmc_moments,

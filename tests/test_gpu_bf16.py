@@ -25,7 +25,7 @@ def _bf16_case(N, D, C, seed=2, L=6, eps=0.004):
     return W.logreg(N, D, C, L=L, step_size=eps, bf16=True, init=0.05, seed=seed)
 
 
-@pytest.mark.parametrize("N,D,C", [(3000, 40, 300), (777, 25, 130), (4096, 256, 256)])
+@pytest.mark.parametrize("N,D,C", [(3000, 40, 300), (777, 25, 130), (4096, 256, 256), (3000, 64, 300), (2056, 128, 520)])
 def test_bf16_form_one_step(N, D, C):
     w = _bf16_case(N, D, C)
     s = hmc.sampler_for(w, grad_bf16=True)
