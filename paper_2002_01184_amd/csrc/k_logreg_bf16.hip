@@ -293,18 +293,18 @@ __global__ __launch_bounds__(256) void k_lr16_grad(PlainArgs a, const float* __r
 }
 
 // ---------------------------------------------------------------------------
-// The same gradient partials with the sub-tiles copied global -> LDS by the
-// load-to-LDS instructions (global_load_lds_dwordx4: lane i of an instruction
-// writes bytes 16 i .. 16 i + 15 of a 1 KB block), for D and N multiples of 8.
-// A ring of LD_NB sub-tile buffers keeps three sub-tiles in flight without
-// staging registers; the barrier between sub-tiles waits for LDS only, each
-// wave first waiting (vmcnt) for its own copies of the sub-tile it is about
-// to read.  Both tiles use 16-byte slots XOR-swizzled by row so that the
-// operand reads of the MFMAs spread over the LDS banks:
+// Copy-staged kernels (D and N multiples of 8): the sub-tiles are copied global
+// -> LDS by the load-to-LDS instructions (global_load_lds_dwordx4: lane i of an
+// instruction writes bytes 16 i .. 16 i + 15 of a 1 KB block), so a ring of
+// sub-tile buffers keeps several sub-tiles in flight without staging
+// registers; the barrier between sub-tiles waits for LDS only, each wave first
+// waiting (vmcnt) for its own copies of the sub-tile it is about to read.  The
+// tiles use 16-byte slots XOR-swizzled by row so that the operand reads of the
+// MFMAs spread over the LDS banks:
 //   X   [32 rows][DP / 8 slots]: slot c of row r at position c ^ (r & XM)
 //   X^T [DP dims][4 slots of 8 rows]: slot c of dim d at position c ^ ((d >> 1) & 3)
 // ---------------------------------------------------------------------------
-constexpr int LD_NB = 4;      // sub-tile buffers
+constexpr int LD_NB = 4;      // sub-tile buffers of the log-probability kernel
 #ifndef LD_XM_MAX
 #define LD_XM_MAX 8
 #endif
@@ -316,8 +316,6 @@ __host__ __device__ constexpr int ld_xmask(int SR) { return (SR < LD_XM_MAX ? SR
 __device__ __forceinline__ int ld_tsw(int d) { return (d >> LD_TSHIFT) & 3; }
 constexpr int LD_YB = 256;    // bytes reserved for the labels of a sub-tile (32 used)
 
-template <int KS>
-__host__ __device__ constexpr int ld_buf_bytes() { return 2 * LB_RS * 32 * KS * 2 + LD_YB; }
 
 // s_waitcnt vmcnt(n) leaving the other counters unconstrained (gfx9 encoding)
 template <int n>
@@ -338,252 +336,27 @@ static bool ld_copy_ok(const TargetDev& tg) {
     return tg.D % 8 == 0 && tg.N % 8 == 0 && tg.N >= 64 && (uint64_t)tg.D * (uint64_t)tg.N * 2u < (1ull << 32);
 }
 
-template <int KS>
-__global__ __launch_bounds__(256) void k_lr16_grad_dma(PlainArgs a, const float* __restrict__ xsrc,
-                                                       const float* __restrict__ psrc, int drift,
-                                                       int64_t rows_per_split, int nsplit,
-                                                       const uint16_t* __restrict__ Xt) {
-    constexpr int NT = 2 * KS;
-    constexpr int CS = lb_cs(KS);
-    constexpr int CW = 16 * CS, CT = LB_NW * CW;
-    constexpr int DP = 32 * KS;
-    constexpr int SR = DP / 8;                  // 16-byte slots per X row
-    constexpr int XM = ld_xmask(SR);            // swizzle mask of X
-    constexpr int XB = LB_RS * DP * 2;          // bytes of an X sub-tile
-    constexpr int TB = DP * LB_RS * 2;          // bytes of an X^T sub-tile
-    constexpr int BUF = ld_buf_bytes<KS>();
-    constexpr int XI = XB / 1024, TI = TB / 1024;      // copy instructions per tile (multiples of 2)
-    constexpr int JW = (XI + TI) / LB_NW;              // tile copy instructions per wave
-    constexpr int J = JW + 1;                          // plus the labels
-    static_assert((XI + TI) % LB_NW == 0, "copies must split evenly over the waves");
-    extern __shared__ __align__(16) uint8_t ldsb[];
-
-    const int64_t D = a.tg.D, N = a.tg.N, C = a.C;
-    const int ntile = (int)((C + CT - 1) / CT);
-    int tile, split;
-    lb_map(blockIdx.x, ntile, nsplit, &tile, &split);
-    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int l16 = lane & 15, g = lane >> 4;
-    const int64_t cw = (int64_t)tile * CT + CW * w;
-    const uint16_t* X = (const uint16_t*)a.tg.X;
-    const uint8_t* Y = a.tg.y;
-
-    bf16x8 thb[CS][KS];
-#pragma unroll
-    for (int cs = 0; cs < CS; ++cs) {
-        const int64_t c = cw + 16 * cs + l16;
-        const bool cok = c < C;
-        const float eps = cok ? (float)a.ws.eps[c] : 0.f;
-        const float* xr = xsrc + (cok ? c : 0) * D;
-        const float* pr = psrc + (cok ? c : 0) * D;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int d0 = 32 * ks + 8 * g;
-            floatx8 v = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (cok && d0 < D) {      // D % 8 == 0: the 8 dims are all in range
-                const float4 x0 = *(const float4*)(xr + d0), x1 = *(const float4*)(xr + d0 + 4);
-                v = floatx8{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-                if (drift) {
-                    const float4 p0 = *(const float4*)(pr + d0), p1 = *(const float4*)(pr + d0 + 4);
-                    const floatx8 pv = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) v[e] = fmaf(eps, pv[e], v[e]);
-                }
-            }
-            thb[cs][ks] = pack_bf16(v);
-        }
-    }
-
-    const int64_t r_begin = (int64_t)split * rows_per_split;
-    int64_t r_end = r_begin + rows_per_split;
-    if (r_end > N) r_end = N;
-    const int nsub = r_begin < r_end ? (int)((r_end - r_begin + LB_RS - 1) / LB_RS) : 0;
-
-    // copies of sub-tile sidx into buffer sidx % LD_NB; rows past the chunk and
-    // dims past D read in-range data whose products are masked or discarded
-    // sources: a sub-tile base (uniform) plus a 32-bit per-lane byte offset
-    auto copy_in = [&](int sidx, uint8_t* __restrict__ base) {
-        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
-        const int nrow = (int)(r_end - r0 < LB_RS ? r_end - r0 : LB_RS);   // rows of this sub-tile (multiple of 8)
-        const char* xsrc_t = (const char*)(X + r0 * D);
-        const char* tsrc_t = (const char*)(Xt + r0);
-#pragma unroll
-        for (int k = 0; k < JW; ++k) {
-            const int i = w + LB_NW * k;
-            if (i < XI) {
-                const int q = i * 64 + lane;
-                const int row = q / SR, c = (q % SR) ^ (row & XM);
-                const int rowc = row < nrow ? row : nrow - 1;
-                const uint32_t off = (uint32_t)(rowc * (int)D + (8 * c < D ? 8 * c : 0)) * 2u;
-                __builtin_amdgcn_global_load_lds((const void*)(xsrc_t + off), (lds_void_t*)(base + i * 1024), 16, 0,
-                                                 0);
-            } else {
-                const int ii = i - XI;
-                const int q = ii * 64 + lane;
-                const int dim = q >> 2, c = (q & 3) ^ ld_tsw(dim);
-                const int rr = 8 * c + 8 <= nrow ? 8 * c : 0;
-                const uint32_t off = ((uint32_t)(dim < D ? dim : 0) * (uint32_t)N + (uint32_t)rr) * 2u;
-                __builtin_amdgcn_global_load_lds((const void*)(tsrc_t + off), (lds_void_t*)(base + XB + ii * 1024), 16,
-                                                 0, 0);
-            }
-        }
-        // labels: dword (lane % 8) of the 32 rows when all of them exist, else a dummy copy
-        const int64_t yo = r0 + LB_RS <= r_end ? r0 + 4 * (lane & 7) : 0;
-        __builtin_amdgcn_global_load_lds((const void*)(Y + yo), (lds_void_t*)(base + XB + TB), 4, 0, 0);
-    };
-
-    floatx4 gacc[CS][NT];
-#pragma unroll
-    for (int cs = 0; cs < CS; ++cs)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) gacc[cs][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    if (nsub > 0) copy_in(0, ldsb);
-    if (nsub > 1) copy_in(1, ldsb + BUF);
-    if (nsub > 2) copy_in(2, ldsb + 2 * BUF);
-    // one sub-tile: the copy of sub-tile sidx + 3 into nxt and the products of
-    // sub-tile sidx from cur, two distinct buffers (restrict: the LDS reads need
-    // not wait for the copy; the explicit vmcnt waits order the sub-tiles)
-    auto step = [&](int sidx, uint8_t* __restrict__ nxt, const uint8_t* __restrict__ base) {
-        if (sidx + 3 < nsub) copy_in(sidx + 3, nxt);
-        const uint8_t* tb = base + XB;
-        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
-        floatx4 sacc[2][CS];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int cs = 0; cs < CS; ++cs) sacc[mt][cs] = floatx4{0.f, 0.f, 0.f, 0.f};
-        // X fragments read three k-steps ahead of their MFMAs (LDS latency off the MFMA path)
-        auto xfrag = [&](int idx) {
-            const int ks = idx >> 1, row = (idx & 1) * 16 + l16;
-            return *(const bf16x8*)(base + row * (DP * 2) + (((4 * ks + g) ^ (row & XM)) * 16));
-        };
-        bf16x8 xf0 = xfrag(0), xf1 = xfrag(1), xf2 = xfrag(2);
-#pragma unroll
-        for (int idx = 0; idx < 2 * KS; ++idx) {
-            const bf16x8 ax = xf0;
-            xf0 = xf1;
-            xf1 = xf2;
-            if (idx + 3 < 2 * KS) xf2 = xfrag(idx + 3);
-            const int ks = idx >> 1, mt = idx & 1;
-#pragma unroll
-            for (int cs = 0; cs < CS; ++cs)
-                sacc[mt][cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, thb[cs][ks], sacc[mt][cs], 0, 0, 0);
-        }
-        // issue order: three fragment reads, then per k-step its MFMAs followed by the
-        // read three steps ahead (the LDS latency overlaps two steps of MFMAs)
-        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
-#pragma unroll
-        for (int idx = 0; idx < 2 * KS; ++idx) {
-            __builtin_amdgcn_sched_group_barrier(0x008, CS, 0);
-            if (idx + 3 < 2 * KS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        // labels of the lane's rows 4 g .. 4 g + 3 and 16 + 4 g .. 16 + 4 g + 3
-        uint32_t yw[2];
-        if (r0 + LB_RS <= r_end) {
-            yw[0] = *(const uint32_t*)(base + XB + TB + 4 * g);
-            yw[1] = *(const uint32_t*)(base + XB + TB + 16 + 4 * g);
-        } else {
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
-                uint32_t t = 0;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t gr = r0 + mt * 16 + 4 * g + v;
-                    t |= (gr < r_end ? (uint32_t)Y[gr] : 0u) << (8 * v);
-                }
-                yw[mt] = t;
-            }
-        }
-        bf16x8 ra[CS];
-#pragma unroll
-        for (int cs = 0; cs < CS; ++cs) {
-            floatx8 rv;
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = mt * 16 + 4 * g + v;
-                    const float y = (float)((yw[mt] >> (8 * v)) & 0xffu);
-                    rv[4 * mt + v] = (r0 + row < r_end) ? y - sigmoid_hw(sacc[mt][cs][v]) : 0.f;
-                }
-            ra[cs] = pack_bf16(rv);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        auto tfrag = [&](int nt) {
-            const int dim = 16 * nt + l16, sw = ld_tsw(dim);
-            const uint8_t* tr = tb + dim * 64 + (g & 1) * 8;
-            const uint2 lo = *(const uint2*)(tr + (((g >> 1)) ^ sw) * 16);
-            const uint2 hi = *(const uint2*)(tr + ((2 + (g >> 1)) ^ sw) * 16);
-            return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
-        };
-        bf16x8 tf0 = tfrag(0), tf1 = tfrag(1);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 bx = tf0;
-            tf0 = tf1;
-            if (nt + 2 < NT) tf1 = tfrag(nt + 2);
-#pragma unroll
-            for (int cs = 0; cs < CS; ++cs)
-                gacc[cs][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[cs], bx, gacc[cs][nt], 0, 0, 0);
-        }
-        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            __builtin_amdgcn_sched_group_barrier(0x008, CS, 0);
-            if (nt + 2 < NT) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
-        }
-    };
-    for (int sidx = 0; sidx < nsub; ++sidx) {
-        if (sidx + 2 < nsub) wait_vmcnt<2 * J>();
-        else if (sidx + 1 < nsub) wait_vmcnt<J>();
-        else wait_vmcnt<0>();
-        lds_barrier();
-        step(sidx, ldsb + ((sidx + 3) % LD_NB) * BUF, ldsb + (sidx % LD_NB) * BUF);
-    }
-#pragma unroll
-    for (int cs = 0; cs < CS; ++cs)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t c = cw + 16 * cs + 4 * g + v;
-                const int64_t d = 16 * nt + l16;
-                if (c < C && d < D) a.ws.part_g[((int64_t)split * C + c) * D + d] = gacc[cs][nt][v];
-            }
-}
-
 // ---------------------------------------------------------------------------
-// Gradient partials, software-pipelined (D and N multiples of 8): 64 chains per
-// wave (four 16-chain tiles, so 256 chains per workgroup and, at 8192 chains, 32
-// chain tiles x 8 row splits = one workgroup per CU with each split on its own
-// XCD).  The residuals of sub-tile s are formed on the vector ALUs while the
-// matrix cores run the other contraction, in three phases per sub-tile:
-//   1. S of rows 0..15 of sub-tile s          || sigmoids of rows 16..31 of s - 1
-//   2. G^T += R^T X^T of sub-tile s - 1       || sigmoids of rows 0..15 of s
-//   3. S of rows 16..31 of sub-tile s
+// Gradient partials, software-pipelined (copy-staged): 64 chains per wave (four
+// 16-chain tiles, so 256 chains per workgroup and, at 8192 chains, 32 chain
+// tiles x 8 row splits = one workgroup per CU with each split on its own XCD).
+// The residuals of one sub-tile are formed on the vector ALUs while the matrix
+// cores run the other contraction, in three phases per sub-tile s:
+//   1. the X fragments of rows 0..15 of s are read, the residuals of rows
+//      16..31 of s - 1 computed while they arrive, then S of rows 0..15
+//   2. the X fragments of rows 16..31 of s are read; G^T += R^T X^T of s - 1,
+//      with the residuals of rows 0..15 of s computed between its MFMAs
+//   3. S of rows 16..31 of s
 // X^T of sub-tile s - 1 is still read in the iteration of s, so the X^T tiles
 // (with their labels) sit in a ring of five buffers and the X tiles in a ring of
-// four; the copies run three sub-tiles ahead.
+// four; the copies run three sub-tiles ahead.  Its X tiles use their own slot
+// swizzle (see xsw) and row order within the S halves (see below).
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
 
 // four floats to BF16 (round to nearest even), packed in two dwords
 __device__ __forceinline__ uint2 pack4_bf16(floatx4 f) {
     return __builtin_bit_cast(uint2, __builtin_convertvector(f, bf16x4v));
-}
-
-// y - sigmoid(s) of the lane's four rows row0 + v (v = 0..3, rows counted from the
-// sub-tile's first), labels packed one per byte in yw; rows at or past nvalid give 0
-__device__ __forceinline__ uint2 residual4(floatx4 s, uint32_t yw, int row0, int nvalid) {
-    floatx4 r;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const float y = (float)((yw >> (8 * v)) & 0xffu);
-        r[v] = (row0 + v < nvalid) ? y - sigmoid_hw(s[v]) : 0.f;
-    }
-    return pack4_bf16(r);
 }
 
 constexpr int LP_NBX = 4;     // X sub-tile buffers of the pipelined kernel
@@ -594,7 +367,9 @@ __host__ __device__ constexpr int pipe_lds_bytes() {
     return LP_NBX * LB_RS * 32 * KS * 2 + LP_NBT * (32 * KS * LB_RS * 2 + LD_YB);
 }
 
-template <int KS>
+// FULL: D == 32 KS and every sub-tile whole (N a multiple of 32): the copies
+// need no clamps and the residuals no row masks.
+template <int KS, bool FULL>
 __global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float* __restrict__ xsrc,
                                                         const float* __restrict__ psrc, int drift,
                                                         int64_t rows_per_split, int nsplit,
@@ -604,7 +379,9 @@ __global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float
     constexpr int CW = 16 * CS, CT = LB_NW * CW;
     constexpr int DP = 32 * KS;
     constexpr int SR = DP / 8;
-    constexpr int XM = ld_xmask(SR);
+    // X slot swizzle of row r: (r & 3) | (bit 3 of r) << 2 (r & 3 with 4 slots), so
+    // the rows one quarter-wave reads (8 q + 4 mt + (0..3)) fall on distinct slots
+    auto xsw = [](int r) { return SR >= 8 ? ((r & 3) | (((r >> 3) & 1) << 2)) : (r & 3); };
     constexpr int XB = LB_RS * DP * 2;          // bytes of an X sub-tile
     constexpr int TB = DP * LB_RS * 2;          // bytes of an X^T sub-tile
     constexpr int TBY = TB + LD_YB;             // X^T sub-tile + labels
@@ -658,12 +435,11 @@ __global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float
     if (r_end > N) r_end = N;
     const int nsub = r_begin < r_end ? (int)((r_end - r_begin + LB_RS - 1) / LB_RS) : 0;
 
-    // copies of sub-tile sidx: X into X buffer sidx % 4, X^T and the labels into
-    // X^T buffer sidx % 5; rows past the chunk and dims past D read in-range data
+    // copies of sub-tile sidx: X into xbase, X^T and the labels into tbase; in
+    // the general case rows past the chunk and dims past D read in-range data
     // whose products are masked (residual 0) or discarded
     auto copy_in = [&](int sidx, uint8_t* __restrict__ xbase, uint8_t* __restrict__ tbase) {
         const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
-        const int nrow = (int)(r_end - r0 < LB_RS ? r_end - r0 : LB_RS);   // multiple of 8
         const char* xsrc_t = (const char*)(X + r0 * D);
         const char* tsrc_t = (const char*)(Xt + r0);
         // the lane index through an empty asm: the per-lane offsets below are
@@ -671,34 +447,43 @@ __global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float
         // (and spilled: a reload's wait would also wait for the copies in flight)
         int ln = lane;
         asm volatile("" : "+v"(ln));
-        if (nrow == LB_RS && D == DP) {
-            // whole sub-tile, rows of exactly DP dims: X rows are contiguous and the
-            // swizzle term of a wave's copies does not depend on k (likewise for X^T)
-            const int xrow = (64 / SR) * w + ln / SR;
-            const uint32_t xoff = (uint32_t)(ln / SR) * (uint32_t)(DP * 2) +
-                                  16u * (uint32_t)((ln % SR) ^ (xrow & XM));
-            const int tdim = 16 * w + (ln >> 2);
-            const uint32_t toff = (uint32_t)(ln >> 2) * (uint32_t)N * 2u + 16u * (uint32_t)((ln & 3) ^ ld_tsw(tdim));
+        if constexpr (FULL) {
+            // rows of exactly DP dims, X rows contiguous; the swizzle term of a wave's
+            // copies does not depend on k (nor does that of X^T)
+            // row of lane ln in copy k: A + (256 / SR) k with A below; its swizzle
+            // depends on k only through bit 3 of the row, i.e. the parity of k when
+            // SR = 32 (two offsets), not at all otherwise
+            const int arow = (64 / SR) * w + ln / SR;
+            uint32_t xoff[2];
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+                const int sw = SR >= 8 ? ((arow & 3) | ((((arow >> 3) & 1) ^ par) << 2)) : (arow & 3);
+                xoff[par] = (uint32_t)(ln / SR) * (uint32_t)(DP * 2) + 16u * (uint32_t)((ln % SR) ^ sw);
+            }
+            const uint32_t toff = (uint32_t)(ln >> 2) * (uint32_t)N * 2u + 16u * (uint32_t)((ln & 3) ^ ((ln >> 3) & 3));
 #pragma unroll
             for (int k = 0; k < JW; ++k) {
                 const int i = w + LB_NW * k;
-                if (i < XI) {
-                    __builtin_amdgcn_global_load_lds((const void*)(xsrc_t + (uint32_t)i * 1024u + xoff),
+                const bool isx = (XI % LB_NW == 0) ? (k < XI / LB_NW) : (i < XI);
+                if (isx) {
+                    __builtin_amdgcn_global_load_lds((const void*)(xsrc_t + (uint32_t)i * 1024u +
+                                                                   xoff[SR == 32 ? (k & 1) : 0]),
                                                      (lds_void_t*)(xbase + i * 1024), 16, 0, 0);
                 } else {
                     const int ii = i - XI;
-                    __builtin_amdgcn_global_load_lds(
-                        (const void*)(tsrc_t + (uint32_t)(16 * ii) * (uint32_t)N * 2u + toff),
-                        (lds_void_t*)(tbase + ii * 1024), 16, 0, 0);
+                    __builtin_amdgcn_global_load_lds((const void*)(tsrc_t + (uint32_t)(16 * ii) * (uint32_t)N * 2u + toff),
+                                                     (lds_void_t*)(tbase + ii * 1024), 16, 0, 0);
                 }
             }
+            __builtin_amdgcn_global_load_lds((const void*)(Y + r0 + 4 * (ln & 7)), (lds_void_t*)(tbase + TB), 4, 0, 0);
         } else {
+            const int nrow = (int)(r_end - r0 < LB_RS ? r_end - r0 : LB_RS);   // multiple of 8
 #pragma unroll
             for (int k = 0; k < JW; ++k) {
                 const int i = w + LB_NW * k;
                 if (i < XI) {
                     const int q = i * 64 + ln;
-                    const int row = q / SR, c = (q % SR) ^ (row & XM);
+                    const int row = q / SR, c = (q % SR) ^ xsw(row);
                     const int rowc = row < nrow ? row : nrow - 1;
                     const uint32_t off = (uint32_t)(rowc * (int)D + (8 * c < D ? 8 * c : 0)) * 2u;
                     __builtin_amdgcn_global_load_lds((const void*)(xsrc_t + off), (lds_void_t*)(xbase + i * 1024),
@@ -713,24 +498,67 @@ __global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float
                                                      16, 0, 0);
                 }
             }
+            // labels: dword (lane % 8) of the sub-tile's rows; the rows left in the chunk are a
+            // multiple of 8, so a dword that starts in range ends in range (else row r0's is read)
+            const int64_t yo = r0 + 4 * (ln & 7) < r_end ? r0 + 4 * (ln & 7) : r0;
+            __builtin_amdgcn_global_load_lds((const void*)(Y + yo), (lds_void_t*)(tbase + TB), 4, 0, 0);
         }
-        // labels: dword (lane % 8) of the sub-tile's rows; the rows left in the chunk are a
-        // multiple of 8, so a dword that starts in range ends in range (else row r0's is read)
-        const int64_t yo = r0 + 4 * (ln & 7) < r_end ? r0 + 4 * (ln & 7) : r0;
-        __builtin_amdgcn_global_load_lds((const void*)(Y + yo), (lds_void_t*)(tbase + TB), 4, 0, 0);
     };
     auto xbuf = [&](int sidx) { return xring + (sidx % LP_NBX) * XB; };
     auto tbuf = [&](int sidx) { return tring + (sidx % LP_NBT) * TBY; };
-    auto xfrag = [&](const uint8_t* xb, int ks, int mt) {
-        const int row = mt * 16 + l16;
-        return *(const bf16x8*)(xb + row * (DP * 2) + (((4 * ks + g) ^ (row & XM)) * 16));
+    // Rows of the S halves: half mt, lane position i = 4 q + v holds sub-tile row
+    // 8 q + 4 mt + v, so lane group g ends up with the residuals of rows 8 g .. 8 g + 7
+    // (rows 8 g + v from half 0, 8 g + 4 + v from half 1), the K order of the second
+    // contraction; its X^T operand is then the one 16-byte slot g of a dim.
+    // Fragment addresses from a few per-lane offsets plus immediates.  X: row
+    // rho = 8 (l16 >> 2) + 4 mt + (l16 & 3) has swizzle l16 & 7, and slot
+    // (4 ks + g) ^ (l16 & 7) = 8 (ks >> 1) + 4 ((ks & 1) ^ rb) + (g ^ (l16 & 3)) with
+    // rb = (l16 >> 2) & 1: two offsets (even / odd ks) per half.  X^T: the swizzle of
+    // dim 16 nt + l16 is (l16 >> 1) & 3 for every nt.
+    uint32_t xoff[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        const int row = 8 * (l16 >> 2) + 4 * mt + (l16 & 3);
+        const int sw = xsw(row);
+        const int rb = (sw >> 2) & 1, gg = g ^ (sw & 3);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) xoff[mt][e] = (uint32_t)(row * (DP * 2) + 16 * (4 * (e ^ rb) + gg));
+    }
+    const uint32_t toff = (uint32_t)(l16 * 64 + 16 * (g ^ ((l16 >> 1) & 3)));
+    // a phase's base offsets pass through one empty asm at the phase's start, so
+    // that a register per offset plus the instructions' immediate offsets address
+    // its fragments (instead of one hoisted register per fragment)
+    auto xfrag_o = [&](const uint8_t* xb, const uint32_t* o2, int ks) {
+        return *(const bf16x8*)(xb + o2[ks & 1] + 128 * (ks >> 1));
     };
-    auto tfrag = [&](const uint8_t* tb, int nt) {
-        const int dim = 16 * nt + l16, sw = ld_tsw(dim);
-        const uint8_t* tr = tb + dim * 64 + (g & 1) * 8;
-        const uint2 lo = *(const uint2*)(tr + (((g >> 1)) ^ sw) * 16);
-        const uint2 hi = *(const uint2*)(tr + ((2 + (g >> 1)) ^ sw) * 16);
-        return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+    auto xfrag = [&](const uint8_t* xb, int ks, int mt) { return xfrag_o(xb, xoff[mt], ks); };
+    auto tfrag_o = [&](const uint8_t* tb, uint32_t o, int nt) { return *(const bf16x8*)(tb + o + 1024 * nt); };
+    auto tfrag = [&](const uint8_t* tb, int nt) { return tfrag_o(tb, toff, nt); };
+    // residuals of one 16-row half (rows row0 + v of the sub-tile, v = 0..3)
+    auto resid = [&](floatx4 sv, uint32_t yw, int row0, int nvalid) {
+        floatx4 r;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float y = (float)((yw >> (8 * v)) & 0xffu);
+            const float t = y - sigmoid_hw(sv[v]);
+            r[v] = (FULL || row0 + v < nvalid) ? t : 0.f;
+        }
+        return pack4_bf16(r);
+    };
+    // S of one 16-row half of the sub-tile in xb
+    auto sphase = [&](const uint8_t* __restrict__ xb, int mt, floatx4* sacc) {
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs) sacc[cs] = floatx4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 xf0 = xfrag(xb, 0, mt), xf1 = KS > 1 ? xfrag(xb, 1, mt) : xf0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf16x8 ax = xf0;
+            xf0 = xf1;
+            if (ks + 2 < KS) xf1 = xfrag(xb, ks + 2, mt);
+#pragma unroll
+            for (int cs = 0; cs < CS; ++cs)
+                sacc[cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, thb[cs][ks], sacc[cs], 0, 0, 0);
+        }
     };
 
     floatx4 gacc[CS][NT];
@@ -739,19 +567,9 @@ __global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) gacc[cs][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    if (nsub > 0) copy_in(0, xbuf(0), tbuf(0));
-    if (nsub > 1) copy_in(1, xbuf(1), tbuf(1));
-    if (nsub > 2) copy_in(2, xbuf(2), tbuf(2));
-
-    // pipeline registers: S of rows 16..31 of the previous sub-tile, the packed
-    // residuals of rows 0..15 of the previous (lo_p) and current (lo_c) sub-tile
-    floatx4 s1p[CS];
-    uint2 lo_p[CS];
-    uint32_t yprev[2] = {0u, 0u};
-    int nvp = 0;          // valid rows of the previous sub-tile
-
     // G^T += R^T X^T of the sub-tile in tb with residual operands ra
-    auto gphase = [&](const uint8_t* __restrict__ tb, const bf16x8* ra) {
+    auto gphase = [&](const uint8_t* __restrict__ tb, const bf16x8* ra, uint32_t to) {
+        auto tfrag = [&](const uint8_t* t, int nt) { return tfrag_o(t, to, nt); };
         bf16x8 tf0 = tfrag(tb, 0), tf1 = tfrag(tb, 1);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
@@ -764,6 +582,40 @@ __global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float
         }
     };
 
+    if (nsub > 0) copy_in(0, xbuf(0), tbuf(0));
+    if (nsub > 1) copy_in(1, xbuf(1), tbuf(1));
+    if (nsub > 2) copy_in(2, xbuf(2), tbuf(2));
+    auto wait_tile = [&](int sidx) {
+        if (sidx + 2 < nsub) wait_vmcnt<2 * J>();
+        else if (sidx + 1 < nsub) wait_vmcnt<J>();
+        else wait_vmcnt<0>();
+        lds_barrier();
+    };
+    auto nvalid = [&](int sidx) {
+        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
+        return (int)(r_end - r0 < LB_RS ? r_end - r0 : LB_RS);
+    };
+
+    // pipeline registers: S of rows 16..31 of the previous sub-tile, the packed
+    // residuals of its rows 0..15, its labels and valid rows
+    floatx4 s1p[CS];
+    uint2 lo_p[CS];
+    uint32_t yp1 = 0u;
+    int nvp = 0;
+    if (nsub > 0) {       // the first sub-tile: no G of a previous one
+        wait_tile(0);
+        if (3 < nsub) copy_in(3, xbuf(3), tbuf(3));
+        const uint8_t* tb = tbuf(0);
+        const uint2 yl = *(const uint2*)(tb + TB + 8 * g);
+        const uint32_t y0 = yl.x;
+        yp1 = yl.y;
+        nvp = nvalid(0);
+        floatx4 s0[CS];
+        sphase(xbuf(0), 0, s0);
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs) lo_p[cs] = resid(s0[cs], y0, 8 * g, nvp);
+        sphase(xbuf(0), 1, s1p);
+    }
     // one sub-tile; the copy targets (xdst, tdst) and the buffers read (xb, tprev,
     // tcur) are distinct, which the restrict qualifiers tell the compiler, so the
     // LDS reads need not wait for the copies in flight (the explicit vmcnt waits
@@ -771,81 +623,63 @@ __global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float
     auto iter = [&](int sidx, uint8_t* __restrict__ xdst, uint8_t* __restrict__ tdst, const uint8_t* __restrict__ xb,
                     const uint8_t* __restrict__ tprev, const uint8_t* __restrict__ tcur) {
         if (sidx + 3 < nsub) copy_in(sidx + 3, xdst, tdst);
-        const int64_t r0 = r_begin + (int64_t)sidx * LB_RS;
-        const int nv = (int)(r_end - r0 < LB_RS ? r_end - r0 : LB_RS);
-        // labels of the lane's rows 4 g .. 4 g + 3 (half 0) and 16 + 4 g .. (half 1)
-        const uint32_t ycur0 = *(const uint32_t*)(tcur + TB + 4 * g);
-        const uint32_t ycur1 = *(const uint32_t*)(tcur + TB + 16 + 4 * g);
-
-        // phase 1: S of rows 0..15 || residuals of rows 16..31 of the previous sub-tile
+        const int nv = nvalid(sidx);
+        // phase 1: the X fragments of rows 0..15 are read first, the residuals of
+        // rows 16..31 of the previous sub-tile computed while they arrive, then S
+        uint32_t o1[2] = {xoff[0][0], xoff[0][1]};
+        asm volatile("" : "+v"(o1[0]), "+v"(o1[1]));
+        bf16x8 xa[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) xa[ks] = xfrag_o(xb, o1, ks);
+        const uint2 yl = *(const uint2*)(tcur + TB + 8 * g);
+        const uint32_t y0 = yl.x, y1 = yl.y;
+        bf16x8 rp[CS];
+#pragma unroll
+        for (int cs = 0; cs < CS; ++cs) {
+            const uint2 hi = resid(s1p[cs], yp1, 8 * g + 4, nvp);
+            rp[cs] = __builtin_bit_cast(bf16x8, make_uint4(lo_p[cs].x, lo_p[cs].y, hi.x, hi.y));
+        }
         floatx4 s0[CS];
 #pragma unroll
         for (int cs = 0; cs < CS; ++cs) s0[cs] = floatx4{0.f, 0.f, 0.f, 0.f};
-        {
-            bf16x8 xf0 = xfrag(xb, 0, 0), xf1 = KS > 1 ? xfrag(xb, 1, 0) : xf0;
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const bf16x8 ax = xf0;
-                xf0 = xf1;
-                if (ks + 2 < KS) xf1 = xfrag(xb, ks + 2, 0);
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                for (int cs = 0; cs < CS; ++cs)
-                    s0[cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, thb[cs][ks], s0[cs], 0, 0, 0);
-            }
-        }
-        bf16x8 rp[CS];
-        if (sidx > 0) {
+            for (int cs = 0; cs < CS; ++cs)
+                s0[cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], thb[cs][ks], s0[cs], 0, 0, 0);
+        // phase 2: the X fragments of rows 16..31 read for phase 3; G of the previous
+        // sub-tile with the residuals of rows 0..15 of this one in between
+        uint32_t o2[2] = {xoff[1][0], xoff[1][1]}, ot = toff;
+        asm volatile("" : "+v"(o2[0]), "+v"(o2[1]), "+v"(ot));
+        bf16x8 xb1[KS];
 #pragma unroll
-            for (int cs = 0; cs < CS; ++cs) {
-                const uint2 hi = residual4(s1p[cs], yprev[1], 16 + 4 * g, nvp);
-                rp[cs] = __builtin_bit_cast(bf16x8, make_uint4(lo_p[cs].x, lo_p[cs].y, hi.x, hi.y));
-            }
-        }
-        // phase 2: G of the previous sub-tile || residuals of rows 0..15 of this one
-        if (sidx > 0) gphase(tprev, rp);
-        uint2 lo_c[CS];
+        for (int ks = 0; ks < KS; ++ks) xb1[ks] = xfrag_o(xb, o2, ks);
+        gphase(tprev, rp, ot);
 #pragma unroll
-        for (int cs = 0; cs < CS; ++cs) lo_c[cs] = residual4(s0[cs], ycur0, 4 * g, nv);
+        for (int cs = 0; cs < CS; ++cs) lo_p[cs] = resid(s0[cs], y0, 8 * g, nv);
         // phase 3: S of rows 16..31
-        floatx4 s1[CS];
 #pragma unroll
-        for (int cs = 0; cs < CS; ++cs) s1[cs] = floatx4{0.f, 0.f, 0.f, 0.f};
-        {
-            bf16x8 xf0 = xfrag(xb, 0, 1), xf1 = KS > 1 ? xfrag(xb, 1, 1) : xf0;
+        for (int cs = 0; cs < CS; ++cs) s1p[cs] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const bf16x8 ax = xf0;
-                xf0 = xf1;
-                if (ks + 2 < KS) xf1 = xfrag(xb, ks + 2, 1);
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                for (int cs = 0; cs < CS; ++cs)
-                    s1[cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, thb[cs][ks], s1[cs], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int cs = 0; cs < CS; ++cs) {
-            s1p[cs] = s1[cs];
-            lo_p[cs] = lo_c[cs];
-        }
-        yprev[0] = ycur0;
-        yprev[1] = ycur1;
+            for (int cs = 0; cs < CS; ++cs)
+                s1p[cs] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb1[ks], thb[cs][ks], s1p[cs], 0, 0, 0);
+        yp1 = y1;
         nvp = nv;
     };
-    for (int sidx = 0; sidx < nsub; ++sidx) {
-        if (sidx + 2 < nsub) wait_vmcnt<2 * J>();
-        else if (sidx + 1 < nsub) wait_vmcnt<J>();
-        else wait_vmcnt<0>();
-        lds_barrier();
+    for (int sidx = 1; sidx < nsub; ++sidx) {
+        wait_tile(sidx);
         iter(sidx, xbuf(sidx + 3), tbuf(sidx + 3), xbuf(sidx), tbuf(sidx + LP_NBT - 1), tbuf(sidx));
     }
     if (nsub > 0) {
         bf16x8 rp[CS];
 #pragma unroll
         for (int cs = 0; cs < CS; ++cs) {
-            const uint2 hi = residual4(s1p[cs], yprev[1], 16 + 4 * g, nvp);
+            const uint2 hi = resid(s1p[cs], yp1, 8 * g + 4, nvp);
             rp[cs] = __builtin_bit_cast(bf16x8, make_uint4(lo_p[cs].x, lo_p[cs].y, hi.x, hi.y));
         }
-        gphase(tbuf(nsub - 1), rp);
+        gphase(tbuf(nsub - 1), rp, toff);
     }
 #pragma unroll
     for (int cs = 0; cs < CS; ++cs)
@@ -1242,10 +1076,11 @@ static hipError_t lb_grad_k(const PlainArgs& a, const float* x, const float* p, 
         constexpr int PCT = LB_NW * 64;
         const int ptile = (int)((a.C + PCT - 1) / PCT);
         const size_t ldd = (size_t)pipe_lds_bytes<KS>();
+        const bool full = a.tg.D == 32 * KS && a.tg.N % LB_RS == 0;
+        auto kern = full ? k_lr16_grad_pipe<KS, true> : k_lr16_grad_pipe<KS, false>;
         if (ldd > 65536)
-            (void)hipFuncSetAttribute((const void*)k_lr16_grad_pipe<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)ldd);
-        hipLaunchKernelGGL(k_lr16_grad_pipe<KS>, dim3((unsigned)(ptile * nsplit)), dim3(256), ldd, s, a, x, p, drift,
+            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldd);
+        hipLaunchKernelGGL(kern, dim3((unsigned)(ptile * nsplit)), dim3(256), ldd, s, a, x, p, drift,
                            rows_for(a.tg.N, nsplit), nsplit, (const uint16_t*)Xt);
         return hipGetLastError();
     }
