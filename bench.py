@@ -462,7 +462,7 @@ def bench_served(args):
     # inputs of every request uploaded before the clock starts (arrivals then cost one C call)
     preps = []
     for _, w in stream:
-        bf = w.kind == W.LOGREG and w.dim <= 256
+        bf = w.kind == W.LOGREG and w.dim <= 512
         preps.append(srv.prepare(w, grad_bf16=bf, server_samples=True, trace=False))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -506,7 +506,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--grad", default="auto", choices=["auto", "f32", "bf16"],
                     help="bf16: BF16 MFMA gradient contractions (logistic regression with BF16 X); auto: bf16 where "
-                         "the workload stores X in BF16 and D <= 256")
+                         "the workload stores X in BF16 and D <= 512")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload: skip the FP32-gradient and secondary-workload lines")
     ap.add_argument("--transitions", type=int, default=None,
@@ -588,7 +588,7 @@ def main():
 # block of 25 adapted burn-in + 25 kept transitions from the seeded start.
 DEFAULT_CONFIG = "logreg_100000x256"
 DEFAULT_TRANSITIONS = {"logreg_100000x256": 50}
-BF16_X_CONFIGS = ("logreg_100000x256",)      # workloads whose X is stored in BF16 (D <= 256)
+BF16_X_CONFIGS = ("logreg_100000x256",)      # workloads whose X is stored in BF16 (D <= 512)
 
 
 def cpu_model():
@@ -623,7 +623,7 @@ def bench_workload(args, config, grad, form_name, steps, warmup, transitions, es
         w.num_burnin = transitions // 2
         w.num_results = transitions - w.num_burnin
     if grad == "auto":
-        grad = "bf16" if (w.X_bf16 is not None and w.dim <= 256) else "f32"
+        grad = "bf16" if (w.X_bf16 is not None and w.dim <= 512) else "f32"
     form = {"auto": hmc.HMC_FORM_AUTO, "plain": hmc.HMC_FORM_PLAIN, "graph": hmc.HMC_FORM_GRAPH,
             "fused": hmc.HMC_FORM_FUSED}[form_name]
     s = hmc.sampler_for(w, device=dev, form=form, grad_bf16=grad == "bf16")

@@ -77,7 +77,7 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
     int64_t nsplit_lp = nsplit;
     if (bf16) {
         nsplit = nsplit > 8 ? nsplit : 8;          // BF16 split counts 1, 2, 4, 8
-        nsplit_lp = nsplit > lb_logp_nsplit(tg.N, C) ? nsplit : lb_logp_nsplit(tg.N, C);
+        nsplit_lp = nsplit > lb_logp_nsplit(tg.N, C, D) ? nsplit : lb_logp_nsplit(tg.N, C, D);
     }
     char* p = (char*)base;
     size_t off = 0;
@@ -99,7 +99,11 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
     w.h0 = (double*)take((size_t)C * 8);
     w.part_g = (float*)take((size_t)nsplit * C * D * 4);
     w.part_lp = (double*)take((size_t)nsplit_lp * C * 8);
-    w.xt = bf16 ? take((size_t)tg.N * D * 2) : nullptr;
+    int64_t np = 0;
+    const size_t padb = bf16 ? lb_pad_bytes(tg.N, D, &np, nullptr) : 0;
+    w.xt = bf16 ? take(padb) : nullptr;
+    w.xp = bf16 ? take(padb) : nullptr;
+    w.yp = bf16 ? take((size_t)np) : nullptr;
     w.bk_x = take(state);
     w.bk_g = take(state);
     w.bk_logp = (double*)take((size_t)C * 8);
@@ -167,7 +171,7 @@ hmc_status hmc::validate_args(const hmc_target* tg, const hmc_config* cfg, Targe
     if (cfg->grad_dtype == HMC_BF16 && !(tg->kind == HMC_TGT_LOGREG && tg->x_dtype == HMC_BF16))
         return fail(HMC_E_UNSUPPORTED, "BF16 gradients need a logistic-regression target with BF16 X");
     if (cfg->grad_dtype == HMC_BF16 && !bf16_grad_supported(t))
-        return fail(HMC_E_UNSUPPORTED, "BF16 gradients support D <= 256");
+        return fail(HMC_E_UNSUPPORTED, "BF16 gradients support D <= 512");
     if (cfg->grad_dtype == HMC_BF16 && cfg->form == HMC_FORM_FUSED)
         return fail(HMC_E_UNSUPPORTED, "BF16 gradients run in the plain or graph form");
     if (out) *out = t;
@@ -253,7 +257,7 @@ static hmc_status init_ctx(hmc_ctx* ctx, const TargetDev& t, const hmc_config* c
     }
 
     st = upload_eps(ctx, step_size, step_size_len);
-    if (st == HMC_OK && a.bf16_grad) st = check_hip(launch_transpose_bf16(a, a.ws.xt, ctx->stream), "transpose X");
+    if (st == HMC_OK && a.bf16_grad) st = check_hip(launch_pad_bf16(a, ctx->stream), "padded copies of X");
     if (st == HMC_OK) st = check_hip(launch_set_ctrl(base_ctrl(ctx), a.ws.ctrl, ctx->stream), "init control");
     if (st == HMC_OK) st = check_hip(launch_da_init(a, ctx->stream), "init adaptation");
     if (st == HMC_OK) st = check_hip(launch_bootstrap(a, init_state, ctx->stream), "bootstrap");

@@ -38,7 +38,9 @@ struct Workspace {
     double* h0;    // [C] initial energy
     float* part_g;     // [nsplit, C, D] split-N gradient partials (LOGREG plain)
     double* part_lp;   // [nsplit, C]
-    void* xt;          // [D, N] BF16 transposed copy of X (BF16 gradients only)
+    void* xt;          // [DP, NP] BF16 zero-padded transposed copy of X (BF16 gradients only)
+    void* xp;          // [NP, DP] BF16 zero-padded copy of X
+    void* yp;          // [NP] labels, zeros past N
     void* bk_x;        // autotuner backup of the chain state: [C, D] x and g, [C] logp and eps, [C] da
     void* bk_g;
     double* bk_logp;
@@ -57,8 +59,10 @@ hmc_status validate_args(const hmc_target* tg, const hmc_config* cfg, TargetDev*
 int64_t logreg_nsplit(int64_t N, int64_t C);
 int64_t logreg_nsplit_cap(int64_t N, int64_t C);
 int lb_grad_nsplit(int64_t N, int64_t C, int64_t D);
-int lb_logp_nsplit(int64_t N, int64_t C);
+int lb_logp_nsplit(int64_t N, int64_t C, int64_t D);
 bool bf16_grad_supported(const TargetDev& tg);
+// bytes of the padded copy of X for the BF16 form ([NP, DP] BF16), with NP and DP
+size_t lb_pad_bytes(int64_t N, int64_t D, int64_t* np, int64_t* dp);
 Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg, size_t* total);
 size_t elem_size(int32_t dtype);
 
@@ -166,9 +170,9 @@ hipError_t launch_remc_swap(const PlainArgs& a, int64_t K, int64_t M, uint32_t t
                             void* sample_row, hipStream_t s);
 
 // ---- BF16 gradients (k_logreg_bf16.hip) -------------------------------------
-hipError_t launch_transpose_bf16(const PlainArgs& a, void* Xt, hipStream_t s);
-hipError_t launch_lr16_grad(const PlainArgs& a, const float* x, const float* p, int drift, const void* Xt,
-                            hipStream_t s);
+// zero-padded copies of X (row-major and transposed) and y into the workspace
+hipError_t launch_pad_bf16(const PlainArgs& a, hipStream_t s);
+hipError_t launch_lr16_grad(const PlainArgs& a, const float* x, const float* p, int drift, hipStream_t s);
 hipError_t launch_lr16_logp(const PlainArgs& a, const float* x, hipStream_t s);
 
 // ---- fused path (k_fused.hip) -----------------------------------------------

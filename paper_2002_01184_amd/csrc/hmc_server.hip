@@ -135,7 +135,7 @@ hipError_t admit(Request* q, void* pool, hipStream_t s) {
     q->eps_host.assign((size_t)a.C, q->req.step_size);
     hipError_t e = hipMemcpyAsync(a.ws.eps, q->eps_host.data(), (size_t)a.C * 8, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
-    if (a.bf16_grad && (e = launch_transpose_bf16(a, a.ws.xt, s)) != hipSuccess) return e;
+    if (a.bf16_grad && (e = launch_pad_bf16(a, s)) != hipSuccess) return e;
     Ctrl c;
     memset(&c, 0, sizeof(c));
     c.n_burnin = q->req.num_burnin;

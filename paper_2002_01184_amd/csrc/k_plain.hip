@@ -751,7 +751,7 @@ hipError_t launch_bootstrap(const PlainArgs& a_in, const void* x_src, hipStream_
         break;
     case HMC_TGT_LOGREG:
         if (a.bf16_grad) {
-            (void)launch_lr16_grad(a, (const float*)a.ws.x, nullptr, 0, a.ws.xt, s);
+            (void)launch_lr16_grad(a, (const float*)a.ws.x, nullptr, 0, s);
             hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, (float*)a.ws.x,
                                (float*)nullptr, (float*)a.ws.g, lb_grad_nsplit_t(a), 0, 0, 0.0, 0);
             (void)launch_lr16_logp(a, (const float*)a.ws.x, s);
@@ -784,7 +784,7 @@ hipError_t launch_leapfrog_step(const PlainArgs& a, double ks, hipStream_t s) {
         break;
     case HMC_TGT_LOGREG:
         if (a.bf16_grad) {
-            (void)launch_lr16_grad(a, (const float*)a.ws.xq, (const float*)a.ws.pq, 1, a.ws.xt, s);
+            (void)launch_lr16_grad(a, (const float*)a.ws.xq, (const float*)a.ws.pq, 1, s);
             hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, (float*)a.ws.xq,
                                (float*)a.ws.pq, (float*)a.ws.gq, lb_grad_nsplit_t(a), 1, 1, ks, 0);
             (void)launch_lr16_logp(a, (const float*)a.ws.xq, s);
@@ -825,7 +825,7 @@ hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipSt
         case HMC_TGT_LOGREG:
             if (a.bf16_grad) {
                 timer_begin(a, s);
-                (void)launch_lr16_grad(a, (const float*)a.ws.xq, (const float*)a.ws.pq, 1, a.ws.xt, s);
+                (void)launch_lr16_grad(a, (const float*)a.ws.xq, (const float*)a.ws.pq, 1, s);
                 timer_end(a, s, "k_lr16_grad");
                 hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, (float*)a.ws.xq,
                                    (float*)a.ws.pq, last ? (float*)a.ws.gq : (float*)nullptr,
