@@ -447,9 +447,15 @@ def to_host(t):
 
 def bench_served(args):
     """Served stream: requests arrive by a seeded Poisson process; each is
-    submitted to the continuous-batching server at its arrival time.  Reports
-    p50/p99 request latency (submission to completion) and whole-stream
-    leapfrog chain-steps/s."""
+    submitted to the continuous-batching server at its arrival time, with its
+    samples held by the server.  A client thread collects every finished
+    request's samples (hmc_server_take into one reused device buffer), which
+    returns their memory to the pool as a serving client would.  Reports p50/p99
+    request latency (submission to completion) and whole-stream leapfrog
+    chain-steps/s; offered_load is the stream's GPU work per second of arrivals
+    over the throughput the server achieved (above 1: saturated)."""
+    import threading
+
     import numpy as np
     import torch
 
@@ -457,40 +463,88 @@ def bench_served(args):
     from paper_2002_01184_amd import hmc
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    stream = W.served_stream(n_requests=args.requests, rate=args.rate, seed=0, scale=args.scale)
+    print(f"served stream: generating {args.requests} requests ({args.scale})", file=sys.stderr, flush=True)
+    def gen_progress(i, n):
+        if i % 8 == 0 or i == n:
+            print(f"served stream: {i}/{n} requests generated", file=sys.stderr, flush=True)
+    stream = W.served_stream(n_requests=args.requests, rate=args.rate, seed=0, scale=args.scale,
+                             progress=gen_progress)
     srv = hmc.Server(int(args.budget_gb * (1 << 30)), transitions_per_tick=args.tick)
     # inputs of every request uploaded before the clock starts (arrivals then cost one C call)
     preps = []
-    for _, w in stream:
+    for k, (_, w) in enumerate(stream):
         bf = w.kind == W.LOGREG and w.dim <= 512
         preps.append(srv.prepare(w, grad_bf16=bf, server_samples=True, trace=False))
+        if (k + 1) % 16 == 0:
+            print(f"served stream: {k + 1} requests uploaded", file=sys.stderr, flush=True)
+    sink_bytes = max(w.num_results * w.num_chains * w.dim * (8 if w.state_dtype == "f64" else 4) for _, w in stream)
+    sink = torch.empty((sink_bytes + 3) // 4, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
+    print(f"served stream: {len(stream)} requests uploaded; arrivals over {stream[-1][0]:.1f} s",
+          file=sys.stderr, flush=True)
+    ids, lats, errors = [], {}, []
+    lock = threading.Lock()
+    done_submitting = threading.Event()
+
+    def collect():
+        seen, outstanding = 0, []
+        try:
+            while True:
+                with lock:
+                    outstanding.extend(ids[seen:])
+                    seen = len(ids)
+                    last = done_submitting.is_set()
+                for rid in list(outstanding):
+                    state, lat = hmc.hmc_server_poll(srv.srv, rid)
+                    if state == hmc.HMC_REQ_DONE:
+                        hmc.hmc_server_take(srv.srv, rid, ctypes_ptr(sink))
+                        outstanding.remove(rid)
+                        lats[rid] = lat
+                        print(f"served stream: request {rid} done after {lat:.2f} s ({len(lats)} done)",
+                              file=sys.stderr, flush=True)
+                if last and not outstanding and seen == len(ids):
+                    return
+                time.sleep(0.002)
+        except Exception as e:      # reported by the main thread
+            errors.append(e)
+
+    th = threading.Thread(target=collect)
     t0 = time.perf_counter()
-    ids = []
+    th.start()
     for (ta, w), p in zip(stream, preps):
         now = time.perf_counter() - t0
         if ta > now:
             time.sleep(ta - now)
-        ids.append(srv.submit_prepared(p))
-    lats = []
-    for rid in ids:
-        state, lat = hmc.hmc_server_wait(srv.srv, rid)
-        lats.append(lat)
+        rid = srv.submit_prepared(p)
+        with lock:
+            ids.append(rid)
+    done_submitting.set()
+    th.join()
+    if errors:
+        raise errors[0]
     makespan = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
-    lats = np.array(lats)
+    lat = np.array([lats[i] for i in ids])
     chain_steps = sum(w.chain_steps() for _, w in stream)
+    arrivals_s = stream[-1][0]
+    value = chain_steps / makespan
     return {
-        "metric": METRIC, "value": chain_steps / makespan, "unit": "leapfrog chain-steps/s", "n_gpus": 1,
+        "metric": METRIC, "value": value, "unit": "leapfrog chain-steps/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": makespan * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 (Gaussian), bf16/f32 (logistic)", "data": "synthetic (seeded stream)",
         "config": {"workload": f"served_stream_{args.scale}", "requests": args.requests, "rate_per_s": args.rate,
                    "transitions_per_tick": args.tick, "hbm_budget_gb": args.budget_gb},
-        "latency_p50_s": float(np.percentile(lats, 50)), "latency_p99_s": float(np.percentile(lats, 99)),
-        "latency_max_s": float(lats.max()), "offered_chain_steps": chain_steps,
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_max_s": float(lat.max()), "offered_chain_steps": chain_steps, "arrivals_s": arrivals_s,
+        "offered_load": (chain_steps / max(arrivals_s, 1e-9)) / value,
         "server": {k: int(v) for k, v in st.items()},
     }
+
+
+def ctypes_ptr(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def main():
@@ -517,8 +571,9 @@ def main():
     ap.add_argument("--tick", type=int, default=10, help="served_stream: transitions per server tick")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="served_stream: server HBM pool")
     ap.add_argument("--autotune", action="store_true", help="run the library's autotuner before timing")
-    ap.add_argument("--ess-results", type=int, default=9000,
-                    help="kept draws of the separate ESS run (same burn-in); 0 skips it")
+    ap.add_argument("--ess-results", type=int, default=None,
+                    help="kept draws of the separate ESS run (same burn-in); 0 skips it (default: 16000 for the "
+                         "100000 x 256 workload, whose split R-hat reaches 1.01 near 14000 draws, else 9000)")
     ap.add_argument("--moments", action="store_true",
                     help="streaming expectations: moments through a ring instead of stored samples")
     ap.add_argument("--ring-rows", type=int, default=64, help="--moments: kept states per fold")
@@ -528,9 +583,11 @@ def main():
     ap.add_argument("--remc", type=int, default=0,
                     help="replica exchange with this many replicas (divides the workload's chains)")
     ap.add_argument("--remc-beta-min", type=float, default=0.1, help="smallest inverse temperature of the ladder")
-    ap.add_argument("--ess-seconds", type=float, default=60.0,
-                    help="time budget of the separate ESS run (burn-in included)")
-    ap.add_argument("--ess-gb", type=float, default=16.0, help="memory budget of its kept samples (GiB)")
+    ap.add_argument("--ess-seconds", type=float, default=None,
+                    help="time budget of the separate ESS run, burn-in included (default 240 s for the 100000 x 256 "
+                         "workload, else 60 s)")
+    ap.add_argument("--ess-gb", type=float, default=None,
+                    help="memory budget of its kept samples in GiB (default 150 for the 100000 x 256 workload, else 16)")
     ap.add_argument("--ess-min-results", type=int, default=100, help="fewest kept draws worth an ESS run")
     args = ap.parse_args()
 
@@ -552,6 +609,13 @@ def main():
         args.config = "logreg_1000x25" if special else DEFAULT_CONFIG
     if args.grad == "auto":
         args.grad = "bf16" if args.config in BF16_X_CONFIGS else "f32"
+    long_ess = args.config == DEFAULT_CONFIG
+    if args.ess_results is None:
+        args.ess_results = 16000 if long_ess else 9000
+    if args.ess_seconds is None:
+        args.ess_seconds = 240.0 if long_ess else 60.0
+    if args.ess_gb is None:
+        args.ess_gb = 150.0 if long_ess else 16.0
     if args.config == "served_stream":
         print(json.dumps(bench_served(args)), flush=True)
         return
@@ -761,8 +825,10 @@ def bench_workload(args, config, grad, form_name, steps, warmup, transitions, es
 
 def default_extras(args):
     """Beside the headline: the same workload with FP32 gradient operands (a short
-    run), and the logistic 1000 x 25 and dense Gaussian D = 100 workloads on their
-    fused kernels with ESS at their configured run lengths."""
+    run); the logistic 1000 x 25 and dense Gaussian D = 100 workloads on their
+    fused kernels with ESS at their configured run lengths; and the plain step
+    (one launch per leapfrog step) of every target family at its workload's
+    size, with its roofline."""
     extras = {}
     r = bench_workload(args, DEFAULT_CONFIG, "f32", "plain", 2, 1, 4, ess=False, cpu=False)
     extras["fp32_gradients"] = {k: r[k] for k in ("value", "ms_per_step", "roofline", "roofline_step", "config")}
@@ -770,6 +836,11 @@ def default_extras(args):
         r = bench_workload(args, cfg, "f32", "auto", 5, 2, None, ess=True, cpu=False, ess_seconds=20.0)
         keep = ("value", "ms_per_step", "roofline", "accept_rate", "max_rhat", "ess_per_sec", "ess_run", "config")
         extras[cfg] = {k: r[k] for k in keep if k in r}
+    plain = {}
+    for cfg in ("logreg_1000x25", "gauss_dense_100", "std_normal_1d_wide", "gauss_diag_1000"):
+        r = bench_workload(args, cfg, "f32", "plain", 3, 1, None, ess=False, cpu=False)
+        plain[cfg] = {k: r[k] for k in ("value", "ms_per_step", "roofline", "roofline_step") if k in r}
+    extras["plain_step"] = plain
     return extras
 
 

@@ -99,6 +99,7 @@ Workspace carve_workspace(void* base, const TargetDev& tg, const hmc_config& cfg
     w.h0 = (double*)take((size_t)C * 8);
     w.part_g = (float*)take((size_t)nsplit * C * D * 4);
     w.part_lp = (double*)take((size_t)nsplit_lp * C * 8);
+    w.lr_cnt = (int32_t*)take(tg.kind == HMC_TGT_LOGREG ? (size_t)((C + 63) / 64) * 4 : 0);
     int64_t np = 0;
     const size_t padb = bf16 ? lb_pad_bytes(tg.N, D, &np, nullptr) : 0;
     w.xt = bf16 ? take(padb) : nullptr;

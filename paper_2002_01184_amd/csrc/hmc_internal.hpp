@@ -38,6 +38,7 @@ struct Workspace {
     double* h0;    // [C] initial energy
     float* part_g;     // [nsplit, C, D] split-N gradient partials (LOGREG plain)
     double* part_lp;   // [nsplit, C]
+    int32_t* lr_cnt;   // [ceil(C / 64)] finished splits per chain tile of the FP32 logistic step (0 between launches)
     void* xt;          // [DP, NP] BF16 zero-padded transposed copy of X (BF16 gradients only)
     void* xp;          // [NP, DP] BF16 zero-padded copy of X
     void* yp;          // [NP] labels, zeros past N

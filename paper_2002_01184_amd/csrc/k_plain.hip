@@ -111,6 +111,9 @@ __global__ __launch_bounds__(256) void k_logp_finish(PlainArgs a) {
     if (active && lane == 0) a.ws.logp[c] = lp;
 }
 
+__device__ __forceinline__ void end_scalars(const PlainArgs& a, const Ctrl& ct, int64_t c, int64_t i, bool acc,
+                                            double lar, double dh, double lp_new, double eps_used);
+
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_end(PlainArgs a) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -158,6 +161,14 @@ __global__ __launch_bounds__(256) void k_end(PlainArgs a) {
     }
     if (lane != 0) return;
     a.ws.logp[c] = lp_new;
+    end_scalars(a, ct, c, i, acc, lar, dh, lp_new, eps_used);
+}
+
+// The per-chain scalars at the end of transition i of the call (one lane per
+// chain): step-size adaptation during the burn-in, the trace row of a kept
+// transition, and the hmc_step outputs.
+__device__ __forceinline__ void end_scalars(const PlainArgs& a, const Ctrl& ct, int64_t c, int64_t i, bool acc,
+                                            double lar, double dh, double lp_new, double eps_used) {
     if (ct.adapt && i < ct.n_burnin) {
         const double alpha = lar < 0.0 ? exp(lar) : 1.0;
         if (ct.adapt_kind == HMC_ADAPT_SIMPLE) {
@@ -292,6 +303,207 @@ __global__ __launch_bounds__(256) void k_elem_leapfrog(PlainArgs a, const T* __r
 }
 
 // ---------------------------------------------------------------------------
+// Element-wise targets, merged transition: L launches per transition, each
+// one leapfrog step that reads and writes the trajectory once.
+//   k_elem_first  momentum draw, H0, first half kick, then leapfrog step 1
+//   k_elem_mid    leapfrog steps 2 .. L-1 on (xq, pq)
+//   k_elem_last   leapfrog step L, energy at the end, Metropolis test; an
+//                 accepted chain writes its new x, g and logp from registers,
+//                 a rejected one leaves them as they are (no select copy)
+// G lanes per chain (as chain_group); the arithmetic and the order of every
+// FP64 sum are those of k_begin / k_elem_leapfrog / k_end, so both sequences
+// give bitwise the same chains.  Needs L >= 2.
+// ---------------------------------------------------------------------------
+
+// n (1..4) consecutive elements at p; vector loads when vec (p 16-byte aligned)
+__device__ __forceinline__ void load4(const float* p, int n, bool vec, float v[4]) {
+    if (vec && n == 4) {
+        const float4 q = *(const float4*)p;
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = j < n ? p[j] : 0.f;
+    }
+}
+__device__ __forceinline__ void load4(const double* p, int n, bool vec, double v[4]) {
+    if (vec && n == 4) {
+        const double2 q0 = *(const double2*)p, q1 = *(const double2*)(p + 2);
+        v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = j < n ? p[j] : 0.0;
+    }
+}
+__device__ __forceinline__ void store4(float* p, int n, bool vec, const float v[4]) {
+    if (vec && n == 4) {
+        *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < n) p[j] = v[j];
+    }
+}
+__device__ __forceinline__ void store4(double* p, int n, bool vec, const double v[4]) {
+    if (vec && n == 4) {
+        *(double2*)p = make_double2(v[0], v[1]);
+        *(double2*)(p + 2) = make_double2(v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < n) p[j] = v[j];
+    }
+}
+
+// vec: every row of [C, D] starts 16-byte aligned (D % 4 == 0 in FP32, D even in FP64)
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_elem_first(PlainArgs a, int vec) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x % G;
+    const int64_t c = gid / G;
+    const bool active = c < a.C;
+    const int64_t D = a.tg.D;
+    const uint32_t t = (uint32_t)a.ws.ctrl->t;
+    const T* x = (const T*)a.ws.x;
+    const T* g = (const T*)a.ws.g;
+    T* xq = (T*)a.ws.xq;
+    T* pq = (T*)a.ws.pq;
+    const T* prec = (const T*)a.tg.prec;
+    const bool diag = a.tg.kind == HMC_TGT_GAUSS_DIAG;
+    const double eps = active ? a.ws.eps[c] : 0.0;
+    const double bt = (active && a.ws.beta) ? a.ws.beta[c] : 1.0;
+    const T half_eps = (T)(0.5 * eps * bt);
+    double k0 = 0.0;
+    const int64_t nblk = (D + 3) / 4;
+    if (active) {
+        for (int64_t b = lane; b < nblk; b += G) {
+            T z[4], xv[4], gv[4], xo[4], po[4];
+            momentum4<T>(a.key, (uint32_t)c, t, (uint32_t)b, z, 4 * b + 2 < D);
+            const int n = D - 4 * b < 4 ? (int)(D - 4 * b) : 4;
+            load4(x + c * D + 4 * b, n, vec != 0, xv);
+            load4(g + c * D + 4 * b, n, vec != 0, gv);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                xo[j] = (T)0;
+                po[j] = (T)0;
+                if (j < n) {
+                    const int64_t d = 4 * b + j;
+                    k0 += 0.5 * (double)z[j] * (double)z[j];
+                    const double sd = a.ws.scale ? a.ws.scale[d] : 1.0;
+                    const T hk = a.ws.scale ? (T)(0.5 * eps * bt * sd) : half_eps;
+                    T p = z[j] + hk * gv[j];
+                    const T e = a.ws.scale ? (T)(eps * sd) : (T)eps;
+                    const T xx = fma(e, p, xv[j]);
+                    const T gg = diag ? -prec[d] * xx : -xx;
+                    p = fma((T)(1.0 * eps * bt * sd), gg, p);
+                    xo[j] = xx;
+                    po[j] = p;
+                }
+            }
+            store4(xq + c * D + 4 * b, n, vec != 0, xo);
+            store4(pq + c * D + 4 * b, n, vec != 0, po);
+        }
+    }
+    k0 = group_sum<G>(k0);
+    if (active && lane == 0) a.ws.h0[c] = -(bt * a.ws.logp[c]) + k0;
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_elem_mid(PlainArgs a) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x % G;
+    const int64_t c = gid / G;
+    if (c >= a.C) return;
+    const int64_t D = a.tg.D;
+    T* xq = (T*)a.ws.xq;
+    T* pq = (T*)a.ws.pq;
+    const T* prec = (const T*)a.tg.prec;
+    const bool diag = a.tg.kind == HMC_TGT_GAUSS_DIAG;
+    const double eps = a.ws.eps[c];
+    const double bt = a.ws.beta ? a.ws.beta[c] : 1.0;
+    for (int64_t d = lane; d < D; d += G) {
+        const int64_t i = c * D + d;
+        const double sd = a.ws.scale ? a.ws.scale[d] : 1.0;
+        const T e = a.ws.scale ? (T)(eps * sd) : (T)eps;
+        const T xx = fma(e, pq[i], xq[i]);
+        const T gg = diag ? -prec[d] * xx : -xx;
+        const T p = fma((T)(1.0 * eps * bt * sd), gg, pq[i]);
+        xq[i] = xx;
+        pq[i] = p;
+    }
+}
+
+// NE >= ceil(D / G): dimension lane + G k of the chain is held in slot k
+template <typename T, int G, int NE>
+__global__ __launch_bounds__(256) void k_elem_last(PlainArgs a) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x % G;
+    const int64_t c = gid / G;
+    const bool active = c < a.C;
+    const int64_t D = a.tg.D;
+    const Ctrl& ct = *a.ws.ctrl;
+    const uint64_t t = ct.t;
+    T* x = (T*)a.ws.x;
+    T* g = (T*)a.ws.g;
+    const T* xq = (const T*)a.ws.xq;
+    const T* pq = (const T*)a.ws.pq;
+    const T* prec = (const T*)a.tg.prec;
+    const bool diag = a.tg.kind == HMC_TGT_GAUSS_DIAG;
+    const double eps = active ? a.ws.eps[c] : 0.0;
+    const double bt = (active && a.ws.beta) ? a.ws.beta[c] : 1.0;
+    T xl[NE], gl[NE];
+    double k1 = 0.0, lp1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const int64_t d = lane + (int64_t)G * k;
+        xl[k] = (T)0;
+        gl[k] = (T)0;
+        if (active && d < D) {
+            const int64_t i = c * D + d;
+            const double sd = a.ws.scale ? a.ws.scale[d] : 1.0;
+            const T e = a.ws.scale ? (T)(eps * sd) : (T)eps;
+            const T pv0 = pq[i];
+            const T xx = fma(e, pv0, xq[i]);
+            const T gg = diag ? -prec[d] * xx : -xx;
+            const T p = fma((T)(0.5 * eps * bt * sd), gg, pv0);
+            k1 += 0.5 * (double)p * (double)p;
+            lp1 += 0.5 * (double)xx * (double)gg;
+            xl[k] = xx;
+            gl[k] = gg;
+            if (ct.out_xprop) ((T*)ct.out_xprop)[i] = xx;
+            if (ct.out_pprop) ((T*)ct.out_pprop)[i] = p;
+        }
+    }
+    k1 = group_sum<G>(k1);
+    lp1 = group_sum<G>(lp1);
+    if (!active) return;
+
+    const double dh = (-(bt * lp1) + k1) - a.ws.h0[c];
+    const double lar = log_accept_ratio_of(dh);
+    const bool acc = log_accept_uniform(a.key, (uint32_t)c, (uint32_t)t) < lar;
+    const int64_t i = (int64_t)(t - ct.t_begin);
+    const bool keep = ct.samples && i >= ct.n_burnin && i < ct.n_burnin + ct.n_results;
+    T* smp = keep ? (T*)ct.samples + ((i - ct.n_burnin) * a.C + c) * D : nullptr;
+    if (acc) {
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int64_t d = lane + (int64_t)G * k;
+            if (d < D) {
+                x[c * D + d] = xl[k];
+                g[c * D + d] = gl[k];
+                if (keep) smp[d] = xl[k];
+            }
+        }
+    } else if (keep) {
+        for (int64_t d = lane; d < D; d += G) smp[d] = x[c * D + d];
+    }
+    if (lane != 0) return;
+    double lp_new = lp1;
+    if (acc) a.ws.logp[c] = lp1;
+    else lp_new = a.ws.logp[c];
+    end_scalars(a, ct, c, i, acc, lar, dh, lp_new, eps);
+}
+
+// ---------------------------------------------------------------------------
 // Dense Gaussian: g = -P x with v_mfma_f32_16x16x4f32.
 // Operand layouts (16x16x4, wave64): A[i][k] at lane i + 16 k; B[k][j] at
 // lane j + 16 k; D[i][j] in VGPR v of lane j + 16 (i / 4) with v = i % 4.
@@ -365,6 +577,219 @@ __global__ __launch_bounds__(256) void k_dense_leapfrog(PlainArgs a, const float
 }
 
 // ---------------------------------------------------------------------------
+// Dense Gaussian, merged transition (D <= 128): one launch per leapfrog step,
+// 16 chains per workgroup of 8 waves, wave w owning M-tile w of g = -P x.
+// P is loaded once per launch into VGPRs as the A operands of
+// v_mfma_f32_16x16x4f32 (zero-padded, so the 4 NT k-steps run unrolled), and
+// x is staged chain-major in LDS for the B operands: the operand layout and
+// MFMA sequence of the fused dense kernel (k = g4 KM + ks, even and odd
+// k-steps in two accumulators), so the gradient is bitwise the one of
+// k_dense_leapfrog and of the fused form.  Lane (i16, g4) of wave w holds
+// dims 16 w + 4 g4 + v of chain i16.  FIRST also draws the momentum (Philox
+// block 4 w + g4), forms H0 and makes the first half kick; LAST forms H at the
+// trajectory's end, takes the Metropolis decision and writes the accepted
+// chain's x, g and logp (a rejected chain's are left as they are).
+// ---------------------------------------------------------------------------
+constexpr int DS_NW = 8;
+
+template <int NT, bool FIRST, bool LAST>
+__global__ __launch_bounds__(64 * DS_NW) void k_dense_step(PlainArgs a) {
+    constexpr int KM = 4 * NT;
+    constexpr int XS = 16 * NT + 4;        // floats per chain row of the staged x, and per row of the staged P
+    extern __shared__ float plds[];        // P [16 NT][XS], zero-padded
+    __shared__ __attribute__((aligned(16))) float xs[16 * XS];
+    __shared__ double red[3 * DS_NW * 16];
+    const int64_t D = a.tg.D;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i16 = lane & 15, g4 = lane >> 4;
+    const int64_t c = (int64_t)blockIdx.x * 16 + i16;
+    const bool cvalid = c < a.C;
+    const int64_t cc = cvalid ? c : 0;
+    const bool tile_ok = w < NT;
+    const float* P = (const float*)a.tg.prec;
+    const Ctrl& ct = *a.ws.ctrl;
+    const uint64_t t = ct.t;
+    const double eps = a.ws.eps[cc];
+    const double bt = a.ws.beta ? a.ws.beta[cc] : 1.0;
+    const double* sc = a.ws.scale;
+    float* xq = (float*)a.ws.xq;
+    float* pq = (float*)a.ws.pq;
+    float* X = (float*)a.ws.x;
+    float* Gs = (float*)a.ws.g;
+
+    // P into LDS with contiguous loads (16 bytes at a time when rows are 16-byte
+    // aligned), the padding rows and columns zero; then each lane's A operands
+    // pa[ks] = P[16 w + i16][g4 KM + ks] with 16-byte LDS reads
+    {
+        const int Di = (int)D;
+        if ((Di & 3) == 0 && ((uintptr_t)P & 15) == 0) {
+            for (int e = 4 * (int)threadIdx.x; e < Di * Di; e += 4 * 64 * DS_NW) {
+                const int row = e / Di, col = e - row * Di;
+                *(floatx4*)(plds + row * XS + col) = *(const floatx4*)(P + e);
+            }
+        } else {
+            for (int e = threadIdx.x; e < Di * Di; e += 64 * DS_NW) {
+                const int row = e / Di, col = e - row * Di;
+                plds[row * XS + col] = P[e];
+            }
+        }
+        const int pad = 16 * NT - Di;
+        for (int e = threadIdx.x; e < pad * 16 * NT; e += 64 * DS_NW) {
+            const int r = e / (16 * NT), k = e - r * 16 * NT;
+            plds[(Di + r) * XS + k] = 0.f;          // rows D .. 16 NT
+            plds[k * XS + Di + r] = 0.f;            // columns D .. 16 NT
+        }
+    }
+    __syncthreads();
+    float pa[KM];
+    if (tile_ok) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const floatx4 v4 = *(const floatx4*)(plds + (16 * w + i16) * XS + g4 * KM + 4 * j);
+            pa[4 * j] = v4[0];
+            pa[4 * j + 1] = v4[1];
+            pa[4 * j + 2] = v4[2];
+            pa[4 * j + 3] = v4[3];
+        }
+    } else {
+#pragma unroll
+        for (int ks = 0; ks < KM; ++ks) pa[ks] = 0.f;
+    }
+
+    float xv[4], pv[4], gv[4];
+    bool ok[4];
+    double k0 = 0.0;
+    const int64_t d0 = 16 * w + 4 * g4;
+    if (FIRST) {
+        float z[4] = {0.f, 0.f, 0.f, 0.f};
+        if (tile_ok && d0 < D) momentum4<float>(a.key, (uint32_t)cc, (uint32_t)t, (uint32_t)(4 * w + g4), z, d0 + 2 < D);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t d = d0 + v;
+            ok[v] = tile_ok && cvalid && d < D;
+            const float x0 = ok[v] ? X[c * D + d] : 0.f;
+            const float g0 = ok[v] ? Gs[c * D + d] : 0.f;
+            const float p0 = ok[v] ? z[v] : 0.f;
+            if (ok[v]) k0 += 0.5 * (double)p0 * (double)p0;
+            const float hk = (sc && ok[v]) ? (float)(0.5 * eps * bt * sc[d]) : (float)(0.5 * eps * bt);
+            pv[v] = p0 + hk * g0;
+            xv[v] = x0;
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t d = d0 + v;
+            ok[v] = tile_ok && cvalid && d < D;
+            xv[v] = ok[v] ? xq[c * D + d] : 0.f;
+            pv[v] = ok[v] ? pq[c * D + d] : 0.f;
+        }
+    }
+    // drift, then x of the tile into LDS
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const float e = (sc && ok[v]) ? (float)(eps * sc[d0 + v]) : (float)eps;
+        xv[v] = fmaf(e, pv[v], xv[v]);
+    }
+    if (tile_ok) *(floatx4*)(xs + i16 * XS + 16 * w + 4 * g4) = floatx4{xv[0], xv[1], xv[2], xv[3]};
+    __syncthreads();
+    if (tile_ok) {
+        floatx4 bq[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) bq[q] = *(const floatx4*)(xs + i16 * XS + g4 * KM + 4 * q);
+        floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int ks = 0; ks < KM; ++ks)
+            acc[ks & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[ks], bq[ks >> 2][ks & 3], acc[ks & 1], 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gv[v] = -(acc[0][v] + acc[1][v]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gv[v] = 0.f;
+    }
+    const double ksc = LAST ? 0.5 : 1.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const float kd = (sc && ok[v]) ? (float)(ksc * eps * bt * sc[d0 + v]) : (float)(ksc * eps * bt);
+        pv[v] = fmaf(kd, gv[v], pv[v]);
+    }
+
+    if (!LAST) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (ok[v]) {
+                xq[c * D + d0 + v] = xv[v];
+                pq[c * D + d0 + v] = pv[v];
+            }
+        if (FIRST) {
+            k0 += __shfl_xor(k0, 16, 64);
+            k0 += __shfl_xor(k0, 32, 64);
+            if (g4 == 0) red[w * 16 + i16] = k0;
+            __syncthreads();
+            if (threadIdx.x < 16 && cvalid) {
+                double s0 = 0.0;
+                for (int ww = 0; ww < DS_NW; ++ww) s0 += red[ww * 16 + i16];
+                a.ws.h0[c] = -(bt * a.ws.logp[c]) + s0;
+            }
+        }
+        return;
+    }
+
+    // end of the trajectory: kinetic energy and logp = 1/2 x.g, summed over the
+    // lane groups, then over the waves in wave order
+    double k1 = 0.0, lp1 = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        if (ok[v]) {
+            k1 += 0.5 * (double)pv[v] * (double)pv[v];
+            lp1 += 0.5 * (double)xv[v] * (double)gv[v];
+            if (ct.out_xprop) ((float*)ct.out_xprop)[c * D + d0 + v] = xv[v];
+            if (ct.out_pprop) ((float*)ct.out_pprop)[c * D + d0 + v] = pv[v];
+        }
+    k0 += __shfl_xor(k0, 16, 64);
+    k0 += __shfl_xor(k0, 32, 64);
+    k1 += __shfl_xor(k1, 16, 64);
+    k1 += __shfl_xor(k1, 32, 64);
+    lp1 += __shfl_xor(lp1, 16, 64);
+    lp1 += __shfl_xor(lp1, 32, 64);
+    if (g4 == 0) {
+        red[w * 16 + i16] = k0;
+        red[(DS_NW + w) * 16 + i16] = k1;
+        red[(2 * DS_NW + w) * 16 + i16] = lp1;
+    }
+    __syncthreads();
+    if (!cvalid) return;
+    double s0 = 0.0, s1 = 0.0, sl = 0.0;
+    for (int ww = 0; ww < DS_NW; ++ww) {
+        s0 += red[ww * 16 + i16];
+        s1 += red[(DS_NW + ww) * 16 + i16];
+        sl += red[(2 * DS_NW + ww) * 16 + i16];
+    }
+    const double lp_old = a.ws.logp[c];
+    const double h0 = FIRST ? -(bt * lp_old) + s0 : a.ws.h0[c];
+    const double dh = (-(bt * sl) + s1) - h0;
+    const double lar = log_accept_ratio_of(dh);
+    const bool acc = log_accept_uniform(a.key, (uint32_t)c, (uint32_t)t) < lar;
+    const int64_t i = (int64_t)(t - ct.t_begin);
+    const bool keep = ct.samples && i >= ct.n_burnin && i < ct.n_burnin + ct.n_results;
+    float* smp = keep ? (float*)ct.samples + ((i - ct.n_burnin) * a.C + c) * D : nullptr;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        if (!ok[v]) continue;
+        const int64_t d = d0 + v;
+        if (acc) {
+            X[c * D + d] = xv[v];
+            Gs[c * D + d] = gv[v];
+            if (keep) smp[d] = xv[v];
+        } else if (keep) {
+            smp[d] = X[c * D + d];
+        }
+    }
+    if (threadIdx.x >= 16) return;
+    if (acc) a.ws.logp[c] = sl;
+    end_scalars(a, ct, c, i, acc, lar, dh, acc ? sl : lp_old, eps);
+}
+
+// ---------------------------------------------------------------------------
 // Logistic regression, split over rows.  Workgroup (chain tile of 16, split s)
 // handles rows [s*rows, (s+1)*rows).  Per 16-row tile:
 //   S = X_tile theta^T   (M = rows, N = chains, K = dims)      16x16x4 MFMA
@@ -391,106 +816,306 @@ __device__ __forceinline__ float softplusf_(float s) {
     return fmaxf(s, 0.f) + log1pf(expf(-fabsf(s)));
 }
 
-template <typename XT, int GT>
-__global__ __launch_bounds__(256) void k_logreg_partial(PlainArgs a, const float* __restrict__ xsrc,
-                                                        const float* __restrict__ psrc, int drift, int want_logp,
-                                                        int64_t rows_per_split) {
-    extern __shared__ float lds[];
+// ---------------------------------------------------------------------------
+// Logistic regression, FP32 operands: one launch per leapfrog step.
+// A workgroup (4 waves) owns 64 chains and one split of the rows; wave w runs
+// both contractions for chains c0 + 16 w + i16 over the split's rows on
+// v_mfma_f32_16x16x4f32, 16 rows at a time:
+//   S = X_sub theta^T  (M = 16 rows, N = 16 chains, K = 4 dims): k-step (b, v)
+//                      takes dims 16 b + 4 q + v at lane group q, so one
+//                      16-byte LDS read gives the A operands of 4 k-steps and
+//                      lane (i16, q) holds theta of dims 16 b + 4 q .. + 3 as B
+//   R = y - sigmoid(S) (0 for rows outside the split)
+//   G += X_sub^T R     (M = 16 dims, N = 16 chains, K = 4 rows): k-step v takes
+//                      rows 4 q + v, the S accumulator's own VGPR v
+// theta (drifted) stays in VGPRs, G in KT accumulators; 16-row stages of X
+// (FP32, upcast when stored BF16) are double-buffered in LDS through
+// registers and shared by the 4 waves (row stride 16 KT + 4 floats: both
+// operand reads hit distinct banks).  Each workgroup writes its partial G and
+// logp to part_g / part_lp; the last one of a chain tile to finish (an atomic
+// count per tile, reset by that workgroup) sums the partials in split order,
+// adds the prior gradient, kicks and writes x, p, g and the data part of logp
+// -- the partial-sum and finish passes in one launch, in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int LR32_CT = 64;      // chains per workgroup
+constexpr int LR32_RS = 16;      // rows per sub-tile (one M tile of S)
+
+// rows per LDS stage: 16 for 128 dims and more, else 128 / KT (8 stage elements
+// per thread in every case below 256 dims), so that narrow problems do not wait
+// on one global load latency per 16 rows
+template <int KT>
+constexpr int lr32_rs() { return KT >= 8 ? 16 : 128 / KT; }
+
+template <typename XT>
+struct Lr32Stage;
+// FP32 X: 16-byte loads when rows are 16-byte aligned (D % 4 == 0)
+template <>
+struct Lr32Stage<float> {
+    static constexpr int V = 4;
+    typedef float4 raw;
+    __device__ static raw load(const float* X, int64_t e) { return *(const float4*)(X + e); }
+    __device__ static void to_f32(raw r, float f[4]) { f[0] = r.x; f[1] = r.y; f[2] = r.z; f[3] = r.w; }
+    __device__ static float one(const float* X, int64_t e) { return X[e]; }
+};
+// BF16 X: 8 values (16 bytes) per load when D % 8 == 0
+template <>
+struct Lr32Stage<uint16_t> {
+    static constexpr int V = 8;
+    typedef uint4 raw;
+    __device__ static raw load(const uint16_t* X, int64_t e) { return *(const uint4*)(X + e); }
+    __device__ static void to_f32(raw r, float f[8]) {
+        const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            f[2 * k] = __uint_as_float(u[k] << 16);
+            f[2 * k + 1] = __uint_as_float(u[k] & 0xffff0000u);
+        }
+    }
+    __device__ static float one(const uint16_t* X, int64_t e) { return bf16_to_f32(X[e]); }
+};
+
+// Sum of the split partials of element i in split order.  They were written by
+// other workgroups of this launch; the caller's agent-scope fence (after the
+// tile's count showed every split done) makes them visible to plain loads,
+// which are issued eight at a time before the additions.
+__device__ __forceinline__ float lr32_sum_splits(const float* __restrict__ part, int64_t stride, int nsplit,
+                                                 int64_t i) {
+    float g = 0.f;
+    for (int s0 = 0; s0 < nsplit; s0 += 8) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = s0 + k < nsplit ? part[(int64_t)(s0 + k) * stride + i] : 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (s0 + k < nsplit) g += v[k];
+    }
+    return g;
+}
+
+// Registers of the next stage: thread t holds elements (k 256 + t) V .. + V - 1
+// (VEC: one 16-byte load each; rows 16-byte aligned) or k 256 + t of the
+// stage's RS x D block of X, which is contiguous in the row-major array.
+template <typename XT, int KT, bool VEC>
+struct Lr32Pre {
+    typedef Lr32Stage<XT> SL;
+    static constexpr int XS = 16 * KT + 4;
+    static constexpr int RS = lr32_rs<KT>();
+    static constexpr int NV = (RS * 16 * KT) / (SL::V * 256) > 0 ? (RS * 16 * KT) / (SL::V * 256) : 1;
+    static constexpr int NS = VEC ? 1 : NV * SL::V;
+    typename SL::raw r[VEC ? NV : 1];
+    float f[NS];
+
+    __device__ __forceinline__ void fetch(const XT* X, int64_t D, int64_t r_begin, int64_t r_end, int st) {
+        const int64_t r0 = r_begin + (int64_t)st * RS;
+        const int64_t lim = ((r_end - r0) < RS ? (r_end - r0) : RS) * D;   // valid elements
+        if (VEC) {
+            // an element past the valid rows loads the last valid vector (zeroed at the store)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const int64_t e = ((int64_t)k * 256 + threadIdx.x) * SL::V;
+                r[k] = SL::load(X, r0 * D + (e < lim ? e : lim - SL::V));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const int64_t e = (int64_t)k * 256 + threadIdx.x;
+                f[k] = e < lim ? SL::one(X, r0 * D + e) : 0.f;
+            }
+        }
+    }
+    __device__ __forceinline__ void store(float* lds, int64_t D, int64_t r_begin, int64_t r_end, int st, int buf) const {
+        const int64_t r0 = r_begin + (int64_t)st * RS;
+        const int lim = (int)(((r_end - r0) < RS ? (r_end - r0) : RS) * D);
+        const int nel = RS * (int)D;
+        float* xb = lds + buf * RS * XS;
+        if (VEC) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const int e = (k * 256 + (int)threadIdx.x) * SL::V;
+                if (e >= nel) continue;
+                float v[SL::V];
+                SL::to_f32(r[k], v);
+                const bool ok = e < lim;
+                const int row = e / (int)D, col = e - row * (int)D;
+#pragma unroll
+                for (int j = 0; j < SL::V; j += 4)
+                    *(floatx4*)(xb + row * XS + col + j) = ok ? floatx4{v[j], v[j + 1], v[j + 2], v[j + 3]}
+                                                              : floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const int e = k * 256 + (int)threadIdx.x;
+                if (e >= nel) continue;
+                const int row = e / (int)D, col = e - row * (int)D;
+                xb[row * XS + col] = f[k];
+            }
+        }
+    }
+};
+
+template <int RS>
+__device__ __forceinline__ float lr32_label(const uint8_t* y, int64_t r_begin, int64_t r_end, int st) {
+    const int64_t r = r_begin + (int64_t)st * RS + threadIdx.x;
+    return (threadIdx.x < RS && r < r_end) ? (float)y[r] : 0.f;
+}
+
+template <typename XT, int KT, bool VEC>
+__global__ __launch_bounds__(256) void k_lr32_step(PlainArgs a, float* __restrict__ xio, float* __restrict__ pio,
+                                                   float* __restrict__ gout, int drift, int kick, double kick_scale,
+                                                   int want_logp, int nsplit, int64_t rows_per_split) {
+    constexpr int XS = 16 * KT + 4;                       // LDS row stride (floats)
+    constexpr int RS = lr32_rs<KT>();                    // rows per stage
+    constexpr int STAGE = RS * XS;
+    extern __shared__ float lds[];                        // [2][RS][XS] X stages, then [2][RS] labels
+    float* ys = lds + 2 * STAGE;
+    __shared__ int s_last;
     const int64_t D = a.tg.D, N = a.tg.N, C = a.C;
-    const int K4 = (int)((D + 3) / 4);
-    const int ntiles = (int)((D + 15) / 16);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i16 = lane & 15, g4 = lane >> 4;
-    const int64_t c0 = (int64_t)blockIdx.x * 16;
-    const int s = blockIdx.y;
+    const int i16 = lane & 15, q = lane >> 4;
+    const int tile = blockIdx.x, split = blockIdx.y;
+    const int64_t c = (int64_t)tile * LR32_CT + 16 * w + i16;
+    const bool cv = c < C;
     const XT* X = (const XT*)a.tg.X;
     const uint8_t* y = a.tg.y;
-    float* th = lds;                         // [4*K4][17] theta^T (after drift)
-    float* red = lds + 4 * K4 * 17;          // [16*ntiles][17] gradient reduction
-    double* redlp = (double*)(lds + ((4 * K4 * 17 + 16 * ntiles * 17 + 1) & ~1));   // [16]
+    const double* sc = a.ws.scale;
+    const double eps = cv ? a.ws.eps[c] : 0.0;
 
-    // theta tile (with drift): thread loops over (d, chain)
-    for (int idx = threadIdx.x; idx < 4 * K4 * 16; idx += blockDim.x) {
-        const int d = idx / 16, j = idx % 16;
-        const int64_t c = c0 + j;
-        float v = 0.f;
-        if (d < D && c < C) {
-            v = xsrc[c * D + d];
-            // the drift is recomputed (same fmaf) and stored by k_logreg_finish
-            if (drift)
-                v = fmaf(a.ws.scale ? (float)(a.ws.eps[c] * a.ws.scale[d]) : (float)a.ws.eps[c], psrc[c * D + d], v);
-        }
-        th[d * 17 + j] = v;
-    }
-    __syncthreads();
-
-    const int64_t r_begin = (int64_t)s * rows_per_split;
-    const int64_t r_end = r_begin + rows_per_split < N ? r_begin + rows_per_split : N;
-    floatx4 gacc[GT];
+    // theta (drifted) as B operands: th[b][v] = theta[c][16 b + 4 q + v]
+    float th[KT][4];
 #pragma unroll
-    for (int m = 0; m < GT; ++m) gacc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-    double lp = 0.0;
-
-    for (int64_t n0 = r_begin + 16 * w; n0 < r_end; n0 += 64) {
-        floatx4 sacc = {0.f, 0.f, 0.f, 0.f};
-        const int64_t arow = n0 + i16;
-        const bool arow_ok = arow < r_end;
-        for (int ks = 0; ks < K4; ++ks) {
-            const int64_t col = 4 * ks + g4;
-            const float av = (arow_ok && col < D) ? ld_x<XT>(X, arow * D + col) : 0.f;
-            const float bv = th[(4 * ks + g4) * 17 + i16];
-            sacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, sacc, 0, 0, 0);
-        }
-        float r[4];
+    for (int b = 0; b < KT; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t row = n0 + 4 * g4 + v;
-            const bool ok = row < r_end;
-            const float yv = ok ? (float)y[row] : 0.f;
-            r[v] = ok ? yv - sigmoidf_(sacc[v]) : 0.f;
-            if (want_logp && ok) lp -= (double)softplusf_(yv > 0.5f ? -sacc[v] : sacc[v]);
-        }
-#pragma unroll
-        for (int m = 0; m < GT; ++m) {
-            if (m >= ntiles) break;
-            const int64_t dcol = 16 * m + i16;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = n0 + 4 * g4 + v;
-                const float av = (row < r_end && dcol < D) ? ld_x<XT>(X, row * D + dcol) : 0.f;
-                gacc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, r[v], gacc[m], 0, 0, 0);
+            const int64_t d = 16 * b + 4 * q + v;
+            float t = 0.f;
+            if (cv && d < D) {
+                t = xio[c * D + d];
+                // the same fmaf as the finish below, which stores the drifted x
+                if (drift) t = fmaf(sc ? (float)(eps * sc[d]) : (float)eps, pio[c * D + d], t);
             }
+            th[b][v] = t;
         }
-    }
-    // log-prob partial: lanes of the same chain are i16, i16+16, +32, +48
-    lp += __shfl_xor(lp, 16, 64);
-    lp += __shfl_xor(lp, 32, 64);
 
-    // wave partials summed in wave order (deterministic)
-    for (int ww = 0; ww < 4; ++ww) {
-        if (w == ww) {
+    const int64_t r_begin = (int64_t)split * rows_per_split;
+    const int64_t r_end = r_begin + rows_per_split < N ? r_begin + rows_per_split : N;
+    const int nst = (int)((r_end - r_begin + RS - 1) / RS);
+
+    // columns D .. 16 KT of both stage buffers stay zero
+    for (int idx = threadIdx.x; idx < 2 * RS * (16 * KT - (int)D); idx += 256) {
+        const int pad = 16 * KT - (int)D;
+        const int row = idx / pad, col = (int)D + idx % pad;
+        lds[row * XS + col] = 0.f;
+    }
+    // stage loads: element e of the stage's RS x D block of X (contiguous rows)
+    Lr32Pre<XT, KT, VEC> pre;
+    float pre_y = 0.f;
+    floatx4 gacc[KT];
 #pragma unroll
-            for (int m = 0; m < GT; ++m) {
-                if (m >= ntiles) break;
+    for (int b = 0; b < KT; ++b) gacc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    double lp = 0.0;
+    if (nst > 0) {
+        pre.fetch(X, D, r_begin, r_end, 0);
+        pre_y = lr32_label<RS>(y, r_begin, r_end, 0);
+        pre.store(lds, D, r_begin, r_end, 0, 0);
+        if (threadIdx.x < RS) ys[threadIdx.x] = pre_y;
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) {
+            pre.fetch(X, D, r_begin, r_end, st + 1);
+            pre_y = lr32_label<RS>(y, r_begin, r_end, st + 1);
+        }
+        const float* xst = lds + buf * STAGE;
+#pragma unroll
+        for (int h = 0; h < RS / LR32_RS; ++h) {
+            const int64_t r0 = r_begin + (int64_t)st * RS + LR32_RS * h;
+            if (RS > LR32_RS && r0 >= r_end) continue;     // sub-tiles past the split's end (uniform)
+            const float* xb = xst + LR32_RS * h * XS;
+            // S = X_sub theta^T
+            floatx4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < KT; ++b) {
+                const floatx4 a4 = *(const floatx4*)(xb + i16 * XS + 16 * b + 4 * q);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int d = 16 * m + 4 * g4 + v;
-                    float* dst = &red[d * 17 + i16];
-                    *dst = (ww == 0) ? gacc[m][v] : *dst + gacc[m][v];
+                    if (b & 1) s1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[v], th[b][v], s1, 0, 0, 0);
+                    else s0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[v], th[b][v], s0, 0, 0, 0);
                 }
             }
-            if (lane < 16) redlp[lane] = (ww == 0) ? lp : redlp[lane] + lp;
+            float rr[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float sv = s0[v] + s1[v];
+                const bool ok = r0 + 4 * q + v < r_end;
+                const float yv = ys[buf * RS + LR32_RS * h + 4 * q + v];
+                rr[v] = ok ? yv - sigmoidf_(sv) : 0.f;
+                if (want_logp && ok) lp -= (double)softplusf_(yv > 0.5f ? -sv : sv);
+            }
+            // G += X_sub^T R
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int b = 0; b < KT; ++b)
+                    gacc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xb[(4 * q + v) * XS + 16 * b + i16], rr[v],
+                                                                   gacc[b], 0, 0, 0);
+        }
+        if (st + 1 < nst) {
+            pre.store(lds, D, r_begin, r_end, st + 1, buf ^ 1);
+            if (threadIdx.x < RS) ys[(buf ^ 1) * RS + threadIdx.x] = pre_y;
         }
         __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < 16 * D; idx += blockDim.x) {
-        const int j = idx / (int)D;
-        const int d = idx % (int)D;
-        const int64_t c = c0 + j;
-        if (c < C) a.ws.part_g[((int64_t)s * C + c) * D + d] = red[d * 17 + j];
+
+    // this workgroup's partials: lane (i16, q) holds G[c][16 b + 4 q + v]
+    const int64_t CD = C * D;
+    if (cv) {
+        float* pg = a.ws.part_g + (int64_t)split * CD + c * D;
+#pragma unroll
+        for (int b = 0; b < KT; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t d = 16 * b + 4 * q + v;
+                if (d < D) pg[d] = gacc[b][v];
+            }
     }
-    if (want_logp && threadIdx.x < 16 && c0 + threadIdx.x < C)
-        a.ws.part_lp[(int64_t)s * C + c0 + threadIdx.x] = redlp[threadIdx.x];
+    lp += __shfl_xor(lp, 16, 64);
+    lp += __shfl_xor(lp, 32, 64);
+    if (want_logp && cv && q == 0) a.ws.part_lp[(int64_t)split * C + c] = lp;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&a.ws.lr_cnt[tile], 1) == nsplit - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+
+    // last workgroup of the tile: drift (the same fmaf), split sum in split order,
+    // prior gradient, kick
+    const int64_t c0 = (int64_t)tile * LR32_CT;
+    const int64_t nc = C - c0 < LR32_CT ? C - c0 : LR32_CT;
+    for (int64_t idx = threadIdx.x; idx < nc * D; idx += 256) {
+        const int64_t i = c0 * D + idx;
+        const int64_t cc = i / D, d = i - cc * D;
+        const double ec = a.ws.eps[cc];
+        const double sd = sc ? sc[d] : 1.0;
+        float x = xio[i];
+        const float p = (drift || kick) ? pio[i] : 0.f;
+        if (drift) {
+            x = fmaf(sc ? (float)(ec * sd) : (float)ec, p, x);
+            xio[i] = x;
+        }
+        const float gv = lr32_sum_splits(a.ws.part_g, CD, nsplit, i) - x * (float)a.tg.inv_var;
+        if (kick) pio[i] = fmaf((float)(kick_scale * ec * (a.ws.beta ? a.ws.beta[cc] : 1.0) * sd), gv, p);
+        if (gout) gout[i] = gv;
+    }
+    if (want_logp && threadIdx.x < nc) {
+        const int64_t cc = c0 + threadIdx.x;
+        double l = 0.0;
+        for (int s2 = 0; s2 < nsplit; ++s2) l += a.ws.part_lp[(int64_t)s2 * C + cc];
+        a.ws.lpq[cc] = l;
+    }
+    if (threadIdx.x == 0) a.ws.lr_cnt[tile] = 0;
 }
 
 // drift (same fmaf as the partial kernel), sum the split partials in split
@@ -551,20 +1176,15 @@ static dim3 elem_grid(int64_t n) {
 }
 
 int64_t logreg_nsplit(int64_t N, int64_t C) {
-    // enough workgroups to fill 256 CUs several times, splits of >= 64 rows
-    const int64_t tiles = (C + 15) / 16;
-    int64_t want = (1024 + tiles - 1) / tiles;
-    int64_t maxs = (N + 63) / 64;
+    // about two workgroups per CU (64 chains each), splits of >= 8 stages of rows
+    // (the last workgroup of a tile sums one partial per split)
+    const int64_t tiles = (C + 63) / 64;
+    int64_t want = (512 + tiles - 1) / tiles;
+    const int64_t maxs = (N + 127) / 128;
     if (want > maxs) want = maxs;
     if (want < 1) want = 1;
-    if (want > 64) want = 64;
+    if (want > 32) want = 32;
     return want;
-}
-
-static size_t logreg_lds(int64_t D) {
-    const int K4 = (int)((D + 3) / 4);
-    const int ntiles = (int)((D + 15) / 16);
-    return (size_t)((4 * K4 * 17 + 16 * ntiles * 17 + 1) & ~1) * sizeof(float) + 16 * sizeof(double);
 }
 
 static size_t dense_lds(int64_t D) { return (size_t)16 * ((D + 15) / 16) * 17 * sizeof(float); }
@@ -587,25 +1207,10 @@ static hipError_t launch_dense(const PlainArgs& a, const float* xs, float* xd, f
     return hipGetLastError();
 }
 
-template <typename XT>
-static void launch_logreg_partial_t(const PlainArgs& a, dim3 grid, size_t lds, hipStream_t s, const float* xs,
-                                    const float* ps, int drift, int want_logp, int64_t rows) {
-    const int ntiles = (int)((a.tg.D + 15) / 16);
-    if (ntiles <= 2) hipLaunchKernelGGL((k_logreg_partial<XT, 2>), grid, dim3(256), lds, s, a, xs, ps, drift, want_logp, rows);
-    else if (ntiles <= 4) hipLaunchKernelGGL((k_logreg_partial<XT, 4>), grid, dim3(256), lds, s, a, xs, ps, drift, want_logp, rows);
-    else if (ntiles <= 8) hipLaunchKernelGGL((k_logreg_partial<XT, 8>), grid, dim3(256), lds, s, a, xs, ps, drift, want_logp, rows);
-    else if (ntiles <= 16) hipLaunchKernelGGL((k_logreg_partial<XT, 16>), grid, dim3(256), lds, s, a, xs, ps, drift, want_logp, rows);
-    else {
-        allow_lds(k_logreg_partial<XT, 32>, lds);
-        hipLaunchKernelGGL((k_logreg_partial<XT, 32>), grid, dim3(256), lds, s, a, xs, ps, drift, want_logp, rows);
-    }
-}
-
-// x (in place, drifted when drift), p (kicked when kick), g into gd if not null
 // largest split count the workspace is sized for (the autotuner tries up to 2x the default)
 int64_t logreg_nsplit_cap(int64_t N, int64_t C) {
     int64_t cap = 2 * logreg_nsplit(N, C);
-    const int64_t maxs = (N + 63) / 64;
+    const int64_t maxs = (N + 4 * LR32_RS - 1) / (4 * LR32_RS);
     if (cap > maxs) cap = maxs;
     if (cap > 64) cap = 64;
     return cap < 1 ? 1 : cap;
@@ -619,20 +1224,58 @@ int64_t logreg_nsplit_t(const PlainArgs& a) {
     return logreg_nsplit(a.tg.N, a.C);
 }
 
+template <int KT>
+static size_t lr32_lds() {
+    constexpr int RS = lr32_rs<KT>();
+    return (size_t)(2 * RS * (16 * KT + 4) + 2 * RS) * sizeof(float);
+}
+
+template <typename XT, int KT>
+static void launch_lr32_kt(const PlainArgs& a, dim3 grid, hipStream_t s, float* x, float* p, float* gd, int drift,
+                           int kick, double ks, int want_logp, int nsplit, int64_t rows, int vec) {
+    const size_t lds = lr32_lds<KT>();
+    if (vec) {
+        allow_lds(k_lr32_step<XT, KT, true>, lds);
+        hipLaunchKernelGGL((k_lr32_step<XT, KT, true>), grid, dim3(256), lds, s, a, x, p, gd, drift, kick, ks,
+                           want_logp, nsplit, rows);
+    } else {
+        allow_lds(k_lr32_step<XT, KT, false>, lds);
+        hipLaunchKernelGGL((k_lr32_step<XT, KT, false>), grid, dim3(256), lds, s, a, x, p, gd, drift, kick, ks,
+                           want_logp, nsplit, rows);
+    }
+}
+
+template <typename XT>
+static void launch_lr32(const PlainArgs& a, dim3 grid, hipStream_t s, float* x, float* p, float* gd, int drift,
+                        int kick, double ks, int want_logp, int nsplit, int64_t rows, int vec) {
+    const int kt = (int)((a.tg.D + 15) / 16);
+    if (kt <= 1) launch_lr32_kt<XT, 1>(a, grid, s, x, p, gd, drift, kick, ks, want_logp, nsplit, rows, vec);
+    else if (kt <= 2) launch_lr32_kt<XT, 2>(a, grid, s, x, p, gd, drift, kick, ks, want_logp, nsplit, rows, vec);
+    else if (kt <= 4) launch_lr32_kt<XT, 4>(a, grid, s, x, p, gd, drift, kick, ks, want_logp, nsplit, rows, vec);
+    else if (kt <= 8) launch_lr32_kt<XT, 8>(a, grid, s, x, p, gd, drift, kick, ks, want_logp, nsplit, rows, vec);
+    else if (kt <= 16) launch_lr32_kt<XT, 16>(a, grid, s, x, p, gd, drift, kick, ks, want_logp, nsplit, rows, vec);
+    else launch_lr32_kt<XT, 32>(a, grid, s, x, p, gd, drift, kick, ks, want_logp, nsplit, rows, vec);
+}
+
+// One FP32 gradient evaluation of logistic regression at x (drifted in place
+// first when drift), kicking p when kick, the gradient into gd if not null and
+// the data part of logp into lpq when want_logp.
 static hipError_t launch_logreg(const PlainArgs& a, float* x, float* p, float* gd, int drift, int kick, double ks,
                                 int want_logp, hipStream_t s) {
-    const int64_t nsplit = logreg_nsplit_t(a);
-    const int64_t rows = (a.tg.N + nsplit - 1) / nsplit;
-    const size_t lds = logreg_lds(a.tg.D);
-    const dim3 grid((unsigned)((a.C + 15) / 16), (unsigned)nsplit);
+    int64_t nsplit = logreg_nsplit_t(a);
+    int64_t rows = (a.tg.N + nsplit - 1) / nsplit;
+    rows = (rows + LR32_RS - 1) / LR32_RS * LR32_RS;
+    nsplit = (a.tg.N + rows - 1) / rows;
+    const dim3 grid((unsigned)((a.C + LR32_CT - 1) / LR32_CT), (unsigned)nsplit);
+    const bool x_aligned = ((uintptr_t)a.tg.X & 15) == 0;
     timer_begin(a, s);
     if (a.tg.x_bf16)
-        launch_logreg_partial_t<uint16_t>(a, grid, lds, s, x, p, drift, want_logp, rows);
+        launch_lr32<uint16_t>(a, grid, s, x, p, gd, drift, kick, ks, want_logp, (int)nsplit, rows,
+                              a.tg.D % 8 == 0 && x_aligned);
     else
-        launch_logreg_partial_t<float>(a, grid, lds, s, x, p, drift, want_logp, rows);
-    timer_end(a, s, "k_logreg_partial");
-    hipLaunchKernelGGL(k_logreg_finish, elem_grid(a.C * a.tg.D), dim3(256), 0, s, a, x, p, gd, (int)nsplit, drift,
-                       kick, ks, want_logp);
+        launch_lr32<float>(a, grid, s, x, p, gd, drift, kick, ks, want_logp, (int)nsplit, rows,
+                           a.tg.D % 4 == 0 && x_aligned);
+    timer_end(a, s, "k_lr32_step");
     return hipGetLastError();
 }
 
@@ -686,6 +1329,10 @@ __global__ __launch_bounds__(256) void k_moments(const T* __restrict__ ring, int
     }
 }
 
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 __global__ void k_fill_f64(double* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
@@ -727,6 +1374,8 @@ hipError_t launch_remc_swap(const PlainArgs& a, int64_t K, int64_t M, uint32_t t
     return hipGetLastError();
 }
 
+static bool launch_dense_logp(const PlainArgs& a, hipStream_t s);
+
 // gradient (and logp) at ws.x into ws.g / ws.logp
 hipError_t launch_bootstrap(const PlainArgs& a_in, const void* x_src, hipStream_t s) {
     PlainArgs a = a_in;
@@ -756,10 +1405,12 @@ hipError_t launch_bootstrap(const PlainArgs& a_in, const void* x_src, hipStream_
                                (float*)nullptr, (float*)a.ws.g, lb_grad_nsplit_t(a), 0, 0, 0.0, 0);
             (void)launch_lr16_logp(a, (const float*)a.ws.x, s);
         } else {
+            hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, a.ws.lr_cnt, (a.C + LR32_CT - 1) / LR32_CT);
             (void)launch_logreg(a, (float*)a.ws.x, nullptr, (float*)a.ws.g, 0, 0, 0.0, 1, s);
         }
         break;
     }
+    if (a.tg.kind == HMC_TGT_GAUSS_DENSE && launch_dense_logp(a, s)) return hipGetLastError();
     if (a.f64) HMC_GROUP_DISPATCH(k_logp_finish, double, a, s);
     else HMC_GROUP_DISPATCH(k_logp_finish, float, a, s);
     return hipGetLastError();
@@ -796,7 +1447,164 @@ hipError_t launch_leapfrog_step(const PlainArgs& a, double ks, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Slots per lane of k_elem_last for G lanes per chain (0: D beyond the merged kernels).
+static int elem_last_slots(int64_t D, int G) {
+    const int64_t need = (D + G - 1) / G;
+    const int cap = G == 64 ? 32 : 4;
+    for (int ne = 1; ne <= cap; ne *= 2)
+        if (need <= ne) return ne;
+    return 0;
+}
+
+template <typename T>
+static void launch_elem_last(const PlainArgs& a, int G, int NE, dim3 grid, hipStream_t s) {
+#define HMC_ELEM_LAST(GG, NN)                                                              \
+    if (G == GG && NE == NN) {                                                             \
+        hipLaunchKernelGGL((k_elem_last<T, GG, NN>), grid, dim3(256), 0, s, a);            \
+        return;                                                                            \
+    }
+    HMC_ELEM_LAST(1, 1) HMC_ELEM_LAST(1, 2) HMC_ELEM_LAST(1, 4)
+    HMC_ELEM_LAST(4, 1) HMC_ELEM_LAST(4, 2) HMC_ELEM_LAST(4, 4)
+    HMC_ELEM_LAST(16, 1) HMC_ELEM_LAST(16, 2) HMC_ELEM_LAST(16, 4)
+    HMC_ELEM_LAST(64, 1) HMC_ELEM_LAST(64, 2) HMC_ELEM_LAST(64, 4) HMC_ELEM_LAST(64, 8)
+    HMC_ELEM_LAST(64, 16) HMC_ELEM_LAST(64, 32)
+#undef HMC_ELEM_LAST
+}
+
+template <typename T>
+static void launch_elem_group(int which, const PlainArgs& a, int G, dim3 grid, int vec, hipStream_t s) {
+    // which: 0 = first step, 1 = middle step
+    if (which == 0) {
+        if (G == 1) hipLaunchKernelGGL((k_elem_first<T, 1>), grid, dim3(256), 0, s, a, vec);
+        else if (G == 4) hipLaunchKernelGGL((k_elem_first<T, 4>), grid, dim3(256), 0, s, a, vec);
+        else if (G == 16) hipLaunchKernelGGL((k_elem_first<T, 16>), grid, dim3(256), 0, s, a, vec);
+        else hipLaunchKernelGGL((k_elem_first<T, 64>), grid, dim3(256), 0, s, a, vec);
+    } else {
+        if (G == 1) hipLaunchKernelGGL((k_elem_mid<T, 1>), grid, dim3(256), 0, s, a);
+        else if (G == 4) hipLaunchKernelGGL((k_elem_mid<T, 4>), grid, dim3(256), 0, s, a);
+        else if (G == 16) hipLaunchKernelGGL((k_elem_mid<T, 16>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_elem_mid<T, 64>), grid, dim3(256), 0, s, a);
+    }
+}
+
+// Merged element-wise transition (k_elem_first, k_elem_mid x (L-2), k_elem_last);
+// false when the shape is not covered (L < 2 or D > 2048).
+static bool launch_elem_transition(const PlainArgs& a, hipStream_t s) {
+    const int G = chain_group(a.tg.D);
+    const int NE = elem_last_slots(a.tg.D, G);
+    if (a.L < 2 || NE == 0) return false;
+    const dim3 grid((unsigned)((a.C * G + 255) / 256));
+    const int vec = a.f64 ? (a.tg.D % 2 == 0) : (a.tg.D % 4 == 0);
+    for (int l = 0; l < a.L; ++l) {
+        timer_begin(a, s);
+        if (l == a.L - 1) {
+            if (a.f64) launch_elem_last<double>(a, G, NE, grid, s);
+            else launch_elem_last<float>(a, G, NE, grid, s);
+        } else if (a.f64) {
+            launch_elem_group<double>(l == 0 ? 0 : 1, a, G, grid, vec, s);
+        } else {
+            launch_elem_group<float>(l == 0 ? 0 : 1, a, G, grid, vec, s);
+        }
+        timer_end(a, s, "k_elem_first/mid/last");
+    }
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, a.ws.ctrl);
+    return true;
+}
+
+// logp = 1/2 x.g of the state (after the bootstrap gradient), summed in the
+// order of k_dense_step's end-of-trajectory sum, so that a chain's cached logp
+// is bitwise the same whether it was reset or reached in a transition.
+template <int NT>
+__global__ __launch_bounds__(64 * DS_NW) void k_dense_logp(PlainArgs a) {
+    __shared__ double red[DS_NW * 16];
+    const int64_t D = a.tg.D;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i16 = lane & 15, g4 = lane >> 4;
+    const int64_t c = (int64_t)blockIdx.x * 16 + i16;
+    const bool cvalid = c < a.C;
+    const int64_t d0 = 16 * w + 4 * g4;
+    const float* X = (const float*)a.ws.x;
+    const float* Gs = (const float*)a.ws.g;
+    double lp = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t d = d0 + v;
+        if (w < NT && cvalid && d < D) lp += 0.5 * (double)X[c * D + d] * (double)Gs[c * D + d];
+    }
+    lp += __shfl_xor(lp, 16, 64);
+    lp += __shfl_xor(lp, 32, 64);
+    if (g4 == 0) red[w * 16 + i16] = lp;
+    __syncthreads();
+    if (threadIdx.x < 16 && cvalid) {
+        double sl = 0.0;
+        for (int ww = 0; ww < DS_NW; ++ww) sl += red[ww * 16 + i16];
+        a.ws.logp[c] = sl;
+    }
+}
+
+static bool launch_dense_logp(const PlainArgs& a, hipStream_t s) {
+    const int nt = (int)((a.tg.D + 15) / 16);
+    if (nt > DS_NW) return false;
+    const dim3 grid((unsigned)((a.C + 15) / 16)), blk(64 * DS_NW);
+    switch (nt) {
+    case 1: hipLaunchKernelGGL(k_dense_logp<1>, grid, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_dense_logp<2>, grid, blk, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_dense_logp<3>, grid, blk, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_dense_logp<4>, grid, blk, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_dense_logp<5>, grid, blk, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_dense_logp<6>, grid, blk, 0, s, a); break;
+    case 7: hipLaunchKernelGGL(k_dense_logp<7>, grid, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_dense_logp<8>, grid, blk, 0, s, a); break;
+    }
+    return true;
+}
+
+template <int NT>
+static void launch_dense_step_nt(const PlainArgs& a, int first, int last, hipStream_t s) {
+    const dim3 grid((unsigned)((a.C + 15) / 16));
+    const size_t lds = (size_t)16 * NT * (16 * NT + 4) * sizeof(float);
+    if (first && last) {
+        allow_lds(k_dense_step<NT, true, true>, lds);
+        hipLaunchKernelGGL((k_dense_step<NT, true, true>), grid, dim3(64 * DS_NW), lds, s, a);
+    } else if (first) {
+        allow_lds(k_dense_step<NT, true, false>, lds);
+        hipLaunchKernelGGL((k_dense_step<NT, true, false>), grid, dim3(64 * DS_NW), lds, s, a);
+    } else if (last) {
+        allow_lds(k_dense_step<NT, false, true>, lds);
+        hipLaunchKernelGGL((k_dense_step<NT, false, true>), grid, dim3(64 * DS_NW), lds, s, a);
+    } else {
+        allow_lds(k_dense_step<NT, false, false>, lds);
+        hipLaunchKernelGGL((k_dense_step<NT, false, false>), grid, dim3(64 * DS_NW), lds, s, a);
+    }
+}
+
+// Merged dense transition (k_dense_step x L); false when D > 128.
+static bool launch_dense_transition(const PlainArgs& a, hipStream_t s) {
+    const int nt = (int)((a.tg.D + 15) / 16);
+    if (nt > DS_NW) return false;
+    for (int l = 0; l < a.L; ++l) {
+        const int first = l == 0, last = l == a.L - 1;
+        timer_begin(a, s);
+        switch (nt) {
+        case 1: launch_dense_step_nt<1>(a, first, last, s); break;
+        case 2: launch_dense_step_nt<2>(a, first, last, s); break;
+        case 3: launch_dense_step_nt<3>(a, first, last, s); break;
+        case 4: launch_dense_step_nt<4>(a, first, last, s); break;
+        case 5: launch_dense_step_nt<5>(a, first, last, s); break;
+        case 6: launch_dense_step_nt<6>(a, first, last, s); break;
+        case 7: launch_dense_step_nt<7>(a, first, last, s); break;
+        default: launch_dense_step_nt<8>(a, first, last, s); break;
+        }
+        timer_end(a, s, "k_dense_step");
+    }
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, a.ws.ctrl);
+    return true;
+}
+
 hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipStream_t s) {
+    if ((a.tg.kind == HMC_TGT_STD_NORMAL || a.tg.kind == HMC_TGT_GAUSS_DIAG) && launch_elem_transition(a, s))
+        return hipGetLastError();
+    if (a.tg.kind == HMC_TGT_GAUSS_DENSE && launch_dense_transition(a, s)) return hipGetLastError();
     if (a.f64) HMC_GROUP_DISPATCH(k_begin, double, a, s);
     else HMC_GROUP_DISPATCH(k_begin, float, a, s);
     for (int l = 0; l < a.L; ++l) {

@@ -2,9 +2,11 @@
 contractions, paper Sec. 2.1 with the batch semantics of Sec. 2) at the widths
 every instantiation covers, against the FP64 oracle.
 
-  * D = 100, 200, 257, 384 and 512 (tile counts 7, 13, 17, 24 and 32 of 16
-    columns: the GT = 8, 16 and 32 instantiations, the last beyond 64 KB of LDS),
-    every chain against the oracle;
+  * D = 9, 100, 200, 250, 257, 384 and 512 (1 to 32 tiles of 16 dims: every
+    instantiation of the step kernel, 16-byte and element-wise stage loads of
+    FP32 and BF16 X, the largest beyond 64 KB of LDS; chain counts that leave
+    the last 64-chain tile ragged, row counts not a multiple of 16), every
+    chain against the oracle;
   * the 100000 x 256 workload (BF16-stored X, 8192 chains, L = 10) in its
     FP32-gradient form, every chain on the GPU, the oracle on sampled chains
     spread over the chain tiles;
@@ -57,7 +59,8 @@ def _check(name, g, o, chains, seed, t):
 
 
 @pytest.mark.parametrize("N,D,C,bf16x", [(2000, 100, 200, False), (2500, 200, 150, True), (2000, 257, 200, False),
-                                         (3000, 384, 130, True), (4000, 512, 300, False)])
+                                         (3000, 384, 130, True), (4000, 512, 300, False), (1200, 100, 70, True),
+                                         (900, 250, 66, False), (37, 9, 5, False)])
 def test_fp32_logreg_wide_dims_every_chain(N, D, C, bf16x):
     w = W.logreg(N, D, C, L=6, step_size=0.01, bf16=bf16x, init=0.1, seed=D)
     s = hmc.sampler_for(w, form=hmc.HMC_FORM_PLAIN)
@@ -79,8 +82,8 @@ def test_fp32_logreg_wide_dims_graph_form():
 
 
 def _sampled(C):
-    # chains at tile edges (16 chains per tile), in the middle and at the end
-    return sorted({0, 1, 15, 16, 17, 255, 256, C // 2 - 1, C // 2, C // 2 + 7, C - 17, C - 16, C - 2, C - 1})
+    # chains at wave and tile edges (16 chains per wave, 64 per tile), in the middle and at the end
+    return sorted({0, 1, 15, 16, 17, 63, 64, 255, 256, C // 2 - 1, C // 2, C // 2 + 7, C - 17, C - 16, C - 2, C - 1})
 
 
 def test_fp32_path_logreg_100000x256_sampled_chains():

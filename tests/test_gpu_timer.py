@@ -15,9 +15,9 @@ from paper_2002_01184_amd import hmc  # noqa: E402
 
 @pytest.mark.parametrize("case,form,grad_bf16,name", [
     ("logreg_bf16", hmc.HMC_FORM_PLAIN, True, "k_lr16_grad"),
-    ("logreg_f32", hmc.HMC_FORM_PLAIN, False, "k_logreg_partial"),
-    ("dense", hmc.HMC_FORM_PLAIN, False, "k_dense_leapfrog"),
-    ("diag", hmc.HMC_FORM_PLAIN, False, "k_elem_leapfrog"),
+    ("logreg_f32", hmc.HMC_FORM_PLAIN, False, "k_lr32_step"),
+    ("dense", hmc.HMC_FORM_PLAIN, False, "k_dense_step"),
+    ("diag", hmc.HMC_FORM_PLAIN, False, "k_elem_first/mid/last"),
     ("dense", hmc.HMC_FORM_FUSED, False, "fused transition kernel"),
 ])
 def test_kernel_timer_counts_the_dominant_launches(case, form, grad_bf16, name):
@@ -58,5 +58,5 @@ def test_kernel_timer_skips_the_bootstrap(form):
     if form == hmc.HMC_FORM_FUSED:
         assert (n, name) == (2, "fused transition kernel")
     else:
-        assert (n, name) == (2 * 3 * 3, "k_logreg_partial")
+        assert (n, name) == (2 * 3 * 3, "k_lr32_step")
     s.close()

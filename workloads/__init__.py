@@ -200,7 +200,7 @@ CONFIGS = {
 }
 
 
-def served_stream(n_requests=64, rate=50.0, seed=0, scale="small"):
+def served_stream(n_requests=64, rate=50.0, seed=0, scale="small", progress=None):
     """Seeded stream of sampling requests with Poisson arrivals.
 
     Mix: 50% diagonal-Gaussian requests (D ~ U{10..1000}), 50% logistic
@@ -210,6 +210,7 @@ def served_stream(n_requests=64, rate=50.0, seed=0, scale="small"):
     chains up to 16384, 500 + 500 transitions); scale="small" keeps the mix and
     the arrival process but bounds N <= 1e4, D <= 128, chains <= 2048 and uses
     100 + 100 transitions, so that a stream finishes in seconds.
+    progress(i, n) is called after each request is generated.
     Returns a list of (arrival_time_s, Workload)."""
     rng = _rng(seed, 41)
     if scale == "full":
@@ -233,4 +234,6 @@ def served_stream(n_requests=64, rate=50.0, seed=0, scale="small"):
                        init=0.1)
         w.name = f"req{i}_{w.name}"
         out.append((t, w))
+        if progress is not None:
+            progress(i + 1, n_requests)
     return out
