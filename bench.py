@@ -40,10 +40,14 @@ PEAK = {"fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12, "fp64": 78.6e
 # A figure is reported only while the kernel's sources still hash to the value
 # recorded with it; otherwise traffic is null until the counters are taken again.
 MEASURED_TRAFFIC = {
-    # (workload, form, gradient dtype, burn-in, results)
+    # (workload, form, gradient dtype, burn-in, results): bytes per launch of the dominant kernel
     ("logreg_1000x25", "fused", "f32", 1000, 1000): {
         "sources": ["k_fused_logreg.hip", "hmc_device.hpp", "hmc_internal.hpp"],
         "sha256_16": "76ace38a5388c7a5", "read": 11286400, "write": 152447360},
+    # k_lr16_grad_pipe<8> per leapfrog step: FETCH_SIZE 119344 KiB, WRITE_SIZE 68352 KiB
+    ("logreg_100000x256_bf16", "plain", "bf16", 25, 25): {
+        "sources": ["k_logreg_bf16.hip", "hmc_device.hpp", "hmc_internal.hpp"],
+        "sha256_16": "d8e53e0627787a68", "read": 2 * 119344 * 1024, "write": 68352 * 1024},
 }
 
 
@@ -61,12 +65,16 @@ def measured_traffic(w, form, grad):
     return rec["read"] + rec["write"]
 
 
-def algorithmic_work(w):
-    """(kind, per chain-step amount, unit) of the dominant contraction / traffic."""
+def algorithmic_work(w, form=None):
+    """(kind, per chain-step amount, unit) of the dominant contraction / traffic.
+    The dense Gaussian's plain step (12.5 flop per state byte at D = 100, below
+    the FP32 ridge) is priced against HBM; its fused kernel against FP32 MFMA."""
     import workloads as W
     if w.kind == W.LOGREG:
         return "mfma", 4.0 * w.n_rows * w.dim, "flop"          # X theta and X^T r
     if w.kind == W.GAUSS_DENSE:
+        if form in ("plain", "graph"):
+            return "hbm", 16.0 * w.dim, "byte"                  # read x, p; write x, p (FP32)
         return "mfma", 2.0 * w.dim * w.dim, "flop"             # P x
     es = 8 if w.state_dtype == "f64" else 4
     return "hbm", 4.0 * es * w.dim, "byte"                      # read x, p; write x, p
@@ -735,7 +743,7 @@ def bench_workload(args, config, grad, form_name, steps, warmup, transitions, es
     print(f"bench: {w.name}: {value:.3e} chain-steps/s, {kern_name} {kern_ms:.4f} ms x {kern_n}", file=sys.stderr,
           flush=True)
 
-    bound, per_cs, unit = algorithmic_work(w)
+    bound, per_cs, unit = algorithmic_work(w, s.form)
     if bound == "mfma":
         peak = PEAK["bf16_mfma"] if grad == "bf16" else PEAK["fp32_mfma"]
         work = per_cs * per_launch_cs

@@ -617,45 +617,7 @@ __global__ __launch_bounds__(64 * DS_NW) void k_dense_step(PlainArgs a) {
     float* X = (float*)a.ws.x;
     float* Gs = (float*)a.ws.g;
 
-    // P into LDS with contiguous loads (16 bytes at a time when rows are 16-byte
-    // aligned), the padding rows and columns zero; then each lane's A operands
-    // pa[ks] = P[16 w + i16][g4 KM + ks] with 16-byte LDS reads
-    {
-        const int Di = (int)D;
-        if ((Di & 3) == 0 && ((uintptr_t)P & 15) == 0) {
-            for (int e = 4 * (int)threadIdx.x; e < Di * Di; e += 4 * 64 * DS_NW) {
-                const int row = e / Di, col = e - row * Di;
-                *(floatx4*)(plds + row * XS + col) = *(const floatx4*)(P + e);
-            }
-        } else {
-            for (int e = threadIdx.x; e < Di * Di; e += 64 * DS_NW) {
-                const int row = e / Di, col = e - row * Di;
-                plds[row * XS + col] = P[e];
-            }
-        }
-        const int pad = 16 * NT - Di;
-        for (int e = threadIdx.x; e < pad * 16 * NT; e += 64 * DS_NW) {
-            const int r = e / (16 * NT), k = e - r * 16 * NT;
-            plds[(Di + r) * XS + k] = 0.f;          // rows D .. 16 NT
-            plds[k * XS + Di + r] = 0.f;            // columns D .. 16 NT
-        }
-    }
-    __syncthreads();
-    float pa[KM];
-    if (tile_ok) {
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const floatx4 v4 = *(const floatx4*)(plds + (16 * w + i16) * XS + g4 * KM + 4 * j);
-            pa[4 * j] = v4[0];
-            pa[4 * j + 1] = v4[1];
-            pa[4 * j + 2] = v4[2];
-            pa[4 * j + 3] = v4[3];
-        }
-    } else {
-#pragma unroll
-        for (int ks = 0; ks < KM; ++ks) pa[ks] = 0.f;
-    }
-
+    // this chain's state first (its loads are in flight while P is staged)
     float xv[4], pv[4], gv[4];
     bool ok[4];
     double k0 = 0.0;
@@ -684,6 +646,70 @@ __global__ __launch_bounds__(64 * DS_NW) void k_dense_step(PlainArgs a) {
             pv[v] = ok[v] ? pq[c * D + d] : 0.f;
         }
     }
+    // P into LDS with contiguous loads (16 bytes at a time when rows are 16-byte
+    // aligned), the padding rows and columns zero; then each lane's A operands
+    // pa[ks] = P[16 w + i16][g4 KM + ks] with 16-byte LDS reads
+    {
+        // every load of a thread is issued before the first LDS store (D <= 16 NT:
+        // at most 16 NT x 16 NT / (4 x 512) 16-byte loads per thread)
+        const int Di = (int)D;
+        constexpr int PV = (16 * NT * 16 * NT + 4 * 64 * DS_NW - 1) / (4 * 64 * DS_NW);
+        if ((Di & 3) == 0 && ((uintptr_t)P & 15) == 0) {
+            floatx4 pv4[PV];
+#pragma unroll
+            for (int k = 0; k < PV; ++k) {
+                const int e = 4 * ((int)threadIdx.x + k * 64 * DS_NW);
+                if (e < Di * Di) pv4[k] = *(const floatx4*)(P + e);
+            }
+#pragma unroll
+            for (int k = 0; k < PV; ++k) {
+                const int e = 4 * ((int)threadIdx.x + k * 64 * DS_NW);
+                if (e < Di * Di) {
+                    const int row = e / Di, col = e - row * Di;
+                    *(floatx4*)(plds + row * XS + col) = pv4[k];
+                }
+            }
+        } else {
+            for (int e0 = 0; e0 < Di * Di; e0 += 8 * 64 * DS_NW) {
+                float pv1[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int e = e0 + (int)threadIdx.x + k * 64 * DS_NW;
+                    if (e < Di * Di) pv1[k] = P[e];
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int e = e0 + (int)threadIdx.x + k * 64 * DS_NW;
+                    if (e < Di * Di) {
+                        const int row = e / Di, col = e - row * Di;
+                        plds[row * XS + col] = pv1[k];
+                    }
+                }
+            }
+        }
+        const int pad = 16 * NT - Di;
+        for (int e = threadIdx.x; e < pad * 16 * NT; e += 64 * DS_NW) {
+            const int r = e / (16 * NT), k = e - r * 16 * NT;
+            plds[(Di + r) * XS + k] = 0.f;          // rows D .. 16 NT
+            plds[k * XS + Di + r] = 0.f;            // columns D .. 16 NT
+        }
+    }
+    __syncthreads();
+    float pa[KM];
+    if (tile_ok) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const floatx4 v4 = *(const floatx4*)(plds + (16 * w + i16) * XS + g4 * KM + 4 * j);
+            pa[4 * j] = v4[0];
+            pa[4 * j + 1] = v4[1];
+            pa[4 * j + 2] = v4[2];
+            pa[4 * j + 3] = v4[3];
+        }
+    } else {
+#pragma unroll
+        for (int ks = 0; ks < KM; ++ks) pa[ks] = 0.f;
+    }
+
     // drift, then x of the tile into LDS
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -873,24 +899,6 @@ struct Lr32Stage<uint16_t> {
     }
     __device__ static float one(const uint16_t* X, int64_t e) { return bf16_to_f32(X[e]); }
 };
-
-// Sum of the split partials of element i in split order.  They were written by
-// other workgroups of this launch; the caller's agent-scope fence (after the
-// tile's count showed every split done) makes them visible to plain loads,
-// which are issued eight at a time before the additions.
-__device__ __forceinline__ float lr32_sum_splits(const float* __restrict__ part, int64_t stride, int nsplit,
-                                                 int64_t i) {
-    float g = 0.f;
-    for (int s0 = 0; s0 < nsplit; s0 += 8) {
-        float v[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = s0 + k < nsplit ? part[(int64_t)(s0 + k) * stride + i] : 0.f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (s0 + k < nsplit) g += v[k];
-    }
-    return g;
-}
 
 // Registers of the next stage: thread t holds elements (k 256 + t) V .. + V - 1
 // (VEC: one 16-byte load each; rows 16-byte aligned) or k 256 + t of the
@@ -1083,31 +1091,67 @@ __global__ __launch_bounds__(256) void k_lr32_step(PlainArgs a, float* __restric
     lp += __shfl_xor(lp, 16, 64);
     lp += __shfl_xor(lp, 32, 64);
     if (want_logp && cv && q == 0) a.ws.part_lp[(int64_t)split * C + c] = lp;
-    __threadfence();
+    // release this workgroup's partials (agent scope: the other splits may run on other XCDs),
+    // then count it; the last one to count acquires them all
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) s_last = atomicAdd(&a.ws.lr_cnt[tile], 1) == nsplit - 1;
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
     // last workgroup of the tile: drift (the same fmaf), split sum in split order,
-    // prior gradient, kick
+    // prior gradient, kick -- four elements per thread at a time, every load of
+    // the four (state, step size, split partials) issued before the arithmetic
     const int64_t c0 = (int64_t)tile * LR32_CT;
     const int64_t nc = C - c0 < LR32_CT ? C - c0 : LR32_CT;
-    for (int64_t idx = threadIdx.x; idx < nc * D; idx += 256) {
-        const int64_t i = c0 * D + idx;
-        const int64_t cc = i / D, d = i - cc * D;
-        const double ec = a.ws.eps[cc];
-        const double sd = sc ? sc[d] : 1.0;
-        float x = xio[i];
-        const float p = (drift || kick) ? pio[i] : 0.f;
-        if (drift) {
-            x = fmaf(sc ? (float)(ec * sd) : (float)ec, p, x);
-            xio[i] = x;
+    const int64_t ne = nc * D;
+    constexpr int U = 4;
+    for (int64_t base = threadIdx.x; base < ne; base += 256 * U) {
+        float xv[U], pv[U], gs[U];
+        double ec[U], sd[U], bt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t idx = base + 256 * u < ne ? base + 256 * u : ne - 1;    // clamped: loads stay in range
+            const int64_t i = c0 * D + idx;
+            const int64_t cc = i / D, d = i - cc * D;
+            ec[u] = a.ws.eps[cc];
+            sd[u] = sc ? sc[d] : 1.0;
+            bt[u] = a.ws.beta ? a.ws.beta[cc] : 1.0;
+            xv[u] = xio[i];
+            pv[u] = (drift || kick) ? pio[i] : 0.f;
+            gs[u] = 0.f;
         }
-        const float gv = lr32_sum_splits(a.ws.part_g, CD, nsplit, i) - x * (float)a.tg.inv_var;
-        if (kick) pio[i] = fmaf((float)(kick_scale * ec * (a.ws.beta ? a.ws.beta[cc] : 1.0) * sd), gv, p);
-        if (gout) gout[i] = gv;
+        for (int s0 = 0; s0 < nsplit; s0 += 8) {
+            float v[U][8];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t idx = base + 256 * u < ne ? base + 256 * u : ne - 1;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int sk = s0 + k < nsplit ? s0 + k : nsplit - 1;
+                    v[u][k] = a.ws.part_g[(int64_t)sk * CD + c0 * D + idx];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (s0 + k < nsplit) gs[u] += v[u][k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + 256 * u >= ne) continue;
+            const int64_t i = c0 * D + base + 256 * u;
+            float x = xv[u];
+            if (drift) {
+                x = fmaf(sc ? (float)(ec[u] * sd[u]) : (float)ec[u], pv[u], x);
+                xio[i] = x;
+            }
+            const float gv = gs[u] - x * (float)a.tg.inv_var;
+            if (kick) pio[i] = fmaf((float)(kick_scale * ec[u] * bt[u] * sd[u]), gv, pv[u]);
+            if (gout) gout[i] = gv;
+        }
     }
     if (want_logp && threadIdx.x < nc) {
         const int64_t cc = c0 + threadIdx.x;

@@ -23,18 +23,27 @@ from paper_2002_01184_amd import hmc  # noqa: E402
 
 def _requests():
     a = W.std_normal_1d(num_chains=300, dim=7, state_dtype="f32", L=5, step_size=0.4, burnin=30, results=20, seed=11)
-    b = W.gauss_diag(dim=100, num_chains=200, L=8, step_size=0.05, burnin=200, results=250, seed=12)
-    b2 = W.gauss_diag(dim=90, num_chains=77, L=6, step_size=0.05, burnin=130, results=170, seed=13, adapt=True)
+    # two requests of one element-wise shape class, long enough (hundreds of ticks) that they are resident
+    # together whatever the delay between their submissions, so they share ragged launches
+    b = W.gauss_diag(dim=100, num_chains=200, L=8, step_size=0.05, burnin=1500, results=250, seed=12)
+    b2 = W.gauss_diag(dim=90, num_chains=77, L=6, step_size=0.05, burnin=1400, results=170, seed=13, adapt=True)
     c = W.std_normal_1d(num_chains=100, burnin=40, results=20, seed=14)
     d = W.gauss_dense(dim=37, num_chains=45, L=7, step_size=0.1, burnin=10, results=12, seed=15)
     e = W.logreg(1000, 25, 64, L=5, step_size=0.05, burnin=25, results=15, seed=16)
     f = W.logreg(3000, 40, 100, L=4, step_size=0.01, burnin=6, results=9, seed=17, init=0.3)
     g = W.logreg(2000, 300, 48, L=4, step_size=0.005, burnin=5, results=6, seed=18, bf16=True, init=0.1)
-    return [a, b, b2, c, d, e, f, g]
+    # served with BF16 gradient operands (the server's form for BF16 X up to D = 512)
+    h = W.logreg(2500, 400, 70, L=4, step_size=0.004, burnin=6, results=5, seed=19, bf16=True, init=0.1)
+    h.extra["grad_bf16"] = True
+    return [a, b, b2, c, d, e, f, g, h]
+
+
+def _bf16(w):
+    return w.extra.get("grad_bf16", False)
 
 
 def _reference(w):
-    s = hmc.sampler_for(w)
+    s = hmc.sampler_for(w, grad_bf16=_bf16(w))
     out = s.sample_chain(w.num_results, w.num_burnin, adapt=w.adapt)
     torch.cuda.synchronize()
     res = {k: v.clone() for k, v in out.items() if v is not None}
@@ -49,21 +58,25 @@ def test_server_results_equal_sample_chain_alone_and_in_mix():
     srv = hmc.Server(2 << 30, transitions_per_tick=7)
     alone = []
     for w in reqs:
-        rid = srv.submit(w)
+        rid = srv.submit(w, grad_bf16=_bf16(w))
         out, lat = srv.wait(rid)
         assert lat > 0
         alone.append(out)
+    st_alone = srv.stats()
+    print("server stats after the requests alone:", st_alone)
     # mix: the long diagonal Gaussians first, the rest arriving while they run,
     # some with server-held samples
-    order = [1, 2, 0, 3, 4, 7, 5, 6]
-    preps = {i: srv.prepare(reqs[i], server_samples=(n % 2 == 1)) for n, i in enumerate(order)}
+    order = [1, 2, 0, 3, 4, 7, 8, 5, 6]
+    preps = {i: srv.prepare(reqs[i], server_samples=(n % 2 == 1), grad_bf16=_bf16(reqs[i])) for n, i in enumerate(order)}
     mix_ids = {}
     for i in order:
         mix_ids[i] = srv.submit_prepared(preps[i])
-    mix = [srv.wait(mix_ids[i])[0] for i in range(len(reqs))]
+    waited = [srv.wait(mix_ids[i]) for i in range(len(reqs))]
+    mix = [o for o, _ in waited]
     st = srv.stats()
     srv.close()
     print("server stats:", st)
+    print("mix latencies (s):", {reqs[i].name: round(waited[i][1], 3) for i in range(len(reqs))})
     for w, r, al, mx in zip(reqs, refs, alone, mix):
         for k in ["samples", "is_accepted", "step_size", "target_log_prob"]:
             assert torch.equal(al[k], r[k]), (w.name, k, "alone vs sample_chain")
