@@ -377,10 +377,11 @@ __global__ __launch_bounds__(256) void k_elem_first(PlainArgs a, int vec) {
     if (active) {
         for (int64_t b = lane; b < nblk; b += G) {
             T z[4], xv[4], gv[4], xo[4], po[4];
-            momentum4<T>(a.key, (uint32_t)c, t, (uint32_t)b, z, 4 * b + 2 < D);
+            // the state's loads first: the draw below runs while they are in flight
             const int n = D - 4 * b < 4 ? (int)(D - 4 * b) : 4;
             load4(x + c * D + 4 * b, n, vec != 0, xv);
             load4(g + c * D + 4 * b, n, vec != 0, gv);
+            momentum4<T>(a.key, (uint32_t)c, t, (uint32_t)b, z, 4 * b + 2 < D);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 xo[j] = (T)0;
@@ -450,20 +451,31 @@ __global__ __launch_bounds__(256) void k_elem_last(PlainArgs a) {
     const bool diag = a.tg.kind == HMC_TGT_GAUSS_DIAG;
     const double eps = active ? a.ws.eps[c] : 0.0;
     const double bt = (active && a.ws.beta) ? a.ws.beta[c] : 1.0;
-    T xl[NE], gl[NE];
+    T xl[NE], gl[NE], pl[NE], pr[NE];
     double k1 = 0.0, lp1 = 0.0;
+    // every slot's loads first (addresses clamped into the chain's row), then the arithmetic
+    const int64_t cr = (active ? c : 0) * D;
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
         const int64_t d = lane + (int64_t)G * k;
+        const int64_t dd = d < D ? d : 0;
+        xl[k] = xq[cr + dd];
+        pl[k] = pq[cr + dd];
+        pr[k] = diag ? prec[dd] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const int64_t d = lane + (int64_t)G * k;
+        const T xq0 = xl[k];
         xl[k] = (T)0;
         gl[k] = (T)0;
         if (active && d < D) {
             const int64_t i = c * D + d;
             const double sd = a.ws.scale ? a.ws.scale[d] : 1.0;
             const T e = a.ws.scale ? (T)(eps * sd) : (T)eps;
-            const T pv0 = pq[i];
-            const T xx = fma(e, pv0, xq[i]);
-            const T gg = diag ? -prec[d] * xx : -xx;
+            const T pv0 = pl[k];
+            const T xx = fma(e, pv0, xq0);
+            const T gg = diag ? -pr[k] * xx : -xx;
             const T p = fma((T)(0.5 * eps * bt * sd), gg, pv0);
             k1 += 0.5 * (double)p * (double)p;
             lp1 += 0.5 * (double)xx * (double)gg;
@@ -726,6 +738,9 @@ __global__ __launch_bounds__(64 * DS_NW) void k_dense_step(PlainArgs a) {
 #pragma unroll
         for (int ks = 0; ks < KM; ++ks)
             acc[ks & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[ks], bq[ks >> 2][ks & 3], acc[ks & 1], 0, 0, 0);
+        // all operand reads first (one LDS latency), then the MFMAs
+        __builtin_amdgcn_sched_group_barrier(0x100, NT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, KM, 0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) gv[v] = -(acc[0][v] + acc[1][v]);
     } else {
@@ -962,10 +977,13 @@ struct Lr32Pre {
     }
 };
 
+// The label of row threadIdx.x of a stage as its raw byte (0 past the split):
+// converted only at the LDS store, so that its load is not waited for (with
+// the stage's X loads ahead of it) before the current stage is computed.
 template <int RS>
-__device__ __forceinline__ float lr32_label(const uint8_t* y, int64_t r_begin, int64_t r_end, int st) {
+__device__ __forceinline__ uint32_t lr32_label(const uint8_t* y, int64_t r_begin, int64_t r_end, int st) {
     const int64_t r = r_begin + (int64_t)st * RS + threadIdx.x;
-    return (threadIdx.x < RS && r < r_end) ? (float)y[r] : 0.f;
+    return (threadIdx.x < RS && r < r_end) ? (uint32_t)y[r] : 0u;
 }
 
 template <typename XT, int KT, bool VEC>
@@ -989,21 +1007,36 @@ __global__ __launch_bounds__(256) void k_lr32_step(PlainArgs a, float* __restric
     const double* sc = a.ws.scale;
     const double eps = cv ? a.ws.eps[c] : 0.0;
 
-    // theta (drifted) as B operands: th[b][v] = theta[c][16 b + 4 q + v]
+    // theta (drifted) as B operands: th[b][v] = theta[c][16 b + 4 q + v], loaded
+    // four 16-dim blocks at a time with every load of a group issued before its
+    // arithmetic (the drift is the same fmaf as the finish below, which stores
+    // the drifted x)
     float th[KT][4];
+    const int64_t cr = (cv ? c : 0) * D;
+    constexpr int PB = KT < 4 ? KT : 4;
 #pragma unroll
-    for (int b = 0; b < KT; ++b)
+    for (int b0 = 0; b0 < KT; b0 += PB) {
+        float pm[PB][4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t d = 16 * b + 4 * q + v;
-            float t = 0.f;
-            if (cv && d < D) {
-                t = xio[c * D + d];
-                // the same fmaf as the finish below, which stores the drifted x
-                if (drift) t = fmaf(sc ? (float)(eps * sc[d]) : (float)eps, pio[c * D + d], t);
+        for (int bb = 0; bb < PB; ++bb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t d = 16 * (b0 + bb) + 4 * q + v;
+                const int64_t dd = d < D ? d : 0;
+                th[b0 + bb][v] = xio[cr + dd];
+                pm[bb][v] = drift ? pio[cr + dd] : 0.f;
             }
-            th[b][v] = t;
-        }
+#pragma unroll
+        for (int bb = 0; bb < PB; ++bb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t d = 16 * (b0 + bb) + 4 * q + v;
+                const bool ok = cv && d < D;
+                float t = th[b0 + bb][v];
+                if (drift) t = fmaf(sc ? (float)(eps * sc[ok ? d : 0]) : (float)eps, pm[bb][v], t);
+                th[b0 + bb][v] = ok ? t : 0.f;
+            }
+    }
 
     const int64_t r_begin = (int64_t)split * rows_per_split;
     const int64_t r_end = r_begin + rows_per_split < N ? r_begin + rows_per_split : N;
@@ -1017,7 +1050,7 @@ __global__ __launch_bounds__(256) void k_lr32_step(PlainArgs a, float* __restric
     }
     // stage loads: element e of the stage's RS x D block of X (contiguous rows)
     Lr32Pre<XT, KT, VEC> pre;
-    float pre_y = 0.f;
+    uint32_t pre_y = 0u;
     floatx4 gacc[KT];
 #pragma unroll
     for (int b = 0; b < KT; ++b) gacc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -1026,7 +1059,7 @@ __global__ __launch_bounds__(256) void k_lr32_step(PlainArgs a, float* __restric
         pre.fetch(X, D, r_begin, r_end, 0);
         pre_y = lr32_label<RS>(y, r_begin, r_end, 0);
         pre.store(lds, D, r_begin, r_end, 0, 0);
-        if (threadIdx.x < RS) ys[threadIdx.x] = pre_y;
+        if (threadIdx.x < RS) ys[threadIdx.x] = (float)pre_y;
     }
     __syncthreads();
     for (int st = 0; st < nst; ++st) {
@@ -1071,7 +1104,7 @@ __global__ __launch_bounds__(256) void k_lr32_step(PlainArgs a, float* __restric
         }
         if (st + 1 < nst) {
             pre.store(lds, D, r_begin, r_end, st + 1, buf ^ 1);
-            if (threadIdx.x < RS) ys[(buf ^ 1) * RS + threadIdx.x] = pre_y;
+            if (threadIdx.x < RS) ys[(buf ^ 1) * RS + threadIdx.x] = (float)pre_y;
         }
         __syncthreads();
     }
@@ -1155,8 +1188,16 @@ __global__ __launch_bounds__(256) void k_lr32_step(PlainArgs a, float* __restric
     }
     if (want_logp && threadIdx.x < nc) {
         const int64_t cc = c0 + threadIdx.x;
+        // eight loads in flight, then the sums in split order
         double l = 0.0;
-        for (int s2 = 0; s2 < nsplit; ++s2) l += a.ws.part_lp[(int64_t)s2 * C + cc];
+        for (int s0 = 0; s0 < nsplit; s0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = a.ws.part_lp[(int64_t)(s0 + k < nsplit ? s0 + k : nsplit - 1) * C + cc];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (s0 + k < nsplit) l += v[k];
+        }
         a.ws.lpq[cc] = l;
     }
     if (threadIdx.x == 0) a.ws.lr_cnt[tile] = 0;
