@@ -419,6 +419,8 @@ typedef struct hmc_server_stats {
     int64_t batched_launches;    /* ragged launches that covered >= 2 requests */
     int64_t max_active;          /* most requests resident at once */
     size_t pool_bytes, bytes_in_use, peak_bytes_in_use;
+    int64_t batched_plain_transitions;   /* plain transitions run once for >= 2 BF16-gradient
+                                            logistic requests of one shape class */
 } hmc_server_stats;
 
 enum { HMC_REQ_QUEUED = 0, HMC_REQ_RUNNING = 1, HMC_REQ_DONE = 2, HMC_REQ_FAILED = 3 };

@@ -176,6 +176,47 @@ hipError_t launch_pad_bf16(const PlainArgs& a, hipStream_t s);
 hipError_t launch_lr16_grad(const PlainArgs& a, const float* x, const float* p, int drift, hipStream_t s);
 hipError_t launch_lr16_logp(const PlainArgs& a, const float* x, hipStream_t s);
 
+// Several BF16-gradient logistic requests of one shape class (padded width,
+// lanes per chain, leapfrog count) advanced together, one launch per kernel
+// of the transition: job j owns blocks begin[k] .. begin[k] + nblk[k] - 1 of
+// kernel kind k (gradient and logit grids start at multiples of 8, so that a
+// job's blocks keep their XCD).
+enum { LR16_KIND_GROUP = 0, LR16_KIND_GRAD = 1, LR16_KIND_FINISH = 2, LR16_KIND_LOGP = 3, LR16_KIND_LPSUM = 4,
+       LR16_KINDS = 5 };
+struct Lr16Job {
+    PlainArgs a;
+    int64_t rows_g, rows_lp;        // rows per split of the gradient and logit kernels
+    int32_t nsplit_g, nsplit_lp;
+    int64_t begin[LR16_KINDS];
+    int64_t nblk[LR16_KINDS];
+};
+// The job owning block b of the grid of kernel kind k and the block's index within the job (-1: a
+// padding block between jobs).
+__device__ __forceinline__ int lr16_job_of(const Lr16Job* __restrict__ jobs, int njobs, int kind, int64_t b,
+                                           int64_t* lb) {
+    for (int j = 0; j < njobs; ++j) {
+        const int64_t b0 = jobs[j].begin[kind];
+        if (b >= b0 && b < b0 + jobs[j].nblk[kind]) {
+            *lb = b - b0;
+            return j;
+        }
+    }
+    return -1;
+}
+// Shape class of a request for batching (-1: not a BF16-gradient logistic plain request).
+int lr16_batch_class(const PlainArgs& a);
+int plain_chain_group(int64_t D);   // lanes per chain of the plain form's begin/end kernels
+// Fills a job's split counts and block counts (begin is left to the caller).
+void lr16_job_shape(const PlainArgs& a, Lr16Job* j);
+// One launch of kernel kind k (GRAD, LOGP or LPSUM) over all jobs.
+hipError_t launch_lr16_kind_multi(int kind, int64_t D, const Lr16Job* jobs_dev, int njobs, int64_t blocks,
+                                  hipStream_t s);
+// Block ranges of every job (fills the shapes); false if a grid would exceed 2^31 blocks.
+bool lr16_layout(Lr16Job* jobs, int njobs);
+// One transition of every job (host copy of the table for the grid sizes, device copy for the kernels).
+hipError_t launch_lr16_transition_multi(const Lr16Job* jobs_host, const Lr16Job* jobs_dev, int njobs,
+                                        hipStream_t s);
+
 // ---- fused path (k_fused.hip) -----------------------------------------------
 struct FusedRun {
     uint64_t t_begin;

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -106,6 +107,8 @@ struct hmc_server {
     hipStream_t streams[kStreams] = {};
     ElemJob* jobs_host = nullptr;   // pinned
     ElemJob* jobs_dev = nullptr;
+    Lr16Job* lr16_host = nullptr;   // pinned
+    Lr16Job* lr16_dev = nullptr;
     std::mutex mu;
     std::condition_variable cv, cv_done;
     std::deque<Request*> pending;
@@ -239,11 +242,20 @@ void worker_loop(hmc_server* srv) {
 
         // ---- one tick ----
         std::map<int, std::vector<Request*>> classes;
+        std::map<std::tuple<int, int, int>, std::vector<Request*>> lr16_classes;
         std::vector<Request*> others;
         for (Request* q : act) {
-            if (q->form == HMC_FORM_FUSED && q->cls >= 0) classes[q->cls].push_back(q);
-            else others.push_back(q);
+            if (q->form == HMC_FORM_FUSED && q->cls >= 0) {
+                classes[q->cls].push_back(q);
+            } else if (q->form == HMC_FORM_PLAIN && lr16_batch_class(q->a) >= 0) {
+                lr16_classes[std::make_tuple(lr16_batch_class(q->a), plain_chain_group(q->a.tg.D), q->a.L)]
+                    .push_back(q);
+            } else {
+                others.push_back(q);
+            }
         }
+        for (auto& kv : lr16_classes)   // a class of one runs as an ordinary plain request
+            if (kv.second.size() == 1) others.push_back(kv.second[0]);
         bool ok = true;
         int njob = 0;
         for (auto& kv : classes) {
@@ -270,6 +282,47 @@ void worker_loop(hmc_server* srv) {
                 if (njob + kMaxJobs > 4 * kMaxJobs) {   // job table reuse needs the copies done
                     (void)hipStreamSynchronize(s);
                     njob = 0;
+                }
+            }
+        }
+        // BF16-gradient logistic plain requests of one class: transition i of the tick
+        // runs once for every member with more than i transitions left (chunks of kMaxJobs)
+        int nlr = 0;
+        for (auto& kv : lr16_classes) {
+            if (kv.second.size() < 2) continue;
+            for (size_t b0 = 0; b0 < kv.second.size() && ok; b0 += kMaxJobs) {
+                const size_t b1 = std::min(kv.second.size(), b0 + kMaxJobs);
+                hipStream_t s = srv->streams[0];
+                int first = -1, n = 0;
+                for (int64_t i = 0; i < srv->K && ok; ++i) {
+                    std::vector<Request*> mem;
+                    for (size_t k = b0; k < b1; ++k)
+                        if (kv.second[k]->total - kv.second[k]->done > i) mem.push_back(kv.second[k]);
+                    if (mem.empty()) break;
+                    if ((int)mem.size() != n) {   // the set only shrinks: a new table when it does
+                        if (nlr + (int)mem.size() > 4 * kMaxJobs) {   // table reuse needs the copies done
+                            (void)hipStreamSynchronize(s);
+                            nlr = 0;
+                        }
+                        first = nlr;
+                        n = (int)mem.size();
+                        for (int k = 0; k < n; ++k) srv->lr16_host[first + k].a = mem[k]->a;
+                        nlr += n;
+                        if (!lr16_layout(srv->lr16_host + first, n) ||
+                            hipMemcpyAsync(srv->lr16_dev + first, srv->lr16_host + first, sizeof(Lr16Job) * n,
+                                           hipMemcpyHostToDevice, s) != hipSuccess) {
+                            ok = false;
+                            break;
+                        }
+                    }
+                    if (n == 1) {
+                        if (launch_plain_transition(mem[0]->a, false, s) != hipSuccess) ok = false;
+                    } else {
+                        if (launch_lr16_transition_multi(srv->lr16_host + first, srv->lr16_dev + first, n, s) !=
+                            hipSuccess)
+                            ok = false;
+                        srv->st.batched_plain_transitions++;
+                    }
                 }
             }
         }
@@ -327,12 +380,17 @@ hmc_status hmc_server_create(size_t hbm_budget_bytes, int32_t transitions_per_ti
     bool ok = hipMalloc(&srv->pool, srv->budget) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&srv->jobs_host, sizeof(ElemJob) * 4 * kMaxJobs, hipHostMallocDefault) == hipSuccess;
     ok = ok && hipMalloc((void**)&srv->jobs_dev, sizeof(ElemJob) * 4 * kMaxJobs) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&srv->lr16_host, sizeof(Lr16Job) * 4 * kMaxJobs, hipHostMallocDefault) ==
+                   hipSuccess;
+    ok = ok && hipMalloc((void**)&srv->lr16_dev, sizeof(Lr16Job) * 4 * kMaxJobs) == hipSuccess;
     for (int k = 0; ok && k < kStreams; ++k)
         ok = hipStreamCreateWithFlags(&srv->streams[k], hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         if (srv->pool) (void)hipFree(srv->pool);
         if (srv->jobs_host) (void)hipHostFree(srv->jobs_host);
         if (srv->jobs_dev) (void)hipFree(srv->jobs_dev);
+        if (srv->lr16_host) (void)hipHostFree(srv->lr16_host);
+        if (srv->lr16_dev) (void)hipFree(srv->lr16_dev);
         for (int k = 0; k < kStreams; ++k)
             if (srv->streams[k]) (void)hipStreamDestroy(srv->streams[k]);
         delete srv;
@@ -461,6 +519,8 @@ hmc_status hmc_server_destroy(hmc_server* srv) {
     (void)hipFree(srv->pool);
     (void)hipFree(srv->jobs_dev);
     (void)hipHostFree(srv->jobs_host);
+    (void)hipFree(srv->lr16_dev);
+    (void)hipHostFree(srv->lr16_host);
     for (auto& kv : srv->all) delete kv.second;
     delete srv->alloc;
     delete srv;

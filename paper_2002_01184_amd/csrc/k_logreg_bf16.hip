@@ -214,9 +214,9 @@ struct LbGrad {
 };
 
 template <int KS>
-__global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float* __restrict__ xsrc,
-                                                        const float* __restrict__ psrc, int drift,
-                                                        int64_t rows_per_split, int nsplit) {
+__device__ __forceinline__ void lr16_grad_body(const PlainArgs& a, const float* __restrict__ xsrc,
+                                               const float* __restrict__ psrc, int drift, int64_t rows_per_split,
+                                               int nsplit, int blk) {
     using P = LbGrad<KS>;
     constexpr int CS = P::CS, CT = P::CT, NT = 2 * KS, DP = P::DP, XB = P::XB, TBY = P::TBY, XI = P::XI;
     constexpr int JW = P::JW, J = P::J, PF = P::PF, NBX = P::NBX, NBT = P::NBT;
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float
     const int64_t D = a.tg.D, C = a.C, NP = (a.tg.N + LB_RS - 1) / LB_RS * LB_RS;
     const int ntile = (int)((C + CT - 1) / CT);
     int tile, split;
-    lb_map(blockIdx.x, ntile, nsplit, &tile, &split);
+    lb_map(blk, ntile, nsplit, &tile, &split);
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l16 = lane & 15, g = lane >> 4;
     const int64_t cw = (int64_t)tile * CT + 16 * CS * w;
@@ -497,8 +497,8 @@ struct LbLogp {
 };
 
 template <int KS>
-__global__ __launch_bounds__(256) void k_lr16_logp_pipe(PlainArgs a, const float* __restrict__ xsrc,
-                                                        int64_t rows_per_split, int nsplit) {
+__device__ __forceinline__ void lr16_logp_body(const PlainArgs& a, const float* __restrict__ xsrc,
+                                               int64_t rows_per_split, int nsplit, int blk) {
     using P = LbLogp<KS>;
     constexpr int CS = P::CS, CT = P::CT, NB = P::NB, XB = P::XB, BUF = P::BUF, XI = P::XI, JW = P::JW, J = P::J;
     constexpr int DP = P::DP;
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(256) void k_lr16_logp_pipe(PlainArgs a, const float
     const int64_t N = a.tg.N, C = a.C, NP = (N + LB_RS - 1) / LB_RS * LB_RS;
     const int ntile = (int)((C + CT - 1) / CT);
     int tile, split;
-    lb_map(blockIdx.x, ntile, nsplit, &tile, &split);
+    lb_map(blk, ntile, nsplit, &tile, &split);
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l16 = lane & 15, g = lane >> 4;
     const int64_t cw = (int64_t)tile * CT + 16 * CS * w;
@@ -643,12 +643,60 @@ __global__ __launch_bounds__(256) void k_lr16_logp_pipe(PlainArgs a, const float
 }
 
 // lpq[c] = sum over splits (fixed order) of the log-probability partials
-__global__ __launch_bounds__(256) void k_lr16_lp_sum(PlainArgs a, int nsplit) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lr16_lp_sum_body(const PlainArgs& a, int nsplit, int blk) {
+    const int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= a.C) return;
     double l = 0.0;
     for (int s = 0; s < nsplit; ++s) l += a.ws.part_lp[(int64_t)s * a.C + c];
     a.ws.lpq[c] = l;
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float* __restrict__ xsrc,
+                                                        const float* __restrict__ psrc, int drift,
+                                                        int64_t rows_per_split, int nsplit) {
+    lr16_grad_body<KS>(a, xsrc, psrc, drift, rows_per_split, nsplit, blockIdx.x);
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_lr16_logp_pipe(PlainArgs a, const float* __restrict__ xsrc,
+                                                        int64_t rows_per_split, int nsplit) {
+    lr16_logp_body<KS>(a, xsrc, rows_per_split, nsplit, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_lr16_lp_sum(PlainArgs a, int nsplit) { lr16_lp_sum_body(a, nsplit, blockIdx.x); }
+
+// ---------------------------------------------------------------------------
+// Several requests in one launch (the serving form): job j owns blocks
+// begin[k] .. begin[k] + nblk[k] - 1 of the grid of kernel kind k; its
+// arguments are copied out of the device job table into registers, and the
+// body is the one-request kernel's with the job-local block index, so every
+// request computes bitwise what it computes alone.
+// ---------------------------------------------------------------------------
+template <int KS>
+__global__ __launch_bounds__(256) void k_lr16_grad_multi(const Lr16Job* __restrict__ jobs, int njobs) {
+    int64_t lb;
+    const int j = lr16_job_of(jobs, njobs, LR16_KIND_GRAD, blockIdx.x, &lb);
+    if (j < 0) return;
+    const PlainArgs a = jobs[j].a;
+    lr16_grad_body<KS>(a, (const float*)a.ws.xq, (const float*)a.ws.pq, 1, jobs[j].rows_g, jobs[j].nsplit_g, (int)lb);
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_lr16_logp_multi(const Lr16Job* __restrict__ jobs, int njobs) {
+    int64_t lb;
+    const int j = lr16_job_of(jobs, njobs, LR16_KIND_LOGP, blockIdx.x, &lb);
+    if (j < 0) return;
+    const PlainArgs a = jobs[j].a;
+    lr16_logp_body<KS>(a, (const float*)a.ws.xq, jobs[j].rows_lp, jobs[j].nsplit_lp, (int)lb);
+}
+
+__global__ __launch_bounds__(256) void k_lr16_lp_sum_multi(const Lr16Job* __restrict__ jobs, int njobs) {
+    int64_t lb;
+    const int j = lr16_job_of(jobs, njobs, LR16_KIND_LPSUM, blockIdx.x, &lb);
+    if (j < 0) return;
+    const PlainArgs a = jobs[j].a;
+    lr16_lp_sum_body(a, jobs[j].nsplit_lp, (int)lb);
 }
 
 // Padded copies: X [N, D] -> Xp [NP, DP] and Xt [DP, NP] (zeros outside), y -> yp
@@ -759,6 +807,60 @@ static hipError_t lb_logp_k(const PlainArgs& a, const float* x, hipStream_t s) {
                        rows_for(NP, nsplit), nsplit);
     hipLaunchKernelGGL(k_lr16_lp_sum, dim3((unsigned)((a.C + 255) / 256)), dim3(256), 0, s, a, nsplit);
     return hipGetLastError();
+}
+
+int lr16_batch_class(const PlainArgs& a) {
+    if (a.tg.kind != HMC_TGT_LOGREG || !a.bf16_grad || a.f64) return -1;
+    const int ks = lb_ks(a.tg.D);
+    return ks > 0 ? ks : -1;
+}
+
+void lr16_job_shape(const PlainArgs& a, Lr16Job* j) {
+    const int64_t NP = (a.tg.N + LB_RS - 1) / LB_RS * LB_RS;
+    j->nsplit_g = lb_grad_nsplit_t(a);
+    j->nsplit_lp = lb_logp_nsplit(a.tg.N, a.C, a.tg.D);
+    j->rows_g = rows_for(NP, j->nsplit_g);
+    j->rows_lp = rows_for(NP, j->nsplit_lp);
+    const int64_t ctg = lb_grad_ct(a.tg.D), ctl = lb_logp_ct(a.tg.D);
+    j->nblk[LR16_KIND_GRAD] = (a.C + ctg - 1) / ctg * j->nsplit_g;
+    j->nblk[LR16_KIND_LOGP] = (a.C + ctl - 1) / ctl * j->nsplit_lp;
+    j->nblk[LR16_KIND_LPSUM] = (a.C + 255) / 256;
+}
+
+template <int KS>
+static hipError_t lb_multi_k(int kind, const Lr16Job* jobs, int njobs, int64_t blocks, hipStream_t s) {
+    const dim3 grid((unsigned)blocks);
+    if (kind == LR16_KIND_GRAD) {
+        const size_t lds = (size_t)LbGrad<KS>::LDS;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void*)k_lr16_grad_multi<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+        hipLaunchKernelGGL(k_lr16_grad_multi<KS>, grid, dim3(256), lds, s, jobs, njobs);
+    } else if (kind == LR16_KIND_LOGP) {
+        const size_t lds = (size_t)LbLogp<KS>::LDS;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void*)k_lr16_logp_multi<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+        hipLaunchKernelGGL(k_lr16_logp_multi<KS>, grid, dim3(256), lds, s, jobs, njobs);
+    } else {
+        hipLaunchKernelGGL(k_lr16_lp_sum_multi, grid, dim3(256), 0, s, jobs, njobs);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lr16_kind_multi(int kind, int64_t D, const Lr16Job* jobs_dev, int njobs, int64_t blocks,
+                                  hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    switch (lb_ks(D)) {
+    case 1: return lb_multi_k<1>(kind, jobs_dev, njobs, blocks, s);
+    case 2: return lb_multi_k<2>(kind, jobs_dev, njobs, blocks, s);
+    case 4: return lb_multi_k<4>(kind, jobs_dev, njobs, blocks, s);
+    case 6: return lb_multi_k<6>(kind, jobs_dev, njobs, blocks, s);
+    case 8: return lb_multi_k<8>(kind, jobs_dev, njobs, blocks, s);
+    case 12: return lb_multi_k<12>(kind, jobs_dev, njobs, blocks, s);
+    case 16: return lb_multi_k<16>(kind, jobs_dev, njobs, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_lr16_grad(const PlainArgs& a, const float* x, const float* p, int drift, hipStream_t s) {

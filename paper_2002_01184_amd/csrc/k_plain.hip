@@ -42,8 +42,8 @@ __global__ void k_tick(Ctrl* c) {
 // the 4-dim Philox blocks b = lane, lane + G, ...
 // ---------------------------------------------------------------------------
 template <typename T, int G>
-__global__ __launch_bounds__(256) void k_begin(PlainArgs a) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void begin_body(const PlainArgs& a, int64_t blk) {
+    const int64_t gid = blk * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % G;
     const int64_t c = gid / G;
     const bool active = c < a.C;
@@ -77,6 +77,9 @@ __global__ __launch_bounds__(256) void k_begin(PlainArgs a) {
     k0 = group_sum<G>(k0);
     if (active && lane == 0) a.ws.h0[c] = -(bt * a.ws.logp[c]) + k0;
 }
+
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_begin(PlainArgs a) { begin_body<T, G>(a, blockIdx.x); }
 
 // logp at (x, g) from the closed form that remains after the gradient kernel:
 // Gaussians 1/2 x.g; logistic regression -|x|^2/(2 s^2) + the data part in lpq.
@@ -115,8 +118,8 @@ __device__ __forceinline__ void end_scalars(const PlainArgs& a, const Ctrl& ct, 
                                             double lar, double dh, double lp_new, double eps_used);
 
 template <typename T, int G>
-__global__ __launch_bounds__(256) void k_end(PlainArgs a) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void end_body(const PlainArgs& a, int64_t blk) {
+    const int64_t gid = blk * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % G;
     const int64_t c = gid / G;
     const bool active = c < a.C;
@@ -163,6 +166,9 @@ __global__ __launch_bounds__(256) void k_end(PlainArgs a) {
     a.ws.logp[c] = lp_new;
     end_scalars(a, ct, c, i, acc, lar, dh, lp_new, eps_used);
 }
+
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_end(PlainArgs a) { end_body<T, G>(a, blockIdx.x); }
 
 // The per-chain scalars at the end of transition i of the call (one lane per
 // chain): step-size adaptation during the burn-in, the trace row of a kept
@@ -1205,12 +1211,12 @@ __global__ __launch_bounds__(256) void k_lr32_step(PlainArgs a, float* __restric
 
 // drift (same fmaf as the partial kernel), sum the split partials in split
 // order, add the prior gradient, kick.
-__global__ __launch_bounds__(256) void k_logreg_finish(PlainArgs a, float* __restrict__ xd, float* __restrict__ pd,
-                                                       float* __restrict__ gd, int nsplit, int drift, int kick,
-                                                       double kick_scale, int want_logp) {
+__device__ __forceinline__ void finish_body(const PlainArgs& a, float* __restrict__ xd, float* __restrict__ pd,
+                                            float* __restrict__ gd, int nsplit, int drift, int kick,
+                                            double kick_scale, int want_logp, int64_t blk, int64_t nblk) {
     const int64_t D = a.tg.D, C = a.C;
     const int64_t n = C * D;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = blk * blockDim.x + threadIdx.x; i < n; i += nblk * blockDim.x) {
         const int64_t c = i / D;
         const double sd = a.ws.scale ? a.ws.scale[i - c * D] : 1.0;
         float x = xd[i];
@@ -1232,6 +1238,49 @@ __global__ __launch_bounds__(256) void k_logreg_finish(PlainArgs a, float* __res
     }
 }
 
+__global__ __launch_bounds__(256) void k_logreg_finish(PlainArgs a, float* __restrict__ xd, float* __restrict__ pd,
+                                                       float* __restrict__ gd, int nsplit, int drift, int kick,
+                                                       double kick_scale, int want_logp) {
+    finish_body(a, xd, pd, gd, nsplit, drift, kick, kick_scale, want_logp, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Several BF16-gradient logistic requests in one launch per kernel (serving):
+// the one-request bodies with job-local block indices (see Lr16Job).
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ __launch_bounds__(256) void k_begin_multi(const Lr16Job* __restrict__ jobs, int njobs) {
+    int64_t lb;
+    const int j = lr16_job_of(jobs, njobs, LR16_KIND_GROUP, blockIdx.x, &lb);
+    if (j < 0) return;
+    const PlainArgs a = jobs[j].a;
+    begin_body<float, G>(a, lb);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_end_multi(const Lr16Job* __restrict__ jobs, int njobs) {
+    int64_t lb;
+    const int j = lr16_job_of(jobs, njobs, LR16_KIND_GROUP, blockIdx.x, &lb);
+    if (j < 0) return;
+    const PlainArgs a = jobs[j].a;
+    end_body<float, G>(a, lb);
+}
+
+// leapfrog step of the transition: drift, split sums, kick (ks), the gradient kept on the last step
+__global__ __launch_bounds__(256) void k_finish_multi(const Lr16Job* __restrict__ jobs, int njobs, int last) {
+    int64_t lb;
+    const int j = lr16_job_of(jobs, njobs, LR16_KIND_FINISH, blockIdx.x, &lb);
+    if (j < 0) return;
+    const PlainArgs a = jobs[j].a;
+    finish_body(a, (float*)a.ws.xq, (float*)a.ws.pq, last ? (float*)a.ws.gq : nullptr, jobs[j].nsplit_g, 1, 1,
+                last ? 0.5 : 1.0, 0, lb, jobs[j].nblk[LR16_KIND_FINISH]);
+}
+
+__global__ void k_tick_multi(const Lr16Job* __restrict__ jobs, int njobs) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < njobs) jobs[j].a.ws.ctrl->t += 1;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -1241,6 +1290,8 @@ static int chain_group(int64_t D) {
     if (D <= 64) return 16;
     return 64;
 }
+
+int plain_chain_group(int64_t D) { return chain_group(D); }
 
 #define HMC_GROUP_DISPATCH(KERNEL, T, a, s)                                                       \
     do {                                                                                          \
@@ -1739,6 +1790,65 @@ hipError_t launch_plain_transition(const PlainArgs& a, bool copy_proposal, hipSt
     }
     hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, a.ws.ctrl);
     return hipGetLastError();
+}
+
+// One transition of every job, in the order of launch_plain_transition for a
+// BF16-gradient logistic request: begin, L x (gradient, finish), logit pass and
+// its split sum after the last gradient, end, tick.  Every job has the same
+// lanes per chain G, padded width and L (the batch class).
+hipError_t launch_lr16_transition_multi(const Lr16Job* jobs_host, const Lr16Job* jobs_dev, int njobs,
+                                        hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    const PlainArgs& a0 = jobs_host[0].a;
+    const int G = chain_group(a0.tg.D);
+    int64_t tot[LR16_KINDS];
+    for (int k = 0; k < LR16_KINDS; ++k)
+        tot[k] = jobs_host[njobs - 1].begin[k] + jobs_host[njobs - 1].nblk[k];
+    const dim3 gg((unsigned)tot[LR16_KIND_GROUP]);
+    if (G == 1) hipLaunchKernelGGL(k_begin_multi<1>, gg, dim3(256), 0, s, jobs_dev, njobs);
+    else if (G == 4) hipLaunchKernelGGL(k_begin_multi<4>, gg, dim3(256), 0, s, jobs_dev, njobs);
+    else if (G == 16) hipLaunchKernelGGL(k_begin_multi<16>, gg, dim3(256), 0, s, jobs_dev, njobs);
+    else hipLaunchKernelGGL(k_begin_multi<64>, gg, dim3(256), 0, s, jobs_dev, njobs);
+    for (int l = 0; l < a0.L; ++l) {
+        const int last = l == a0.L - 1;
+        hipError_t e = launch_lr16_kind_multi(LR16_KIND_GRAD, a0.tg.D, jobs_dev, njobs, tot[LR16_KIND_GRAD], s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_finish_multi, dim3((unsigned)tot[LR16_KIND_FINISH]), dim3(256), 0, s, jobs_dev, njobs,
+                           last);
+        if (last) {
+            e = launch_lr16_kind_multi(LR16_KIND_LOGP, a0.tg.D, jobs_dev, njobs, tot[LR16_KIND_LOGP], s);
+            if (e != hipSuccess) return e;
+            e = launch_lr16_kind_multi(LR16_KIND_LPSUM, a0.tg.D, jobs_dev, njobs, tot[LR16_KIND_LPSUM], s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    if (G == 1) hipLaunchKernelGGL(k_end_multi<1>, gg, dim3(256), 0, s, jobs_dev, njobs);
+    else if (G == 4) hipLaunchKernelGGL(k_end_multi<4>, gg, dim3(256), 0, s, jobs_dev, njobs);
+    else if (G == 16) hipLaunchKernelGGL(k_end_multi<16>, gg, dim3(256), 0, s, jobs_dev, njobs);
+    else hipLaunchKernelGGL(k_end_multi<64>, gg, dim3(256), 0, s, jobs_dev, njobs);
+    hipLaunchKernelGGL(k_tick_multi, dim3((unsigned)((njobs + 63) / 64)), dim3(64), 0, s, jobs_dev, njobs);
+    return hipGetLastError();
+}
+
+// Grid layout of a batch: block ranges of every job for every kernel kind
+// (gradient and logit ranges start at multiples of 8); false if a grid would
+// exceed 2^31 blocks.
+bool lr16_layout(Lr16Job* jobs, int njobs) {
+    int64_t next[LR16_KINDS] = {0, 0, 0, 0, 0};
+    for (int j = 0; j < njobs; ++j) {
+        Lr16Job& jb = jobs[j];
+        lr16_job_shape(jb.a, &jb);
+        const int G = chain_group(jb.a.tg.D);
+        jb.nblk[LR16_KIND_GROUP] = (jb.a.C * G + 255) / 256;
+        jb.nblk[LR16_KIND_FINISH] = elem_grid(jb.a.C * jb.a.tg.D).x;
+        for (int k = 0; k < LR16_KINDS; ++k) {
+            if (k == LR16_KIND_GRAD || k == LR16_KIND_LOGP) next[k] = (next[k] + 7) / 8 * 8;
+            jb.begin[k] = next[k];
+            next[k] += jb.nblk[k];
+            if (next[k] > 0x7fffffffLL) return false;
+        }
+    }
+    return true;
 }
 
 }  // namespace hmc

@@ -89,7 +89,8 @@ class hmc_request(ctypes.Structure):
 class hmc_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "admitted", "completed", "failed", "active", "pending",
                                               "ticks", "batched_launches", "max_active")] + \
-               [(n, ctypes.c_size_t) for n in ("pool_bytes", "bytes_in_use", "peak_bytes_in_use")]
+               [(n, ctypes.c_size_t) for n in ("pool_bytes", "bytes_in_use", "peak_bytes_in_use")] + \
+               [("batched_plain_transitions", ctypes.c_int64)]
 
 
 HMC_REQ_QUEUED, HMC_REQ_RUNNING, HMC_REQ_DONE, HMC_REQ_FAILED = range(4)

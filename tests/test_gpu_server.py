@@ -86,6 +86,36 @@ def test_server_results_equal_sample_chain_alone_and_in_mix():
     assert st["batched_launches"] >= 1         # the two diagonal Gaussians share a ragged launch
 
 
+def test_server_batches_bf16_logistic_requests():
+    # three BF16-gradient logistic requests of one shape class (D in (384, 512], L = 4) but
+    # different rows, dimension and chain count, with different lengths so that the set of
+    # members shrinks inside a tick: each runs one launch per kernel for all of them, and
+    # each result is bitwise that of its own hmc_sample_chain call
+    reqs = [W.logreg(2500, 400, 70, L=4, step_size=0.004, burnin=30, results=12, seed=31, bf16=True, init=0.1),
+            W.logreg(1800, 450, 150, L=4, step_size=0.004, burnin=28, results=10, seed=32, bf16=True, init=0.1),
+            W.logreg(700, 500, 33, L=4, step_size=0.004, burnin=33, results=13, seed=33, bf16=True, init=0.1,
+                     adapt=False)]
+    refs = [hmc.sampler_for(w, grad_bf16=True) for w in reqs]
+    ref_out = []
+    for s, w in zip(refs, reqs):
+        out = s.sample_chain(w.num_results, w.num_burnin, adapt=w.adapt)
+        torch.cuda.synchronize()
+        ref_out.append({k: v.clone() for k, v in out.items() if v is not None})
+        s.close()
+    srv = hmc.Server(2 << 30, transitions_per_tick=7)
+    preps = [srv.prepare(w, server_samples=(i == 1), grad_bf16=True) for i, w in enumerate(reqs)]
+    ids = [srv.submit_prepared(p) for p in preps]
+    outs = [srv.wait(i)[0] for i in ids]
+    st = srv.stats()
+    srv.close()
+    print("server stats:", st)
+    for w, r, o in zip(reqs, ref_out, outs):
+        for k in ["samples", "is_accepted", "step_size", "target_log_prob"]:
+            assert torch.equal(o[k], r[k]), (w.name, k)
+    assert st["completed"] == 3 and st["failed"] == 0
+    assert st["batched_plain_transitions"] >= 1
+
+
 def test_server_admission_follows_budget():
     w = W.gauss_diag(dim=64, num_chains=512, L=5, step_size=0.05, burnin=10, results=10, seed=3)
     t = hmc.hmc_target(w.kind, 0, w.dim, None, None, hmc.HMC_F32, 0, 0, None, 1.0)
