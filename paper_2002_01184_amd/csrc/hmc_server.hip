@@ -154,6 +154,14 @@ hipError_t admit(Request* q, void* pool, hipStream_t s) {
     return launch_da_init(a, s);
 }
 
+// a request whose gradient launch alone has a workgroup for every CU gains nothing
+// from sharing launches and would hold back the small requests it shares them with
+bool lr16_fills_gpu(const PlainArgs& a) {
+    Lr16Job j;
+    lr16_job_shape(a, &j);
+    return j.nblk[LR16_KIND_GRAD] >= 256;
+}
+
 // the launch parameters of the next n transitions of a fused request
 FusedRun tick_run(const Request* q, int64_t n) {
     FusedRun r;
@@ -247,7 +255,7 @@ void worker_loop(hmc_server* srv) {
         for (Request* q : act) {
             if (q->form == HMC_FORM_FUSED && q->cls >= 0) {
                 classes[q->cls].push_back(q);
-            } else if (q->form == HMC_FORM_PLAIN && lr16_batch_class(q->a) >= 0) {
+            } else if (q->form == HMC_FORM_PLAIN && lr16_batch_class(q->a) >= 0 && !lr16_fills_gpu(q->a)) {
                 lr16_classes[std::make_tuple(lr16_batch_class(q->a), plain_chain_group(q->a.tg.D), q->a.L)]
                     .push_back(q);
             } else {
@@ -287,12 +295,15 @@ void worker_loop(hmc_server* srv) {
         }
         // BF16-gradient logistic plain requests of one class: transition i of the tick
         // runs once for every member with more than i transitions left (chunks of kMaxJobs)
+        // on the streams of the other requests (stream 0 carries the element-wise classes), so
+        // that classes overlap
+        int si = 1;
         int nlr = 0;
         for (auto& kv : lr16_classes) {
             if (kv.second.size() < 2) continue;
             for (size_t b0 = 0; b0 < kv.second.size() && ok; b0 += kMaxJobs) {
                 const size_t b1 = std::min(kv.second.size(), b0 + kMaxJobs);
-                hipStream_t s = srv->streams[0];
+                hipStream_t s = srv->streams[si++ % kStreams];
                 int first = -1, n = 0;
                 for (int64_t i = 0; i < srv->K && ok; ++i) {
                     std::vector<Request*> mem;
@@ -300,8 +311,8 @@ void worker_loop(hmc_server* srv) {
                         if (kv.second[k]->total - kv.second[k]->done > i) mem.push_back(kv.second[k]);
                     if (mem.empty()) break;
                     if ((int)mem.size() != n) {   // the set only shrinks: a new table when it does
-                        if (nlr + (int)mem.size() > 4 * kMaxJobs) {   // table reuse needs the copies done
-                            (void)hipStreamSynchronize(s);
+                        if (nlr + (int)mem.size() > 4 * kMaxJobs) {   // table reuse needs every copy done
+                            for (int k = 0; k < kStreams; ++k) (void)hipStreamSynchronize(srv->streams[k]);
                             nlr = 0;
                         }
                         first = nlr;
@@ -326,7 +337,6 @@ void worker_loop(hmc_server* srv) {
                 }
             }
         }
-        int si = 1;
         for (Request* q : others) {
             hipStream_t s = srv->streams[si++ % kStreams];
             const int64_t n = std::min<int64_t>(srv->K, q->total - q->done);
