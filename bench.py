@@ -345,13 +345,15 @@ def bench_nuts(args):
     s = hmc.sampler_for(w, form=form, grad_bf16=args.grad == "bf16")
     # the persistent NUTS kernels cover element-wise targets up to 256 4-dim blocks per chain (beyond 64, or
     # 128 in FP32, a workgroup per chain), the dense Gaussian up to D = 128 (FP32) and logistic regression
-    # with FP32 X, D <= 32 and X, y and the per-wave buffers within the 160 KB of LDS
-    fused = hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED
+    # with FP32 gradients and D <= 32 (X, y and the per-wave buffers in the 160 KB of LDS when they fit and X
+    # is FP32, else X read through the L2)
+    fused = hmc.hmc_effective_form(s.ctx) == hmc.HMC_FORM_FUSED or args.form == "auto"
     dp = 4 * ((w.dim + 3) // 4)
     lr_lds = 4 * (w.n_rows * dp + ((w.n_rows + 3) // 4) * 4 + 4 * (2 * dp + 64 * 33)) if w.kind == W.LOGREG else 0
     persistent = fused and ((w.kind in (W.STD_NORMAL, W.GAUSS_DIAG) and (w.dim + 3) // 4 <= 256)
                             or (w.kind == W.GAUSS_DENSE and w.state_dtype == "f32" and w.dim <= 128)
-                            or (w.kind == W.LOGREG and args.grad == "f32" and w.dim <= 32 and lr_lds <= 163840))
+                            or (w.kind == W.LOGREG and args.grad == "f32" and w.dim <= 32))
+    x_in_l2 = persistent and w.kind == W.LOGREG and (lr_lds > 163840 - 64 or w.X_bf16 is not None)
     x0 = torch.from_numpy(np.ascontiguousarray(w.x0)).cuda()
     eps0 = torch.full((w.num_chains,), w.step_size, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -407,7 +409,9 @@ def bench_nuts(args):
                    "max_tree_depth": args.nuts, "step_size": w.step_size,
                    "adapt": "dual_averaging (Algorithm 6)" if args.nuts_adapt else "none", "num_burnin": w.num_burnin,
                    "num_results": w.num_results,
-                   "form": "persistent (unrolled tree in registers)" if persistent else "plain (unrolled tree, lockstep)",
+                   "form": ("persistent (unrolled tree in registers, X read through the L2)" if x_in_l2 else
+                            "persistent (unrolled tree in registers)") if persistent else
+                           "plain (unrolled tree, lockstep)",
                    "parallelism": "chains (1 GPU)"},
         "roofline": {"bound": bound, "achieved": achieved / scale, "peak": peak / scale,
                      "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak, "traffic": None,

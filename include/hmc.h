@@ -318,13 +318,15 @@ hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale);
  * in the transition's last doubling (0 with max_depth 0) -- by dual averaging
  * (as in hmc_sample_chain: iteration m = burn-in transition m of this call;
  * the last burn-in transition sets the averaged iterate) or by the
- * multiplicative rule.  On a context of the fused form one persistent kernel
- * runs every transition of the call where one covers the target: N(0, I) and
- * the diagonal Gaussian up to D = 1024 (a lane group, or above 256 (FP64) /
- * 512 (FP32) dims a workgroup, per chain); the dense Gaussian in FP32 up to
- * D = 128 (16 chains per workgroup on MFMA, building their trees in
- * lockstep); logistic regression with FP32 X and states, D <= 32 and X and y
- * within the workgroup's LDS (N <= 1000 at D = 25; a wavefront per chain).
+ * multiplicative rule.  On a context created with the fused or the automatic
+ * form one persistent kernel runs every transition of the call where one
+ * covers the target: N(0, I) and the diagonal Gaussian up to D = 1024 (a lane
+ * group, or above 256 (FP64) / 512 (FP32) dims a workgroup, per chain); the
+ * dense Gaussian in FP32 up to D = 128 (16 chains per workgroup on MFMA,
+ * building their trees in lockstep); logistic regression with FP32 states and
+ * gradients and D <= 32 (a wavefront per chain), with X and y in the
+ * workgroup's LDS when X is FP32 and they fit (N <= 1000 at D = 25), else X
+ * (FP32 or BF16) read through the L2 from a copy in the NUTS workspace.
  * Otherwise the chains run in lockstep on the plain kernels of the target and
  * a chain whose trajectory has stopped is masked.  All build the same trees.
  * The context must have no inverse temperatures or transform

@@ -993,7 +993,7 @@ extern "C" hmc_status hmc_set_transform_scale(hmc_ctx* ctx, const double* scale)
 extern "C" hmc_status hmc_nuts_workspace_size(const hmc_ctx* ctx, int32_t max_depth, size_t* bytes) {
     if (!ctx || !bytes) return fail(HMC_E_INVALID, "ctx and bytes must not be NULL");
     if (max_depth < 0 || max_depth > 10) return fail(HMC_E_INVALID, "max_depth must be in 0..10");
-    carve_nuts(nullptr, ctx->a.C, ctx->a.tg.D, max_depth, ctx->a.f64 ? 8 : 4, bytes);
+    carve_nuts(nullptr, ctx->a.C, ctx->a.tg.D, max_depth, ctx->a.f64 ? 8 : 4, nuts_l2_rows(ctx->a), bytes);
     return HMC_OK;
 }
 
@@ -1009,7 +1009,8 @@ extern "C" hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int
         return fail(HMC_E_UNSUPPORTED, "NUTS runs without inverse temperatures or a transform");
     if (!nuts_workspace) return fail(HMC_E_INVALID, "nuts_workspace must not be NULL");
     size_t need = 0;
-    NutsWs nw = carve_nuts(nuts_workspace, ctx->a.C, ctx->a.tg.D, max_depth, ctx->a.f64 ? 8 : 4, &need);
+    NutsWs nw = carve_nuts(nuts_workspace, ctx->a.C, ctx->a.tg.D, max_depth, ctx->a.f64 ? 8 : 4,
+                           nuts_l2_rows(ctx->a), &need);
     if (nuts_workspace_bytes < need) return fail(HMC_E_NOMEM, "NUTS workspace smaller than hmc_nuts_workspace_size");
     const int64_t total = num_results + num_burnin_steps;
     if (ctx->t + (uint64_t)total > 0xffffffffull) return fail(HMC_E_INVALID, "transition counter would exceed 2^32");
@@ -1020,7 +1021,7 @@ extern "C" hmc_status hmc_nuts_sample_chain(hmc_ctx* ctx, int32_t max_depth, int
     if (ad.adapt && ad.adapt_kind == HMC_ADAPT_DUAL_AVERAGING)
         st = check_hip(launch_da_init(ctx->a, ctx->stream), "adaptation init");
     if (st != HMC_OK) return st;
-    if (ctx->form == HMC_FORM_FUSED && nuts_fused_supported(ctx->a)) {
+    if ((ctx->form == HMC_FORM_FUSED || ctx->cfg.form == HMC_FORM_AUTO) && nuts_fused_supported(ctx->a)) {
         // element-wise targets: one persistent launch for all transitions
         st = check_hip(launch_nuts_fused(ctx->a, nw, ad, (uint32_t)ctx->t, total, max_depth, samples, tree_depth,
                                          n_leapfrog, accept_stat, ctx->stream),

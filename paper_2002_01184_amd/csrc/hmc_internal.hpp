@@ -135,9 +135,12 @@ struct NutsWs {
     int32_t *lc_n;             // [MD, C]
     int32_t *active, *alive, *rc_n, *depth, *nleap, *moved, *dir;   // [C]
     int32_t *n_active;         // [1]
+    float *xt4, *yf;           // logistic X beyond the LDS, 4-dim chunk major, and y (null when unused)
     size_t bytes;
 };
-NutsWs carve_nuts(void* base, int64_t C, int64_t D, int32_t max_depth, size_t es, size_t* total);
+// l2_rows: rows of the logistic X copy the persistent kernel reads through the L2 (nuts_l2_rows), else 0
+NutsWs carve_nuts(void* base, int64_t C, int64_t D, int32_t max_depth, size_t es, int64_t l2_rows, size_t* total);
+int64_t nuts_l2_rows(const PlainArgs& a);
 // Step-size adaptation of a NUTS run (the fields set_adapt fills), during the
 // first n_burnin transitions.
 struct NutsAdapt {

@@ -57,7 +57,7 @@ __device__ __attribute__((noinline)) double nuts_adapt(const NutsAdapt& ad, int6
 
 static size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-NutsWs carve_nuts(void* base, int64_t C, int64_t D, int32_t max_depth, size_t es, size_t* total) {
+NutsWs carve_nuts(void* base, int64_t C, int64_t D, int32_t max_depth, size_t es, int64_t l2_rows, size_t* total) {
     char* p = (char*)base;
     size_t off = 0;
     auto take = [&](size_t n) {
@@ -85,6 +85,9 @@ NutsWs carve_nuts(void* base, int64_t C, int64_t D, int32_t max_depth, size_t es
     n.nleap = (int32_t*)take((size_t)C * 4); n.moved = (int32_t*)take((size_t)C * 4);
     n.dir = (int32_t*)take((size_t)C * 4);
     n.n_active = (int32_t*)take(4);
+    n.xt4 = (float*)take((size_t)((D + 3) / 4) * 16 * l2_rows);
+    n.yf = (float*)take((size_t)l2_rows * 4);
+    if (l2_rows == 0) n.xt4 = n.yf = nullptr;
     n.bytes = off;
     if (total) *total = off;
     return n;
@@ -442,9 +445,48 @@ inline size_t nuts_lr_lds_bytes(int64_t N, int64_t D) {
     return (size_t)(nuts_lr_lds_fixed(N, D) + (int64_t)nuts_lr_lds_levels(N, D) * 4 * 4 * dp) * sizeof(float);
 }
 
+// The L2 variant (GK = 2, X beyond the LDS): X and y stay in global memory, so
+// a workgroup holds only the per-wave buffers and as many parked levels as fit
+// in a third of the LDS, and three workgroups (12 waves) share a CU.
+constexpr int NUTS_L2_LDS = 53248;
+__host__ __device__ inline int nuts_l2_lds_levels(int64_t D) {
+    const int64_t dp = 4 * ((D + 3) / 4);
+    const int64_t room = NUTS_L2_LDS / 4 - 16 - nuts_lr_lds_fixed(0, D);
+    const int64_t lv = room > 0 ? room / (4 * 4 * dp) : 0;
+    return (int)(lv > 9 ? 9 : lv);
+}
+inline size_t nuts_l2_lds_bytes(int64_t D) {
+    const int64_t dp = 4 * ((D + 3) / 4);
+    return (size_t)(nuts_lr_lds_fixed(0, D) + (int64_t)nuts_l2_lds_levels(D) * 4 * 4 * dp) * sizeof(float);
+}
+
+// Copy of X for the L2 variant, 4-dim chunk major: xt4[q][r] holds dims
+// 4q .. 4q + 3 of row r (zeros past D), so that the 64 lanes of a wave, on 64
+// consecutive rows, read 1 KB of consecutive bytes per chunk; y as floats.
+__global__ __launch_bounds__(256) void k_nuts_pad_x(const void* __restrict__ X, int x_bf16,
+                                                    const uint8_t* __restrict__ y, float* __restrict__ xt4,
+                                                    float* __restrict__ yf, int64_t N, int64_t D) {
+    const int64_t dq = (D + 3) / 4;
+    const int64_t n = dq * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = i / N, r = i - q * N;
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t d = 4 * q + e;
+            v[e] = 0.f;
+            if (d < D)
+                v[e] = x_bf16 ? bf16_to_f32(((const uint16_t*)X)[r * D + d]) : ((const float*)X)[r * D + d];
+        }
+        *(float4*)(xt4 + 4 * i) = make_float4(v[0], v[1], v[2], v[3]);
+        if (q == 0) yf[r] = y[r] ? 1.f : 0.f;
+    }
+}
+
 // ST: the run adapts the step size or traces the statistic (a template
 // parameter, so that plain runs carry none of it).  GK: 0 element-wise
-// Gaussian gradient, 1 logistic regression through LDS.
+// Gaussian gradient, 1 logistic regression with X in LDS, 2 logistic
+// regression with X read from global memory (the L2 holds it).
 template <typename T, int G, int NB, bool ST, int GK>
 __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, NutsAdapt ad, uint32_t t_begin,
                                                          int64_t n_trans, int32_t max_depth, T* samples,
@@ -453,16 +495,19 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
     extern __shared__ float lr_lds[];
     __shared__ double gsr[G > 64 ? 2 * 2 * (G / 64) : 1];
     int gk = 0;
-    const int64_t NR = GK == 1 ? a.tg.N : 0;
-    const int dq = GK == 1 ? (int)((a.tg.D + 3) / 4) : 0;
+    const int64_t NR = GK >= 1 ? a.tg.N : 0;
+    const int64_t NL = GK == 1 ? NR : 0;                 // rows of X held in LDS
+    const int dq = GK >= 1 ? (int)((a.tg.D + 3) / 4) : 0;
     const int dp = 4 * dq;
-    float* xl = lr_lds;                                  // [N][dp]
-    float* yl = xl + NR * dp;                            // [N]
-    float* thl = yl + ((NR + 3) & ~(int64_t)3) + (threadIdx.x >> 6) * (2 * dp + 64 * LR_SCR);   // wave's theta [dp]
+    float* xl = lr_lds;                                  // [N][dp] (GK = 1)
+    float* yl = xl + NL * dp;                            // [N] (GK = 1)
+    const floatx4* xg4 = (const floatx4*)n.xt4;          // [dq][N] (GK = 2)
+    const float* yg = n.yf;                              // [N] (GK = 2)
+    float* thl = yl + ((NL + 3) & ~(int64_t)3) + (threadIdx.x >> 6) * (2 * dp + 64 * LR_SCR);   // wave's theta [dp]
     float* gsl = thl + dp;                               // gradient sums [dp]
     float* scr = gsl + dp;                               // [64][LR_SCR]
-    const int nlv = GK == 1 ? nuts_lr_lds_levels(NR, a.tg.D) : 0;
-    float* lvl = lr_lds + (GK == 1 ? nuts_lr_lds_fixed(NR, a.tg.D) : 0) +
+    const int nlv = GK == 1 ? nuts_lr_lds_levels(NR, a.tg.D) : GK == 2 ? nuts_l2_lds_levels(a.tg.D) : 0;
+    float* lvl = lr_lds + (GK >= 1 ? nuts_lr_lds_fixed(NL, a.tg.D) : 0) +
                  (int64_t)(threadIdx.x >> 6) * nlv * 4 * dp;  // this wave's level records [nlv][4][dp]
     if (GK == 1) {
         const float* Xg = (const float*)a.tg.X;
@@ -504,7 +549,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
     // pointer), the rest in the NutsWs buffers
     T* const grec[4] = {lfx, lfr, lcx, lcg};
     auto recp = [&](int k, int q) -> T* {
-        if (GK == 1 && k <= nlv) return (T*)(lvl + ((k - 1) * 4 + q) * dp);
+        if (GK >= 1 && k <= nlv) return (T*)(lvl + ((k - 1) * 4 + q) * dp);
         return grec[q] + ((int64_t)k * C + cc) * D;
     };
     // logistic data gradient X^T (y - sigmoid(X theta)) at theta = wxa into
@@ -531,11 +576,12 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
             float sv = 0.f;
 #pragma unroll
             for (int q = 0; q < LR_DQ; ++q) {
-                xq[q] = q < dq ? *(const floatx4*)(xr + 4 * q) : floatx4{0.f, 0.f, 0.f, 0.f};
+                if constexpr (GK == 2) xq[q] = q < dq ? xg4[(int64_t)q * nr + r] : floatx4{0.f, 0.f, 0.f, 0.f};
+                else xq[q] = q < dq ? *(const floatx4*)(xr + 4 * q) : floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) sv = fmaf(xq[q][e], th[q][e], sv);
             }
-            const float res = nuts_lr_row(sv, yl[r], lpd);
+            const float res = nuts_lr_row(sv, GK == 2 ? yg[r] : yl[r], lpd);
 #pragma unroll
             for (int q = 0; q < LR_DQ; ++q)
 #pragma unroll
@@ -628,7 +674,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                             kin += 0.5 * (double)wr[b][e] * (double)wr[b][e];
                         }
                     }
-                if (GK == 1) {
+                if (GK >= 1) {
                     const double lpd = logreg_grad_lds(wx, wg);
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
@@ -1277,8 +1323,17 @@ static bool nuts_lr_supported(const PlainArgs& a) {
            a.tg.D <= 4 * LR_DQ && nuts_lr_lds_bytes(a.tg.N, a.tg.D) <= (size_t)ND_LDS_MAX - 64;
 }
 
+// the L2 variant: FP32 states, X (FP32 or BF16) beyond the LDS or stored in BF16,
+// D <= 4 LR_DQ
+static bool nuts_l2_supported(const PlainArgs& a) {
+    return a.tg.kind == HMC_TGT_LOGREG && !a.f64 && !a.bf16_grad && a.tg.D >= 1 && a.tg.D <= 4 * LR_DQ &&
+           a.tg.N >= 1 && !nuts_lr_supported(a);
+}
+
+int64_t nuts_l2_rows(const PlainArgs& a) { return nuts_l2_supported(a) ? a.tg.N : 0; }
+
 static int nuts_elem_shape(const PlainArgs& a, int* G) {
-    if (nuts_lr_supported(a)) { *G = 64; return 1; }
+    if (nuts_lr_supported(a) || nuts_l2_supported(a)) { *G = 64; return 1; }
     if (a.tg.kind != HMC_TGT_STD_NORMAL && a.tg.kind != HMC_TGT_GAUSS_DIAG) return 0;
     const int64_t nblk = (a.tg.D + 3) / 4;
     if (nblk <= 1) { *G = 1; return 1; }
@@ -1352,7 +1407,21 @@ hipError_t launch_nuts_fused(const PlainArgs& a, const NutsWs& n, const NutsAdap
             hipLaunchKernelGGL((k_nuts_fused_elem<TT, GG, NN, false, 0>), grid, dim3(256), 0, s, a, n, ad, t_begin,  \
                                n_trans, max_depth, (TT*)samples, tr_depth, tr_nleap, tr_stat);                       \
     } while (0)
-    if (nuts_lr_supported(a)) {
+    if (nuts_l2_supported(a)) {
+        if (!n.xt4 || !n.yf) return hipErrorInvalidValue;
+        const int64_t ne = (a.tg.D + 3) / 4 * a.tg.N;
+        int64_t pb = (ne + 255) / 256;
+        if (pb > 4096) pb = 4096;
+        hipLaunchKernelGGL(k_nuts_pad_x, dim3((unsigned)pb), dim3(256), 0, s, a.tg.X, a.tg.x_bf16 ? 1 : 0, a.tg.y,
+                           n.xt4, n.yf, a.tg.N, a.tg.D);
+        const size_t lds = nuts_l2_lds_bytes(a.tg.D);
+        if (st)
+            hipLaunchKernelGGL((k_nuts_fused_elem<float, 64, 1, true, 2>), grid, dim3(256), lds, s, a, n, ad, t_begin,
+                               n_trans, max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);
+        else
+            hipLaunchKernelGGL((k_nuts_fused_elem<float, 64, 1, false, 2>), grid, dim3(256), lds, s, a, n, ad,
+                               t_begin, n_trans, max_depth, (float*)samples, tr_depth, tr_nleap, tr_stat);
+    } else if (nuts_lr_supported(a)) {
         const size_t lds = nuts_lr_lds_bytes(a.tg.N, a.tg.D);
         if (st) {
             if (lds > 65536)

@@ -67,6 +67,9 @@ def _fp32_cases():
         "gauss_dense_37": W.gauss_dense(dim=37, num_chains=45, step_size=0.1, seed=3),
         "logreg_77x3": W.logreg(77, 3, 33, step_size=0.2, seed=5),
         "logreg_1000x25": W.logreg(1000, 25, 64, step_size=0.05),
+        # X beyond the LDS (persistent form: X read through the L2), and BF16-stored X
+        "logreg_3000x25": W.logreg(3000, 25, 40, step_size=0.03, seed=10),
+        "logreg_bf16_500x17": W.logreg(500, 17, 37, step_size=0.06, seed=11, bf16=True),
     }
 
 
@@ -125,6 +128,9 @@ def _persistent_cases():
         "logreg_1000x25": W.logreg(1000, 25, 64, step_size=0.05),                  # X in LDS, a wave per chain
         "logreg_77x3": W.logreg(77, 3, 33, step_size=0.2, seed=5),                 # N not a multiple of 4
         "logreg_max_960x32": W.logreg(960, 32, 12, step_size=0.03, seed=8),        # the largest X that fits
+        "logreg_l2_1300x32": W.logreg(1300, 32, 9, step_size=0.03, seed=12),       # the smallest beyond it
+        "logreg_l2_5000x7": W.logreg(5000, 7, 70, step_size=0.02, seed=13),        # X read through the L2
+        "logreg_l2_bf16_700x30": W.logreg(700, 30, 23, step_size=0.04, seed=14, bf16=True),
     }
 
 
@@ -132,7 +138,7 @@ def _persistent_cases():
 def test_persistent_and_lockstep_build_the_same_trees(name):
     w = _persistent_cases()[name]
     out = []
-    for form in (hmc.HMC_FORM_PLAIN, hmc.HMC_FORM_FUSED):
+    for form in (hmc.HMC_FORM_PLAIN, hmc.HMC_FORM_AUTO):     # automatic form: the persistent kernel
         s = hmc.sampler_for(w, form=form)
         out.append(s.nuts_sample_chain(6, 2, max_depth=7, adapt=True))
         out[-1]["eps"] = s.get_state()[1]

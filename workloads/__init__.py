@@ -168,6 +168,11 @@ def cfg_logreg_1000x25():
     return logreg(1000, 25, 1024, L=10, step_size=0.05, burnin=1000, results=1000)
 
 
+def cfg_logreg_10000x25():
+    # ten times the rows of the 1000x25 workload: X (1.1 MB padded) is beyond a workgroup's LDS
+    return logreg(10000, 25, 1024, L=10, step_size=0.015, burnin=1000, results=1000)
+
+
 def cfg_gauss_dense_100():
     return gauss_dense(100, 4096, L=20, step_size=0.1, burnin=1000, results=1000)
 
@@ -195,6 +200,7 @@ CONFIGS = {
     "std_normal_1d_wide": cfg_std_normal_1d_wide,
     "gauss_diag_1000": cfg_gauss_diag_1000,
     "logreg_1000x25": cfg_logreg_1000x25,
+    "logreg_10000x25": cfg_logreg_10000x25,
     "gauss_dense_100": cfg_gauss_dense_100,
     "logreg_100000x256": cfg_logreg_100000x256,
 }
