@@ -554,6 +554,65 @@ def bench_served(args):
     }
 
 
+def measured_peak(bound, grad, fused_logistic):
+    """The achievable peak of the dominant kernel's bound, measured live by the
+    library's microbenchmark: the streaming read rate of 4 GiB for HBM-bound
+    kernels, else the issue rate of the MFMA instruction the kernel uses (BF16
+    16x16x32 for BF16 gradients, FP32 4x4x1 for the fused logistic kernel, FP32
+    16x16x4 otherwise).  In the roofline's unit (GB/s or TFLOP/s)."""
+    import torch
+
+    from paper_2002_01184_amd import hmc
+
+    st = ctypes_ptr_stream(torch.cuda.current_stream())
+    if bound == "hbm":
+        buf = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
+        v = hmc.hmc_peak_memory(ctypes_ptr(buf), buf.numel() * 4, 0, 1, 5, st)
+        del buf
+        return v
+    if bound == "mfma":
+        kind = 2 if grad == "bf16" else (1 if fused_logistic else 0)
+        return hmc.hmc_peak_compute(kind, 5000 if kind == 2 else 20000, 3, st)
+    return None
+
+
+def bench_peaks():
+    """Achievable peaks on this GPU (the library's microbenchmark kernels),
+    beside the published figures the roofline fractions use: streaming read
+    and copy bandwidth of 4 GiB (HBM), reads of 128 MiB (Infinity Cache) and of
+    16 MiB (each XCD's L2 holds the part its CUs read) repeated inside a launch,
+    and the issue rate of the MFMA and FP32 FMA instructions the kernels use."""
+    import torch
+
+    from paper_2002_01184_amd import hmc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    st = ctypes_ptr_stream(torch.cuda.current_stream())
+    out = {"config": "peaks", "published": {"hbm_GBps": PEAK["hbm"] / 1e9, "fp32_mfma_TFLOPs": PEAK["fp32_mfma"] / 1e12,
+                                            "bf16_mfma_TFLOPs": PEAK["bf16_mfma"] / 1e12, "fp32_vector_TFLOPs": 157.3}}
+    mem = {}
+    big = torch.zeros(1 << 30, dtype=torch.float32, device="cuda")            # 4 GiB
+    mem["hbm_read_4GiB"] = hmc.hmc_peak_memory(ctypes_ptr(big), big.numel() * 4, 0, 1, 10, st)
+    mem["hbm_copy_4GiB"] = hmc.hmc_peak_memory(ctypes_ptr(big), big.numel() * 4, 1, 1, 10, st)
+    del big
+    mid = torch.zeros(1 << 25, dtype=torch.float32, device="cuda")           # 128 MiB
+    mem["infinity_cache_read_128MiB_x20"] = hmc.hmc_peak_memory(ctypes_ptr(mid), mid.numel() * 4, 0, 20, 5, st)
+    small = torch.zeros(1 << 22, dtype=torch.float32, device="cuda")         # 16 MiB
+    mem["l2_read_16MiB_x200"] = hmc.hmc_peak_memory(ctypes_ptr(small), small.numel() * 4, 0, 200, 5, st)
+    out["memory_GBps"] = mem
+    comp = {}
+    for kind, name in ((0, "fp32_mfma_16x16x4"), (1, "fp32_mfma_4x4x1"), (2, "bf16_mfma_16x16x32"),
+                       (3, "fp32_fma_vector_unpacked")):
+        comp[name] = hmc.hmc_peak_compute(kind, 20000 if kind != 2 else 5000, 5, st)
+    out["compute_TFLOPs"] = comp
+    return out
+
+
+def ctypes_ptr_stream(stream):
+    import ctypes
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
 def ctypes_ptr(t):
     import ctypes
     return ctypes.c_void_p(t.data_ptr())
@@ -639,6 +698,9 @@ def main():
         return
     if args.nuts > 0:
         print(json.dumps(bench_nuts(args)), flush=True)
+        return
+    if args.config == "peaks":
+        print(json.dumps(bench_peaks()), flush=True)
         return
     if args.config == "copy_calibration":
         # a plain device-to-device copy of known size: the reference for scaling
@@ -786,6 +848,10 @@ def bench_workload(args, config, grad, form_name, steps, warmup, transitions, es
     roof["kernel_ms_per_launch"] = kern_ms
     roof["launches_timed"] = kern_n
     roof["work_per_launch"] = work
+    mp = measured_peak(roof["bound"], grad, w.kind == W.LOGREG and effective == hmc.HMC_FORM_FUSED)
+    if mp is not None:
+        roof["peak_measured"] = mp
+        roof["frac_of_measured"] = roof["achieved"] / mp
 
     result = {
         "metric": METRIC, "value": value, "unit": "leapfrog chain-steps/s", "n_gpus": 1, "steps": steps,

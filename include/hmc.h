@@ -452,6 +452,33 @@ hmc_status hmc_server_get_stats(hmc_server* srv, hmc_server_stats* out);
 /* Waits for every request, stops the worker and frees the pool. */
 hmc_status hmc_server_destroy(hmc_server* srv);
 
+/* ---------------------------------------------------------------------------
+ * Measurement helpers: the achievable peaks that roofline fractions can be
+ * quoted against beside the published ones.  Not part of the sampler.
+ * ------------------------------------------------------------------------- */
+
+/* Streaming bandwidth over the caller's device buffer (16-byte aligned):
+ * mode 0 reads bytes / 16 float4 `passes` times per launch (a buffer that fits
+ * the L2 or the Infinity Cache is then served from there after the first
+ * pass); mode 1 copies the first half of the buffer to the second (passes =
+ * 1).  Grid-stride kernels, eight 16-byte loads in flight per thread, 8192
+ * workgroups for buffers above 64 MiB, else 2048; non-temporal accesses for a
+ * single pass and for copies, cached loads for repeated passes; one untimed
+ * launch, then reps
+ * launches timed with HIP events on hip_stream (synchronized before return).
+ * *gbytes_per_s = bytes read (+ written) / time, in 1e9 B/s.  The buffer's
+ * contents are only read (mode 0) or overwritten in its second half (mode 1). */
+hmc_status hmc_peak_memory(void* buf, size_t bytes, int32_t mode, int32_t passes, int32_t reps, void* hip_stream,
+                           double* gbytes_per_s);
+
+/* Issue rate of one instruction kind, eight independent accumulators per wave
+ * and eight waves per SIMD, iters iterations per launch: kind 0
+ * v_mfma_f32_16x16x4f32 (2048 flop per wave instruction), 1 v_mfma_f32_4x4x1f32
+ * (16 blocks, 512), 2 v_mfma_f32_16x16x32_bf16 (16384), 3 v_fma_f32 (128; the
+ * library is built without packed FP32 instructions).  Timing as above;
+ * *tflops in 1e12 flop/s. */
+hmc_status hmc_peak_compute(int32_t kind, int32_t iters, int32_t reps, void* hip_stream, double* tflops);
+
 #ifdef __cplusplus
 }
 #endif

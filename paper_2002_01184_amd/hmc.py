@@ -100,7 +100,8 @@ EXPORTED = ["hmc_workspace_size", "hmc_init", "hmc_step", "hmc_sample_chain", "h
             "hmc_remc_swap", "hmc_remc_sample_chain", "hmc_sample_chain_moments", "hmc_set_transform_scale",
             "hmc_nuts_workspace_size", "hmc_nuts_sample_chain", "hmc_server_create", "hmc_server_submit",
             "hmc_server_poll", "hmc_server_wait", "hmc_server_take", "hmc_server_get_stats",
-            "hmc_server_destroy", "hmc_sample_chain_noalloc", "hmc_kernel_timer_start", "hmc_kernel_timer_read"]
+            "hmc_server_destroy", "hmc_sample_chain_noalloc", "hmc_kernel_timer_start", "hmc_kernel_timer_read",
+            "hmc_peak_memory", "hmc_peak_compute"]
 
 HMC_NOALLOC_WORKSPACE_BYTES = 64 << 20
 
@@ -180,6 +181,11 @@ def lib():
     L.hmc_server_get_stats.restype = st
     L.hmc_server_destroy.argtypes = [vp]
     L.hmc_server_destroy.restype = st
+    L.hmc_peak_memory.argtypes = [vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.hmc_peak_memory.restype = st
+    L.hmc_peak_compute.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
+    L.hmc_peak_compute.restype = st
     _lib = L
     return L
 
@@ -326,6 +332,20 @@ def hmc_server_get_stats(srv) -> dict:
 
 def hmc_server_destroy(srv):
     _check(lib().hmc_server_destroy(srv))
+
+
+def hmc_peak_memory(buf, nbytes: int, mode: int, passes: int, reps: int, stream) -> float:
+    """GB/s of a streaming read (mode 0, `passes` per launch) or copy (mode 1) over a device buffer."""
+    r = ctypes.c_double(0.0)
+    _check(lib().hmc_peak_memory(buf, nbytes, mode, passes, reps, stream, ctypes.byref(r)))
+    return r.value
+
+
+def hmc_peak_compute(kind: int, iters: int, reps: int, stream) -> float:
+    """TFLOP/s of one instruction kind (0 FP32 MFMA 16x16x4, 1 FP32 MFMA 4x4x1, 2 BF16 MFMA 16x16x32, 3 FP32 FMA)."""
+    r = ctypes.c_double(0.0)
+    _check(lib().hmc_peak_compute(kind, iters, reps, stream, ctypes.byref(r)))
+    return r.value
 
 
 # ---- convenience wrapper over torch tensors --------------------------------
