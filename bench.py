@@ -41,13 +41,14 @@ PEAK = {"fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12, "fp64": 78.6e
 # recorded with it; otherwise traffic is null until the counters are taken again.
 MEASURED_TRAFFIC = {
     # (workload, form, gradient dtype, burn-in, results): bytes per launch of the dominant kernel
+    # k_fused_logreg4<2, 7, float, false> per launch (the whole run): FETCH_SIZE 5515 KiB, WRITE_SIZE 148875 KiB
     ("logreg_1000x25", "fused", "f32", 1000, 1000): {
         "sources": ["k_fused_logreg.hip", "hmc_device.hpp", "hmc_internal.hpp"],
-        "sha256_16": "76ace38a5388c7a5", "read": 11286400, "write": 152447360},
-    # k_lr16_grad_pipe<8> per leapfrog step: FETCH_SIZE 119344 KiB, WRITE_SIZE 68352 KiB
+        "sha256_16": "173eeb1a88bfd81e", "read": 2 * 5515 * 1024, "write": 148875 * 1024},
+    # k_lr16_grad_pipe<8> per leapfrog step: FETCH_SIZE 119336 KiB, WRITE_SIZE 68352 KiB
     ("logreg_100000x256_bf16", "plain", "bf16", 25, 25): {
         "sources": ["k_logreg_bf16.hip", "hmc_device.hpp", "hmc_internal.hpp"],
-        "sha256_16": "d8e53e0627787a68", "read": 2 * 119344 * 1024, "write": 68352 * 1024},
+        "sha256_16": "9cb20bd3dac96fb7", "read": 2 * 119336 * 1024, "write": 68352 * 1024},
 }
 
 
@@ -572,7 +573,7 @@ def measured_peak(bound, grad, fused_logistic):
         return v
     if bound == "mfma":
         kind = 2 if grad == "bf16" else (1 if fused_logistic else 0)
-        return hmc.hmc_peak_compute(kind, 5000 if kind == 2 else 20000, 3, st)
+        return hmc.hmc_peak_compute(kind, 2500 if kind == 2 else 10000, 3, st)
     return None
 
 
@@ -600,11 +601,13 @@ def bench_peaks():
     small = torch.zeros(1 << 22, dtype=torch.float32, device="cuda")         # 16 MiB
     mem["l2_read_16MiB_x200"] = hmc.hmc_peak_memory(ctypes_ptr(small), small.numel() * 4, 0, 200, 5, st)
     out["memory_GBps"] = mem
-    comp = {}
+    comp, clock = {}, {}
     for kind, name in ((0, "fp32_mfma_16x16x4"), (1, "fp32_mfma_4x4x1"), (2, "bf16_mfma_16x16x32"),
-                       (3, "fp32_fma_vector_unpacked")):
-        comp[name] = hmc.hmc_peak_compute(kind, 20000 if kind != 2 else 5000, 5, st)
+                       (4, "bf16_mfma_32x32x16"), (3, "fp32_fma_vector_unpacked")):
+        comp[name], clock[name] = hmc.hmc_peak_compute(kind, 10000 if kind in (0, 1, 3) else 2500, 5, st,
+                                                       with_clock=True)
     out["compute_TFLOPs"] = comp
+    out["shader_clock_MHz"] = clock
     return out
 
 

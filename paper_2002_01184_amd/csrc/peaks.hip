@@ -11,10 +11,13 @@ namespace hmc {
 // the arithmetic alive without a store per thread (external linkage, so that
 // the stores, and what they depend on, are not removed as dead).
 __device__ float g_peak_sink;
+// Shader-clock and 100 MHz real-time counters of one wave at the start and end of a compute launch.
+__device__ uint64_t g_peak_clk[4];
 
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kNever = -1.2345e-31f;
@@ -67,25 +70,51 @@ __global__ __launch_bounds__(256) void k_peak_copy(const floatx4* __restrict__ s
 }
 
 // KIND 0: v_mfma_f32_16x16x4f32; 1: v_mfma_f32_4x4x1f32 (16 blocks);
-// 2: v_mfma_f32_16x16x32_bf16; 3: v_fma_f32 (vector ALU, no packed FP32).
-// Eight independent accumulators per wave, so the pipe never waits on a result.
+// 2: v_mfma_f32_16x16x32_bf16; 3: v_fma_f32 (vector ALU, no packed FP32);
+// 4: v_mfma_f32_32x32x16_bf16.  Independent accumulators per wave: sixteen
+// 4-register ones (a matrix pipe fed by fewer, eight, issued 16x16x32 BF16 at
+// about 60% of its rate in measurements), four 16-register ones for 32x32x16.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_peak_compute(int iters) {
     const float a = 1.0f + 1e-7f * (float)threadIdx.x, b = 1.0f - 1e-7f * (float)blockIdx.x;
     float s = 0.f;
+    const bool clk = blockIdx.x == gridDim.x / 2 && threadIdx.x == 0;   // a wave in the middle of the launch
+    uint64_t c0 = 0, r0 = 0;
+    if (clk) {
+        c0 = __builtin_amdgcn_s_memtime();
+        r0 = __builtin_amdgcn_s_memrealtime();
+    }
+    constexpr int NA = KIND == 4 ? 4 : 16;
     if constexpr (KIND == 3) {
-        float acc[8];
+        float acc[NA];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] = 1e-3f * (float)k;
+        for (int k = 0; k < NA; ++k) acc[k] = 1e-3f * (float)k;
         for (int it = 0; it < iters; ++it)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) acc[k] = fmaf(acc[k], a, b);
+            for (int k = 0; k < NA; ++k) acc[k] = fmaf(acc[k], a, b);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s += acc[k];
+        for (int k = 0; k < NA; ++k) s += acc[k];
+    } else if constexpr (KIND == 4) {
+        floatx16 acc[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[k][j] = 0.f;
+        bf16x8 av, bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            av[e] = (__bf16)(a + (float)e);
+            bv[e] = (__bf16)(b - (float)e);
+        }
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int k = 0; k < NA; ++k) acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[k], 0, 0, 0);
+#pragma unroll
+        for (int k = 0; k < NA; ++k) s += acc[k][0] + acc[k][15];
     } else {
-        floatx4 acc[8];
+        floatx4 acc[NA];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < NA; ++k) acc[k] = floatx4{0.f, 0.f, 0.f, 0.f};
         if constexpr (KIND == 2) {
             bf16x8 av, bv;
 #pragma unroll
@@ -95,20 +124,30 @@ __global__ __launch_bounds__(256) void k_peak_compute(int iters) {
             }
             for (int it = 0; it < iters; ++it)
 #pragma unroll
-                for (int k = 0; k < 8; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[k], 0, 0, 0);
+                for (int k = 0; k < NA; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[k], 0, 0, 0);
         } else {
             for (int it = 0; it < iters; ++it)
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
+                for (int k = 0; k < NA; ++k) {
                     if constexpr (KIND == 0) acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[k], 0, 0, 0);
                     else acc[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc[k], 0, 0, 0);
                 }
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s += (acc[k][0] + acc[k][1]) + (acc[k][2] + acc[k][3]);
+        for (int k = 0; k < NA; ++k) s += (acc[k][0] + acc[k][1]) + (acc[k][2] + acc[k][3]);
     }
     if (s == kNever) g_peak_sink = s;
+    if (clk) {
+        const uint64_t c1 = __builtin_amdgcn_s_memtime(), r1 = __builtin_amdgcn_s_memrealtime();
+        g_peak_clk[0] = c0;
+        g_peak_clk[1] = c1;
+        g_peak_clk[2] = r0;
+        g_peak_clk[3] = r1;
+    }
 }
+
+// independent accumulators per wave of each kind
+int compute_accumulators(int kind) { return kind == 4 ? 4 : 16; }
 
 // flops of one wave-level instruction of each kind
 double compute_flops_per_instr(int kind) {
@@ -116,6 +155,7 @@ double compute_flops_per_instr(int kind) {
     case 0: return 16.0 * 16 * 4 * 2;
     case 1: return 4.0 * 4 * 1 * 16 * 2;
     case 2: return 16.0 * 16 * 32 * 2;
+    case 4: return 32.0 * 32 * 16 * 2;
     default: return 64.0 * 2;
     }
 }
@@ -185,9 +225,10 @@ hmc_status hmc_peak_memory(void* buf, size_t bytes, int32_t mode, int32_t passes
     return HMC_OK;
 }
 
-hmc_status hmc_peak_compute(int32_t kind, int32_t iters, int32_t reps, void* hip_stream, double* tflops) {
+hmc_status hmc_peak_compute(int32_t kind, int32_t iters, int32_t reps, void* hip_stream, double* tflops,
+                            double* clock_mhz) {
     if (!tflops) return fail(HMC_E_INVALID, "tflops must not be NULL");
-    if (kind < 0 || kind > 3) return fail(HMC_E_INVALID, "kind must be 0..3");
+    if (kind < 0 || kind > 4) return fail(HMC_E_INVALID, "kind must be 0..4");
     if (iters < 1 || reps < 1) return fail(HMC_E_INVALID, "iters and reps must be >= 1");
     hipStream_t s = (hipStream_t)hip_stream;
     const dim3 grid(256 * 8), block(256);      // 8 waves per SIMD
@@ -197,12 +238,19 @@ hmc_status hmc_peak_compute(int32_t kind, int32_t iters, int32_t reps, void* hip
     case 0: st = time_launches([&] { hipLaunchKernelGGL(k_peak_compute<0>, grid, block, 0, s, iters); }, reps, s, &ms); break;
     case 1: st = time_launches([&] { hipLaunchKernelGGL(k_peak_compute<1>, grid, block, 0, s, iters); }, reps, s, &ms); break;
     case 2: st = time_launches([&] { hipLaunchKernelGGL(k_peak_compute<2>, grid, block, 0, s, iters); }, reps, s, &ms); break;
-    default: st = time_launches([&] { hipLaunchKernelGGL(k_peak_compute<3>, grid, block, 0, s, iters); }, reps, s, &ms); break;
+    case 3: st = time_launches([&] { hipLaunchKernelGGL(k_peak_compute<3>, grid, block, 0, s, iters); }, reps, s, &ms); break;
+    default: st = time_launches([&] { hipLaunchKernelGGL(k_peak_compute<4>, grid, block, 0, s, iters); }, reps, s, &ms); break;
     }
     if (st != HMC_OK) return st;
     const double waves = (double)grid.x * (block.x / 64);
-    const double flops = waves * iters * 8.0 * compute_flops_per_instr(kind) * reps;
+    const double flops = waves * iters * (double)compute_accumulators(kind) * compute_flops_per_instr(kind) * reps;
     *tflops = flops / (ms * 1e-3) / 1e12;
+    if (clock_mhz) {
+        uint64_t c[4] = {0, 0, 0, 0};
+        const hipError_t e = hipMemcpyFromSymbol(c, HIP_SYMBOL(g_peak_clk), sizeof(c), 0, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail(HMC_E_DEVICE, hipGetErrorString(e));
+        *clock_mhz = c[3] > c[2] ? 100.0 * (double)(c[1] - c[0]) / (double)(c[3] - c[2]) : 0.0;
+    }
     return HMC_OK;
 }
 
