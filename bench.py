@@ -606,6 +606,9 @@ def bench_peaks():
                        (4, "bf16_mfma_32x32x16"), (3, "fp32_fma_vector_unpacked")):
         comp[name], clock[name] = hmc.hmc_peak_compute(kind, 10000 if kind in (0, 1, 3) else 2500, 5, st,
                                                        with_clock=True)
+    # one wave per SIMD, the occupancy of the BF16 gradient kernel (its accumulators fill the register file)
+    comp["bf16_mfma_16x16x32_one_wave_per_simd"] = hmc.hmc_peak_compute(2, 20000, 5, st, waves_per_simd=1)
+    comp["bf16_mfma_32x32x16_one_wave_per_simd"] = hmc.hmc_peak_compute(4, 20000, 5, st, waves_per_simd=1)
     out["compute_TFLOPs"] = comp
     out["shader_clock_MHz"] = clock
     return out

@@ -471,8 +471,9 @@ hmc_status hmc_server_destroy(hmc_server* srv);
 hmc_status hmc_peak_memory(void* buf, size_t bytes, int32_t mode, int32_t passes, int32_t reps, void* hip_stream,
                            double* gbytes_per_s);
 
-/* Issue rate of one instruction kind, eight waves per SIMD, iters iterations
- * per launch of one instruction on each of the wave's independent accumulators
+/* Issue rate of one instruction kind at waves_per_simd (1..8) waves per SIMD
+ * (256 x waves_per_simd workgroups of 4 waves), iters iterations per launch of
+ * one instruction on each of the wave's independent accumulators
  * (16, or 4 for kind 4): kind 0 v_mfma_f32_16x16x4f32 (2048 flop per wave
  * instruction), 1 v_mfma_f32_4x4x1f32 (16 blocks, 512), 2
  * v_mfma_f32_16x16x32_bf16 (16384), 3 v_fma_f32 (128; the library is built
@@ -481,8 +482,8 @@ hmc_status hmc_peak_memory(void* buf, size_t bytes, int32_t mode, int32_t passes
  * *tflops in 1e12 flop/s.  clock_mhz (may be NULL): the shader clock of one
  * wave over the last launch, from its clock counter against the 100 MHz
  * real-time counter. */
-hmc_status hmc_peak_compute(int32_t kind, int32_t iters, int32_t reps, void* hip_stream, double* tflops,
-                            double* clock_mhz);
+hmc_status hmc_peak_compute(int32_t kind, int32_t waves_per_simd, int32_t iters, int32_t reps, void* hip_stream,
+                            double* tflops, double* clock_mhz);
 
 #ifdef __cplusplus
 }

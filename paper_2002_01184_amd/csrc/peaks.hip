@@ -225,13 +225,14 @@ hmc_status hmc_peak_memory(void* buf, size_t bytes, int32_t mode, int32_t passes
     return HMC_OK;
 }
 
-hmc_status hmc_peak_compute(int32_t kind, int32_t iters, int32_t reps, void* hip_stream, double* tflops,
-                            double* clock_mhz) {
+hmc_status hmc_peak_compute(int32_t kind, int32_t waves_per_simd, int32_t iters, int32_t reps, void* hip_stream,
+                            double* tflops, double* clock_mhz) {
     if (!tflops) return fail(HMC_E_INVALID, "tflops must not be NULL");
     if (kind < 0 || kind > 4) return fail(HMC_E_INVALID, "kind must be 0..4");
+    if (waves_per_simd < 1 || waves_per_simd > 8) return fail(HMC_E_INVALID, "waves_per_simd must be 1..8");
     if (iters < 1 || reps < 1) return fail(HMC_E_INVALID, "iters and reps must be >= 1");
     hipStream_t s = (hipStream_t)hip_stream;
-    const dim3 grid(256 * 8), block(256);      // 8 waves per SIMD
+    const dim3 grid(256 * waves_per_simd), block(256);      // a workgroup of 4 waves per CU per wave per SIMD
     double ms = 0.0;
     hmc_status st;
     switch (kind) {

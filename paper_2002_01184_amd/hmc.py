@@ -184,8 +184,8 @@ def lib():
     L.hmc_peak_memory.argtypes = [vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                   ctypes.POINTER(ctypes.c_double)]
     L.hmc_peak_memory.restype = st
-    L.hmc_peak_compute.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double),
-                                   ctypes.POINTER(ctypes.c_double)]
+    L.hmc_peak_compute.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.hmc_peak_compute.restype = st
     _lib = L
     return L
@@ -342,12 +342,12 @@ def hmc_peak_memory(buf, nbytes: int, mode: int, passes: int, reps: int, stream)
     return r.value
 
 
-def hmc_peak_compute(kind: int, iters: int, reps: int, stream, with_clock: bool = False):
+def hmc_peak_compute(kind: int, iters: int, reps: int, stream, with_clock: bool = False, waves_per_simd: int = 8):
     """TFLOP/s of one instruction kind (0 FP32 MFMA 16x16x4, 1 FP32 MFMA 4x4x1, 2 BF16 MFMA 16x16x32, 3 FP32 FMA,
-    4 BF16 MFMA 32x32x16);
+    4 BF16 MFMA 32x32x16) at waves_per_simd waves per SIMD;
     with_clock: (TFLOP/s, shader clock in MHz during the last launch)."""
     r, mhz = ctypes.c_double(0.0), ctypes.c_double(0.0)
-    _check(lib().hmc_peak_compute(kind, iters, reps, stream, ctypes.byref(r), ctypes.byref(mhz)))
+    _check(lib().hmc_peak_compute(kind, waves_per_simd, iters, reps, stream, ctypes.byref(r), ctypes.byref(mhz)))
     return (r.value, mhz.value) if with_clock else r.value
 
 
