@@ -118,3 +118,19 @@ def test_noalloc_rejects_without_device_work():
     with pytest.raises(hmc.HMCError) as e:
         hmc.hmc_sample_chain_noalloc(_target(), _config(), fake, [1.5], -1, 10, None, None, None, None, None, None)
     assert e.value.status == hmc.HMC_E_INVALID
+
+
+def test_peak_helpers_reject_bad_arguments():
+    st = hmc.lib().hmc_peak_compute
+    out = ctypes.c_double(0.0)
+    assert st(9, 8, 10, 1, None, ctypes.byref(out), None) == hmc.HMC_E_INVALID          # kind
+    assert st(0, 0, 10, 1, None, ctypes.byref(out), None) == hmc.HMC_E_INVALID          # waves per SIMD
+    assert st(0, 9, 10, 1, None, ctypes.byref(out), None) == hmc.HMC_E_INVALID
+    assert st(0, 8, 0, 1, None, ctypes.byref(out), None) == hmc.HMC_E_INVALID           # iterations
+    assert st(0, 8, 10, 1, None, None, None) == hmc.HMC_E_INVALID                        # output
+    mem = hmc.lib().hmc_peak_memory
+    assert mem(None, 1 << 20, 0, 1, 1, None, ctypes.byref(out)) == hmc.HMC_E_INVALID      # buffer
+    assert mem(ctypes.c_void_p(16), 1 << 20, 2, 1, 1, None, ctypes.byref(out)) == hmc.HMC_E_INVALID   # mode
+    assert mem(ctypes.c_void_p(8), 1 << 20, 0, 1, 1, None, ctypes.byref(out)) == hmc.HMC_E_INVALID    # alignment
+    assert mem(ctypes.c_void_p(16), 1 << 20, 1, 2, 1, None, ctypes.byref(out)) == hmc.HMC_E_INVALID   # copy passes
+    assert mem(ctypes.c_void_p(16), 8, 0, 1, 1, None, ctypes.byref(out)) == hmc.HMC_E_INVALID         # size
