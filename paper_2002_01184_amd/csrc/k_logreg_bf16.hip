@@ -198,8 +198,13 @@ __device__ __forceinline__ void lb_load_theta(const PlainArgs& a, const float* _
 // ---------------------------------------------------------------------------
 template <int KS>
 struct LbGrad {
-    static constexpr int CS = KS <= 8 ? 4 : 2;            // 16-chain tiles per wave
-    static constexpr int CT = LB_NW * 16 * CS;            // chains per workgroup
+    // waves per workgroup and 16-chain tiles per wave: from D = 33 to 256 eight waves of
+    // 32 chains (two waves per SIMD, so that one's residual work overlaps the other's
+    // MFMAs); up to D = 32, whose sub-tile has too few copies for eight waves, four of
+    // 64; beyond D = 256 four of 32 (theta and G^T of wider chains fill the registers)
+    static constexpr int NW = KS >= 2 && KS <= 8 ? 8 : 4;
+    static constexpr int CS = KS == 1 ? 4 : 2;
+    static constexpr int CT = NW * 16 * CS;               // chains per workgroup
     static constexpr int NBX = KS <= 8 ? 4 : 2;           // X buffers
     static constexpr int NBT = NBX + 1;                   // X^T buffers
     static constexpr int PF = NBX - 1;                    // sub-tiles copied ahead
@@ -208,7 +213,7 @@ struct LbGrad {
     static constexpr int XB = LB_RS * DP * 2;             // bytes of an X (or X^T) sub-tile
     static constexpr int TBY = XB + (YLDS ? LD_YB : 0);   // X^T sub-tile + labels
     static constexpr int XI = XB / 1024;                  // 1 KB copy blocks of a tile
-    static constexpr int JW = (2 * XI) / LB_NW;           // tile copies per wave
+    static constexpr int JW = (2 * XI) / NW;              // tile copies per wave
     static constexpr int J = JW + (YLDS ? 1 : 0);         // copy instructions per wave and sub-tile
     static constexpr int LDS = NBX * XB + NBT * TBY;
 };
@@ -219,8 +224,8 @@ __device__ __forceinline__ void lr16_grad_body(const PlainArgs& a, const float* 
                                                int nsplit, int blk) {
     using P = LbGrad<KS>;
     constexpr int CS = P::CS, CT = P::CT, NT = 2 * KS, DP = P::DP, XB = P::XB, TBY = P::TBY, XI = P::XI;
-    constexpr int JW = P::JW, J = P::J, PF = P::PF, NBX = P::NBX, NBT = P::NBT;
-    static_assert((2 * XI) % LB_NW == 0, "copies must split evenly over the waves");
+    constexpr int JW = P::JW, J = P::J, PF = P::PF, NBX = P::NBX, NBT = P::NBT, NW = P::NW;
+    static_assert((2 * XI) % NW == 0, "copies must split evenly over the waves");
     static_assert(P::LDS <= 160 * 1024, "LDS");
     extern __shared__ __align__(16) uint8_t ldsb[];
     uint8_t* xring = ldsb;                      // [NBX][XB]
@@ -262,12 +267,13 @@ __device__ __forceinline__ void lr16_grad_body(const PlainArgs& a, const float* 
         int ln = lane;
         asm volatile("" : "+v"(ln));
         const uint32_t toff = (uint32_t)(ln >> 2) * (uint32_t)NP * 2u + 16u * (uint32_t)((ln & 3) ^ ((ln >> 3) & 3));
-        // with SR dividing 64 the row of lane ln in copy k is A + (256 / SR) k, A below
-        // (A < 8 for SR >= 32), and its swizzle depends on k only through bit 3 of the
-        // row: bit 0 of k when SR = 32, bit 1 of k when SR = 64, no bit of k for smaller
-        // SR -- two offsets per sub-tile
+        // with SR dividing 64 the row of lane ln in copy k is A + (64 NW / SR) k, A below,
+        // with no carry from A's low bits into bit 3, so its swizzle depends on k only
+        // through bit 3 of (64 NW / SR) k -- two offsets per sub-tile
         constexpr int SR = DP / 8;
         constexpr bool POW2 = (64 % SR) == 0;
+        constexpr int KSTR = 64 * NW / SR;
+        static_assert(!POW2 || KSTR % 8 == 0 || (KSTR == 4 && NW == 4), "row stride of the copies");
         uint32_t xo[2] = {0u, 0u};
         if constexpr (POW2) {
             const int arow = (64 / SR) * w + ln / SR;
@@ -279,12 +285,12 @@ __device__ __forceinline__ void lr16_grad_body(const PlainArgs& a, const float* 
         }
 #pragma unroll
         for (int k = 0; k < JW; ++k) {
-            const int i = w + LB_NW * k;
-            const bool isx = (XI % LB_NW == 0) ? (k < XI / LB_NW) : (i < XI);
+            const int i = w + NW * k;
+            const bool isx = (XI % NW == 0) ? (k < XI / NW) : (i < XI);
             if (isx) {
                 if constexpr (POW2)
                     __builtin_amdgcn_global_load_lds((const void*)(xsrc_t + (uint32_t)i * 1024u +
-                                                                   xo[SR == 32 ? (k & 1) : SR == 64 ? ((k >> 1) & 1) : 0]),
+                                                                   xo[((KSTR * k) >> 3) & 1]),
                                                      (lds_void_t*)(xbase + i * 1024), 16, 0, 0);
                 else
                     lb_copy_x_block<KS>(xsrc_t, xbase, i, ln);
@@ -652,7 +658,7 @@ __device__ __forceinline__ void lr16_lp_sum_body(const PlainArgs& a, int nsplit,
 }
 
 template <int KS>
-__global__ __launch_bounds__(256) void k_lr16_grad_pipe(PlainArgs a, const float* __restrict__ xsrc,
+__global__ __launch_bounds__(64 * LbGrad<KS>::NW) void k_lr16_grad_pipe(PlainArgs a, const float* __restrict__ xsrc,
                                                         const float* __restrict__ psrc, int drift,
                                                         int64_t rows_per_split, int nsplit) {
     lr16_grad_body<KS>(a, xsrc, psrc, drift, rows_per_split, nsplit, blockIdx.x);
@@ -674,7 +680,7 @@ __global__ __launch_bounds__(256) void k_lr16_lp_sum(PlainArgs a, int nsplit) { 
 // request computes bitwise what it computes alone.
 // ---------------------------------------------------------------------------
 template <int KS>
-__global__ __launch_bounds__(256) void k_lr16_grad_multi(const Lr16Job* __restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(64 * LbGrad<KS>::NW) void k_lr16_grad_multi(const Lr16Job* __restrict__ jobs, int njobs) {
     int64_t lb;
     const int j = lr16_job_of(jobs, njobs, LR16_KIND_GRAD, blockIdx.x, &lb);
     if (j < 0) return;
@@ -788,8 +794,8 @@ static hipError_t lb_grad_k(const PlainArgs& a, const float* x, const float* p, 
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_lr16_grad_pipe<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-    hipLaunchKernelGGL(k_lr16_grad_pipe<KS>, dim3((unsigned)(ntile * nsplit)), dim3(256), lds, s, a, x, p, drift,
-                       rows_for(NP, nsplit), nsplit);
+    hipLaunchKernelGGL(k_lr16_grad_pipe<KS>, dim3((unsigned)(ntile * nsplit)), dim3(64 * P::NW), lds, s, a, x, p,
+                       drift, rows_for(NP, nsplit), nsplit);
     return hipGetLastError();
 }
 
@@ -835,7 +841,7 @@ static hipError_t lb_multi_k(int kind, const Lr16Job* jobs, int njobs, int64_t b
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void*)k_lr16_grad_multi<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds);
-        hipLaunchKernelGGL(k_lr16_grad_multi<KS>, grid, dim3(256), lds, s, jobs, njobs);
+        hipLaunchKernelGGL(k_lr16_grad_multi<KS>, grid, dim3(64 * LbGrad<KS>::NW), lds, s, jobs, njobs);
     } else if (kind == LR16_KIND_LOGP) {
         const size_t lds = (size_t)LbLogp<KS>::LDS;
         if (lds > 65536)
