@@ -481,23 +481,24 @@ __device__ __forceinline__ void lr16_grad_body(const PlainArgs& a, const float* 
 
 // ---------------------------------------------------------------------------
 // Accurate log-probability partials: theta = hi + mid + lo (three BF16 terms,
-// smallest first), 16 CS chains per wave (CS = 2, or 1 beyond D = 256 where
-// three terms of two tiles would not fit the registers), each X fragment
-// feeding 3 CS MFMAs; the softplus terms summed per chain in FP64.  Pipelined
+// smallest first), 16 chains per wave, each X fragment feeding 3 MFMAs; the
+// softplus terms summed per chain in FP64.  Pipelined
 // like the gradient: the softplus of one 16-row half is computed while the
 // fragments of the next half arrive and before its MFMAs.  X tiles (with their
 // labels) in a ring of four buffers, copies three sub-tiles ahead.
 // ---------------------------------------------------------------------------
 template <int KS>
 struct LbLogp {
-    static constexpr int CS = KS <= 8 ? 2 : 1;
-    static constexpr int CT = LB_NW * 16 * CS;
+    // up to D = 256 eight waves of 16 chains (two waves per SIMD), beyond four
+    static constexpr int NW = KS <= 8 ? 8 : 4;
+    static constexpr int CS = 1;
+    static constexpr int CT = NW * 16 * CS;
     static constexpr int NB = 4;
     static constexpr int DP = 32 * KS;
     static constexpr int XB = LB_RS * DP * 2;
     static constexpr int BUF = XB + LD_YB;
     static constexpr int XI = XB / 1024;
-    static constexpr int JW = (XI + LB_NW - 1) / LB_NW;   // X copy instructions per wave (a wave may repeat one)
+    static constexpr int JW = (XI + NW - 1) / NW;         // X copy instructions per wave (a wave may repeat one)
     static constexpr int J = JW + 1;                      // plus the labels
     static constexpr int LDS = NB * BUF;
 };
@@ -553,7 +554,7 @@ __device__ __forceinline__ void lr16_logp_body(const PlainArgs& a, const float* 
         asm volatile("" : "+v"(ln));
 #pragma unroll
         for (int k = 0; k < JW; ++k) {
-            int i = w + LB_NW * k;
+            int i = w + P::NW * k;
             if (i >= XI) i = XI - 1;          // a repeated copy keeps the count equal over the waves
             lb_copy_x_block<KS>(xsrc_t, base, i, ln);
         }
@@ -665,7 +666,7 @@ __global__ __launch_bounds__(64 * LbGrad<KS>::NW) void k_lr16_grad_pipe(PlainArg
 }
 
 template <int KS>
-__global__ __launch_bounds__(256) void k_lr16_logp_pipe(PlainArgs a, const float* __restrict__ xsrc,
+__global__ __launch_bounds__(64 * LbLogp<KS>::NW) void k_lr16_logp_pipe(PlainArgs a, const float* __restrict__ xsrc,
                                                         int64_t rows_per_split, int nsplit) {
     lr16_logp_body<KS>(a, xsrc, rows_per_split, nsplit, blockIdx.x);
 }
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(64 * LbGrad<KS>::NW) void k_lr16_grad_multi(const L
 }
 
 template <int KS>
-__global__ __launch_bounds__(256) void k_lr16_logp_multi(const Lr16Job* __restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(64 * LbLogp<KS>::NW) void k_lr16_logp_multi(const Lr16Job* __restrict__ jobs, int njobs) {
     int64_t lb;
     const int j = lr16_job_of(jobs, njobs, LR16_KIND_LOGP, blockIdx.x, &lb);
     if (j < 0) return;
@@ -809,7 +810,7 @@ static hipError_t lb_logp_k(const PlainArgs& a, const float* x, hipStream_t s) {
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_lr16_logp_pipe<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-    hipLaunchKernelGGL(k_lr16_logp_pipe<KS>, dim3((unsigned)(ntile * nsplit)), dim3(256), lds, s, a, x,
+    hipLaunchKernelGGL(k_lr16_logp_pipe<KS>, dim3((unsigned)(ntile * nsplit)), dim3(64 * P::NW), lds, s, a, x,
                        rows_for(NP, nsplit), nsplit);
     hipLaunchKernelGGL(k_lr16_lp_sum, dim3((unsigned)((a.C + 255) / 256)), dim3(256), 0, s, a, nsplit);
     return hipGetLastError();
@@ -847,7 +848,7 @@ static hipError_t lb_multi_k(int kind, const Lr16Job* jobs, int njobs, int64_t b
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void*)k_lr16_logp_multi<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds);
-        hipLaunchKernelGGL(k_lr16_logp_multi<KS>, grid, dim3(256), lds, s, jobs, njobs);
+        hipLaunchKernelGGL(k_lr16_logp_multi<KS>, grid, dim3(64 * LbLogp<KS>::NW), lds, s, jobs, njobs);
     } else {
         hipLaunchKernelGGL(k_lr16_lp_sum_multi, grid, dim3(256), 0, s, jobs, njobs);
     }
