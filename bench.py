@@ -731,8 +731,8 @@ def main():
 # BF16, 8192 chains, L = 10), its gradients on BF16 MFMA.  A timed step is one
 # block of 25 adapted burn-in + 25 kept transitions from the seeded start.
 DEFAULT_CONFIG = "logreg_100000x256"
-DEFAULT_TRANSITIONS = {"logreg_100000x256": 50}
-BF16_X_CONFIGS = ("logreg_100000x256",)      # workloads whose X is stored in BF16 (D <= 512)
+DEFAULT_TRANSITIONS = {"logreg_100000x256": 50, "logreg_100000x512": 20}
+BF16_X_CONFIGS = ("logreg_100000x256", "logreg_100000x512")      # workloads whose X is stored in BF16 (D <= 512)
 
 
 def cpu_model():

@@ -198,12 +198,12 @@ __device__ __forceinline__ void lb_load_theta(const PlainArgs& a, const float* _
 // ---------------------------------------------------------------------------
 template <int KS>
 struct LbGrad {
-    // waves per workgroup and 16-chain tiles per wave: from D = 33 to 256 eight waves of
-    // 32 chains (two waves per SIMD, so that one's residual work overlaps the other's
-    // MFMAs); up to D = 32, whose sub-tile has too few copies for eight waves, four of
-    // 64; beyond D = 256 four of 32 (theta and G^T of wider chains fill the registers)
-    static constexpr int NW = KS >= 2 && KS <= 8 ? 8 : 4;
-    static constexpr int CS = KS == 1 ? 4 : 2;
+    // waves per workgroup and 16-chain tiles per wave: eight waves (two per SIMD, so that
+    // one's residual work overlaps the other's MFMAs) of 32 chains from D = 33 to 256 and
+    // of 16 beyond (theta and G^T of wider chains fill the registers); up to D = 32, whose
+    // sub-tile has too few copies for eight waves, four of 64
+    static constexpr int NW = KS >= 2 ? 8 : 4;
+    static constexpr int CS = KS == 1 ? 4 : (KS <= 8 ? 2 : 1);
     static constexpr int CT = NW * 16 * CS;               // chains per workgroup
     static constexpr int NBX = KS <= 8 ? 4 : 2;           // X buffers
     static constexpr int NBT = NBX + 1;                   // X^T buffers

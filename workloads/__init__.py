@@ -182,6 +182,12 @@ def cfg_logreg_100000x256():
                   init=0.05)
 
 
+def cfg_logreg_100000x512():
+    # the widest logistic request of the served stream (D up to 512), 4096 chains
+    return logreg(100000, 512, 4096, L=10, step_size=0.003, burnin=1000, results=1000, bf16=True,
+                  init=0.05)
+
+
 # Wide shapes of the element-wise targets, for the HBM roofline of the plain step:
 # the paper's 1-D example at 2^24 chains (FP64) and a diagonal Gaussian D=1000
 # (variances 1e-2..1e2) with 16384 chains (FP32).
@@ -203,6 +209,7 @@ CONFIGS = {
     "logreg_10000x25": cfg_logreg_10000x25,
     "gauss_dense_100": cfg_gauss_dense_100,
     "logreg_100000x256": cfg_logreg_100000x256,
+    "logreg_100000x512": cfg_logreg_100000x512,
 }
 
 
