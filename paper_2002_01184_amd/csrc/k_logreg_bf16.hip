@@ -489,8 +489,8 @@ __device__ __forceinline__ void lr16_grad_body(const PlainArgs& a, const float* 
 // ---------------------------------------------------------------------------
 template <int KS>
 struct LbLogp {
-    // up to D = 256 eight waves of 16 chains (two waves per SIMD), beyond four
-    static constexpr int NW = KS <= 8 ? 8 : 4;
+    // eight waves of 16 chains (two waves per SIMD)
+    static constexpr int NW = 8;
     static constexpr int CS = 1;
     static constexpr int CT = NW * 16 * CS;
     static constexpr int NB = 4;
