@@ -17,11 +17,11 @@
 // in X: they add nothing to S or G (their residuals multiply zeros), and the
 // log-probability pass skips rows >= N.
 //
-// Work decomposition: a workgroup (4 waves) owns 64 CS chains and a chunk of
-// rows; each wave computes S and G^T for its own 16 CS chains, so the residuals
-// never leave registers.  theta (drifted) stays in VGPRs as the B operands of
-// the first contraction, the G^T accumulators in AGPRs; every LDS operand
-// fragment feeds CS MFMAs.  32-row sub-tiles of X and X^T are copied global ->
+// Work decomposition: a workgroup (NW waves) owns 16 NW CS chains and a chunk
+// of rows; each wave computes S and G^T for its own 16 CS chains, so the
+// residuals never leave registers.  theta (drifted) stays in registers as the B
+// operands of the first contraction, beside the G^T accumulators; every LDS
+// operand fragment feeds CS MFMAs.  32-row sub-tiles of X and X^T are copied global ->
 // LDS by the load-to-LDS instructions (global_load_lds_dwordx4: lane i of an
 // instruction writes bytes 16 i .. 16 i + 15 of a 1 KB block) into rings of
 // buffers, a few sub-tiles ahead, with no staging registers; the barrier
@@ -179,10 +179,10 @@ __device__ __forceinline__ void lb_load_theta(const PlainArgs& a, const float* _
 }
 
 // ---------------------------------------------------------------------------
-// Gradient partials, software-pipelined: 16 CS chains per wave (CS = 4 up to
-// D = 256, so at 8192 chains 32 chain tiles x 8 row splits = one workgroup per
-// CU with each split on its own XCD; CS = 2 beyond, where four tiles of theta
-// and of G^T would not fit the registers).  The residuals of one sub-tile are
+// Gradient partials, software-pipelined: 16 CS chains per wave, NW waves per
+// workgroup (LbGrad: 256 chains per workgroup up to D = 256, so at 8192 chains
+// 32 chain tiles x 8 row splits = one workgroup per CU with each split on its
+// own XCD; two waves per SIMD from D = 33 on).  The residuals of one sub-tile are
 // formed on the vector ALUs while the matrix cores run the other contraction,
 // in three phases per sub-tile s:
 //   1. the X fragments of rows 0..15 of s are read, the residuals of rows
