@@ -867,25 +867,36 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
 // chain waits for the 15 others of its tile only, and there is one launch for
 // the whole run.  A chain's sums over its dims (energies, U-turn products)
 // are reduced across its 16 lane positions by shuffles and one LDS exchange;
-// every reduction and vote sits where the control flow is uniform across the
+// every reduction sits where the control flow is uniform across the
 // workgroup (their count depends on the leaf index only).  The trajectory
 // ends, the levels' parked first leaves and candidates and the doubling's
 // candidate live in the NutsWs buffers, each lane touching only its own dims,
-// except the parked records of the shallow levels 1 .. ND_LV (the merges of
-// all but 1 / 2^ND_LV of the leaves), which sit in LDS: with one wave per
-// SIMD a global read there is latency nothing hides.
+// except the parked records of the shallow levels (the merges of all but a
+// few of the leaves), which sit in LDS: a global read there is latency that
+// nothing hides.  Every wave holds all 16 chains, so whether any chain of the
+// tile is still running is a wave-local ballot (every wave computes the same
+// flags from the same sums and random numbers); a leaf costs two barriers,
+// the drifted x and one reduction that carries the leaf's energies and every
+// U-turn check ending at it.
 // Same tree, uniforms and arithmetic order per lane as the lockstep kernels
 // up to the order of the FP64 sums.
 // ---------------------------------------------------------------------------
 constexpr int ND_NW = 8;                    // waves per workgroup (2 per SIMD)
 constexpr int ND_LDS_MAX = 163840;          // LDS bytes of a gfx950 workgroup
-constexpr int ND_RV = 2;                    // values per chain in one reduction
+constexpr int ND_RV = 2;                    // values per chain in a per-transition / per-doubling reduction
+constexpr int ND_LV = 2 * NUTS_MAXD;        // values per chain in a leaf's reduction: the two energies and
+                                            // the two U-turn products of each subtree that ends at the leaf
+constexpr int ND_LRS = 10;                  // doubles per (value, chain) row of the leaf reduction: the 8
+                                            // waves' partials, padded so 16 chains' rows hit distinct banks
 
 template <int NT>
 constexpr int nd_xs() { return 16 * NT + 4; }
-// LDS bytes before the level records: x staging, reductions, votes
+// LDS bytes before the level records: x staging, the leaf reduction, the
+// other reductions
 template <int NT>
-constexpr int nd_fixed_bytes() { return 2 * 16 * nd_xs<NT>() * 4 + 2 * ND_RV * ND_NW * 16 * 8 + 2 * 16 * 4; }
+constexpr int nd_fixed_bytes() {
+    return 16 * nd_xs<NT>() * 4 + ND_LV * 16 * ND_LRS * 8 + 2 * ND_RV * ND_NW * 16 * 8;
+}
 // levels whose records (first leaf x, r; candidate x, g of 16 chains) fit in LDS
 template <int NT>
 constexpr int nd_lds_levels() {
@@ -895,29 +906,32 @@ constexpr int nd_lds_levels() {
 template <int NT>
 constexpr int nd_lds_bytes() { return nd_fixed_bytes<NT>() + nd_lds_levels<NT>() * 4 * 16 * nd_xs<NT>() * 4; }
 
-// Sums over each chain's dims of NV values, returned to every lane of the
-// chain: two shuffles over the chain's 4 lane rows, then the 4 waves' partials
-// through LDS (parity rk alternates the buffer, so one barrier suffices).
+// Sums over each chain's dims of the first nv (<= NV, the same for the whole
+// workgroup) of sv's values, returned to every lane of the chain: two
+// shuffles over the chain's 4 lane rows, then the waves' partials through the
+// LDS buffer rb (one barrier; the caller makes sure no wave still reads rb
+// from the previous use).
 template <int NV>
-__device__ __forceinline__ void nd_chain_sum(double* sv, double* red, int& rk, int w, int g4, int i16) {
-    double* rb = red + (rk & 1) * (ND_RV * ND_NW * 16);
+__device__ __forceinline__ void nd_chain_sum(double* sv, int nv, double* rb, int w, int g4, int i16) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        sv[q] += __shfl_xor(sv[q], 16, 64);
-        sv[q] += __shfl_xor(sv[q], 32, 64);
-    }
+    for (int q = 0; q < NV; ++q)
+        if (q < nv) {
+            sv[q] += __shfl_xor(sv[q], 16, 64);
+            sv[q] += __shfl_xor(sv[q], 32, 64);
+        }
     if (g4 == 0)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) rb[(q * ND_NW + w) * 16 + i16] = sv[q];
+        for (int q = 0; q < NV; ++q)
+            if (q < nv) rb[(q * ND_NW + w) * 16 + i16] = sv[q];
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        double acc = 0.0;
+    for (int q = 0; q < NV; ++q)
+        if (q < nv) {
+            double acc = 0.0;
 #pragma unroll
-        for (int ww = 0; ww < ND_NW; ++ww) acc += rb[(q * ND_NW + ww) * 16 + i16];
-        sv[q] = acc;
-    }
-    ++rk;
+            for (int ww = 0; ww < ND_NW; ++ww) acc += rb[(q * ND_NW + ww) * 16 + i16];
+            sv[q] = acc;
+        }
 }
 
 template <int NT, bool ST>
@@ -935,11 +949,10 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
     const int64_t c = (int64_t)blockIdx.x * 16 + i16;
     const bool cvalid = c < C;
     const int64_t cc = cvalid ? c : 0;
-    float* xs0 = lds;
-    float* xs1 = lds + 16 * XS;
-    double* red = (double*)(lds + 2 * 16 * XS);          // [2 parity][ND_RV values][NW][16]
-    int* vote = (int*)(red + 2 * ND_RV * ND_NW * 16);    // [2 parity][16]
-    float* lvl = (float*)(vote + 2 * 16);                // [LV][4 records][16 chains][XS]
+    float* xs = lds;                                     // [16 chains][XS]
+    double* lred = (double*)(lds + 16 * XS);             // [ND_LV values][16 chains][ND_LRS]
+    double* red = lred + ND_LV * 16 * ND_LRS;            // [2 parity][ND_RV values][NW][16]
+    float* lvl = (float*)(red + 2 * ND_RV * ND_NW * 16); // [LV][4 records][16 chains][XS]
     const float* P = (const float*)a.tg.prec;
     float *mx = (float*)n.mx, *mr = (float*)n.mr, *mg = (float*)n.mg;
     float *px = (float*)n.px, *pr = (float*)n.pr, *pg = (float*)n.pg;
@@ -973,6 +986,14 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
     // parked records of level k (1 ..): 0 first leaf x, 1 first leaf r, 2
     // candidate x, 3 candidate g; the lane's 4 dims of tile m
     float* const grec[4] = {lfx, lfr, lcx, lcg};
+    // element offset of level k's record of this lane's chain; formed where it
+    // is used (the empty asm keeps the compiler from hoisting one 64-bit
+    // address per level and record out of the leaf loop into registers)
+    auto rec_off = [&](int k) -> int64_t {
+        int64_t off = ((int64_t)k * C + cc) * D;
+        asm volatile("" : "+v"(off));
+        return off;
+    };
     auto rec_load = [&](int k, int q, int m, float out[4]) {
         if (k <= LV) {
             const floatx4 v4 = *(const floatx4*)(lvl + (((k - 1) * 4 + q) * 16 + i16) * XS + 16 * (w + ND_NW * m) +
@@ -980,7 +1001,7 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
 #pragma unroll
             for (int v = 0; v < 4; ++v) out[v] = v4[v];
         } else {
-            const float* gp = grec[q] + ((int64_t)k * C + cc) * D;
+            const float* gp = grec[q] + rec_off(k);
 #pragma unroll
             for (int v = 0; v < 4; ++v) out[v] = ok[m][v] ? gp[dim_of(m, v)] : 0.f;
         }
@@ -990,7 +1011,7 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
             *(floatx4*)(lvl + (((k - 1) * 4 + q) * 16 + i16) * XS + 16 * (w + ND_NW * m) + 4 * g4) =
                 floatx4{in[0], in[1], in[2], in[3]};
         } else {
-            float* gp = grec[q] + ((int64_t)k * C + cc) * D;
+            float* gp = grec[q] + rec_off(k);
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 if (ok[m][v]) gp[dim_of(m, v)] = in[v];
@@ -1000,25 +1021,20 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
     double eps = a.ws.eps[cc];
     DualAvg da{};
     if (ST) da = a.ws.da[cc];
-    int buf = 0, rk = 0, vk = 0;
+    int rk = 0;
 
+    // the per-transition and per-doubling reductions alternate two buffers,
+    // so one barrier each suffices
     auto chain_sum2 = [&](double& s0, double& s1) {
         double sv[2] = {s0, s1};
-        nd_chain_sum<2>(sv, red, rk, w, g4, i16);
+        nd_chain_sum<2>(sv, 2, red + (rk & 1) * (ND_RV * ND_NW * 16), w, g4, i16);
+        ++rk;
         s0 = sv[0];
         s1 = sv[1];
     };
-    // does any chain of the tile satisfy pred (one value per chain)
-    auto tile_any = [&](bool pred) -> bool {
-        int* vb = vote + (vk & 1) * 16;
-        if (w == 0 && g4 == 0) vb[i16] = pred ? 1 : 0;
-        __syncthreads();
-        int any = 0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) any |= vb[q];
-        ++vk;
-        return any != 0;
-    };
+    // does any chain of the tile satisfy pred (one value per chain, the same
+    // in every wave)
+    auto tile_any = [&](bool pred) -> bool { return __ballot(pred ? 1 : 0) != 0ull; };
 
     for (int64_t it = 0; it < n_trans; ++it) {
         const uint32_t t = t_begin + (uint32_t)it;
@@ -1075,7 +1091,6 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
             for (int i = 0; i < nleaves; ++i) {
                 if (!tile_any(alive)) break;
                 // one leapfrog step of size dir eps for every chain of the tile
-                float* xs = buf ? xs1 : xs0;
 #pragma unroll
                 for (int m = 0; m < MT; ++m) {
 #pragma unroll
@@ -1106,20 +1121,74 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
                 }
                 __builtin_amdgcn_sched_group_barrier(0x100, NT, 0);
                 __builtin_amdgcn_sched_group_barrier(0x008, KM * MT, 0);
-                double lp = 0.0, kin = 0.0;
+                // the leaf's energies, then for each subtree that ends at this leaf
+                // (levels k = 1 .. nm: bit k-1 of i set, k <= j) the U-turn products of
+                // its first leaf (parked at level k) and this leaf: each value's lane
+                // partials go to the leaf reduction buffer as they are formed, and one
+                // barrier later the chain's sums are read where they are used
+                const int nm = min(__builtin_ctz(~(unsigned)i), j);
+                // two values' lane partials summed over the chain's 4 lane rows and
+                // stored as this wave's partials of values q, q + 1
+                auto lred_put2 = [&](int q, double v0, double v1) {
+                    v0 += __shfl_xor(v0, 16, 64);
+                    v1 += __shfl_xor(v1, 16, 64);
+                    v0 += __shfl_xor(v0, 32, 64);
+                    v1 += __shfl_xor(v1, 32, 64);
+                    if (g4 == 0) {
+                        lred[(q * 16 + i16) * ND_LRS + w] = v0;
+                        lred[((q + 1) * 16 + i16) * ND_LRS + w] = v1;
+                    }
+                };
+                auto lred_get = [&](int q) -> double {
+                    const double2* r2 = (const double2*)(lred + (q * 16 + i16) * ND_LRS);
+                    double2 pv[ND_NW / 2];
 #pragma unroll
-                for (int m = 0; m < MT; ++m)
+                    for (int h = 0; h < ND_NW / 2; ++h) pv[h] = r2[h];
+                    double acc = pv[0].x;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        wg[m][v] = -(acc[m][0][v] + acc[m][1][v]);
-                        wr[m][v] = fmaf(hse, wg[m][v], wr[m][v]);
-                        if (ok[m][v]) {
+                    for (int h = 0; h < ND_NW / 2; ++h) {
+                        if (h > 0) acc += pv[h].x;
+                        acc += pv[h].y;
+                    }
+                    return acc;
+                };
+                {
+                    double lp = 0.0, kin = 0.0;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            // dims beyond D (and chains beyond C) hold zeros
+                            wg[m][v] = -(acc[m][0][v] + acc[m][1][v]);
+                            wr[m][v] = fmaf(hse, wg[m][v], wr[m][v]);
                             kin += 0.5 * (double)wr[m][v] * (double)wr[m][v];
                             lp += 0.5 * (double)wx[m][v] * (double)wg[m][v];
                         }
+                    lred_put2(0, lp, kin);
+                }
+#pragma unroll
+                for (int k = 1; k < NUTS_MAXD; ++k) {
+                    if (k > nm) break;
+                    double dm = 0.0, dp = 0.0;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        if (!tile_ok[m]) continue;
+                        float f0[4], f1[4];
+                        rec_load(k, 0, m, f0);
+                        rec_load(k, 1, m, f1);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const double fx = (double)f0[v], fr = (double)f1[v];
+                            const double lx = (double)wx[m][v], lr = (double)wr[m][v];
+                            const double dx = dir > 0 ? lx - fx : fx - lx;
+                            dm += dx * (dir > 0 ? fr : lr);
+                            dp += dx * (dir > 0 ? lr : fr);
+                        }
                     }
-                buf ^= 1;
-                chain_sum2(lp, kin);
+                    lred_put2(2 * k, dm, dp);
+                }
+                __syncthreads();
+                const double lp = lred_get(0), kin = lred_get(1);
                 int32_t n_node = 0;
                 if (alive) {
                     wlogp = lp;
@@ -1132,52 +1201,14 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
                     n_node = (log_u <= -H) ? 1 : 0;
                     if (!(log_u < 1000.0 - H)) alive = false;
                 }
-                // the subtrees that end at leaf i: merge levels k with bit k-1 of i
-                // set, park at the first unset bit (the same k for every chain)
+                // merge the subtrees that end here (levels 1 .. nm), then park the
+                // merged tree at level nm + 1, or, at the doubling's last leaf
+                // (nm == j), keep its candidate
                 int cand = -1, first = -1;
                 double cand_lp = lp;
-                bool parked = false;
 #pragma unroll
-                for (int k = 1; k <= NUTS_MAXD; ++k) {
-                    if (k > j) break;
-                    if (((i >> (k - 1)) & 1) == 0) {
-                        if (alive) {
-#pragma unroll
-                            for (int m = 0; m < MT; ++m) {
-                                if (!tile_ok[m]) continue;
-                                float f0[4], f1[4], c0[4], c1[4];
-                                if (first < 0) {
-#pragma unroll
-                                    for (int v = 0; v < 4; ++v) {
-                                        f0[v] = wx[m][v];
-                                        f1[v] = wr[m][v];
-                                    }
-                                } else {
-                                    rec_load(first, 0, m, f0);
-                                    rec_load(first, 1, m, f1);
-                                }
-                                if (cand < 0) {
-#pragma unroll
-                                    for (int v = 0; v < 4; ++v) {
-                                        c0[v] = wx[m][v];
-                                        c1[v] = wg[m][v];
-                                    }
-                                } else {
-                                    rec_load(cand, 2, m, c0);
-                                    rec_load(cand, 3, m, c1);
-                                }
-                                rec_store(k, 0, m, f0);
-                                rec_store(k, 1, m, f1);
-                                rec_store(k, 2, m, c0);
-                                rec_store(k, 3, m, c1);
-                            }
-                            lcn[k - 1] = n_node;
-                            lclp[k - 1] = cand_lp;
-                        }
-                        parked = true;
-                        break;
-                    }
-                    double dm = 0.0, dp = 0.0;
+                for (int k = 1; k < NUTS_MAXD; ++k) {
+                    if (k > nm) break;
                     if (alive) {
                         const int32_t nl = lcn[k - 1];
                         const uint32_t block = ((uint32_t)j * 1024u + (uint32_t)i) * 16u + (uint32_t)k;
@@ -1187,28 +1218,47 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
                             cand_lp = lclp[k - 1];
                         }
                         n_node += nl;
+                    }
+                    first = k;
+                    if (alive && !(lred_get(2 * k) >= 0.0 && lred_get(2 * k + 1) >= 0.0)) alive = false;
+                }
+                if (nm < j) {
+#pragma unroll
+                    for (int k = 1; k < NUTS_MAXD; ++k) {
+                        if (k != nm + 1 || !alive) continue;
 #pragma unroll
                         for (int m = 0; m < MT; ++m) {
                             if (!tile_ok[m]) continue;
-                            float f0[4], f1[4];
-                            rec_load(k, 0, m, f0);
-                            rec_load(k, 1, m, f1);
+                            float f0[4], f1[4], c0[4], c1[4];
+                            if (first < 0) {
 #pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                if (ok[m][v]) {
-                                    const double fx = (double)f0[v], fr = (double)f1[v];
-                                    const double lx = (double)wx[m][v], lr = (double)wr[m][v];
-                                    const double dx = dir > 0 ? lx - fx : fx - lx;
-                                    dm += dx * (dir > 0 ? fr : lr);
-                                    dp += dx * (dir > 0 ? lr : fr);
+                                for (int v = 0; v < 4; ++v) {
+                                    f0[v] = wx[m][v];
+                                    f1[v] = wr[m][v];
                                 }
+                            } else {
+                                rec_load(first, 0, m, f0);
+                                rec_load(first, 1, m, f1);
+                            }
+                            if (cand < 0) {
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    c0[v] = wx[m][v];
+                                    c1[v] = wg[m][v];
+                                }
+                            } else {
+                                rec_load(cand, 2, m, c0);
+                                rec_load(cand, 3, m, c1);
+                            }
+                            rec_store(k, 0, m, f0);
+                            rec_store(k, 1, m, f1);
+                            rec_store(k, 2, m, c0);
+                            rec_store(k, 3, m, c1);
                         }
+                        lcn[k - 1] = n_node;
+                        lclp[k - 1] = cand_lp;
                     }
-                    chain_sum2(dm, dp);
-                    first = k;
-                    if (alive && !(dm >= 0.0 && dp >= 0.0)) alive = false;
-                }
-                if (!parked && alive) {     // the last leaf: every subtree of doubling j ends here
+                } else if (alive) {         // the last leaf: every subtree of doubling j ends here
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
                         if (!tile_ok[m]) continue;
