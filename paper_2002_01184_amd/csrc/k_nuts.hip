@@ -892,10 +892,10 @@ constexpr int ND_LRS = 10;                  // doubles per (value, chain) row of
 template <int NT>
 constexpr int nd_xs() { return 16 * NT + 4; }
 // LDS bytes before the level records: x staging, the leaf reduction, the
-// other reductions
+// other reductions, each level's parked leaf count and candidate logp
 template <int NT>
 constexpr int nd_fixed_bytes() {
-    return 16 * nd_xs<NT>() * 4 + ND_LV * 16 * ND_LRS * 8 + 2 * ND_RV * ND_NW * 16 * 8;
+    return 16 * nd_xs<NT>() * 4 + ND_LV * 16 * ND_LRS * 8 + 2 * ND_RV * ND_NW * 16 * 8 + NUTS_MAXD * 16 * (8 + 4);
 }
 // levels whose records (first leaf x, r; candidate x, g of 16 chains) fit in LDS
 template <int NT>
@@ -934,6 +934,25 @@ __device__ __forceinline__ void nd_chain_sum(double* sv, int nv, double* rb, int
         }
 }
 
+// Sum of v over lanes l, l ^ 16, l ^ 32, l ^ 48 (a chain's 4 lane rows),
+// exact in rows 0 (the lanes that store it): register-only lane swaps of
+// gfx950 instead of LDS permutes.  v_permlane32_swap trades the upper 32 lanes
+// of its first operand for the lower 32 of its second, so the second result
+// holds x[l + 32] in rows 0, 1; v_permlane16_swap trades the odd rows of its
+// first operand for the even rows of its second, so the second result holds
+// x[l + 16] in rows 0, 2.
+__device__ __forceinline__ double nd_rows_sum(double v) {
+    uint32_t lo = (uint32_t)__double_as_longlong(v), hi = (uint32_t)((uint64_t)__double_as_longlong(v) >> 32);
+    const auto l32 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h32 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double s = v + __longlong_as_double((long long)(((uint64_t)h32[1] << 32) | l32[1]));
+    lo = (uint32_t)__double_as_longlong(s);
+    hi = (uint32_t)((uint64_t)__double_as_longlong(s) >> 32);
+    const auto l16 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h16 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return s + __longlong_as_double((long long)(((uint64_t)h16[1] << 32) | l16[1]));
+}
+
 template <int NT, bool ST>
 __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, NutsWs n, NutsAdapt ad, uint32_t t_begin,
                                                           int64_t n_trans, int32_t max_depth, float* samples,
@@ -942,6 +961,7 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
     constexpr int KM = 4 * NT;
     constexpr int XS = nd_xs<NT>();
     constexpr int LV = nd_lds_levels<NT>();
+    static_assert(LV >= 1, "the level records need at least one LDS level");
     extern __shared__ float lds[];
     const int64_t C = a.C, D = a.tg.D;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -952,7 +972,9 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
     float* xs = lds;                                     // [16 chains][XS]
     double* lred = (double*)(lds + 16 * XS);             // [ND_LV values][16 chains][ND_LRS]
     double* red = lred + ND_LV * 16 * ND_LRS;            // [2 parity][ND_RV values][NW][16]
-    float* lvl = (float*)(red + 2 * ND_RV * ND_NW * 16); // [LV][4 records][16 chains][XS]
+    double* lclp = red + 2 * ND_RV * ND_NW * 16;         // [NUTS_MAXD levels][16]: candidate logp
+    int32_t* lcn = (int32_t*)(lclp + NUTS_MAXD * 16);    // [NUTS_MAXD levels][16]: slice leaf count
+    float* lvl = (float*)(lcn + NUTS_MAXD * 16);         // [LV][4 records][16 chains][XS]
     const float* P = (const float*)a.tg.prec;
     float *mx = (float*)n.mx, *mr = (float*)n.mr, *mg = (float*)n.mg;
     float *px = (float*)n.px, *pr = (float*)n.pr, *pg = (float*)n.pg;
@@ -1016,6 +1038,16 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
             for (int v = 0; v < 4; ++v)
                 if (ok[m][v]) gp[dim_of(m, v)] = in[v];
         }
+    };
+    // the two halves of rec_load for a level known to sit in LDS (1 .. LV; any
+    // lane may pass its own) or in global memory (lanes of dims beyond D read 0)
+    auto rec_lds = [&](int k, int q, int m) -> floatx4 {
+        return *(const floatx4*)(lvl + (((k - 1) * 4 + q) * 16 + i16) * XS + 16 * (w + ND_NW * m) + 4 * g4);
+    };
+    auto rec_glb = [&](int k, int q, int m, float out[4]) {
+        const float* gp = grec[q] + rec_off(k);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[v] = ok[m][v] ? gp[dim_of(m, v)] : 0.f;
     };
     double logp = a.ws.logp[cc];
     double eps = a.ws.eps[cc];
@@ -1083,8 +1115,6 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
                 alpha = 0.0;
                 n_alpha = 0;
             }
-            int32_t lcn[NUTS_MAXD];
-            double lclp[NUTS_MAXD];
             double rclp = 0.0;
             int32_t rcn = 0;
             const int nleaves = 1 << j;
@@ -1128,12 +1158,10 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
                 // barrier later the chain's sums are read where they are used
                 const int nm = min(__builtin_ctz(~(unsigned)i), j);
                 // two values' lane partials summed over the chain's 4 lane rows and
-                // stored as this wave's partials of values q, q + 1
+                // stored (from row 0) as this wave's partials of values q, q + 1
                 auto lred_put2 = [&](int q, double v0, double v1) {
-                    v0 += __shfl_xor(v0, 16, 64);
-                    v1 += __shfl_xor(v1, 16, 64);
-                    v0 += __shfl_xor(v0, 32, 64);
-                    v1 += __shfl_xor(v1, 32, 64);
+                    v0 = nd_rows_sum(v0);
+                    v1 = nd_rows_sum(v1);
                     if (g4 == 0) {
                         lred[(q * 16 + i16) * ND_LRS + w] = v0;
                         lred[((q + 1) * 16 + i16) * ND_LRS + w] = v1;
@@ -1204,59 +1232,83 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
                 // merge the subtrees that end here (levels 1 .. nm), then park the
                 // merged tree at level nm + 1, or, at the doubling's last leaf
                 // (nm == j), keep its candidate
-                int cand = -1, first = -1;
+                int cand = -1;
                 double cand_lp = lp;
 #pragma unroll
                 for (int k = 1; k < NUTS_MAXD; ++k) {
                     if (k > nm) break;
                     if (alive) {
-                        const int32_t nl = lcn[k - 1];
+                        const int32_t nl = lcn[(k - 1) * 16 + i16];
                         const uint32_t block = ((uint32_t)j * 1024u + (uint32_t)i) * 16u + (uint32_t)k;
                         const double u = nuts_u52(a.key, (uint32_t)cc, t, block, TAG_NUTS_MERGE);
                         if (!((nl + n_node > 0) && u < (double)n_node / (double)(nl + n_node))) {
                             cand = k;
-                            cand_lp = lclp[k - 1];
+                            cand_lp = lclp[(k - 1) * 16 + i16];
                         }
                         n_node += nl;
                     }
-                    first = k;
                     if (alive && !(lred_get(2 * k) >= 0.0 && lred_get(2 * k + 1) >= 0.0)) alive = false;
                 }
                 if (nm < j) {
+                    // park at level nm + 1 (the same for the whole tile): its first leaf is
+                    // that of level nm's subtree (this leaf when nm = 0).  Stopped chains
+                    // park too (their records are never merged again), so the stores are
+                    // not divergent; the candidate's level is per chain: its LDS record
+                    // is read from a clamped level by every lane, the global one only when
+                    // some chain's candidate sits there.  The count and the candidate's
+                    // logp go to LDS, read back by every lane of the chain at the merge
+                    // (one barrier or more later).
+                    const int kp = nm + 1;
+                    const int cl = min(max(cand, 1), LV);
+                    const bool cand_glb = __ballot(cand > LV ? 1 : 0) != 0ull;
 #pragma unroll
-                    for (int k = 1; k < NUTS_MAXD; ++k) {
-                        if (k != nm + 1 || !alive) continue;
+                    for (int m = 0; m < MT; ++m) {
+                        if (!tile_ok[m]) continue;
+                        float f0[4], f1[4], c0[4], c1[4];
+                        if (nm == 0) {
 #pragma unroll
-                        for (int m = 0; m < MT; ++m) {
-                            if (!tile_ok[m]) continue;
-                            float f0[4], f1[4], c0[4], c1[4];
-                            if (first < 0) {
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    f0[v] = wx[m][v];
-                                    f1[v] = wr[m][v];
-                                }
-                            } else {
-                                rec_load(first, 0, m, f0);
-                                rec_load(first, 1, m, f1);
+                            for (int v = 0; v < 4; ++v) {
+                                f0[v] = wx[m][v];
+                                f1[v] = wr[m][v];
                             }
-                            if (cand < 0) {
+                        } else if (nm <= LV) {
+                            const floatx4 a0 = rec_lds(nm, 0, m), a1 = rec_lds(nm, 1, m);
 #pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    c0[v] = wx[m][v];
-                                    c1[v] = wg[m][v];
-                                }
-                            } else {
-                                rec_load(cand, 2, m, c0);
-                                rec_load(cand, 3, m, c1);
+                            for (int v = 0; v < 4; ++v) {
+                                f0[v] = a0[v];
+                                f1[v] = a1[v];
                             }
-                            rec_store(k, 0, m, f0);
-                            rec_store(k, 1, m, f1);
-                            rec_store(k, 2, m, c0);
-                            rec_store(k, 3, m, c1);
+                        } else {
+                            rec_glb(nm, 0, m, f0);
+                            rec_glb(nm, 1, m, f1);
                         }
-                        lcn[k - 1] = n_node;
-                        lclp[k - 1] = cand_lp;
+                        const floatx4 l0 = rec_lds(cl, 2, m), l1 = rec_lds(cl, 3, m);
+                        float g0[4] = {0.f, 0.f, 0.f, 0.f}, g1[4] = {0.f, 0.f, 0.f, 0.f};
+                        if (cand_glb) {
+                            rec_glb(max(cand, LV + 1), 2, m, g0);
+                            rec_glb(max(cand, LV + 1), 3, m, g1);
+                        }
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            c0[v] = cand < 0 ? wx[m][v] : (cand <= LV ? l0[v] : g0[v]);
+                            c1[v] = cand < 0 ? wg[m][v] : (cand <= LV ? l1[v] : g1[v]);
+                        }
+                        if (kp <= LV) {
+                            float* base = lvl + (((kp - 1) * 4) * 16 + i16) * XS + 16 * (w + ND_NW * m) + 4 * g4;
+                            *(floatx4*)(base) = floatx4{f0[0], f0[1], f0[2], f0[3]};
+                            *(floatx4*)(base + 16 * XS) = floatx4{f1[0], f1[1], f1[2], f1[3]};
+                            *(floatx4*)(base + 2 * 16 * XS) = floatx4{c0[0], c0[1], c0[2], c0[3]};
+                            *(floatx4*)(base + 3 * 16 * XS) = floatx4{c1[0], c1[1], c1[2], c1[3]};
+                        } else {
+                            rec_store(kp, 0, m, f0);
+                            rec_store(kp, 1, m, f1);
+                            rec_store(kp, 2, m, c0);
+                            rec_store(kp, 3, m, c1);
+                        }
+                    }
+                    if (w == 0 && g4 == 0) {
+                        lcn[(kp - 1) * 16 + i16] = n_node;
+                        lclp[(kp - 1) * 16 + i16] = cand_lp;
                     }
                 } else if (alive) {         // the last leaf: every subtree of doubling j ends here
 #pragma unroll
