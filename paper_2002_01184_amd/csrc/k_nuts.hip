@@ -858,26 +858,27 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
 
 // ---------------------------------------------------------------------------
 // Persistent NUTS for the dense Gaussian on MFMA (FP32, D <= 128).  A
-// workgroup of 4 waves owns 16 chains in the layout of the fused dense HMC
-// kernel: P as the A operands of v_mfma_f32_16x16x4f32 in VGPRs, x staged
-// chain-major in LDS as the B operands, lane (g4, i16) of wave w holding dims
-// 16 (w + 4 m) + 4 g4 + v of chain i16.  The 16 chains build their trees in
-// lockstep -- the same doubling and leaf at a time, a chain that has stopped
-// masked -- and the tile moves on as soon as none of them is running, so a
-// chain waits for the 15 others of its tile only, and there is one launch for
-// the whole run.  A chain's sums over its dims (energies, U-turn products)
-// are reduced across its 16 lane positions by shuffles and one LDS exchange;
-// every reduction sits where the control flow is uniform across the
-// workgroup (their count depends on the leaf index only).  The trajectory
-// ends, the levels' parked first leaves and candidates and the doubling's
-// candidate live in the NutsWs buffers, each lane touching only its own dims,
-// except the parked records of the shallow levels (the merges of all but a
-// few of the leaves), which sit in LDS: a global read there is latency that
-// nothing hides.  Every wave holds all 16 chains, so whether any chain of the
-// tile is still running is a wave-local ballot (every wave computes the same
-// flags from the same sums and random numbers); a leaf costs two barriers,
-// the drifted x and one reduction that carries the leaf's energies and every
-// U-turn check ending at it.
+// workgroup of 8 waves (two per SIMD) owns 16 chains in the layout of the
+// fused dense HMC kernel: P as the A operands of v_mfma_f32_16x16x4f32 in
+// VGPRs, x staged chain-major in LDS as the B operands, lane (g4, i16) of wave
+// w holding dims 16 (w + 8 m) + 4 g4 + v of chain i16.  The 16 chains build
+// their trees in lockstep -- the same doubling and leaf at a time, a chain
+// that has stopped masked -- and the tile moves on as soon as none of them is
+// running, so a chain waits for the 15 others of its tile only, and there is
+// one launch for the whole run.  A chain's sums over its dims (energies,
+// U-turn products) are summed over its 4 lane rows with register-only lane
+// swaps and over the 8 waves through one LDS exchange; every reduction sits
+// where the control flow is uniform across the workgroup (their count depends
+// on the leaf index only).  The trajectory ends, the levels' parked first
+// leaves and candidates and the doubling's candidate live in the NutsWs
+// buffers, each lane touching only its own dims, except the parked records of
+// the shallow levels (the merges of all but a few of the leaves) and every
+// level's parked leaf count and candidate logp, which sit in LDS: a global
+// read there is latency that nothing hides.  Every wave holds all 16 chains,
+// so whether any chain of the tile is still running is a wave-local ballot
+// (every wave computes the same flags from the same sums and random numbers);
+// a leaf costs two barriers, the drifted x and one reduction that carries the
+// leaf's energies and every U-turn check ending at it.
 // Same tree, uniforms and arithmetic order per lane as the lockstep kernels
 // up to the order of the FP64 sums.
 // ---------------------------------------------------------------------------
