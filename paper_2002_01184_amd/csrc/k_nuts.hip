@@ -494,6 +494,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
     const int64_t n_burnin = ad.n_burnin;
     extern __shared__ float lr_lds[];
     __shared__ double gsr[G > 64 ? 2 * 2 * (G / 64) : 1];
+    __shared__ double gsb[G > 64 ? 2 * 2 * NUTS_MAXD * (G / 64) : 1];   // [2 parity][values][waves]
     int gk = 0;
     const int64_t NR = GK >= 1 ? a.tg.N : 0;
     const int64_t NL = GK == 1 ? NR : 0;                 // rows of X held in LDS
@@ -550,7 +551,11 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
     T* const grec[4] = {lfx, lfr, lcx, lcg};
     auto recp = [&](int k, int q) -> T* {
         if (GK >= 1 && k <= nlv) return (T*)(lvl + ((k - 1) * 4 + q) * dp);
-        return grec[q] + ((int64_t)k * C + cc) * D;
+        // formed where it is used: the empty asm keeps the compiler from hoisting
+        // one 64-bit address per level and record out of the leaf loop
+        int64_t off = ((int64_t)k * C + cc) * D;
+        asm volatile("" : "+v"(off));
+        return grec[q] + off;
     };
     // logistic data gradient X^T (y - sigmoid(X theta)) at theta = wxa into
     // wga (the lane's dims), and the data log-likelihood (wave-uniform).  The
@@ -674,6 +679,115 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                             kin += 0.5 * (double)wr[b][e] * (double)wr[b][e];
                         }
                     }
+                if constexpr (G > 64) {
+                    // a workgroup per chain: one reduction (one barrier) carries the leaf's
+                    // energies and the U-turn products of every subtree that ends at the
+                    // leaf (levels 1 .. nm: bit k-1 of i set, k <= j); each value's wave
+                    // sums go to gsb as they are formed and are read where they are used
+                    static_assert(GK == 0, "a workgroup per chain runs element-wise targets only");
+                    constexpr int NWG = G / 64;
+                    const int nm = min(__builtin_ctz(~(unsigned)i), j);
+                    double* gb = gsb + (gk & 1) * (2 * NUTS_MAXD * NWG);
+                    auto put = [&](int q, double val) {
+                        val = group_sum<64>(val);
+                        if ((threadIdx.x & 63) == 0) gb[q * NWG + (threadIdx.x >> 6)] = val;
+                    };
+                    auto get = [&](int q) -> double {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int q2 = 0; q2 < NWG; ++q2) acc += gb[q * NWG + q2];
+                        return acc;
+                    };
+                    put(0, lp);
+                    put(1, kin);
+                    for (int k = 1; k <= nm; ++k) {
+                        const T *kfx = recp(k, 0), *kfr = recp(k, 1);
+                        double dm = 0.0, dp = 0.0;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (ok[b][e]) {
+                                    const int64_t d = dim_of(b, e);
+                                    const double fx = (double)kfx[d], fr = (double)kfr[d];
+                                    const double lx = (double)wx[b][e], lr = (double)wr[b][e];
+                                    const double dx = v > 0 ? lx - fx : fx - lx;
+                                    dm += dx * (v > 0 ? fr : lr);
+                                    dp += dx * (v > 0 ? lr : fr);
+                                }
+                        put(2 * k, dm);
+                        put(2 * k + 1, dp);
+                    }
+                    __syncthreads();
+                    ++gk;
+                    lp = get(0);
+                    kin = get(1);
+                    wlogp = lp;
+                    nleap += 1;
+                    const double H = -lp + kin;
+                    if (ST) {
+                        alpha += leaf_accept_prob(h0 - H);
+                        n_alpha += 1;
+                    }
+                    int32_t n_node = (log_u <= -H) ? 1 : 0;
+                    if (!(log_u < 1000.0 - H)) {
+                        alive = false;
+                        break;
+                    }
+                    int cand = -1;
+                    double cand_lp = lp;
+                    for (int k = 1; k <= nm; ++k) {
+                        const int32_t nl = lcn[k - 1];
+                        const uint32_t block = ((uint32_t)j * 1024u + (uint32_t)i) * 16u + (uint32_t)k;
+                        const double u = nuts_u52(a.key, (uint32_t)cc, t, block, TAG_NUTS_MERGE);
+                        if (!((nl + n_node > 0) && u < (double)n_node / (double)(nl + n_node))) {
+                            cand = k;
+                            cand_lp = lclp[k - 1];
+                        }
+                        n_node += nl;
+                        if (!(get(2 * k) >= 0.0 && get(2 * k + 1) >= 0.0)) {
+                            alive = false;
+                            break;
+                        }
+                    }
+                    if (!alive) break;
+                    if (nm < j) {           // park the merged tree at level nm + 1
+                        const int kp = nm + 1, first = nm > 0 ? nm : -1;
+                        T *kfx = recp(kp, 0), *kfr = recp(kp, 1), *kcx = recp(kp, 2), *kcg = recp(kp, 3);
+                        const T* ffx = recp(first < 0 ? 1 : first, 0);
+                        const T* ffr = recp(first < 0 ? 1 : first, 1);
+                        const T* ccx = recp(cand < 0 ? 1 : cand, 2);
+                        const T* ccg = recp(cand < 0 ? 1 : cand, 3);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (ok[b][e]) {
+                                    const int64_t d = dim_of(b, e);
+                                    kfx[d] = first < 0 ? wx[b][e] : ffx[d];
+                                    kfr[d] = first < 0 ? wr[b][e] : ffr[d];
+                                    kcx[d] = cand < 0 ? wx[b][e] : ccx[d];
+                                    kcg[d] = cand < 0 ? wg[b][e] : ccg[d];
+                                }
+                        lcn[kp - 1] = n_node;
+                        lclp[kp - 1] = cand_lp;
+                    } else {                // the last leaf: every subtree of doubling j ends here
+                        const T* ccx = recp(cand < 0 ? 1 : cand, 2);
+                        const T* ccg = recp(cand < 0 ? 1 : cand, 3);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int64_t d = dim_of(b, e);
+                                rcx[b][e] = cand < 0 ? wx[b][e] : (ok[b][e] ? ccx[d] : (T)0);
+                                rcg[b][e] = cand < 0 ? wg[b][e] : (ok[b][e] ? ccg[d] : (T)0);
+                            }
+                        rclp = cand_lp;
+                        rcn = n_node;
+                        complete = true;
+                    }
+                    continue;
+                }
                 if (GK >= 1) {
                     const double lpd = logreg_grad_lds(wx, wg);
 #pragma unroll
