@@ -1309,24 +1309,40 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
                         }
                     lred_put2(0, lp, kin);
                 }
+                // (the levels in LDS first, as straight-line reads; the deep ones, at few
+                // leaves, from global memory)
+                auto uturn_part = [&](int k, const float (&f0)[4], const float (&f1)[4], int m, double& dm,
+                                      double& dp) {
 #pragma unroll
-                for (int k = 1; k < NUTS_MAXD; ++k) {
-                    if (k > nm) break;
+                    for (int v = 0; v < 4; ++v) {
+                        const double fx = (double)f0[v], fr = (double)f1[v];
+                        const double lx = (double)wx[m][v], lr = (double)wr[m][v];
+                        const double dx = dir > 0 ? lx - fx : fx - lx;
+                        dm += dx * (dir > 0 ? fr : lr);
+                        dp += dx * (dir > 0 ? lr : fr);
+                    }
+                };
+                const int nm_l = min(nm, LV);
+                for (int k = 1; k <= nm_l; ++k) {
+                    double dm = 0.0, dp = 0.0;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        if (!tile_ok[m]) continue;
+                        const floatx4 a0 = rec_lds(k, 0, m), a1 = rec_lds(k, 1, m);
+                        const float f0[4] = {a0[0], a0[1], a0[2], a0[3]}, f1[4] = {a1[0], a1[1], a1[2], a1[3]};
+                        uturn_part(k, f0, f1, m, dm, dp);
+                    }
+                    lred_put2(2 * k, dm, dp);
+                }
+                for (int k = LV + 1; k <= nm; ++k) {
                     double dm = 0.0, dp = 0.0;
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
                         if (!tile_ok[m]) continue;
                         float f0[4], f1[4];
-                        rec_load(k, 0, m, f0);
-                        rec_load(k, 1, m, f1);
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const double fx = (double)f0[v], fr = (double)f1[v];
-                            const double lx = (double)wx[m][v], lr = (double)wr[m][v];
-                            const double dx = dir > 0 ? lx - fx : fx - lx;
-                            dm += dx * (dir > 0 ? fr : lr);
-                            dp += dx * (dir > 0 ? lr : fr);
-                        }
+                        rec_glb(k, 0, m, f0);
+                        rec_glb(k, 1, m, f1);
+                        uturn_part(k, f0, f1, m, dm, dp);
                     }
                     lred_put2(2 * k, dm, dp);
                 }
@@ -1349,9 +1365,7 @@ __global__ __launch_bounds__(64 * ND_NW) void k_nuts_fused_dense(PlainArgs a, Nu
                 // (nm == j), keep its candidate
                 int cand = -1;
                 double cand_lp = lp;
-#pragma unroll
-                for (int k = 1; k < NUTS_MAXD; ++k) {
-                    if (k > nm) break;
+                for (int k = 1; k <= nm; ++k) {
                     if (alive) {
                         const int32_t nl = lcn[(k - 1) * 16 + i16];
                         const uint32_t block = ((uint32_t)j * 1024u + (uint32_t)i) * 16u + (uint32_t)k;
