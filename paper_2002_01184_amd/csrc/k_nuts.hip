@@ -495,6 +495,15 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
     extern __shared__ float lr_lds[];
     __shared__ double gsr[G > 64 ? 2 * 2 * (G / 64) : 1];
     __shared__ double gsb[G > 64 ? 2 * 2 * NUTS_MAXD * (G / 64) : 1];   // [2 parity][values][waves]
+    // a workgroup per chain: per pending level its slice leaf count and candidate logp
+    // (written by thread 0 at the park, read at a merge one barrier or more later) and the
+    // slots of its first-leaf and candidate records (read before the next barrier, so each
+    // wave keeps its own copy, written by its lane 0: a wave's LDS accesses run in order)
+    __shared__ int32_t wg_cn[G > 64 ? NUTS_MAXD : 1];
+    __shared__ double wg_lp[G > 64 ? NUTS_MAXD : 1];
+    __shared__ int32_t wg_fsa[G > 64 ? (G / 64) * NUTS_MAXD : 1], wg_csa[G > 64 ? (G / 64) * NUTS_MAXD : 1];
+    int32_t* const wg_fs = wg_fsa + (G > 64 ? (threadIdx.x >> 6) * NUTS_MAXD : 0);
+    int32_t* const wg_cs = wg_csa + (G > 64 ? (threadIdx.x >> 6) * NUTS_MAXD : 0);
     int gk = 0;
     const int64_t NR = GK >= 1 ? a.tg.N : 0;
     const int64_t NL = GK == 1 ? NR : 0;                 // rows of X held in LDS
@@ -661,6 +670,10 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
             int32_t lcn[NUTS_MAXD];
             double lclp[NUTS_MAXD];
             T rcx[NB][4], rcg[NB][4];
+            // a workgroup per chain: each pending level's first-leaf and candidate records
+            // live in slots of the level buffers, handed from level to level by index, so a
+            // park writes only the records it creates (bit s of ffree / cfree: slot s free)
+            uint32_t ffree = ~0u, cfree = ~0u;
             double rclp = 0.0;
             int32_t rcn = 0;
             const int nleaves = 1 << j;
@@ -701,7 +714,7 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                     put(0, lp);
                     put(1, kin);
                     for (int k = 1; k <= nm; ++k) {
-                        const T *kfx = recp(k, 0), *kfr = recp(k, 1);
+                        const T *kfx = recp(wg_fs[k - 1], 0), *kfr = recp(wg_fs[k - 1], 1);
                         double dm = 0.0, dp = 0.0;
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
@@ -737,12 +750,12 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                     int cand = -1;
                     double cand_lp = lp;
                     for (int k = 1; k <= nm; ++k) {
-                        const int32_t nl = lcn[k - 1];
+                        const int32_t nl = wg_cn[k - 1];
                         const uint32_t block = ((uint32_t)j * 1024u + (uint32_t)i) * 16u + (uint32_t)k;
                         const double u = nuts_u52(a.key, (uint32_t)cc, t, block, TAG_NUTS_MERGE);
                         if (!((nl + n_node > 0) && u < (double)n_node / (double)(nl + n_node))) {
                             cand = k;
-                            cand_lp = lclp[k - 1];
+                            cand_lp = wg_lp[k - 1];
                         }
                         n_node += nl;
                         if (!(get(2 * k) >= 0.0 && get(2 * k + 1) >= 0.0)) {
@@ -752,28 +765,55 @@ __global__ __launch_bounds__(256) void k_nuts_fused_elem(PlainArgs a, NutsWs n, 
                     }
                     if (!alive) break;
                     if (nm < j) {           // park the merged tree at level nm + 1
-                        const int kp = nm + 1, first = nm > 0 ? nm : -1;
-                        T *kfx = recp(kp, 0), *kfr = recp(kp, 1), *kcx = recp(kp, 2), *kcg = recp(kp, 3);
-                        const T* ffx = recp(first < 0 ? 1 : first, 0);
-                        const T* ffr = recp(first < 0 ? 1 : first, 1);
-                        const T* ccx = recp(cand < 0 ? 1 : cand, 2);
-                        const T* ccg = recp(cand < 0 ? 1 : cand, 3);
+                        const int kp = nm + 1;
+                        // its first leaf: this leaf's (x, r) in a free slot, or level nm's slot;
+                        // the slots of levels 1 .. nm - 1 are released
+                        if (nm == 0) {
+                            const int sf = __builtin_ctz(ffree);
+                            ffree &= ~(1u << sf);
+                            if ((threadIdx.x & 63) == 0) wg_fs[kp - 1] = sf;
+                            T *kfx = recp(sf, 0), *kfr = recp(sf, 1);
 #pragma unroll
-                        for (int b = 0; b < NB; ++b)
+                            for (int b = 0; b < NB; ++b)
 #pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                if (ok[b][e]) {
-                                    const int64_t d = dim_of(b, e);
-                                    kfx[d] = first < 0 ? wx[b][e] : ffx[d];
-                                    kfr[d] = first < 0 ? wr[b][e] : ffr[d];
-                                    kcx[d] = cand < 0 ? wx[b][e] : ccx[d];
-                                    kcg[d] = cand < 0 ? wg[b][e] : ccg[d];
-                                }
-                        lcn[kp - 1] = n_node;
-                        lclp[kp - 1] = cand_lp;
+                                for (int e = 0; e < 4; ++e)
+                                    if (ok[b][e]) {
+                                        kfx[dim_of(b, e)] = wx[b][e];
+                                        kfr[dim_of(b, e)] = wr[b][e];
+                                    }
+                        } else {
+                            const int32_t sfn = wg_fs[nm - 1];
+                            if ((threadIdx.x & 63) == 0) wg_fs[kp - 1] = sfn;
+                            for (int k = 1; k < nm; ++k) ffree |= 1u << wg_fs[k - 1];
+                        }
+                        // its candidate: level cand's slot, or this leaf's (x, g) in a slot freed
+                        // from the merged levels first
+                        for (int k = 1; k <= nm; ++k)
+                            if (k != cand) cfree |= 1u << wg_cs[k - 1];
+                        if (cand < 0) {
+                            const int sc = __builtin_ctz(cfree);
+                            cfree &= ~(1u << sc);
+                            if ((threadIdx.x & 63) == 0) wg_cs[kp - 1] = sc;
+                            T *kcx = recp(sc, 2), *kcg = recp(sc, 3);
+#pragma unroll
+                            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    if (ok[b][e]) {
+                                        kcx[dim_of(b, e)] = wx[b][e];
+                                        kcg[dim_of(b, e)] = wg[b][e];
+                                    }
+                        } else {
+                            const int32_t scn = wg_cs[cand - 1];
+                            if ((threadIdx.x & 63) == 0) wg_cs[kp - 1] = scn;
+                        }
+                        if (threadIdx.x == 0) {
+                            wg_cn[kp - 1] = n_node;
+                            wg_lp[kp - 1] = cand_lp;
+                        }
                     } else {                // the last leaf: every subtree of doubling j ends here
-                        const T* ccx = recp(cand < 0 ? 1 : cand, 2);
-                        const T* ccg = recp(cand < 0 ? 1 : cand, 3);
+                        const T* ccx = recp(cand < 0 ? 0 : wg_cs[cand - 1], 2);
+                        const T* ccg = recp(cand < 0 ? 0 : wg_cs[cand - 1], 3);
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
 #pragma unroll
