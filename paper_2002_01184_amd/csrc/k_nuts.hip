@@ -366,8 +366,12 @@ __global__ __launch_bounds__(256) void k_nuts_end(PlainArgs a, NutsWs n, NutsAda
 // waits only for the chains of its own wavefront, not for the whole batch.
 // The levels' parked first leaves and candidates live in the NutsWs buffers
 // (each lane touches only its own dims); their counts and log-probabilities
-// in registers (levels unrolled).  Same tree, same uniforms, same arithmetic
-// order per leaf as the lockstep kernels.
+// in registers (levels unrolled).  With a workgroup per chain (G = 256) a
+// leaf's sums (energies, the U-turn products of every subtree ending at it)
+// share one LDS exchange and barrier, the per-level counts sit in LDS and the
+// records move between levels by slot index, a park writing only the records
+// it creates.  Same tree, same uniforms, same arithmetic order per leaf as the
+// lockstep kernels.
 // ---------------------------------------------------------------------------
 constexpr int NUTS_MAXD = 10;
 
